@@ -1,0 +1,158 @@
+"""Throughput of the graph-partitioned SP2 density matrix on one MI355X.
+
+One step = the whole hot path on one synthetic system already resident in HBM: X2 graph,
+block partition with halos, gather, batched SP2 squarings with the FP64 trace/branch
+decision, refinement (mixed precision), scatter into column-ELL D.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32]
+                  [--workload n18000|n1024] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "orbitals/s of D at ≤1e-6 err vs FP64 oracle; mixed vs FP64 GPU; X² MFMA util"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+WORKLOADS = {"n18000": dict(tau=1e-5, core=32), "n1024": dict(tau=1e-5, core=16)}
+
+
+def run_step(gb, Hc, Hv, n_occ, tau, core, precision, D):
+    g = gb.build_graph(Hc, Hv, tau)
+    p = gb.partition(g, core)
+    return gb.density(Hc, Hv, n_occ, tau, partition=p, core_size=core, precision=precision, D=D)
+
+
+def sample_error(D_col, D_val, golden):
+    dc = D_col.cpu().numpy()
+    dv = D_val.cpu().numpy()
+    errs = []
+    for r, s, v in golden["samples"]:
+        errs.append(abs(dv[r, s] - float.fromhex(v)))
+    from synth import ell_sha256
+    return float(max(errs)), ell_sha256(dc) == golden["D_col_sha256"]
+
+
+def cpu_baseline(model, workload, golden, n_sub_sample):
+    """The CPU oracle on a bounded sample: graph rows of the sampled cores, their halos,
+    gather and the full SP2 sequence (the oracle's own branch sequence, replayed, since
+    the branch needs every subgraph's trace) for n_sub_sample subgraphs."""
+    from threadpoolctl import threadpool_info
+    from oracle.bounds import gershgorin, x0_values
+    from oracle.graph import graph_x2
+    from oracle.sp2 import gather, sp2_partitioned
+    cfg = WORKLOADS[workload]
+    Hc, Hv = model["H_col"], model["H_val"]
+    N = model["N"]
+    core = cfg["core"]
+    n_cores = (N + core - 1) // core
+    rng = np.random.default_rng(0)
+    picks = np.sort(rng.choice(n_cores, size=n_sub_sample, replace=False))
+    branch = [int(c) for c in golden["branch"]] if golden else None
+    t0 = time.time()
+    emin, emax = gershgorin(Hc, Hv)
+    x0 = x0_values(Hc, Hv, emin, emax)
+    blocks, kc = [], []
+    for c in picks:
+        verts = np.arange(c * core, min((c + 1) * core, N))
+        rows = graph_x2(Hc, Hv, cfg["tau"], emin, emax, rows=verts)
+        halo = np.setdiff1d(np.unique(np.concatenate(rows)), verts)
+        sub = np.concatenate([verts, halo]).astype(np.int32)
+        blocks.append(gather(Hc, x0, sub))
+        kc.append(len(verts))
+    sp2_partitioned(blocks, kc, model["n_occ"], 0.0, branch_in=branch)
+    dt = time.time() - t0
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    return {"value": float(sum(kc) / dt), "unit": "orbitals/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{n_sub_sample} of {n_cores} subgraphs of {workload} (graph rows, halo, "
+                      f"gather, {len(branch) if branch else 'all'} SP2 steps), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=12)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(subgraphs would shard across GPUs with one 16-byte trace all-reduce per "
+              "SP2 iteration; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1603_00937_amd as gb
+    from synth import make_model, ell_sha256
+
+    cfg = WORKLOADS[args.workload]
+    model = make_model(args.workload)
+    N, n_occ = model["N"], model["n_occ"]
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_fp64_partitioned.json")
+    golden = json.load(open(gpath)) if os.path.exists(gpath) else None
+    if golden and golden["H_sha256"] != ell_sha256(model["H_col"], model["H_val"]):
+        golden = None
+    dev = torch.device("cuda:0")
+    Hc = torch.from_numpy(model["H_col"]).to(dev)
+    Hv = torch.from_numpy(model["H_val"]).to(dev)
+    g = gb.build_graph(Hc, Hv, cfg["tau"])
+    p = gb.partition(g, cfg["core"])
+    D = (torch.empty((N, p.max_sub), dtype=torch.int32, device=dev),
+         torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
+    del g, p
+    for _ in range(args.warmup):
+        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D)
+    torch.cuda.synchronize()
+    sq_ms, sq_n, flops_alg, flops_exec, stats = 0.0, 0, 0.0, 0.0, None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D)
+        sq_ms += stats["ms"]["square"]
+        sq_n += stats["n_square"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    flops_alg = stats["square_flops"]
+    flops_exec = stats["square_flops_exec"]
+    avg_launch_s = sq_ms / sq_n / 1e3
+    # the FP32 path also runs FP64 refinement squares; the roofline is quoted for the
+    # dominant kernel at the precision of the bulk of its launches
+    peak = PEAK_TFLOPS[args.precision]
+    achieved = flops_alg / avg_launch_s / 1e12
+    err, pattern_ok = (sample_error(D[0], D[1], golden) if golden else (None, None))
+    out = {
+        "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: seeded 3D tight-binding model, N={N} orbitals, "
+                               f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}",
+                   "precision": args.precision, "n_sub": stats["n_sub"],
+                   "max_sub": stats["max_sub"], "sp2_iters": stats["iters"]},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_symm_mm (batched X^2)",
+                     "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
+                     "exec_tflops": flops_exec / avg_launch_s / 1e12,
+                     "avg_launch_ms": avg_launch_s * 1e3},
+        "accuracy": {"max_abs_err_vs_oracle_samples": err, "D_pattern_bit_exact": pattern_ok,
+                     "converged": stats["converged"], "trace_D": stats["trace"]},
+        "stage_ms": stats["ms"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(model, args.workload, golden, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,178 @@
+/*
+ * gb.h -- C ABI of libgb: graph-partitioned SP2 density matrices on one MI355X.
+ *
+ * The calls follow the paper's statement of the problem (Niklasson et al., "Graph-based
+ * linear scaling electronic structure theory"): from a sparse symmetric Hamiltonian H in a
+ * local basis, a threshold tau and an occupation n_occ, build the data-dependency graph S
+ * (Eq. 2; any graph is allowed, obs. viii), split it into cores with halos (Eq. 6 and
+ * obs. vi), expand every subgraph's dense principal submatrix with the same recursive SP2
+ * sequence (the zero-temperature expansion after Eq. 7) and assemble the core columns into
+ * D (obs. i).
+ *
+ * Conventions shared by every call
+ *   - Matrix and index pointers are DEVICE pointers unless marked (host).
+ *   - `stream` is a hipStream_t (NULL = the null stream); every call is ordered on it.
+ *   - Return value: GB_OK or a negative gb_status; gb_last_error() then holds a message
+ *     (thread-local, valid until the next failing call on the same thread).
+ *   - Argument checks (null pointers, sizes, ranges, NaN) run on the host before any device
+ *     work and return GB_EINVAL or GB_ESHAPE; HIP failures return GB_EHIP.
+ *   - No call keeps a pointer to caller memory after it returns.  Handles (graph, partition)
+ *     own their device memory until *_destroy; destroying NULL is a no-op.
+ *   - Floating point on the graph, bounds and gather steps is evaluated in a fixed
+ *     (canonical) order with separately rounded products and sums, so index results are
+ *     reproducible bit for bit on any device and agree with a sequential CPU evaluation.
+ */
+#ifndef GB_H
+#define GB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gb_status;
+#define GB_OK 0
+#define GB_EINVAL (-1)        /* invalid argument value or null pointer               */
+#define GB_ENOMEM (-2)        /* device allocation failed                              */
+#define GB_EHIP (-3)          /* a HIP runtime call or kernel launch failed            */
+#define GB_ESHAPE (-4)        /* an output array is too small / sizes are inconsistent */
+#define GB_EUNSUPPORTED (-5)  /* valid request outside what this build implements      */
+
+/* Library version string (static storage). */
+const char* gb_version(void);
+/* Message for the last failing call on this thread ("" if none). */
+const char* gb_last_error(void);
+
+/*
+ * Row-major ELLPACK matrix: `n` rows, `width` slots per row.  Row i occupies
+ * col[i*width .. i*width+width-1] / val[...]: valid entries first with strictly ascending
+ * column indices in [0, n), then padding col = -1, val = 0.0.
+ * For H (input): symmetric in pattern and value, diagonal entry present in every row.
+ * For D (output): COLUMN-ELLPACK -- row i of the arrays holds column i of D (the paper
+ * assembles D column by column and D is not symmetric, obs. i): col = global row indices
+ * ascending, val = D[row, i].
+ */
+typedef struct {
+  int32_t n;
+  int32_t width;
+  int32_t* col;
+  double* val;
+} gb_ell;
+
+/*
+ * a1. Gershgorin bounds of H (the SP2 start map X0 = (e_max I - H)/(e_max - e_min) needs a
+ * spectral enclosure; the global bounds also enclose every principal submatrix).
+ *   e_min = min_i (h_ii - R_i), e_max = max_i (h_ii + R_i), R_i = sum_{j != i} |h_ij| summed
+ *   sequentially in ascending column order.  Results written to host doubles.
+ * Synchronises `stream`.
+ */
+gb_status gb_spectral_bounds(const gb_ell* H, void* stream, double* emin, double* emax);
+
+/* Graph rules (Eq. 2, Eq. 8, obs. viii).  Every rule adds all self-loops (T^(0) = I puts
+ * vertex i in its own subgraph, Eqs. 5-6) and the result is symmetric. */
+typedef enum {
+  /* S = {(i,j): j two hops from i in pattern(H), |(X0^2)_ij| >= tau}; (X0^2)_ij is summed
+   * over k ascending with separate rounding (no fused multiply-add).  aux unused. */
+  GB_GRAPH_X2 = 0,
+  /* S = {(i,j): |aux_ij| >= tau} (aux = H if NULL); aux symmetric ELL. */
+  GB_GRAPH_PATTERN = 1,
+  /* Adaptive MD graph: {|Dprev_ij| >= tau_aux} united with X2(H, tau), symmetrised; aux is
+   * the previous D in column-ELL form. */
+  GB_GRAPH_DPREV = 2
+} gb_graph_mode;
+
+typedef struct gb_graph_s gb_graph_t;
+
+/*
+ * a2. Build the data-dependency graph.  `aux`: see gb_graph_mode.  tau, tau_aux >= 0.
+ * On success *out owns a device CSR (row_ptr int32 [n+1], col int32 [nnz], rows sorted
+ * ascending, no duplicates).  Synchronises `stream` once (to size the CSR).
+ */
+gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double tau_aux,
+                         int32_t mode, void* stream, gb_graph_t** out);
+/* Sizes of a graph (host outputs). */
+gb_status gb_graph_info(const gb_graph_t* g, int32_t* n, int64_t* nnz);
+/* Copy the CSR into caller device buffers row_ptr [n+1] and col [nnz]. */
+gb_status gb_graph_copy(const gb_graph_t* g, int32_t* row_ptr, int32_t* col, void* stream);
+void gb_graph_destroy(gb_graph_t* g);
+
+/* Core selection (obs. vi-vii: a core may be any set of vertices, a "community"). */
+typedef enum {
+  GB_PART_BLOCK = 0  /* cores = consecutive runs of core_size vertices in vertex order */
+} gb_part_method;
+
+typedef struct gb_partition_s gb_partition_t;
+
+/*
+ * a3 + a4. Partition the graph into cores and build every core's subgraph (Eq. 6): the core
+ * vertices ascending, then the halo -- every vertex outside the core adjacent to it --
+ * ascending.  Synchronises `stream` once (to size the subgraph lists).
+ */
+gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, void* stream,
+                       gb_partition_t** out);
+/* n_sub subgraphs, the largest has max_sub vertices, total = sum of sizes (host outputs). */
+gb_status gb_partition_info(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
+                            int64_t* total);
+/* Copy core_ptr [n_sub+1], sub_ptr [n_sub+1] and sub_idx [total] into caller device buffers
+ * (any may be NULL to skip it). */
+gb_status gb_partition_copy(const gb_partition_t* p, int32_t* core_ptr, int32_t* sub_ptr,
+                            int32_t* sub_idx, void* stream);
+void gb_partition_destroy(gb_partition_t* p);
+
+/* Arithmetic of the squaring loop. */
+typedef enum {
+  GB_FP64 = 0,        /* every square in FP64 on the matrix cores                         */
+  GB_FP32_REFINE = 1  /* squares in FP32 (FP32 accumulate), then FP64 refinement steps      */
+} gb_precision;
+
+typedef struct {
+  int32_t precision;         /* gb_precision; default GB_FP64                                */
+  int32_t n_refine;          /* FP64 McWeeny steps after the loop (default 0; FP32: 2)       */
+  int32_t max_iter;          /* default 100 when 0                                           */
+  double idem_tol;           /* stop when |Tr X - Tr X^2| <= idem_tol; 0 = 1e-10 * n / 1024   */
+  const gb_partition_t* partition; /* NULL: build X2(threshold) + BLOCK(core_size) inside    */
+  int32_t core_size;         /* used when partition == NULL; default 32                      */
+  const uint8_t* branch_in;  /* (host) replay this branch sequence instead of choosing it    */
+  int32_t n_branch_in;
+  double emin, emax;         /* spectral bounds; both 0 = Gershgorin                          */
+} gb_sp2_opts;
+
+typedef struct {
+  int32_t iters;             /* SP2 updates applied                                          */
+  int32_t converged;         /* 1 if the stop rule fired (or the replay ended idempotent)    */
+  int32_t n_sub, max_sub;
+  uint8_t branch[128];       /* branch of each update: 0 = X^2, 1 = 2X - X^2                  */
+  double trace;              /* Tr D (sum of the assembled diagonal)                         */
+  double idem;               /* |Tr X - Tr X^2| at the stop                                  */
+  double idem_max;           /* max over core columns of |X^2 - X| after the loop            */
+  double emin, emax;
+  double min_margin;         /* smallest | |t2-n| - |2t1-t2-n| | over chosen branches        */
+  double t1[128], t2[128];   /* core traces of X and X^2 at each square                      */
+  float ms_bounds, ms_graph, ms_part, ms_gather, ms_sp2, ms_refine, ms_scatter, ms_total;
+  float ms_square;           /* summed device time of the squaring kernel launches           */
+  int32_t n_square;          /* number of squaring kernel launches                           */
+  double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
+  double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
+} gb_sp2_stats;
+
+/*
+ * a5-a12. Density matrix D = P_tau(X0) of the partitioned SP2 expansion (Eq. 6 with the SP2
+ * recursion), assembled into caller-owned column-ELL D (D->n = H->n, D->width >= max_sub;
+ * slots beyond a column's subgraph size are padding).
+ *   Loop: square every subgraph block; t1, t2 = sums of the core diagonals of X and X^2 over
+ *   all subgraphs (FP64); stop if |t1 - t2| <= idem_tol (D is the current X); otherwise
+ *   X <- X^2 if |t2 - n_occ| < |2 t1 - t2 - n_occ|, else X <- 2X - X^2, for every subgraph.
+ * Non-convergence is not an error (stats->converged = 0).  stats may be NULL.  The call
+ * synchronises `stream` once per SP2 iteration (to read the stop flag) and at the end.
+ * GB_ESHAPE if D->width < max_sub (stats->max_sub then holds the needed width).
+ */
+gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_sp2_opts* opts,
+                     gb_ell* D, gb_sp2_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GB_H */

@@ -1,0 +1,8 @@
+"""Graph-partitioned SP2 density matrices on MI355X (Python binding of libgb).
+
+Every step runs in the HIP library ``libgb.so``; this package only marshals torch
+device tensors (memory) and the current HIP stream into the C ABI of include/gb.h.
+"""
+from .api import (  # noqa: F401
+    GbError, Graph, Partition, spectral_bounds, build_graph, partition, density, version,
+)

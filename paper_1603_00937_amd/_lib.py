@@ -1,0 +1,82 @@
+"""ctypes view of the libgb C ABI (include/gb.h).  Argument marshalling only."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgb.so")
+
+GB_OK, GB_EINVAL, GB_ENOMEM, GB_EHIP, GB_ESHAPE, GB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "GB_OK", -1: "GB_EINVAL", -2: "GB_ENOMEM", -3: "GB_EHIP", -4: "GB_ESHAPE",
+                -5: "GB_EUNSUPPORTED"}
+GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2}
+PART_METHODS = {"block": 0}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+
+
+class GbEll(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class GbSp2Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("idem_tol", ctypes.c_double),
+                ("partition", ctypes.c_void_p), ("core_size", ctypes.c_int32),
+                ("branch_in", ctypes.c_void_p), ("n_branch_in", ctypes.c_int32),
+                ("emin", ctypes.c_double), ("emax", ctypes.c_double)]
+
+
+class GbSp2Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("n_sub", ctypes.c_int32), ("max_sub", ctypes.c_int32),
+                ("branch", ctypes.c_uint8 * 128),
+                ("trace", ctypes.c_double), ("idem", ctypes.c_double),
+                ("idem_max", ctypes.c_double), ("emin", ctypes.c_double),
+                ("emax", ctypes.c_double), ("min_margin", ctypes.c_double),
+                ("t1", ctypes.c_double * 128), ("t2", ctypes.c_double * 128),
+                ("ms_bounds", ctypes.c_float), ("ms_graph", ctypes.c_float),
+                ("ms_part", ctypes.c_float), ("ms_gather", ctypes.c_float),
+                ("ms_sp2", ctypes.c_float), ("ms_refine", ctypes.c_float),
+                ("ms_scatter", ctypes.c_float), ("ms_total", ctypes.c_float),
+                ("ms_square", ctypes.c_float), ("n_square", ctypes.c_int32),
+                ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+SIGNATURES = {
+    "gb_version": (ctypes.c_char_p, []),
+    "gb_last_error": (ctypes.c_char_p, []),
+    "gb_spectral_bounds": (ctypes.c_int32, [_P(GbEll), _vp, _P(ctypes.c_double),
+                                            _P(ctypes.c_double)]),
+    "gb_build_graph": (ctypes.c_int32, [_P(GbEll), _P(GbEll), ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int32, _vp, _P(_vp)]),
+    "gb_graph_info": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int64)]),
+    "gb_graph_copy": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
+    "gb_graph_destroy": (None, [_vp]),
+    "gb_partition": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _P(_vp)]),
+    "gb_partition_info": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                           _P(ctypes.c_int64)]),
+    "gb_partition_copy": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "gb_partition_destroy": (None, [_vp]),
+    "gb_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double, _P(GbSp2Opts),
+                                    _P(GbEll), _P(GbSp2Stats), _vp]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgb.so (built by paper_1603_00937_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libgb.so not found at {path}: run __graft_entry__.build() first")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,306 @@
+// C ABI entry points: argument checks on the host, handle management, error strings.
+// C++ exceptions raised inside the library are converted to gb_status codes here.
+#include "internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+
+namespace gbi {
+
+namespace {
+thread_local char g_err[1024] = "";
+std::once_flag g_pool_once;
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+void fail(gb_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  throw Error{code};
+}
+
+void* dmalloc(size_t bytes, hipStream_t s) {
+  // keep freed pool memory cached instead of returning it at every synchronisation
+  std::call_once(g_pool_once, [] {
+    int dev = 0;
+    hipMemPool_t pool;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
+  void* p = nullptr;
+  const hipError_t e = hipMallocAsync(&p, bytes ? bytes : 1, s);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    fail(GB_ENOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  return p;
+}
+
+void dfree(void* p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
+}
+
+void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
+             double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s);
+
+}  // namespace gbi
+
+using namespace gbi;
+
+namespace {
+
+template <typename F>
+gb_status guarded(F&& f) {
+  try {
+    f();
+    g_err[0] = '\0';
+    return GB_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return GB_ENOMEM;
+  } catch (...) {
+    set_error("unexpected internal error");
+    return GB_EHIP;
+  }
+}
+
+void check_ell(const gb_ell* A, const char* name, bool need_val = true) {
+  if (!A) fail(GB_EINVAL, "%s is NULL", name);
+  if (A->n <= 0) fail(GB_EINVAL, "%s->n = %d must be positive", name, A->n);
+  if (A->width <= 0) fail(GB_EINVAL, "%s->width = %d must be positive", name, A->width);
+  if (!A->col) fail(GB_EINVAL, "%s->col is NULL", name);
+  if (need_val && !A->val) fail(GB_EINVAL, "%s->val is NULL", name);
+}
+
+void check_tau(double t, const char* name) {
+  if (!(t >= 0.0) || std::isinf(t)) fail(GB_EINVAL, "%s = %g must be finite and >= 0", name, t);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+const char* gb_version(void) { return "libgb 0.1.0 (gfx950)"; }
+
+const char* gb_last_error(void) { return g_err; }
+
+gb_status gb_spectral_bounds(const gb_ell* H, void* stream, double* emin, double* emax) {
+  return guarded([&] {
+    check_ell(H, "H");
+    if (!emin || !emax) fail(GB_EINVAL, "emin / emax output pointer is NULL");
+    bounds(*H, as_stream(stream), emin, emax);
+  });
+}
+
+gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double tau_aux,
+                         int32_t mode, void* stream, gb_graph_t** out) {
+  return guarded([&] {
+    if (!out) fail(GB_EINVAL, "out is NULL");
+    *out = nullptr;
+    check_ell(H, "H");
+    check_tau(tau, "tau");
+    if (mode < GB_GRAPH_X2 || mode > GB_GRAPH_DPREV) fail(GB_EINVAL, "unknown graph mode %d", mode);
+    if (mode == GB_GRAPH_DPREV) {
+      check_ell(aux, "aux (previous D)");
+      check_tau(tau_aux, "tau_aux");
+      if (aux->n != H->n) fail(GB_ESHAPE, "aux->n = %d differs from H->n = %d", aux->n, H->n);
+    }
+    if (mode == GB_GRAPH_PATTERN && aux) {
+      check_ell(aux, "aux");
+      if (aux->n != H->n) fail(GB_ESHAPE, "aux->n = %d differs from H->n = %d", aux->n, H->n);
+    }
+    hipStream_t s = as_stream(stream);
+    auto* g = new gb_graph_s();
+    try {
+      if (mode == GB_GRAPH_PATTERN) {
+        graph_pattern(aux ? *aux : *H, tau, g->csr, s);
+      } else {
+        double emin, emax;
+        bounds(*H, s, &emin, &emax);
+        DBuf<double> x0((size_t)H->n * H->width, s);
+        x0_ell(*H, emin, emax, x0.get(), s);
+        if (mode == GB_GRAPH_X2) {
+          graph_x2(*H, x0.get(), tau, g->csr, s);
+        } else {
+          Csr base;
+          graph_x2(*H, x0.get(), tau, base, s);
+          graph_union_dprev(base, *aux, tau_aux, g->csr, s);
+        }
+      }
+      GB_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
+gb_status gb_graph_info(const gb_graph_t* g, int32_t* n, int64_t* nnz) {
+  return guarded([&] {
+    if (!g) fail(GB_EINVAL, "graph is NULL");
+    if (n) *n = g->csr.n;
+    if (nnz) *nnz = g->csr.nnz;
+  });
+}
+
+gb_status gb_graph_copy(const gb_graph_t* g, int32_t* row_ptr, int32_t* col, void* stream) {
+  return guarded([&] {
+    if (!g) fail(GB_EINVAL, "graph is NULL");
+    hipStream_t s = as_stream(stream);
+    if (row_ptr)
+      GB_HIP(hipMemcpyAsync(row_ptr, g->csr.row_ptr.get(), (g->csr.n + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, s));
+    if (col && g->csr.nnz)
+      GB_HIP(hipMemcpyAsync(col, g->csr.col.get(), g->csr.nnz * sizeof(int32_t),
+                            hipMemcpyDeviceToDevice, s));
+  });
+}
+
+void gb_graph_destroy(gb_graph_t* g) { delete g; }
+
+gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, void* stream,
+                       gb_partition_t** out) {
+  return guarded([&] {
+    if (!out) fail(GB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) fail(GB_EINVAL, "graph is NULL");
+    if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
+    if (method != GB_PART_BLOCK) fail(GB_EUNSUPPORTED, "partition method %d", method);
+    hipStream_t s = as_stream(stream);
+    auto* p = new gb_partition_s();
+    try {
+      partition_block(g->csr, core_size, p->part, s);
+      GB_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+gb_status gb_partition_info(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
+                            int64_t* total) {
+  return guarded([&] {
+    if (!p) fail(GB_EINVAL, "partition is NULL");
+    if (n_sub) *n_sub = p->part.n_sub;
+    if (max_sub) *max_sub = p->part.max_sub;
+    if (total) *total = p->part.total;
+  });
+}
+
+gb_status gb_partition_copy(const gb_partition_t* p, int32_t* core_ptr, int32_t* sub_ptr,
+                            int32_t* sub_idx, void* stream) {
+  return guarded([&] {
+    if (!p) fail(GB_EINVAL, "partition is NULL");
+    hipStream_t s = as_stream(stream);
+    const Part& P = p->part;
+    if (core_ptr)
+      GB_HIP(hipMemcpyAsync(core_ptr, P.core_ptr.get(), (P.n_sub + 1) * 4, hipMemcpyDeviceToDevice, s));
+    if (sub_ptr)
+      GB_HIP(hipMemcpyAsync(sub_ptr, P.sub_ptr.get(), (P.n_sub + 1) * 4, hipMemcpyDeviceToDevice, s));
+    if (sub_idx && P.total)
+      GB_HIP(hipMemcpyAsync(sub_idx, P.sub_idx.get(), P.total * 4, hipMemcpyDeviceToDevice, s));
+  });
+}
+
+void gb_partition_destroy(gb_partition_t* p) { delete p; }
+
+gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_sp2_opts* opts,
+                     gb_ell* D, gb_sp2_stats* stats, void* stream) {
+  gb_sp2_stats local{};
+  gb_sp2_stats& st = stats ? *stats : local;
+  return guarded([&] {
+    std::memset(&st, 0, sizeof(st));
+    st.min_margin = INFINITY;
+    check_ell(H, "H");
+    check_ell(D, "D");
+    if (D->n != H->n) fail(GB_ESHAPE, "D->n = %d differs from H->n = %d", D->n, H->n);
+    if (n_occ < 0 || n_occ > H->n) fail(GB_EINVAL, "n_occ = %d outside [0, %d]", n_occ, H->n);
+    check_tau(threshold, "threshold");
+    gb_sp2_opts o{};
+    if (opts) o = *opts;
+    if (o.precision != GB_FP64 && o.precision != GB_FP32_REFINE)
+      fail(GB_EINVAL, "unknown precision %d", o.precision);
+    if (o.max_iter < 0 || o.n_refine < 0) fail(GB_EINVAL, "max_iter / n_refine must be >= 0");
+    if (!(o.idem_tol >= 0.0)) fail(GB_EINVAL, "idem_tol must be >= 0");
+    if (o.branch_in && (o.n_branch_in < 0 || o.n_branch_in > 128))
+      fail(GB_EINVAL, "n_branch_in = %d outside [0, 128]", o.n_branch_in);
+    if (o.branch_in)
+      for (int i = 0; i < o.n_branch_in; ++i)
+        if (o.branch_in[i] > 1) fail(GB_EINVAL, "branch_in[%d] = %d is not 0 or 1", i, o.branch_in[i]);
+    if ((o.max_iter > 0 ? o.max_iter : 100) > 127) fail(GB_EINVAL, "max_iter must be <= 127");
+    const bool given_bounds = !(o.emin == 0.0 && o.emax == 0.0);
+    if (given_bounds && !(o.emax > o.emin)) fail(GB_EINVAL, "need emax > emin");
+    if (o.partition && o.partition->part.n != H->n)
+      fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", o.partition->part.n, H->n);
+    const int core_size = o.core_size > 0 ? o.core_size : 32;
+
+    hipStream_t s = as_stream(stream);
+    hipEvent_t e0, e1;
+    GB_HIP(hipEventCreate(&e0));
+    GB_HIP(hipEventCreate(&e1));
+    struct EvGuard {
+      hipEvent_t a, b;
+      ~EvGuard() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } eg{e0, e1};
+    GB_HIP(hipEventRecord(e0, s));
+    double emin = o.emin, emax = o.emax;
+    if (!given_bounds) bounds(*H, s, &emin, &emax);
+    DBuf<double> x0((size_t)H->n * H->width, s);
+    x0_ell(*H, emin, emax, x0.get(), s);
+    GB_HIP(hipEventRecord(e1, s));
+    GB_HIP(hipStreamSynchronize(s));
+    GB_HIP(hipEventElapsedTime(&st.ms_bounds, e0, e1));
+    st.emin = emin;
+    st.emax = emax;
+    float ms_front = st.ms_bounds;
+
+    gb_partition_s own;
+    const Part* P = o.partition ? &o.partition->part : nullptr;
+    if (!P) {
+      GB_HIP(hipEventRecord(e0, s));
+      Csr g;
+      graph_x2(*H, x0.get(), threshold, g, s);
+      GB_HIP(hipEventRecord(e1, s));
+      GB_HIP(hipStreamSynchronize(s));
+      GB_HIP(hipEventElapsedTime(&st.ms_graph, e0, e1));
+      GB_HIP(hipEventRecord(e0, s));
+      partition_block(g, core_size, own.part, s);
+      GB_HIP(hipEventRecord(e1, s));
+      GB_HIP(hipStreamSynchronize(s));
+      GB_HIP(hipEventElapsedTime(&st.ms_part, e0, e1));
+      ms_front += st.ms_graph + st.ms_part;
+      P = &own.part;
+    }
+    st.n_sub = P->n_sub;
+    st.max_sub = P->max_sub;
+    if (D->width < P->max_sub)
+      fail(GB_ESHAPE, "D->width = %d is smaller than the largest subgraph (%d)", D->width,
+           P->max_sub);
+    density(*H, n_occ, o, *P, emin, emax, x0.get(), *D, st, s);
+    st.ms_total += ms_front;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,472 @@
+// Spectral bounds, the SP2 start map X0, and the data-dependency graphs (Eq. 2, Eq. 8,
+// obs. viii).  Every floating-point result that decides an integer (a graph edge) is
+// evaluated in a canonical order with separately rounded operations, so the graph is the
+// same bit for bit as a sequential CPU evaluation: Gershgorin row sums in ascending column
+// order, x0 = (e_max*delta_ij - h_ij)/(e_max - e_min), and (X0^2)_ij accumulated over k in
+// ascending order.  The library is compiled with floating-point contraction disabled.
+#include "internal.h"
+
+#pragma clang fp contract(off)
+
+namespace gbi {
+namespace {
+
+constexpr int kT = 256;
+
+__device__ __forceinline__ double x0_entry(double h, bool diag, double emax, double denom) {
+  const double num = diag ? (emax - h) : (0.0 - h);
+  return num / denom;
+}
+
+// One thread per row: Gershgorin ends lo_i = h_ii - R_i, hi_i = h_ii + R_i, with
+// R_i = sum_{j != i} |h_ij| accumulated in slot (ascending column) order.
+__global__ void k_row_discs(const int32_t* __restrict__ col, const double* __restrict__ val, int n,
+                            int w, double* __restrict__ lo, double* __restrict__ hi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t* c = col + (int64_t)i * w;
+  const double* v = val + (int64_t)i * w;
+  double r = 0.0, d = 0.0;
+  for (int t = 0; t < w; ++t) {
+    const int32_t j = c[t];
+    if (j < 0) break;
+    if (j == i) d = v[t];
+    else r = r + fabs(v[t]);
+  }
+  lo[i] = d - r;
+  hi[i] = d + r;
+}
+
+// min of lo, max of hi over n rows (exact, order-free); one block.
+__global__ void k_minmax(const double* __restrict__ lo, const double* __restrict__ hi, int n,
+                         double* __restrict__ out) {
+  __shared__ double smin[kT], smax[kT];
+  double a = INFINITY, b = -INFINITY;
+  for (int i = threadIdx.x; i < n; i += kT) {
+    a = fmin(a, lo[i]);
+    b = fmax(b, hi[i]);
+  }
+  smin[threadIdx.x] = a;
+  smax[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = smin[0];
+    out[1] = smax[0];
+  }
+}
+
+__global__ void k_x0(const int32_t* __restrict__ col, const double* __restrict__ val, int n, int w,
+                     double emax, double denom, double* __restrict__ x0) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)n * w) return;
+  const int i = (int)(p / w);
+  const int32_t j = col[p];
+  x0[p] = j < 0 ? 0.0 : x0_entry(val[p], j == i, emax, denom);
+}
+
+// ---- X2 graph, one workgroup per row i --------------------------------------------------
+// LDS: candidate bitmap over all n vertices, per-word rank base, accumulators of the
+// candidates (indexed by rank), and row i's columns / x0 values.
+//   1. mark every j in row k for every k in row i (two-hop candidates) and i itself;
+//   2. rank = number of candidates below j (per-word popcount prefix);
+//   3. for k in row i, ascending: acc[rank(j)] += x0_ik * x0_kj for j in row k -- each j
+//      appears once per k, and a barrier separates the k steps, so every accumulator takes
+//      its terms in ascending k;
+//   4. keep j if |acc| >= tau or j == i; PASS 0 counts, PASS 1 writes the sorted columns.
+struct X2Lds {
+  uint32_t* bits;
+  int32_t* pre;
+  double* acc;
+  int32_t* ci;
+  double* xi;
+  int32_t* wcnt;
+};
+
+__device__ __forceinline__ int32_t block_sum_i32(int32_t v, int32_t* red) {
+  __syncthreads();
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = kT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  const int32_t r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// exclusive scan of v[0..m) in place (LDS), returns total; all threads call
+__device__ int32_t lds_exclusive_scan(int32_t* v, int m, int32_t* red) {
+  int32_t carry = 0;
+  for (int base = 0; base < m; base += kT) {
+    const int k = base + threadIdx.x;
+    const int32_t x = k < m ? v[k] : 0;
+    __syncthreads();
+    red[threadIdx.x] = x;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over kT values
+    for (int d = 1; d < kT; d <<= 1) {
+      const int32_t y = threadIdx.x >= d ? red[threadIdx.x - d] : 0;
+      __syncthreads();
+      red[threadIdx.x] += y;
+      __syncthreads();
+    }
+    if (k < m) v[k] = carry + red[threadIdx.x] - x;
+    carry += red[kT - 1];
+    __syncthreads();
+  }
+  return carry;
+}
+
+template <int PASS>
+__global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol,
+                                                const double* __restrict__ x0, int n, int w,
+                                                double tau, int cap, int32_t* __restrict__ cnt,
+                                                const int32_t* __restrict__ row_ptr,
+                                                int32_t* __restrict__ out_col,
+                                                int32_t* __restrict__ overflow) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int i = blockIdx.x;
+  const int nw = (n + 31) >> 5;
+  X2Lds L;
+  L.acc = reinterpret_cast<double*>(smem);
+  L.xi = L.acc + cap;
+  L.bits = reinterpret_cast<uint32_t*>(L.xi + w);
+  L.pre = reinterpret_cast<int32_t*>(L.bits + nw);
+  L.ci = L.pre + nw + 1;
+  L.wcnt = L.ci + w;
+  int32_t* red = L.wcnt + nw;  // kT ints
+
+  for (int t = threadIdx.x; t < w; t += kT) {
+    L.ci[t] = hcol[(int64_t)i * w + t];
+    L.xi[t] = x0[(int64_t)i * w + t];
+  }
+  for (int q = threadIdx.x; q < nw; q += kT) L.bits[q] = 0u;
+  __syncthreads();
+  // 1. two-hop candidates
+  for (int p = threadIdx.x; p < w * w; p += kT) {  // entries outside [0, n) are padding
+    const int t = p / w, u = p - t * w;
+    const int32_t k = L.ci[t];
+    if ((unsigned)k >= (unsigned)n) continue;
+    const int32_t j = hcol[(int64_t)k * w + u];
+    if ((unsigned)j < (unsigned)n) atomicOr(&L.bits[j >> 5], 1u << (j & 31));
+  }
+  if (threadIdx.x == 0) atomicOr(&L.bits[i >> 5], 1u << (i & 31));
+  __syncthreads();
+  // 2. ranks
+  for (int q = threadIdx.x; q < nw; q += kT) L.pre[q] = __popc(L.bits[q]);
+  __syncthreads();
+  const int32_t ncand = lds_exclusive_scan(L.pre, nw, red);
+  if (ncand > cap) {
+    if (threadIdx.x == 0) {
+      atomicMax(overflow, ncand);
+      if (PASS == 0) cnt[i] = 0;
+    }
+    return;
+  }
+  for (int r = threadIdx.x; r < ncand; r += kT) L.acc[r] = 0.0;
+  __syncthreads();
+  // 3. canonical accumulation, k ascending
+  for (int t = 0; t < w; ++t) {
+    const int32_t k = L.ci[t];
+    if ((unsigned)k >= (unsigned)n) break;
+    const double xik = L.xi[t];
+    for (int u = threadIdx.x; u < w; u += kT) {
+      const int32_t j = hcol[(int64_t)k * w + u];
+      if ((unsigned)j >= (unsigned)n) continue;
+      const uint32_t word = L.bits[j >> 5];
+      const int r = L.pre[j >> 5] + __popc(word & ((1u << (j & 31)) - 1u));
+      const double prod = xik * x0[(int64_t)k * w + u];
+      L.acc[r] = L.acc[r] + prod;
+    }
+    __syncthreads();
+  }
+  // 4. keep decision and ordered compaction
+  for (int q = threadIdx.x; q < nw; q += kT) {
+    uint32_t word = L.bits[q];
+    int r = L.pre[q];
+    int32_t c = 0;
+    while (word) {
+      const int b = __ffs(word) - 1;
+      const int j = (q << 5) + b;
+      if (fabs(L.acc[r]) >= tau || j == i) ++c;
+      ++r;
+      word &= word - 1u;
+    }
+    L.wcnt[q] = c;
+  }
+  __syncthreads();
+  const int32_t kept = lds_exclusive_scan(L.wcnt, nw, red);
+  if (PASS == 0) {
+    if (threadIdx.x == 0) cnt[i] = kept;
+    return;
+  }
+  const int32_t base = row_ptr[i];
+  for (int q = threadIdx.x; q < nw; q += kT) {
+    uint32_t word = L.bits[q];
+    int r = L.pre[q];
+    int32_t pos = base + L.wcnt[q];
+    while (word) {
+      const int b = __ffs(word) - 1;
+      const int j = (q << 5) + b;
+      if (fabs(L.acc[r]) >= tau || j == i) out_col[pos++] = j;
+      ++r;
+      word &= word - 1u;
+    }
+  }
+}
+
+size_t x2_lds_bytes(int n, int w, int cap) {
+  const int nw = (n + 31) >> 5;
+  return (size_t)cap * 8 + (size_t)w * 8 + (size_t)nw * 4 + (size_t)(nw + 1) * 4 + (size_t)w * 4 +
+         (size_t)nw * 4 + (size_t)kT * 4 + 64;
+}
+
+// ---- row unions through an LDS bitmap (pattern graphs, symmetrisation) --------------------
+// Row i of the result = (row i of up to two CSR inputs) U {i}, sorted and unique.
+template <int PASS>
+__global__ __launch_bounds__(kT) void k_union_rows(int n, const int32_t* __restrict__ rp0,
+                                                   const int32_t* __restrict__ c0,
+                                                   const int32_t* __restrict__ rp1,
+                                                   const int32_t* __restrict__ c1,
+                                                   int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ row_ptr,
+                                                   int32_t* __restrict__ out_col) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int i = blockIdx.x;
+  const int nw = (n + 31) >> 5;
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem);
+  int32_t* wc = reinterpret_cast<int32_t*>(bits + nw);
+  int32_t* red = wc + nw;
+  for (int q = threadIdx.x; q < nw; q += kT) bits[q] = 0u;
+  __syncthreads();
+  for (int p = rp0[i] + threadIdx.x; p < rp0[i + 1]; p += kT) {
+    const int j = c0[p];
+    atomicOr(&bits[j >> 5], 1u << (j & 31));
+  }
+  if (rp1)
+    for (int p = rp1[i] + threadIdx.x; p < rp1[i + 1]; p += kT) {
+      const int j = c1[p];
+      atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+  if (threadIdx.x == 0) atomicOr(&bits[i >> 5], 1u << (i & 31));
+  __syncthreads();
+  for (int q = threadIdx.x; q < nw; q += kT) wc[q] = __popc(bits[q]);
+  __syncthreads();
+  const int32_t tot = lds_exclusive_scan(wc, nw, red);
+  if (PASS == 0) {
+    if (threadIdx.x == 0) cnt[i] = tot;
+    return;
+  }
+  const int32_t base = row_ptr[i];
+  for (int q = threadIdx.x; q < nw; q += kT) {
+    uint32_t word = bits[q];
+    int32_t pos = base + wc[q];
+    while (word) {
+      const int b = __ffs(word) - 1;
+      out_col[pos++] = (q << 5) + b;
+      word &= word - 1u;
+    }
+  }
+}
+
+// entries of an ELL matrix with |a| >= tau, as (row-list) CSR counts / fill (rows unsorted
+// only if the ELL rows are; ELL rows are ascending so the output rows are ascending)
+template <int PASS>
+__global__ void k_ell_threshold(const int32_t* __restrict__ col, const double* __restrict__ val,
+                                int n, int w, double tau, int32_t* __restrict__ cnt,
+                                const int32_t* __restrict__ row_ptr, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t c = 0;
+  int32_t pos = PASS ? row_ptr[i] : 0;
+  for (int t = 0; t < w; ++t) {
+    const int32_t j = col[(int64_t)i * w + t];
+    if (j < 0) break;
+    if ((unsigned)j >= (unsigned)n) continue;
+    if (fabs(val[(int64_t)i * w + t]) >= tau) {
+      if (PASS) out[pos++] = j;
+      ++c;
+    }
+  }
+  if (!PASS) cnt[i] = c;
+}
+
+// transpose of a CSR pattern: count per column, then fill (order within a row arbitrary)
+__global__ void k_tr_count(const int32_t* __restrict__ rp, const int32_t* __restrict__ c, int n,
+                           int32_t* __restrict__ cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(&cnt[c[p]], 1);
+}
+__global__ void k_tr_fill(const int32_t* __restrict__ rp, const int32_t* __restrict__ c, int n,
+                          const int32_t* __restrict__ trp, int32_t* __restrict__ fill,
+                          int32_t* __restrict__ tc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    const int j = c[p];
+    tc[trp[j] + atomicAdd(&fill[j], 1)] = i;
+  }
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
+
+void check_lds(size_t bytes, const char* what) {
+  if (bytes > 160 * 1024)
+    fail(GB_EUNSUPPORTED, "%s needs %zu bytes of LDS per workgroup (limit 163840)", what, bytes);
+}
+
+// union of one or two CSRs plus self-loops -> out (sorted rows)
+void union_rows(int n, const int32_t* rp0, const int32_t* c0, const int32_t* rp1,
+                const int32_t* c1, Csr& out, hipStream_t s) {
+  const int nw = (n + 31) >> 5;
+  const size_t lds = (size_t)nw * 8 + kT * 4 + 64;
+  check_lds(lds, "graph row union");
+  DBuf<int32_t> cnt(n, s);
+  out.n = n;
+  out.row_ptr = DBuf<int32_t>(n + 1, s);
+  hipLaunchKernelGGL(k_union_rows<0>, dim3(n), dim3(kT), lds, s, n, rp0, c0, rp1, c1, cnt.get(),
+                     nullptr, nullptr);
+  GB_LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
+  int32_t nnz = 0;
+  GB_HIP(hipMemcpyAsync(&nnz, out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  out.nnz = nnz;
+  out.col = DBuf<int32_t>(nnz, s);
+  hipLaunchKernelGGL(k_union_rows<1>, dim3(n), dim3(kT), lds, s, n, rp0, c0, rp1, c1, nullptr,
+                     out.row_ptr.get(), out.col.get());
+  GB_LAUNCH_CHECK();
+}
+
+// CSR of the entries |a| >= tau of an ELL matrix (row-wise, rows ascending)
+void ell_threshold(const gb_ell& A, double tau, DBuf<int32_t>& rp, DBuf<int32_t>& c,
+                   hipStream_t s) {
+  const int n = A.n;
+  DBuf<int32_t> cnt(n, s);
+  rp = DBuf<int32_t>(n + 1, s);
+  hipLaunchKernelGGL(k_ell_threshold<0>, dim3(blocks_for(n, kT)), dim3(kT), 0, s, A.col, A.val, n,
+                     A.width, tau, cnt.get(), nullptr, nullptr);
+  GB_LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.get(), rp.get(), n, s);
+  int32_t nnz = 0;
+  GB_HIP(hipMemcpyAsync(&nnz, rp.get() + n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  c = DBuf<int32_t>(nnz > 0 ? nnz : 1, s);
+  hipLaunchKernelGGL(k_ell_threshold<1>, dim3(blocks_for(n, kT)), dim3(kT), 0, s, A.col, A.val, n,
+                     A.width, tau, nullptr, rp.get(), c.get());
+  GB_LAUNCH_CHECK();
+}
+
+void transpose(int n, const int32_t* rp, const int32_t* c, int64_t nnz, DBuf<int32_t>& trp,
+               DBuf<int32_t>& tc, hipStream_t s) {
+  DBuf<int32_t> cnt(n, s), fill(n, s);
+  hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, kT)), dim3(kT), 0, s, cnt.get(), (int64_t)n);
+  hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, kT)), dim3(kT), 0, s, fill.get(), (int64_t)n);
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_tr_count, dim3(blocks_for(n, kT)), dim3(kT), 0, s, rp, c, n, cnt.get());
+  GB_LAUNCH_CHECK();
+  trp = DBuf<int32_t>(n + 1, s);
+  exclusive_scan_i32(cnt.get(), trp.get(), n, s);
+  tc = DBuf<int32_t>(nnz > 0 ? nnz : 1, s);
+  hipLaunchKernelGGL(k_tr_fill, dim3(blocks_for(n, kT)), dim3(kT), 0, s, rp, c, n, trp.get(),
+                     fill.get(), tc.get());
+  GB_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void bounds(const gb_ell& H, hipStream_t s, double* emin, double* emax) {
+  const int n = H.n;
+  DBuf<double> lo(n, s), hi(n, s), out(2, s);
+  hipLaunchKernelGGL(k_row_discs, dim3(blocks_for(n, kT)), dim3(kT), 0, s, H.col, H.val, n,
+                     H.width, lo.get(), hi.get());
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_minmax, dim3(1), dim3(kT), 0, s, lo.get(), hi.get(), n, out.get());
+  GB_LAUNCH_CHECK();
+  double h[2];
+  GB_HIP(hipMemcpyAsync(h, out.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  *emin = h[0];
+  *emax = h[1];
+}
+
+void x0_ell(const gb_ell& H, double emin, double emax, double* x0, hipStream_t s) {
+  const int64_t tot = (int64_t)H.n * H.width;
+  const double denom = emax - emin;
+  hipLaunchKernelGGL(k_x0, dim3(blocks_for(tot, kT)), dim3(kT), 0, s, H.col, H.val, H.n, H.width,
+                     emax, denom, x0);
+  GB_LAUNCH_CHECK();
+}
+
+void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s) {
+  const int n = H.n, w = H.width;
+  // candidate capacity: at most w*w two-hop candidates, at most n, bounded by LDS
+  const size_t fixed = x2_lds_bytes(n, w, 0);
+  if (fixed > 150 * 1024) fail(GB_EUNSUPPORTED, "X2 graph: n = %d too large for one LDS bitmap", n);
+  int64_t cap = std::min<int64_t>((int64_t)w * w, n);
+  cap = std::min<int64_t>(cap, (int64_t)((160 * 1024 - fixed) / 8));
+  const size_t lds = x2_lds_bytes(n, w, (int)cap);
+  check_lds(lds, "X2 graph");
+  DBuf<int32_t> cnt(n, s), ovf(1, s);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
+  hipLaunchKernelGGL(k_x2_rows<0>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
+                     cnt.get(), nullptr, nullptr, ovf.get());
+  GB_LAUNCH_CHECK();
+  out.n = n;
+  out.row_ptr = DBuf<int32_t>(n + 1, s);
+  exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
+  int32_t h[2];
+  GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(&h[1], ovf.get(), 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  if (h[1] > 0)
+    fail(GB_EUNSUPPORTED, "X2 graph: a row has %d two-hop candidates, LDS capacity is %lld", h[1],
+         (long long)cap);
+  out.nnz = h[0];
+  out.col = DBuf<int32_t>(h[0] > 0 ? h[0] : 1, s);
+  hipLaunchKernelGGL(k_x2_rows<1>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
+                     nullptr, out.row_ptr.get(), out.col.get(), ovf.get());
+  GB_LAUNCH_CHECK();
+}
+
+void graph_pattern(const gb_ell& A, double tau, Csr& out, hipStream_t s) {
+  DBuf<int32_t> rp, c, trp, tc;
+  ell_threshold(A, tau, rp, c, s);
+  int32_t nnz = 0;
+  GB_HIP(hipMemcpyAsync(&nnz, rp.get() + A.n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  transpose(A.n, rp.get(), c.get(), nnz, trp, tc, s);
+  union_rows(A.n, rp.get(), c.get(), trp.get(), tc.get(), out, s);
+}
+
+void graph_union_dprev(const Csr& base, const gb_ell& Dp, double tau_d, Csr& out,
+                       hipStream_t s) {
+  // column-ELL row i lists the rows r of column i with |D_ri| >= tau_d: edges (r, i).
+  // The union of base (symmetric), that list (row i gets r) and its transpose (row r gets i)
+  // is symmetric.
+  DBuf<int32_t> rp, c, trp, tc;
+  ell_threshold(Dp, tau_d, rp, c, s);
+  int32_t nnz = 0;
+  GB_HIP(hipMemcpyAsync(&nnz, rp.get() + Dp.n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  transpose(Dp.n, rp.get(), c.get(), nnz, trp, tc, s);
+  Csr tmp;
+  union_rows(Dp.n, rp.get(), c.get(), trp.get(), tc.get(), tmp, s);
+  union_rows(Dp.n, base.row_ptr.get(), base.col.get(), tmp.row_ptr.get(), tmp.col.get(), out, s);
+}
+
+}  // namespace gbi

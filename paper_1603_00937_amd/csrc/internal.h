@@ -1,0 +1,99 @@
+// Internal declarations shared by the libgb translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/gb.h"
+
+namespace gbi {
+
+// ---- errors: C++ exceptions never cross the C ABI; api.hip converts them to codes ----
+struct Error {
+  gb_status code;
+};
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+[[noreturn]] void fail(gb_status code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define GB_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      ::gbi::fail(GB_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                  __LINE__);                                                                \
+  } while (0)
+
+#define GB_LAUNCH_CHECK() GB_HIP(hipGetLastError())
+
+// ---- device memory: stream-ordered allocations from the device pool ----
+void* dmalloc(size_t bytes, hipStream_t s);
+void dfree(void* p, hipStream_t s);
+
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipStream_t s = nullptr;
+  DBuf() = default;
+  DBuf(size_t count, hipStream_t st) : n(count), s(st) {
+    if (count) p = static_cast<T*>(dmalloc(count * sizeof(T), st));
+  }
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() {
+    if (p) dfree(p, s);
+    p = nullptr;
+    n = 0;
+  }
+  T* get() const { return p; }
+};
+
+// ---- scans (scan.hip) ----
+// out[0..n] = exclusive prefix sums of in[0..n-1]; out[n] = total.
+void exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t s);
+void exclusive_scan_i64(const int32_t* in, int64_t* out, int n, hipStream_t s);
+
+// ---- graph (graph.hip) ----
+struct Csr {
+  int32_t n = 0;
+  int64_t nnz = 0;
+  DBuf<int32_t> row_ptr, col;
+};
+void bounds(const gb_ell& H, hipStream_t s, double* emin, double* emax);  // synchronises
+void x0_ell(const gb_ell& H, double emin, double emax, double* x0, hipStream_t s);
+void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s);
+void graph_pattern(const gb_ell& A, double tau, Csr& out, hipStream_t s);
+void graph_union_dprev(const Csr& base, const gb_ell& Dp, double tau_d, Csr& out,
+                       hipStream_t s);
+
+// ---- partition (partition.hip) ----
+struct Part {
+  int32_t n = 0, n_sub = 0, max_sub = 0;
+  int64_t total = 0;
+  DBuf<int32_t> core_ptr, core_vtx, sub_ptr, sub_idx;
+  DBuf<int32_t> sub_pos;            // rank of sub_idx[p] in its subgraph's ascending order
+  DBuf<int32_t> col_sub, col_loc;   // vertex -> (subgraph, local index) of its core
+  std::vector<int32_t> h_core_ptr, h_sub_ptr;  // host copies (sizes for planning)
+};
+void partition_block(const Csr& g, int32_t core_size, Part& out, hipStream_t s);
+
+}  // namespace gbi
+
+// graph / partition handles behind the opaque ABI types
+struct gb_graph_s {
+  gbi::Csr csr;
+};
+struct gb_partition_s {
+  gbi::Part part;
+};

@@ -1,0 +1,110 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and rejects bad
+arguments on the host with the documented codes before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gb.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gb_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1603_00937_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1603_00937_amd.build import build
+        build()
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "gb_density" in names and "gb_build_graph" in names and "gb_partition" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1603_00937_amd import _lib
+    assert set(_declared()) == set(_lib.SIGNATURES)
+
+
+def test_version(lib):
+    assert lib.gb_version().startswith(b"libgb")
+
+
+def _err(lib):
+    return lib.gb_last_error().decode()
+
+
+def test_density_rejects_bad_arguments(lib):
+    from paper_1603_00937_amd._lib import GbEll, GbSp2Opts, GB_EINVAL, GB_ESHAPE
+    bogus = 0x1000  # never dereferenced: the checks fail first
+    H = GbEll(8, 3, bogus, bogus)
+    D = GbEll(8, 3, bogus, bogus)
+    assert lib.gb_density(None, 4, 1e-5, None, ctypes.byref(D), None, None) == GB_EINVAL
+    assert "H is NULL" in _err(lib)
+    assert lib.gb_density(ctypes.byref(H), 9, 1e-5, None, ctypes.byref(D), None, None) == GB_EINVAL
+    assert "n_occ" in _err(lib)
+    assert lib.gb_density(ctypes.byref(H), -1, 1e-5, None, ctypes.byref(D), None, None) == GB_EINVAL
+    assert lib.gb_density(ctypes.byref(H), 4, float("nan"), None, ctypes.byref(D), None,
+                          None) == GB_EINVAL
+    assert lib.gb_density(ctypes.byref(H), 4, -1.0, None, ctypes.byref(D), None, None) == GB_EINVAL
+    D2 = GbEll(7, 3, bogus, bogus)
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, None, ctypes.byref(D2), None, None) == GB_ESHAPE
+    o = GbSp2Opts()
+    o.precision = 7
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                          None) == GB_EINVAL
+    o = GbSp2Opts()
+    o.max_iter = 500
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                          None) == GB_EINVAL
+    o = GbSp2Opts()
+    bad = (ctypes.c_uint8 * 2)(0, 3)
+    o.branch_in = ctypes.cast(bad, ctypes.c_void_p)
+    o.n_branch_in = 2
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                          None) == GB_EINVAL
+    assert "branch_in" in _err(lib)
+    o = GbSp2Opts()
+    o.emin, o.emax = 2.0, 1.0
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                          None) == GB_EINVAL
+
+
+def test_graph_and_partition_reject_bad_arguments(lib):
+    from paper_1603_00937_amd._lib import GbEll, GB_EINVAL
+    bogus = 0x1000
+    H = GbEll(8, 3, bogus, bogus)
+    out = ctypes.c_void_p()
+    assert lib.gb_build_graph(ctypes.byref(H), None, -1.0, 0.0, 0, None, ctypes.byref(out)) == GB_EINVAL
+    assert lib.gb_build_graph(ctypes.byref(H), None, 1e-5, 0.0, 9, None, ctypes.byref(out)) == GB_EINVAL
+    assert lib.gb_build_graph(ctypes.byref(H), None, 1e-5, 0.0, 2, None, ctypes.byref(out)) == GB_EINVAL
+    assert lib.gb_build_graph(None, None, 1e-5, 0.0, 0, None, ctypes.byref(out)) == GB_EINVAL
+    Hn = GbEll(0, 3, bogus, bogus)
+    assert lib.gb_build_graph(ctypes.byref(Hn), None, 1e-5, 0.0, 0, None, ctypes.byref(out)) == GB_EINVAL
+    assert lib.gb_partition(None, 16, 0, None, ctypes.byref(out)) == GB_EINVAL
+    assert lib.gb_graph_info(None, None, None) == GB_EINVAL
+    lib.gb_graph_destroy(None)
+    lib.gb_partition_destroy(None)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    assert lib.gb_spectral_bounds(None, None, ctypes.byref(lo), ctypes.byref(hi)) == GB_EINVAL
+    assert lib.gb_spectral_bounds(ctypes.byref(H), None, None, None) == GB_EINVAL
+
+
+def test_no_cpu_fallback_in_product_path():
+    """The package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_1603_00937_amd")
+    for fn in os.listdir(pkg):
+        if fn.endswith(".py"):
+            src = open(os.path.join(pkg, fn)).read()
+            assert "oracle" not in src, fn
