@@ -19,14 +19,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "orbitals/s of D at ≤1e-6 err vs FP64 oracle; mixed vs FP64 GPU; X² MFMA util"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-WORKLOADS = {"n18000": dict(tau=1e-5, core=32), "n1024": dict(tau=1e-5, core=16)}
+# dense matrix-core peaks of the precision the dominant squaring kernel runs in (TFLOP/s)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "bf16x6": 2500.0}
+# bf16 plane products per algorithmic multiply-add
+PLANE_PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6}
+WORKLOADS = {"n18000": dict(tau=1e-5, core=32), "n1024": dict(tau=1e-5, core=16),
+             "n100000": dict(tau=1e-5, core=32)}
 
 
-def run_step(gb, Hc, Hv, n_occ, tau, core, precision, D):
+def run_step(gb, Hc, Hv, n_occ, tau, core, precision, D, launch_mode):
     g = gb.build_graph(Hc, Hv, tau)
     p = gb.partition(g, core)
-    return gb.density(Hc, Hv, n_occ, tau, partition=p, core_size=core, precision=precision, D=D)
+    return gb.density(Hc, Hv, n_occ, tau, partition=p, core_size=core, precision=precision, D=D,
+                      launch_mode=launch_mode)
+
+
+def copy_calibration(nbytes=4 << 30, reps=5):
+    """A plain device copy of known size (the scale for rocprof FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
 def sample_error(D_col, D_val, golden):
@@ -80,11 +96,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64",
+                    choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
+    ap.add_argument("--launch-mode", default="batched", choices=["batched", "per_subgraph", "graph"])
+    ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12)
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(subgraphs would shard across GPUs with one 16-byte trace all-reduce per "
@@ -111,42 +133,50 @@ def main():
          torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
     del g, p
     for _ in range(args.warmup):
-        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D)
+        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D, args.launch_mode)
     torch.cuda.synchronize()
-    sq_ms, sq_n, flops_alg, flops_exec, stats = 0.0, 0, 0.0, 0.0, None
+    low = args.precision != "fp64"
+    key = "square_lo" if low else "square"
+    sq_ms, sq_n, stats = 0.0, 0, None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D)
-        sq_ms += stats["ms"]["square"]
-        sq_n += stats["n_square"]
+        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D,
+                               args.launch_mode)
+        sq_ms += stats["ms"][key]
+        sq_n += stats["n_" + key]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     flops_alg = stats["square_flops"]
-    flops_exec = stats["square_flops_exec"]
-    avg_launch_s = sq_ms / sq_n / 1e3
-    # the FP32 path also runs FP64 refinement squares; the roofline is quoted for the
-    # dominant kernel at the precision of the bulk of its launches
+    flops_exec = stats["square_flops_exec"] * PLANE_PRODUCTS.get(args.precision, 1)
+    # the dominant kernel is the squaring launch of the loop's precision (the low-precision
+    # path also runs a few FP64 refinement squares, reported in stage_ms)
     peak = PEAK_TFLOPS[args.precision]
+    avg_launch_s = (sq_ms / sq_n / 1e3) if sq_n else float("nan")
     achieved = flops_alg / avg_launch_s / 1e12
     err, pattern_ok = (sample_error(D[0], D[1], golden) if golden else (None, None))
     out = {
         "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64"}.get(args.precision, "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: seeded 3D tight-binding model, N={N} orbitals, "
                                f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}",
-                   "precision": args.precision, "n_sub": stats["n_sub"],
+                   "precision": args.precision, "launch_mode": args.launch_mode,
+                   "n_sub": stats["n_sub"],
                    "max_sub": stats["max_sub"], "sp2_iters": stats["iters"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_symm_mm (batched X^2)",
+                     "kernel": "k_symm_mm_bf16 (batched X^2)" if args.precision.startswith("bf16")
+                     else "k_symm_mm (batched X^2)",
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
                      "exec_tflops": flops_exec / avg_launch_s / 1e12,
                      "avg_launch_ms": avg_launch_s * 1e3},
         "accuracy": {"max_abs_err_vs_oracle_samples": err, "D_pattern_bit_exact": pattern_ok,
-                     "converged": stats["converged"], "trace_D": stats["trace"]},
+                     "converged": stats["converged"], "trace_D": stats["trace"],
+                     "idem_max": stats["idem_max"], "branch": "".join(map(str, stats["branch"])),
+                     "branch_matches_oracle": (golden is not None and
+                                               "".join(map(str, stats["branch"])) == golden["branch"])},
         "stage_ms": stats["ms"],
     }
     if not args.no_cpu_baseline:

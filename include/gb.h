@@ -122,9 +122,14 @@ gb_status gb_partition_copy(const gb_partition_t* p, int32_t* core_ptr, int32_t*
 void gb_partition_destroy(gb_partition_t* p);
 
 /* Arithmetic of the squaring loop. */
+/* Low-precision variants square an FP32 iterate, keep the traces and the branch decision in
+ * FP64, and finish with FP64 SP2 steps (refinement) until the FP64 stop rule holds. */
 typedef enum {
-  GB_FP64 = 0,        /* every square in FP64 on the matrix cores                         */
-  GB_FP32_REFINE = 1  /* squares in FP32 (FP32 accumulate), then FP64 refinement steps      */
+  GB_FP64 = 0,          /* every square in FP64 on the matrix cores                         */
+  GB_FP32_REFINE = 1,   /* squares on FP32 MFMA (FP32 accumulate), then FP64 refinement      */
+  GB_BF16_REFINE = 2,   /* squares on BF16 MFMA from one bf16 plane (FP32 accumulate)        */
+  GB_BF16X3_REFINE = 3, /* two bf16 planes hi + lo, three products (about 16 bits)           */
+  GB_BF16X6_REFINE = 4  /* three bf16 planes, six products (about FP32 precision)            */
 } gb_precision;
 
 typedef struct {
@@ -137,6 +142,14 @@ typedef struct {
   const uint8_t* branch_in;  /* (host) replay this branch sequence instead of choosing it    */
   int32_t n_branch_in;
   double emin, emax;         /* spectral bounds; both 0 = Gershgorin                          */
+  int32_t keep_tape;         /* 1: keep SP2 checkpoints for gb_density_vjp (GB_FP64 only)    */
+  int32_t tape_stride;       /* checkpoint every tape_stride-th iterate; 0 = 4               */
+  int32_t launch_mode;       /* 0: one batched squaring launch per step, the host reads the   *
+                              *    stop flag after every step (default);                      *
+                              * 1: one launch per subgraph per step (baseline);               *
+                              * 2: batched launches with the stop flag, counter and branch    *
+                              *    records on the device, two steps captured in a hipGraph    *
+                              *    and replayed (no host round trip per step; no tape)        */
 } gb_sp2_opts;
 
 typedef struct {
@@ -151,11 +164,16 @@ typedef struct {
   double min_margin;         /* smallest | |t2-n| - |2t1-t2-n| | over chosen branches        */
   double t1[128], t2[128];   /* core traces of X and X^2 at each square                      */
   float ms_bounds, ms_graph, ms_part, ms_gather, ms_sp2, ms_refine, ms_scatter, ms_total;
-  float ms_square;           /* summed device time of the squaring kernel launches           */
-  int32_t n_square;          /* number of squaring kernel launches                           */
+  float ms_square;           /* summed device time of the FP64 squaring launches (mode 0, 1) */
+  int32_t n_square;          /* number of FP64 squaring launches                             */
+  float ms_square_lo;        /* the same for the low-precision squaring launches             */
+  int32_t n_square_lo;
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
+  struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */
 } gb_sp2_stats;
+
+typedef struct gb_tape_s gb_tape_t;
 
 /*
  * a5-a12. Density matrix D = P_tau(X0) of the partitioned SP2 expansion (Eq. 6 with the SP2
@@ -170,6 +188,23 @@ typedef struct {
  */
 gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_sp2_opts* opts,
                      gb_ell* D, gb_sp2_stats* stats, void* stream);
+
+/*
+ * a14. Adjoint of the expansion recorded by gb_density(keep_tape = 1): given dL/dD on D's
+ * column-ELL pattern (G_D: n x width with the same layout as the D that call produced; only
+ * G_D->val is read), write dL/dH per ELL slot of H into G_H->val.  G_H->col must be H's column
+ * array (the pattern is read from it; G_H->width = H's width).  Observables are traces with D
+ * (<A> = Tr[D A], SP2 paragraph after Eq. 7); the derivative runs the recursion backwards with
+ * the graph, partition, spectral bounds and branch sequence held fixed:
+ *   X <- X^2:       Gbar <- Gbar X + X Gbar;      X <- 2X - X^2:  Gbar <- 2 Gbar - (Gbar X + X Gbar)
+ * seeded with the symmetric part of dL/dD on each block's core columns, and
+ * dL/dh = -Gbar_0 / (e_max - e_min) summed over every subgraph holding both vertices (ascending
+ * subgraph order, deterministic).  The result is the symmetric per-slot gradient: perturbing
+ * H_ij and H_ji together by h changes L by h (G_ij + G_ji).  Segments between checkpoints are
+ * recomputed forward.  Synchronises `stream`.  The tape stays valid until gb_tape_destroy.
+ */
+gb_status gb_density_vjp(const gb_tape_t* tape, const gb_ell* G_D, gb_ell* G_H, void* stream);
+void gb_tape_destroy(gb_tape_t* tape);
 
 #ifdef __cplusplus
 }

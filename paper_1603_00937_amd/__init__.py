@@ -4,5 +4,6 @@ Every step runs in the HIP library ``libgb.so``; this package only marshals torc
 device tensors (memory) and the current HIP stream into the C ABI of include/gb.h.
 """
 from .api import (  # noqa: F401
-    GbError, Graph, Partition, spectral_bounds, build_graph, partition, density, version,
+    GbError, Graph, Partition, Tape, DensityFn, spectral_bounds, build_graph, partition, density,
+    density_with_grad, version,
 )

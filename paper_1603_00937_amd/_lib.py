@@ -10,7 +10,7 @@ STATUS_NAMES = {0: "GB_OK", -1: "GB_EINVAL", -2: "GB_ENOMEM", -3: "GB_EHIP", -4:
                 -5: "GB_EUNSUPPORTED"}
 GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2}
 PART_METHODS = {"block": 0}
-PRECISIONS = {"fp64": 0, "fp32": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4}
 
 
 class GbEll(ctypes.Structure):
@@ -23,7 +23,9 @@ class GbSp2Opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("idem_tol", ctypes.c_double),
                 ("partition", ctypes.c_void_p), ("core_size", ctypes.c_int32),
                 ("branch_in", ctypes.c_void_p), ("n_branch_in", ctypes.c_int32),
-                ("emin", ctypes.c_double), ("emax", ctypes.c_double)]
+                ("emin", ctypes.c_double), ("emax", ctypes.c_double),
+                ("keep_tape", ctypes.c_int32), ("tape_stride", ctypes.c_int32),
+                ("launch_mode", ctypes.c_int32)]
 
 
 class GbSp2Stats(ctypes.Structure):
@@ -39,7 +41,9 @@ class GbSp2Stats(ctypes.Structure):
                 ("ms_sp2", ctypes.c_float), ("ms_refine", ctypes.c_float),
                 ("ms_scatter", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_square", ctypes.c_float), ("n_square", ctypes.c_int32),
-                ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double)]
+                ("ms_square_lo", ctypes.c_float), ("n_square_lo", ctypes.c_int32),
+                ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double),
+                ("tape", ctypes.c_void_p)]
 
 
 _P = ctypes.POINTER
@@ -61,6 +65,8 @@ SIGNATURES = {
     "gb_partition_destroy": (None, [_vp]),
     "gb_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double, _P(GbSp2Opts),
                                     _P(GbEll), _P(GbSp2Stats), _vp]),
+    "gb_density_vjp": (ctypes.c_int32, [_vp, _P(GbEll), _P(GbEll), _vp]),
+    "gb_tape_destroy": (None, [_vp]),
 }
 
 _lib = None

@@ -141,15 +141,42 @@ def _stats_dict(st: L.GbSp2Stats) -> dict:
         "t1": list(st.t1[:nt]), "t2": list(st.t2[:nt]),
         "ms": {n: getattr(st, "ms_" + n) for n in
                ("bounds", "graph", "part", "gather", "sp2", "refine", "scatter", "total",
-                "square")},
-        "n_square": st.n_square, "square_flops": st.square_flops,
+                "square", "square_lo")},
+        "n_square": st.n_square, "n_square_lo": st.n_square_lo, "square_flops": st.square_flops,
         "square_flops_exec": st.square_flops_exec,
     }
 
 
+class Tape:
+    """Recorded SP2 expansion (checkpoints) for the adjoint."""
+
+    def __init__(self, handle, H_col, width):
+        self._h = handle
+        self.H_col = H_col
+        self.width = width
+
+    def vjp(self, G_D_val, G_H_val=None):
+        """dL/dH on H's ELL pattern from dL/dD on D's column-ELL pattern."""
+        _dev(G_D_val, torch.float64, "G_D_val")
+        n = self.H_col.shape[0]
+        if G_D_val.dim() != 2 or G_D_val.shape[0] != n:
+            raise ValueError("G_D_val must be [n, width]")
+        if G_H_val is None:
+            G_H_val = torch.empty(self.H_col.shape, dtype=torch.float64, device="cuda")
+        Gd = L.GbEll(n, G_D_val.shape[1], None, G_D_val.data_ptr())
+        Gh = _ell(self.H_col, G_H_val)
+        _check(_lib().gb_density_vjp(self._h, ctypes.byref(Gd), ctypes.byref(Gh), _stream()))
+        return G_H_val
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib().gb_tape_destroy(self._h)
+            self._h = None
+
+
 def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precision="fp64",
             n_refine=0, max_iter=0, idem_tol=0.0, branch_in=None, emin=None, emax=None,
-            D=None):
+            D=None, keep_tape=False, tape_stride=0, launch_mode=0):
     """Partitioned SP2 density matrix.  Returns (D_col, D_val, stats); D is column-ELL
     [n, max_sub] (row i of the arrays = column i of D).  With ``partition`` None the X2 graph
     at ``threshold`` and a block partition with ``core_size`` are built first."""
@@ -178,7 +205,44 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
         o.n_branch_in = len(branch_in)
     if emin is not None and emax is not None:
         o.emin, o.emax = float(emin), float(emax)
+    o.keep_tape = 1 if keep_tape else 0
+    o.tape_stride = int(tape_stride)
+    o.launch_mode = {"batched": 0, "per_subgraph": 1, "graph": 2}.get(launch_mode, launch_mode)
     st = L.GbSp2Stats()
     _check(_lib().gb_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),
                              ctypes.byref(De), ctypes.byref(st), _stream()))
-    return D_col, D_val, _stats_dict(st)
+    out = _stats_dict(st)
+    if keep_tape:
+        out["tape"] = Tape(ctypes.c_void_p(st.tape), H_col, D_col.shape[1])
+    return D_col, D_val, out
+
+
+class DensityFn(torch.autograd.Function):
+    """D_val = DensityFn.apply(H_val, H_col, n_occ, threshold, partition, core_size):
+    the partitioned SP2 density matrix (column-ELL values; the row indices are in
+    ``ctx``-independent D_col returned by :func:`density_with_grad`).  Backward runs the
+    library's adjoint; the graph, partition, bounds and branch sequence are held fixed."""
+
+    @staticmethod
+    def forward(ctx, H_val, H_col, n_occ, threshold, part, core_size, D_col_out):
+        D_col, D_val, st = density(H_col, H_val.detach(), n_occ, threshold, partition=part,
+                                   core_size=core_size, keep_tape=True)
+        D_col_out.append(D_col)
+        D_col_out.append(st)
+        ctx.tape = st.pop("tape")
+        ctx.mark_non_differentiable(D_col)
+        return D_val
+
+    @staticmethod
+    def backward(ctx, g):
+        G_H = ctx.tape.vjp(g.contiguous())
+        return G_H, None, None, None, None, None, None
+
+
+def density_with_grad(H_col, H_val, n_occ, threshold, partition=None, core_size=32):
+    """(D_col, D_val, stats) with D_val differentiable with respect to H_val."""
+    if partition is None:
+        partition = globals()["partition"](build_graph(H_col, H_val.detach(), threshold), core_size)
+    box = []
+    D_val = DensityFn.apply(H_val, H_col, n_occ, threshold, partition, core_size, box)
+    return box[0], D_val, box[1]

@@ -53,7 +53,22 @@ void dfree(void* p, hipStream_t s) {
 }
 
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
-             double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s);
+             double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s,
+             TapeData** tape_out);
+
+void detach(Csr& c) {
+  c.row_ptr.detach_stream();
+  c.col.detach_stream();
+}
+void detach(Part& p) {
+  p.core_ptr.detach_stream();
+  p.core_vtx.detach_stream();
+  p.sub_ptr.detach_stream();
+  p.sub_idx.detach_stream();
+  p.sub_pos.detach_stream();
+  p.col_sub.detach_stream();
+  p.col_loc.detach_stream();
+}
 
 }  // namespace gbi
 
@@ -144,6 +159,7 @@ gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double 
         }
       }
       GB_HIP(hipStreamSynchronize(s));
+      detach(g->csr);
     } catch (...) {
       delete g;
       throw;
@@ -188,6 +204,7 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
     try {
       partition_block(g->csr, core_size, p->part, s);
       GB_HIP(hipStreamSynchronize(s));
+      detach(p->part);
     } catch (...) {
       delete p;
       throw;
@@ -237,7 +254,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     check_tau(threshold, "threshold");
     gb_sp2_opts o{};
     if (opts) o = *opts;
-    if (o.precision != GB_FP64 && o.precision != GB_FP32_REFINE)
+    if (o.precision < GB_FP64 || o.precision > GB_BF16X6_REFINE)
       fail(GB_EINVAL, "unknown precision %d", o.precision);
     if (o.max_iter < 0 || o.n_refine < 0) fail(GB_EINVAL, "max_iter / n_refine must be >= 0");
     if (!(o.idem_tol >= 0.0)) fail(GB_EINVAL, "idem_tol must be >= 0");
@@ -247,6 +264,12 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
       for (int i = 0; i < o.n_branch_in; ++i)
         if (o.branch_in[i] > 1) fail(GB_EINVAL, "branch_in[%d] = %d is not 0 or 1", i, o.branch_in[i]);
     if ((o.max_iter > 0 ? o.max_iter : 100) > 127) fail(GB_EINVAL, "max_iter must be <= 127");
+    if (o.keep_tape && o.precision != GB_FP64)
+      fail(GB_EUNSUPPORTED, "keep_tape needs precision GB_FP64");
+    if (o.tape_stride < 0) fail(GB_EINVAL, "tape_stride must be >= 0");
+    if (o.launch_mode < 0 || o.launch_mode > 2) fail(GB_EINVAL, "unknown launch_mode %d", o.launch_mode);
+    if (o.keep_tape && o.launch_mode == 2)
+      fail(GB_EUNSUPPORTED, "keep_tape needs launch_mode 0 or 1");
     const bool given_bounds = !(o.emin == 0.0 && o.emax == 0.0);
     if (given_bounds && !(o.emax > o.emin)) fail(GB_EINVAL, "need emax > emin");
     if (o.partition && o.partition->part.n != H->n)
@@ -298,9 +321,40 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (D->width < P->max_sub)
       fail(GB_ESHAPE, "D->width = %d is smaller than the largest subgraph (%d)", D->width,
            P->max_sub);
-    density(*H, n_occ, o, *P, emin, emax, x0.get(), *D, st, s);
+    TapeData* tape = nullptr;
+    try {
+      density(*H, n_occ, o, *P, emin, emax, x0.get(), *D, st, s, o.keep_tape ? &tape : nullptr);
+    } catch (...) {
+      tape_destroy(tape);
+      throw;
+    }
+    if (tape) {
+      st.tape = new gb_tape_s{tape};
+    }
     st.ms_total += ms_front;
   });
+}
+
+gb_status gb_density_vjp(const gb_tape_t* tape, const gb_ell* G_D, gb_ell* G_H, void* stream) {
+  return guarded([&] {
+    if (!tape || !tape->data) fail(GB_EINVAL, "tape is NULL");
+    int tn = 0, tmax = 0;
+    tape_dims(tape->data, &tn, &tmax);
+    if (!G_D || !G_D->val) fail(GB_EINVAL, "G_D or G_D->val is NULL");
+    if (G_D->n != tn) fail(GB_ESHAPE, "G_D->n = %d, the tape has n = %d", G_D->n, tn);
+    if (G_D->width < tmax)
+      fail(GB_ESHAPE, "G_D->width = %d is smaller than the largest subgraph (%d)", G_D->width,
+           tmax);
+    check_ell(G_H, "G_H");
+    if (G_H->n != tn) fail(GB_ESHAPE, "G_H->n = %d, the tape has n = %d", G_H->n, tn);
+    density_vjp(*tape->data, *G_D, *G_H, G_H->val, as_stream(stream));
+  });
+}
+
+void gb_tape_destroy(gb_tape_t* tape) {
+  if (!tape) return;
+  tape_destroy(tape->data);
+  delete tape;
 }
 
 }  // extern "C"

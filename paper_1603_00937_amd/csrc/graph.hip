@@ -414,30 +414,38 @@ void x0_ell(const gb_ell& H, double emin, double emax, double* x0, hipStream_t s
 
 void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s) {
   const int n = H.n, w = H.width;
-  // candidate capacity: at most w*w two-hop candidates, at most n, bounded by LDS
+  // candidate capacity: small enough for several workgroups per CU; a row with more two-hop
+  // candidates makes the counting pass report its count, and both passes rerun with it
   const size_t fixed = x2_lds_bytes(n, w, 0);
   if (fixed > 150 * 1024) fail(GB_EUNSUPPORTED, "X2 graph: n = %d too large for one LDS bitmap", n);
-  int64_t cap = std::min<int64_t>((int64_t)w * w, n);
-  cap = std::min<int64_t>(cap, (int64_t)((160 * 1024 - fixed) / 8));
-  const size_t lds = x2_lds_bytes(n, w, (int)cap);
-  check_lds(lds, "X2 graph");
+  const int64_t cap_lds = (int64_t)((160 * 1024 - fixed) / 8);
+  int64_t cap = std::min<int64_t>(std::min<int64_t>((int64_t)w * w, n), 4096);
+  cap = std::min(cap, cap_lds);
   DBuf<int32_t> cnt(n, s), ovf(1, s);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
-  hipLaunchKernelGGL(k_x2_rows<0>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
-                     cnt.get(), nullptr, nullptr, ovf.get());
-  GB_LAUNCH_CHECK();
   out.n = n;
   out.row_ptr = DBuf<int32_t>(n + 1, s);
-  exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
   int32_t h[2];
-  GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
-  GB_HIP(hipMemcpyAsync(&h[1], ovf.get(), 4, hipMemcpyDeviceToHost, s));
-  GB_HIP(hipStreamSynchronize(s));
-  if (h[1] > 0)
-    fail(GB_EUNSUPPORTED, "X2 graph: a row has %d two-hop candidates, LDS capacity is %lld", h[1],
-         (long long)cap);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const size_t lds = x2_lds_bytes(n, w, (int)cap);
+    check_lds(lds, "X2 graph");
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
+    hipLaunchKernelGGL(k_x2_rows<0>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
+                       cnt.get(), nullptr, nullptr, ovf.get());
+    GB_LAUNCH_CHECK();
+    exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
+    GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(&h[1], ovf.get(), 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipStreamSynchronize(s));
+    if (h[1] == 0) break;
+    if (attempt == 1 || h[1] > cap_lds)
+      fail(GB_EUNSUPPORTED, "X2 graph: a row has %d two-hop candidates, LDS capacity is %lld",
+           h[1], (long long)cap_lds);
+    cap = ((h[1] + 255) / 256) * 256;
+    cap = std::min(cap, cap_lds);
+  }
   out.nnz = h[0];
   out.col = DBuf<int32_t>(h[0] > 0 ? h[0] : 1, s);
+  const size_t lds = x2_lds_bytes(n, w, (int)cap);
   hipLaunchKernelGGL(k_x2_rows<1>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
                      nullptr, out.row_ptr.get(), out.col.get(), ovf.get());
   GB_LAUNCH_CHECK();

@@ -57,6 +57,8 @@ struct DBuf {
     n = 0;
   }
   T* get() const { return p; }
+  // handle-owned buffers are freed on the null stream (the creating stream may be gone)
+  void detach_stream() { s = nullptr; }
 };
 
 // ---- scans (scan.hip) ----
@@ -87,6 +89,14 @@ struct Part {
   std::vector<int32_t> h_core_ptr, h_sub_ptr;  // host copies (sizes for planning)
 };
 void partition_block(const Csr& g, int32_t core_size, Part& out, hipStream_t s);
+void detach(Csr& c);
+void detach(Part& p);
+
+struct TapeData;  // SP2 checkpoints for the adjoint (sp2.hip)
+void tape_destroy(TapeData* t);
+void tape_dims(const TapeData* t, int* n, int* max_sub);
+void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H_pattern, double* G_H,
+                 hipStream_t s);
 
 }  // namespace gbi
 
@@ -96,4 +106,7 @@ struct gb_graph_s {
 };
 struct gb_partition_s {
   gbi::Part part;
+};
+struct gb_tape_s {
+  gbi::TapeData* data;
 };

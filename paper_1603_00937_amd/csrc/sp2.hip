@@ -8,7 +8,9 @@
 #include "internal.h"
 
 #include <cmath>
+#include <cstring>
 #include <numeric>
+#include <type_traits>
 
 #pragma clang fp contract(off)
 
@@ -116,11 +118,15 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
 // k slice [g*KC/4, (g+1)*KC/4): the contraction is a sum over k, so any k order shared by
 // both operands is valid, and each lane reads its slice with 16-byte LDS loads.
 //   MODE 0: out = A*B          MODE 1: out = alpha*(A*B) + beta*E   (E symmetric)
+//   MODE 3: out = A*B for a general (non-symmetric) product with B symmetric: every tile
+//           (bi, bj) is listed and nothing is mirrored (the adjoint's Gbar*X)
 template <typename T, int MODE>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, const T* __restrict__ B,
                                                    const T* __restrict__ E, T* __restrict__ out,
                                                    T alpha, T beta, const int4* __restrict__ tiles,
-                                                   const int64_t* __restrict__ offs) {
+                                                   const int64_t* __restrict__ offs,
+                                                   const int32_t* __restrict__ stopped) {
+  if (stopped && *stopped) return;  // device-driven loop: the expansion already stopped
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
   constexpr int KC = M::KC;
@@ -170,6 +176,12 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 
   const int g = lane >> 4, r16 = lane & 15;
   const int nk = np / KC;
+  // a wave whose 64-row or 64-column block lies in the padding beyond np has nothing to
+  // compute; on a diagonal tile of a symmetric product the lower-left block is the transpose
+  // of the upper-right one, which that wave writes twice
+  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
+  const bool lower_diag = MODE != 3 && bi == bj && wr > wc;
+  const bool active = in_range && !lower_diag;
   gload(0);
   sstore(0);
   __syncthreads();
@@ -179,7 +191,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
     const T* as = &As[buf][(wr * 64 + r16) * STR + g * KG];
     const T* bs = &Bs[buf][(wc * 64 + r16) * STR + g * KG];
 #pragma unroll
-    for (int h = 0; h < KG; h += V) {
+    for (int h = 0; h < KG && active; h += V) {
       T fa[4][V], fb[4][V];
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -199,8 +211,10 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
     __syncthreads();
   }
 
+  if (!active) return;
   T* o = out + off;
   const T* e = E + off;
+  const bool mirror = MODE != 3 && (bi != bj || wr < wc);
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -213,7 +227,134 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
           T v = acc[m][n][r];
           if (MODE == 1) v = alpha * v + beta * e[(int64_t)grow * np + gcol];
           o[(int64_t)grow * np + gcol] = v;
-          if (bi != bj) o[(int64_t)gcol * np + grow] = v;
+          if (mirror) o[(int64_t)gcol * np + grow] = v;
+        }
+      }
+}
+
+
+// ---- split-BF16 squaring of an FP32 iterate ------------------------------------------------
+// x = hi + mid + lo with each part rounded to bf16 from the running remainder; X*X is summed
+// over the plane products that keep about NP*8 bits (NP = 1: hi*hi; NP = 2: + hi*lo, lo*hi;
+// NP = 3: + hi*mid, mid*hi, hi*lo, lo*hi, mid*mid) on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation.  The leading product and the correction products accumulate separately and
+// are added once at the end.  Same tiling, symmetry and k-slice assignment as k_symm_mm (a
+// lane group owns 8 consecutive k of each 32-k chunk).
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+template <int NP>
+__global__ __launch_bounds__(kT, 2) void k_symm_mm_bf16(const float* __restrict__ X,
+                                                        float* __restrict__ out,
+                                                        const int4* __restrict__ tiles,
+                                                        const int64_t* __restrict__ offs,
+                                                        const int32_t* __restrict__ stopped) {
+  if (stopped && *stopped) return;
+  constexpr int KC = 32;            // k per chunk (one bf16 MFMA)
+  constexpr int STR = KC + 8;       // padded LDS row stride in bf16 elements (80 B)
+  __shared__ __align__(16) __bf16 As[NP][kBT * STR];
+  __shared__ __align__(16) __bf16 Bs[NP][kBT * STR];
+  const int4 tl = tiles[blockIdx.x];
+  const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
+  const int64_t off = offs[s];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int lr = tid >> 1, lh = tid & 1;
+  const int arow = bi * kBT + lr, brow = bj * kBT + lr;
+  const bool aok = arow < np, bok = brow < np;
+  const float* ap = X + off + (int64_t)(aok ? arow : 0) * np + lh * 16;
+  const float* bp = X + off + (int64_t)(bok ? brow : 0) * np + lh * 16;
+  float4 ra[4], rb[4];
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ra[q] = aok ? *reinterpret_cast<const float4*>(ap + k0 + 4 * q) : z4;
+      rb[q] = bok ? *reinterpret_cast<const float4*>(bp + k0 + 4 * q) : z4;
+    }
+  };
+  auto split_store = [&](const float4* r, __bf16 (*dst)[kBT * STR]) {
+    __bf16 pl[NP][16];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float v[4] = {r[q].x, r[q].y, r[q].z, r[q].w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float rem = v[e];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const __bf16 h = (__bf16)rem;
+          pl[p][4 * q + e] = h;
+          rem = rem - (float)h;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      __bf16* d = &dst[p][lr * STR + lh * 16];
+      __builtin_memcpy(d, &pl[p][0], 16);
+      __builtin_memcpy(d + 8, &pl[p][8], 16);
+    }
+  };
+  f4v big[4][4], small[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      big[m][n] = f4v{0, 0, 0, 0};
+      small[m][n] = f4v{0, 0, 0, 0};
+    }
+  const int g = lane >> 4, r16 = lane & 15;
+  const int nk = np / KC;
+  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
+  const bool active = in_range && !(bi == bj && wr > wc);
+  gload(0);
+  for (int kc = 0; kc < nk; ++kc) {
+    __syncthreads();
+    split_store(ra, As);
+    split_store(rb, Bs);
+    __syncthreads();
+    if (kc + 1 < nk) gload((kc + 1) * KC);
+    if (!active) continue;
+    bf8v fa[NP][4], fb[NP][4];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        __builtin_memcpy(&fa[p][m], &As[p][(wr * 64 + m * 16 + r16) * STR + g * 8], 16);
+        __builtin_memcpy(&fb[p][m], &Bs[p][(wc * 64 + m * 16 + r16) * STR + g * 8], 16);
+      }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        big[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][m], fb[0][n], big[m][n], 0, 0, 0);
+        if (NP >= 2) {
+          const int lo = NP - 1;
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][m], fb[lo][n], small[m][n], 0, 0, 0);
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[lo][m], fb[0][n], small[m][n], 0, 0, 0);
+        }
+        if (NP >= 3) {
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][m], fb[1][n], small[m][n], 0, 0, 0);
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][m], fb[0][n], small[m][n], 0, 0, 0);
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][m], fb[1][n], small[m][n], 0, 0, 0);
+        }
+      }
+  }
+  if (!active) return;
+  float* o = out + off;
+  const bool mirror = bi != bj || wr < wc;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int grow = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4) + r;
+        const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
+        if (grow < np && gcol < np) {
+          const float v = big[m][n][r] + small[m][n][r];
+          o[(int64_t)grow * np + gcol] = v;
+          if (mirror) o[(int64_t)gcol * np + grow] = v;
         }
       }
 }
@@ -282,6 +423,89 @@ __global__ __launch_bounds__(kT) void k_trace_branch(const T* __restrict__ X, co
     }
     *rec = q;
   }
+}
+
+
+// ---- device-driven loop (hipGraph): the stop flag, iteration counter and records live on the
+// device, so a captured pair of iterations can be replayed without host round trips.  After
+// every update the new iterate sits in the other buffer (X^2 is written there, and 2X - X^2
+// is formed in place), so buffer roles simply alternate.
+struct LoopState {
+  int32_t it, stopped, max_iter, n_forced;  // n_forced < 0: choose by the trace rule
+  int32_t stag, pad;
+  double n_occ, tol;
+  uint8_t forced[128];
+  StepRec recs[128];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kT) void k_trace_branch_dev(const T* __restrict__ X,
+                                                         const T* __restrict__ S,
+                                                         const int64_t* __restrict__ offs,
+                                                         const int32_t* __restrict__ npad,
+                                                         const int32_t* __restrict__ core_ptr,
+                                                         int n_sub, LoopState* __restrict__ st) {
+  if (st->stopped) return;
+  __shared__ double r1[kT], r2[kT];
+  double p1 = 0.0, p2 = 0.0;
+  for (int s = threadIdx.x; s < n_sub; s += kT) {
+    const int np = npad[s];
+    const int k = core_ptr[s + 1] - core_ptr[s];
+    const T* xs = X + offs[s];
+    const T* ss = S + offs[s];
+    for (int j = 0; j < k; ++j) {
+      p1 += (double)xs[(int64_t)j * np + j];
+      p2 += (double)ss[(int64_t)j * np + j];
+    }
+  }
+  r1[threadIdx.x] = p1;
+  r2[threadIdx.x] = p2;
+  __syncthreads();
+  for (int h = kT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int it = st->it;
+    const double t1 = r1[0], t2 = r2[0], n_occ = st->n_occ;
+    const double e = fabs(t1 - t2);
+    const double dsq = fabs(t2 - n_occ), dlin = fabs(2.0 * t1 - t2 - n_occ);
+    StepRec q;
+    q.t1 = t1;
+    q.t2 = t2;
+    q.e = e;
+    q.margin = fabs(dsq - dlin);
+    q.pad0 = q.pad1 = 0;
+    q.b = -1;
+    q.stop = 0;
+    if (st->n_forced >= 0) {
+      if (it >= st->n_forced) q.stop = 1;
+      else q.b = st->forced[it];
+    } else if (e <= st->tol) {
+      q.stop = 1;
+    } else if (it >= st->max_iter) {
+      q.stop = 2;
+    } else if (st->stag && it >= 9 && e > st->recs[it - 2].e) {
+      q.stop = 4;
+    } else {
+      q.b = dsq < dlin ? 0 : 1;
+    }
+    st->recs[it] = q;
+    if (q.stop) st->stopped = 1;
+    else st->it = it + 1;
+  }
+}
+
+template <typename T>
+__global__ void k_update_dev(const T* __restrict__ X, T* __restrict__ S, int64_t n,
+                             const LoopState* __restrict__ st) {
+  if (st->stopped || st->recs[st->it - 1].b != 1) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = i; p < n; p += stride) S[p] = (T)2 * X[p] - S[p];
 }
 
 // S <- 2X - S over the whole batch buffer (padding stays 0)
@@ -365,6 +589,132 @@ __global__ void k_max(const double* __restrict__ in, int n, double* __restrict__
   if (threadIdx.x == 0) *out = red[0];
 }
 
+
+// ---- adjoint kernels ------------------------------------------------------------------------
+__global__ void k_fill(double* __restrict__ p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = i; q < n; q += stride) p[q] = v;
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Gbar_K of every block from dL/dD on D's column-ELL pattern, symmetrised:
+// Gbar[a][j] = (G(a, j) + G(j, a)) / 2 with G(a, j) = dL/dD[sub_a, sub_j] on core columns j.
+__global__ __launch_bounds__(kT) void k_seed(const double* __restrict__ gval, int gw,
+                                             const int32_t* __restrict__ core_ptr,
+                                             const int32_t* __restrict__ sub_ptr,
+                                             const int32_t* __restrict__ sub_idx,
+                                             const int32_t* __restrict__ sub_pos,
+                                             const int64_t* __restrict__ offs,
+                                             const int32_t* __restrict__ npad,
+                                             double* __restrict__ G) {
+  const int s = blockIdx.x;
+  const int b = sub_ptr[s], n = sub_ptr[s + 1] - b, k = core_ptr[s + 1] - core_ptr[s];
+  const int np = npad[s];
+  double* g = G + offs[s];
+  for (int64_t p = threadIdx.x; p < (int64_t)n * k; p += kT) {
+    const int a = (int)(p / k), j = (int)(p - (int64_t)a * k);
+    double v = gval[(int64_t)sub_idx[b + j] * gw + sub_pos[b + a]];
+    if (a < k) v += gval[(int64_t)sub_idx[b + a] * gw + sub_pos[b + j]];
+    v *= 0.5;
+    g[(int64_t)a * np + j] = v;
+    if (a >= k) g[(int64_t)j * np + a] = v;
+  }
+}
+
+// out = c1 (P + P^T) + c2 G per block, through a 32 x 32 LDS transpose
+__global__ __launch_bounds__(256) void k_sym_combine(const double* __restrict__ P,
+                                                     const double* __restrict__ G,
+                                                     double* __restrict__ out, double c1, double c2,
+                                                     const int64_t* __restrict__ offs,
+                                                     const int32_t* __restrict__ npad, int max_nt) {
+  __shared__ double t[32][33];
+  const int s = blockIdx.y;
+  const int np = npad[s], nt = np / 32;
+  const int bx = blockIdx.x % max_nt, by = blockIdx.x / max_nt;
+  if (bx >= nt || by >= nt) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double* p = P + offs[s];
+  for (int r = ty; r < 32; r += 8) t[r][tx] = p[(int64_t)(bx * 32 + r) * np + by * 32 + tx];
+  __syncthreads();
+  const double* g = G + offs[s];
+  double* o = out + offs[s];
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t q = (int64_t)(by * 32 + r) * np + bx * 32 + tx;
+    o[q] = c1 * (p[q] + t[tx][r]) + c2 * g[q];
+  }
+}
+
+// vertex -> subgraphs holding it: counts, fill, per-vertex sort by subgraph
+__global__ void k_vs_count(const int32_t* __restrict__ sub_ptr, const int32_t* __restrict__ sub_idx,
+                           int32_t* __restrict__ cnt) {
+  const int s = blockIdx.x;
+  for (int p = sub_ptr[s] + threadIdx.x; p < sub_ptr[s + 1]; p += blockDim.x)
+    atomicAdd(&cnt[sub_idx[p]], 1);
+}
+__global__ void k_vs_fill(const int32_t* __restrict__ sub_ptr, const int32_t* __restrict__ sub_idx,
+                          const int32_t* __restrict__ vs_ptr, int32_t* __restrict__ fill,
+                          int32_t* __restrict__ vs_sub, int32_t* __restrict__ vs_loc) {
+  const int s = blockIdx.x;
+  for (int p = sub_ptr[s] + threadIdx.x; p < sub_ptr[s + 1]; p += blockDim.x) {
+    const int v = sub_idx[p];
+    const int q = vs_ptr[v] + atomicAdd(&fill[v], 1);
+    vs_sub[q] = s;
+    vs_loc[q] = p - sub_ptr[s];
+  }
+}
+__global__ void k_vs_sort(int n, const int32_t* __restrict__ vs_ptr, int32_t* __restrict__ vs_sub,
+                          int32_t* __restrict__ vs_loc) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  for (int p = vs_ptr[v] + 1; p < vs_ptr[v + 1]; ++p) {
+    const int ks = vs_sub[p], kl = vs_loc[p];
+    int q = p - 1;
+    while (q >= vs_ptr[v] && vs_sub[q] > ks) {
+      vs_sub[q + 1] = vs_sub[q];
+      vs_loc[q + 1] = vs_loc[q];
+      --q;
+    }
+    vs_sub[q + 1] = ks;
+    vs_loc[q + 1] = kl;
+  }
+}
+
+// dL/dH per ELL slot (i, j): sum over the subgraphs holding both i and j, ascending, of
+// scale * Gbar_0[loc(i)][loc(j)]
+__global__ void k_assemble(const int32_t* __restrict__ hcol, int n, int w,
+                           const int32_t* __restrict__ vs_ptr, const int32_t* __restrict__ vs_sub,
+                           const int32_t* __restrict__ vs_loc, const int64_t* __restrict__ offs,
+                           const int32_t* __restrict__ npad, const double* __restrict__ G0,
+                           double scale, double* __restrict__ gh) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= (int64_t)n * w) return;
+  const int i = (int)(q / w);
+  const int j = hcol[q];
+  if ((unsigned)j >= (unsigned)n) {
+    gh[q] = 0.0;
+    return;
+  }
+  int pi = vs_ptr[i], ei = vs_ptr[i + 1], pj = vs_ptr[j], ej = vs_ptr[j + 1];
+  double acc = 0.0;
+  while (pi < ei && pj < ej) {
+    const int si = vs_sub[pi], sj = vs_sub[pj];
+    if (si < sj) ++pi;
+    else if (sj < si) ++pj;
+    else {
+      const double g = G0[offs[si] + (int64_t)vs_loc[pi] * npad[si] + vs_loc[pj]];
+      acc = acc + scale * g;
+      ++pi;
+      ++pj;
+    }
+  }
+  gh[q] = acc;
+}
+
 int grid_for(int64_t n, int t, int cap = 1 << 20) {
   const int64_t b = (n + t - 1) / t;
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
@@ -376,7 +726,9 @@ struct Plan {
   std::vector<int32_t> npad;
   std::vector<int64_t> off;
   int64_t total = 0;
-  std::vector<int4> tiles;
+  std::vector<int4> tiles;       // bi <= bj (symmetric products)
+  std::vector<int4> tiles_full;  // every (bi, bj) (general products)
+  std::vector<int2> ranges;      // per subgraph: first tile and tile count in `tiles`
   double flops_alg = 0, flops_exec = 0;
   int max_npad = 0;
 };
@@ -402,20 +754,57 @@ Plan make_plan(const Part& P) {
   for (int s : order) {
     const int np = pl.npad[s];
     const int nb = (np + kBT - 1) / kBT;
+    const int first = (int)pl.tiles.size();
     for (int bi = 0; bi < nb; ++bi)
-      for (int bj = bi; bj < nb; ++bj) {
+      for (int bj = 0; bj < nb; ++bj) {
+        pl.tiles_full.push_back(make_int4(s, bi, bj, np));
+        if (bj < bi) continue;
         pl.tiles.push_back(make_int4(s, bi, bj, np));
         pl.flops_exec += 2.0 * kBT * kBT * (double)np;
       }
+    pl.ranges.push_back(make_int2(first, (int)pl.tiles.size() - first));
   }
   return pl;
 }
 
+}  // namespace
+
+struct TapeData {
+  int N = 0, K = 0, stride = 4, max_sub = 0;
+  double emin = 0, emax = 0;
+  std::vector<uint8_t> branch;
+  Plan pl;
+  DBuf<int64_t> offs;
+  DBuf<int32_t> npad;
+  DBuf<int4> tiles, tiles_full;
+  DBuf<int32_t> core_ptr, sub_ptr, sub_idx, sub_pos;
+  std::vector<DBuf<double>> ckpt;  // X_0, X_stride, X_2stride, ...
+};
+
+namespace {
+
 template <typename T>
-void launch_square(const T* X, T* S, const DBuf<int4>& tiles, int ntiles, const int64_t* offs,
-                   hipStream_t s) {
+void launch_square(const T* X, T* S, const int4* tiles, int ntiles, const int64_t* offs,
+                   hipStream_t s, int planes = 0, const int32_t* stopped = nullptr) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (planes == 1) {
+      hipLaunchKernelGGL(k_symm_mm_bf16<1>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, stopped);
+      GB_LAUNCH_CHECK();
+      return;
+    }
+    if (planes == 2) {
+      hipLaunchKernelGGL(k_symm_mm_bf16<2>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, stopped);
+      GB_LAUNCH_CHECK();
+      return;
+    }
+    if (planes == 3) {
+      hipLaunchKernelGGL(k_symm_mm_bf16<3>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, stopped);
+      GB_LAUNCH_CHECK();
+      return;
+    }
+  }
   hipLaunchKernelGGL((k_symm_mm<T, 0>), dim3(ntiles), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                     tiles.get(), offs);
+                     tiles, offs, stopped);
   GB_LAUNCH_CHECK();
 }
 
@@ -452,7 +841,8 @@ template <typename T>
 int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
              const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
              const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
-             gb_sp2_stats& st, DBuf<StepRec>& recs, hipStream_t s, int* stop_kind) {
+             gb_sp2_stats& st, DBuf<StepRec>& recs, hipStream_t s, int* stop_kind,
+             TapeData* tape = nullptr, int planes = 0, bool per_subgraph = false) {
   Timer tm;
   PinnedRec pin;
   int it = it0;
@@ -460,7 +850,12 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
   const int ntiles = (int)pl.tiles.size();
   for (;;) {
     GB_HIP(hipEventRecord(tm.a, s));
-    launch_square<T>(X, S, tiles, ntiles, offs.get(), s);
+    if (per_subgraph) {
+      for (const int2& r : pl.ranges)
+        launch_square<T>(X, S, tiles.get() + r.x, r.y, offs.get(), s, planes);
+    } else {
+      launch_square<T>(X, S, tiles.get(), ntiles, offs.get(), s, planes);
+    }
     GB_HIP(hipEventRecord(tm.b, s));
     int forced = -1;
     if (branch_in) forced = it < n_branch_in ? (int)branch_in[it] : 2;
@@ -470,8 +865,13 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
     GB_LAUNCH_CHECK();
     GB_HIP(hipMemcpyAsync(pin.h, recs.get() + (it % 2), sizeof(StepRec), hipMemcpyDeviceToHost, s));
     GB_HIP(hipStreamSynchronize(s));
-    st.ms_square += elapsed(tm.a, tm.b);
-    st.n_square += 1;
+    if (std::is_same<T, float>::value) {
+      st.ms_square_lo += elapsed(tm.a, tm.b);
+      st.n_square_lo += 1;
+    } else {
+      st.ms_square += elapsed(tm.a, tm.b);
+      st.n_square += 1;
+    }
     const StepRec r = *pin.h;
     if (it < 128) {
       st.t1[it] = r.t1;
@@ -497,14 +897,103 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
     }
     std::swap(X, S);
     ++it;
+    if (tape) {
+      tape->branch.push_back((uint8_t)r.b);
+      if (it % tape->stride == 0) {
+        DBuf<double> c(pl.total, nullptr);
+        GB_HIP(hipMemcpyAsync(c.get(), X, pl.total * sizeof(T), hipMemcpyDeviceToDevice, s));
+        tape->ckpt.push_back(std::move(c));
+      }
+    }
   }
+}
+
+
+// Device-driven loop: two iterations (one per buffer parity) captured once in a hipGraph and
+// replayed; the host reads the stop flag every kReplays graph launches.
+template <typename T>
+int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
+                   const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
+                   const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
+                   gb_sp2_stats& st, hipStream_t s, int* stop_kind, int planes) {
+  constexpr int kReplays = 4;
+  LoopState h;
+  std::memset(&h, 0, sizeof(h));
+  h.it = it0;
+  h.max_iter = max_iter;
+  h.n_forced = branch_in ? n_branch_in : -1;
+  h.stag = stagnation_stop ? 1 : 0;
+  h.n_occ = n_occ;
+  h.tol = tol;
+  if (branch_in) std::memcpy(h.forced, branch_in, std::min(n_branch_in, 128));
+  DBuf<LoopState> d(1, s);
+  GB_HIP(hipMemcpyAsync(d.get(), &h, sizeof(h), hipMemcpyHostToDevice, s));
+  GB_HIP(hipStreamSynchronize(s));
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  struct Cleanup {
+    hipStream_t& cs;
+    hipGraph_t& g;
+    hipGraphExec_t& e;
+    ~Cleanup() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+      if (cs) (void)hipStreamDestroy(cs);
+    }
+  } cleanup{cs, graph, exec};
+  GB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  GB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  const int ntiles = (int)pl.tiles.size();
+  const int ug = grid_for(pl.total, kT, 65536);
+  for (int par = 0; par < 2; ++par) {
+    T* A = par ? S : X;
+    T* B = par ? X : S;
+    launch_square<T>(A, B, tiles.get(), ntiles, offs.get(), cs, planes, &d.get()->stopped);
+    hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
+                       npad.get(), P.core_ptr.get(), P.n_sub, d.get());
+    hipLaunchKernelGGL(k_update_dev<T>, dim3(ug), dim3(kT), 0, cs, A, B, pl.total, d.get());
+  }
+  GB_HIP(hipStreamEndCapture(cs, &graph));
+  GB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  int32_t flag[2] = {0, 0};
+  int launched = 0;
+  for (;;) {
+    for (int r = 0; r < kReplays; ++r) GB_HIP(hipGraphLaunch(exec, s));
+    launched += 2 * kReplays;
+    GB_HIP(hipMemcpyAsync(flag, d.get(), sizeof(flag), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipStreamSynchronize(s));
+    if (flag[1]) break;
+    if (launched > max_iter + 2 * kReplays + 2) fail(GB_EHIP, "device-driven SP2 loop did not stop");
+  }
+  GB_HIP(hipMemcpyAsync(&h, d.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  const int it_stop = h.it;
+  for (int it = it0; it <= it_stop && it < 128; ++it) {
+    const StepRec& r = h.recs[it];
+    st.t1[it] = r.t1;
+    st.t2[it] = r.t2;
+    st.idem = r.e;
+    if (it < it_stop) {
+      st.branch[it] = (uint8_t)r.b;
+      if (!branch_in) st.min_margin = std::min(st.min_margin, r.margin);
+    }
+  }
+  if (std::is_same<T, float>::value) st.n_square_lo += it_stop - it0 + 1;
+  else st.n_square += it_stop - it0 + 1;
+  const StepRec& last = h.recs[it_stop];
+  if (last.stop == 1) *stop_kind = (branch_in && last.e > tol) ? 3 : 1;
+  else *stop_kind = last.stop == 4 ? 4 : 2;
+  if ((it_stop - it0) % 2 == 1) std::swap(X, S);
+  return it_stop;
 }
 
 }  // namespace
 
 // Full gb_density pipeline on an already built partition.
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
-             double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s) {
+             double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s,
+             TapeData** tape_out) {
   Timer t_all, t_stage;
   GB_HIP(hipEventRecord(t_all.a, s));
   const Plan pl = make_plan(P);
@@ -521,7 +1010,10 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   const int N = H.n;
   const double tol = o.idem_tol > 0 ? o.idem_tol : 1e-10 * N / 1024.0;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
-  const bool low = o.precision == GB_FP32_REFINE;
+  const bool low = o.precision != GB_FP64;
+  // bf16 planes of the low-precision square: 0 = native FP32 MFMA
+  const int planes = o.precision == GB_BF16_REFINE ? 1 : o.precision == GB_BF16X3_REFINE ? 2
+                   : o.precision == GB_BF16X6_REFINE ? 3 : 0;
   const int n_refine = o.n_refine;
   int stop_kind = 0;
   // the gather is timed with the first buffer allocation included
@@ -546,8 +1038,13 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     float* xf = X32.get();
     float* sf = S32.get();
     const double tol_lo = 1e-5 * N / 1024.0;
-    it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter, o.branch_in,
-                             o.n_branch_in, true, 0, st, recs, s, &stop_kind);
+    if (o.launch_mode == 2)
+      it_end = sp2_loop_graph<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
+                                     o.branch_in, o.n_branch_in, true, 0, st, s, &stop_kind, planes);
+    else
+      it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
+                               o.branch_in, o.n_branch_in, true, 0, st, recs, s, &stop_kind,
+                               nullptr, planes, o.launch_mode == 1);
     // the final low-precision square was only the stop test: continue from X in FP64
     X64 = DBuf<double>(pl.total, s);
     S64 = DBuf<double>(pl.total, s);
@@ -564,6 +1061,37 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
                        P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
                        X64.get());
     GB_LAUNCH_CHECK();
+    if (tape_out) {
+      TapeData* t = new TapeData();
+      *tape_out = t;
+      t->N = N;
+      t->emin = emin;
+      t->emax = emax;
+      t->stride = o.tape_stride > 0 ? o.tape_stride : 4;
+      t->max_sub = P.max_sub;
+      t->pl = pl;
+      auto dup_i32 = [&](DBuf<int32_t>& dst, const DBuf<int32_t>& src, size_t n) {
+        dst = DBuf<int32_t>(n, nullptr);
+        GB_HIP(hipMemcpyAsync(dst.get(), src.get(), n * 4, hipMemcpyDeviceToDevice, s));
+      };
+      t->offs = DBuf<int64_t>(pl.n_sub, nullptr);
+      GB_HIP(hipMemcpyAsync(t->offs.get(), pl.off.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
+      dup_i32(t->npad, npad, pl.n_sub);
+      t->tiles = DBuf<int4>(pl.tiles.size(), nullptr);
+      GB_HIP(hipMemcpyAsync(t->tiles.get(), pl.tiles.data(), pl.tiles.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, s));
+      t->tiles_full = DBuf<int4>(pl.tiles_full.size(), nullptr);
+      GB_HIP(hipMemcpyAsync(t->tiles_full.get(), pl.tiles_full.data(),
+                            pl.tiles_full.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      dup_i32(t->core_ptr, P.core_ptr, P.n_sub + 1);
+      dup_i32(t->sub_ptr, P.sub_ptr, P.n_sub + 1);
+      dup_i32(t->sub_idx, P.sub_idx, P.total);
+      dup_i32(t->sub_pos, P.sub_pos, P.total);
+      DBuf<double> c(pl.total, nullptr);
+      GB_HIP(hipMemcpyAsync(c.get(), X64.get(), pl.total * 8, hipMemcpyDeviceToDevice, s));
+      t->ckpt.push_back(std::move(c));
+      GB_HIP(hipStreamSynchronize(s));  // host plan vectors above are copied before return
+    }
     GB_HIP(hipEventRecord(t_stage.b, s));
     GB_HIP(hipStreamSynchronize(s));
     st.ms_gather = elapsed(t_stage.a, t_stage.b);
@@ -579,12 +1107,22 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       bin = o.branch_in;
       nbin = o.n_branch_in;
     }
-    const int cap = n_refine > 0 ? it_end + n_refine : max_iter;
-    it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin, false,
-                              it_end, st, recs, s, &stop_kind);
+    const int cap = n_refine > 0 ? std::min(it_end + n_refine, 127) : max_iter;
+    if (o.launch_mode == 2)
+      it_end = sp2_loop_graph<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin,
+                                      false, it_end, st, s, &stop_kind, 0);
+    else
+      it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin, false,
+                                it_end, st, recs, s, &stop_kind, nullptr, 0, o.launch_mode == 1);
   } else {
-    it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter, o.branch_in,
-                              o.n_branch_in, false, 0, st, recs, s, &stop_kind);
+    if (o.launch_mode == 2)
+      it_end = sp2_loop_graph<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter,
+                                      o.branch_in, o.n_branch_in, false, 0, st, s, &stop_kind, 0);
+    else
+      it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter,
+                                o.branch_in, o.n_branch_in, false, 0, st, recs, s, &stop_kind,
+                                tape_out ? *tape_out : nullptr, 0, o.launch_mode == 1);
+    if (tape_out) (*tape_out)->K = it_end;
   }
   GB_HIP(hipEventRecord(t_stage.b, s));
   GB_HIP(hipStreamSynchronize(s));
@@ -616,6 +1154,86 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   const int last = std::min(it_end, 127);
   st.trace = st.t1[last];
   st.ms_total += elapsed(t_all.a, t_all.b);
+}
+
+
+void tape_destroy(TapeData* t) { delete t; }
+void tape_dims(const TapeData* t, int* n, int* max_sub) {
+  *n = t->N;
+  *max_sub = t->max_sub;
+}
+
+// Reverse sweep: Gbar <- Gbar X + X Gbar (X <- X^2) or 2 Gbar - (Gbar X + X Gbar)
+// (X <- 2X - X^2) from the last step to the first, recomputing each checkpoint segment
+// forward; then dL/dH per slot of H.
+void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H, double* G_H, hipStream_t s) {
+  const Plan& pl = t.pl;
+  const int K = t.K, c = t.stride;
+  DBuf<double> G(pl.total, s), G2(pl.total, s), Pm(pl.total, s);
+  const int gfill = grid_for(pl.total, kT, 65536);
+  hipLaunchKernelGGL(k_fill, dim3(gfill), dim3(kT), 0, s, G.get(), pl.total, 0.0);
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_seed, dim3(pl.n_sub), dim3(kT), 0, s, G_D.val, G_D.width, t.core_ptr.get(),
+                     t.sub_ptr.get(), t.sub_idx.get(), t.sub_pos.get(), t.offs.get(), t.npad.get(),
+                     G.get());
+  GB_LAUNCH_CHECK();
+  std::vector<DBuf<double>> seg;
+  for (int q = 1; q < c; ++q) seg.emplace_back(pl.total, s);
+  const int max_nt = pl.max_npad / 32;
+  const dim3 cgrid(max_nt * max_nt, pl.n_sub);
+  const int ntf = (int)pl.tiles_full.size();
+  for (int m = (K - 1) / c; m >= 0 && K > 0; --m) {
+    const int start = m * c, end = std::min(start + c, K);
+    std::vector<double*> xs;
+    xs.push_back(t.ckpt[m].get());
+    for (int n = start; n + 1 < end; ++n) {
+      double* xin = xs.back();
+      double* xout = seg[n - start].get();
+      launch_square<double>(xin, xout, t.tiles.get(), (int)pl.tiles.size(), t.offs.get(), s);
+      if (t.branch[n] == 1) {
+        hipLaunchKernelGGL(k_lin_update<double>, dim3(gfill), dim3(kT), 0, s, xin, xout, pl.total);
+        GB_LAUNCH_CHECK();
+      }
+      xs.push_back(xout);
+    }
+    for (int n = end - 1; n >= start; --n) {
+      const double* X = xs[n - start];
+      hipLaunchKernelGGL((k_symm_mm<double, 3>), dim3(ntf), dim3(kT), 0, s, G.get(), X, X,
+                         Pm.get(), 1.0, 0.0, t.tiles_full.get(), t.offs.get(), nullptr);
+      GB_LAUNCH_CHECK();
+      const double c1 = t.branch[n] == 0 ? 1.0 : -1.0, c2 = t.branch[n] == 0 ? 0.0 : 2.0;
+      hipLaunchKernelGGL(k_sym_combine, cgrid, dim3(256), 0, s, Pm.get(), G.get(), G2.get(), c1,
+                         c2, t.offs.get(), t.npad.get(), max_nt);
+      GB_LAUNCH_CHECK();
+      std::swap(G, G2);
+    }
+  }
+  // vertex -> subgraph index and the deterministic assembly on H's pattern
+  const int n = t.N;
+  DBuf<int32_t> cnt(n, s), fill(n, s), vs_ptr(n + 1, s);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kT)), dim3(kT), 0, s, cnt.get(), (int64_t)n);
+  hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kT)), dim3(kT), 0, s, fill.get(), (int64_t)n);
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_vs_count, dim3(pl.n_sub), dim3(kT), 0, s, t.sub_ptr.get(), t.sub_idx.get(),
+                     cnt.get());
+  GB_LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.get(), vs_ptr.get(), n, s);
+  int32_t tot = 0;
+  GB_HIP(hipMemcpyAsync(&tot, vs_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  DBuf<int32_t> vs_sub(tot, s), vs_loc(tot, s);
+  hipLaunchKernelGGL(k_vs_fill, dim3(pl.n_sub), dim3(kT), 0, s, t.sub_ptr.get(), t.sub_idx.get(),
+                     vs_ptr.get(), fill.get(), vs_sub.get(), vs_loc.get());
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_vs_sort, dim3((n + kT - 1) / kT), dim3(kT), 0, s, n, vs_ptr.get(),
+                     vs_sub.get(), vs_loc.get());
+  GB_LAUNCH_CHECK();
+  const int64_t slots = (int64_t)H.n * H.width;
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(slots, kT)), dim3(kT), 0, s, H.col, H.n, H.width,
+                     vs_ptr.get(), vs_sub.get(), vs_loc.get(), t.offs.get(), t.npad.get(), G.get(),
+                     -1.0 / (t.emax - t.emin), G_H);
+  GB_LAUNCH_CHECK();
+  GB_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace gbi

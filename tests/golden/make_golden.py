@@ -66,3 +66,5 @@ if __name__ == "__main__":
         write_partitioned("n1024", 1e-5, 16)
     if "n18000" in what:
         write_partitioned("n18000", 1e-5, 32)
+    if "n100000" in what:
+        write_partitioned("n100000", 1e-5, 32)

@@ -108,3 +108,29 @@ def test_no_cpu_fallback_in_product_path():
         if fn.endswith(".py"):
             src = open(os.path.join(pkg, fn)).read()
             assert "oracle" not in src, fn
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors of the option and stats structs have the C sizes and offsets."""
+    import shutil
+    import subprocess
+    from paper_1603_00937_amd import _lib as L
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    fields = {"gb_sp2_opts": L.GbSp2Opts, "gb_sp2_stats": L.GbSp2Stats, "gb_ell": L.GbEll}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'printf("{cname}.{f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.rsplit(" ", 1) for line in out if line)
+    for cname, py in fields.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert int(got[f"{cname}.{f[0]}"]) == getattr(py, f[0]).offset, (cname, f[0])

@@ -160,3 +160,30 @@ def test_diagonal_hamiltonian(gb):
     assert st["converged"]
     assert np.array_equal(dc[:, 0], np.arange(N))
     assert np.abs(dv[:, 0] - want).max() < 1e-14
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_launch_modes_agree(gb, model_cache, precision):
+    """Batched launch, one launch per subgraph, and the device-driven hipGraph loop run the
+    same kernels on the same data: results agree bit for bit."""
+    m = model_cache("small256")
+    outs = {}
+    for mode in ("batched", "per_subgraph", "graph"):
+        D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      core_size=16, precision=precision, launch_mode=mode)
+        outs[mode] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"], st["iters"])
+    ref = outs["batched"]
+    for mode in ("per_subgraph", "graph"):
+        o = outs[mode]
+        assert o[2] == ref[2] and o[3] == ref[3], mode
+        assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), mode
+
+
+def test_graph_mode_replay_and_max_iter(gb, model_cache):
+    m = model_cache("small256")
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, launch_mode="graph", max_iter=5)
+    assert st["iters"] == 5 and not st["converged"]
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, launch_mode="graph", branch_in=[1, 0, 1])
+    assert st["iters"] == 3 and st["branch"] == [1, 0, 1]

@@ -1,0 +1,72 @@
+"""Low-precision squarings with FP64 traces, branches and refinement (GPU).
+
+Error bar: max-abs 1e-6 against the FP64 oracle.  Plain BF16 is a negative control: its
+rounding rotates the occupied subspace, which no purification step can undo."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1603_00937_amd as gb
+    return gb
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ref1024():
+    return json.load(open(os.path.join(GOLDEN, "n1024_fp64_partitioned.json")))
+
+
+def _sample_err(D_val, ref):
+    dv = D_val.cpu().numpy()
+    return max(abs(dv[r, s] - float.fromhex(v)) for r, s, v in ref["samples"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_mixed_precision_within_1e6(gb, model_cache, ref1024, precision):
+    from synth import ell_sha256
+    m = model_cache("n1024")
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, precision=precision)
+    assert ell_sha256(D_col.cpu().numpy()) == ref1024["D_col_sha256"]
+    assert st["converged"]
+    err = _sample_err(D_val, ref1024)
+    print(f"{precision}: iters={st['iters']} err={err:.3e} trace={st['trace']:.9f}")
+    assert err <= 1e-6
+    assert abs(st["trace"] - m["n_occ"]) < 1e-5
+    assert st["idem_max"] < 1e-6
+
+
+def test_bf16x3_and_plain_bf16_are_less_accurate(gb, model_cache, ref1024):
+    m = model_cache("n1024")
+    errs = {}
+    for p in ("bf16x3", "bf16"):
+        D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      core_size=16, precision=p)
+        errs[p] = _sample_err(D_val, ref1024)
+    print(errs)
+    assert errs["bf16"] > 1e-5, "plain BF16 misses the 1e-6 bar (negative control)"
+    assert errs["bf16x3"] < errs["bf16"]
+
+
+def test_fp32_small_matches_oracle_pattern(gb, model_cache):
+    from oracle.sp2 import density_partitioned
+    m = model_cache("small256")
+    oc, ov, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], 1e-5, 16)
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, precision="fp32")
+    assert np.array_equal(D_col.cpu().numpy(), oc)
+    assert np.abs(D_val.cpu().numpy() - ov).max() <= 1e-6
