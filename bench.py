@@ -27,11 +27,40 @@ WORKLOADS = {"n18000": dict(tau=1e-5, core=32), "n1024": dict(tau=1e-5, core=16)
              "n100000": dict(tau=1e-5, core=32)}
 
 
-def run_step(gb, Hc, Hv, n_occ, tau, core, precision, D, launch_mode):
+def run_step(gb, Hc, Hv, n_occ, tau, core, D, args):
     g = gb.build_graph(Hc, Hv, tau)
     p = gb.partition(g, core)
-    return gb.density(Hc, Hv, n_occ, tau, partition=p, core_size=core, precision=precision, D=D,
-                      launch_mode=launch_mode)
+    return gb.density(Hc, Hv, n_occ, tau, partition=p, core_size=core, precision=args.precision,
+                      D=D, launch_mode=args.launch_mode, tile_policy=args.tile_policy,
+                      tile_order=args.tile_order, refine=args.refine,
+                      n_fp64_first=args.n_fp64_first)
+
+
+def rocpd_summary(path):
+    """Per-kernel summary of a rocprofv3 database (--kernel-trace): calls, total and average
+    duration; for the squaring kernel also the launches with the largest grid (the SP2 loop's
+    batched launches, as opposed to the autotuner's single-bucket launches)."""
+    import sqlite3
+    c = sqlite3.connect(path)
+    rows = c.execute("select name, duration, grid_x from kernels").fetchall()
+    agg = {}
+    for name, dur, grid in rows:
+        short = name.replace("gbi::(anonymous namespace)::", "").replace("void ", "", 1)
+        short = short.split("(")[0]
+        a = agg.setdefault(short, [0, 0.0, {}])
+        a[0] += 1
+        a[1] += dur
+        g = a[2].setdefault(grid, [0, 0.0])
+        g[0] += 1
+        g[1] += dur
+    total = sum(v[1] for v in agg.values())
+    print("| kernel | calls | total ms | avg ms | % | largest-grid launches: calls, avg ms |")
+    print("|---|---|---|---|---|---|")
+    for k, (n, t, grids) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        gmax = max(grids)
+        gn, gt = grids[gmax]
+        print(f"| {k} | {n} | {t / 1e6:.3f} | {t / n / 1e6:.4f} | {100 * t / total:.1f} | "
+              f"{gn}, {gt / gn / 1e6:.4f} (grid {gmax // 256} WGs) |")
 
 
 def copy_calibration(nbytes=4 << 30, reps=5):
@@ -100,10 +129,18 @@ def main():
                     choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
     ap.add_argument("--launch-mode", default="batched", choices=["batched", "per_subgraph", "graph"])
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64"])
+    ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
+    ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
+    ap.add_argument("--n-fp64-first", type=int, default=0)
+    ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12)
     args = ap.parse_args()
+    if args.rocpd_summary:
+        rocpd_summary(args.rocpd_summary)
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -133,15 +170,14 @@ def main():
          torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
     del g, p
     for _ in range(args.warmup):
-        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D, args.launch_mode)
+        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, args)
     torch.cuda.synchronize()
     low = args.precision != "fp64"
     key = "square_lo" if low else "square"
     sq_ms, sq_n, stats = 0.0, 0, None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], args.precision, D,
-                               args.launch_mode)
+        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, args)
         sq_ms += stats["ms"][key]
         sq_n += stats["n_" + key]
     torch.cuda.synchronize()
@@ -163,6 +199,9 @@ def main():
         "config": {"workload": f"{args.workload}: seeded 3D tight-binding model, N={N} orbitals, "
                                f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}",
                    "precision": args.precision, "launch_mode": args.launch_mode,
+                   "tile_policy": args.tile_policy, "tile_order": args.tile_order,
+                   "refine": args.refine, "n_fp64_first": args.n_fp64_first,
+                   "n_tile64": stats["n_tile64"],
                    "n_sub": stats["n_sub"],
                    "max_sub": stats["max_sub"], "sp2_iters": stats["iters"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

@@ -123,7 +123,8 @@ void gb_partition_destroy(gb_partition_t* p);
 
 /* Arithmetic of the squaring loop. */
 /* Low-precision variants square an FP32 iterate, keep the traces and the branch decision in
- * FP64, and finish with FP64 SP2 steps (refinement) until the FP64 stop rule holds. */
+ * FP64, stop the low-precision loop when |t1 - t2| <= 1e-5 n / 1024 or when it stops
+ * decreasing, and finish with FP64 refinement (McWeeny by default). */
 typedef enum {
   GB_FP64 = 0,          /* every square in FP64 on the matrix cores                         */
   GB_FP32_REFINE = 1,   /* squares on FP32 MFMA (FP32 accumulate), then FP64 refinement      */
@@ -134,7 +135,11 @@ typedef enum {
 
 typedef struct {
   int32_t precision;         /* gb_precision; default GB_FP64                                */
-  int32_t n_refine;          /* FP64 McWeeny steps after the loop (default 0; FP32: 2)       */
+  int32_t n_refine;          /* low precision: at most this many FP64 refinement steps       *
+                              * (0 = 8 McWeeny steps / max_iter SP2 steps)                    */
+  int32_t refine_kind;       /* low precision: 0 = McWeeny X <- 3X^2 - 2X^3 until the FP64    *
+                              * stop test holds; 1 = FP64 SP2 steps with the trace rule       */
+  int32_t n_fp64_first;      /* low precision: run the first SP2 steps in FP64 (default 0)   */
   int32_t max_iter;          /* default 100 when 0                                           */
   double idem_tol;           /* stop when |Tr X - Tr X^2| <= idem_tol; 0 = 1e-10 * n / 1024   */
   const gb_partition_t* partition; /* NULL: build X2(threshold) + BLOCK(core_size) inside    */
@@ -150,6 +155,9 @@ typedef struct {
                               * 2: batched launches with the stop flag, counter and branch    *
                               *    records on the device, two steps captured in a hipGraph    *
                               *    and replayed (no host round trip per step; no tape)        */
+  int32_t tile_policy;       /* squaring tile edge: 0 autotuned per 256-wide size bucket      *
+                              * (timed once per process), 1 = 128, 2 = 64                     */
+  int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
 } gb_sp2_opts;
 
 typedef struct {
@@ -168,6 +176,8 @@ typedef struct {
   int32_t n_square;          /* number of FP64 squaring launches                             */
   float ms_square_lo;        /* the same for the low-precision squaring launches             */
   int32_t n_square_lo;
+  int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */
+  int32_t n_refine_done;     /* McWeeny steps applied                                        */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
   struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */

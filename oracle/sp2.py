@@ -53,10 +53,15 @@ def gather(H_col: np.ndarray, x0: np.ndarray, s: np.ndarray) -> np.ndarray:
 
 
 def sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter=100, branch_in=None,
-                    n_refine=0, keep_tape=False):
+                    n_refine=0, keep_tape=False, consume=False):
     """Run the shared SP2 sequence on every block (list of dense symmetric arrays,
-    core rows first).  Returns (blocks, info)."""
-    xs = [np.array(b, dtype=np.float64, copy=True) for b in blocks]
+    core rows first).  Returns (blocks, info).  With ``consume`` the given list is emptied
+    and its arrays are used directly (they are never written), to bound memory."""
+    if consume:
+        xs = list(blocks)
+        blocks.clear()
+    else:
+        xs = [np.array(b, dtype=np.float64, copy=True) for b in blocks]
     branches, margins, traces = [], [], []
     tape = [list(xs)] if keep_tape else None
     converged = False
@@ -92,7 +97,10 @@ def sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter=100, branch_i
             d_lin = abs(2.0 * t1 - t2 - n_occ)
             margins.append(abs(d_sq - d_lin))
         branches.append(b)
-        xs = S if b == 0 else [2.0 * x - s for x, s in zip(xs, S)]
+        if b == 1:
+            for x, s in zip(xs, S):
+                np.subtract(2.0 * x, s, out=s)   # s <- 2x - s, the same rounding as 2x - s
+        xs = S
         if keep_tape:
             tape.append(list(xs))
         it += 1
@@ -140,13 +148,14 @@ def density_partitioned(H_col, H_val, n_occ, tau, core_size, method="block", ide
     subs = [sub_idx[sub_ptr[s]:sub_ptr[s + 1]] for s in range(len(sub_ptr) - 1)]
     blocks = [gather(H_col, x0, s) for s in subs]
     core_counts = np.diff(core_ptr)
+    blocks0 = list(blocks) if keep_tape else None
     xs, info = sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter, branch_in,
-                               n_refine, keep_tape)
+                               n_refine, keep_tape, consume=True)
     D_col, D_val = scatter_columns(xs, sub_ptr, sub_idx, core_counts, N)
     info.update(emin=emin, emax=emax, row_ptr=row_ptr, col=col, core_ptr=core_ptr,
                 core_vertices=core_vertices, sub_ptr=sub_ptr, sub_idx=sub_idx,
                 trace=float(sum(D_val[i][D_col[i] == i].sum() for i in range(N))),
-                blocks0=blocks if keep_tape else None)
+                blocks0=blocks0)
     return D_col, D_val, info
 
 

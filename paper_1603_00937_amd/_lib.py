@@ -20,12 +20,14 @@ class GbEll(ctypes.Structure):
 
 class GbSp2Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_refine", ctypes.c_int32),
+                ("refine_kind", ctypes.c_int32), ("n_fp64_first", ctypes.c_int32),
                 ("max_iter", ctypes.c_int32), ("idem_tol", ctypes.c_double),
                 ("partition", ctypes.c_void_p), ("core_size", ctypes.c_int32),
                 ("branch_in", ctypes.c_void_p), ("n_branch_in", ctypes.c_int32),
                 ("emin", ctypes.c_double), ("emax", ctypes.c_double),
                 ("keep_tape", ctypes.c_int32), ("tape_stride", ctypes.c_int32),
-                ("launch_mode", ctypes.c_int32)]
+                ("launch_mode", ctypes.c_int32), ("tile_policy", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 class GbSp2Stats(ctypes.Structure):
@@ -42,6 +44,7 @@ class GbSp2Stats(ctypes.Structure):
                 ("ms_scatter", ctypes.c_float), ("ms_total", ctypes.c_float),
                 ("ms_square", ctypes.c_float), ("n_square", ctypes.c_int32),
                 ("ms_square_lo", ctypes.c_float), ("n_square_lo", ctypes.c_int32),
+                ("n_tile64", ctypes.c_int32), ("n_refine_done", ctypes.c_int32),
                 ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double),
                 ("tape", ctypes.c_void_p)]
 

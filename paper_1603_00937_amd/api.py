@@ -142,7 +142,8 @@ def _stats_dict(st: L.GbSp2Stats) -> dict:
         "ms": {n: getattr(st, "ms_" + n) for n in
                ("bounds", "graph", "part", "gather", "sp2", "refine", "scatter", "total",
                 "square", "square_lo")},
-        "n_square": st.n_square, "n_square_lo": st.n_square_lo, "square_flops": st.square_flops,
+        "n_square": st.n_square, "n_square_lo": st.n_square_lo, "n_tile64": st.n_tile64,
+        "n_refine_done": st.n_refine_done, "square_flops": st.square_flops,
         "square_flops_exec": st.square_flops_exec,
     }
 
@@ -176,7 +177,8 @@ class Tape:
 
 def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precision="fp64",
             n_refine=0, max_iter=0, idem_tol=0.0, branch_in=None, emin=None, emax=None,
-            D=None, keep_tape=False, tape_stride=0, launch_mode=0):
+            D=None, refine="mcweeny", n_fp64_first=0, keep_tape=False, tape_stride=0, launch_mode=0,
+            tile_policy="auto", tile_order="xcd"):
     """Partitioned SP2 density matrix.  Returns (D_col, D_val, stats); D is column-ELL
     [n, max_sub] (row i of the arrays = column i of D).  With ``partition`` None the X2 graph
     at ``threshold`` and a block partition with ``core_size`` are built first."""
@@ -194,6 +196,8 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     o = L.GbSp2Opts()
     o.precision = L.PRECISIONS[precision]
     o.n_refine = int(n_refine)
+    o.refine_kind = {"mcweeny": 0, "sp2": 1}[refine]
+    o.n_fp64_first = int(n_fp64_first)
     o.max_iter = int(max_iter)
     o.idem_tol = float(idem_tol)
     o.partition = part.handle
@@ -208,6 +212,8 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     o.keep_tape = 1 if keep_tape else 0
     o.tape_stride = int(tape_stride)
     o.launch_mode = {"batched": 0, "per_subgraph": 1, "graph": 2}.get(launch_mode, launch_mode)
+    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2}.get(tile_policy, tile_policy)
+    o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     st = L.GbSp2Stats()
     _check(_lib().gb_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),
                              ctypes.byref(De), ctypes.byref(st), _stream()))

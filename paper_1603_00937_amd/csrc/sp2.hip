@@ -9,6 +9,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <type_traits>
 
@@ -120,7 +122,7 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
 //   MODE 0: out = A*B          MODE 1: out = alpha*(A*B) + beta*E   (E symmetric)
 //   MODE 3: out = A*B for a general (non-symmetric) product with B symmetric: every tile
 //           (bi, bj) is listed and nothing is mirrored (the adjoint's Gbar*X)
-template <typename T, int MODE>
+template <typename T, int MODE, int BT = 128>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, const T* __restrict__ B,
                                                    const T* __restrict__ E, T* __restrict__ out,
                                                    T alpha, T beta, const int4* __restrict__ tiles,
@@ -133,53 +135,58 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   constexpr int V = 16 / sizeof(T);      // elements per 16-byte vector
   constexpr int STR = KC + V;            // padded LDS row stride (elements)
   constexpr int KG = KC / 4;             // k elements per lane group per chunk
-  __shared__ __align__(16) T As[2][kBT * STR];
-  __shared__ __align__(16) T Bs[2][kBT * STR];
+  constexpr int WM = BT / 2;             // wave tile edge (2 x 2 waves)
+  constexpr int MB = WM / 16;            // 16 x 16 blocks per wave tile edge
+  constexpr int TPR = kT / BT;           // staging threads per tile row
+  constexpr int VPT = 8 / TPR;           // 16-byte vectors per thread per operand and chunk
+  __shared__ __align__(16) T As[2][BT * STR];
+  __shared__ __align__(16) T Bs[2][BT * STR];
 
   const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;  // padding entry of an XCD queue
   const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
   const int64_t off = offs[s];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // global -> LDS staging: thread -> one row, one 64-byte half of the chunk
-  const int lr = tid >> 1, lh = tid & 1;
-  const int arow = bi * kBT + lr, brow = bj * kBT + lr;
+  // global -> LDS staging: thread -> one tile row, VPT consecutive vectors of the chunk
+  const int lr = tid / TPR, lq = tid % TPR;
+  const int arow = bi * BT + lr, brow = bj * BT + lr;
   const bool aok = arow < np, bok = brow < np;
-  const T* ap = A + off + (int64_t)(aok ? arow : 0) * np + lh * (KC / 2);
-  const T* bp = B + off + (int64_t)(bok ? brow : 0) * np + lh * (KC / 2);
-  uint4 ra[4], rb[4];
+  const T* ap = A + off + (int64_t)(aok ? arow : 0) * np + lq * VPT * V;
+  const T* bp = B + off + (int64_t)(bok ? brow : 0) * np + lq * VPT * V;
+  uint4 ra[VPT], rb[VPT];
   const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
 
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < VPT; ++q) {
       ra[q] = aok ? *reinterpret_cast<const uint4*>(ap + k0 + q * V) : z4;
       rb[q] = bok ? *reinterpret_cast<const uint4*>(bp + k0 + q * V) : z4;
     }
   };
   auto sstore = [&](int buf) {
-    T* da = &As[buf][lr * STR + lh * (KC / 2)];
-    T* db = &Bs[buf][lr * STR + lh * (KC / 2)];
+    T* da = &As[buf][lr * STR + lq * VPT * V];
+    T* db = &Bs[buf][lr * STR + lq * VPT * V];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < VPT; ++q) {
       *reinterpret_cast<uint4*>(da + q * V) = ra[q];
       *reinterpret_cast<uint4*>(db + q * V) = rb[q];
     }
   };
 
-  acc_t acc[4][4];
+  acc_t acc[MB][MB];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[m][n] = acc_t{0, 0, 0, 0};
+    for (int n = 0; n < MB; ++n) acc[m][n] = acc_t{0, 0, 0, 0};
 
   const int g = lane >> 4, r16 = lane & 15;
   const int nk = np / KC;
-  // a wave whose 64-row or 64-column block lies in the padding beyond np has nothing to
-  // compute; on a diagonal tile of a symmetric product the lower-left block is the transpose
-  // of the upper-right one, which that wave writes twice
-  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
+  // a wave whose row or column block lies in the padding beyond np has nothing to compute;
+  // on a diagonal tile of a symmetric product the lower-left block is the transpose of the
+  // upper-right one, which that wave writes twice
+  const bool in_range = bi * BT + wr * WM < np && bj * BT + wc * WM < np;
   const bool lower_diag = MODE != 3 && bi == bj && wr > wc;
   const bool active = in_range && !lower_diag;
   gload(0);
@@ -188,13 +195,13 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
     if (kc + 1 < nk) gload((kc + 1) * KC);
-    const T* as = &As[buf][(wr * 64 + r16) * STR + g * KG];
-    const T* bs = &Bs[buf][(wc * 64 + r16) * STR + g * KG];
+    const T* as = &As[buf][(wr * WM + r16) * STR + g * KG];
+    const T* bs = &Bs[buf][(wc * WM + r16) * STR + g * KG];
 #pragma unroll
     for (int h = 0; h < KG && active; h += V) {
-      T fa[4][V], fb[4][V];
+      T fa[MB][V], fb[MB][V];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < MB; ++m) {
         const uint4 va = *reinterpret_cast<const uint4*>(as + m * 16 * STR + h);
         const uint4 vb = *reinterpret_cast<const uint4*>(bs + m * 16 * STR + h);
         __builtin_memcpy(fa[m], &va, 16);
@@ -203,9 +210,9 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 #pragma unroll
       for (int e = 0; e < V; ++e)
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MB; ++m)
 #pragma unroll
-          for (int n = 0; n < 4; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
+          for (int n = 0; n < MB; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
     }
     if (kc + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
@@ -216,13 +223,13 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   const T* e = E + off;
   const bool mirror = MODE != 3 && (bi != bj || wr < wc);
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < MB; ++n)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int grow = bi * kBT + wr * 64 + m * 16 + M::row(lane, r);
-        const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
+        const int grow = bi * BT + wr * WM + m * 16 + M::row(lane, r);
+        const int gcol = bj * BT + wc * WM + n * 16 + r16;
         if (grow < np && gcol < np) {
           T v = acc[m][n][r];
           if (MODE == 1) v = alpha * v + beta * e[(int64_t)grow * np + gcol];
@@ -254,6 +261,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_bf16(const float* __restrict_
   __shared__ __align__(16) __bf16 As[NP][kBT * STR];
   __shared__ __align__(16) __bf16 Bs[NP][kBT * STR];
   const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;  // padding entry of an XCD queue
   const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
   const int64_t off = offs[s];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -508,12 +516,18 @@ __global__ void k_update_dev(const T* __restrict__ X, T* __restrict__ S, int64_t
   for (int64_t p = i; p < n; p += stride) S[p] = (T)2 * X[p] - S[p];
 }
 
-// S <- 2X - S over the whole batch buffer (padding stays 0)
+// S <- 2X - S over the whole batch buffer (padding stays 0); 16-byte vectors (every block
+// holds a multiple of 64 x 64 elements)
 template <typename T>
 __global__ void k_lin_update(const T* __restrict__ X, T* __restrict__ S, int64_t n) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T vec_t __attribute__((ext_vector_type(V)));
+  const vec_t* x = reinterpret_cast<const vec_t*>(X);
+  vec_t* sv = reinterpret_cast<vec_t*>(S);
+  const int64_t nv = n / V;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = i; p < n; p += stride) S[p] = (T)2 * X[p] - S[p];
+  for (int64_t p = i; p < nv; p += stride) sv[p] = (T)2 * x[p] - sv[p];
 }
 
 template <typename TI, typename TO>
@@ -720,24 +734,59 @@ int grid_for(int64_t n, int t, int cap = 1 << 20) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
 }
 
-// ---- plan: padded sizes, offsets, tile list --------------------------------------------
+// ---- plan: padded sizes, offsets, tile lists ---------------------------------------------
+// Square tiles are listed 128-edge tiles first, then 64-edge tiles; within each group the
+// largest blocks come first (most k work per tile).
 struct Plan {
   int n_sub = 0;
   std::vector<int32_t> npad;
   std::vector<int64_t> off;
+  std::vector<int> bt;           // tile edge chosen for each subgraph (64 or 128)
   int64_t total = 0;
-  std::vector<int4> tiles;       // bi <= bj (symmetric products)
-  std::vector<int4> tiles_full;  // every (bi, bj) (general products)
-  std::vector<int2> ranges;      // per subgraph: first tile and tile count in `tiles`
+  std::vector<int4> tiles;       // bi <= bj (symmetric products): n128 tiles of edge 128 first,
+  int n128 = 0;                  //   subgraph-major (per-subgraph launches use `ranges`)
+  std::vector<int4> launch;      // the same tiles as launched in one batch: l128 entries of edge
+  int l128 = 0;                  //   128 then the 64-edge ones, each group in XCD order
+  std::vector<int4> tiles_full;  // every (bi, bj) with edge 128 (general products)
+  std::vector<int4> ranges;      // per subgraph: first tile, tile count, edge
   double flops_alg = 0, flops_exec = 0;
   int max_npad = 0;
 };
 
-Plan make_plan(const Part& P) {
+// XCD-aware order: the hardware hands workgroup b to XCD b % 8.  Whole subgraphs are dealt to
+// the eight XCD queues (greedy, costliest first, onto the least loaded queue) and the queues
+// are interleaved, so every tile of a subgraph runs on one XCD and its row panels stay in that
+// XCD's L2.  Queues are padded to equal length with empty entries (subgraph -1).
+constexpr int kXcd = 8;
+
+void xcd_order(std::vector<int4>& out, const std::vector<int4>& tiles,
+               const std::vector<int4>& ranges, size_t r0, size_t r1) {
+  if (r1 <= r0) return;
+  std::vector<std::vector<int4>> q(kXcd);
+  std::vector<double> load(kXcd, 0.0);
+  for (size_t r = r0; r < r1; ++r) {
+    const int4 rg = ranges[r];
+    int best = 0;
+    for (int x = 1; x < kXcd; ++x)
+      if (load[x] < load[best]) best = x;
+    for (int t = 0; t < rg.y; ++t) q[best].push_back(tiles[rg.x + t]);
+    load[best] += (double)rg.y * tiles[rg.x].w;
+  }
+  size_t len = 0;
+  for (auto& v : q) len = std::max(len, v.size());
+  const size_t base = out.size();
+  out.resize(base + len * kXcd, make_int4(-1, 0, 0, 0));
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t j = 0; j < q[x].size(); ++j) out[base + j * kXcd + x] = q[x][j];
+}
+
+Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = true) {
   Plan pl;
   pl.n_sub = P.n_sub;
   pl.npad.resize(P.n_sub);
   pl.off.resize(P.n_sub);
+  pl.bt.assign(P.n_sub, kBT);
+  if (bt) pl.bt = *bt;
   std::vector<int> order(P.n_sub);
   for (int s = 0; s < P.n_sub; ++s) {
     const int n = P.h_sub_ptr[s + 1] - P.h_sub_ptr[s];
@@ -748,21 +797,39 @@ Plan make_plan(const Part& P) {
     pl.max_npad = std::max(pl.max_npad, pl.npad[s]);
     order[s] = s;
   }
-  // longest first: tiles of the largest blocks (most k work per tile) start earliest
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return pl.npad[a] > pl.npad[b]; });
+  for (int edge : {128, 64}) {
+    for (int s : order) {
+      if (pl.bt[s] != edge) continue;
+      const int np = pl.npad[s];
+      const int nb = (np + edge - 1) / edge;
+      const int first = (int)pl.tiles.size();
+      for (int bi = 0; bi < nb; ++bi)
+        for (int bj = bi; bj < nb; ++bj) {
+          pl.tiles.push_back(make_int4(s, bi, bj, np));
+          pl.flops_exec += 2.0 * edge * edge * (double)np;
+        }
+      pl.ranges.push_back(make_int4(first, (int)pl.tiles.size() - first, edge, s));
+    }
+    if (edge == 128) pl.n128 = (int)pl.tiles.size();
+  }
+  // launch list of the batched squaring: each group in XCD order (or as listed)
+  size_t r_split = 0;
+  while (r_split < pl.ranges.size() && pl.ranges[r_split].z == 128) ++r_split;
+  if (xcd) {
+    xcd_order(pl.launch, pl.tiles, pl.ranges, 0, r_split);
+    pl.l128 = (int)pl.launch.size();
+    xcd_order(pl.launch, pl.tiles, pl.ranges, r_split, pl.ranges.size());
+  } else {
+    pl.launch = pl.tiles;
+    pl.l128 = pl.n128;
+  }
   for (int s : order) {
     const int np = pl.npad[s];
     const int nb = (np + kBT - 1) / kBT;
-    const int first = (int)pl.tiles.size();
     for (int bi = 0; bi < nb; ++bi)
-      for (int bj = 0; bj < nb; ++bj) {
-        pl.tiles_full.push_back(make_int4(s, bi, bj, np));
-        if (bj < bi) continue;
-        pl.tiles.push_back(make_int4(s, bi, bj, np));
-        pl.flops_exec += 2.0 * kBT * kBT * (double)np;
-      }
-    pl.ranges.push_back(make_int2(first, (int)pl.tiles.size() - first));
+      for (int bj = 0; bj < nb; ++bj) pl.tiles_full.push_back(make_int4(s, bi, bj, np));
   }
   return pl;
 }
@@ -784,28 +851,51 @@ struct TapeData {
 namespace {
 
 template <typename T>
-void launch_square(const T* X, T* S, const int4* tiles, int ntiles, const int64_t* offs,
+void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const int64_t* offs,
                    hipStream_t s, int planes = 0, const int32_t* stopped = nullptr) {
   if constexpr (std::is_same<T, float>::value) {
+    if (planes > 0 && n64 > 0) fail(GB_EUNSUPPORTED, "split-bf16 squaring uses 128 tiles only");
     if (planes == 1) {
-      hipLaunchKernelGGL(k_symm_mm_bf16<1>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, stopped);
+      hipLaunchKernelGGL(k_symm_mm_bf16<1>, dim3(n128), dim3(kT), 0, s, X, S, tiles, offs, stopped);
       GB_LAUNCH_CHECK();
       return;
     }
     if (planes == 2) {
-      hipLaunchKernelGGL(k_symm_mm_bf16<2>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, stopped);
+      hipLaunchKernelGGL(k_symm_mm_bf16<2>, dim3(n128), dim3(kT), 0, s, X, S, tiles, offs, stopped);
       GB_LAUNCH_CHECK();
       return;
     }
     if (planes == 3) {
-      hipLaunchKernelGGL(k_symm_mm_bf16<3>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, stopped);
+      hipLaunchKernelGGL(k_symm_mm_bf16<3>, dim3(n128), dim3(kT), 0, s, X, S, tiles, offs, stopped);
       GB_LAUNCH_CHECK();
       return;
     }
   }
-  hipLaunchKernelGGL((k_symm_mm<T, 0>), dim3(ntiles), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                     tiles, offs, stopped);
-  GB_LAUNCH_CHECK();
+  if (n128 > 0) {
+    hipLaunchKernelGGL((k_symm_mm<T, 0, 128>), dim3(n128), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
+                       tiles, offs, stopped);
+    GB_LAUNCH_CHECK();
+  }
+  if (n64 > 0) {
+    hipLaunchKernelGGL((k_symm_mm<T, 0, 64>), dim3(n64), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
+                       tiles + n128, offs, stopped);
+    GB_LAUNCH_CHECK();
+  }
+}
+
+// device tile table: the launch list, then the subgraph-major list
+DBuf<int4> upload_tiles(const Plan& pl, hipStream_t s) {
+  DBuf<int4> t(pl.launch.size() + pl.tiles.size(), s);
+  GB_HIP(hipMemcpyAsync(t.get(), pl.launch.data(), pl.launch.size() * sizeof(int4),
+                        hipMemcpyHostToDevice, s));
+  GB_HIP(hipMemcpyAsync(t.get() + pl.launch.size(), pl.tiles.data(), pl.tiles.size() * sizeof(int4),
+                        hipMemcpyHostToDevice, s));
+  return t;
+}
+
+void launch_plan_square_f64(const double* X, double* S, const Plan& pl, const int4* tiles,
+                            const int64_t* offs, hipStream_t s) {
+  launch_square<double>(X, S, tiles, pl.l128, (int)pl.launch.size() - pl.l128, offs, s);
 }
 
 struct Timer {
@@ -834,6 +924,70 @@ struct PinnedRec {
   }
 };
 
+// ---- autotuner: tile edge per size bucket ----------------------------------------------------
+// Subgraphs are bucketed by padded size (256-wide buckets).  The first time a bucket is seen
+// for a precision, one squaring launch of that bucket's blocks is timed with 128- and 64-edge
+// tiles (one warm-up, two timed launches each) and the faster edge is kept for the life of
+// the process.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tune;  // (precision kind, bucket) -> tile edge
+
+template <typename T>
+std::vector<int> tune_tiles(const Part& P, const Plan& pl, T* X, T* S, const int64_t* offs,
+                            hipStream_t s, int kind, bool xcd) {
+  std::vector<int> bt(pl.n_sub, kBT);
+  std::map<int, std::vector<int>> buckets;
+  for (int i = 0; i < pl.n_sub; ++i) buckets[(pl.npad[i] + 255) / 256].push_back(i);
+  Timer tm;
+  for (auto& kv : buckets) {
+    int choice = 0;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find({kind, kv.first});
+      if (it != g_tune.end()) choice = it->second;
+    }
+    if (!choice) {
+      float best = INFINITY;
+      for (int edge : {128, 64}) {
+        std::vector<int> e(pl.n_sub, 0);
+        for (int i : kv.second) e[i] = edge;
+        const Plan sub = make_plan(P, &e, xcd);
+        DBuf<int4> tl = upload_tiles(sub, s);
+        const int n128 = sub.l128, n64 = (int)sub.launch.size() - sub.l128;
+        launch_square<T>(X, S, tl.get(), n128, n64, offs, s);
+        GB_HIP(hipEventRecord(tm.a, s));
+        launch_square<T>(X, S, tl.get(), n128, n64, offs, s);
+        launch_square<T>(X, S, tl.get(), n128, n64, offs, s);
+        GB_HIP(hipEventRecord(tm.b, s));
+        GB_HIP(hipStreamSynchronize(s));
+        const float ms = elapsed(tm.a, tm.b);
+        if (ms < best) {
+          best = ms;
+          choice = edge;
+        }
+      }
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune[{kind, kv.first}] = choice;
+    }
+    for (int i : kv.second) bt[i] = choice;
+  }
+  return bt;
+}
+
+template <typename T>
+void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const int64_t* offs,
+                  hipStream_t s, int policy, int kind, gb_sp2_stats& st, bool xcd) {
+  std::vector<int> bt(pl.n_sub, kBT);
+  if (policy == 2) bt.assign(pl.n_sub, 64);
+  else if (policy == 0) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd);
+  if (policy == 1) return;
+  pl = make_plan(P, &bt, xcd);
+  tiles = upload_tiles(pl, s);
+  st.n_tile64 = 0;
+  for (int e : bt) st.n_tile64 += e == 64;
+  st.square_flops_exec = pl.flops_exec;
+}
+
 // Runs the SP2 loop in precision T on buffers X (current iterate) and S (scratch).
 // Returns when the stop rule fires, the replay ends, max_iter is reached, or (low precision)
 // when the idempotency error stagnates.  Records every step into stats.
@@ -847,14 +1001,15 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
   PinnedRec pin;
   int it = it0;
   std::vector<double> es;
-  const int ntiles = (int)pl.tiles.size();
+  const int nl = (int)pl.launch.size();
   for (;;) {
     GB_HIP(hipEventRecord(tm.a, s));
     if (per_subgraph) {
-      for (const int2& r : pl.ranges)
-        launch_square<T>(X, S, tiles.get() + r.x, r.y, offs.get(), s, planes);
+      for (const int4& r : pl.ranges)
+        launch_square<T>(X, S, tiles.get() + nl + r.x, r.z == 128 ? r.y : 0,
+                         r.z == 128 ? 0 : r.y, offs.get(), s, planes);
     } else {
-      launch_square<T>(X, S, tiles.get(), ntiles, offs.get(), s, planes);
+      launch_square<T>(X, S, tiles.get(), pl.l128, nl - pl.l128, offs.get(), s, planes);
     }
     GB_HIP(hipEventRecord(tm.b, s));
     int forced = -1;
@@ -944,12 +1099,13 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
   } cleanup{cs, graph, exec};
   GB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   GB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  const int ntiles = (int)pl.tiles.size();
+  const int nl = (int)pl.launch.size();
   const int ug = grid_for(pl.total, kT, 65536);
   for (int par = 0; par < 2; ++par) {
     T* A = par ? S : X;
     T* B = par ? X : S;
-    launch_square<T>(A, B, tiles.get(), ntiles, offs.get(), cs, planes, &d.get()->stopped);
+    launch_square<T>(A, B, tiles.get(), pl.l128, nl - pl.l128, offs.get(), cs, planes,
+                     &d.get()->stopped);
     hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
                        npad.get(), P.core_ptr.get(), P.n_sub, d.get());
     hipLaunchKernelGGL(k_update_dev<T>, dim3(ug), dim3(kT), 0, cs, A, B, pl.total, d.get());
@@ -996,16 +1152,15 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
              TapeData** tape_out) {
   Timer t_all, t_stage;
   GB_HIP(hipEventRecord(t_all.a, s));
-  const Plan pl = make_plan(P);
+  const bool xcd = o.tile_order == 0;
+  Plan pl = make_plan(P, nullptr, xcd);
   st.square_flops = pl.flops_alg;
   st.square_flops_exec = pl.flops_exec;
   DBuf<int64_t> offs(pl.n_sub, s);
   DBuf<int32_t> npad(pl.n_sub, s);
-  DBuf<int4> tiles(pl.tiles.size(), s);
+  DBuf<int4> tiles = upload_tiles(pl, s);
   GB_HIP(hipMemcpyAsync(offs.get(), pl.off.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
   GB_HIP(hipMemcpyAsync(npad.get(), pl.npad.data(), pl.n_sub * 4, hipMemcpyHostToDevice, s));
-  GB_HIP(hipMemcpyAsync(tiles.get(), pl.tiles.data(), pl.tiles.size() * sizeof(int4),
-                        hipMemcpyHostToDevice, s));
   DBuf<StepRec> recs(2, s);
   const int N = H.n;
   const double tol = o.idem_tol > 0 ? o.idem_tol : 1e-10 * N / 1024.0;
@@ -1025,32 +1180,59 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   double* xd = nullptr;
   double* sd = nullptr;
   int it_end = 0;
+  bool done = false;  // the FP64 steps before a low-precision loop already converged
   if (low) {
     DBuf<float> X32(pl.total, s), S32(pl.total, s);
-    hipLaunchKernelGGL(k_gather<float>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
-                       P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
-                       X32.get());
+    float* xf = X32.get();
+    float* sf = S32.get();
+    const int nhi = std::min(std::max(0, o.n_fp64_first), max_iter);
+    X64 = DBuf<double>(pl.total, s);
+    S64 = DBuf<double>(pl.total, s);
+    xd = X64.get();
+    sd = S64.get();
+    if (nhi > 0) {
+      hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
+                         P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(),
+                         npad.get(), xd);
+    } else {
+      hipLaunchKernelGGL(k_gather<float>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
+                         P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(),
+                         npad.get(), xf);
+    }
     GB_LAUNCH_CHECK();
     GB_HIP(hipEventRecord(t_stage.b, s));
     GB_HIP(hipStreamSynchronize(s));
     st.ms_gather = elapsed(t_stage.a, t_stage.b);
     GB_HIP(hipEventRecord(t_stage.a, s));
-    float* xf = X32.get();
-    float* sf = S32.get();
-    const double tol_lo = 1e-5 * N / 1024.0;
-    if (o.launch_mode == 2)
-      it_end = sp2_loop_graph<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
-                                     o.branch_in, o.n_branch_in, true, 0, st, s, &stop_kind, planes);
-    else
-      it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
-                               o.branch_in, o.n_branch_in, true, 0, st, recs, s, &stop_kind,
-                               nullptr, planes, o.launch_mode == 1);
-    // the final low-precision square was only the stop test: continue from X in FP64
-    X64 = DBuf<double>(pl.total, s);
-    S64 = DBuf<double>(pl.total, s);
-    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT), 0,
-                       s, xf, X64.get(), pl.total);
-    GB_LAUNCH_CHECK();
+    if (nhi > 0) {
+      // the first steps, where the spectral gap of X is smallest and rounding errors are
+      // amplified most, in FP64
+      it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, nhi, o.branch_in,
+                                o.n_branch_in, false, 0, st, recs, s, &stop_kind, nullptr, 0,
+                                o.launch_mode == 1);
+      done = stop_kind == 1 || stop_kind == 3;
+      if (!done) {
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(pl.total, kT, 65536)),
+                           dim3(kT), 0, s, xd, xf, pl.total);
+        GB_LAUNCH_CHECK();
+      }
+    }
+    if (!done) {
+      if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
+      const double tol_lo = 1e-5 * N / 1024.0;
+      if (o.launch_mode == 2)
+        it_end = sp2_loop_graph<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
+                                       o.branch_in, o.n_branch_in, true, it_end, st, s, &stop_kind,
+                                       planes);
+      else
+        it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
+                                 o.branch_in, o.n_branch_in, true, it_end, st, recs, s, &stop_kind,
+                                 nullptr, planes, o.launch_mode == 1);
+      // the final low-precision square was only the stop test: continue from X in FP64
+      hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT),
+                         0, s, xf, xd, pl.total);
+      GB_LAUNCH_CHECK();
+    }
     GB_HIP(hipEventRecord(t_stage.b, s));
     GB_HIP(hipStreamSynchronize(s));
     st.ms_sp2 = elapsed(t_stage.a, t_stage.b);
@@ -1077,8 +1259,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       t->offs = DBuf<int64_t>(pl.n_sub, nullptr);
       GB_HIP(hipMemcpyAsync(t->offs.get(), pl.off.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
       dup_i32(t->npad, npad, pl.n_sub);
-      t->tiles = DBuf<int4>(pl.tiles.size(), nullptr);
-      GB_HIP(hipMemcpyAsync(t->tiles.get(), pl.tiles.data(), pl.tiles.size() * sizeof(int4),
+      t->tiles = DBuf<int4>(pl.launch.size(), nullptr);
+      GB_HIP(hipMemcpyAsync(t->tiles.get(), pl.launch.data(), pl.launch.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
       t->tiles_full = DBuf<int4>(pl.tiles_full.size(), nullptr);
       GB_HIP(hipMemcpyAsync(t->tiles_full.get(), pl.tiles_full.data(),
@@ -1096,10 +1278,54 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     GB_HIP(hipStreamSynchronize(s));
     st.ms_gather = elapsed(t_stage.a, t_stage.b);
   }
-  xd = X64.get();
-  sd = S64.get();
+  if (!low) {
+    xd = X64.get();
+    sd = S64.get();
+  }
+  if (!low && !tape_out) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
+  else if (low && planes > 0) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
   GB_HIP(hipEventRecord(t_stage.a, s));
-  if (low) {
+  if (low && done) {
+    // converged during the FP64 steps: nothing to refine
+  } else if (low && o.refine_kind == 0) {
+    // FP64 refinement by McWeeny purification X <- 3X^2 - 2X^3 = 3S - 2 S X (S = X^2; S and X
+    // commute, so S X is symmetric and computed on upper tiles).  It drives every eigenvalue to
+    // 0 or 1 without acting on the trace, so the occupation the low-precision loop reached is
+    // kept.  Steps repeat until the FP64 stop test holds (at most n_refine, default 8).
+    DBuf<double> T64(pl.total, s);
+    double* td = T64.get();
+    const int max_steps = n_refine > 0 ? n_refine : 8;
+    const int n64 = (int)pl.launch.size() - pl.l128;
+    const int at = std::min(it_end, 127);
+    StepRec r;
+    for (int step = 0;; ++step) {
+      launch_square<double>(xd, sd, tiles.get(), pl.l128, n64, offs.get(), s);
+      hipLaunchKernelGGL(k_trace_branch<double>, dim3(1), dim3(kT), 0, s, xd, sd, offs.get(),
+                         npad.get(), P.core_ptr.get(), P.n_sub, (double)n_occ, tol, 2, 0, recs.get());
+      GB_LAUNCH_CHECK();
+      GB_HIP(hipMemcpyAsync(&r, recs.get(), sizeof(r), hipMemcpyDeviceToHost, s));
+      GB_HIP(hipStreamSynchronize(s));
+      if (r.e <= tol || step == max_steps) break;
+      if (pl.l128 > 0)
+        hipLaunchKernelGGL((k_symm_mm<double, 1, 128>), dim3(pl.l128), dim3(kT), 0, s, sd, xd, sd,
+                           td, -2.0, 3.0, tiles.get(), offs.get(), nullptr);
+      if (n64 > 0)
+        hipLaunchKernelGGL((k_symm_mm<double, 1, 64>), dim3(n64), dim3(kT), 0, s, sd, xd, sd, td,
+                           -2.0, 3.0, tiles.get() + pl.l128, offs.get(), nullptr);
+      GB_LAUNCH_CHECK();
+      std::swap(xd, td);
+      ++st.n_refine_done;
+    }
+    st.idem = r.e;
+    st.t1[at] = r.t1;
+    st.t2[at] = r.t2;
+    stop_kind = r.e <= tol ? 1 : 2;
+    // T64 is released at the end of this block: keep the refined X in X64's storage
+    if (xd == td) {
+      GB_HIP(hipMemcpyAsync(X64.get(), xd, pl.total * 8, hipMemcpyDeviceToDevice, s));
+      xd = X64.get();
+    }
+  } else if (low) {
     // FP64 refinement: SP2 steps with FP64 traces from where the FP32 loop stopped
     const uint8_t* bin = nullptr;
     int nbin = 0;
@@ -1189,7 +1415,7 @@ void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H, double* G_H, h
     for (int n = start; n + 1 < end; ++n) {
       double* xin = xs.back();
       double* xout = seg[n - start].get();
-      launch_square<double>(xin, xout, t.tiles.get(), (int)pl.tiles.size(), t.offs.get(), s);
+      launch_plan_square_f64(xin, xout, pl, t.tiles.get(), t.offs.get(), s);
       if (t.branch[n] == 1) {
         hipLaunchKernelGGL(k_lin_update<double>, dim3(gfill), dim3(kT), 0, s, xin, xout, pl.total);
         GB_LAUNCH_CHECK();

@@ -1,0 +1,75 @@
+"""Full-size parity (GPU): the N = 18000 and N = 100000 systems in the configuration the
+benchmark times, against oracle outputs stored by tests/golden/make_golden.py (graph,
+partition and D pattern by SHA-256; D values on 4096 sampled entries)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, f"{name}_fp64_partitioned.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored oracle run for {name}")
+    return json.load(open(path))
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1603_00937_amd as gb
+    return gb
+
+
+def _run(gb, name, precision, launch_mode="batched"):
+    import torch
+    from synth import make_model, ell_sha256
+    ref = _golden(name)
+    m = make_model(name)
+    assert ell_sha256(m["H_col"], m["H_val"]) == ref["H_sha256"], "inputs differ from the oracle's"
+    Hc = torch.from_numpy(m["H_col"]).cuda()
+    Hv = torch.from_numpy(m["H_val"]).cuda()
+    lo, hi = gb.spectral_bounds(Hc, Hv)
+    assert (lo.hex(), hi.hex()) == (ref["emin"], ref["emax"])
+    g = gb.build_graph(Hc, Hv, ref["tau"])
+    rp, cl = [t.cpu().numpy() for t in g.arrays()]
+    assert ell_sha256(rp, cl) == ref["graph_sha256"]
+    p = gb.partition(g, ref["core_size"])
+    cp, sp, si = [t.cpu().numpy() for t in p.arrays()]
+    assert ell_sha256(cp, sp, si) == ref["partition_sha256"]
+    D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], ref["tau"], partition=p,
+                                  core_size=ref["core_size"], precision=precision,
+                                  launch_mode=launch_mode)
+    dc = D_col.cpu().numpy()
+    dv = D_val.cpu().numpy()
+    assert ell_sha256(dc) == ref["D_col_sha256"]
+    err = max(abs(dv[r, s] - float.fromhex(v)) for r, s, v in ref["samples"])
+    print(f"{name} {precision}: iters={st['iters']} err={err:.3e} trace={st['trace']:.9f} "
+          f"idem_max={st['idem_max']:.2e} ms={st['ms']}")
+    return ref, st, err
+
+
+def test_n18000_fp64(gb):
+    ref, st, err = _run(gb, "n18000", "fp64")
+    assert "".join(map(str, st["branch"])) == ref["branch"]
+    assert st["iters"] == ref["iters"] and st["converged"]
+    assert err <= 1e-9
+    assert abs(st["trace"] - ref["trace_D"]) < 1e-8
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+def test_n18000_mixed(gb, precision):
+    ref, st, err = _run(gb, "n18000", precision)
+    assert st["converged"]
+    assert err <= 1e-6
+
+
+def test_n100000_fp32(gb):
+    ref, st, err = _run(gb, "n100000", "fp32")
+    assert st["converged"]
+    assert err <= 1e-6

@@ -70,3 +70,17 @@ def test_fp32_small_matches_oracle_pattern(gb, model_cache):
                                   core_size=16, precision="fp32")
     assert np.array_equal(D_col.cpu().numpy(), oc)
     assert np.abs(D_val.cpu().numpy() - ov).max() <= 1e-6
+
+
+@pytest.mark.parametrize("refine,first", [("mcweeny", 0), ("sp2", 0), ("mcweeny", 3)])
+def test_refinement_variants(gb, model_cache, ref1024, refine, first):
+    m = model_cache("n1024")
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, precision="fp32", refine=refine,
+                                  n_fp64_first=first)
+    err = _sample_err(D_val, ref1024)
+    print(f"fp32 refine={refine} fp64_first={first}: err={err:.3e} idem={st['idem']:.2e} "
+          f"trace={st['trace']:.9f} steps={st['n_refine_done']} iters={st['iters']}")
+    assert st["converged"]
+    assert st["idem_max"] < 1e-8
+    assert err <= 2e-6
