@@ -63,6 +63,59 @@ def rocpd_summary(path):
               f"{gn}, {gt / gn / 1e6:.4f} (grid {gmax // 256} WGs) |")
 
 
+def md_run(args):
+    """Adaptive-graph displacement loop (the MD use of the paper's Eq. 8 estimate): each step
+    displaces every site by N(0, sigma^2) per coordinate, rebuilds H on the host, derives the
+    graph from the previous D and the new H (|D| >= 1e-4 united with the X2 graph), partitions,
+    computes D and the gradient of Tr[D V].  Prints one JSON line with per-step statistics."""
+    import torch
+    import paper_1603_00937_amd as gb
+    from synth import make_model, make_operator_v, displace_sites, rebuild_hamiltonian
+    cfg = WORKLOADS[args.workload]
+    m = make_model(args.workload)
+    rng = np.random.default_rng(52)
+    dev = torch.device("cuda:0")
+    up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    V = make_operator_v(m["H_col"], 51)
+    Hc, Hv = up(m["H_col"]), up(m["H_val"])
+    D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], core_size=cfg["core"])
+    steps = []
+    pos = m["pos"]
+    for t in range(args.md_steps):
+        pos = displace_sites(pos, m["L"], 0.02, rng)
+        m = rebuild_hamiltonian(m, pos)
+        Hc, Hv = up(m["H_col"]), up(m["H_val"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
+        p = gb.partition(g, cfg["core"])
+        D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
+                                      core_size=cfg["core"], keep_tape=True)
+        # dL/dD for L = Tr[D V] on D's pattern (V on H's pattern), then the adjoint
+        tape = st.pop("tape")
+        Vd = up(V)
+        # V[i, r] for the entries r of column i of D that lie on row i of H (searchsorted in
+        # the ascending ELL row; padding -1 mapped past every column)
+        big = np.iinfo(np.int32).max
+        Hs = torch.where(Hc >= 0, Hc, torch.full_like(Hc, big)).long().contiguous()
+        rows = D_col.long().contiguous()
+        pos = torch.searchsorted(Hs, rows).clamp(max=Hs.shape[1] - 1)
+        hit = (torch.gather(Hs, 1, pos) == rows) & (rows >= 0)
+        GD = torch.where(hit, torch.gather(Vd, 1, pos), torch.zeros_like(D_val))
+        L = float((GD * D_val).sum())
+        G_H = tape.vjp(GD.contiguous())
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sizes = np.diff(p.arrays()[1].cpu().numpy())
+        steps.append({"step": t + 1, "ms": dt * 1e3, "iters": st["iters"],
+                      "converged": st["converged"], "graph_nnz": g.nnz,
+                      "sub_min": int(sizes.min()), "sub_mean": float(sizes.mean()),
+                      "sub_max": int(sizes.max()), "trace_DV": L,
+                      "grad_norm": float(G_H.norm())})
+        print(json.dumps(steps[-1]), file=sys.stderr, flush=True)
+    print(json.dumps({"md_steps": steps, "workload": args.workload}), flush=True)
+
+
 def copy_calibration(nbytes=4 << 30, reps=5):
     """A plain device copy of known size (the scale for rocprof FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -125,7 +178,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64",
+    ap.add_argument("--precision", default="bf16x6",
                     choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
     ap.add_argument("--launch-mode", default="batched", choices=["batched", "per_subgraph", "graph"])
     ap.add_argument("--copy-calibration", action="store_true")
@@ -134,8 +187,12 @@ def main():
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
+    ap.add_argument("--md-steps", type=int, default=0,
+                    help="run the adaptive-graph displacement loop instead of the benchmark")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="skip the FP64 GPU measurement reported beside a mixed-precision run")
     ap.add_argument("--cpu-sample", type=int, default=12)
     args = ap.parse_args()
     if args.rocpd_summary:
@@ -143,6 +200,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.md_steps:
+        md_run(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -156,7 +216,7 @@ def main():
 
     cfg = WORKLOADS[args.workload]
     model = make_model(args.workload)
-    N, n_occ = model["N"], model["n_occ"]
+    N = model["N"]
     gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_fp64_partitioned.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     if golden and golden["H_sha256"] != ell_sha256(model["H_col"], model["H_val"]):
@@ -169,58 +229,74 @@ def main():
     D = (torch.empty((N, p.max_sub), dtype=torch.int32, device=dev),
          torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
     del g, p
+
+    out = measure(gb, torch, args, args.precision, model, cfg, Hc, Hv, D, golden)
+    if args.precision != "fp64" and not args.no_fp64_compare:
+        ref = measure(gb, torch, args, "fp64", model, cfg, Hc, Hv, D, golden)
+        out["fp64_gpu"] = {k: ref[k] for k in ("value", "ms_per_step", "roofline", "accuracy")}
+        out["speedup_vs_fp64_gpu"] = out["value"] / ref["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(model, args.workload, golden, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
+    """Warm-up, then K timed steps of the whole path in ``precision``; one result record."""
+    N, n_occ = model["N"], model["n_occ"]
+    a = argparse.Namespace(**vars(args))
+    a.precision = precision
     for _ in range(args.warmup):
-        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, args)
+        run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, a)
     torch.cuda.synchronize()
-    low = args.precision != "fp64"
+    low = precision != "fp64"
     key = "square_lo" if low else "square"
     sq_ms, sq_n, stats = 0.0, 0, None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, args)
+        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, a)
         sq_ms += stats["ms"][key]
         sq_n += stats["n_" + key]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     flops_alg = stats["square_flops"]
-    flops_exec = stats["square_flops_exec"] * PLANE_PRODUCTS.get(args.precision, 1)
+    flops_exec = stats["square_flops_exec"] * PLANE_PRODUCTS.get(precision, 1)
     # the dominant kernel is the squaring launch of the loop's precision (the low-precision
     # path also runs a few FP64 refinement squares, reported in stage_ms)
-    peak = PEAK_TFLOPS[args.precision]
-    avg_launch_s = (sq_ms / sq_n / 1e3) if sq_n else float("nan")
-    achieved = flops_alg / avg_launch_s / 1e12
+    peak = PEAK_TFLOPS[precision]
+    # per-launch events exist in the host-driven modes only (the hipGraph loop runs unsplit)
+    avg_launch_s = (sq_ms / sq_n / 1e3) if (sq_n and sq_ms > 0) else None
+    achieved = flops_alg / avg_launch_s / 1e12 if avg_launch_s else None
     err, pattern_ok = (sample_error(D[0], D[1], golden) if golden else (None, None))
-    out = {
+    return {
         "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64"}.get(args.precision, "bf16+f64"),
+        "dtype": {"fp64": "f64", "fp32": "f32+f64"}.get(precision, "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: seeded 3D tight-binding model, N={N} orbitals, "
                                f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}",
-                   "precision": args.precision, "launch_mode": args.launch_mode,
+                   "precision": precision, "launch_mode": args.launch_mode,
                    "tile_policy": args.tile_policy, "tile_order": args.tile_order,
                    "refine": args.refine, "n_fp64_first": args.n_fp64_first,
-                   "n_tile64": stats["n_tile64"],
-                   "n_sub": stats["n_sub"],
-                   "max_sub": stats["max_sub"], "sp2_iters": stats["iters"]},
+                   "n_tile64": stats["n_tile64"], "n_sub": stats["n_sub"],
+                   "max_sub": stats["max_sub"], "sp2_iters": stats["iters"],
+                   "refine_steps": stats["n_refine_done"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
-                     "kernel": "k_symm_mm_bf16 (batched X^2)" if args.precision.startswith("bf16")
-                     else "k_symm_mm (batched X^2)",
+                     "frac": achieved / peak if achieved else None, "traffic": None,
+                     "kernel": ("k_symm_mm_planes (batched X^2, split bf16)"
+                                if precision.startswith("bf16") else "k_symm_mm (batched X^2)"),
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
-                     "exec_tflops": flops_exec / avg_launch_s / 1e12,
-                     "avg_launch_ms": avg_launch_s * 1e3},
-        "accuracy": {"max_abs_err_vs_oracle_samples": err, "D_pattern_bit_exact": pattern_ok,
+                     "exec_tflops": flops_exec / avg_launch_s / 1e12 if avg_launch_s else None,
+                     "avg_launch_ms": avg_launch_s * 1e3 if avg_launch_s else None},
+        "accuracy": {"max_abs_err_vs_oracle_samples": err,
+                     "meets_1e-6": (err is not None and err <= 1e-6),
+                     "D_pattern_bit_exact": pattern_ok,
                      "converged": stats["converged"], "trace_D": stats["trace"],
                      "idem_max": stats["idem_max"], "branch": "".join(map(str, stats["branch"])),
                      "branch_matches_oracle": (golden is not None and
                                                "".join(map(str, stats["branch"])) == golden["branch"])},
         "stage_ms": stats["ms"],
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(model, args.workload, golden, args.cpu_sample)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -53,10 +53,14 @@ def gather(H_col: np.ndarray, x0: np.ndarray, s: np.ndarray) -> np.ndarray:
 
 
 def sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter=100, branch_in=None,
-                    n_refine=0, keep_tape=False, consume=False):
+                    n_refine=0, keep_tape=False, consume=False, low_memory=False):
     """Run the shared SP2 sequence on every block (list of dense symmetric arrays,
     core rows first).  Returns (blocks, info).  With ``consume`` the given list is emptied
-    and its arrays are used directly (they are never written), to bound memory."""
+    and its arrays are used directly (they are never written), to bound memory.  With
+    ``low_memory`` the traces of X^2 are taken from its core diagonal alone (a dot product per
+    entry) and X^2 is recomputed block by block for the update, so one copy of the blocks
+    is held; the diagonal dot products may round differently from the full product, which
+    only matters at the last bit of the traces."""
     if consume:
         xs = list(blocks)
         blocks.clear()
@@ -68,13 +72,18 @@ def sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter=100, branch_i
     last_e = np.inf
     it = 0
     while True:
-        S = [x @ x for x in xs]
+        if low_memory:
+            # only the core diagonals of the squares are needed before the branch is known;
+            # the squares are recomputed for the update, one block at a time
+            S = [np.einsum("ij,ji->i", x[:k], x[:, :k]) for x, k in zip(xs, core_counts)]
+        else:
+            S = [x @ x for x in xs]
         t1 = 0.0
         t2 = 0.0
         for x, s, k in zip(xs, S, core_counts):
             for j in range(k):
                 t1 += x[j, j]
-                t2 += s[j, j]
+                t2 += s[j] if low_memory else s[j, j]
         e = abs(t1 - t2)
         traces.append((t1, t2))
         last_e = e
@@ -97,10 +106,15 @@ def sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter=100, branch_i
             d_lin = abs(2.0 * t1 - t2 - n_occ)
             margins.append(abs(d_sq - d_lin))
         branches.append(b)
-        if b == 1:
-            for x, s in zip(xs, S):
-                np.subtract(2.0 * x, s, out=s)   # s <- 2x - s, the same rounding as 2x - s
-        xs = S
+        if low_memory:
+            for q in range(len(xs)):
+                sq = xs[q] @ xs[q]
+                xs[q] = sq if b == 0 else np.subtract(2.0 * xs[q], sq, out=sq)
+        else:
+            if b == 1:
+                for x, s in zip(xs, S):
+                    np.subtract(2.0 * x, s, out=s)   # s <- 2x - s, the same rounding as 2x - s
+            xs = S
         if keep_tape:
             tape.append(list(xs))
         it += 1
@@ -134,7 +148,8 @@ def scatter_columns(xs, sub_ptr, sub_idx, core_counts, N: int, width: int | None
 
 
 def density_partitioned(H_col, H_val, n_occ, tau, core_size, method="block", idem_tol=None,
-                        max_iter=100, branch_in=None, n_refine=0, graph=None, keep_tape=False):
+                        max_iter=100, branch_in=None, n_refine=0, graph=None, keep_tape=False,
+                        low_memory=False):
     """The whole partitioned method: bounds, X2 graph, partition, gather, SP2, scatter."""
     N = H_col.shape[0]
     if idem_tol is None:
@@ -150,7 +165,7 @@ def density_partitioned(H_col, H_val, n_occ, tau, core_size, method="block", ide
     core_counts = np.diff(core_ptr)
     blocks0 = list(blocks) if keep_tape else None
     xs, info = sp2_partitioned(blocks, core_counts, n_occ, idem_tol, max_iter, branch_in,
-                               n_refine, keep_tape, consume=True)
+                               n_refine, keep_tape, consume=True, low_memory=low_memory)
     D_col, D_val = scatter_columns(xs, sub_ptr, sub_idx, core_counts, N)
     info.update(emin=emin, emax=emax, row_ptr=row_ptr, col=col, core_ptr=core_ptr,
                 core_vertices=core_vertices, sub_ptr=sub_ptr, sub_idx=sub_idx,

@@ -131,16 +131,17 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   if (stopped && *stopped) return;  // device-driven loop: the expansion already stopped
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
-  constexpr int KC = M::KC;
-  constexpr int V = 16 / sizeof(T);      // elements per 16-byte vector
-  constexpr int STR = KC + V;            // padded LDS row stride (elements)
-  constexpr int KG = KC / 4;             // k elements per lane group per chunk
+  constexpr int KC = M::KC;              // k elements per 128-byte row chunk
+  constexpr int V = 16 / sizeof(T);      // elements per 16-byte piece
+  constexpr int KG = KC / 4;             // k elements per lane group per chunk (two pieces)
   constexpr int WM = BT / 2;             // wave tile edge (2 x 2 waves)
   constexpr int MB = WM / 16;            // 16 x 16 blocks per wave tile edge
-  constexpr int TPR = kT / BT;           // staging threads per tile row
-  constexpr int VPT = 8 / TPR;           // 16-byte vectors per thread per operand and chunk
-  __shared__ __align__(16) T As[2][BT * STR];
-  __shared__ __align__(16) T Bs[2][BT * STR];
+  constexpr int OPB = BT * 128;          // LDS bytes per operand per buffer
+  constexpr int NLD = BT / 32;           // 1-KB wave loads per operand per chunk
+  // [buffer][operand][row-major 128-byte rows, the eight 16-byte pieces of row r stored at
+  // slot (piece ^ (r & 7)) so that sixteen lanes reading one piece of sixteen rows hit
+  // different banks]
+  __shared__ __align__(1024) unsigned char lds[2][2][OPB];
 
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;  // padding entry of an XCD queue
@@ -149,31 +150,27 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // global -> LDS staging: thread -> one tile row, VPT consecutive vectors of the chunk
-  const int lr = tid / TPR, lq = tid % TPR;
-  const int arow = bi * BT + lr, brow = bj * BT + lr;
-  const bool aok = arow < np, bok = brow < np;
-  const T* ap = A + off + (int64_t)(aok ? arow : 0) * np + lq * VPT * V;
-  const T* bp = B + off + (int64_t)(bok ? brow : 0) * np + lq * VPT * V;
-  uint4 ra[VPT], rb[VPT];
-  const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-
-  auto gload = [&](int k0) {
+  // Global -> LDS without registers (global_load_lds_dwordx4: lane L of a wave writes bytes
+  // [16 L, 16 L + 16) of the wave's 1-KB LDS window).  Each lane's source is chosen so the
+  // window receives the swizzled layout; rows beyond np (half-empty edge tiles) read row 0
+  // instead, which only feeds output rows / columns that are never stored.
+  const T* asrc[NLD];
+  const T* bsrc[NLD];
 #pragma unroll
-    for (int q = 0; q < VPT; ++q) {
-      ra[q] = aok ? *reinterpret_cast<const uint4*>(ap + k0 + q * V) : z4;
-      rb[q] = bok ? *reinterpret_cast<const uint4*>(bp + k0 + q * V) : z4;
-    }
-  };
-  auto sstore = [&](int buf) {
-    T* da = &As[buf][lr * STR + lq * VPT * V];
-    T* db = &Bs[buf][lr * STR + lq * VPT * V];
-#pragma unroll
-    for (int q = 0; q < VPT; ++q) {
-      *reinterpret_cast<uint4*>(da + q * V) = ra[q];
-      *reinterpret_cast<uint4*>(db + q * V) = rb[q];
-    }
-  };
+  for (int j = 0; j < NLD; ++j) {
+    const int slot = (wave * NLD + j) * 64 + lane;
+    const int r = slot >> 3, c = (slot & 7) ^ (r & 7);
+    const int ar = bi * BT + r, br = bj * BT + r;
+    asrc[j] = A + off + (int64_t)(ar < np ? ar : 0) * np + c * V;
+    bsrc[j] = B + off + (int64_t)(br < np ? br : 0) * np + c * V;
+  }
+#define GB_ISSUE(buf, k0)                                                                   \
+  _Pragma("unroll") for (int j = 0; j < NLD; ++j) {                                         \
+    __builtin_amdgcn_global_load_lds(asrc[j] + (k0), &lds[buf][0][(wave * NLD + j) * 1024], \
+                                     16, 0, 0);                                             \
+    __builtin_amdgcn_global_load_lds(bsrc[j] + (k0), &lds[buf][1][(wave * NLD + j) * 1024], \
+                                     16, 0, 0);                                             \
+  }
 
   acc_t acc[MB][MB];
 #pragma unroll
@@ -189,34 +186,44 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   const bool in_range = bi * BT + wr * WM < np && bj * BT + wc * WM < np;
   const bool lower_diag = MODE != 3 && bi == bj && wr > wc;
   const bool active = in_range && !lower_diag;
-  gload(0);
-  sstore(0);
+  // byte offsets of this lane's pieces (2g + h) in rows wr*WM + m*16 + r16 (A) and
+  // wc*WM + n*16 + r16 (B); (row & 7) = (r16 & 7) for every m
+  const int sw = r16 & 7;
+  const int pa0 = (wr * WM + r16) * 128, pb0 = (wc * WM + r16) * 128;
+  const int pc0 = (((2 * g) ^ sw) << 4), pc1 = (((2 * g + 1) ^ sw) << 4);
+
+  GB_ISSUE(0, 0)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
-    if (kc + 1 < nk) gload((kc + 1) * KC);
-    const T* as = &As[buf][(wr * WM + r16) * STR + g * KG];
-    const T* bs = &Bs[buf][(wc * WM + r16) * STR + g * KG];
-#pragma unroll
-    for (int h = 0; h < KG && active; h += V) {
-      T fa[MB][V], fb[MB][V];
-#pragma unroll
-      for (int m = 0; m < MB; ++m) {
-        const uint4 va = *reinterpret_cast<const uint4*>(as + m * 16 * STR + h);
-        const uint4 vb = *reinterpret_cast<const uint4*>(bs + m * 16 * STR + h);
-        __builtin_memcpy(fa[m], &va, 16);
-        __builtin_memcpy(fb[m], &vb, 16);
-      }
-#pragma unroll
-      for (int e = 0; e < V; ++e)
-#pragma unroll
-        for (int m = 0; m < MB; ++m)
-#pragma unroll
-          for (int n = 0; n < MB; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
+    if (kc + 1 < nk) {
+      GB_ISSUE(buf ^ 1, (kc + 1) * KC)
     }
-    if (kc + 1 < nk) sstore(buf ^ 1);
+    if (active) {
+      const unsigned char* la = lds[buf][0];
+      const unsigned char* lb = lds[buf][1];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int pc = h ? pc1 : pc0;
+        T fa[MB][V], fb[MB][V];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          __builtin_memcpy(fa[m], la + pa0 + m * 16 * 128 + pc, 16);
+          __builtin_memcpy(fb[m], lb + pb0 + m * 16 * 128 + pc, 16);
+        }
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+#pragma unroll
+          for (int m = 0; m < MB; ++m)
+#pragma unroll
+            for (int n = 0; n < MB; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
+      }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
+#undef GB_ISSUE
 
   if (!active) return;
   T* o = out + off;
@@ -240,69 +247,59 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 }
 
 
-// ---- split-BF16 squaring of an FP32 iterate ------------------------------------------------
-// x = hi + mid + lo with each part rounded to bf16 from the running remainder; X*X is summed
-// over the plane products that keep about NP*8 bits (NP = 1: hi*hi; NP = 2: + hi*lo, lo*hi;
-// NP = 3: + hi*mid, mid*hi, hi*lo, lo*hi, mid*mid) on v_mfma_f32_16x16x32_bf16 with FP32
-// accumulation.  The leading product and the correction products accumulate separately and
-// are added once at the end.  Same tiling, symmetry and k-slice assignment as k_symm_mm (a
-// lane group owns 8 consecutive k of each 32-k chunk).
+// ---- split-BF16 squaring ------------------------------------------------------------------
+// An FP32 iterate x is kept alongside its bf16 planes: hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid) (each remainder is exact in FP32, and hi + mid + lo = x whenever x
+// is an FP32 number).  X*X is summed over the plane products that keep about NP*8 bits
+// (NP = 1: hi*hi; NP = 2 (hi, lo = bf16(x - hi)): + hi*lo, lo*hi; NP = 3: + hi*mid, mid*hi,
+// hi*lo, lo*hi, mid*mid) on v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the leading
+// product and the corrections accumulate separately and are added once at the end.  The
+// epilogue writes X^2 in FP32 and its planes, so the next step reads ready planes (the
+// update 2X - X^2 rewrites them).  Tiling, symmetry and XCD order as in k_symm_mm; a lane
+// group owns 8 consecutive k of each 32-k chunk.
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 template <int NP>
-__global__ __launch_bounds__(kT, 2) void k_symm_mm_bf16(const float* __restrict__ X,
-                                                        float* __restrict__ out,
-                                                        const int4* __restrict__ tiles,
-                                                        const int64_t* __restrict__ offs,
-                                                        const int32_t* __restrict__ stopped) {
+__device__ __forceinline__ void split_planes(float x, __bf16* out) {
+  float rem = x;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const __bf16 h = (__bf16)rem;
+    out[p] = h;
+    rem = rem - (float)h;
+  }
+}
+
+template <int NP>
+__global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restrict__ Xp,
+                                                          int64_t pstride, float* __restrict__ S,
+                                                          __bf16* __restrict__ Sp,
+                                                          const int4* __restrict__ tiles,
+                                                          const int64_t* __restrict__ offs,
+                                                          const int32_t* __restrict__ stopped) {
   if (stopped && *stopped) return;
-  constexpr int KC = 32;            // k per chunk (one bf16 MFMA)
-  constexpr int STR = KC + 8;       // padded LDS row stride in bf16 elements (80 B)
-  __shared__ __align__(16) __bf16 As[NP][kBT * STR];
-  __shared__ __align__(16) __bf16 Bs[NP][kBT * STR];
+  constexpr int KC = 32;   // k per chunk (one bf16 MFMA): 64-byte rows of four 16-byte pieces
+  constexpr int OPB = kBT * 64;
+  // [plane][operand][rows of 64 B; piece c of row r at slot c ^ ((r >> 2) & 3), so sixteen
+  // lanes reading one piece of sixteen consecutive rows cover all sixteen 16-byte bank groups]
+  __shared__ __align__(1024) unsigned char lds[NP][2][OPB];
   const int4 tl = tiles[blockIdx.x];
-  if (tl.x < 0) return;  // padding entry of an XCD queue
+  if (tl.x < 0) return;
   const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
   const int64_t off = offs[s];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int lr = tid >> 1, lh = tid & 1;
-  const int arow = bi * kBT + lr, brow = bj * kBT + lr;
-  const bool aok = arow < np, bok = brow < np;
-  const float* ap = X + off + (int64_t)(aok ? arow : 0) * np + lh * 16;
-  const float* bp = X + off + (int64_t)(bok ? brow : 0) * np + lh * 16;
-  float4 ra[4], rb[4];
-  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-  auto gload = [&](int k0) {
+  // global -> LDS (global_load_lds_dwordx4, two 1-KB wave windows per plane and operand)
+  const __bf16* asrc[2];
+  const __bf16* bsrc[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ra[q] = aok ? *reinterpret_cast<const float4*>(ap + k0 + 4 * q) : z4;
-      rb[q] = bok ? *reinterpret_cast<const float4*>(bp + k0 + 4 * q) : z4;
-    }
-  };
-  auto split_store = [&](const float4* r, __bf16 (*dst)[kBT * STR]) {
-    __bf16 pl[NP][16];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float v[4] = {r[q].x, r[q].y, r[q].z, r[q].w};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        float rem = v[e];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const __bf16 h = (__bf16)rem;
-          pl[p][4 * q + e] = h;
-          rem = rem - (float)h;
-        }
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      __bf16* d = &dst[p][lr * STR + lh * 16];
-      __builtin_memcpy(d, &pl[p][0], 16);
-      __builtin_memcpy(d + 8, &pl[p][8], 16);
-    }
-  };
+  for (int j = 0; j < 2; ++j) {
+    const int slot = (wave * 2 + j) * 64 + lane;
+    const int r = slot >> 2, c = (slot & 3) ^ ((r >> 2) & 3);
+    const int ar = bi * kBT + r, br = bj * kBT + r;
+    asrc[j] = Xp + off + (int64_t)(ar < np ? ar : 0) * np + c * 8;
+    bsrc[j] = Xp + off + (int64_t)(br < np ? br : 0) * np + c * 8;
+  }
   f4v big[4][4], small[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -315,41 +312,80 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_bf16(const float* __restrict_
   const int nk = np / KC;
   const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
   const bool active = in_range && !(bi == bj && wr > wc);
-  gload(0);
+  const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
+  const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
+#define GB_FRAG(dst, plane, opnd, base, m) \
+  __builtin_memcpy(&(dst), &lds[plane][opnd][(base) + (m) * 16 * 64 + pc], 16)
   for (int kc = 0; kc < nk; ++kc) {
-    __syncthreads();
-    split_store(ra, As);
-    split_store(rb, Bs);
-    __syncthreads();
-    if (kc + 1 < nk) gload((kc + 1) * KC);
-    if (!active) continue;
-    bf8v fa[NP][4], fb[NP][4];
+    const int k0 = kc * KC;
+    __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
     for (int p = 0; p < NP; ++p)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        __builtin_memcpy(&fa[p][m], &As[p][(wr * 64 + m * 16 + r16) * STR + g * 8], 16);
-        __builtin_memcpy(&fb[p][m], &Bs[p][(wc * 64 + m * 16 + r16) * STR + g * 8], 16);
+      for (int j = 0; j < 2; ++j) {
+        __builtin_amdgcn_global_load_lds(asrc[j] + p * pstride + k0,
+                                         &lds[p][0][(wave * 2 + j) * 1024], 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(bsrc[j] + p * pstride + k0,
+                                         &lds[p][1][(wave * 2 + j) * 1024], 16, 0, 0);
       }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (!active) continue;
+    bf8v A0[4], B0[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      GB_FRAG(A0[m], 0, 0, pa0, m);
+      GB_FRAG(B0[m], 0, 1, pb0, m);
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        big[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][m], fb[0][n], big[m][n], 0, 0, 0);
-        if (NP >= 2) {
-          const int lo = NP - 1;
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][m], fb[lo][n], small[m][n], 0, 0, 0);
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[lo][m], fb[0][n], small[m][n], 0, 0, 0);
-        }
-        if (NP >= 3) {
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[0][m], fb[1][n], small[m][n], 0, 0, 0);
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][m], fb[0][n], small[m][n], 0, 0, 0);
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[1][m], fb[1][n], small[m][n], 0, 0, 0);
+      for (int n = 0; n < 4; ++n)
+        big[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], B0[n], big[m][n], 0, 0, 0);
+    if (NP >= 2) {
+      // (hi, last plane) and (last plane, hi)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        bf8v BL;
+        GB_FRAG(BL, NP - 1, 1, pb0, m);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          small[r][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[r], BL, small[r][m], 0, 0, 0);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        bf8v AL;
+        GB_FRAG(AL, NP - 1, 0, pa0, m);
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, B0[n], small[m][n], 0, 0, 0);
+      }
+    }
+    if (NP >= 3) {
+      // (hi, mid), (mid, hi), (mid, mid)
+      bf8v BM[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) GB_FRAG(BM[m], 1, 1, pb0, m);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], BM[n], small[m][n], 0, 0, 0);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        bf8v AM;
+        GB_FRAG(AM, 1, 0, pa0, m);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AM, B0[n], small[m][n], 0, 0, 0);
+          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AM, BM[n], small[m][n], 0, 0, 0);
         }
       }
+    }
   }
+#undef GB_FRAG
   if (!active) return;
-  float* o = out + off;
+  float* o = S + off;
   const bool mirror = bi != bj || wr < wc;
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -361,11 +397,34 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_bf16(const float* __restrict_
         const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
         if (grow < np && gcol < np) {
           const float v = big[m][n][r] + small[m][n][r];
-          o[(int64_t)grow * np + gcol] = v;
-          if (mirror) o[(int64_t)gcol * np + grow] = v;
+          __bf16 pl[NP];
+          split_planes<NP>(v, pl);
+          const int64_t q1 = (int64_t)grow * np + gcol, q2 = (int64_t)gcol * np + grow;
+          o[q1] = v;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p];
+          if (mirror) {
+            o[q2] = v;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q2] = pl[p];
+          }
         }
       }
 }
+
+// planes of an FP32 batch buffer (after the gather)
+template <int NP>
+__global__ void k_make_planes(const float* __restrict__ X, __bf16* __restrict__ Xp, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = i; q < n; q += stride) {
+    __bf16 pl[NP];
+    split_planes<NP>(X[q], pl);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) Xp[p * n + q] = pl[p];
+  }
+}
+
 
 // ---- traces and the branch decision (one workgroup, deterministic order) -----------------
 struct StepRec {
@@ -514,6 +573,26 @@ __global__ void k_update_dev(const T* __restrict__ X, T* __restrict__ S, int64_t
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = i; p < n; p += stride) S[p] = (T)2 * X[p] - S[p];
+}
+
+
+// S <- 2X - S and its planes (the branch 2X - X^2 of a split-bf16 loop); with a loop state
+// (device-driven loop) it acts only when that step's branch is 2X - X^2
+template <int NP>
+__global__ void k_lin_update_planes(const float* __restrict__ X, float* __restrict__ S,
+                                    __bf16* __restrict__ Sp, int64_t n,
+                                    const LoopState* __restrict__ st) {
+  if (st && (st->stopped || st->recs[st->it - 1].b != 1)) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t q = i; q < n; q += stride) {
+    const float v = 2.0f * X[q] - S[q];
+    S[q] = v;
+    __bf16 pl[NP];
+    split_planes<NP>(v, pl);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) Sp[p * n + q] = pl[p];
+  }
 }
 
 // S <- 2X - S over the whole batch buffer (padding stays 0); 16-byte vectors (every block
@@ -853,24 +932,6 @@ namespace {
 template <typename T>
 void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const int64_t* offs,
                    hipStream_t s, int planes = 0, const int32_t* stopped = nullptr) {
-  if constexpr (std::is_same<T, float>::value) {
-    if (planes > 0 && n64 > 0) fail(GB_EUNSUPPORTED, "split-bf16 squaring uses 128 tiles only");
-    if (planes == 1) {
-      hipLaunchKernelGGL(k_symm_mm_bf16<1>, dim3(n128), dim3(kT), 0, s, X, S, tiles, offs, stopped);
-      GB_LAUNCH_CHECK();
-      return;
-    }
-    if (planes == 2) {
-      hipLaunchKernelGGL(k_symm_mm_bf16<2>, dim3(n128), dim3(kT), 0, s, X, S, tiles, offs, stopped);
-      GB_LAUNCH_CHECK();
-      return;
-    }
-    if (planes == 3) {
-      hipLaunchKernelGGL(k_symm_mm_bf16<3>, dim3(n128), dim3(kT), 0, s, X, S, tiles, offs, stopped);
-      GB_LAUNCH_CHECK();
-      return;
-    }
-  }
   if (n128 > 0) {
     hipLaunchKernelGGL((k_symm_mm<T, 0, 128>), dim3(n128), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
                        tiles, offs, stopped);
@@ -881,6 +942,43 @@ void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const
                        tiles + n128, offs, stopped);
     GB_LAUNCH_CHECK();
   }
+}
+
+// split-bf16 square: planes of X -> X^2 (FP32) and its planes
+void launch_square_planes(const __bf16* Xp, float* S, __bf16* Sp, int64_t total,
+                          const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s,
+                          int planes, const int32_t* stopped = nullptr) {
+  if (ntiles <= 0) return;
+  if (planes == 1)
+    hipLaunchKernelGGL(k_symm_mm_planes<1>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
+                       offs, stopped);
+  else if (planes == 2)
+    hipLaunchKernelGGL(k_symm_mm_planes<2>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
+                       offs, stopped);
+  else
+    hipLaunchKernelGGL(k_symm_mm_planes<3>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
+                       offs, stopped);
+  GB_LAUNCH_CHECK();
+}
+
+void launch_update_planes(const float* X, float* S, __bf16* Sp, int64_t total, hipStream_t s,
+                          int planes, const LoopState* st = nullptr) {
+  const int gr = grid_for(total, kT, 65536);
+  if (planes == 1)
+    hipLaunchKernelGGL(k_lin_update_planes<1>, dim3(gr), dim3(kT), 0, s, X, S, Sp, total, st);
+  else if (planes == 2)
+    hipLaunchKernelGGL(k_lin_update_planes<2>, dim3(gr), dim3(kT), 0, s, X, S, Sp, total, st);
+  else
+    hipLaunchKernelGGL(k_lin_update_planes<3>, dim3(gr), dim3(kT), 0, s, X, S, Sp, total, st);
+  GB_LAUNCH_CHECK();
+}
+
+void make_planes(const float* X, __bf16* Xp, int64_t total, hipStream_t s, int planes) {
+  const int gr = grid_for(total, kT, 65536);
+  if (planes == 1) hipLaunchKernelGGL(k_make_planes<1>, dim3(gr), dim3(kT), 0, s, X, Xp, total);
+  else if (planes == 2) hipLaunchKernelGGL(k_make_planes<2>, dim3(gr), dim3(kT), 0, s, X, Xp, total);
+  else hipLaunchKernelGGL(k_make_planes<3>, dim3(gr), dim3(kT), 0, s, X, Xp, total);
+  GB_LAUNCH_CHECK();
 }
 
 // device tile table: the launch list, then the subgraph-major list
@@ -996,7 +1094,8 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
              const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
              const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
              gb_sp2_stats& st, DBuf<StepRec>& recs, hipStream_t s, int* stop_kind,
-             TapeData* tape = nullptr, int planes = 0, bool per_subgraph = false) {
+             TapeData* tape = nullptr, int planes = 0, bool per_subgraph = false,
+             __bf16** Xp = nullptr, __bf16** Sp = nullptr) {
   Timer tm;
   PinnedRec pin;
   int it = it0;
@@ -1004,12 +1103,24 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
   const int nl = (int)pl.launch.size();
   for (;;) {
     GB_HIP(hipEventRecord(tm.a, s));
-    if (per_subgraph) {
-      for (const int4& r : pl.ranges)
-        launch_square<T>(X, S, tiles.get() + nl + r.x, r.z == 128 ? r.y : 0,
-                         r.z == 128 ? 0 : r.y, offs.get(), s, planes);
-    } else {
-      launch_square<T>(X, S, tiles.get(), pl.l128, nl - pl.l128, offs.get(), s, planes);
+    if constexpr (std::is_same<T, float>::value) {
+      if (planes > 0) {
+        if (per_subgraph)
+          for (const int4& r : pl.ranges)
+            launch_square_planes(*Xp, S, *Sp, pl.total, tiles.get() + nl + r.x, r.y, offs.get(), s,
+                                 planes);
+        else
+          launch_square_planes(*Xp, S, *Sp, pl.total, tiles.get(), nl, offs.get(), s, planes);
+      }
+    }
+    if (planes == 0) {
+      if (per_subgraph) {
+        for (const int4& r : pl.ranges)
+          launch_square<T>(X, S, tiles.get() + nl + r.x, r.z == 128 ? r.y : 0,
+                           r.z == 128 ? 0 : r.y, offs.get(), s);
+      } else {
+        launch_square<T>(X, S, tiles.get(), pl.l128, nl - pl.l128, offs.get(), s);
+      }
     }
     GB_HIP(hipEventRecord(tm.b, s));
     int forced = -1;
@@ -1047,10 +1158,20 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
     if (branch_in == nullptr) st.min_margin = std::min(st.min_margin, r.margin);
     if (r.b == 1) {
       const int64_t n = pl.total;
-      hipLaunchKernelGGL(k_lin_update<T>, dim3(grid_for(n, kT, 65536)), dim3(kT), 0, s, X, S, n);
-      GB_LAUNCH_CHECK();
+      bool done_planes = false;
+      if constexpr (std::is_same<T, float>::value) {
+        if (planes > 0) {
+          launch_update_planes(X, S, *Sp, n, s, planes);
+          done_planes = true;
+        }
+      }
+      if (!done_planes) {
+        hipLaunchKernelGGL(k_lin_update<T>, dim3(grid_for(n, kT, 65536)), dim3(kT), 0, s, X, S, n);
+        GB_LAUNCH_CHECK();
+      }
     }
     std::swap(X, S);
+    if (planes > 0) std::swap(*Xp, *Sp);
     ++it;
     if (tape) {
       tape->branch.push_back((uint8_t)r.b);
@@ -1070,7 +1191,8 @@ template <typename T>
 int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
                    const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
                    const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
-                   gb_sp2_stats& st, hipStream_t s, int* stop_kind, int planes) {
+                   gb_sp2_stats& st, hipStream_t s, int* stop_kind, int planes,
+                   __bf16** Xp = nullptr, __bf16** Sp = nullptr) {
   constexpr int kReplays = 4;
   LoopState h;
   std::memset(&h, 0, sizeof(h));
@@ -1104,11 +1226,26 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
   for (int par = 0; par < 2; ++par) {
     T* A = par ? S : X;
     T* B = par ? X : S;
-    launch_square<T>(A, B, tiles.get(), pl.l128, nl - pl.l128, offs.get(), cs, planes,
-                     &d.get()->stopped);
-    hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
-                       npad.get(), P.core_ptr.get(), P.n_sub, d.get());
-    hipLaunchKernelGGL(k_update_dev<T>, dim3(ug), dim3(kT), 0, cs, A, B, pl.total, d.get());
+    bool planes_done = false;
+    if constexpr (std::is_same<T, float>::value) {
+      if (planes > 0) {
+        __bf16* Ap = par ? *Sp : *Xp;
+        __bf16* Bp = par ? *Xp : *Sp;
+        launch_square_planes(Ap, B, Bp, pl.total, tiles.get(), nl, offs.get(), cs, planes,
+                             &d.get()->stopped);
+        hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
+                           npad.get(), P.core_ptr.get(), P.n_sub, d.get());
+        launch_update_planes(A, B, Bp, pl.total, cs, planes, d.get());
+        planes_done = true;
+      }
+    }
+    if (!planes_done) {
+      launch_square<T>(A, B, tiles.get(), pl.l128, nl - pl.l128, offs.get(), cs, 0,
+                       &d.get()->stopped);
+      hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
+                         npad.get(), P.core_ptr.get(), P.n_sub, d.get());
+      hipLaunchKernelGGL(k_update_dev<T>, dim3(ug), dim3(kT), 0, cs, A, B, pl.total, d.get());
+    }
   }
   GB_HIP(hipStreamEndCapture(cs, &graph));
   GB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -1140,7 +1277,10 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
   const StepRec& last = h.recs[it_stop];
   if (last.stop == 1) *stop_kind = (branch_in && last.e > tol) ? 3 : 1;
   else *stop_kind = last.stop == 4 ? 4 : 2;
-  if ((it_stop - it0) % 2 == 1) std::swap(X, S);
+  if ((it_stop - it0) % 2 == 1) {
+    std::swap(X, S);
+    if (planes > 0) std::swap(*Xp, *Sp);
+  }
   return it_stop;
 }
 
@@ -1219,15 +1359,21 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     }
     if (!done) {
       if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
+      // split-bf16: planes of X and of X^2 (NP bf16 arrays of the batch size each)
+      DBuf<__bf16> XP(planes > 0 ? (size_t)planes * pl.total : 0, s);
+      DBuf<__bf16> SP(planes > 0 ? (size_t)planes * pl.total : 0, s);
+      __bf16* xp = XP.get();
+      __bf16* sp = SP.get();
+      if (planes > 0) make_planes(xf, xp, pl.total, s, planes);
       const double tol_lo = 1e-5 * N / 1024.0;
       if (o.launch_mode == 2)
         it_end = sp2_loop_graph<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
                                        o.branch_in, o.n_branch_in, true, it_end, st, s, &stop_kind,
-                                       planes);
+                                       planes, &xp, &sp);
       else
         it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
                                  o.branch_in, o.n_branch_in, true, it_end, st, recs, s, &stop_kind,
-                                 nullptr, planes, o.launch_mode == 1);
+                                 nullptr, planes, o.launch_mode == 1, &xp, &sp);
       // the final low-precision square was only the stop test: continue from X in FP64
       hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT),
                          0, s, xf, xd, pl.total);

@@ -26,10 +26,11 @@ def write_hashes():
     json.dump(out, open(os.path.join(HERE, "model_hashes.json"), "w"), indent=1)
 
 
-def write_partitioned(name, tau, core_size, n_samples=4096, seed=123):
+def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory=False):
     m = make_model(name)
     t = time.time()
-    D_col, D_val, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], tau, core_size)
+    D_col, D_val, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], tau, core_size,
+                                             low_memory=low_memory)
     N = m["N"]
     rng = np.random.default_rng(seed)
     rows = rng.integers(0, N, n_samples)
@@ -67,4 +68,4 @@ if __name__ == "__main__":
     if "n18000" in what:
         write_partitioned("n18000", 1e-5, 32)
     if "n100000" in what:
-        write_partitioned("n100000", 1e-5, 32)
+        write_partitioned("n100000", 1e-5, 32, low_memory=True)

@@ -241,3 +241,13 @@ def test_scatter_sorted_column_ell():
     assert D_col[2].tolist() == [0, 2, 5, 7, -1]
     assert D_val[2].tolist() == [13.0, 5.0, 1.0, 9.0, 0.0]
     assert (D_col[0] == -1).all()
+
+
+def test_low_memory_mode_matches(mid):
+    """The low-memory oracle (traces from diagonal dot products, squares recomputed for the
+    update) takes the same branches and returns the same D."""
+    m = mid
+    a = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], 1e-5, 16)
+    b = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], 1e-5, 16, low_memory=True)
+    assert a[2]["branch"] == b[2]["branch"]
+    assert np.abs(a[1] - b[1]).max() < 1e-13
