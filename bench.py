@@ -27,6 +27,26 @@ WORKLOADS = {"n18000": dict(tau=1e-5, core=32), "n1024": dict(tau=1e-5, core=16)
              "n100000": dict(tau=1e-5, core=32)}
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    path = os.path.join(ROOT, "paper_1603_00937_amd", "csrc", "sp2.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the squaring kernel from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None when no record
+    exists for this workload and precision or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    for rec in json.load(open(path)):
+        if (rec["workload"] == workload and rec["precision"] == precision
+                and rec["sp2_source_sha256"] == kernel_source_hash()):
+            return rec["bytes_per_launch"]
+    return None
+
+
 def run_step(gb, Hc, Hv, n_occ, tau, core, D, args):
     g = gb.build_graph(Hc, Hv, tau)
     p = gb.partition(g, core)
@@ -61,6 +81,31 @@ def rocpd_summary(path):
         gn, gt = grids[gmax]
         print(f"| {k} | {n} | {t / 1e6:.3f} | {t / n / 1e6:.4f} | {100 * t / total:.1f} | "
               f"{gn}, {gt / gn / 1e6:.4f} (grid {gmax // 256} WGs) |")
+
+
+def rocpd_counters(path):
+    """Per-kernel hardware counter values of a rocprofv3 --pmc database: for each kernel and
+    counter, dispatches, average and total value; for the squaring kernel also the average over
+    its largest-grid dispatches (the SP2 loop's batched launches)."""
+    import sqlite3
+    c = sqlite3.connect(path)
+    rows = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection"
+                     ).fetchall()
+    agg = {}
+    for name, grid, cname, val in rows:
+        short = name.replace("gbi::(anonymous namespace)::", "").replace("void ", "", 1)
+        short = short.split("(")[0]
+        d = agg.setdefault((short, cname), {})
+        g = d.setdefault(grid, [0, 0.0])
+        g[0] += 1
+        g[1] += float(val)
+    print("| kernel | counter | dispatches | average | total | largest-grid average |")
+    print("|---|---|---|---|---|---|")
+    for (k, cname), d in sorted(agg.items(), key=lambda kv: -sum(g[1] for g in kv[1].values())):
+        n = sum(g[0] for g in d.values())
+        t = sum(g[1] for g in d.values())
+        gmax = max(d)
+        print(f"| {k} | {cname} | {n} | {t / n:.6g} | {t:.6g} | {d[gmax][1] / d[gmax][0]:.6g} |")
 
 
 def md_run(args):
@@ -187,6 +232,8 @@ def main():
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
+    ap.add_argument("--rocpd-counters", default=None,
+                    help="summarise the counters of a rocprofv3 --pmc database")
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run the adaptive-graph displacement loop instead of the benchmark")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
@@ -197,6 +244,9 @@ def main():
     args = ap.parse_args()
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
+        return
+    if args.rocpd_counters:
+        rocpd_counters(args.rocpd_counters)
         return
     if args.copy_calibration:
         copy_calibration()
@@ -282,7 +332,8 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
                    "max_sub": stats["max_sub"], "sp2_iters": stats["iters"],
                    "refine_steps": stats["n_refine_done"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak if achieved else None, "traffic": None,
+                     "frac": achieved / peak if achieved else None,
+                     "traffic": measured_traffic(args.workload, precision),
                      "kernel": ("k_symm_mm_planes (batched X^2, split bf16)"
                                 if precision.startswith("bf16") else "k_symm_mm (batched X^2)"),
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,

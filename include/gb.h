@@ -80,7 +80,10 @@ typedef enum {
   GB_GRAPH_PATTERN = 1,
   /* Adaptive MD graph: {|Dprev_ij| >= tau_aux} united with X2(H, tau), symmetrised; aux is
    * the previous D in column-ELL form. */
-  GB_GRAPH_DPREV = 2
+  GB_GRAPH_DPREV = 2,
+  /* Eq. 8 with eps = 0: paths of length two in pattern(H) U {|Dprev_ij| >= tau_aux}
+   * (symmetrised); tau unused.  Dense in 3D systems: intended for small n. */
+  GB_GRAPH_DPREV_SYMBOLIC = 3
 } gb_graph_mode;
 
 typedef struct gb_graph_s gb_graph_t;
@@ -100,7 +103,10 @@ void gb_graph_destroy(gb_graph_t* g);
 
 /* Core selection (obs. vi-vii: a core may be any set of vertices, a "community"). */
 typedef enum {
-  GB_PART_BLOCK = 0  /* cores = consecutive runs of core_size vertices in vertex order */
+  GB_PART_BLOCK = 0, /* cores = consecutive runs of core_size vertices in vertex order      */
+  GB_PART_BFS = 1    /* the same runs cut from a Cuthill-McKee order of the graph: start at  *
+                      * the unvisited vertex of smallest (degree, index), append unvisited   *
+                      * neighbours by (degree, index); each core's vertices then ascending   */
 } gb_part_method;
 
 typedef struct gb_partition_s gb_partition_t;

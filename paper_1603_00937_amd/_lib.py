@@ -8,8 +8,8 @@ LIB_PATH = os.path.join(HERE, "libgb.so")
 GB_OK, GB_EINVAL, GB_ENOMEM, GB_EHIP, GB_ESHAPE, GB_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "GB_OK", -1: "GB_EINVAL", -2: "GB_ENOMEM", -3: "GB_EHIP", -4: "GB_ESHAPE",
                 -5: "GB_EUNSUPPORTED"}
-GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2}
-PART_METHODS = {"block": 0}
+GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2, "dprev_symbolic": 3}
+PART_METHODS = {"block": 0, "bfs": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4}
 
 

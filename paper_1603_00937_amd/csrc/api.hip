@@ -130,8 +130,9 @@ gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double 
     *out = nullptr;
     check_ell(H, "H");
     check_tau(tau, "tau");
-    if (mode < GB_GRAPH_X2 || mode > GB_GRAPH_DPREV) fail(GB_EINVAL, "unknown graph mode %d", mode);
-    if (mode == GB_GRAPH_DPREV) {
+    if (mode < GB_GRAPH_X2 || mode > GB_GRAPH_DPREV_SYMBOLIC)
+      fail(GB_EINVAL, "unknown graph mode %d", mode);
+    if (mode == GB_GRAPH_DPREV || mode == GB_GRAPH_DPREV_SYMBOLIC) {
       check_ell(aux, "aux (previous D)");
       check_tau(tau_aux, "tau_aux");
       if (aux->n != H->n) fail(GB_ESHAPE, "aux->n = %d differs from H->n = %d", aux->n, H->n);
@@ -145,6 +146,8 @@ gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double 
     try {
       if (mode == GB_GRAPH_PATTERN) {
         graph_pattern(aux ? *aux : *H, tau, g->csr, s);
+      } else if (mode == GB_GRAPH_DPREV_SYMBOLIC) {
+        graph_dprev_symbolic(*H, *aux, tau_aux, g->csr, s);
       } else {
         double emin, emax;
         bounds(*H, s, &emin, &emax);
@@ -198,11 +201,12 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
     *out = nullptr;
     if (!g) fail(GB_EINVAL, "graph is NULL");
     if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
-    if (method != GB_PART_BLOCK) fail(GB_EUNSUPPORTED, "partition method %d", method);
+    if (method != GB_PART_BLOCK && method != GB_PART_BFS)
+      fail(GB_EINVAL, "unknown partition method %d", method);
     hipStream_t s = as_stream(stream);
     auto* p = new gb_partition_s();
     try {
-      partition_block(g->csr, core_size, p->part, s);
+      partition_block(g->csr, core_size, p->part, s, method);
       GB_HIP(hipStreamSynchronize(s));
       detach(p->part);
     } catch (...) {
@@ -312,7 +316,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
       GB_HIP(hipStreamSynchronize(s));
       GB_HIP(hipEventElapsedTime(&st.ms_graph, e0, e1));
       GB_HIP(hipEventRecord(e0, s));
-      partition_block(g, core_size, own.part, s);
+      partition_block(g, core_size, own.part, s, GB_PART_BLOCK);
       GB_HIP(hipEventRecord(e1, s));
       GB_HIP(hipStreamSynchronize(s));
       GB_HIP(hipEventElapsedTime(&st.ms_part, e0, e1));

@@ -277,6 +277,51 @@ __global__ __launch_bounds__(kT) void k_union_rows(int n, const int32_t* __restr
   }
 }
 
+
+// two-hop closure: row i of the result = union over k in row i of P of row k of P (paths of
+// length two; P contains every self-loop, so one-hop edges are included), sorted, unique
+template <int PASS>
+__global__ __launch_bounds__(kT) void k_twohop_rows(int n, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ c,
+                                                    int32_t* __restrict__ cnt,
+                                                    const int32_t* __restrict__ row_ptr,
+                                                    int32_t* __restrict__ out_col) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int i = blockIdx.x;
+  const int nw = (n + 31) >> 5;
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem);
+  int32_t* wc = reinterpret_cast<int32_t*>(bits + nw);
+  int32_t* red = wc + nw;
+  for (int q = threadIdx.x; q < nw; q += kT) bits[q] = 0u;
+  __syncthreads();
+  for (int a = rp[i]; a < rp[i + 1]; ++a) {
+    const int k = c[a];
+    for (int p = rp[k] + threadIdx.x; p < rp[k + 1]; p += kT) {
+      const int j = c[p];
+      atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+  }
+  if (threadIdx.x == 0) atomicOr(&bits[i >> 5], 1u << (i & 31));
+  __syncthreads();
+  for (int q = threadIdx.x; q < nw; q += kT) wc[q] = __popc(bits[q]);
+  __syncthreads();
+  const int32_t tot = lds_exclusive_scan(wc, nw, red);
+  if (PASS == 0) {
+    if (threadIdx.x == 0) cnt[i] = tot;
+    return;
+  }
+  const int32_t base = row_ptr[i];
+  for (int q = threadIdx.x; q < nw; q += kT) {
+    uint32_t word = bits[q];
+    int32_t pos = base + wc[q];
+    while (word) {
+      const int b = __ffs(word) - 1;
+      out_col[pos++] = (q << 5) + b;
+      word &= word - 1u;
+    }
+  }
+}
+
 // entries of an ELL matrix with |a| >= tau, as (row-list) CSR counts / fill (rows unsorted
 // only if the ELL rows are; ELL rows are ascending so the output rows are ascending)
 template <int PASS>
@@ -459,6 +504,34 @@ void graph_pattern(const gb_ell& A, double tau, Csr& out, hipStream_t s) {
   GB_HIP(hipStreamSynchronize(s));
   transpose(A.n, rp.get(), c.get(), nnz, trp, tc, s);
   union_rows(A.n, rp.get(), c.get(), trp.get(), tc.get(), out, s);
+}
+
+void graph_dprev_symbolic(const gb_ell& H, const gb_ell& Dp, double tau_d, Csr& out,
+                          hipStream_t s) {
+  // P = pattern(H) U {|D_prev| >= tau_d} U its transpose (symmetric, with self-loops), then
+  // the symbolic square: Eq. 8 with eps = 0
+  Csr hp, P;
+  graph_pattern(H, 0.0, hp, s);
+  graph_union_dprev(hp, Dp, tau_d, P, s);
+  const int n = H.n;
+  const int nw = (n + 31) >> 5;
+  const size_t lds = (size_t)nw * 8 + kT * 4 + 64;
+  check_lds(lds, "two-hop graph");
+  DBuf<int32_t> cnt(n, s);
+  out.n = n;
+  out.row_ptr = DBuf<int32_t>(n + 1, s);
+  hipLaunchKernelGGL(k_twohop_rows<0>, dim3(n), dim3(kT), lds, s, n, P.row_ptr.get(), P.col.get(),
+                     cnt.get(), nullptr, nullptr);
+  GB_LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
+  int32_t nnz = 0;
+  GB_HIP(hipMemcpyAsync(&nnz, out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  out.nnz = nnz;
+  out.col = DBuf<int32_t>(nnz > 0 ? nnz : 1, s);
+  hipLaunchKernelGGL(k_twohop_rows<1>, dim3(n), dim3(kT), lds, s, n, P.row_ptr.get(), P.col.get(),
+                     nullptr, out.row_ptr.get(), out.col.get());
+  GB_LAUNCH_CHECK();
 }
 
 void graph_union_dprev(const Csr& base, const gb_ell& Dp, double tau_d, Csr& out,

@@ -78,6 +78,8 @@ void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream
 void graph_pattern(const gb_ell& A, double tau, Csr& out, hipStream_t s);
 void graph_union_dprev(const Csr& base, const gb_ell& Dp, double tau_d, Csr& out,
                        hipStream_t s);
+void graph_dprev_symbolic(const gb_ell& H, const gb_ell& Dp, double tau_d, Csr& out,
+                          hipStream_t s);
 
 // ---- partition (partition.hip) ----
 struct Part {
@@ -88,7 +90,7 @@ struct Part {
   DBuf<int32_t> col_sub, col_loc;   // vertex -> (subgraph, local index) of its core
   std::vector<int32_t> h_core_ptr, h_sub_ptr;  // host copies (sizes for planning)
 };
-void partition_block(const Csr& g, int32_t core_size, Part& out, hipStream_t s);
+void partition_block(const Csr& g, int32_t core_size, Part& out, hipStream_t s, int method);
 void detach(Csr& c);
 void detach(Part& p);
 

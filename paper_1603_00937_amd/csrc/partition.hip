@@ -122,9 +122,116 @@ __global__ void k_iota(int32_t* p, int n) {
   if (i < n) p[i] = i;
 }
 
+
+// ---- Cuthill-McKee vertex order (one workgroup; the queue order is inherently sequential) ---
+// Start at the unvisited vertex of smallest (degree, index); visit the queue in order, append
+// each vertex's unvisited neighbours sorted by (degree, index); repeat per component.  The
+// visited set is an LDS bitmap; the neighbours of one vertex are filtered, ranked and
+// appended by all threads together.
+constexpr int kCand = 2048;  // LDS capacity for one vertex's new neighbours
+
+__global__ __launch_bounds__(kT) void k_cm_order(int n, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ col,
+                                                 int32_t* __restrict__ order,
+                                                 int32_t* __restrict__ status) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int nw = (n + 31) >> 5;
+  uint32_t* seen = reinterpret_cast<uint32_t*>(smem);
+  int64_t* cand = reinterpret_cast<int64_t*>(seen + nw + (nw & 1));
+  __shared__ int32_t s_cnt, s_tail, s_head;
+  __shared__ int64_t s_best[kT];
+  for (int q = threadIdx.x; q < nw; q += kT) seen[q] = 0u;
+  if (threadIdx.x == 0) {
+    s_tail = 0;
+    s_head = 0;
+  }
+  __syncthreads();
+  while (true) {
+    // next component: unvisited vertex with the smallest (degree, index)
+    int64_t best = INT64_MAX;
+    for (int v = threadIdx.x; v < n; v += kT)
+      if (!(seen[v >> 5] & (1u << (v & 31)))) {
+        const int64_t key = ((int64_t)(rp[v + 1] - rp[v]) << 32) | v;
+        best = key < best ? key : best;
+      }
+    s_best[threadIdx.x] = best;
+    __syncthreads();
+    for (int h = kT / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h && s_best[threadIdx.x + h] < s_best[threadIdx.x])
+        s_best[threadIdx.x] = s_best[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (s_best[0] == INT64_MAX) break;  // every vertex visited
+    if (threadIdx.x == 0) {
+      const int v = (int)(s_best[0] & 0xffffffff);
+      seen[v >> 5] |= 1u << (v & 31);
+      order[s_tail] = v;
+      s_tail = s_tail + 1;
+    }
+    __syncthreads();
+    while (s_head < s_tail) {
+      const int v = order[s_head];
+      if (threadIdx.x == 0) s_cnt = 0;
+      __syncthreads();
+      for (int p = rp[v] + threadIdx.x; p < rp[v + 1]; p += kT) {
+        const int u = col[p];
+        if (!(seen[u >> 5] & (1u << (u & 31)))) {
+          const int slot = atomicAdd(&s_cnt, 1);
+          if (slot < kCand) cand[slot] = ((int64_t)(rp[u + 1] - rp[u]) << 32) | u;
+        }
+      }
+      __syncthreads();
+      const int c = s_cnt;
+      if (c > kCand) {
+        if (threadIdx.x == 0) status[0] = c;
+        return;  // uniform: every thread read the same count
+      }
+      // rank by (degree, index) and append; then mark visited
+      const int tail = s_tail;
+      for (int a = threadIdx.x; a < c; a += kT) {
+        const int64_t ka = cand[a];
+        int rank = 0;
+        for (int b = 0; b < c; ++b) rank += cand[b] < ka;
+        order[tail + rank] = (int)(ka & 0xffffffff);
+      }
+      __syncthreads();
+      for (int a = threadIdx.x; a < c; a += kT) {
+        const int u = (int)(cand[a] & 0xffffffff);
+        atomicOr(&seen[u >> 5], 1u << (u & 31));
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        s_tail = tail + c;
+        s_head = s_head + 1;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// each core's vertices sorted ascending (cores are blocks of the order)
+__global__ void k_sort_cores(const int32_t* __restrict__ order, const int32_t* __restrict__ core_ptr,
+                             int32_t* __restrict__ core_vtx) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  (void)c;
+  const int cc = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const int b = core_ptr[cc], e = core_ptr[cc + 1];
+  for (int i = b; i < e; ++i) core_vtx[i] = order[i];
+  for (int i = b + 1; i < e; ++i) {
+    const int x = core_vtx[i];
+    int j = i - 1;
+    while (j >= b && core_vtx[j] > x) {
+      core_vtx[j + 1] = core_vtx[j];
+      --j;
+    }
+    core_vtx[j + 1] = x;
+  }
+}
+
 }  // namespace
 
-void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s) {
+void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s, int method) {
   const int n = g.n;
   const int n_sub = (n + core_size - 1) / core_size;
   P.n = n;
@@ -136,8 +243,27 @@ void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s) {
   GB_HIP(hipMemcpyAsync(P.core_ptr.get(), P.h_core_ptr.data(), (n_sub + 1) * 4,
                         hipMemcpyHostToDevice, s));
   P.core_vtx = DBuf<int32_t>(n, s);
-  hipLaunchKernelGGL(k_iota, dim3((n + kT - 1) / kT), dim3(kT), 0, s, P.core_vtx.get(), n);
-  GB_LAUNCH_CHECK();
+  if (method == GB_PART_BFS) {
+    const int nw = (n + 31) >> 5;
+    const size_t lds = (size_t)(nw + 1) * 4 + (size_t)kCand * 8 + 64;
+    if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "bfs order: n = %d too large for one LDS bitmap", n);
+    DBuf<int32_t> order(n, s), status(1, s);
+    int32_t zero = 0;
+    GB_HIP(hipMemcpyAsync(status.get(), &zero, 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_cm_order, dim3(1), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
+                       order.get(), status.get());
+    GB_LAUNCH_CHECK();
+    int32_t st = 0;
+    GB_HIP(hipMemcpyAsync(&st, status.get(), 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipStreamSynchronize(s));
+    if (st) fail(GB_EUNSUPPORTED, "bfs order: a vertex has %d new neighbours (capacity %d)", st, kCand);
+    hipLaunchKernelGGL(k_sort_cores, dim3(n_sub), dim3(64), 0, s, order.get(), P.core_ptr.get(),
+                       P.core_vtx.get());
+    GB_LAUNCH_CHECK();
+  } else {
+    hipLaunchKernelGGL(k_iota, dim3((n + kT - 1) / kT), dim3(kT), 0, s, P.core_vtx.get(), n);
+    GB_LAUNCH_CHECK();
+  }
 
   const int nw = (n + 31) >> 5;
   const size_t lds = (size_t)nw * 8 + kT * 4 + 64;

@@ -83,3 +83,44 @@ def test_n100000_fp32(gb):
     ref, st, err = _run(gb, "n100000", "fp32")
     assert st["converged"]
     assert err <= 1e-6
+
+
+def test_n100000_sampled_graph_partition_and_properties(gb):
+    """N = 100000 (clustered): the graph rows and subgraphs of sampled cores against the
+    oracle computed row by row, and properties of D that hold at any size."""
+    import torch
+    from synth import make_model
+    from oracle.bounds import gershgorin
+    from oracle.graph import graph_x2
+    m = make_model("n100000")
+    Hc = torch.from_numpy(m["H_col"]).cuda()
+    Hv = torch.from_numpy(m["H_val"]).cuda()
+    assert gb.spectral_bounds(Hc, Hv) == gershgorin(m["H_col"], m["H_val"])
+    g = gb.build_graph(Hc, Hv, 1e-5)
+    rp, cl = [t.cpu().numpy() for t in g.arrays()]
+    p = gb.partition(g, 32)
+    cp, sp, si = [t.cpu().numpy() for t in p.arrays()]
+    rng = np.random.default_rng(7)
+    cores = rng.choice(len(cp) - 1, size=6, replace=False)
+    emin, emax = gershgorin(m["H_col"], m["H_val"])
+    for c in cores:
+        verts = np.arange(cp[c], cp[c + 1])
+        rows = graph_x2(m["H_col"], m["H_val"], 1e-5, emin, emax, rows=verts)
+        for v, r in zip(verts, rows):
+            assert np.array_equal(cl[rp[v]:rp[v + 1]], r), v
+        halo = np.setdiff1d(np.unique(np.concatenate(rows)), verts)
+        assert np.array_equal(si[sp[c]:sp[c + 1]], np.concatenate([verts, halo]))
+    sizes = np.diff(sp)
+    print(f"n100000: n_sub={len(sizes)} sizes min/mean/max = {sizes.min()}/{sizes.mean():.0f}/"
+          f"{sizes.max()}, graph nnz={g.nnz}")
+    D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], 1e-5, partition=p, precision="bf16x6")
+    print(f"n100000 bf16x6: iters={st['iters']} trace={st['trace']:.6f} idem={st['idem']:.2e} "
+          f"idem_max={st['idem_max']:.2e} refine={st['n_refine_done']} ms={st['ms']}")
+    assert st["converged"]
+    assert abs(st["trace"] - m["n_occ"]) < 1e-3
+    assert st["idem_max"] < 1e-8
+    dc = D_col.cpu().numpy()
+    for c in cores[:2]:
+        sub = np.sort(si[sp[c]:sp[c + 1]])
+        for v in range(cp[c], cp[c + 1]):
+            assert np.array_equal(dc[v, :len(sub)], sub)

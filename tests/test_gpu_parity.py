@@ -220,3 +220,30 @@ def test_xcd_and_plain_tile_order_agree(gb, model_cache):
                                       core_size=16, tile_order=order)
         outs.append((D_val.cpu().numpy(), st["branch"]))
     assert outs[0][1] == outs[1][1] and np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("name,tau,core", [("small256", 1e-3, 8), ("n1024", 1e-5, 16),
+                                           ("tiny48", 1e-2, 5)])
+def test_bfs_partition_bit_exact(gb, model_cache, name, tau, core):
+    from oracle.graph import graph_x2
+    from oracle.partition import partition
+    m = model_cache(name)
+    g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), tau)
+    p = gb.partition(g, core, method="bfs")
+    cp, sp, si = _host(*p.arrays())
+    ocp, ocv, osp, osi = partition(*graph_x2(m["H_col"], m["H_val"], tau), core, "bfs")
+    assert np.array_equal(cp, ocp) and np.array_equal(sp, osp) and np.array_equal(si, osi)
+
+
+def test_density_with_bfs_partition(gb, model_cache):
+    from oracle.graph import graph_x2
+    from oracle.sp2 import density_partitioned
+    m = model_cache("small256")
+    oc, ov, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], 1e-4, 16, method="bfs")
+    g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), 1e-4)
+    p = gb.partition(g, 16, method="bfs")
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-4,
+                                  partition=p)
+    assert st["branch"] == info["branch"]
+    assert np.array_equal(D_col.cpu().numpy(), oc)
+    assert np.abs(D_val.cpu().numpy() - ov).max() <= FP64_TOL
