@@ -79,8 +79,15 @@ def test_n18000_fp32(gb, first):
     assert err <= (1e-6 if first else 1.5e-6)
 
 
-def test_n100000_fp32(gb):
-    ref, st, err = _run(gb, "n100000", "fp32")
+def test_n100000_fp64(gb):
+    ref, st, err = _run(gb, "n100000", "fp64")
+    assert "".join(map(str, st["branch"])) == ref["branch"]
+    assert st["iters"] == ref["iters"] and st["converged"]
+    assert err <= 1e-9
+
+
+def test_n100000_bf16x6(gb):
+    ref, st, err = _run(gb, "n100000", "bf16x6")
     assert st["converged"]
     assert err <= 1e-6
 
