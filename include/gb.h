@@ -178,8 +178,8 @@ typedef struct {
   double min_margin;         /* smallest | |t2-n| - |2t1-t2-n| | over chosen branches        */
   double t1[128], t2[128];   /* core traces of X and X^2 at each square                      */
   float ms_bounds, ms_graph, ms_part, ms_gather, ms_sp2, ms_refine, ms_scatter, ms_total;
-  float ms_square;           /* summed device time of the FP64 squaring launches (mode 0, 1) */
-  int32_t n_square;          /* number of FP64 squaring launches                             */
+  float ms_square;           /* summed device time of the FP64 SP2 steps (mode 0, 1)         */
+  int32_t n_square;          /* number of FP64 SP2 steps, one fused square+update launch each */
   float ms_square_lo;        /* the same for the low-precision squaring launches             */
   int32_t n_square_lo;
   int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */

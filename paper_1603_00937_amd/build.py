@@ -27,6 +27,14 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libgb.so")
+    # every symbol must resolve at load time (a kernel whose launch stub the host pass
+    # dropped shows up as an undefined symbol here, not as a compile error)
+    chk = subprocess.run(
+        [sys.executable, "-c", "import ctypes, sys; ctypes.CDLL(sys.argv[1], mode=2)", tmp],
+        capture_output=True, text=True)
+    if chk.returncode != 0:
+        sys.stderr.write(chk.stderr)
+        raise RuntimeError("libgb.so has unresolved symbols")
     os.replace(tmp, LIB)
     return LIB
 

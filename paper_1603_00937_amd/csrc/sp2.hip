@@ -20,6 +20,7 @@ namespace gbi {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 template <typename T>
 struct Mfma;
@@ -43,6 +44,19 @@ struct Mfma<float> {
   // output register r of lane l holds row (4(l/16) + r), column l%16
   __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Target builtins are called only from these non-template device functions: a kernel template
+// that names one directly is dropped from the host pass (no launch stub is emitted for it).
+// 16-byte global -> LDS copy of one lane: lane L of the wave fills bytes [16L, 16L + 16) of
+// the 1-KB LDS window that starts at `lds` (the same for every lane of the wave).
+__device__ inline void load_lds16(const void* g, void* lds) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void*)lds, 16, 0, 0);
+}
+__device__ inline f4v mma_bf16(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 namespace {
 
@@ -122,12 +136,16 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
 //   MODE 0: out = A*B          MODE 1: out = alpha*(A*B) + beta*E   (E symmetric)
 //   MODE 3: out = A*B for a general (non-symmetric) product with B symmetric: every tile
 //           (bi, bj) is listed and nothing is mirrored (the adjoint's Gbar*X)
+// In MODE 0 (A = B = X) the SP2 update is fused into the epilogue: with the branch
+// 2X - X^2 selected (lin, or *lin_flag on the device-driven loop) the kernel writes 2X - X^2,
+// else X^2.  X is symmetric, so the mirrored entry takes the same value.
 template <typename T, int MODE, int BT = 128>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, const T* __restrict__ B,
                                                    const T* __restrict__ E, T* __restrict__ out,
                                                    T alpha, T beta, const int4* __restrict__ tiles,
                                                    const int64_t* __restrict__ offs,
-                                                   const int32_t* __restrict__ stopped) {
+                                                   const int32_t* __restrict__ stopped,
+                                                   int lin, const int32_t* __restrict__ lin_flag) {
   if (stopped && *stopped) return;  // device-driven loop: the expansion already stopped
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
@@ -166,10 +184,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   }
 #define GB_ISSUE(buf, k0)                                                                   \
   _Pragma("unroll") for (int j = 0; j < NLD; ++j) {                                         \
-    __builtin_amdgcn_global_load_lds(asrc[j] + (k0), &lds[buf][0][(wave * NLD + j) * 1024], \
-                                     16, 0, 0);                                             \
-    __builtin_amdgcn_global_load_lds(bsrc[j] + (k0), &lds[buf][1][(wave * NLD + j) * 1024], \
-                                     16, 0, 0);                                             \
+    load_lds16(asrc[j] + (k0), &lds[buf][0][(wave * NLD + j) * 1024]);                      \
+    load_lds16(bsrc[j] + (k0), &lds[buf][1][(wave * NLD + j) * 1024]);                      \
   }
 
   acc_t acc[MB][MB];
@@ -228,6 +244,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   if (!active) return;
   T* o = out + off;
   const T* e = E + off;
+  const T* xa = A + off;
+  const bool do_lin = MODE == 0 && (lin_flag ? *lin_flag == 1 : lin != 0);
   const bool mirror = MODE != 3 && (bi != bj || wr < wc);
 #pragma unroll
   for (int m = 0; m < MB; ++m)
@@ -240,6 +258,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
         if (grow < np && gcol < np) {
           T v = acc[m][n][r];
           if (MODE == 1) v = alpha * v + beta * e[(int64_t)grow * np + gcol];
+          if (do_lin) v = (T)2 * xa[(int64_t)grow * np + gcol] - v;
           o[(int64_t)grow * np + gcol] = v;
           if (mirror) o[(int64_t)gcol * np + grow] = v;
         }
@@ -254,10 +273,9 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 // (NP = 1: hi*hi; NP = 2 (hi, lo = bf16(x - hi)): + hi*lo, lo*hi; NP = 3: + hi*mid, mid*hi,
 // hi*lo, lo*hi, mid*mid) on v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the leading
 // product and the corrections accumulate separately and are added once at the end.  The
-// epilogue writes X^2 in FP32 and its planes, so the next step reads ready planes (the
-// update 2X - X^2 rewrites them).  Tiling, symmetry and XCD order as in k_symm_mm; a lane
+// epilogue applies the SP2 update (X^2 or 2X - X^2, from the FP32 iterate) and writes the new
+// iterate in FP32 and its planes, so the next step reads ready planes.  Tiling, symmetry and XCD order as in k_symm_mm; a lane
 // group owns 8 consecutive k of each 32-k chunk.
-typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 template <int NP>
 __device__ __forceinline__ void split_planes(float x, __bf16* out) {
@@ -276,7 +294,9 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
                                                           __bf16* __restrict__ Sp,
                                                           const int4* __restrict__ tiles,
                                                           const int64_t* __restrict__ offs,
-                                                          const int32_t* __restrict__ stopped) {
+                                                          const int32_t* __restrict__ stopped,
+                                                          const float* __restrict__ X, int lin,
+                                                          const int32_t* __restrict__ lin_flag) {
   if (stopped && *stopped) return;
   constexpr int KC = 32;   // k per chunk (one bf16 MFMA): 64-byte rows of four 16-byte pieces
   constexpr int OPB = kBT * 64;
@@ -323,10 +343,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
     for (int p = 0; p < NP; ++p)
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        __builtin_amdgcn_global_load_lds(asrc[j] + p * pstride + k0,
-                                         &lds[p][0][(wave * 2 + j) * 1024], 16, 0, 0);
-        __builtin_amdgcn_global_load_lds(bsrc[j] + p * pstride + k0,
-                                         &lds[p][1][(wave * 2 + j) * 1024], 16, 0, 0);
+        load_lds16(asrc[j] + p * pstride + k0, &lds[p][0][(wave * 2 + j) * 1024]);
+        load_lds16(bsrc[j] + p * pstride + k0, &lds[p][1][(wave * 2 + j) * 1024]);
       }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
@@ -341,7 +359,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int n = 0; n < 4; ++n)
-        big[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], B0[n], big[m][n], 0, 0, 0);
+        big[m][n] = mma_bf16(A0[m], B0[n], big[m][n]);
     if (NP >= 2) {
       // (hi, last plane) and (last plane, hi)
 #pragma unroll
@@ -350,7 +368,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
         GB_FRAG(BL, NP - 1, 1, pb0, m);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          small[r][m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[r], BL, small[r][m], 0, 0, 0);
+          small[r][m] = mma_bf16(A0[r], BL, small[r][m]);
       }
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -358,7 +376,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
         GB_FRAG(AL, NP - 1, 0, pa0, m);
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, B0[n], small[m][n], 0, 0, 0);
+          small[m][n] = mma_bf16(AL, B0[n], small[m][n]);
       }
     }
     if (NP >= 3) {
@@ -370,15 +388,15 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
       for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0[m], BM[n], small[m][n], 0, 0, 0);
+          small[m][n] = mma_bf16(A0[m], BM[n], small[m][n]);
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
         bf8v AM;
         GB_FRAG(AM, 1, 0, pa0, m);
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AM, B0[n], small[m][n], 0, 0, 0);
-          small[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AM, BM[n], small[m][n], 0, 0, 0);
+          small[m][n] = mma_bf16(AM, B0[n], small[m][n]);
+          small[m][n] = mma_bf16(AM, BM[n], small[m][n]);
         }
       }
     }
@@ -386,6 +404,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
 #undef GB_FRAG
   if (!active) return;
   float* o = S + off;
+  const float* xa = X + off;
+  const bool do_lin = lin_flag ? *lin_flag == 1 : lin != 0;
   const bool mirror = bi != bj || wr < wc;
 #pragma unroll
   for (int m = 0; m < 4; ++m)
@@ -396,7 +416,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
         const int grow = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4) + r;
         const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
         if (grow < np && gcol < np) {
-          const float v = big[m][n][r] + small[m][n][r];
+          float v = big[m][n][r] + small[m][n][r];
+          if (do_lin) v = 2.0f * xa[(int64_t)grow * np + gcol] - v;
           __bf16 pl[NP];
           split_planes<NP>(v, pl);
           const int64_t q1 = (int64_t)grow * np + gcol, q2 = (int64_t)gcol * np + grow;
@@ -426,31 +447,38 @@ __global__ void k_make_planes(const float* __restrict__ X, __bf16* __restrict__ 
 }
 
 
-// ---- traces and the branch decision (one workgroup, deterministic order) -----------------
+// ---- traces and the branch decision --------------------------------------------------------
+// t1 = sum over subgraphs of the core diagonal of X; t2 = the same for X^2, which for the
+// symmetric X is the sum of the squared entries of the core rows.  Taking t2 from X lets the
+// stop test and the branch come before the square: the last square of the loop is not
+// needed, and the square kernel applies the update in its epilogue.  One workgroup per
+// subgraph writes its two partial sums (fixed order); one workgroup adds them (fixed order)
+// and decides.
 struct StepRec {
   double t1, t2, e, margin;
   int32_t b, stop, pad0, pad1;
 };
 
-// forced: -1 choose by the trace rule, 0/1 replay that branch, 2 stop (replay exhausted)
 template <typename T>
-__global__ __launch_bounds__(kT) void k_trace_branch(const T* __restrict__ X, const T* __restrict__ S,
-                                                     const int64_t* __restrict__ offs,
-                                                     const int32_t* __restrict__ npad,
-                                                     const int32_t* __restrict__ core_ptr, int n_sub,
-                                                     double n_occ, double tol, int forced,
-                                                     int at_max, StepRec* __restrict__ rec) {
+__global__ __launch_bounds__(kT) void k_trace_rows(const T* __restrict__ X,
+                                                   const int64_t* __restrict__ offs,
+                                                   const int32_t* __restrict__ npad,
+                                                   const int32_t* __restrict__ core_ptr,
+                                                   double* __restrict__ part,
+                                                   const int32_t* __restrict__ stopped) {
+  if (stopped && *stopped) return;
   __shared__ double r1[kT], r2[kT];
+  const int s = blockIdx.x;
+  const int np = npad[s], k = core_ptr[s + 1] - core_ptr[s];
+  const T* xs = X + offs[s];
   double p1 = 0.0, p2 = 0.0;
-  for (int s = threadIdx.x; s < n_sub; s += kT) {
-    const int np = npad[s];
-    const int k = core_ptr[s + 1] - core_ptr[s];
-    const T* xs = X + offs[s];
-    const T* ss = S + offs[s];
-    for (int j = 0; j < k; ++j) {
-      p1 += (double)xs[(int64_t)j * np + j];
-      p2 += (double)ss[(int64_t)j * np + j];
+  for (int j = 0; j < k; ++j) {
+    const T* row = xs + (int64_t)j * np;
+    for (int a = threadIdx.x; a < np; a += kT) {
+      const double v = (double)row[a];
+      p2 += v * v;
     }
+    if (threadIdx.x == 0) p1 += (double)row[j];
   }
   r1[threadIdx.x] = p1;
   r2[threadIdx.x] = p2;
@@ -463,7 +491,39 @@ __global__ __launch_bounds__(kT) void k_trace_branch(const T* __restrict__ X, co
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double t1 = r1[0], t2 = r2[0];
+    part[2 * s] = r1[0];
+    part[2 * s + 1] = r2[0];
+  }
+}
+
+__device__ void sum_partials(const double* __restrict__ part, int n_sub, double* t1, double* t2) {
+  __shared__ double r1[kT], r2[kT];
+  double p1 = 0.0, p2 = 0.0;
+  for (int s = threadIdx.x; s < n_sub; s += kT) {
+    p1 += part[2 * s];
+    p2 += part[2 * s + 1];
+  }
+  r1[threadIdx.x] = p1;
+  r2[threadIdx.x] = p2;
+  __syncthreads();
+  for (int h = kT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      r1[threadIdx.x] += r1[threadIdx.x + h];
+      r2[threadIdx.x] += r2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  *t1 = r1[0];
+  *t2 = r2[0];
+}
+
+// forced: -1 choose by the trace rule, 0/1 replay that branch, 2 stop (record only)
+__global__ __launch_bounds__(kT) void k_decide(const double* __restrict__ part, int n_sub,
+                                               double n_occ, double tol, int forced, int at_max,
+                                               StepRec* __restrict__ rec) {
+  double t1, t2;
+  sum_partials(part, n_sub, &t1, &t2);
+  if (threadIdx.x == 0) {
     const double e = fabs(t1 - t2);
     const double dsq = fabs(t2 - n_occ), dlin = fabs(2.0 * t1 - t2 - n_occ);
     StepRec q;
@@ -472,72 +532,37 @@ __global__ __launch_bounds__(kT) void k_trace_branch(const T* __restrict__ X, co
     q.e = e;
     q.margin = fabs(dsq - dlin);
     q.pad0 = q.pad1 = 0;
-    if (forced == 2) {
-      q.stop = 1;
-      q.b = -1;
-    } else if (forced >= 0) {
-      q.stop = 0;
-      q.b = forced;
-    } else if (e <= tol) {
-      q.stop = 1;
-      q.b = -1;
-    } else if (at_max) {
-      q.stop = 2;
-      q.b = -1;
-    } else {
-      q.stop = 0;
-      q.b = dsq < dlin ? 0 : 1;
-    }
+    q.b = -1;
+    q.stop = 0;
+    if (forced == 2) q.stop = 1;
+    else if (forced >= 0) q.b = forced;
+    else if (e <= tol) q.stop = 1;
+    else if (at_max) q.stop = 2;
+    else q.b = dsq < dlin ? 0 : 1;
     *rec = q;
   }
 }
 
-
-// ---- device-driven loop (hipGraph): the stop flag, iteration counter and records live on the
-// device, so a captured pair of iterations can be replayed without host round trips.  After
-// every update the new iterate sits in the other buffer (X^2 is written there, and 2X - X^2
-// is formed in place), so buffer roles simply alternate.
+// ---- device-driven loop (hipGraph): the stop flag, iteration counter, current branch and
+// records live on the device, so a captured pair of iterations can be replayed without host
+// round trips.  Every update writes the new iterate into the other buffer, so buffer roles
+// simply alternate.
 struct LoopState {
   int32_t it, stopped, max_iter, n_forced;  // n_forced < 0: choose by the trace rule
-  int32_t stag, pad;
+  int32_t stag, cur_b, it0;  // it0: first step of this loop (stagnation looks back 2 steps)
   double n_occ, tol;
   uint8_t forced[128];
   StepRec recs[128];
 };
 
-template <typename T>
-__global__ __launch_bounds__(kT) void k_trace_branch_dev(const T* __restrict__ X,
-                                                         const T* __restrict__ S,
-                                                         const int64_t* __restrict__ offs,
-                                                         const int32_t* __restrict__ npad,
-                                                         const int32_t* __restrict__ core_ptr,
-                                                         int n_sub, LoopState* __restrict__ st) {
+__global__ __launch_bounds__(kT) void k_decide_dev(const double* __restrict__ part, int n_sub,
+                                                   LoopState* __restrict__ st) {
   if (st->stopped) return;
-  __shared__ double r1[kT], r2[kT];
-  double p1 = 0.0, p2 = 0.0;
-  for (int s = threadIdx.x; s < n_sub; s += kT) {
-    const int np = npad[s];
-    const int k = core_ptr[s + 1] - core_ptr[s];
-    const T* xs = X + offs[s];
-    const T* ss = S + offs[s];
-    for (int j = 0; j < k; ++j) {
-      p1 += (double)xs[(int64_t)j * np + j];
-      p2 += (double)ss[(int64_t)j * np + j];
-    }
-  }
-  r1[threadIdx.x] = p1;
-  r2[threadIdx.x] = p2;
-  __syncthreads();
-  for (int h = kT / 2; h > 0; h >>= 1) {
-    if (threadIdx.x < h) {
-      r1[threadIdx.x] += r1[threadIdx.x + h];
-      r2[threadIdx.x] += r2[threadIdx.x + h];
-    }
-    __syncthreads();
-  }
+  double t1, t2;
+  sum_partials(part, n_sub, &t1, &t2);
   if (threadIdx.x == 0) {
     const int it = st->it;
-    const double t1 = r1[0], t2 = r2[0], n_occ = st->n_occ;
+    const double n_occ = st->n_occ;
     const double e = fabs(t1 - t2);
     const double dsq = fabs(t2 - n_occ), dlin = fabs(2.0 * t1 - t2 - n_occ);
     StepRec q;
@@ -555,58 +580,16 @@ __global__ __launch_bounds__(kT) void k_trace_branch_dev(const T* __restrict__ X
       q.stop = 1;
     } else if (it >= st->max_iter) {
       q.stop = 2;
-    } else if (st->stag && it >= 9 && e > st->recs[it - 2].e) {
+    } else if (st->stag && it - st->it0 >= 9 && e > st->recs[it - 2].e) {
       q.stop = 4;
     } else {
       q.b = dsq < dlin ? 0 : 1;
     }
     st->recs[it] = q;
+    st->cur_b = q.b;
     if (q.stop) st->stopped = 1;
     else st->it = it + 1;
   }
-}
-
-template <typename T>
-__global__ void k_update_dev(const T* __restrict__ X, T* __restrict__ S, int64_t n,
-                             const LoopState* __restrict__ st) {
-  if (st->stopped || st->recs[st->it - 1].b != 1) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = i; p < n; p += stride) S[p] = (T)2 * X[p] - S[p];
-}
-
-
-// S <- 2X - S and its planes (the branch 2X - X^2 of a split-bf16 loop); with a loop state
-// (device-driven loop) it acts only when that step's branch is 2X - X^2
-template <int NP>
-__global__ void k_lin_update_planes(const float* __restrict__ X, float* __restrict__ S,
-                                    __bf16* __restrict__ Sp, int64_t n,
-                                    const LoopState* __restrict__ st) {
-  if (st && (st->stopped || st->recs[st->it - 1].b != 1)) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = i; q < n; q += stride) {
-    const float v = 2.0f * X[q] - S[q];
-    S[q] = v;
-    __bf16 pl[NP];
-    split_planes<NP>(v, pl);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) Sp[p * n + q] = pl[p];
-  }
-}
-
-// S <- 2X - S over the whole batch buffer (padding stays 0); 16-byte vectors (every block
-// holds a multiple of 64 x 64 elements)
-template <typename T>
-__global__ void k_lin_update(const T* __restrict__ X, T* __restrict__ S, int64_t n) {
-  constexpr int V = 16 / sizeof(T);
-  typedef T vec_t __attribute__((ext_vector_type(V)));
-  const vec_t* x = reinterpret_cast<const vec_t*>(X);
-  vec_t* sv = reinterpret_cast<vec_t*>(S);
-  const int64_t nv = n / V;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = i; p < nv; p += stride) sv[p] = (T)2 * x[p] - sv[p];
 }
 
 template <typename TI, typename TO>
@@ -828,6 +811,7 @@ struct Plan {
   int l128 = 0;                  //   128 then the 64-edge ones, each group in XCD order
   std::vector<int4> tiles_full;  // every (bi, bj) with edge 128 (general products)
   std::vector<int4> ranges;      // per subgraph: first tile, tile count, edge
+  std::vector<int4> idem;        // 128-edge upper tiles covering the core rows (final check)
   double flops_alg = 0, flops_exec = 0;
   int max_npad = 0;
 };
@@ -907,8 +891,12 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
   for (int s : order) {
     const int np = pl.npad[s];
     const int nb = (np + kBT - 1) / kBT;
+    const int k = P.h_core_ptr[s + 1] - P.h_core_ptr[s];
     for (int bi = 0; bi < nb; ++bi)
-      for (int bj = 0; bj < nb; ++bj) pl.tiles_full.push_back(make_int4(s, bi, bj, np));
+      for (int bj = 0; bj < nb; ++bj) {
+        pl.tiles_full.push_back(make_int4(s, bi, bj, np));
+        if (bj >= bi && bi * kBT < k) pl.idem.push_back(make_int4(s, bi, bj, np));
+      }
   }
   return pl;
 }
@@ -929,47 +917,39 @@ struct TapeData {
 
 namespace {
 
+// One SP2 step on the tile lists: the new iterate X^2 (lin = 0) or 2X - X^2 (lin = 1), or the
+// branch read from *lin_flag on the device-driven loop.
 template <typename T>
 void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const int64_t* offs,
-                   hipStream_t s, int planes = 0, const int32_t* stopped = nullptr) {
+                   hipStream_t s, int lin = 0, const int32_t* stopped = nullptr,
+                   const int32_t* lin_flag = nullptr) {
   if (n128 > 0) {
     hipLaunchKernelGGL((k_symm_mm<T, 0, 128>), dim3(n128), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                       tiles, offs, stopped);
+                       tiles, offs, stopped, lin, lin_flag);
     GB_LAUNCH_CHECK();
   }
   if (n64 > 0) {
     hipLaunchKernelGGL((k_symm_mm<T, 0, 64>), dim3(n64), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                       tiles + n128, offs, stopped);
+                       tiles + n128, offs, stopped, lin, lin_flag);
     GB_LAUNCH_CHECK();
   }
 }
 
-// split-bf16 square: planes of X -> X^2 (FP32) and its planes
-void launch_square_planes(const __bf16* Xp, float* S, __bf16* Sp, int64_t total,
+// the same with split-bf16 squares: planes of X -> new iterate (FP32) and its planes
+void launch_square_planes(const __bf16* Xp, const float* X, float* S, __bf16* Sp, int64_t total,
                           const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s,
-                          int planes, const int32_t* stopped = nullptr) {
+                          int planes, int lin, const int32_t* stopped = nullptr,
+                          const int32_t* lin_flag = nullptr) {
   if (ntiles <= 0) return;
   if (planes == 1)
     hipLaunchKernelGGL(k_symm_mm_planes<1>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped);
+                       offs, stopped, X, lin, lin_flag);
   else if (planes == 2)
     hipLaunchKernelGGL(k_symm_mm_planes<2>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped);
+                       offs, stopped, X, lin, lin_flag);
   else
     hipLaunchKernelGGL(k_symm_mm_planes<3>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped);
-  GB_LAUNCH_CHECK();
-}
-
-void launch_update_planes(const float* X, float* S, __bf16* Sp, int64_t total, hipStream_t s,
-                          int planes, const LoopState* st = nullptr) {
-  const int gr = grid_for(total, kT, 65536);
-  if (planes == 1)
-    hipLaunchKernelGGL(k_lin_update_planes<1>, dim3(gr), dim3(kT), 0, s, X, S, Sp, total, st);
-  else if (planes == 2)
-    hipLaunchKernelGGL(k_lin_update_planes<2>, dim3(gr), dim3(kT), 0, s, X, S, Sp, total, st);
-  else
-    hipLaunchKernelGGL(k_lin_update_planes<3>, dim3(gr), dim3(kT), 0, s, X, S, Sp, total, st);
+                       offs, stopped, X, lin, lin_flag);
   GB_LAUNCH_CHECK();
 }
 
@@ -992,8 +972,8 @@ DBuf<int4> upload_tiles(const Plan& pl, hipStream_t s) {
 }
 
 void launch_plan_square_f64(const double* X, double* S, const Plan& pl, const int4* tiles,
-                            const int64_t* offs, hipStream_t s) {
-  launch_square<double>(X, S, tiles, pl.l128, (int)pl.launch.size() - pl.l128, offs, s);
+                            const int64_t* offs, hipStream_t s, int lin = 0) {
+  launch_square<double>(X, S, tiles, pl.l128, (int)pl.launch.size() - pl.l128, offs, s, lin);
 }
 
 struct Timer {
@@ -1086,9 +1066,11 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   st.square_flops_exec = pl.flops_exec;
 }
 
-// Runs the SP2 loop in precision T on buffers X (current iterate) and S (scratch).
-// Returns when the stop rule fires, the replay ends, max_iter is reached, or (low precision)
-// when the idempotency error stagnates.  Records every step into stats.
+// Runs the SP2 loop in precision T on buffers X (current iterate) and S (scratch).  Each step:
+// core traces of X and X^2 (from X), the FP64 decision, then one squaring launch that writes
+// the next iterate.  Returns the step index at which the stop rule fired, the replay ended,
+// max_iter was reached, or (low precision) the idempotency error stagnated; X then holds the
+// result.  Records every step into stats.
 template <typename T>
 int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
              const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
@@ -1101,43 +1083,18 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
   int it = it0;
   std::vector<double> es;
   const int nl = (int)pl.launch.size();
+  DBuf<double> part(2 * (size_t)pl.n_sub, s);
   for (;;) {
-    GB_HIP(hipEventRecord(tm.a, s));
-    if constexpr (std::is_same<T, float>::value) {
-      if (planes > 0) {
-        if (per_subgraph)
-          for (const int4& r : pl.ranges)
-            launch_square_planes(*Xp, S, *Sp, pl.total, tiles.get() + nl + r.x, r.y, offs.get(), s,
-                                 planes);
-        else
-          launch_square_planes(*Xp, S, *Sp, pl.total, tiles.get(), nl, offs.get(), s, planes);
-      }
-    }
-    if (planes == 0) {
-      if (per_subgraph) {
-        for (const int4& r : pl.ranges)
-          launch_square<T>(X, S, tiles.get() + nl + r.x, r.z == 128 ? r.y : 0,
-                           r.z == 128 ? 0 : r.y, offs.get(), s);
-      } else {
-        launch_square<T>(X, S, tiles.get(), pl.l128, nl - pl.l128, offs.get(), s);
-      }
-    }
-    GB_HIP(hipEventRecord(tm.b, s));
+    hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, s, X, offs.get(), npad.get(),
+                       P.core_ptr.get(), part.get(), nullptr);
     int forced = -1;
     if (branch_in) forced = it < n_branch_in ? (int)branch_in[it] : 2;
     const int at_max = it >= max_iter ? 1 : 0;
-    hipLaunchKernelGGL(k_trace_branch<T>, dim3(1), dim3(kT), 0, s, X, S, offs.get(), npad.get(),
-                       P.core_ptr.get(), P.n_sub, n_occ, tol, forced, at_max, recs.get() + (it % 2));
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, n_occ, tol, forced,
+                       at_max, recs.get());
     GB_LAUNCH_CHECK();
-    GB_HIP(hipMemcpyAsync(pin.h, recs.get() + (it % 2), sizeof(StepRec), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(pin.h, recs.get(), sizeof(StepRec), hipMemcpyDeviceToHost, s));
     GB_HIP(hipStreamSynchronize(s));
-    if (std::is_same<T, float>::value) {
-      st.ms_square_lo += elapsed(tm.a, tm.b);
-      st.n_square_lo += 1;
-    } else {
-      st.ms_square += elapsed(tm.a, tm.b);
-      st.n_square += 1;
-    }
     const StepRec r = *pin.h;
     if (it < 128) {
       st.t1[it] = r.t1;
@@ -1156,20 +1113,31 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
     }
     if (it < 128) st.branch[it] = (uint8_t)r.b;
     if (branch_in == nullptr) st.min_margin = std::min(st.min_margin, r.margin);
-    if (r.b == 1) {
-      const int64_t n = pl.total;
-      bool done_planes = false;
-      if constexpr (std::is_same<T, float>::value) {
-        if (planes > 0) {
-          launch_update_planes(X, S, *Sp, n, s, planes);
-          done_planes = true;
-        }
-      }
-      if (!done_planes) {
-        hipLaunchKernelGGL(k_lin_update<T>, dim3(grid_for(n, kT, 65536)), dim3(kT), 0, s, X, S, n);
-        GB_LAUNCH_CHECK();
+    const int lin = r.b == 1 ? 1 : 0;
+    GB_HIP(hipEventRecord(tm.a, s));
+    bool launched = false;
+    if constexpr (std::is_same<T, float>::value) {
+      if (planes > 0) {
+        if (per_subgraph)
+          for (const int4& rg : pl.ranges)
+            launch_square_planes(*Xp, X, S, *Sp, pl.total, tiles.get() + nl + rg.x, rg.y,
+                                 offs.get(), s, planes, lin);
+        else
+          launch_square_planes(*Xp, X, S, *Sp, pl.total, tiles.get(), nl, offs.get(), s, planes,
+                               lin);
+        launched = true;
       }
     }
+    if (!launched) {
+      if (per_subgraph) {
+        for (const int4& rg : pl.ranges)
+          launch_square<T>(X, S, tiles.get() + nl + rg.x, rg.z == 128 ? rg.y : 0,
+                           rg.z == 128 ? 0 : rg.y, offs.get(), s, lin);
+      } else {
+        launch_square<T>(X, S, tiles.get(), pl.l128, nl - pl.l128, offs.get(), s, lin);
+      }
+    }
+    GB_HIP(hipEventRecord(tm.b, s));
     std::swap(X, S);
     if (planes > 0) std::swap(*Xp, *Sp);
     ++it;
@@ -1181,12 +1149,21 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
         tape->ckpt.push_back(std::move(c));
       }
     }
+    GB_HIP(hipEventSynchronize(tm.b));
+    if (std::is_same<T, float>::value) {
+      st.ms_square_lo += elapsed(tm.a, tm.b);
+      st.n_square_lo += 1;
+    } else {
+      st.ms_square += elapsed(tm.a, tm.b);
+      st.n_square += 1;
+    }
   }
 }
 
 
-// Device-driven loop: two iterations (one per buffer parity) captured once in a hipGraph and
-// replayed; the host reads the stop flag every kReplays graph launches.
+// Device-driven loop: two iterations (one per buffer parity: traces, decision, squaring
+// launch reading the decision) captured once in a hipGraph and replayed; the host reads the
+// stop flag every kReplays graph launches.
 template <typename T>
 int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
                    const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
@@ -1197,6 +1174,7 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
   LoopState h;
   std::memset(&h, 0, sizeof(h));
   h.it = it0;
+  h.it0 = it0;
   h.max_iter = max_iter;
   h.n_forced = branch_in ? n_branch_in : -1;
   h.stag = stagnation_stop ? 1 : 0;
@@ -1204,6 +1182,7 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
   h.tol = tol;
   if (branch_in) std::memcpy(h.forced, branch_in, std::min(n_branch_in, 128));
   DBuf<LoopState> d(1, s);
+  DBuf<double> part(2 * (size_t)pl.n_sub, s);
   GB_HIP(hipMemcpyAsync(d.get(), &h, sizeof(h), hipMemcpyHostToDevice, s));
   GB_HIP(hipStreamSynchronize(s));
   hipStream_t cs = nullptr;
@@ -1222,30 +1201,26 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
   GB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   GB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   const int nl = (int)pl.launch.size();
-  const int ug = grid_for(pl.total, kT, 65536);
+  const int32_t* stopped = &d.get()->stopped;
+  const int32_t* cur_b = &d.get()->cur_b;
   for (int par = 0; par < 2; ++par) {
     T* A = par ? S : X;
     T* B = par ? X : S;
-    bool planes_done = false;
+    hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, cs, A, offs.get(), npad.get(),
+                       P.core_ptr.get(), part.get(), stopped);
+    hipLaunchKernelGGL(k_decide_dev, dim3(1), dim3(kT), 0, cs, part.get(), pl.n_sub, d.get());
+    bool launched = false;
     if constexpr (std::is_same<T, float>::value) {
       if (planes > 0) {
         __bf16* Ap = par ? *Sp : *Xp;
         __bf16* Bp = par ? *Xp : *Sp;
-        launch_square_planes(Ap, B, Bp, pl.total, tiles.get(), nl, offs.get(), cs, planes,
-                             &d.get()->stopped);
-        hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
-                           npad.get(), P.core_ptr.get(), P.n_sub, d.get());
-        launch_update_planes(A, B, Bp, pl.total, cs, planes, d.get());
-        planes_done = true;
+        launch_square_planes(Ap, A, B, Bp, pl.total, tiles.get(), nl, offs.get(), cs, planes, 0,
+                             stopped, cur_b);
+        launched = true;
       }
     }
-    if (!planes_done) {
-      launch_square<T>(A, B, tiles.get(), pl.l128, nl - pl.l128, offs.get(), cs, 0,
-                       &d.get()->stopped);
-      hipLaunchKernelGGL(k_trace_branch_dev<T>, dim3(1), dim3(kT), 0, cs, A, B, offs.get(),
-                         npad.get(), P.core_ptr.get(), P.n_sub, d.get());
-      hipLaunchKernelGGL(k_update_dev<T>, dim3(ug), dim3(kT), 0, cs, A, B, pl.total, d.get());
-    }
+    if (!launched)
+      launch_square<T>(A, B, tiles.get(), pl.l128, nl - pl.l128, offs.get(), cs, 0, stopped, cur_b);
   }
   GB_HIP(hipStreamEndCapture(cs, &graph));
   GB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -1272,11 +1247,12 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
       if (!branch_in) st.min_margin = std::min(st.min_margin, r.margin);
     }
   }
-  if (std::is_same<T, float>::value) st.n_square_lo += it_stop - it0 + 1;
-  else st.n_square += it_stop - it0 + 1;
+  if (std::is_same<T, float>::value) st.n_square_lo += it_stop - it0;
+  else st.n_square += it_stop - it0;
   const StepRec& last = h.recs[it_stop];
   if (last.stop == 1) *stop_kind = (branch_in && last.e > tol) ? 3 : 1;
   else *stop_kind = last.stop == 4 ? 4 : 2;
+  // it_stop - it0 squares were applied, each moving the iterate to the other buffer
   if ((it_stop - it0) % 2 == 1) {
     std::swap(X, S);
     if (planes > 0) std::swap(*Xp, *Sp);
@@ -1435,29 +1411,33 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     // converged during the FP64 steps: nothing to refine
   } else if (low && o.refine_kind == 0) {
     // FP64 refinement by McWeeny purification X <- 3X^2 - 2X^3 = 3S - 2 S X (S = X^2; S and X
-    // commute, so S X is symmetric and computed on upper tiles).  It drives every eigenvalue to
+    // commute, so S X is computed on upper tiles and mirrored).  It drives every eigenvalue to
     // 0 or 1 without acting on the trace, so the occupation the low-precision loop reached is
-    // kept.  Steps repeat until the FP64 stop test holds (at most n_refine, default 8).
-    DBuf<double> T64(pl.total, s);
+    // kept.  Steps repeat until the FP64 stop test holds (at most n_refine, default 8); the
+    // test takes the traces from X itself, so no square is spent on it.
+    T64 = DBuf<double>(pl.total, s);
+    DBuf<double> part(2 * (size_t)pl.n_sub, s);
     double* td = T64.get();
     const int max_steps = n_refine > 0 ? n_refine : 8;
     const int n64 = (int)pl.launch.size() - pl.l128;
     const int at = std::min(it_end, 127);
     StepRec r;
     for (int step = 0;; ++step) {
-      launch_square<double>(xd, sd, tiles.get(), pl.l128, n64, offs.get(), s);
-      hipLaunchKernelGGL(k_trace_branch<double>, dim3(1), dim3(kT), 0, s, xd, sd, offs.get(),
-                         npad.get(), P.core_ptr.get(), P.n_sub, (double)n_occ, tol, 2, 0, recs.get());
+      hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, offs.get(),
+                         npad.get(), P.core_ptr.get(), part.get(), nullptr);
+      hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, (double)n_occ,
+                         tol, 2, 0, recs.get());
       GB_LAUNCH_CHECK();
       GB_HIP(hipMemcpyAsync(&r, recs.get(), sizeof(r), hipMemcpyDeviceToHost, s));
       GB_HIP(hipStreamSynchronize(s));
       if (r.e <= tol || step == max_steps) break;
+      launch_square<double>(xd, sd, tiles.get(), pl.l128, n64, offs.get(), s);
       if (pl.l128 > 0)
         hipLaunchKernelGGL((k_symm_mm<double, 1, 128>), dim3(pl.l128), dim3(kT), 0, s, sd, xd, sd,
-                           td, -2.0, 3.0, tiles.get(), offs.get(), nullptr);
+                           td, -2.0, 3.0, tiles.get(), offs.get(), nullptr, 0, nullptr);
       if (n64 > 0)
         hipLaunchKernelGGL((k_symm_mm<double, 1, 64>), dim3(n64), dim3(kT), 0, s, sd, xd, sd, td,
-                           -2.0, 3.0, tiles.get() + pl.l128, offs.get(), nullptr);
+                           -2.0, 3.0, tiles.get() + pl.l128, offs.get(), nullptr, 0, nullptr);
       GB_LAUNCH_CHECK();
       std::swap(xd, td);
       ++st.n_refine_done;
@@ -1466,11 +1446,6 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     st.t1[at] = r.t1;
     st.t2[at] = r.t2;
     stop_kind = r.e <= tol ? 1 : 2;
-    // T64 is released at the end of this block: keep the refined X in X64's storage
-    if (xd == td) {
-      GB_HIP(hipMemcpyAsync(X64.get(), xd, pl.total * 8, hipMemcpyDeviceToDevice, s));
-      xd = X64.get();
-    }
   } else if (low) {
     // FP64 refinement: SP2 steps with FP64 traces from where the FP32 loop stopped
     const uint8_t* bin = nullptr;
@@ -1503,7 +1478,12 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   st.iters = it_end;
   st.converged = stop_kind == 1 ? 1 : 0;
 
-  // checks on the final X (S = X^2 from the last square)
+  // final idempotency check on the core rows: X^2 restricted to the tiles that hold them (all
+  // upper tiles in tile rows below the core size), then max |X^2 - X| over the core rows
+  DBuf<int4> idem_tiles(std::max<size_t>(pl.idem.size(), 1), s);
+  GB_HIP(hipMemcpyAsync(idem_tiles.get(), pl.idem.data(), pl.idem.size() * sizeof(int4),
+                        hipMemcpyHostToDevice, s));
+  launch_square<double>(xd, sd, idem_tiles.get(), (int)pl.idem.size(), 0, offs.get(), s);
   DBuf<double> per(pl.n_sub, s), mx(1, s);
   hipLaunchKernelGGL(k_idem<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, sd, offs.get(), npad.get(),
                      P.core_ptr.get(), P.sub_ptr.get(), per.get());
@@ -1561,17 +1541,13 @@ void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H, double* G_H, h
     for (int n = start; n + 1 < end; ++n) {
       double* xin = xs.back();
       double* xout = seg[n - start].get();
-      launch_plan_square_f64(xin, xout, pl, t.tiles.get(), t.offs.get(), s);
-      if (t.branch[n] == 1) {
-        hipLaunchKernelGGL(k_lin_update<double>, dim3(gfill), dim3(kT), 0, s, xin, xout, pl.total);
-        GB_LAUNCH_CHECK();
-      }
+      launch_plan_square_f64(xin, xout, pl, t.tiles.get(), t.offs.get(), s, t.branch[n] == 1);
       xs.push_back(xout);
     }
     for (int n = end - 1; n >= start; --n) {
       const double* X = xs[n - start];
       hipLaunchKernelGGL((k_symm_mm<double, 3>), dim3(ntf), dim3(kT), 0, s, G.get(), X, X,
-                         Pm.get(), 1.0, 0.0, t.tiles_full.get(), t.offs.get(), nullptr);
+                         Pm.get(), 1.0, 0.0, t.tiles_full.get(), t.offs.get(), nullptr, 0, nullptr);
       GB_LAUNCH_CHECK();
       const double c1 = t.branch[n] == 0 ? 1.0 : -1.0, c2 = t.branch[n] == 0 ? 0.0 : 2.0;
       hipLaunchKernelGGL(k_sym_combine, cgrid, dim3(256), 0, s, Pm.get(), G.get(), G2.get(), c1,
