@@ -46,6 +46,22 @@ const char* gb_version(void);
 const char* gb_last_error(void);
 
 /*
+ * Device memory hook.  By default every buffer the library needs (handles, batch buffers,
+ * scratch) comes from the device's stream-ordered pool (hipMallocAsync / hipFreeAsync, with
+ * the pool's release threshold raised so freed memory stays cached).  gb_set_allocator
+ * replaces that for every later allocation in the process: alloc(bytes, stream, ctx) returns
+ * device memory usable in stream order on `stream` (NULL on failure: the call then fails with
+ * GB_ENOMEM), free(ptr, stream, ctx) returns it.  Each buffer is freed through the allocator
+ * that made it, so the hook may be changed while handles are alive; it must stay valid (and
+ * ctx alive) until every buffer it made is freed.  gb_set_allocator(NULL, NULL, NULL)
+ * restores the default; exactly one of alloc/free NULL is GB_EINVAL.  Not thread-safe with
+ * respect to concurrent library calls.
+ */
+typedef void* (*gb_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*gb_free_fn)(void* ptr, void* stream, void* ctx);
+gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx);
+
+/*
  * Row-major ELLPACK matrix: `n` rows, `width` slots per row.  Row i occupies
  * col[i*width .. i*width+width-1] / val[...]: valid entries first with strictly ascending
  * column indices in [0, n), then padding col = -1, val = 0.0.
@@ -99,6 +115,9 @@ gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double 
 gb_status gb_graph_info(const gb_graph_t* g, int32_t* n, int64_t* nnz);
 /* Copy the CSR into caller device buffers row_ptr [n+1] and col [nnz]. */
 gb_status gb_graph_copy(const gb_graph_t* g, int32_t* row_ptr, int32_t* col, void* stream);
+/* Device views of the CSR (valid until gb_graph_destroy; the caller must not write them). */
+gb_status gb_graph_view(const gb_graph_t* g, int32_t* n, int64_t* nnz, const int32_t** row_ptr,
+                        const int32_t** col);
 void gb_graph_destroy(gb_graph_t* g);
 
 /* Core selection (obs. vi-vii: a core may be any set of vertices, a "community"). */
@@ -125,6 +144,11 @@ gb_status gb_partition_info(const gb_partition_t* p, int32_t* n_sub, int32_t* ma
  * (any may be NULL to skip it). */
 gb_status gb_partition_copy(const gb_partition_t* p, int32_t* core_ptr, int32_t* sub_ptr,
                             int32_t* sub_idx, void* stream);
+/* Device views of core_ptr [n_sub+1], sub_ptr [n_sub+1] and sub_idx [total] (valid until
+ * gb_partition_destroy; read-only).  Any output pointer may be NULL. */
+gb_status gb_partition_view(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
+                            const int32_t** core_ptr, const int32_t** sub_ptr,
+                            const int32_t** sub_idx);
 void gb_partition_destroy(gb_partition_t* p);
 
 /* Arithmetic of the squaring loop. */

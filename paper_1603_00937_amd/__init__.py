@@ -5,5 +5,5 @@ device tensors (memory) and the current HIP stream into the C ABI of include/gb.
 """
 from .api import (  # noqa: F401
     GbError, Graph, Partition, Tape, DensityFn, spectral_bounds, build_graph, partition, density,
-    density_with_grad, version,
+    density_with_grad, version, TorchAllocator, set_allocator,
 )

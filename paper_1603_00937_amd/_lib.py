@@ -51,6 +51,10 @@ class GbSp2Stats(ctypes.Structure):
 
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
+# gb_alloc_fn / gb_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
 SIGNATURES = {
     "gb_version": (ctypes.c_char_p, []),
     "gb_last_error": (ctypes.c_char_p, []),
@@ -60,12 +64,17 @@ SIGNATURES = {
                                         ctypes.c_int32, _vp, _P(_vp)]),
     "gb_graph_info": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int64)]),
     "gb_graph_copy": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
+    "gb_graph_view": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int64), _P(_vp),
+                                       _P(_vp)]),
     "gb_graph_destroy": (None, [_vp]),
     "gb_partition": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _P(_vp)]),
     "gb_partition_info": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32),
                                            _P(ctypes.c_int64)]),
     "gb_partition_copy": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "gb_partition_view": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32), _P(_vp),
+                                           _P(_vp), _P(_vp)]),
     "gb_partition_destroy": (None, [_vp]),
+    "gb_set_allocator": (ctypes.c_int32, [ALLOC_FN, FREE_FN, _vp]),
     "gb_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double, _P(GbSp2Opts),
                                     _P(GbEll), _P(GbSp2Stats), _vp]),
     "gb_density_vjp": (ctypes.c_int32, [_vp, _P(GbEll), _P(GbEll), _vp]),

@@ -52,6 +52,44 @@ def _ell(col, val):
                    val.data_ptr() if val is not None else None)
 
 
+class TorchAllocator:
+    """Device-memory hook that serves the library's allocations from torch's caching
+    allocator (blocks are reused in the order of the stream they were allocated on).
+    `live` maps pointer -> bytes of the blocks currently held by the library."""
+
+    def __init__(self):
+        self.live = {}
+        self.n_alloc = 0
+        self._alloc_fn = L.ALLOC_FN(self._alloc)
+        self._free_fn = L.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, stream, ctx):
+        try:
+            p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:  # reported by the library as GB_ENOMEM
+            return None
+        self.live[p] = int(nbytes)
+        self.n_alloc += 1
+        return p
+
+    def _free(self, ptr, stream, ctx):
+        self.live.pop(ptr, None)
+        torch.cuda.caching_allocator_delete(ptr)
+
+
+_ALLOCATORS = []  # every hook ever registered stays alive: a buffer is freed by its maker
+
+
+def set_allocator(allocator):
+    """Route later library allocations through `allocator` (a TorchAllocator), or back to
+    the library's own device pool with None."""
+    if allocator is None:
+        _check(_lib().gb_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None))
+        return
+    _ALLOCATORS.append(allocator)
+    _check(_lib().gb_set_allocator(allocator._alloc_fn, allocator._free_fn, None))
+
+
 def spectral_bounds(H_col, H_val):
     """Gershgorin (e_min, e_max) of H."""
     H = _ell(H_col, H_val)
@@ -73,6 +111,12 @@ class Graph:
     @property
     def handle(self):
         return self._h
+
+    def views(self):
+        """Device pointers (row_ptr, col) owned by the graph (read-only, valid while it lives)."""
+        rp, col = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib().gb_graph_view(self._h, None, None, ctypes.byref(rp), ctypes.byref(col)))
+        return rp.value, col.value
 
     def arrays(self):
         rp = torch.empty(self.n + 1, dtype=torch.int32, device="cuda")
@@ -108,6 +152,13 @@ class Partition:
     @property
     def handle(self):
         return self._h
+
+    def views(self):
+        """Device pointers (core_ptr, sub_ptr, sub_idx) owned by the partition (read-only)."""
+        a, b, c = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        _check(_lib().gb_partition_view(self._h, None, None, ctypes.byref(a), ctypes.byref(b),
+                                        ctypes.byref(c)))
+        return a.value, b.value, c.value
 
     def arrays(self):
         cp = torch.empty(self.n_sub + 1, dtype=torch.int32, device="cuda")

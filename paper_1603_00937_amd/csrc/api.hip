@@ -29,7 +29,16 @@ void fail(gb_status code, const char* fmt, ...) {
   throw Error{code};
 }
 
-void* dmalloc(size_t bytes, hipStream_t s) {
+Allocator g_alloc;  // the registered hook (all null: the device pool)
+
+void* dmalloc(size_t bytes, hipStream_t s, Allocator* used) {
+  *used = g_alloc;
+  void* p = nullptr;
+  if (used->alloc) {
+    p = used->alloc(bytes ? bytes : 1, (void*)s, used->ctx);
+    if (!p) fail(GB_ENOMEM, "registered allocator returned NULL for %zu bytes", bytes);
+    return p;
+  }
   // keep freed pool memory cached instead of returning it at every synchronisation
   std::call_once(g_pool_once, [] {
     int dev = 0;
@@ -39,7 +48,6 @@ void* dmalloc(size_t bytes, hipStream_t s) {
       (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
   });
-  void* p = nullptr;
   const hipError_t e = hipMallocAsync(&p, bytes ? bytes : 1, s);
   if (e != hipSuccess || !p) {
     (void)hipGetLastError();
@@ -48,8 +56,10 @@ void* dmalloc(size_t bytes, hipStream_t s) {
   return p;
 }
 
-void dfree(void* p, hipStream_t s) {
-  if (p) (void)hipFreeAsync(p, s);
+void dfree(void* p, hipStream_t s, const Allocator& a) {
+  if (!p) return;
+  if (a.free) a.free(p, (void*)s, a.ctx);
+  else (void)hipFreeAsync(p, s);
 }
 
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
@@ -114,6 +124,16 @@ extern "C" {
 const char* gb_version(void) { return "libgb 0.1.0 (gfx950)"; }
 
 const char* gb_last_error(void) { return g_err; }
+
+gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+      fail(GB_EINVAL, "alloc and free must both be set or both be NULL");
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+  });
+}
 
 gb_status gb_spectral_bounds(const gb_ell* H, void* stream, double* emin, double* emax) {
   return guarded([&] {
@@ -192,6 +212,17 @@ gb_status gb_graph_copy(const gb_graph_t* g, int32_t* row_ptr, int32_t* col, voi
   });
 }
 
+gb_status gb_graph_view(const gb_graph_t* g, int32_t* n, int64_t* nnz, const int32_t** row_ptr,
+                        const int32_t** col) {
+  return guarded([&] {
+    if (!g) fail(GB_EINVAL, "graph is NULL");
+    if (n) *n = g->csr.n;
+    if (nnz) *nnz = g->csr.nnz;
+    if (row_ptr) *row_ptr = g->csr.row_ptr.get();
+    if (col) *col = g->csr.col.get();
+  });
+}
+
 void gb_graph_destroy(gb_graph_t* g) { delete g; }
 
 gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, void* stream,
@@ -239,6 +270,20 @@ gb_status gb_partition_copy(const gb_partition_t* p, int32_t* core_ptr, int32_t*
       GB_HIP(hipMemcpyAsync(sub_ptr, P.sub_ptr.get(), (P.n_sub + 1) * 4, hipMemcpyDeviceToDevice, s));
     if (sub_idx && P.total)
       GB_HIP(hipMemcpyAsync(sub_idx, P.sub_idx.get(), P.total * 4, hipMemcpyDeviceToDevice, s));
+  });
+}
+
+gb_status gb_partition_view(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
+                            const int32_t** core_ptr, const int32_t** sub_ptr,
+                            const int32_t** sub_idx) {
+  return guarded([&] {
+    if (!p) fail(GB_EINVAL, "partition is NULL");
+    const Part& P = p->part;
+    if (n_sub) *n_sub = P.n_sub;
+    if (max_sub) *max_sub = P.max_sub;
+    if (core_ptr) *core_ptr = P.core_ptr.get();
+    if (sub_ptr) *sub_ptr = P.sub_ptr.get();
+    if (sub_idx) *sub_idx = P.sub_idx.get();
   });
 }
 

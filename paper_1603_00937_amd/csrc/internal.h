@@ -30,29 +30,36 @@ void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
 #define GB_LAUNCH_CHECK() GB_HIP(hipGetLastError())
 
-// ---- device memory: stream-ordered allocations from the device pool ----
-void* dmalloc(size_t bytes, hipStream_t s);
-void dfree(void* p, hipStream_t s);
+// ---- device memory: stream-ordered allocations from the device pool, or from the hook
+// registered with gb_set_allocator (each buffer remembers the allocator that made it) ----
+struct Allocator {
+  gb_alloc_fn alloc = nullptr;  // nullptr: the device pool
+  gb_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+void* dmalloc(size_t bytes, hipStream_t s, Allocator* used);
+void dfree(void* p, hipStream_t s, const Allocator& a);
 
 template <typename T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
   hipStream_t s = nullptr;
+  Allocator a;
   DBuf() = default;
   DBuf(size_t count, hipStream_t st) : n(count), s(st) {
-    if (count) p = static_cast<T*>(dmalloc(count * sizeof(T), st));
+    if (count) p = static_cast<T*>(dmalloc(count * sizeof(T), st, &a));
   }
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), a(o.a) { o.p = nullptr; o.n = 0; }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+    if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; a = o.a; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DBuf() { reset(); }
   void reset() {
-    if (p) dfree(p, s);
+    if (p) dfree(p, s, a);
     p = nullptr;
     n = 0;
   }

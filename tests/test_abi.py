@@ -101,6 +101,18 @@ def test_graph_and_partition_reject_bad_arguments(lib):
     assert lib.gb_spectral_bounds(ctypes.byref(H), None, None, None) == GB_EINVAL
 
 
+def test_views_and_allocator_reject_bad_arguments(lib):
+    from paper_1603_00937_amd._lib import ALLOC_FN, FREE_FN, GB_EINVAL, GB_OK
+    p = ctypes.c_void_p()
+    assert lib.gb_graph_view(None, None, None, ctypes.byref(p), None) == GB_EINVAL
+    assert lib.gb_partition_view(None, None, None, ctypes.byref(p), None, None) == GB_EINVAL
+    keep = ALLOC_FN(lambda n, s, c: None)
+    assert lib.gb_set_allocator(keep, FREE_FN(), None) == GB_EINVAL
+    assert lib.gb_set_allocator(ALLOC_FN(), FREE_FN(lambda p, s, c: None), None) == GB_EINVAL
+    assert b"both" in lib.gb_last_error()
+    assert lib.gb_set_allocator(ALLOC_FN(), FREE_FN(), None) == GB_OK
+
+
 def test_no_cpu_fallback_in_product_path():
     """The package never imports the oracle."""
     pkg = os.path.join(ROOT, "paper_1603_00937_amd")
