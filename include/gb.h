@@ -166,9 +166,11 @@ typedef enum {
 typedef struct {
   int32_t precision;         /* gb_precision; default GB_FP64                                */
   int32_t n_refine;          /* low precision: at most this many FP64 refinement steps       *
-                              * (0 = 8 McWeeny steps / max_iter SP2 steps)                    */
+                              * (0 = 8 McWeeny steps / 16 SP2 steps)                          */
   int32_t refine_kind;       /* low precision: 0 = McWeeny X <- 3X^2 - 2X^3 until the FP64    *
-                              * stop test holds; 1 = FP64 SP2 steps with the trace rule       */
+                              * stop test holds; 1 = FP64 SP2 steps until it holds, the first *
+                              * by the trace rule, then alternating X^2 / 2X - X^2 (replayed  *
+                              * from branch_in when that extends past the low-precision loop) */
   int32_t n_fp64_first;      /* low precision: run the first SP2 steps in FP64 (default 0)   */
   int32_t max_iter;          /* default 100 when 0                                           */
   double idem_tol;           /* stop when |Tr X - Tr X^2| <= idem_tol; 0 = 1e-10 * n / 1024   */
@@ -185,8 +187,10 @@ typedef struct {
                               * 2: batched launches with the stop flag, counter and branch    *
                               *    records on the device, two steps captured in a hipGraph    *
                               *    and replayed (no host round trip per step; no tape)        */
-  int32_t tile_policy;       /* squaring tile edge: 0 autotuned per 256-wide size bucket      *
-                              * (timed once per process), 1 = 128, 2 = 64                     */
+  int32_t tile_policy;       /* FP64 / FP32 squares: tile edge autotuned per 256-wide size     *
+                              * bucket (0, timed once per process), 1 = 128, 2 = 64;          *
+                              * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
+                              * buffered LDS, 2 = single-buffered                             */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
 } gb_sp2_opts;
 
@@ -208,6 +212,7 @@ typedef struct {
   int32_t n_square_lo;
   int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */
   int32_t n_refine_done;     /* McWeeny steps applied                                        */
+  int32_t planes_db;         /* split-bf16 loops: 1 if the double-buffered kernel variant ran */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
   struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */

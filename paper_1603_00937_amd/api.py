@@ -194,7 +194,8 @@ def _stats_dict(st: L.GbSp2Stats) -> dict:
                ("bounds", "graph", "part", "gather", "sp2", "refine", "scatter", "total",
                 "square", "square_lo")},
         "n_square": st.n_square, "n_square_lo": st.n_square_lo, "n_tile64": st.n_tile64,
-        "n_refine_done": st.n_refine_done, "square_flops": st.square_flops,
+        "n_refine_done": st.n_refine_done, "planes_db": st.planes_db,
+        "square_flops": st.square_flops,
         "square_flops_exec": st.square_flops_exec,
     }
 
@@ -263,7 +264,9 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     o.keep_tape = 1 if keep_tape else 0
     o.tape_stride = int(tape_stride)
     o.launch_mode = {"batched": 0, "per_subgraph": 1, "graph": 2}.get(launch_mode, launch_mode)
-    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2}.get(tile_policy, tile_policy)
+    # "db" / "sb": the split-bf16 kernel variant (double- / single-buffered LDS)
+    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "db": 1, "sb": 2}.get(
+        tile_policy, tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     st = L.GbSp2Stats()
     _check(_lib().gb_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),

@@ -288,8 +288,11 @@ __device__ __forceinline__ void split_planes(float x, __bf16* out) {
   }
 }
 
-template <int NP>
-__global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restrict__ Xp,
+// DB = 1: the LDS holds two chunks (96 KB with three planes, one workgroup per CU) and the
+// next chunk's loads run under the current chunk's products; DB = 0: one chunk (two
+// workgroups per CU), loaded and then consumed.
+template <int NP, int DB>
+__global__ __launch_bounds__(kT, DB ? 1 : 2) void k_symm_mm_planes(const __bf16* __restrict__ Xp,
                                                           int64_t pstride, float* __restrict__ S,
                                                           __bf16* __restrict__ Sp,
                                                           const int4* __restrict__ tiles,
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
   constexpr int OPB = kBT * 64;
   // [plane][operand][rows of 64 B; piece c of row r at slot c ^ ((r >> 2) & 3), so sixteen
   // lanes reading one piece of sixteen consecutive rows cover all sixteen 16-byte bank groups]
-  __shared__ __align__(1024) unsigned char lds[NP][2][OPB];
+  __shared__ __align__(1024) unsigned char lds[DB + 1][NP][2][OPB];
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;
   const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
@@ -335,20 +338,31 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
   const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
   const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
 #define GB_FRAG(dst, plane, opnd, base, m) \
-  __builtin_memcpy(&(dst), &lds[plane][opnd][(base) + (m) * 16 * 64 + pc], 16)
-  for (int kc = 0; kc < nk; ++kc) {
-    const int k0 = kc * KC;
-    __syncthreads();  // the previous chunk's reads are done
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        load_lds16(asrc[j] + p * pstride + k0, &lds[p][0][(wave * 2 + j) * 1024]);
-        load_lds16(bsrc[j] + p * pstride + k0, &lds[p][1][(wave * 2 + j) * 1024]);
-      }
+  __builtin_memcpy(&(dst), &lds[buf][plane][opnd][(base) + (m) * 16 * 64 + pc], 16)
+#define GB_ISSUE(b, k0)                                                                       \
+  _Pragma("unroll") for (int p = 0; p < NP; ++p)                                              \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
+      load_lds16(asrc[j] + p * pstride + (k0), &lds[b][p][0][(wave * 2 + j) * 1024]);         \
+      load_lds16(bsrc[j] + p * pstride + (k0), &lds[b][p][1][(wave * 2 + j) * 1024]);         \
+    }
+  if (DB) {
+    GB_ISSUE(0, 0)
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    if (!active) continue;
+  }
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = DB ? (kc & 1) : 0;
+    if (DB) {
+      if (kc + 1 < nk) {
+        GB_ISSUE(buf ^ 1, (kc + 1) * KC)
+      }
+    } else {
+      __syncthreads();  // the previous chunk's reads are done
+      GB_ISSUE(0, kc * KC)
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+    if (active) {
     bf8v A0[4], B0[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -400,7 +414,13 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes(const __bf16* __restri
         }
       }
     }
+    }  // active
+    if (DB) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // chunk kc + 1 has landed and every wave is done with chunk kc
+    }
   }
+#undef GB_ISSUE
 #undef GB_FRAG
   if (!active) return;
   float* o = S + off;
@@ -517,7 +537,8 @@ __device__ void sum_partials(const double* __restrict__ part, int n_sub, double*
   *t2 = r2[0];
 }
 
-// forced: -1 choose by the trace rule, 0/1 replay that branch, 2 stop (record only)
+// forced: -1 choose by the trace rule, 0/1 replay that branch, 2 stop (record only),
+// 10/11 take branch 0/1 unless the stop test holds (alternating refinement)
 __global__ __launch_bounds__(kT) void k_decide(const double* __restrict__ part, int n_sub,
                                                double n_occ, double tol, int forced, int at_max,
                                                StepRec* __restrict__ rec) {
@@ -535,6 +556,9 @@ __global__ __launch_bounds__(kT) void k_decide(const double* __restrict__ part, 
     q.b = -1;
     q.stop = 0;
     if (forced == 2) q.stop = 1;
+    else if (forced >= 10 && e <= tol) q.stop = 1;
+    else if (forced >= 10 && at_max) q.stop = 2;
+    else if (forced >= 10) q.b = forced - 10;
     else if (forced >= 0) q.b = forced;
     else if (e <= tol) q.stop = 1;
     else if (at_max) q.stop = 2;
@@ -812,6 +836,7 @@ struct Plan {
   std::vector<int4> tiles_full;  // every (bi, bj) with edge 128 (general products)
   std::vector<int4> ranges;      // per subgraph: first tile, tile count, edge
   std::vector<int4> idem;        // 128-edge upper tiles covering the core rows (final check)
+  int planes_db = 1;             // split-bf16 kernel variant (double-buffered LDS or not)
   double flops_alg = 0, flops_exec = 0;
   int max_npad = 0;
 };
@@ -936,21 +961,30 @@ void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const
 }
 
 // the same with split-bf16 squares: planes of X -> new iterate (FP32) and its planes
+template <int NP>
+void launch_planes_np(const __bf16* Xp, const float* X, float* S, __bf16* Sp, int64_t total,
+                      const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s, int db,
+                      int lin, const int32_t* stopped, const int32_t* lin_flag) {
+  if (db)
+    hipLaunchKernelGGL((k_symm_mm_planes<NP, 1>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
+                       tiles, offs, stopped, X, lin, lin_flag);
+  else
+    hipLaunchKernelGGL((k_symm_mm_planes<NP, 0>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
+                       tiles, offs, stopped, X, lin, lin_flag);
+  GB_LAUNCH_CHECK();
+}
+
 void launch_square_planes(const __bf16* Xp, const float* X, float* S, __bf16* Sp, int64_t total,
                           const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s,
-                          int planes, int lin, const int32_t* stopped = nullptr,
+                          int planes, int db, int lin, const int32_t* stopped = nullptr,
                           const int32_t* lin_flag = nullptr) {
   if (ntiles <= 0) return;
   if (planes == 1)
-    hipLaunchKernelGGL(k_symm_mm_planes<1>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped, X, lin, lin_flag);
+    launch_planes_np<1>(Xp, X, S, Sp, total, tiles, ntiles, offs, s, db, lin, stopped, lin_flag);
   else if (planes == 2)
-    hipLaunchKernelGGL(k_symm_mm_planes<2>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped, X, lin, lin_flag);
+    launch_planes_np<2>(Xp, X, S, Sp, total, tiles, ntiles, offs, s, db, lin, stopped, lin_flag);
   else
-    hipLaunchKernelGGL(k_symm_mm_planes<3>, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped, X, lin, lin_flag);
-  GB_LAUNCH_CHECK();
+    launch_planes_np<3>(Xp, X, S, Sp, total, tiles, ntiles, offs, s, db, lin, stopped, lin_flag);
 }
 
 void make_planes(const float* X, __bf16* Xp, int64_t total, hipStream_t s, int planes) {
@@ -1066,6 +1100,42 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   st.square_flops_exec = pl.flops_exec;
 }
 
+// Split-bf16 kernel variant (double-buffered LDS, one workgroup per CU, or single-buffered,
+// two per CU): policy 1 / 2 force it; policy 0 times one batched launch with each (one
+// warm-up, one timed) the first time a plane count is seen and keeps the faster for the
+// life of the process.
+int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, const float* X,
+                          float* S, __bf16* Sp, const int64_t* offs, hipStream_t s, int planes,
+                          int policy) {
+  if (policy == 1) return 1;
+  if (policy == 2) return 0;
+  const std::pair<int, int> key{20 + planes, 0};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) return it->second;
+  }
+  Timer tm;
+  const int nl = (int)pl.launch.size();
+  float best = INFINITY;
+  int choice = 1;
+  for (int db : {1, 0}) {
+    launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
+    GB_HIP(hipEventRecord(tm.a, s));
+    launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
+    GB_HIP(hipEventRecord(tm.b, s));
+    GB_HIP(hipStreamSynchronize(s));
+    const float ms = elapsed(tm.a, tm.b);
+    if (ms < best) {
+      best = ms;
+      choice = db;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = choice;
+  return choice;
+}
+
 // Runs the SP2 loop in precision T on buffers X (current iterate) and S (scratch).  Each step:
 // core traces of X and X^2 (from X), the FP64 decision, then one squaring launch that writes
 // the next iterate.  Returns the step index at which the stop rule fired, the replay ended,
@@ -1077,10 +1147,11 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
              const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
              gb_sp2_stats& st, DBuf<StepRec>& recs, hipStream_t s, int* stop_kind,
              TapeData* tape = nullptr, int planes = 0, bool per_subgraph = false,
-             __bf16** Xp = nullptr, __bf16** Sp = nullptr) {
+             __bf16** Xp = nullptr, __bf16** Sp = nullptr, bool alternate = false) {
   Timer tm;
   PinnedRec pin;
   int it = it0;
+  int prev_b = -1;
   std::vector<double> es;
   const int nl = (int)pl.launch.size();
   DBuf<double> part(2 * (size_t)pl.n_sub, s);
@@ -1089,6 +1160,7 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
                        P.core_ptr.get(), part.get(), nullptr);
     int forced = -1;
     if (branch_in) forced = it < n_branch_in ? (int)branch_in[it] : 2;
+    else if (alternate && prev_b >= 0) forced = 10 + (1 - prev_b);
     const int at_max = it >= max_iter ? 1 : 0;
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, n_occ, tol, forced,
                        at_max, recs.get());
@@ -1112,7 +1184,8 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
       return it;
     }
     if (it < 128) st.branch[it] = (uint8_t)r.b;
-    if (branch_in == nullptr) st.min_margin = std::min(st.min_margin, r.margin);
+    if (branch_in == nullptr && !alternate) st.min_margin = std::min(st.min_margin, r.margin);
+    prev_b = r.b;
     const int lin = r.b == 1 ? 1 : 0;
     GB_HIP(hipEventRecord(tm.a, s));
     bool launched = false;
@@ -1121,10 +1194,10 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
         if (per_subgraph)
           for (const int4& rg : pl.ranges)
             launch_square_planes(*Xp, X, S, *Sp, pl.total, tiles.get() + nl + rg.x, rg.y,
-                                 offs.get(), s, planes, lin);
+                                 offs.get(), s, planes, pl.planes_db, lin);
         else
           launch_square_planes(*Xp, X, S, *Sp, pl.total, tiles.get(), nl, offs.get(), s, planes,
-                               lin);
+                               pl.planes_db, lin);
         launched = true;
       }
     }
@@ -1214,8 +1287,8 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
       if (planes > 0) {
         __bf16* Ap = par ? *Sp : *Xp;
         __bf16* Bp = par ? *Xp : *Sp;
-        launch_square_planes(Ap, A, B, Bp, pl.total, tiles.get(), nl, offs.get(), cs, planes, 0,
-                             stopped, cur_b);
+        launch_square_planes(Ap, A, B, Bp, pl.total, tiles.get(), nl, offs.get(), cs, planes,
+                             pl.planes_db, 0, stopped, cur_b);
         launched = true;
       }
     }
@@ -1340,8 +1413,16 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       DBuf<__bf16> SP(planes > 0 ? (size_t)planes * pl.total : 0, s);
       __bf16* xp = XP.get();
       __bf16* sp = SP.get();
-      if (planes > 0) make_planes(xf, xp, pl.total, s, planes);
-      const double tol_lo = 1e-5 * N / 1024.0;
+      if (planes > 0) {
+        make_planes(xf, xp, pl.total, s, planes);
+        pl.planes_db = choose_planes_variant(pl, tiles.get(), xp, xf, sf, sp, offs.get(), s,
+                                             planes, o.tile_policy);
+        st.planes_db = pl.planes_db;
+      }
+      // The low-precision loop runs until its own rounding floor (the stagnation stop) unless
+      // the traces already agree to 1e-7 per 1024 orbitals, so that one FP64 McWeeny step
+      // usually finishes the job.
+      const double tol_lo = 1e-7 * N / 1024.0;
       if (o.launch_mode == 2)
         it_end = sp2_loop_graph<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
                                        o.branch_in, o.n_branch_in, true, it_end, st, s, &stop_kind,
@@ -1454,13 +1535,15 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       bin = o.branch_in;
       nbin = o.n_branch_in;
     }
-    const int cap = n_refine > 0 ? std::min(it_end + n_refine, 127) : max_iter;
-    if (o.launch_mode == 2)
-      it_end = sp2_loop_graph<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin,
-                                      false, it_end, st, s, &stop_kind, 0);
-    else
-      it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin, false,
-                                it_end, st, recs, s, &stop_kind, nullptr, 0, o.launch_mode == 1);
+    // Without a replayed sequence the steps alternate X^2 and 2X - X^2 (the first one chosen
+    // by the trace rule): each pair squares the distance of every eigenvalue from 0 or 1, as a
+    // McWeeny step does, and leaves the trace where the low-precision loop put it.  The trace
+    // rule itself would steer towards n_occ, which the rounded partitioned trace cannot reach
+    // with idempotent blocks, and cycles.
+    const int cap = std::min(it_end + (n_refine > 0 ? n_refine : 16), 127);
+    it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin, false,
+                              it_end, st, recs, s, &stop_kind, nullptr, 0, o.launch_mode == 1,
+                              nullptr, nullptr, bin == nullptr);
   } else {
     if (o.launch_mode == 2)
       it_end = sp2_loop_graph<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter,
