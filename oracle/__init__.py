@@ -16,6 +16,7 @@ Modules
   exact        dense diagonalisation: D = occupied eigenprojector
   equivalence  Eq. 3-6: whole-matrix masked polynomial vs subgraph polynomials
   adjoint      reverse-mode derivative of Tr[D V] through the SP2 recursion
+  foe          finite-temperature Chebyshev Fermi-operator expansion per subgraph (Eq. 7)
   metrics      error measures of Fig. 2 (Frobenius per site, band energy)
 
 Parity pins: every function is checked in tests/ against closed forms, brute force,
