@@ -251,6 +251,58 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
 gb_status gb_density_vjp(const gb_tape_t* tape, const gb_ell* G_D, gb_ell* G_H, void* stream);
 void gb_tape_destroy(gb_tape_t* tape);
 
+/*
+ * Finite-temperature density matrix by the Chebyshev Fermi-operator expansion (Eq. 7, with
+ * the terms built by the recurrence of Eq. 5 and evaluated per subgraph as in Eq. 6):
+ *   D = [exp(beta (H - mu)) + 1]^-1 ~ sum_{n=0..order} c_n T_n(Ht),
+ *   Ht = (2H - (e_max + e_min) I)/(e_max - e_min),  T_0 = I, T_1 = Ht,
+ *   T_{n+1} = 2 Ht T_n - T_{n-1}  (one batched FP64 product per term over every subgraph),
+ * c_n by K-node Chebyshev-Gauss quadrature (gb_chebyshev_fermi).  Graph and partition as for
+ * gb_density (X2 graph at `threshold` + block cores of core_size unless a partition is given).
+ * With mu = NaN the chemical potential is chosen so that the summed core traces
+ * sum_n c_n(mu) t_n (t_n = sum over subgraphs of the core diagonal of T_n) equal n_occ
+ * (gb_foe_solve_mu); the recurrence then runs twice (traces, then the sum).
+ * D as for gb_density (caller-owned column-ELL, D->width >= max_sub).  Synchronises `stream`.
+ */
+typedef struct {
+  double beta;               /* inverse temperature (1 / energy unit of H), > 0               */
+  double mu;                 /* chemical potential, or NaN: solved for n_occ                   */
+  int32_t order;             /* highest Chebyshev degree M >= 1                                */
+  int32_t n_nodes;           /* quadrature nodes K for the coefficients; 0 = max(4(M+1), 1024) */
+  const gb_partition_t* partition; /* NULL: build X2(threshold) + BLOCK(core_size) inside      */
+  int32_t core_size;         /* used when partition == NULL; default 32                       */
+  double emin, emax;         /* spectral bounds; both 0 = Gershgorin                           */
+  int32_t tile_policy;       /* as in gb_sp2_opts (FP64 tile edge)                             */
+  int32_t tile_order;        /* as in gb_sp2_opts                                              */
+} gb_foe_opts;
+
+typedef struct {
+  double mu;                 /* the chemical potential used                                    */
+  double trace;              /* sum_n c_n t_n (the summed core traces of the expansion)       */
+  double coef_tail;          /* |c_order| + |c_order-1| (size of the last terms kept)          */
+  double emin, emax;
+  int32_t n_sub, max_sub, passes;
+  float ms_bounds, ms_graph, ms_part, ms_gather, ms_terms, ms_scatter, ms_total;
+  float ms_product;          /* summed device time of the product launches                    */
+  int32_t n_product;         /* number of product launches                                     */
+  double product_flops;      /* algorithmic flops of one product launch: sum_s 2 n_s^3        */
+} gb_foe_stats;
+
+gb_status gb_foe_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_foe_opts* opts,
+                         gb_ell* D, gb_foe_stats* stats, void* stream);
+
+/* Host: the coefficients c_0 .. c_order of the Fermi function on [e_min, e_max] (mapped to
+ * [-1, 1]) by K-node Chebyshev-Gauss quadrature, theta_k = pi (k + 1/2) / K:
+ *   c_n = (2 - delta_n0) / K sum_k f(e(cos theta_k)) cos(n theta_k),
+ *   e(x) = (e_max + e_min)/2 + x (e_max - e_min)/2,  f(e) = 1 / (1 + exp(beta (e - mu))).
+ * n_nodes = 0 takes max(4 (order + 1), 1024).  coef: host array of order + 1 doubles. */
+gb_status gb_chebyshev_fermi(double emin, double emax, double beta, double mu, int32_t order,
+                             int32_t n_nodes, double* coef);
+/* Host: mu in [e_min, e_max] with sum_n c_n(mu) traces[n] = n_occ (bisection to the last
+ * representable bracket); GB_EINVAL if n_occ is outside the range the traces allow. */
+gb_status gb_foe_solve_mu(const double* traces, int32_t order, double emin, double emax,
+                          double beta, double n_occ, int32_t n_nodes, double* mu);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,6 +52,26 @@ class GbSp2Stats(ctypes.Structure):
 
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
+class GbFoeOpts(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_double), ("mu", ctypes.c_double),
+                ("order", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
+                ("partition", ctypes.c_void_p), ("core_size", ctypes.c_int32),
+                ("emin", ctypes.c_double), ("emax", ctypes.c_double),
+                ("tile_policy", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
+
+
+class GbFoeStats(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("trace", ctypes.c_double),
+                ("coef_tail", ctypes.c_double), ("emin", ctypes.c_double),
+                ("emax", ctypes.c_double), ("n_sub", ctypes.c_int32),
+                ("max_sub", ctypes.c_int32), ("passes", ctypes.c_int32),
+                ("ms_bounds", ctypes.c_float), ("ms_graph", ctypes.c_float),
+                ("ms_part", ctypes.c_float), ("ms_gather", ctypes.c_float),
+                ("ms_terms", ctypes.c_float), ("ms_scatter", ctypes.c_float),
+                ("ms_total", ctypes.c_float), ("ms_product", ctypes.c_float),
+                ("n_product", ctypes.c_int32), ("product_flops", ctypes.c_double)]
+
+
 # gb_alloc_fn / gb_free_fn
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -80,6 +100,14 @@ SIGNATURES = {
                                     _P(GbEll), _P(GbSp2Stats), _vp]),
     "gb_density_vjp": (ctypes.c_int32, [_vp, _P(GbEll), _P(GbEll), _vp]),
     "gb_tape_destroy": (None, [_vp]),
+    "gb_foe_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double,
+                                        _P(GbFoeOpts), _P(GbEll), _P(GbFoeStats), _vp]),
+    "gb_chebyshev_fermi": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                            _P(ctypes.c_double)]),
+    "gb_foe_solve_mu": (ctypes.c_int32, [_P(ctypes.c_double), ctypes.c_int32, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int32, _P(ctypes.c_double)]),
 }
 
 _lib = None

@@ -277,6 +277,58 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     return D_col, D_val, out
 
 
+def chebyshev_fermi(emin, emax, beta, mu, order, n_nodes=0):
+    """Host: Chebyshev coefficients c_0 .. c_order of the Fermi function on [emin, emax]."""
+    c = (ctypes.c_double * (int(order) + 1))()
+    _check(_lib().gb_chebyshev_fermi(float(emin), float(emax), float(beta), float(mu),
+                                     int(order), int(n_nodes), c))
+    return list(c)
+
+
+def foe_solve_mu(traces, emin, emax, beta, n_occ, n_nodes=0):
+    """Host: mu with sum_n c_n(mu) traces[n] = n_occ."""
+    t = (ctypes.c_double * len(traces))(*[float(x) for x in traces])
+    mu = ctypes.c_double()
+    _check(_lib().gb_foe_solve_mu(t, len(traces) - 1, float(emin), float(emax), float(beta),
+                                  float(n_occ), int(n_nodes), ctypes.byref(mu)))
+    return mu.value
+
+
+def foe_density(H_col, H_val, n_occ, threshold, beta, order, mu=None, partition=None,
+                core_size=32, n_nodes=0, emin=None, emax=None, D=None, tile_policy="auto",
+                tile_order="xcd"):
+    """Finite-temperature density matrix by the partitioned Chebyshev expansion of the Fermi
+    function (mu None: solved so that the summed core traces equal n_occ).  Returns
+    (D_col, D_val, stats) with D column-ELL as in :func:`density`."""
+    H = _ell(H_col, H_val)
+    part = partition
+    if part is None:
+        part = globals()["partition"](build_graph(H_col, H_val, threshold), core_size)
+    n = H.n
+    if D is None:
+        D_col = torch.empty((n, part.max_sub), dtype=torch.int32, device="cuda")
+        D_val = torch.empty((n, part.max_sub), dtype=torch.float64, device="cuda")
+    else:
+        D_col, D_val = D
+    De = _ell(D_col, D_val)
+    o = L.GbFoeOpts()
+    o.beta = float(beta)
+    o.mu = float("nan") if mu is None else float(mu)
+    o.order = int(order)
+    o.n_nodes = int(n_nodes)
+    o.partition = part.handle
+    o.core_size = int(core_size)
+    if emin is not None and emax is not None:
+        o.emin, o.emax = float(emin), float(emax)
+    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2}.get(tile_policy, tile_policy)
+    o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
+    st = L.GbFoeStats()
+    _check(_lib().gb_foe_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),
+                                 ctypes.byref(De), ctypes.byref(st), _stream()))
+    out = {f: getattr(st, f) for f, _ in L.GbFoeStats._fields_}
+    return D_col, D_val, out
+
+
 class DensityFn(torch.autograd.Function):
     """D_val = DensityFn.apply(H_val, H_col, n_occ, threshold, partition, core_size):
     the partitioned SP2 density matrix (column-ELL values; the row indices are in

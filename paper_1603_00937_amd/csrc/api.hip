@@ -117,6 +117,69 @@ void check_tau(double t, const char* name) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+struct EvPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  EvPair() {
+    GB_HIP(hipEventCreate(&a));
+    GB_HIP(hipEventCreate(&b));
+  }
+  ~EvPair() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+  EvPair(const EvPair&) = delete;
+  EvPair& operator=(const EvPair&) = delete;
+  float ms() const {
+    float t = 0.f;
+    GB_HIP(hipEventElapsedTime(&t, a, b));
+    return t;
+  }
+};
+
+// The front end shared by the expansions: spectral bounds (given or Gershgorin), the X0 values
+// on H's pattern, and (unless a partition is given) the X2 graph at `threshold` cut into block
+// cores of core_size.
+struct Front {
+  double emin = 0, emax = 0;
+  DBuf<double> x0;
+  gb_partition_s own;
+  const Part* P = nullptr;
+  float ms_bounds = 0, ms_graph = 0, ms_part = 0;
+};
+
+void prepare_front(const gb_ell& H, double threshold, double emin_in, double emax_in,
+                   const gb_partition_t* part, int core_size, hipStream_t s, Front& f) {
+  const bool given_bounds = !(emin_in == 0.0 && emax_in == 0.0);
+  if (given_bounds && !(emax_in > emin_in)) fail(GB_EINVAL, "need emax > emin");
+  if (part && part->part.n != H.n)
+    fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", part->part.n, H.n);
+  EvPair ev;
+  GB_HIP(hipEventRecord(ev.a, s));
+  f.emin = emin_in;
+  f.emax = emax_in;
+  if (!given_bounds) bounds(H, s, &f.emin, &f.emax);
+  f.x0 = DBuf<double>((size_t)H.n * H.width, s);
+  x0_ell(H, f.emin, f.emax, f.x0.get(), s);
+  GB_HIP(hipEventRecord(ev.b, s));
+  GB_HIP(hipStreamSynchronize(s));
+  f.ms_bounds = ev.ms();
+  f.P = part ? &part->part : nullptr;
+  if (!f.P) {
+    GB_HIP(hipEventRecord(ev.a, s));
+    Csr g;
+    graph_x2(H, f.x0.get(), threshold, g, s);
+    GB_HIP(hipEventRecord(ev.b, s));
+    GB_HIP(hipStreamSynchronize(s));
+    f.ms_graph = ev.ms();
+    GB_HIP(hipEventRecord(ev.a, s));
+    partition_block(g, core_size, f.own.part, s, GB_PART_BLOCK);
+    GB_HIP(hipEventRecord(ev.b, s));
+    GB_HIP(hipStreamSynchronize(s));
+    f.ms_part = ev.ms();
+    f.P = &f.own.part;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -322,52 +385,18 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
     if (o.keep_tape && o.launch_mode == 2)
       fail(GB_EUNSUPPORTED, "keep_tape needs launch_mode 0 or 1");
-    const bool given_bounds = !(o.emin == 0.0 && o.emax == 0.0);
-    if (given_bounds && !(o.emax > o.emin)) fail(GB_EINVAL, "need emax > emin");
-    if (o.partition && o.partition->part.n != H->n)
-      fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", o.partition->part.n, H->n);
     const int core_size = o.core_size > 0 ? o.core_size : 32;
-
     hipStream_t s = as_stream(stream);
-    hipEvent_t e0, e1;
-    GB_HIP(hipEventCreate(&e0));
-    GB_HIP(hipEventCreate(&e1));
-    struct EvGuard {
-      hipEvent_t a, b;
-      ~EvGuard() {
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-      }
-    } eg{e0, e1};
-    GB_HIP(hipEventRecord(e0, s));
-    double emin = o.emin, emax = o.emax;
-    if (!given_bounds) bounds(*H, s, &emin, &emax);
-    DBuf<double> x0((size_t)H->n * H->width, s);
-    x0_ell(*H, emin, emax, x0.get(), s);
-    GB_HIP(hipEventRecord(e1, s));
-    GB_HIP(hipStreamSynchronize(s));
-    GB_HIP(hipEventElapsedTime(&st.ms_bounds, e0, e1));
+    Front f;
+    prepare_front(*H, threshold, o.emin, o.emax, o.partition, core_size, s, f);
+    const double emin = f.emin, emax = f.emax;
     st.emin = emin;
     st.emax = emax;
-    float ms_front = st.ms_bounds;
-
-    gb_partition_s own;
-    const Part* P = o.partition ? &o.partition->part : nullptr;
-    if (!P) {
-      GB_HIP(hipEventRecord(e0, s));
-      Csr g;
-      graph_x2(*H, x0.get(), threshold, g, s);
-      GB_HIP(hipEventRecord(e1, s));
-      GB_HIP(hipStreamSynchronize(s));
-      GB_HIP(hipEventElapsedTime(&st.ms_graph, e0, e1));
-      GB_HIP(hipEventRecord(e0, s));
-      partition_block(g, core_size, own.part, s, GB_PART_BLOCK);
-      GB_HIP(hipEventRecord(e1, s));
-      GB_HIP(hipStreamSynchronize(s));
-      GB_HIP(hipEventElapsedTime(&st.ms_part, e0, e1));
-      ms_front += st.ms_graph + st.ms_part;
-      P = &own.part;
-    }
+    st.ms_bounds = f.ms_bounds;
+    st.ms_graph = f.ms_graph;
+    st.ms_part = f.ms_part;
+    const float ms_front = f.ms_bounds + f.ms_graph + f.ms_part;
+    const Part* P = f.P;
     st.n_sub = P->n_sub;
     st.max_sub = P->max_sub;
     if (D->width < P->max_sub)
@@ -375,7 +404,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
            P->max_sub);
     TapeData* tape = nullptr;
     try {
-      density(*H, n_occ, o, *P, emin, emax, x0.get(), *D, st, s, o.keep_tape ? &tape : nullptr);
+      density(*H, n_occ, o, *P, emin, emax, f.x0.get(), *D, st, s, o.keep_tape ? &tape : nullptr);
     } catch (...) {
       tape_destroy(tape);
       throw;
@@ -407,6 +436,70 @@ void gb_tape_destroy(gb_tape_t* tape) {
   if (!tape) return;
   tape_destroy(tape->data);
   delete tape;
+}
+
+gb_status gb_chebyshev_fermi(double emin, double emax, double beta, double mu, int32_t order,
+                             int32_t n_nodes, double* coef) {
+  return guarded([&] {
+    if (!coef) fail(GB_EINVAL, "coef is NULL");
+    if (!(emax > emin) || std::isinf(emax) || std::isinf(emin)) fail(GB_EINVAL, "need finite emax > emin");
+    if (!(beta > 0.0) || std::isinf(beta)) fail(GB_EINVAL, "beta = %g must be finite and > 0", beta);
+    if (std::isnan(mu)) fail(GB_EINVAL, "mu is NaN");
+    if (order < 1) fail(GB_EINVAL, "order = %d must be >= 1", order);
+    if (n_nodes < 0) fail(GB_EINVAL, "n_nodes must be >= 0");
+    chebyshev_fermi(emin, emax, beta, mu, order, n_nodes, coef);
+  });
+}
+
+gb_status gb_foe_solve_mu(const double* traces, int32_t order, double emin, double emax,
+                          double beta, double n_occ, int32_t n_nodes, double* mu) {
+  return guarded([&] {
+    if (!traces || !mu) fail(GB_EINVAL, "traces / mu is NULL");
+    if (!(emax > emin)) fail(GB_EINVAL, "need emax > emin");
+    if (!(beta > 0.0) || std::isinf(beta)) fail(GB_EINVAL, "beta = %g must be finite and > 0", beta);
+    if (order < 1) fail(GB_EINVAL, "order = %d must be >= 1", order);
+    if (n_nodes < 0) fail(GB_EINVAL, "n_nodes must be >= 0");
+    *mu = foe_solve_mu(traces, order, emin, emax, beta, n_occ, n_nodes);
+  });
+}
+
+gb_status gb_foe_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_foe_opts* opts,
+                         gb_ell* D, gb_foe_stats* stats, void* stream) {
+  gb_foe_stats local{};
+  gb_foe_stats& st = stats ? *stats : local;
+  return guarded([&] {
+    std::memset(&st, 0, sizeof(st));
+    if (!opts) fail(GB_EINVAL, "opts is NULL (beta and order are required)");
+    const gb_foe_opts o = *opts;
+    check_ell(H, "H");
+    check_ell(D, "D");
+    if (D->n != H->n) fail(GB_ESHAPE, "D->n = %d differs from H->n = %d", D->n, H->n);
+    check_tau(threshold, "threshold");
+    if (!(o.beta > 0.0) || std::isinf(o.beta)) fail(GB_EINVAL, "beta = %g must be finite and > 0", o.beta);
+    if (o.order < 1) fail(GB_EINVAL, "order = %d must be >= 1", o.order);
+    if (o.n_nodes < 0) fail(GB_EINVAL, "n_nodes must be >= 0");
+    if (std::isnan(o.mu) && (n_occ < 0 || n_occ > H->n))
+      fail(GB_EINVAL, "n_occ = %d outside [0, %d]", n_occ, H->n);
+    if (std::isinf(o.mu)) fail(GB_EINVAL, "mu must be finite (or NaN to solve for it)");
+    if (o.tile_policy < 0 || o.tile_policy > 2) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
+    if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
+    const int core_size = o.core_size > 0 ? o.core_size : 32;
+    hipStream_t s = as_stream(stream);
+    Front f;
+    prepare_front(*H, threshold, o.emin, o.emax, o.partition, core_size, s, f);
+    st.emin = f.emin;
+    st.emax = f.emax;
+    st.ms_bounds = f.ms_bounds;
+    st.ms_graph = f.ms_graph;
+    st.ms_part = f.ms_part;
+    st.n_sub = f.P->n_sub;
+    st.max_sub = f.P->max_sub;
+    if (D->width < f.P->max_sub)
+      fail(GB_ESHAPE, "D->width = %d is smaller than the largest subgraph (%d)", D->width,
+           f.P->max_sub);
+    foe(*H, n_occ, o, *f.P, f.emin, f.emax, *D, st, s);
+    st.ms_total += f.ms_bounds + f.ms_graph + f.ms_part;
+  });
 }
 
 }  // extern "C"

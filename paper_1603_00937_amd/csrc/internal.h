@@ -107,6 +107,14 @@ void tape_dims(const TapeData* t, int* n, int* max_sub);
 void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H_pattern, double* G_H,
                  hipStream_t s);
 
+// ---- finite-temperature expansion (sp2.hip) ----
+void chebyshev_fermi(double emin, double emax, double beta, double mu, int order, int n_nodes,
+                     double* c);
+double foe_solve_mu(const double* traces, int order, double emin, double emax, double beta,
+                    double n_occ, int n_nodes);
+void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, double emin,
+         double emax, gb_ell& D, gb_foe_stats& st, hipStream_t s);
+
 }  // namespace gbi
 
 // graph / partition handles behind the opaque ABI types

@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -136,6 +137,7 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
 //   MODE 0: out = A*B          MODE 1: out = alpha*(A*B) + beta*E   (E symmetric)
 //   MODE 3: out = A*B for a general (non-symmetric) product with B symmetric: every tile
 //           (bi, bj) is listed and nothing is mirrored (the adjoint's Gbar*X)
+//   MODE 4: as MODE 1, and dacc += cn * out (the Chebyshev recurrence with the running sum)
 // In MODE 0 (A = B = X) the SP2 update is fused into the epilogue: with the branch
 // 2X - X^2 selected (lin, or *lin_flag on the device-driven loop) the kernel writes 2X - X^2,
 // else X^2.  X is symmetric, so the mirrored entry takes the same value.
@@ -145,7 +147,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
                                                    T alpha, T beta, const int4* __restrict__ tiles,
                                                    const int64_t* __restrict__ offs,
                                                    const int32_t* __restrict__ stopped,
-                                                   int lin, const int32_t* __restrict__ lin_flag) {
+                                                   int lin, const int32_t* __restrict__ lin_flag,
+                                                   T* __restrict__ dacc, T cn) {
   if (stopped && *stopped) return;  // device-driven loop: the expansion already stopped
   using M = Mfma<T>;
   using acc_t = typename M::acc_t;
@@ -256,11 +259,16 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
         const int grow = bi * BT + wr * WM + m * 16 + M::row(lane, r);
         const int gcol = bj * BT + wc * WM + n * 16 + r16;
         if (grow < np && gcol < np) {
+          const int64_t q1 = (int64_t)grow * np + gcol, q2 = (int64_t)gcol * np + grow;
           T v = acc[m][n][r];
-          if (MODE == 1) v = alpha * v + beta * e[(int64_t)grow * np + gcol];
-          if (do_lin) v = (T)2 * xa[(int64_t)grow * np + gcol] - v;
-          o[(int64_t)grow * np + gcol] = v;
-          if (mirror) o[(int64_t)gcol * np + grow] = v;
+          if (MODE == 1 || MODE == 4) v = alpha * v + beta * e[q1];
+          if (do_lin) v = (T)2 * xa[q1] - v;
+          o[q1] = v;
+          if (MODE == 4) dacc[off + q1] += cn * v;
+          if (mirror) {
+            o[q2] = v;
+            if (MODE == 4) dacc[off + q2] += cn * v;
+          }
         }
       }
 }
@@ -950,12 +958,12 @@ void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const
                    const int32_t* lin_flag = nullptr) {
   if (n128 > 0) {
     hipLaunchKernelGGL((k_symm_mm<T, 0, 128>), dim3(n128), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                       tiles, offs, stopped, lin, lin_flag);
+                       tiles, offs, stopped, lin, lin_flag, (T*)nullptr, (T)0);
     GB_LAUNCH_CHECK();
   }
   if (n64 > 0) {
     hipLaunchKernelGGL((k_symm_mm<T, 0, 64>), dim3(n64), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                       tiles + n128, offs, stopped, lin, lin_flag);
+                       tiles + n128, offs, stopped, lin, lin_flag, (T*)nullptr, (T)0);
     GB_LAUNCH_CHECK();
   }
 }
@@ -1016,6 +1024,8 @@ struct Timer {
     GB_HIP(hipEventCreate(&a));
     GB_HIP(hipEventCreate(&b));
   }
+  Timer(const Timer&) = delete;
+  Timer& operator=(const Timer&) = delete;
   ~Timer() {
     if (a) (void)hipEventDestroy(a);
     if (b) (void)hipEventDestroy(b);
@@ -1515,10 +1525,12 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       launch_square<double>(xd, sd, tiles.get(), pl.l128, n64, offs.get(), s);
       if (pl.l128 > 0)
         hipLaunchKernelGGL((k_symm_mm<double, 1, 128>), dim3(pl.l128), dim3(kT), 0, s, sd, xd, sd,
-                           td, -2.0, 3.0, tiles.get(), offs.get(), nullptr, 0, nullptr);
+                           td, -2.0, 3.0, tiles.get(), offs.get(), nullptr, 0, nullptr,
+                           (double*)nullptr, 0.0);
       if (n64 > 0)
         hipLaunchKernelGGL((k_symm_mm<double, 1, 64>), dim3(n64), dim3(kT), 0, s, sd, xd, sd, td,
-                           -2.0, 3.0, tiles.get() + pl.l128, offs.get(), nullptr, 0, nullptr);
+                           -2.0, 3.0, tiles.get() + pl.l128, offs.get(), nullptr, 0, nullptr,
+                           (double*)nullptr, 0.0);
       GB_LAUNCH_CHECK();
       std::swap(xd, td);
       ++st.n_refine_done;
@@ -1630,7 +1642,8 @@ void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H, double* G_H, h
     for (int n = end - 1; n >= start; --n) {
       const double* X = xs[n - start];
       hipLaunchKernelGGL((k_symm_mm<double, 3>), dim3(ntf), dim3(kT), 0, s, G.get(), X, X,
-                         Pm.get(), 1.0, 0.0, t.tiles_full.get(), t.offs.get(), nullptr, 0, nullptr);
+                         Pm.get(), 1.0, 0.0, t.tiles_full.get(), t.offs.get(), nullptr, 0, nullptr,
+                         (double*)nullptr, 0.0);
       GB_LAUNCH_CHECK();
       const double c1 = t.branch[n] == 0 ? 1.0 : -1.0, c2 = t.branch[n] == 0 ? 0.0 : 2.0;
       hipLaunchKernelGGL(k_sym_combine, cgrid, dim3(256), 0, s, Pm.get(), G.get(), G2.get(), c1,
@@ -1665,6 +1678,246 @@ void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H, double* G_H, h
                      -1.0 / (t.emax - t.emin), G_H);
   GB_LAUNCH_CHECK();
   GB_HIP(hipStreamSynchronize(s));
+}
+
+
+// ---- finite-temperature Fermi-operator expansion (Eq. 7; terms by the recurrence of Eq. 5,
+// per subgraph as in Eq. 6) ----------------------------------------------------------------
+
+namespace {
+
+// Ht = (2h - (e_max + e_min) delta) / (e_max - e_min) on H's ELL pattern (0 on padding)
+__global__ void k_ht_ell(const int32_t* __restrict__ col, const double* __restrict__ val, int n,
+                         int w, double emin, double emax, double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= (int64_t)n * w) return;
+  const int i = (int)(p / w);
+  const int32_t j = col[p];
+  double v = 0.0;
+  if (j >= 0) v = (2.0 * val[p] - (j == i ? emax + emin : 0.0)) / (emax - emin);
+  out[p] = v;
+}
+
+// X[s] <- identity on the n_s x n_s part (the rest of the batch must already be zero)
+__global__ __launch_bounds__(kT) void k_set_identity(double* __restrict__ X,
+                                                     const int64_t* __restrict__ offs,
+                                                     const int32_t* __restrict__ npad,
+                                                     const int32_t* __restrict__ sub_ptr) {
+  const int s = blockIdx.x;
+  const int np = npad[s], n = sub_ptr[s + 1] - sub_ptr[s];
+  double* x = X + offs[s];
+  for (int j = threadIdx.x; j < n; j += kT) x[(int64_t)j * np + j] = 1.0;
+}
+
+__global__ void k_axpby(double* __restrict__ out, double a, const double* __restrict__ x, double b,
+                        const double* __restrict__ y, int64_t n) {
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t st = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = i0; i < n; i += st) out[i] = a * x[i] + b * y[i];
+}
+
+// the summed core diagonal (first partial of each subgraph) into *out
+__global__ __launch_bounds__(kT) void k_trace_total(const double* __restrict__ part, int n_sub,
+                                                    double* __restrict__ out) {
+  double t1, t2;
+  sum_partials(part, n_sub, &t1, &t2);
+  if (threadIdx.x == 0) *out = t1;
+}
+
+// T_next = 2 A T_cur - T_prev on every upper tile (A and T_cur commute, so the product is
+// symmetric), and with dacc: dacc += cn T_next
+void launch_cheb(const double* A, const double* Tc, const double* Tp, double* Tn, double* dacc,
+                 double cn, const Plan& pl, const int4* tiles, const int64_t* offs, hipStream_t s) {
+  const int n128 = pl.l128, n64 = (int)pl.launch.size() - pl.l128;
+  if (dacc) {
+    if (n128 > 0)
+      hipLaunchKernelGGL((k_symm_mm<double, 4, 128>), dim3(n128), dim3(kT), 0, s, A, Tc, Tp, Tn,
+                         2.0, -1.0, tiles, offs, nullptr, 0, nullptr, dacc, cn);
+    if (n64 > 0)
+      hipLaunchKernelGGL((k_symm_mm<double, 4, 64>), dim3(n64), dim3(kT), 0, s, A, Tc, Tp, Tn,
+                         2.0, -1.0, tiles + n128, offs, nullptr, 0, nullptr, dacc, cn);
+  } else {
+    if (n128 > 0)
+      hipLaunchKernelGGL((k_symm_mm<double, 1, 128>), dim3(n128), dim3(kT), 0, s, A, Tc, Tp, Tn,
+                         2.0, -1.0, tiles, offs, nullptr, 0, nullptr, (double*)nullptr, 0.0);
+    if (n64 > 0)
+      hipLaunchKernelGGL((k_symm_mm<double, 1, 64>), dim3(n64), dim3(kT), 0, s, A, Tc, Tp, Tn,
+                         2.0, -1.0, tiles + n128, offs, nullptr, 0, nullptr, (double*)nullptr,
+                         0.0);
+  }
+  GB_LAUNCH_CHECK();
+}
+
+int quad_nodes(int order, int n_nodes) { return n_nodes > 0 ? n_nodes : std::max(4 * (order + 1), 1024); }
+
+double fermi(double e, double beta, double mu) { return 1.0 / (1.0 + std::exp(beta * (e - mu))); }
+
+}  // namespace
+
+void chebyshev_fermi(double emin, double emax, double beta, double mu, int order, int n_nodes,
+                     double* c) {
+  const int K = quad_nodes(order, n_nodes);
+  const double mid = 0.5 * (emax + emin), half = 0.5 * (emax - emin);
+  std::vector<double> th(K), f(K);
+  for (int k = 0; k < K; ++k) {
+    th[k] = M_PI * (k + 0.5) / K;
+    f[k] = fermi(mid + half * std::cos(th[k]), beta, mu);
+  }
+  for (int n = 0; n <= order; ++n) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc += std::cos(n * th[k]) * f[k];
+    c[n] = acc * (2.0 / K) * (n == 0 ? 0.5 : 1.0);
+  }
+}
+
+// sum_n c_n(mu) t_n = sum_k f(e_k; mu) w_k with w_k = (2/K) sum_n' t_n cos(n theta_k) (the n = 0
+// term halved): the weights are formed once and each bisection step costs K exponentials.
+double foe_solve_mu(const double* traces, int order, double emin, double emax, double beta,
+                    double n_occ, int n_nodes) {
+  const int K = quad_nodes(order, n_nodes);
+  const double mid = 0.5 * (emax + emin), half = 0.5 * (emax - emin);
+  std::vector<double> e(K), w(K);
+  for (int k = 0; k < K; ++k) {
+    const double th = M_PI * (k + 0.5) / K;
+    e[k] = mid + half * std::cos(th);
+    double acc = 0.5 * traces[0];
+    for (int n = 1; n <= order; ++n) acc += std::cos(n * th) * traces[n];
+    w[k] = acc * (2.0 / K);
+  }
+  auto excess = [&](double mu) {
+    double t = 0.0;
+    for (int k = 0; k < K; ++k) t += fermi(e[k], beta, mu) * w[k];
+    return t - n_occ;
+  };
+  double lo = emin, hi = emax;
+  const double glo = excess(lo), ghi = excess(hi);
+  if (glo > 0.0 || ghi < 0.0)
+    fail(GB_EINVAL, "n_occ = %g is outside the occupations [%g, %g] reachable in [e_min, e_max]",
+         n_occ, glo + n_occ, ghi + n_occ);
+  for (int it = 0; it < 400; ++it) {
+    const double m = 0.5 * (lo + hi);
+    if (!(m > lo && m < hi)) break;
+    if (excess(m) < 0.0) lo = m;
+    else hi = m;
+  }
+  return 0.5 * (lo + hi);
+}
+
+void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, double emin,
+         double emax, gb_ell& D, gb_foe_stats& st, hipStream_t s) {
+  Timer t_all, t_stage;
+  GB_HIP(hipEventRecord(t_all.a, s));
+  const bool xcd = o.tile_order == 0;
+  Plan pl = make_plan(P, nullptr, xcd);
+  st.product_flops = pl.flops_alg;
+  DBuf<int64_t> offs(pl.n_sub, s);
+  DBuf<int32_t> npad(pl.n_sub, s);
+  GB_HIP(hipMemcpyAsync(offs.get(), pl.off.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
+  GB_HIP(hipMemcpyAsync(npad.get(), pl.npad.data(), pl.n_sub * 4, hipMemcpyHostToDevice, s));
+  DBuf<int4> tiles = upload_tiles(pl, s);
+  const int N = H.n;
+  const int M = o.order;
+
+  // gather Ht into the batch
+  GB_HIP(hipEventRecord(t_stage.a, s));
+  const int64_t slots = (int64_t)H.n * H.width;
+  DBuf<double> ht(slots, s);
+  hipLaunchKernelGGL(k_ht_ell, dim3(grid_for(slots, kT)), dim3(kT), 0, s, H.col, H.val, H.n,
+                     H.width, emin, emax, ht.get());
+  GB_LAUNCH_CHECK();
+  const size_t lds_g = (size_t)pl.max_npad * 8 + (size_t)P.max_sub * 4 + 64;
+  if (lds_g > 160 * 1024) fail(GB_EUNSUPPORTED, "subgraph of %d vertices too large", P.max_sub);
+  const dim3 ggrid(pl.n_sub, (pl.max_npad + kRows - 1) / kRows);
+  DBuf<double> A(pl.total, s), B0(pl.total, s), B1(pl.total, s), B2(pl.total, s), Dacc(pl.total, s);
+  hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, ht.get(), H.width,
+                     P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
+                     A.get());
+  GB_LAUNCH_CHECK();
+  GB_HIP(hipEventRecord(t_stage.b, s));
+  GB_HIP(hipStreamSynchronize(s));
+  st.ms_gather = elapsed(t_stage.a, t_stage.b);
+  gb_sp2_stats tune_st{};
+  choose_tiles<double>(P, pl, A.get(), B2.get(), tiles, offs.get(), s, o.tile_policy, 0, tune_st,
+                       xcd);
+
+  double t0 = 0;  // t_0 = sum of the core sizes
+  for (int q = 0; q < P.n_sub; ++q) t0 += P.h_core_ptr[q + 1] - P.h_core_ptr[q];
+  std::vector<double> traces(M + 1, 0.0);
+  DBuf<double> part(2 * (size_t)pl.n_sub, s), tdev(M + 1, s);
+  const int gfill = grid_for(pl.total, kT, 65536);
+  std::deque<Timer> marks;
+  auto record_trace = [&](const double* X, int n) {
+    hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, X, offs.get(),
+                       npad.get(), P.core_ptr.get(), part.get(), nullptr);
+    hipLaunchKernelGGL(k_trace_total, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub,
+                       tdev.get() + n);
+    GB_LAUNCH_CHECK();
+  };
+  // one pass of the recurrence; with c: the running sum in Dacc
+  auto pass = [&](const double* c) {
+    double* tp = B0.get();
+    double* tc = B1.get();
+    double* tn = B2.get();
+    hipLaunchKernelGGL(k_fill, dim3(gfill), dim3(kT), 0, s, tp, pl.total, 0.0);
+    GB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_set_identity, dim3(pl.n_sub), dim3(kT), 0, s, tp, offs.get(), npad.get(),
+                       P.sub_ptr.get());
+    GB_LAUNCH_CHECK();
+    GB_HIP(hipMemcpyAsync(tc, A.get(), pl.total * 8, hipMemcpyDeviceToDevice, s));
+    if (c) {
+      hipLaunchKernelGGL(k_axpby, dim3(gfill), dim3(kT), 0, s, Dacc.get(), c[0], tp, c[1], tc,
+                         pl.total);
+      GB_LAUNCH_CHECK();
+    }
+    record_trace(tc, 1);
+    for (int n = 1; n < M; ++n) {
+      marks.emplace_back();
+      GB_HIP(hipEventRecord(marks.back().a, s));
+      launch_cheb(A.get(), tc, tp, tn, c ? Dacc.get() : nullptr, c ? c[n + 1] : 0.0, pl,
+                  tiles.get(), offs.get(), s);
+      GB_HIP(hipEventRecord(marks.back().b, s));
+      record_trace(tn, n + 1);
+      double* r = tp;
+      tp = tc;
+      tc = tn;
+      tn = r;
+    }
+    GB_HIP(hipMemcpyAsync(traces.data() + 1, tdev.get() + 1, M * 8, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipStreamSynchronize(s));
+    traces[0] = t0;
+    ++st.passes;
+  };
+
+  GB_HIP(hipEventRecord(t_stage.a, s));
+  std::vector<double> c(M + 1);
+  double mu = o.mu;
+  if (std::isnan(mu)) {
+    pass(nullptr);
+    mu = foe_solve_mu(traces.data(), M, emin, emax, o.beta, (double)n_occ, o.n_nodes);
+  }
+  chebyshev_fermi(emin, emax, o.beta, mu, M, o.n_nodes, c.data());
+  pass(c.data());
+  GB_HIP(hipEventRecord(t_stage.b, s));
+  GB_HIP(hipStreamSynchronize(s));
+  st.ms_terms = elapsed(t_stage.a, t_stage.b);
+  for (auto& t : marks) st.ms_product += elapsed(t.a, t.b);
+  st.n_product = (int)marks.size();
+  st.mu = mu;
+  double tr = 0.0;
+  for (int n = 0; n <= M; ++n) tr += c[n] * traces[n];
+  st.trace = tr;
+  st.coef_tail = std::fabs(c[M]) + std::fabs(c[M - 1]);
+
+  GB_HIP(hipEventRecord(t_stage.a, s));
+  hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, Dacc.get(), offs.get(),
+                     npad.get(), P.sub_ptr.get(), P.sub_idx.get(), P.sub_pos.get(),
+                     P.col_sub.get(), P.col_loc.get(), D.width, D.col, D.val);
+  GB_LAUNCH_CHECK();
+  GB_HIP(hipEventRecord(t_stage.b, s));
+  GB_HIP(hipEventRecord(t_all.b, s));
+  GB_HIP(hipStreamSynchronize(s));
+  st.ms_scatter = elapsed(t_stage.a, t_stage.b);
+  st.ms_total += elapsed(t_all.a, t_all.b);
 }
 
 }  // namespace gbi

@@ -1,6 +1,8 @@
 """The C ABI on the CPU: the library loads, exports every declared symbol, and rejects bad
 arguments on the host with the documented codes before any device work."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -129,7 +131,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_1603_00937_amd import _lib as L
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
-    fields = {"gb_sp2_opts": L.GbSp2Opts, "gb_sp2_stats": L.GbSp2Stats, "gb_ell": L.GbEll}
+    fields = {"gb_sp2_opts": L.GbSp2Opts, "gb_sp2_stats": L.GbSp2Stats, "gb_ell": L.GbEll,
+              "gb_foe_opts": L.GbFoeOpts, "gb_foe_stats": L.GbFoeStats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
     for cname, py in fields.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -146,3 +149,49 @@ def test_struct_layout_matches_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert int(got[f"{cname}.{f[0]}"]) == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_chebyshev_coefficients_match_oracle(lib):
+    """Host entry point (no GPU needed) against the oracle's quadrature."""
+    from oracle.foe import fermi_coefficients
+    import paper_1603_00937_amd as gb
+    for emin, emax, beta, mu, order, nodes in [(-4.4, 4.3, 10.0, 0.1, 150, 0),
+                                               (-1.0, 2.0, 3.0, -0.5, 20, 64),
+                                               (-9.5, 9.7, 40.0, 0.3, 600, 0)]:
+        got = np.array(gb.chebyshev_fermi(emin, emax, beta, mu, order, nodes))
+        ref = fermi_coefficients(emin, emax, beta, mu, order, nodes or None)
+        assert np.abs(got - ref).max() < 1e-14
+
+
+def test_solve_mu_matches_oracle(lib):
+    from oracle.foe import foe_partitioned, solve_mu
+    import paper_1603_00937_amd as gb
+    from synth import make_model
+    m = make_model("small256")
+    beta, order = 6.0, 60
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, 16, beta, order, n_occ=m["n_occ"])
+    mu = gb.foe_solve_mu(info["traces"], info["emin"], info["emax"], beta, m["n_occ"])
+    assert abs(mu - info["mu"]) < 1e-11
+    # an occupation no mu in [emin, emax] reaches is rejected
+    with pytest.raises(gb.GbError):
+        gb.foe_solve_mu(info["traces"], info["emin"], info["emax"], beta, m["N"] + 5)
+
+
+def test_foe_rejects_bad_arguments(lib):
+    from paper_1603_00937_amd._lib import GbEll, GbFoeOpts, GB_EINVAL
+    bogus = 0x1000
+    H = GbEll(8, 3, bogus, bogus)
+    D = GbEll(8, 8, bogus, bogus)
+    o = GbFoeOpts()
+    o.beta, o.order, o.mu = 5.0, 10, 0.0
+    assert lib.gb_foe_density(ctypes.byref(H), 4, 1e-5, None, ctypes.byref(D), None, None) == GB_EINVAL
+    o.beta = -1.0
+    assert lib.gb_foe_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None, None) == GB_EINVAL
+    o.beta, o.order = 5.0, 0
+    assert lib.gb_foe_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None, None) == GB_EINVAL
+    o.order, o.mu = 10, float("nan")
+    assert lib.gb_foe_density(ctypes.byref(H), 40, 1e-5, ctypes.byref(o), ctypes.byref(D), None, None) == GB_EINVAL
+    c = (ctypes.c_double * 4)()
+    assert lib.gb_chebyshev_fermi(1.0, 0.0, 1.0, 0.0, 3, 0, c) == GB_EINVAL
+    assert lib.gb_chebyshev_fermi(0.0, 1.0, 1.0, 0.0, 0, 0, c) == GB_EINVAL
+    assert lib.gb_chebyshev_fermi(0.0, 1.0, 1.0, 0.0, 3, 0, None) == GB_EINVAL

@@ -1,0 +1,131 @@
+"""Finite-temperature Chebyshev expansion on the GPU against the oracle (FP64): D pattern
+bit-exact, values within 1e-10 (given mu) / 1e-9 (solved mu), the solved mu itself, the
+degenerate first-order expansion, both tile edges, and sampled subgraphs of the N = 18000
+system at the size the benchmark runs."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1603_00937_amd as gb
+    return gb
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _compare(D_col, D_val, cols, N):
+    from oracle.foe import columns_to_ell
+    dc = D_col.cpu().numpy()
+    dv = D_val.cpu().numpy()
+    oc, ov = columns_to_ell(cols, N, dc.shape[1])
+    assert np.array_equal(dc, oc)
+    return float(np.abs(dv - ov).max())
+
+
+@pytest.mark.parametrize("name,core,beta,order,mu", [
+    ("small256", 16, 6.0, 60, 0.0),
+    ("small256", 37, 2.0, 25, -0.4),
+    ("tiny48", 5, 4.0, 30, 0.2),
+])
+def test_given_mu_matches_oracle(gb, model_cache, name, core, beta, order, mu):
+    from oracle.foe import foe_partitioned
+    m = model_cache(name)
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, core, beta, order, mu=mu)
+    D_col, D_val, st = gb.foe_density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      beta, order, mu=mu, core_size=core)
+    err = _compare(D_col, D_val, cols, m["N"])
+    print(f"{name} core={core} beta={beta} M={order}: err={err:.3e} passes={st['passes']}")
+    assert err <= 1e-10
+    assert st["passes"] == 1 and st["mu"] == mu
+    assert st["n_product"] == order - 1
+
+
+def test_solved_mu_matches_oracle(gb, model_cache):
+    from oracle.foe import foe_partitioned
+    m = model_cache("small256")
+    beta, order = 6.0, 60
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, 16, beta, order, n_occ=m["n_occ"])
+    D_col, D_val, st = gb.foe_density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      beta, order, core_size=16)
+    err = _compare(D_col, D_val, cols, m["N"])
+    print(f"solved mu={st['mu']!r} oracle={info['mu']!r} err={err:.3e} trace={st['trace']!r}")
+    assert abs(st["mu"] - info["mu"]) < 1e-10
+    assert st["passes"] == 2
+    assert abs(st["trace"] - m["n_occ"]) < 1e-8
+    assert err <= 1e-9
+
+
+def test_n1024_solved_mu(gb, model_cache):
+    from oracle.foe import foe_partitioned
+    m = model_cache("n1024")
+    beta, order = 8.0, 40
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, 16, beta, order, n_occ=m["n_occ"])
+    D_col, D_val, st = gb.foe_density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      beta, order, core_size=16)
+    err = _compare(D_col, D_val, cols, m["N"])
+    print(f"n1024 mu={st['mu']!r} err={err:.3e}")
+    assert abs(st["mu"] - info["mu"]) < 1e-10
+    assert err <= 1e-9
+
+
+def test_first_order_expansion(gb, model_cache):
+    """M = 1: D = c_0 I + c_1 Ht, no product launched."""
+    from oracle.foe import foe_partitioned
+    m = model_cache("small256")
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, 16, 1.0, 1, mu=0.3)
+    D_col, D_val, st = gb.foe_density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      1.0, 1, mu=0.3, core_size=16)
+    assert st["n_product"] == 0
+    assert _compare(D_col, D_val, cols, m["N"]) <= 1e-14
+
+
+def test_tile_edges_agree(gb, model_cache):
+    m = model_cache("n1024")
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+    out = {}
+    for pol in ("128", "64"):
+        D_col, D_val, st = gb.foe_density(Hc, Hv, m["n_occ"], 1e-5, 8.0, 30, mu=0.0,
+                                          core_size=16, tile_policy=pol)
+        out[pol] = (D_col.cpu().numpy(), D_val.cpu().numpy())
+    assert np.array_equal(out["128"][0], out["64"][0])
+    assert np.abs(out["128"][1] - out["64"][1]).max() <= 1e-12
+
+
+def test_n18000_sampled_subgraphs(gb, model_cache):
+    """The benchmark's size: every subgraph on the GPU, three of them (largest, smallest and
+    one in the middle) recomputed by the oracle."""
+    import torch
+    from oracle.foe import foe_partitioned
+    m = model_cache("n18000")
+    beta, order, mu, core = 10.0, 60, 0.0, 32
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+    g = gb.build_graph(Hc, Hv, 1e-5)
+    p = gb.partition(g, core)
+    D_col, D_val, st = gb.foe_density(Hc, Hv, m["n_occ"], 1e-5, beta, order, mu=mu,
+                                      partition=p)
+    cp, sp, si = [t.cpu().numpy() for t in p.arrays()]
+    sizes = np.diff(sp)
+    picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), len(sizes) // 2})
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, core, beta, order, mu=mu,
+                                 subgraphs=picks)
+    assert np.array_equal(info["sub_ptr"], sp) and np.array_equal(info["sub_idx"], si)
+    dc = D_col.cpu().numpy()
+    dv = D_val.cpu().numpy()
+    err = 0.0
+    for i, (rows, vals) in cols.items():
+        o = np.argsort(rows, kind="stable")
+        assert np.array_equal(dc[i, :len(rows)], rows[o])
+        err = max(err, float(np.abs(dv[i, :len(rows)] - vals[o]).max()))
+    ms = st["ms_product"] / max(st["n_product"], 1)
+    print(f"n18000 FOE M={order}: err={err:.3e} product {ms:.2f} ms "
+          f"({st['product_flops'] / ms / 1e9:.1f} TF algorithmic) total {st['ms_total']:.0f} ms")
+    assert err <= 1e-10
+    torch.cuda.synchronize()
