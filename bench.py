@@ -161,6 +161,58 @@ def md_run(args):
     print(json.dumps({"md_steps": steps, "workload": args.workload}), flush=True)
 
 
+def foe_run(args):
+    """Finite-temperature Chebyshev expansion (the Fermi function of Eq. 7) on the workload's
+    partition: one JSON line with orbitals/s of the whole path and the roofline of the batched
+    product (one launch per Chebyshev term)."""
+    import torch
+    import paper_1603_00937_amd as gb
+    from synth import make_model
+    cfg = WORKLOADS[args.workload]
+    m = make_model(args.workload)
+    N = m["N"]
+    dev = torch.device("cuda:0")
+    Hc = torch.from_numpy(m["H_col"]).to(dev)
+    Hv = torch.from_numpy(m["H_val"]).to(dev)
+    mu = None if args.mu is None else float(args.mu)
+
+    def step():
+        g = gb.build_graph(Hc, Hv, cfg["tau"])
+        p = gb.partition(g, cfg["core"])
+        return gb.foe_density(Hc, Hv, m["n_occ"], cfg["tau"], args.beta, args.order, mu=mu,
+                              partition=p)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prod_ms, prod_n = 0.0, 0
+    for _ in range(args.steps):
+        _, _, st = step()
+        prod_ms += st["ms_product"]
+        prod_n += st["n_product"]
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    avg = prod_ms / prod_n / 1e3 if prod_n else None
+    ach = st["product_flops"] / avg / 1e12 if avg else None
+    print(json.dumps({
+        "metric": "orbitals/s of the finite-temperature D (Chebyshev Fermi expansion)",
+        "value": N / dt, "unit": "orbitals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: N={N}, tau={cfg['tau']}, cores of {cfg['core']}",
+                   "beta": args.beta, "order": args.order,
+                   "mu": "solved for n_occ" if mu is None else mu, "passes": st["passes"],
+                   "n_sub": st["n_sub"], "max_sub": st["max_sub"]},
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["fp64"],
+                     "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["fp64"] if ach else None,
+                     "traffic": None, "kernel": "k_symm_mm MODE 4 (2 Ht T_n - T_{n-1}, D += c T)",
+                     "flops_per_launch_alg": st["product_flops"],
+                     "avg_launch_ms": avg * 1e3 if avg else None},
+        "result": {"mu": st["mu"], "trace": st["trace"], "coef_tail": st["coef_tail"]},
+        "stage_ms": {k[3:]: st[k] for k in st if k.startswith("ms_")},
+    }), flush=True)
+
+
 def copy_calibration(nbytes=4 << 30, reps=5):
     """A plain device copy of known size (the scale for rocprof FETCH_SIZE / WRITE_SIZE)."""
     import torch
@@ -237,6 +289,11 @@ def main():
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run the adaptive-graph displacement loop instead of the benchmark")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
+    ap.add_argument("--foe", action="store_true",
+                    help="time the finite-temperature Chebyshev expansion instead of SP2")
+    ap.add_argument("--beta", type=float, default=5.0, help="FOE inverse temperature (1/eV)")
+    ap.add_argument("--order", type=int, default=300, help="FOE Chebyshev order")
+    ap.add_argument("--mu", default=None, help="FOE chemical potential (default: solved)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 GPU measurement reported beside a mixed-precision run")
@@ -253,6 +310,9 @@ def main():
         return
     if args.md_steps:
         md_run(args)
+        return
+    if args.foe:
+        foe_run(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
