@@ -279,7 +279,7 @@ def main():
                     choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
     ap.add_argument("--launch-mode", default="batched", choices=["batched", "per_subgraph", "graph"])
     ap.add_argument("--copy-calibration", action="store_true")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "db", "sb"])
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "db", "sb", "pipe"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)

@@ -190,7 +190,8 @@ typedef struct {
   int32_t tile_policy;       /* FP64 / FP32 squares: tile edge autotuned per 256-wide size     *
                               * bucket (0, timed once per process), 1 = 128, 2 = 64;          *
                               * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
-                              * buffered LDS, 2 = single-buffered                             */
+                              * buffered LDS, 2 = single-buffered, 3 = pipelined (three       *
+                              * planes; others as 2).  FP64 / FP32 treat 3 as 0.              */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
 } gb_sp2_opts;
 

@@ -381,7 +381,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
       fail(GB_EUNSUPPORTED, "keep_tape needs precision GB_FP64");
     if (o.tape_stride < 0) fail(GB_EINVAL, "tape_stride must be >= 0");
     if (o.launch_mode < 0 || o.launch_mode > 2) fail(GB_EINVAL, "unknown launch_mode %d", o.launch_mode);
-    if (o.tile_policy < 0 || o.tile_policy > 2) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
+    if (o.tile_policy < 0 || o.tile_policy > 3) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
     if (o.keep_tape && o.launch_mode == 2)
       fail(GB_EUNSUPPORTED, "keep_tape needs launch_mode 0 or 1");

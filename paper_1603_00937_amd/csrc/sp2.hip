@@ -296,6 +296,44 @@ __device__ __forceinline__ void split_planes(float x, __bf16* out) {
   }
 }
 
+// Epilogue shared by the split-bf16 kernels: the new iterate v = big + small (or 2x - v), its
+// planes, each written at (row, col) and, off the diagonal blocks, at (col, row).
+template <int NP>
+__device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4v (&small)[4][4],
+                                                float* __restrict__ S, __bf16* __restrict__ Sp,
+                                                const float* __restrict__ X, int64_t pstride,
+                                                int64_t off, int np, int bi, int bj, int wr,
+                                                int wc, int lane, bool do_lin) {
+  float* o = S + off;
+  const float* xa = X + off;
+  const int r16 = lane & 15;
+  const bool mirror = bi != bj || wr < wc;
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int grow = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4) + r;
+        const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
+        if (grow < np && gcol < np) {
+          float v = big[m][n][r] + small[m][n][r];
+          if (do_lin) v = 2.0f * xa[(int64_t)grow * np + gcol] - v;
+          __bf16 pl[NP];
+          split_planes<NP>(v, pl);
+          const int64_t q1 = (int64_t)grow * np + gcol, q2 = (int64_t)gcol * np + grow;
+          o[q1] = v;
+#pragma unroll
+          for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p];
+          if (mirror) {
+            o[q2] = v;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q2] = pl[p];
+          }
+        }
+      }
+}
+
 // DB = 1: the LDS holds two chunks (96 KB with three planes, one workgroup per CU) and the
 // next chunk's loads run under the current chunk's products; DB = 0: one chunk (two
 // workgroups per CU), loaded and then consumed.
@@ -431,34 +469,133 @@ __global__ __launch_bounds__(kT, DB ? 1 : 2) void k_symm_mm_planes(const __bf16*
 #undef GB_ISSUE
 #undef GB_FRAG
   if (!active) return;
-  float* o = S + off;
-  const float* xa = X + off;
-  const bool do_lin = lin_flag ? *lin_flag == 1 : lin != 0;
-  const bool mirror = bi != bj || wr < wc;
+  planes_epilogue<NP>(big, small, S, Sp, X, pstride, off, np, bi, bj, wr, wc, lane,
+                      lin_flag ? *lin_flag == 1 : lin != 0);
+}
+
+// Three planes, pipelined within 80 KB of LDS (two workgroups per CU): the hi and mid planes
+// of the next chunk load into a second buffer while the current chunk is consumed; the lo
+// plane has one buffer, so each chunk first forms the two lo products, then (after a barrier)
+// starts the next chunk's lo load and forms the hi/mid products under it.
+__global__ __launch_bounds__(kT, 2) void k_symm_mm_planes3p(const __bf16* __restrict__ Xp,
+                                                           int64_t pstride, float* __restrict__ S,
+                                                           __bf16* __restrict__ Sp,
+                                                           const int4* __restrict__ tiles,
+                                                           const int64_t* __restrict__ offs,
+                                                           const int32_t* __restrict__ stopped,
+                                                           const float* __restrict__ X, int lin,
+                                                           const int32_t* __restrict__ lin_flag) {
+  if (stopped && *stopped) return;
+  constexpr int KC = 32;
+  constexpr int OPB = kBT * 64;
+  __shared__ __align__(1024) unsigned char lhi[2][2][OPB];  // [buffer][operand]
+  __shared__ __align__(1024) unsigned char lmid[2][2][OPB];
+  __shared__ __align__(1024) unsigned char llo[2][OPB];     // [operand]
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;
+  const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
+  const int64_t off = offs[s];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const __bf16* asrc[2];
+  const __bf16* bsrc[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int slot = (wave * 2 + j) * 64 + lane;
+    const int r = slot >> 2, c = (slot & 3) ^ ((r >> 2) & 3);
+    const int ar = bi * kBT + r, br = bj * kBT + r;
+    asrc[j] = Xp + off + (int64_t)(ar < np ? ar : 0) * np + c * 8;
+    bsrc[j] = Xp + off + (int64_t)(br < np ? br : 0) * np + c * 8;
+  }
+  f4v big[4][4], small[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < 4; ++n) {
+      big[m][n] = f4v{0, 0, 0, 0};
+      small[m][n] = f4v{0, 0, 0, 0};
+    }
+  const int g = lane >> 4, r16 = lane & 15;
+  const int nk = np / KC;
+  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
+  const bool active = in_range && !(bi == bj && wr > wc);
+  const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
+  const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
+#define GB_LOAD(dst, plane, k0)                                                           \
+  _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                         \
+    load_lds16(asrc[j] + (plane) * pstride + (k0), &(dst)[0][(wave * 2 + j) * 1024]);     \
+    load_lds16(bsrc[j] + (plane) * pstride + (k0), &(dst)[1][(wave * 2 + j) * 1024]);     \
+  }
+#define GB_FRAG(dst, arr, opnd, base, m) \
+  __builtin_memcpy(&(dst), &(arr)[opnd][(base) + (m) * 16 * 64 + pc], 16)
+  GB_LOAD(lhi[0], 0, 0)
+  GB_LOAD(lmid[0], 1, 0)
+  GB_LOAD(llo, 2, 0)
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    const int k1 = (kc + 1) * KC;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();  // chunk kc is in LDS; every wave is done with chunk kc - 1
+    if (kc + 1 < nk) {
+      GB_LOAD(lhi[buf ^ 1], 0, k1)
+      GB_LOAD(lmid[buf ^ 1], 1, k1)
+    }
+    bf8v A0[4], B0[4];
+    if (active) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int grow = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4) + r;
-        const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
-        if (grow < np && gcol < np) {
-          float v = big[m][n][r] + small[m][n][r];
-          if (do_lin) v = 2.0f * xa[(int64_t)grow * np + gcol] - v;
-          __bf16 pl[NP];
-          split_planes<NP>(v, pl);
-          const int64_t q1 = (int64_t)grow * np + gcol, q2 = (int64_t)gcol * np + grow;
-          o[q1] = v;
+      for (int m = 0; m < 4; ++m) {
+        GB_FRAG(A0[m], lhi[buf], 0, pa0, m);
+        GB_FRAG(B0[m], lhi[buf], 1, pb0, m);
+      }
+      // (hi, lo) and (lo, hi)
 #pragma unroll
-          for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p];
-          if (mirror) {
-            o[q2] = v;
+      for (int m = 0; m < 4; ++m) {
+        bf8v BL;
+        GB_FRAG(BL, llo, 1, pb0, m);
 #pragma unroll
-            for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q2] = pl[p];
-          }
+        for (int r = 0; r < 4; ++r) small[r][m] = mma_bf16(A0[r], BL, small[r][m]);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        bf8v AL;
+        GB_FRAG(AL, llo, 0, pa0, m);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(AL, B0[n], small[m][n]);
+      }
+    }
+    __syncthreads();  // every wave is done with the lo plane of chunk kc
+    if (kc + 1 < nk) {
+      GB_LOAD(llo, 2, k1)
+    }
+    if (active) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) big[m][n] = mma_bf16(A0[m], B0[n], big[m][n]);
+      bf8v BM[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) GB_FRAG(BM[m], lmid[buf], 1, pb0, m);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(A0[m], BM[n], small[m][n]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        bf8v AM;
+        GB_FRAG(AM, lmid[buf], 0, pa0, m);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+          small[m][n] = mma_bf16(AM, B0[n], small[m][n]);
+          small[m][n] = mma_bf16(AM, BM[n], small[m][n]);
         }
       }
+    }
+  }
+#undef GB_FRAG
+#undef GB_LOAD
+  if (!active) return;
+  planes_epilogue<3>(big, small, S, Sp, X, pstride, off, np, bi, bj, wr, wc, lane,
+                     lin_flag ? *lin_flag == 1 : lin != 0);
 }
 
 // planes of an FP32 batch buffer (after the gather)
@@ -973,7 +1110,10 @@ template <int NP>
 void launch_planes_np(const __bf16* Xp, const float* X, float* S, __bf16* Sp, int64_t total,
                       const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s, int db,
                       int lin, const int32_t* stopped, const int32_t* lin_flag) {
-  if (db)
+  if (NP == 3 && db == 2)
+    hipLaunchKernelGGL(k_symm_mm_planes3p, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
+                       offs, stopped, X, lin, lin_flag);
+  else if (db)
     hipLaunchKernelGGL((k_symm_mm_planes<NP, 1>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
                        tiles, offs, stopped, X, lin, lin_flag);
   else
@@ -1101,7 +1241,7 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
                   hipStream_t s, int policy, int kind, gb_sp2_stats& st, bool xcd) {
   std::vector<int> bt(pl.n_sub, kBT);
   if (policy == 2) bt.assign(pl.n_sub, 64);
-  else if (policy == 0) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd);
+  else if (policy == 0 || policy == 3) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd);
   if (policy == 1) return;
   pl = make_plan(P, &bt, xcd);
   tiles = upload_tiles(pl, s);
@@ -1110,15 +1250,16 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   st.square_flops_exec = pl.flops_exec;
 }
 
-// Split-bf16 kernel variant (double-buffered LDS, one workgroup per CU, or single-buffered,
-// two per CU): policy 1 / 2 force it; policy 0 times one batched launch with each (one
-// warm-up, one timed) the first time a plane count is seen and keeps the faster for the
-// life of the process.
+// Split-bf16 kernel variant: 1 double-buffered LDS (one workgroup per CU), 0 single-buffered
+// (two per CU), 2 pipelined three-plane kernel (two per CU).  Policy 1 / 2 / 3 force 1 / 0 / 2;
+// policy 0 times one batched launch with each (one warm-up, one timed) the first time a plane
+// count is seen and keeps the fastest for the life of the process.
 int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, const float* X,
                           float* S, __bf16* Sp, const int64_t* offs, hipStream_t s, int planes,
                           int policy) {
   if (policy == 1) return 1;
   if (policy == 2) return 0;
+  if (policy == 3) return planes == 3 ? 2 : 0;
   const std::pair<int, int> key{20 + planes, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1129,7 +1270,8 @@ int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, c
   const int nl = (int)pl.launch.size();
   float best = INFINITY;
   int choice = 1;
-  for (int db : {1, 0}) {
+  for (int db : {2, 1, 0}) {
+    if (db == 2 && planes != 3) continue;
     launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
     GB_HIP(hipEventRecord(tm.a, s));
     launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
@@ -1496,7 +1638,9 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     sd = S64.get();
   }
   if (!low && !tape_out) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
-  else if (low && planes > 0) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
+  // (with split-bf16 squares tile_policy picks that kernel's variant; the FP64 refinement tunes
+  // its own tile edge)
+  else if (low && planes > 0) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, 0, 0, st, xcd);
   GB_HIP(hipEventRecord(t_stage.a, s));
   if (low && done) {
     // converged during the FP64 steps: nothing to refine
