@@ -304,6 +304,18 @@ gb_status gb_chebyshev_fermi(double emin, double emax, double beta, double mu, i
 gb_status gb_foe_solve_mu(const double* traces, int32_t order, double emin, double emax,
                           double beta, double n_occ, int32_t n_nodes, double* mu);
 
+/* Host: the pre-determined SP2 branch sequence for a HOMO/LUMO pair (MD section: the whole
+ * sequence of a step fixed in advance from the previous step's gap, so the subgraph expansions
+ * exchange no traces).  With u = 1 - (e_max - e_homo)/(e_max - e_min) and
+ * v = (e_max - e_lumo)/(e_max - e_min) (the distances of the two X0 images from 1 and 0), each
+ * step is X^2 (0) when v > u, else 2X - X^2 (1), applied to both (X^2: v <- v^2,
+ * u <- 2u - u^2; 2X - X^2: u <- u^2, v <- 2v - v^2), until both are <= delta.  out: host array
+ * of max_len bytes; *len receives the length.  Replay it with gb_sp2_opts.branch_in.
+ * GB_EINVAL unless e_min < e_homo < e_lumo < e_max and delta > 0; GB_ESHAPE if max_len steps
+ * do not reach delta. */
+gb_status gb_sp2_sequence(double emin, double emax, double e_homo, double e_lumo, double delta,
+                          int32_t max_len, uint8_t* out, int32_t* len);
+
 #ifdef __cplusplus
 }
 #endif

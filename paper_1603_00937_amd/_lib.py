@@ -105,6 +105,9 @@ SIGNATURES = {
     "gb_chebyshev_fermi": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                             _P(ctypes.c_double)]),
+    "gb_sp2_sequence": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                         _P(ctypes.c_uint8), _P(ctypes.c_int32)]),
     "gb_foe_solve_mu": (ctypes.c_int32, [_P(ctypes.c_double), ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int32, _P(ctypes.c_double)]),

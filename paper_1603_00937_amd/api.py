@@ -285,6 +285,15 @@ def chebyshev_fermi(emin, emax, beta, mu, order, n_nodes=0):
     return list(c)
 
 
+def sp2_sequence(emin, emax, e_homo, e_lumo, delta=1e-12, max_len=127):
+    """Host: the pre-determined SP2 branch sequence for a HOMO/LUMO pair (list of 0/1)."""
+    out = (ctypes.c_uint8 * max(int(max_len), 1))()
+    n = ctypes.c_int32()
+    _check(_lib().gb_sp2_sequence(float(emin), float(emax), float(e_homo), float(e_lumo),
+                                  float(delta), int(max_len), out, ctypes.byref(n)))
+    return [int(out[i]) for i in range(n.value)]
+
+
 def foe_solve_mu(traces, emin, emax, beta, n_occ, n_nodes=0):
     """Host: mu with sum_n c_n(mu) traces[n] = n_occ."""
     t = (ctypes.c_double * len(traces))(*[float(x) for x in traces])

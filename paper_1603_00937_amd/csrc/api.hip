@@ -451,6 +451,33 @@ gb_status gb_chebyshev_fermi(double emin, double emax, double beta, double mu, i
   });
 }
 
+gb_status gb_sp2_sequence(double emin, double emax, double e_homo, double e_lumo, double delta,
+                          int32_t max_len, uint8_t* out, int32_t* len) {
+  return guarded([&] {
+    if (!out || !len) fail(GB_EINVAL, "out / len is NULL");
+    if (!(emin < e_homo && e_homo < e_lumo && e_lumo < emax))
+      fail(GB_EINVAL, "need e_min < e_homo < e_lumo < e_max");
+    if (!(delta > 0.0)) fail(GB_EINVAL, "delta must be > 0");
+    if (max_len < 0) fail(GB_EINVAL, "max_len must be >= 0");
+    double u = 1.0 - (emax - e_homo) / (emax - emin);
+    double v = (emax - e_lumo) / (emax - emin);
+    int n = 0;
+    while (u > delta || v > delta) {
+      if (n == max_len) fail(GB_ESHAPE, "%d steps do not reach delta = %g", max_len, delta);
+      if (v > u) {
+        out[n++] = 0;
+        u = 2.0 * u - u * u;
+        v = v * v;
+      } else {
+        out[n++] = 1;
+        u = u * u;
+        v = 2.0 * v - v * v;
+      }
+    }
+    *len = n;
+  });
+}
+
 gb_status gb_foe_solve_mu(const double* traces, int32_t order, double emin, double emax,
                           double beta, double n_occ, int32_t n_nodes, double* mu) {
   return guarded([&] {

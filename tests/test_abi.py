@@ -195,3 +195,14 @@ def test_foe_rejects_bad_arguments(lib):
     assert lib.gb_chebyshev_fermi(1.0, 0.0, 1.0, 0.0, 3, 0, c) == GB_EINVAL
     assert lib.gb_chebyshev_fermi(0.0, 1.0, 1.0, 0.0, 0, 0, c) == GB_EINVAL
     assert lib.gb_chebyshev_fermi(0.0, 1.0, 1.0, 0.0, 3, 0, None) == GB_EINVAL
+
+
+def test_sp2_sequence_matches_oracle(lib):
+    from oracle.sequence import sequence_from_gap
+    import paper_1603_00937_amd as gb
+    for args in [(-8.6, 8.7, -1.2, 0.48), (-4.4, 4.3, 0.1, 0.2), (0.0, 1.0, 0.30, 0.55)]:
+        assert gb.sp2_sequence(*args) == sequence_from_gap(*args)
+    with pytest.raises(gb.GbError):
+        gb.sp2_sequence(0.0, 1.0, 0.6, 0.4)
+    with pytest.raises(gb.GbError):
+        gb.sp2_sequence(-8.6, 8.7, -1.2, 0.48, max_len=3)
