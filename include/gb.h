@@ -111,6 +111,17 @@ typedef struct gb_graph_s gb_graph_t;
  */
 gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double tau_aux,
                          int32_t mode, void* stream, gb_graph_t** out);
+/*
+ * Divide-and-conquer comparison graph (the cutoff-radius halos the paper compares with, Fig. 5):
+ * orbital o of site a is vertex a * orbs_per_site + o; (i, j) is an edge iff the minimum-image
+ * distance between their sites in the periodic cube of edge `box` is below r_cut (same site
+ * included).  Canonical distance, per axis d = x_b - x_a, d = d - box * rint(d / box), then
+ * r2 = (dx*dx + dy*dy) + dz*dz, edge iff r2 < r_cut*r_cut.  pos: device [n_sites][3] FP64.
+ * Partitioned with gb_partition, its halos are every orbital within r_cut of a core site.
+ * GB_EINVAL for n_sites < 1, orbs_per_site < 1, r_cut <= 0 or box < 2 r_cut.  Synchronises once.
+ */
+gb_status gb_build_graph_rcut(const double* pos, int32_t n_sites, int32_t orbs_per_site,
+                              double box, double r_cut, void* stream, gb_graph_t** out);
 /* Sizes of a graph (host outputs). */
 gb_status gb_graph_info(const gb_graph_t* g, int32_t* n, int64_t* nnz);
 /* Copy the CSR into caller device buffers row_ptr [n+1] and col [nnz]. */

@@ -13,6 +13,11 @@ vertex i in its own subgraph, Eqs. 5-6, and all are symmetrised by union):
   DPREV     S = {|D_prev_ij| >= tau_d}  U  X2(H, tau)          (adaptive MD graph)
   DPREV_SYMBOLIC   Eq. 8 with eps = 0: paths of length two in
             pattern(|D_prev| >= tau_d) U pattern(H)
+  RCUT      the divide-and-conquer comparison (Fig. 5): orbitals i, j adjacent when the
+            minimum-image distance of their sites is below r_cut (periodic cube of edge L).
+            Canonical distance: per axis d = x_j - x_i, d = d - L * rint(d / L); r2 summed
+            x, y, z in that order; edge iff r2 < r_cut * r_cut (every operation rounded
+            separately, so the GPU reproduces it bit for bit).
 
 Canonical X0^2 entry (bit-exact on the GPU): (X0^2)_ij = sum over k in
 row_i intersect row_j of x0_ik * x0_kj, accumulated sequentially in ascending k,
@@ -167,3 +172,23 @@ def graph_dprev_symbolic(H_col, Dp_col, Dp_val, tau_d):
     S = (Pi @ Pi) > 0
     r, c = np.nonzero(S | S.T)
     return csr_from_edges(N, r, c)
+
+
+def graph_rcut(pos: np.ndarray, L: float, r_cut: float, orbs_per_site: int = 2):
+    """RCUT graph over orbitals (orbital o of site a is a * orbs_per_site + o)."""
+    n_sites = pos.shape[0]
+    m = int(orbs_per_site)
+    rows, cols = [], []
+    rc2 = r_cut * r_cut
+    for a in range(n_sites):
+        d = pos - pos[a]
+        d = d - L * np.rint(d / L)
+        r2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        nb = np.nonzero(r2 < rc2)[0]
+        for o in range(m):
+            i = a * m + o
+            for q in range(m):
+                rows.append(np.full(len(nb), i))
+                cols.append(nb * m + q)
+    N = n_sites * m
+    return csr_from_edges(N, np.concatenate(rows), np.concatenate(cols))

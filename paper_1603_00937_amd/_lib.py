@@ -83,6 +83,8 @@ SIGNATURES = {
                                             _P(ctypes.c_double)]),
     "gb_build_graph": (ctypes.c_int32, [_P(GbEll), _P(GbEll), ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int32, _vp, _P(_vp)]),
+    "gb_build_graph_rcut": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, _vp, _P(_vp)]),
     "gb_graph_info": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int64)]),
     "gb_graph_copy": (ctypes.c_int32, [_vp, _vp, _vp, _vp]),
     "gb_graph_view": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int64), _P(_vp),

@@ -140,6 +140,18 @@ def build_graph(H_col, H_val, tau, mode="x2", aux=None, tau_aux=0.0) -> Graph:
     return Graph(out)
 
 
+def build_graph_rcut(pos, box, r_cut, orbs_per_site=2) -> Graph:
+    """Divide-and-conquer comparison graph: orbitals adjacent when their sites are closer than
+    r_cut (minimum image in the periodic cube of edge ``box``).  pos: GPU float64 [n_sites, 3]."""
+    _dev(pos, torch.float64, "pos")
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("pos must be [n_sites, 3]")
+    out = ctypes.c_void_p()
+    _check(_lib().gb_build_graph_rcut(pos.data_ptr(), pos.shape[0], int(orbs_per_site),
+                                      float(box), float(r_cut), _stream(), ctypes.byref(out)))
+    return Graph(out)
+
+
 class Partition:
     """Cores and core+halo subgraph lists owned by the library."""
 

@@ -254,6 +254,31 @@ gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double 
   });
 }
 
+gb_status gb_build_graph_rcut(const double* pos, int32_t n_sites, int32_t orbs_per_site,
+                              double box, double r_cut, void* stream, gb_graph_t** out) {
+  return guarded([&] {
+    if (!out) fail(GB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!pos) fail(GB_EINVAL, "pos is NULL");
+    if (n_sites < 1 || orbs_per_site < 1) fail(GB_EINVAL, "need n_sites, orbs_per_site >= 1");
+    if (!(r_cut > 0.0) || std::isinf(r_cut)) fail(GB_EINVAL, "r_cut = %g must be finite and > 0", r_cut);
+    if (!(box >= 2.0 * r_cut) || std::isinf(box))
+      fail(GB_EINVAL, "box = %g must be finite and at least 2 r_cut", box);
+    if ((int64_t)n_sites * orbs_per_site > INT32_MAX) fail(GB_EINVAL, "too many orbitals");
+    hipStream_t s = as_stream(stream);
+    auto* g = new gb_graph_s();
+    try {
+      graph_rcut(pos, n_sites, orbs_per_site, box, r_cut, g->csr, s);
+      GB_HIP(hipStreamSynchronize(s));
+      detach(g->csr);
+    } catch (...) {
+      delete g;
+      throw;
+    }
+    *out = g;
+  });
+}
+
 gb_status gb_graph_info(const gb_graph_t* g, int32_t* n, int64_t* nnz) {
   return guarded([&] {
     if (!g) fail(GB_EINVAL, "graph is NULL");

@@ -367,6 +367,56 @@ __global__ void k_zero_i32(int32_t* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
+// ---- RCUT graph (divide-and-conquer comparison): sites within r_cut, periodic cube ----------
+// Site a's neighbours b (ascending, a itself included) with the canonical minimum-image squared
+// distance below rc2.  PASS 0 counts per site; PASS 1 writes the orbital rows of site a in
+// ascending column order (a block-wide scan over each 256-site window keeps the order).
+template <int PASS>
+__global__ __launch_bounds__(kT) void k_rcut_rows(const double* __restrict__ pos, int n_sites,
+                                                  int m, double box, double rc2,
+                                                  int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ row_ptr,
+                                                  int32_t* __restrict__ col) {
+  __shared__ int32_t scan[kT];
+  __shared__ int32_t base;
+  const int a = blockIdx.x;
+  const double xa = pos[3 * a], ya = pos[3 * a + 1], za = pos[3 * a + 2];
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int b0 = 0; b0 < n_sites; b0 += kT) {
+    const int b = b0 + threadIdx.x;
+    int hit = 0;
+    if (b < n_sites) {
+      double dx = pos[3 * b] - xa, dy = pos[3 * b + 1] - ya, dz = pos[3 * b + 2] - za;
+      dx = dx - box * rint(dx / box);
+      dy = dy - box * rint(dy / box);
+      dz = dz - box * rint(dz / box);
+      const double r2 = (dx * dx + dy * dy) + dz * dz;
+      hit = r2 < rc2 ? 1 : 0;
+    }
+    scan[threadIdx.x] = hit;
+    __syncthreads();
+    for (int h = 1; h < kT; h <<= 1) {  // inclusive scan (Hillis-Steele)
+      const int v = threadIdx.x >= h ? scan[threadIdx.x - h] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (PASS == 1 && hit) {
+      const int rank = base + scan[threadIdx.x] - 1;  // neighbour index of b in site a's list
+      for (int o = 0; o < m; ++o) {
+        int32_t* out = col + row_ptr[a * m + o];
+        for (int q = 0; q < m; ++q) out[rank * m + q] = b * m + q;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) base += scan[kT - 1];
+    __syncthreads();
+  }
+  if (PASS == 0 && threadIdx.x == 0)
+    for (int o = 0; o < m; ++o) cnt[a * m + o] = base * m;
+}
+
 int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 void check_lds(size_t bytes, const char* what) {
@@ -504,6 +554,27 @@ void graph_pattern(const gb_ell& A, double tau, Csr& out, hipStream_t s) {
   GB_HIP(hipStreamSynchronize(s));
   transpose(A.n, rp.get(), c.get(), nnz, trp, tc, s);
   union_rows(A.n, rp.get(), c.get(), trp.get(), tc.get(), out, s);
+}
+
+void graph_rcut(const double* pos, int n_sites, int m, double box, double r_cut, Csr& out,
+                hipStream_t s) {
+  const int n = n_sites * m;
+  DBuf<int32_t> cnt(n, s);
+  out.n = n;
+  out.row_ptr = DBuf<int32_t>(n + 1, s);
+  const double rc2 = r_cut * r_cut;
+  hipLaunchKernelGGL(k_rcut_rows<0>, dim3(n_sites), dim3(kT), 0, s, pos, n_sites, m, box, rc2,
+                     cnt.get(), nullptr, nullptr);
+  GB_LAUNCH_CHECK();
+  exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
+  int32_t nnz = 0;
+  GB_HIP(hipMemcpyAsync(&nnz, out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  out.nnz = nnz;
+  out.col = DBuf<int32_t>(nnz > 0 ? nnz : 1, s);
+  hipLaunchKernelGGL(k_rcut_rows<1>, dim3(n_sites), dim3(kT), 0, s, pos, n_sites, m, box, rc2,
+                     nullptr, out.row_ptr.get(), out.col.get());
+  GB_LAUNCH_CHECK();
 }
 
 void graph_dprev_symbolic(const gb_ell& H, const gb_ell& Dp, double tau_d, Csr& out,

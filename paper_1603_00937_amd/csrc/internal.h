@@ -87,6 +87,8 @@ void graph_union_dprev(const Csr& base, const gb_ell& Dp, double tau_d, Csr& out
                        hipStream_t s);
 void graph_dprev_symbolic(const gb_ell& H, const gb_ell& Dp, double tau_d, Csr& out,
                           hipStream_t s);
+void graph_rcut(const double* pos, int n_sites, int m, double box, double r_cut, Csr& out,
+                hipStream_t s);
 
 // ---- partition (partition.hip) ----
 struct Part {

@@ -1,0 +1,94 @@
+"""The divide-and-conquer comparison (Fig. 5): cutoff-radius halos against data-dependency
+graph halos on the GPU.  The RCUT graph is bit-exact against the oracle, the density on it
+matches the oracle's partitioned SP2 on the same graph, and both families of partitions are
+measured for error against the exact density matrix and for cost (sum over subgraphs of 2 n^3
+per SP2 step)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1603_00937_amd as gb
+    return gb
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name,rc", [("tiny48", 5.0), ("small256", 3.0), ("small256", 5.5),
+                                     ("n1024", 6.0), ("n1024", 8.0)])
+def test_rcut_graph_bit_exact(gb, model_cache, name, rc):
+    from oracle.graph import graph_rcut
+    m = model_cache(name)
+    g = gb.build_graph_rcut(_dev(m["pos"]), m["L"], rc)
+    rp, cl = [t.cpu().numpy() for t in g.arrays()]
+    orp, ocl = graph_rcut(m["pos"], m["L"], rc, 2)
+    assert np.array_equal(rp, orp) and np.array_equal(cl, ocl)
+
+
+def test_density_on_rcut_partition_matches_oracle(gb, model_cache):
+    from oracle.bounds import gershgorin, x0_values
+    from oracle.graph import graph_rcut
+    from oracle.partition import partition
+    from oracle.sp2 import gather, sp2_partitioned, scatter_columns, default_idem_tol
+    m = model_cache("n1024")
+    N = m["N"]
+    rp, col = graph_rcut(m["pos"], m["L"], 6.0, 2)
+    cp, cv, sp, si = partition(rp, col, 16)
+    lo, hi = gershgorin(m["H_col"], m["H_val"])
+    x0 = x0_values(m["H_col"], m["H_val"], lo, hi)
+    kc = np.diff(cp)
+    blocks = [gather(m["H_col"], x0, si[sp[s]:sp[s + 1]]) for s in range(len(cp) - 1)]
+    xs, info = sp2_partitioned(blocks, kc, m["n_occ"], default_idem_tol(N))
+    oc, ov = scatter_columns(xs, sp, si, kc, N)
+    g = gb.build_graph_rcut(_dev(m["pos"]), m["L"], 6.0)
+    p = gb.partition(g, 16)
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 0.0,
+                                  partition=p)
+    assert st["branch"] == info["branch"] and st["iters"] == info["iters"]
+    dc, dv = D_col.cpu().numpy(), D_val.cpu().numpy()
+    assert np.array_equal(dc, oc[:, :dc.shape[1]])
+    assert float(np.abs(dv - ov[:, :dv.shape[1]]).max()) <= 1e-9
+
+
+def test_error_against_cost(gb, model_cache):
+    """Both halo rules on the N = 1024 system; prints the table of error (Frobenius norm of
+    D - D_exact per occupied orbital) and cost, and checks that more resources buy accuracy."""
+    from oracle.bounds import ell_to_dense
+    from oracle.exact import density_exact
+    from oracle.metrics import column_ell_to_dense
+    m = model_cache("n1024")
+    N = m["N"]
+    D_ex, _, _ = density_exact(ell_to_dense(m["H_col"], m["H_val"]), m["n_occ"])
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+
+    def run(g):
+        p = gb.partition(g, 16)
+        D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], 0.0, partition=p)
+        Dp = column_ell_to_dense(D_col.cpu().numpy(), D_val.cpu().numpy())
+        sizes = np.diff(p.arrays()[1].cpu().numpy()).astype(float)
+        err = float(np.linalg.norm(Dp - D_ex) / np.sqrt(m["n_occ"]))
+        return err, float((2 * sizes ** 3).sum() * st["iters"]), float(sizes.mean()), \
+            st["iters"], st["converged"]
+
+    rows = []
+    for tau in (1e-4, 1e-5, 1e-6):
+        rows.append(("graph", tau) + run(gb.build_graph(Hc, Hv, tau)))
+    for rc in (6.0, 7.0, 8.0):
+        rows.append(("rcut", rc) + run(gb.build_graph_rcut(_dev(m["pos"]), m["L"], rc)))
+    print("\n| halo rule | parameter | error | cost (flops) | mean n | SP2 steps |")
+    for r in rows:
+        print(f"| {r[0]} | {r[1]:g} | {r[2]:.3e} | {r[3]:.3e} | {r[4]:.0f} | {r[5]} |")
+    for fam in ("graph", "rcut"):
+        errs = [r[2] for r in rows if r[0] == fam and r[6]]
+        costs = [r[3] for r in rows if r[0] == fam and r[6]]
+        assert len(errs) == 3
+        assert errs[0] > errs[1] > errs[2] and costs[0] < costs[1] < costs[2]
+    assert min(r[2] for r in rows) < 2e-3

@@ -196,3 +196,26 @@ def test_bfs_partition_invariants(model_cache):
         for v in core:
             closed |= sets[v]
         assert closed | set(core.tolist()) == set(sub.tolist()), "closed under one hop"
+
+
+def test_rcut_graph_against_kdtree():
+    """RCUT graph: the site pairs within r_cut found by scipy's periodic KD-tree (an
+    independent search), expanded to orbitals, plus every same-site pair."""
+    from scipy.spatial import cKDTree
+    from oracle.graph import graph_rcut
+    from synth import make_model
+    m = make_model("small256")
+    pos, L = m["pos"], m["L"]
+    for rc in (3.0, 5.5):
+        rp, col = graph_rcut(pos, L, rc, 2)
+        pairs = cKDTree(pos, boxsize=L).query_pairs(rc, output_type="ndarray")
+        n = len(pos)
+        site_adj = [set([a]) for a in range(n)]
+        for a, b in pairs:
+            site_adj[a].add(b)
+            site_adj[b].add(a)
+        for i in range(2 * n):
+            got = set(col[rp[i]:rp[i + 1]].tolist())
+            want = {2 * b + q for b in site_adj[i // 2] for q in (0, 1)}
+            assert got == want, (rc, i)
+        assert np.all(np.diff(col[rp[0]:rp[1]]) > 0)
