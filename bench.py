@@ -33,18 +33,73 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
-def measured_traffic(workload, precision):
+def measured_traffic(workload, kernel):
     """HBM bytes per launch of the squaring kernel from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None when no record
-    exists for this workload and precision or the kernel source changed since it was taken."""
+    exists for this workload and kernel or the kernel source changed since it was taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     for rec in json.load(open(path)):
-        if (rec["workload"] == workload and rec["precision"] == precision
+        if (rec["workload"] == workload and rec["kernel"] == kernel
                 and rec["sp2_source_sha256"] == kernel_source_hash()):
             return rec["bytes_per_launch"]
     return None
+
+
+def square_kernel_name(precision, stats):
+    """The rocprof name of the loop's squaring kernel for this run."""
+    if precision.startswith("bf16"):
+        planes = {"bf16": 1, "bf16x3": 2, "bf16x6": 3}[precision]
+        v = stats.get("planes_db", 0)
+        return "k_symm_mm_planes3p" if v == 2 else f"k_symm_mm_planes<{planes}, {v}>"
+    t = "double" if precision == "fp64" else "float"
+    edge = 64 if stats["n_tile64"] == stats["n_sub"] else 128
+    return f"k_symm_mm<{t}, 0, {edge}>"
+
+
+def _largest_grid_counter(db, kernel, counter):
+    import sqlite3
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection"
+                     ).fetchall()
+    per = {}
+    for name, grid, cname, val in rows:
+        short = name.replace("gbi::(anonymous namespace)::", "").replace("void ", "", 1)
+        short = short.split("(")[0]
+        if cname != counter or (kernel is not None and short != kernel):
+            continue
+        if kernel is None and "copy" not in short.lower():
+            continue
+        per.setdefault(grid, []).append(float(val))
+    g = max(per)
+    return sum(per[g]) / len(per[g])
+
+
+def traffic_from_pmc(pmc_dir, workload="n18000"):
+    """Per-launch HBM bytes of the squaring kernels from FETCH_SIZE / WRITE_SIZE passes (KiB
+    per dispatch, largest-grid dispatches), each scaled by what the same counter reads for a
+    device copy of 4 GiB (the --copy-calibration run).  Prints the records for traffic.json."""
+    nbytes = 4 << 30
+    sf = nbytes / (_largest_grid_counter(os.path.join(pmc_dir, "copy_fetch", "run_results.db"),
+                                         None, "FETCH_SIZE") * 1024.0)
+    sw = nbytes / (_largest_grid_counter(os.path.join(pmc_dir, "copy_write", "run_results.db"),
+                                         None, "WRITE_SIZE") * 1024.0)
+    recs = []
+    for tag, kernel in (("bf16x6_pipe", "k_symm_mm_planes3p"),
+                        ("bf16x6_sb", "k_symm_mm_planes<3, 0>"),
+                        ("fp64_auto", "k_symm_mm<double, 0, 64>")):
+        f = os.path.join(pmc_dir, f"{tag}_fetch", "run_results.db")
+        w = os.path.join(pmc_dir, f"{tag}_write", "run_results.db")
+        if not (os.path.exists(f) and os.path.exists(w)):
+            continue
+        fb = _largest_grid_counter(f, kernel, "FETCH_SIZE") * 1024.0 * sf
+        wb = _largest_grid_counter(w, kernel, "WRITE_SIZE") * 1024.0 * sw
+        recs.append({"workload": workload, "kernel": kernel, "precision": tag.split("_")[0],
+                     "sp2_source_sha256": kernel_source_hash(), "fetch_bytes": fb,
+                     "write_bytes": wb, "bytes_per_launch": fb + wb,
+                     "copy_scale_fetch": sf, "copy_scale_write": sw})
+    print(json.dumps(recs, indent=1))
 
 
 def run_step(gb, Hc, Hv, n_occ, tau, core, D, args):
@@ -279,6 +334,8 @@ def main():
                     choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
     ap.add_argument("--launch-mode", default="batched", choices=["batched", "per_subgraph", "graph"])
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--traffic-from-pmc", default=None,
+                    help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
     ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "db", "sb", "pipe"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
@@ -307,6 +364,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.traffic_from_pmc:
+        traffic_from_pmc(args.traffic_from_pmc, args.workload)
         return
     if args.md_steps:
         md_run(args)
@@ -393,9 +453,8 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
                    "refine_steps": stats["n_refine_done"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak if achieved else None,
-                     "traffic": measured_traffic(args.workload, precision),
-                     "kernel": ("k_symm_mm_planes (batched X^2, split bf16)"
-                                if precision.startswith("bf16") else "k_symm_mm (batched X^2)"),
+                     "traffic": measured_traffic(args.workload, square_kernel_name(precision, stats)),
+                     "kernel": square_kernel_name(precision, stats),
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
                      "exec_tflops": flops_exec / avg_launch_s / 1e12 if avg_launch_s else None,
                      "avg_launch_ms": avg_launch_s * 1e3 if avg_launch_s else None},
