@@ -54,8 +54,10 @@ def square_kernel_name(precision, stats):
         v = stats.get("planes_db", 0)
         return "k_symm_mm_planes3p" if v == 2 else f"k_symm_mm_planes<{planes}, {v}>"
     t = "double" if precision == "fp64" else "float"
+    if stats.get("n_stage3", 0) == stats["n_sub"]:
+        return f"k_symm_mm<{t}, 0, 64, 3>"
     edge = 64 if stats["n_tile64"] == stats["n_sub"] else 128
-    return f"k_symm_mm<{t}, 0, {edge}>"
+    return f"k_symm_mm<{t}, 0, {edge}, 2>"
 
 
 def _largest_grid_counter(db, kernel, counter):
@@ -336,7 +338,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from-pmc", default=None,
                     help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "db", "sb", "pipe"])
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "db", "sb", "pipe"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)

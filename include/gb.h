@@ -198,8 +198,9 @@ typedef struct {
                               * 2: batched launches with the stop flag, counter and branch    *
                               *    records on the device, two steps captured in a hipGraph    *
                               *    and replayed (no host round trip per step; no tape)        */
-  int32_t tile_policy;       /* FP64 / FP32 squares: tile edge autotuned per 256-wide size     *
-                              * bucket (0, timed once per process), 1 = 128, 2 = 64;          *
+  int32_t tile_policy;       /* FP64 / FP32 squares: kernel variant autotuned per 256-wide    *
+                              * size bucket (0, timed once per process), 1 = 128-edge tiles,  *
+                              * 2 = 64-edge, 4 = 64-edge with three LDS stages;               *
                               * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
                               * buffered LDS, 2 = single-buffered, 3 = pipelined (three       *
                               * planes; others as 2).  FP64 / FP32 treat 3 as 0.              */
@@ -224,7 +225,9 @@ typedef struct {
   int32_t n_square_lo;
   int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */
   int32_t n_refine_done;     /* McWeeny steps applied                                        */
-  int32_t planes_db;         /* split-bf16 loops: 1 if the double-buffered kernel variant ran */
+  int32_t planes_db;         /* split-bf16 loops: kernel variant (0 single-, 1 double-buffered, *
+                              * 2 pipelined)                                                  */
+  int32_t n_stage3;          /* subgraphs squared with the three-stage 64-edge kernel         */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
   struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */

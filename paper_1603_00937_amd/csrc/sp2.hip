@@ -141,7 +141,9 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
 // In MODE 0 (A = B = X) the SP2 update is fused into the epilogue: with the branch
 // 2X - X^2 selected (lin, or *lin_flag on the device-driven loop) the kernel writes 2X - X^2,
 // else X^2.  X is symmetric, so the mirrored entry takes the same value.
-template <typename T, int MODE, int BT = 128>
+// STAGES = 2: the next chunk loads while the current one is consumed; STAGES = 3: the two next
+// chunks are in flight (one more LDS buffer), for latency the second buffer cannot hide.
+template <typename T, int MODE, int BT = 128, int STAGES = 2>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, const T* __restrict__ B,
                                                    const T* __restrict__ E, T* __restrict__ out,
                                                    T alpha, T beta, const int4* __restrict__ tiles,
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   // [buffer][operand][row-major 128-byte rows, the eight 16-byte pieces of row r stored at
   // slot (piece ^ (r & 7)) so that sixteen lanes reading one piece of sixteen rows hit
   // different banks]
-  __shared__ __align__(1024) unsigned char lds[2][2][OPB];
+  __shared__ __align__(1024) unsigned char lds[STAGES][2][OPB];
 
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;  // padding entry of an XCD queue
@@ -211,13 +213,28 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   const int pa0 = (wr * WM + r16) * 128, pb0 = (wc * WM + r16) * 128;
   const int pc0 = (((2 * g) ^ sw) << 4), pc1 = (((2 * g + 1) ^ sw) << 4);
 
+  // each wave issues 2 NLD loads per chunk; loads complete in order, so waiting until at most
+  // 2 NLD are outstanding means every chunk but the newest has landed
+  static_assert(STAGES == 2 || STAGES == 3, "two or three LDS stages");
+  static_assert(STAGES == 2 || 2 * NLD == 4 || 2 * NLD == 8, "wait count");
+#define GB_WAIT_ALL_BUT_NEWEST()                                   \
+  do {                                                             \
+    if constexpr (2 * NLD == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); \
+    else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");          \
+  } while (0)
   GB_ISSUE(0, 0)
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  if (STAGES == 3 && nk > 1) {
+    GB_ISSUE(1, KC)
+    GB_WAIT_ALL_BUT_NEWEST();
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  }
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nk) {
-      GB_ISSUE(buf ^ 1, (kc + 1) * KC)
+    const int buf = kc % STAGES;
+    const int ahead = kc + STAGES - 1;  // the chunk issued in this iteration
+    if (ahead < nk) {
+      GB_ISSUE(ahead % STAGES, ahead * KC)
     }
     if (active) {
       const unsigned char* la = lds[buf][0];
@@ -239,9 +256,12 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
             for (int n = 0; n < MB; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
       }
     }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    // chunk kc + 1 must have landed; with three stages chunk kc + 2 may stay in flight
+    if (STAGES == 3 && kc + 2 < nk) GB_WAIT_ALL_BUT_NEWEST();
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
+#undef GB_WAIT_ALL_BUT_NEWEST
 #undef GB_ISSUE
 
   if (!active) return;
@@ -968,20 +988,31 @@ int grid_for(int64_t n, int t, int cap = 1 << 20) {
 // ---- plan: padded sizes, offsets, tile lists ---------------------------------------------
 // Square tiles are listed 128-edge tiles first, then 64-edge tiles; within each group the
 // largest blocks come first (most k work per tile).
+// Kernel variants of the batched products, one code per subgraph: 128 (128-edge tiles, two LDS
+// stages), 64 (64-edge, two stages), 63 (64-edge, three stages).
+constexpr int kVariants[3] = {128, 64, 63};
+inline int variant_edge(int code) { return code == 128 ? 128 : 64; }
+
+// tiles per variant group (launch order: 128, 64, 63)
+struct Groups {
+  int n[3] = {0, 0, 0};
+  int total() const { return n[0] + n[1] + n[2]; }
+};
+
 struct Plan {
   int n_sub = 0;
   std::vector<int32_t> npad;
   std::vector<int64_t> off;
-  std::vector<int> bt;           // tile edge chosen for each subgraph (64 or 128)
+  std::vector<int> bt;           // kernel variant code chosen for each subgraph
   int64_t total = 0;
-  std::vector<int4> tiles;       // bi <= bj (symmetric products): n128 tiles of edge 128 first,
-  int n128 = 0;                  //   subgraph-major (per-subgraph launches use `ranges`)
-  std::vector<int4> launch;      // the same tiles as launched in one batch: l128 entries of edge
-  int l128 = 0;                  //   128 then the 64-edge ones, each group in XCD order
+  std::vector<int4> tiles;       // bi <= bj (symmetric products), grouped by variant
+  Groups tg;                     //   (subgraph-major; per-subgraph launches use `ranges`)
+  std::vector<int4> launch;      // the same tiles as launched in one batch, each variant group
+  Groups lg;                     //   in XCD order
   std::vector<int4> tiles_full;  // every (bi, bj) with edge 128 (general products)
-  std::vector<int4> ranges;      // per subgraph: first tile, tile count, edge
+  std::vector<int4> ranges;      // per subgraph: first tile, tile count, variant code, s
   std::vector<int4> idem;        // 128-edge upper tiles covering the core rows (final check)
-  int planes_db = 1;             // split-bf16 kernel variant (double-buffered LDS or not)
+  int planes_db = 1;             // split-bf16 kernel variant
   double flops_alg = 0, flops_exec = 0;
   int max_npad = 0;
 };
@@ -1032,9 +1063,13 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
   }
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return pl.npad[a] > pl.npad[b]; });
-  for (int edge : {128, 64}) {
+  size_t r_first[4] = {0, 0, 0, 0};
+  for (int v = 0; v < 3; ++v) {
+    const int code = kVariants[v], edge = variant_edge(code);
+    const int t0 = (int)pl.tiles.size();
+    r_first[v] = pl.ranges.size();
     for (int s : order) {
-      if (pl.bt[s] != edge) continue;
+      if (pl.bt[s] != code) continue;
       const int np = pl.npad[s];
       const int nb = (np + edge - 1) / edge;
       const int first = (int)pl.tiles.size();
@@ -1043,20 +1078,21 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
           pl.tiles.push_back(make_int4(s, bi, bj, np));
           pl.flops_exec += 2.0 * edge * edge * (double)np;
         }
-      pl.ranges.push_back(make_int4(first, (int)pl.tiles.size() - first, edge, s));
+      pl.ranges.push_back(make_int4(first, (int)pl.tiles.size() - first, code, s));
     }
-    if (edge == 128) pl.n128 = (int)pl.tiles.size();
+    pl.tg.n[v] = (int)pl.tiles.size() - t0;
   }
+  r_first[3] = pl.ranges.size();
   // launch list of the batched squaring: each group in XCD order (or as listed)
-  size_t r_split = 0;
-  while (r_split < pl.ranges.size() && pl.ranges[r_split].z == 128) ++r_split;
   if (xcd) {
-    xcd_order(pl.launch, pl.tiles, pl.ranges, 0, r_split);
-    pl.l128 = (int)pl.launch.size();
-    xcd_order(pl.launch, pl.tiles, pl.ranges, r_split, pl.ranges.size());
+    for (int v = 0; v < 3; ++v) {
+      const size_t before = pl.launch.size();
+      xcd_order(pl.launch, pl.tiles, pl.ranges, r_first[v], r_first[v + 1]);
+      pl.lg.n[v] = (int)(pl.launch.size() - before);
+    }
   } else {
     pl.launch = pl.tiles;
-    pl.l128 = pl.n128;
+    pl.lg = pl.tg;
   }
   for (int s : order) {
     const int np = pl.npad[s];
@@ -1087,22 +1123,41 @@ struct TapeData {
 
 namespace {
 
-// One SP2 step on the tile lists: the new iterate X^2 (lin = 0) or 2X - X^2 (lin = 1), or the
+// One batched symmetric product over the variant groups of a tile list (see k_symm_mm).
+template <typename T, int MODE>
+void launch_symm(const T* A, const T* B, const T* E, T* out, T alpha, T beta, const int4* tiles,
+                 const Groups& g, const int64_t* offs, hipStream_t s,
+                 const int32_t* stopped = nullptr, int lin = 0,
+                 const int32_t* lin_flag = nullptr, T* dacc = nullptr, T cn = (T)0) {
+  const int4* t = tiles;
+  if (g.n[0] > 0)
+    hipLaunchKernelGGL((k_symm_mm<T, MODE, 128, 2>), dim3(g.n[0]), dim3(kT), 0, s, A, B, E, out,
+                       alpha, beta, t, offs, stopped, lin, lin_flag, dacc, cn);
+  t += g.n[0];
+  if (g.n[1] > 0)
+    hipLaunchKernelGGL((k_symm_mm<T, MODE, 64, 2>), dim3(g.n[1]), dim3(kT), 0, s, A, B, E, out,
+                       alpha, beta, t, offs, stopped, lin, lin_flag, dacc, cn);
+  t += g.n[1];
+  if (g.n[2] > 0)
+    hipLaunchKernelGGL((k_symm_mm<T, MODE, 64, 3>), dim3(g.n[2]), dim3(kT), 0, s, A, B, E, out,
+                       alpha, beta, t, offs, stopped, lin, lin_flag, dacc, cn);
+  GB_LAUNCH_CHECK();
+}
+
+// One SP2 step on a tile list: the new iterate X^2 (lin = 0) or 2X - X^2 (lin = 1), or the
 // branch read from *lin_flag on the device-driven loop.
 template <typename T>
-void launch_square(const T* X, T* S, const int4* tiles, int n128, int n64, const int64_t* offs,
+void launch_square(const T* X, T* S, const int4* tiles, const Groups& g, const int64_t* offs,
                    hipStream_t s, int lin = 0, const int32_t* stopped = nullptr,
                    const int32_t* lin_flag = nullptr) {
-  if (n128 > 0) {
-    hipLaunchKernelGGL((k_symm_mm<T, 0, 128>), dim3(n128), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                       tiles, offs, stopped, lin, lin_flag, (T*)nullptr, (T)0);
-    GB_LAUNCH_CHECK();
-  }
-  if (n64 > 0) {
-    hipLaunchKernelGGL((k_symm_mm<T, 0, 64>), dim3(n64), dim3(kT), 0, s, X, X, X, S, (T)1, (T)0,
-                       tiles + n128, offs, stopped, lin, lin_flag, (T*)nullptr, (T)0);
-    GB_LAUNCH_CHECK();
-  }
+  launch_symm<T, 0>(X, X, X, S, (T)1, (T)0, tiles, g, offs, s, stopped, lin, lin_flag);
+}
+
+// a single group (the idempotency check's 128-edge tiles, one subgraph's range)
+inline Groups one_group(int code, int count) {
+  Groups g;
+  g.n[code == 128 ? 0 : (code == 64 ? 1 : 2)] = count;
+  return g;
 }
 
 // the same with split-bf16 squares: planes of X -> new iterate (FP32) and its planes
@@ -1155,7 +1210,7 @@ DBuf<int4> upload_tiles(const Plan& pl, hipStream_t s) {
 
 void launch_plan_square_f64(const double* X, double* S, const Plan& pl, const int4* tiles,
                             const int64_t* offs, hipStream_t s, int lin = 0) {
-  launch_square<double>(X, S, tiles, pl.l128, (int)pl.launch.size() - pl.l128, offs, s, lin);
+  launch_square<double>(X, S, tiles, pl.lg, offs, s, lin);
 }
 
 struct Timer {
@@ -1210,22 +1265,21 @@ std::vector<int> tune_tiles(const Part& P, const Plan& pl, T* X, T* S, const int
     }
     if (!choice) {
       float best = INFINITY;
-      for (int edge : {128, 64}) {
+      for (int code : kVariants) {
         std::vector<int> e(pl.n_sub, 0);
-        for (int i : kv.second) e[i] = edge;
+        for (int i : kv.second) e[i] = code;
         const Plan sub = make_plan(P, &e, xcd);
         DBuf<int4> tl = upload_tiles(sub, s);
-        const int n128 = sub.l128, n64 = (int)sub.launch.size() - sub.l128;
-        launch_square<T>(X, S, tl.get(), n128, n64, offs, s);
+        launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
         GB_HIP(hipEventRecord(tm.a, s));
-        launch_square<T>(X, S, tl.get(), n128, n64, offs, s);
-        launch_square<T>(X, S, tl.get(), n128, n64, offs, s);
+        launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
+        launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
         GB_HIP(hipEventRecord(tm.b, s));
         GB_HIP(hipStreamSynchronize(s));
         const float ms = elapsed(tm.a, tm.b);
         if (ms < best) {
           best = ms;
-          choice = edge;
+          choice = code;
         }
       }
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1241,12 +1295,17 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
                   hipStream_t s, int policy, int kind, gb_sp2_stats& st, bool xcd) {
   std::vector<int> bt(pl.n_sub, kBT);
   if (policy == 2) bt.assign(pl.n_sub, 64);
+  else if (policy == 4) bt.assign(pl.n_sub, 63);
   else if (policy == 0 || policy == 3) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd);
   if (policy == 1) return;
   pl = make_plan(P, &bt, xcd);
   tiles = upload_tiles(pl, s);
   st.n_tile64 = 0;
-  for (int e : bt) st.n_tile64 += e == 64;
+  st.n_stage3 = 0;
+  for (int e : bt) {
+    st.n_tile64 += e != 128;
+    st.n_stage3 += e == 63;
+  }
   st.square_flops_exec = pl.flops_exec;
 }
 
@@ -1356,10 +1415,10 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
     if (!launched) {
       if (per_subgraph) {
         for (const int4& rg : pl.ranges)
-          launch_square<T>(X, S, tiles.get() + nl + rg.x, rg.z == 128 ? rg.y : 0,
-                           rg.z == 128 ? 0 : rg.y, offs.get(), s, lin);
+          launch_square<T>(X, S, tiles.get() + nl + rg.x, one_group(rg.z, rg.y), offs.get(), s,
+                           lin);
       } else {
-        launch_square<T>(X, S, tiles.get(), pl.l128, nl - pl.l128, offs.get(), s, lin);
+        launch_square<T>(X, S, tiles.get(), pl.lg, offs.get(), s, lin);
       }
     }
     GB_HIP(hipEventRecord(tm.b, s));
@@ -1445,7 +1504,7 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
       }
     }
     if (!launched)
-      launch_square<T>(A, B, tiles.get(), pl.l128, nl - pl.l128, offs.get(), cs, 0, stopped, cur_b);
+      launch_square<T>(A, B, tiles.get(), pl.lg, offs.get(), cs, 0, stopped, cur_b);
   }
   GB_HIP(hipStreamEndCapture(cs, &graph));
   GB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -1654,7 +1713,6 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     DBuf<double> part(2 * (size_t)pl.n_sub, s);
     double* td = T64.get();
     const int max_steps = n_refine > 0 ? n_refine : 8;
-    const int n64 = (int)pl.launch.size() - pl.l128;
     const int at = std::min(it_end, 127);
     StepRec r;
     for (int step = 0;; ++step) {
@@ -1666,16 +1724,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       GB_HIP(hipMemcpyAsync(&r, recs.get(), sizeof(r), hipMemcpyDeviceToHost, s));
       GB_HIP(hipStreamSynchronize(s));
       if (r.e <= tol || step == max_steps) break;
-      launch_square<double>(xd, sd, tiles.get(), pl.l128, n64, offs.get(), s);
-      if (pl.l128 > 0)
-        hipLaunchKernelGGL((k_symm_mm<double, 1, 128>), dim3(pl.l128), dim3(kT), 0, s, sd, xd, sd,
-                           td, -2.0, 3.0, tiles.get(), offs.get(), nullptr, 0, nullptr,
-                           (double*)nullptr, 0.0);
-      if (n64 > 0)
-        hipLaunchKernelGGL((k_symm_mm<double, 1, 64>), dim3(n64), dim3(kT), 0, s, sd, xd, sd, td,
-                           -2.0, 3.0, tiles.get() + pl.l128, offs.get(), nullptr, 0, nullptr,
-                           (double*)nullptr, 0.0);
-      GB_LAUNCH_CHECK();
+      launch_square<double>(xd, sd, tiles.get(), pl.lg, offs.get(), s);
+      launch_symm<double, 1>(sd, xd, sd, td, -2.0, 3.0, tiles.get(), pl.lg, offs.get(), s);
       std::swap(xd, td);
       ++st.n_refine_done;
     }
@@ -1722,7 +1772,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   DBuf<int4> idem_tiles(std::max<size_t>(pl.idem.size(), 1), s);
   GB_HIP(hipMemcpyAsync(idem_tiles.get(), pl.idem.data(), pl.idem.size() * sizeof(int4),
                         hipMemcpyHostToDevice, s));
-  launch_square<double>(xd, sd, idem_tiles.get(), (int)pl.idem.size(), 0, offs.get(), s);
+  launch_square<double>(xd, sd, idem_tiles.get(), one_group(128, (int)pl.idem.size()), offs.get(),
+                        s);
   DBuf<double> per(pl.n_sub, s), mx(1, s);
   hipLaunchKernelGGL(k_idem<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, sd, offs.get(), npad.get(),
                      P.core_ptr.get(), P.sub_ptr.get(), per.get());
@@ -1872,24 +1923,11 @@ __global__ __launch_bounds__(kT) void k_trace_total(const double* __restrict__ p
 // symmetric), and with dacc: dacc += cn T_next
 void launch_cheb(const double* A, const double* Tc, const double* Tp, double* Tn, double* dacc,
                  double cn, const Plan& pl, const int4* tiles, const int64_t* offs, hipStream_t s) {
-  const int n128 = pl.l128, n64 = (int)pl.launch.size() - pl.l128;
-  if (dacc) {
-    if (n128 > 0)
-      hipLaunchKernelGGL((k_symm_mm<double, 4, 128>), dim3(n128), dim3(kT), 0, s, A, Tc, Tp, Tn,
-                         2.0, -1.0, tiles, offs, nullptr, 0, nullptr, dacc, cn);
-    if (n64 > 0)
-      hipLaunchKernelGGL((k_symm_mm<double, 4, 64>), dim3(n64), dim3(kT), 0, s, A, Tc, Tp, Tn,
-                         2.0, -1.0, tiles + n128, offs, nullptr, 0, nullptr, dacc, cn);
-  } else {
-    if (n128 > 0)
-      hipLaunchKernelGGL((k_symm_mm<double, 1, 128>), dim3(n128), dim3(kT), 0, s, A, Tc, Tp, Tn,
-                         2.0, -1.0, tiles, offs, nullptr, 0, nullptr, (double*)nullptr, 0.0);
-    if (n64 > 0)
-      hipLaunchKernelGGL((k_symm_mm<double, 1, 64>), dim3(n64), dim3(kT), 0, s, A, Tc, Tp, Tn,
-                         2.0, -1.0, tiles + n128, offs, nullptr, 0, nullptr, (double*)nullptr,
-                         0.0);
-  }
-  GB_LAUNCH_CHECK();
+  if (dacc)
+    launch_symm<double, 4>(A, Tc, Tp, Tn, 2.0, -1.0, tiles, pl.lg, offs, s, nullptr, 0, nullptr,
+                           dacc, cn);
+  else
+    launch_symm<double, 1>(A, Tc, Tp, Tn, 2.0, -1.0, tiles, pl.lg, offs, s);
 }
 
 int quad_nodes(int order, int n_nodes) { return n_nodes > 0 ? n_nodes : std::max(4 * (order + 1), 1024); }
