@@ -201,9 +201,9 @@ def md_run(args):
         big = np.iinfo(np.int32).max
         Hs = torch.where(Hc >= 0, Hc, torch.full_like(Hc, big)).long().contiguous()
         rows = D_col.long().contiguous()
-        pos = torch.searchsorted(Hs, rows).clamp(max=Hs.shape[1] - 1)
-        hit = (torch.gather(Hs, 1, pos) == rows) & (rows >= 0)
-        GD = torch.where(hit, torch.gather(Vd, 1, pos), torch.zeros_like(D_val))
+        slot = torch.searchsorted(Hs, rows).clamp(max=Hs.shape[1] - 1)
+        hit = (torch.gather(Hs, 1, slot) == rows) & (rows >= 0)
+        GD = torch.where(hit, torch.gather(Vd, 1, slot), torch.zeros_like(D_val))
         L = float((GD * D_val).sum())
         G_H = tape.vjp(GD.contiguous())
         torch.cuda.synchronize()
