@@ -40,6 +40,11 @@ typedef int32_t gb_status;
 #define GB_ESHAPE (-4)        /* an output array is too small / sizes are inconsistent */
 #define GB_EUNSUPPORTED (-5)  /* valid request outside what this build implements      */
 
+/* The dense batch buffers of gb_density / gb_foe_density are cached between calls (per device
+ * and per concurrent call, grown when a call needs more), so a loop of calls does not
+ * reallocate them.  gb_trim frees the cached buffers of every call that has returned. */
+gb_status gb_trim(void);
+
 /* Library version string (static storage). */
 const char* gb_version(void);
 /* Message for the last failing call on this thread ("" if none). */

@@ -98,6 +98,7 @@ SIGNATURES = {
                                            _P(_vp), _P(_vp)]),
     "gb_partition_destroy": (None, [_vp]),
     "gb_set_allocator": (ctypes.c_int32, [ALLOC_FN, FREE_FN, _vp]),
+    "gb_trim": (ctypes.c_int32, []),
     "gb_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double, _P(GbSp2Opts),
                                     _P(GbEll), _P(GbSp2Stats), _vp]),
     "gb_density_vjp": (ctypes.c_int32, [_vp, _P(GbEll), _P(GbEll), _vp]),

@@ -90,6 +90,11 @@ def set_allocator(allocator):
     _check(_lib().gb_set_allocator(allocator._alloc_fn, allocator._free_fn, None))
 
 
+def trim():
+    """Free the batch buffers the library caches between calls."""
+    _check(_lib().gb_trim())
+
+
 def spectral_bounds(H_col, H_val):
     """Gershgorin (e_min, e_max) of H."""
     H = _ell(H_col, H_val)

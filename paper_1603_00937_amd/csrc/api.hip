@@ -62,6 +62,67 @@ void dfree(void* p, hipStream_t s, const Allocator& a) {
   else (void)hipFreeAsync(p, s);
 }
 
+void* Workspace::get_bytes(int slot, size_t bytes, hipStream_t s) {
+  Slab& b = slab[slot];
+  if (bytes > b.bytes) {
+    if (b.p) dfree(b.p, s, b.a);
+    b.p = nullptr;
+    b.bytes = 0;
+    const size_t want = bytes + bytes / 16;  // headroom: sizes drift between MD steps
+    b.p = dmalloc(want, s, &b.a);
+    b.bytes = want;
+  }
+  return b.p;
+}
+
+void Workspace::release_all() {
+  for (auto& b : slab) {
+    if (b.p) dfree(b.p, nullptr, b.a);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+}
+
+std::mutex g_ws_mu;
+std::vector<Workspace*> g_ws_idle;
+
+Workspace* ws_acquire() {
+  int dev = 0;
+  GB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  for (size_t i = 0; i < g_ws_idle.size(); ++i)
+    if (g_ws_idle[i]->device == dev) {
+      Workspace* w = g_ws_idle[i];
+      g_ws_idle.erase(g_ws_idle.begin() + i);
+      return w;
+    }
+  Workspace* w = new Workspace();
+  w->device = dev;
+  return w;
+}
+
+void ws_release(Workspace* w) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  g_ws_idle.push_back(w);
+}
+
+void ws_trim() {
+  std::vector<Workspace*> idle;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    idle.swap(g_ws_idle);
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (Workspace* w : idle) {
+    (void)hipSetDevice(w->device);
+    (void)hipDeviceSynchronize();
+    w->release_all();
+    delete w;
+  }
+  (void)hipSetDevice(cur);
+}
+
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
              double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s,
              TapeData** tape_out);
@@ -187,6 +248,10 @@ extern "C" {
 const char* gb_version(void) { return "libgb 0.1.0 (gfx950)"; }
 
 const char* gb_last_error(void) { return g_err; }
+
+gb_status gb_trim(void) {
+  return guarded([&] { ws_trim(); });
+}
 
 gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx) {
   return guarded([&] {

@@ -68,6 +68,40 @@ struct DBuf {
   void detach_stream() { s = nullptr; }
 };
 
+// ---- cached batch buffers -------------------------------------------------------------------
+// The dense batch buffers (tens of GB at N = 100000) are kept between calls instead of being
+// returned to the pool: a call leases a workspace (one per concurrent call and device), takes
+// its buffers from numbered slots that grow when a call needs more, and gives it back at the
+// end.  Every call synchronises its stream before returning, so the next lease may use the
+// memory on any stream.  gb_trim frees the idle workspaces.
+struct Workspace {
+  int device = 0;
+  struct Slab {
+    void* p = nullptr;
+    size_t bytes = 0;
+    Allocator a;
+  };
+  static constexpr int kSlots = 8;
+  Slab slab[kSlots];
+  void* get_bytes(int slot, size_t bytes, hipStream_t s);
+  template <typename T>
+  T* get(int slot, size_t count, hipStream_t s) {
+    return static_cast<T*>(get_bytes(slot, count * sizeof(T), s));
+  }
+  void release_all();
+};
+Workspace* ws_acquire();
+void ws_release(Workspace* w);
+void ws_trim();
+struct WsLease {
+  Workspace* w;
+  WsLease() : w(ws_acquire()) {}
+  ~WsLease() { ws_release(w); }
+  WsLease(const WsLease&) = delete;
+  WsLease& operator=(const WsLease&) = delete;
+  Workspace* operator->() const { return w; }
+};
+
 // ---- scans (scan.hip) ----
 // out[0..n] = exclusive prefix sums of in[0..n-1]; out[n] = total.
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t s);

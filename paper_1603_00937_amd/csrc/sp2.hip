@@ -1576,20 +1576,19 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   const size_t lds_g = (size_t)pl.max_npad * 8 + (size_t)P.max_sub * 4 + 64;
   if (lds_g > 160 * 1024) fail(GB_EUNSUPPORTED, "subgraph of %d vertices too large", P.max_sub);
   const dim3 ggrid(pl.n_sub, (pl.max_npad + kRows - 1) / kRows);
-  DBuf<double> X64, S64, T64;
-  double* xd = nullptr;
-  double* sd = nullptr;
+  // batch buffers from the cached workspace: slots 0-2 FP64 (X, S, McWeeny T), 3-4 FP32,
+  // 5-6 the bf16 planes of X and S
+  WsLease ws;
+  double* const X64 = ws->get<double>(0, pl.total, s);
+  double* const S64 = ws->get<double>(1, pl.total, s);
+  double* xd = X64;
+  double* sd = S64;
   int it_end = 0;
   bool done = false;  // the FP64 steps before a low-precision loop already converged
   if (low) {
-    DBuf<float> X32(pl.total, s), S32(pl.total, s);
-    float* xf = X32.get();
-    float* sf = S32.get();
+    float* xf = ws->get<float>(3, pl.total, s);
+    float* sf = ws->get<float>(4, pl.total, s);
     const int nhi = std::min(std::max(0, o.n_fp64_first), max_iter);
-    X64 = DBuf<double>(pl.total, s);
-    S64 = DBuf<double>(pl.total, s);
-    xd = X64.get();
-    sd = S64.get();
     if (nhi > 0) {
       hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
                          P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(),
@@ -1620,10 +1619,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     if (!done) {
       if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
       // split-bf16: planes of X and of X^2 (NP bf16 arrays of the batch size each)
-      DBuf<__bf16> XP(planes > 0 ? (size_t)planes * pl.total : 0, s);
-      DBuf<__bf16> SP(planes > 0 ? (size_t)planes * pl.total : 0, s);
-      __bf16* xp = XP.get();
-      __bf16* sp = SP.get();
+      __bf16* xp = planes > 0 ? ws->get<__bf16>(5, (size_t)planes * pl.total, s) : nullptr;
+      __bf16* sp = planes > 0 ? ws->get<__bf16>(6, (size_t)planes * pl.total, s) : nullptr;
       if (planes > 0) {
         make_planes(xf, xp, pl.total, s, planes);
         pl.planes_db = choose_planes_variant(pl, tiles.get(), xp, xf, sf, sp, offs.get(), s,
@@ -1651,11 +1648,9 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     GB_HIP(hipStreamSynchronize(s));
     st.ms_sp2 = elapsed(t_stage.a, t_stage.b);
   } else {
-    X64 = DBuf<double>(pl.total, s);
-    S64 = DBuf<double>(pl.total, s);
     hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
                        P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
-                       X64.get());
+                       X64);
     GB_LAUNCH_CHECK();
     if (tape_out) {
       TapeData* t = new TapeData();
@@ -1684,7 +1679,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       dup_i32(t->sub_idx, P.sub_idx, P.total);
       dup_i32(t->sub_pos, P.sub_pos, P.total);
       DBuf<double> c(pl.total, nullptr);
-      GB_HIP(hipMemcpyAsync(c.get(), X64.get(), pl.total * 8, hipMemcpyDeviceToDevice, s));
+      GB_HIP(hipMemcpyAsync(c.get(), X64, pl.total * 8, hipMemcpyDeviceToDevice, s));
       t->ckpt.push_back(std::move(c));
       GB_HIP(hipStreamSynchronize(s));  // host plan vectors above are copied before return
     }
@@ -1692,10 +1687,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     GB_HIP(hipStreamSynchronize(s));
     st.ms_gather = elapsed(t_stage.a, t_stage.b);
   }
-  if (!low) {
-    xd = X64.get();
-    sd = S64.get();
-  }
+
   if (!low && !tape_out) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
   // (with split-bf16 squares tile_policy picks that kernel's variant; the FP64 refinement tunes
   // its own tile edge)
@@ -1709,9 +1701,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     // 0 or 1 without acting on the trace, so the occupation the low-precision loop reached is
     // kept.  Steps repeat until the FP64 stop test holds (at most n_refine, default 8); the
     // test takes the traces from X itself, so no square is spent on it.
-    T64 = DBuf<double>(pl.total, s);
     DBuf<double> part(2 * (size_t)pl.n_sub, s);
-    double* td = T64.get();
+    double* td = ws->get<double>(2, pl.total, s);
     const int max_steps = n_refine > 0 ? n_refine : 8;
     const int at = std::min(it_end, 127);
     StepRec r;
@@ -2010,16 +2001,21 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   const size_t lds_g = (size_t)pl.max_npad * 8 + (size_t)P.max_sub * 4 + 64;
   if (lds_g > 160 * 1024) fail(GB_EUNSUPPORTED, "subgraph of %d vertices too large", P.max_sub);
   const dim3 ggrid(pl.n_sub, (pl.max_npad + kRows - 1) / kRows);
-  DBuf<double> A(pl.total, s), B0(pl.total, s), B1(pl.total, s), B2(pl.total, s), Dacc(pl.total, s);
+  WsLease ws;  // cached batch buffers: Ht, three Chebyshev terms, the running sum
+  double* const A = ws->get<double>(0, pl.total, s);
+  double* const B0 = ws->get<double>(1, pl.total, s);
+  double* const B1 = ws->get<double>(2, pl.total, s);
+  double* const B2 = ws->get<double>(3, pl.total, s);
+  double* const Dacc = ws->get<double>(4, pl.total, s);
   hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, ht.get(), H.width,
                      P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
-                     A.get());
+                     A);
   GB_LAUNCH_CHECK();
   GB_HIP(hipEventRecord(t_stage.b, s));
   GB_HIP(hipStreamSynchronize(s));
   st.ms_gather = elapsed(t_stage.a, t_stage.b);
   gb_sp2_stats tune_st{};
-  choose_tiles<double>(P, pl, A.get(), B2.get(), tiles, offs.get(), s, o.tile_policy, 0, tune_st,
+  choose_tiles<double>(P, pl, A, B2, tiles, offs.get(), s, o.tile_policy, 0, tune_st,
                        xcd);
 
   double t0 = 0;  // t_0 = sum of the core sizes
@@ -2037,17 +2033,17 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   };
   // one pass of the recurrence; with c: the running sum in Dacc
   auto pass = [&](const double* c) {
-    double* tp = B0.get();
-    double* tc = B1.get();
-    double* tn = B2.get();
+    double* tp = B0;
+    double* tc = B1;
+    double* tn = B2;
     hipLaunchKernelGGL(k_fill, dim3(gfill), dim3(kT), 0, s, tp, pl.total, 0.0);
     GB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_set_identity, dim3(pl.n_sub), dim3(kT), 0, s, tp, offs.get(), npad.get(),
                        P.sub_ptr.get());
     GB_LAUNCH_CHECK();
-    GB_HIP(hipMemcpyAsync(tc, A.get(), pl.total * 8, hipMemcpyDeviceToDevice, s));
+    GB_HIP(hipMemcpyAsync(tc, A, pl.total * 8, hipMemcpyDeviceToDevice, s));
     if (c) {
-      hipLaunchKernelGGL(k_axpby, dim3(gfill), dim3(kT), 0, s, Dacc.get(), c[0], tp, c[1], tc,
+      hipLaunchKernelGGL(k_axpby, dim3(gfill), dim3(kT), 0, s, Dacc, c[0], tp, c[1], tc,
                          pl.total);
       GB_LAUNCH_CHECK();
     }
@@ -2055,7 +2051,7 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
     for (int n = 1; n < M; ++n) {
       marks.emplace_back();
       GB_HIP(hipEventRecord(marks.back().a, s));
-      launch_cheb(A.get(), tc, tp, tn, c ? Dacc.get() : nullptr, c ? c[n + 1] : 0.0, pl,
+      launch_cheb(A, tc, tp, tn, c ? Dacc : nullptr, c ? c[n + 1] : 0.0, pl,
                   tiles.get(), offs.get(), s);
       GB_HIP(hipEventRecord(marks.back().b, s));
       record_trace(tn, n + 1);
@@ -2091,7 +2087,7 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   st.coef_tail = std::fabs(c[M]) + std::fabs(c[M - 1]);
 
   GB_HIP(hipEventRecord(t_stage.a, s));
-  hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, Dacc.get(), offs.get(),
+  hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, Dacc, offs.get(),
                      npad.get(), P.sub_ptr.get(), P.sub_idx.get(), P.sub_pos.get(),
                      P.col_sub.get(), P.col_loc.get(), D.width, D.col, D.val);
   GB_LAUNCH_CHECK();

@@ -103,6 +103,10 @@ def test_graph_and_partition_reject_bad_arguments(lib):
     assert lib.gb_spectral_bounds(ctypes.byref(H), None, None, None) == GB_EINVAL
 
 
+def test_trim_without_cached_buffers(lib):
+    assert lib.gb_trim() == 0
+
+
 def test_views_and_allocator_reject_bad_arguments(lib):
     from paper_1603_00937_amd._lib import ALLOC_FN, FREE_FN, GB_EINVAL, GB_OK
     p = ctypes.c_void_p()

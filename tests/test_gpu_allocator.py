@@ -1,6 +1,7 @@
 """The device-memory hook and the device views: with torch's caching allocator registered,
 graph, partition and density give bit-identical results, every library buffer comes from
-the hook, and all of them are returned once the handles are gone."""
+the hook, and all of them are returned once the handles are gone and the cached batch
+buffers are trimmed."""
 import ctypes
 import gc
 
@@ -28,6 +29,7 @@ def test_torch_allocator_bit_identical(model_cache):
     Hv = torch.from_numpy(m["H_val"]).cuda()
     g0, p0, ref, st0 = _run(gb, Hc, Hv, m["n_occ"])
     del g0, p0
+    gb.trim()  # the cached batch buffers come from the hook from now on
     alloc = gb.TorchAllocator()
     gb.set_allocator(alloc)
     try:
@@ -46,6 +48,8 @@ def test_torch_allocator_bit_identical(model_cache):
         assert a.dtype == b.dtype and np.array_equal(a, b)
     del g1, p1
     gc.collect()
+    assert alloc.live != {}  # the cached batch buffers
+    gb.trim()
     torch.cuda.synchronize()
     assert alloc.live == {}
 
