@@ -60,7 +60,9 @@ def square_kernel_name(precision, stats):
     return f"k_symm_mm<{t}, 0, {edge}, 2>"
 
 
-def _largest_grid_counter(db, kernel, counter):
+def _largest_grid_counter(db, prefix, counter):
+    """(kernel, average value) of ``counter`` over the largest-grid dispatches of the kernels
+    whose short name starts with ``prefix`` (None: a device copy)."""
     import sqlite3
     c = sqlite3.connect(db)
     rows = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection"
@@ -69,13 +71,16 @@ def _largest_grid_counter(db, kernel, counter):
     for name, grid, cname, val in rows:
         short = name.replace("gbi::(anonymous namespace)::", "").replace("void ", "", 1)
         short = short.split("(")[0]
-        if cname != counter or (kernel is not None and short != kernel):
+        if cname != counter:
             continue
-        if kernel is None and "copy" not in short.lower():
+        if prefix is None:
+            if "copy" not in short.lower():
+                continue
+        elif not short.startswith(prefix):
             continue
-        per.setdefault(grid, []).append(float(val))
-    g = max(per)
-    return sum(per[g]) / len(per[g])
+        per.setdefault((grid, short), []).append(float(val))
+    key = max(per)
+    return key[1], sum(per[key]) / len(per[key])
 
 
 def traffic_from_pmc(pmc_dir, workload="n18000"):
@@ -83,21 +88,27 @@ def traffic_from_pmc(pmc_dir, workload="n18000"):
     per dispatch, largest-grid dispatches), each scaled by what the same counter reads for a
     device copy of 4 GiB (the --copy-calibration run).  Prints the records for traffic.json."""
     nbytes = 4 << 30
-    sf = nbytes / (_largest_grid_counter(os.path.join(pmc_dir, "copy_fetch", "run_results.db"),
-                                         None, "FETCH_SIZE") * 1024.0)
-    sw = nbytes / (_largest_grid_counter(os.path.join(pmc_dir, "copy_write", "run_results.db"),
-                                         None, "WRITE_SIZE") * 1024.0)
+    _, cf = _largest_grid_counter(os.path.join(pmc_dir, "copy_fetch", "run_results.db"), None,
+                                  "FETCH_SIZE")
+    _, cw = _largest_grid_counter(os.path.join(pmc_dir, "copy_write", "run_results.db"), None,
+                                  "WRITE_SIZE")
+    sf, sw = nbytes / (cf * 1024.0), nbytes / (cw * 1024.0)
     recs = []
-    for tag, kernel in (("bf16x6_pipe", "k_symm_mm_planes3p"),
-                        ("bf16x6_sb", "k_symm_mm_planes<3, 0>"),
-                        ("fp64_auto", "k_symm_mm<double, 0, 64>")):
-        f = os.path.join(pmc_dir, f"{tag}_fetch", "run_results.db")
-        w = os.path.join(pmc_dir, f"{tag}_write", "run_results.db")
+    for tag in sorted(os.listdir(pmc_dir)):
+        if not tag.endswith("_fetch") or tag.startswith("copy"):
+            continue
+        run = tag[:-len("_fetch")]
+        f = os.path.join(pmc_dir, tag, "run_results.db")
+        w = os.path.join(pmc_dir, run + "_write", "run_results.db")
         if not (os.path.exists(f) and os.path.exists(w)):
             continue
-        fb = _largest_grid_counter(f, kernel, "FETCH_SIZE") * 1024.0 * sf
-        wb = _largest_grid_counter(w, kernel, "WRITE_SIZE") * 1024.0 * sw
-        recs.append({"workload": workload, "kernel": kernel, "precision": tag.split("_")[0],
+        prefix = "k_symm_mm_planes" if run.startswith("bf16") else (
+            "k_symm_mm<double, 0," if run.startswith("fp64") else "k_symm_mm<float, 0,")
+        kf, fv = _largest_grid_counter(f, prefix, "FETCH_SIZE")
+        kw, wv = _largest_grid_counter(w, prefix, "WRITE_SIZE")
+        assert kf == kw, (kf, kw)
+        fb, wb = fv * 1024.0 * sf, wv * 1024.0 * sw
+        recs.append({"workload": workload, "kernel": kf, "run": run,
                      "sp2_source_sha256": kernel_source_hash(), "fetch_bytes": fb,
                      "write_bytes": wb, "bytes_per_launch": fb + wb,
                      "copy_scale_fetch": sf, "copy_scale_write": sw})
