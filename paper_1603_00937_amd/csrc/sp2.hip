@@ -270,6 +270,26 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
   const T* xa = A + off;
   const bool do_lin = MODE == 0 && (lin_flag ? *lin_flag == 1 : lin != 0);
   const bool mirror = MODE != 3 && (bi != bj || wr < wc);
+  if constexpr (std::is_same<T, float>::value && MODE == 0) {
+    // FP32 layout: lane l holds rows 4(l/16) .. +3 of column l%16, one contiguous run of the
+    // transposed row, so the mirrored copy (and the symmetric X read of 2X - X^2) moves as one
+    // 16-byte access; row groups of four lie entirely inside or outside npad
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int n = 0; n < MB; ++n) {
+        const int grow0 = bi * BT + wr * WM + m * 16 + 4 * (lane >> 4);
+        const int gcol = bj * BT + wc * WM + n * 16 + r16;
+        if (grow0 >= np || gcol >= np) continue;
+        const int64_t qt = (int64_t)gcol * np + grow0;
+        f4v v = acc[m][n];
+        if (do_lin) v = 2.0f * *reinterpret_cast<const f4v*>(xa + qt) - v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[(int64_t)(grow0 + r) * np + gcol] = v[r];
+        if (mirror) *reinterpret_cast<f4v*>(o + qt) = v;
+      }
+    return;
+  }
 #pragma unroll
   for (int m = 0; m < MB; ++m)
 #pragma unroll
@@ -317,7 +337,11 @@ __device__ __forceinline__ void split_planes(float x, __bf16* out) {
 }
 
 // Epilogue shared by the split-bf16 kernels: the new iterate v = big + small (or 2x - v), its
-// planes, each written at (row, col) and, off the diagonal blocks, at (col, row).
+// planes, each written at (row, col) and, off the diagonal blocks, at (col, row).  Lane l holds
+// rows 4(l/16) .. 4(l/16) + 3 of column l%16 of each 16 x 16 block, so its four values are one
+// contiguous run of the transposed row: the mirrored copy (and the x read by the 2x - v branch,
+// X being symmetric) moves as one 16-byte FP32 access and one 8-byte access per plane.  Rows
+// come in groups of four and npad is a multiple of 64, so a group is entirely inside or outside.
 template <int NP>
 __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4v (&small)[4][4],
                                                 float* __restrict__ S, __bf16* __restrict__ Sp,
@@ -331,27 +355,44 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
+    for (int n = 0; n < 4; ++n) {
+      const int grow0 = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4);
+      const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
+      if (grow0 >= np || gcol >= np) continue;
+      const int64_t qt = (int64_t)gcol * np + grow0;  // (gcol, grow0 .. grow0 + 3)
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = big[m][n][r] + small[m][n][r];
+      if (do_lin) {
+        const f4v xt = *reinterpret_cast<const f4v*>(xa + qt);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = 2.0f * xt[r] - v[r];
+      }
+      __bf16 pl[NP][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int grow = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4) + r;
-        const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
-        if (grow < np && gcol < np) {
-          float v = big[m][n][r] + small[m][n][r];
-          if (do_lin) v = 2.0f * xa[(int64_t)grow * np + gcol] - v;
-          __bf16 pl[NP];
-          split_planes<NP>(v, pl);
-          const int64_t q1 = (int64_t)grow * np + gcol, q2 = (int64_t)gcol * np + grow;
-          o[q1] = v;
+        __bf16 t[NP];
+        split_planes<NP>(v[r], t);
 #pragma unroll
-          for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p];
-          if (mirror) {
-            o[q2] = v;
+        for (int p = 0; p < NP; ++p) pl[p][r] = t[p];
+      }
 #pragma unroll
-            for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q2] = pl[p];
-          }
+      for (int r = 0; r < 4; ++r) {
+        const int64_t q1 = (int64_t)(grow0 + r) * np + gcol;
+        o[q1] = v[r];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p][r];
+      }
+      if (mirror) {
+        *reinterpret_cast<f4v*>(o + qt) = f4v{v[0], v[1], v[2], v[3]};
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          uint2 u;
+          __builtin_memcpy(&u, pl[p], 8);
+          *reinterpret_cast<uint2*>(Sp + p * pstride + off + qt) = u;
         }
       }
+    }
 }
 
 // DB = 1: the LDS holds two chunks (96 KB with three planes, one workgroup per CU) and the
