@@ -183,13 +183,12 @@ def md_run(args):
     computes D and the gradient of Tr[D V].  Prints one JSON line with per-step statistics."""
     import torch
     import paper_1603_00937_amd as gb
-    from synth import make_model, make_operator_v, displace_sites, rebuild_hamiltonian
+    from synth import make_model, operator_v_pairs, displace_sites, rebuild_hamiltonian
     cfg = WORKLOADS[args.workload]
     m = make_model(args.workload)
     rng = np.random.default_rng(52)
     dev = torch.device("cuda:0")
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
-    V = make_operator_v(m["H_col"], 51)
     Hc, Hv = up(m["H_col"]), up(m["H_val"])
     D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], core_size=cfg["core"])
     steps = []
@@ -206,7 +205,11 @@ def md_run(args):
                                       core_size=cfg["core"], keep_tape=True)
         # dL/dD for L = Tr[D V] on D's pattern (V on H's pattern), then the adjoint
         tape = st.pop("tape")
-        Vd = up(V)
+        # V on this step's pattern (the ELL width of H changes as sites move; a pair keeps its
+        # value from step to step)
+        Vd = up(operator_v_pairs(m["H_col"], 51))
+        if Vd.shape != Hc.shape:
+            raise RuntimeError("V must have H's ELL shape")
         # V[i, r] for the entries r of column i of D that lie on row i of H (searchsorted in
         # the ascending ELL row; padding -1 mapped past every column)
         big = np.iinfo(np.int32).max

@@ -9,6 +9,7 @@ from .model import (  # noqa: F401
     ModelSpec,
     make_model,
     make_operator_v,
+    operator_v_pairs,
     displace_sites,
     rebuild_hamiltonian,
     ell_sha256,

@@ -29,7 +29,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 __all__ = [
-    "CONFIGS", "ModelSpec", "make_model", "make_operator_v", "displace_sites",
+    "CONFIGS", "ModelSpec", "make_model", "make_operator_v", "operator_v_pairs", "displace_sites",
     "rebuild_hamiltonian", "ell_sha256", "det_exp",
 ]
 
@@ -264,6 +264,25 @@ def make_operator_v(H_col: np.ndarray, seed: int) -> np.ndarray:
                           dtype=np.int64) if li.size < 200000 else _bulk_find(H_col, lj, li)
     V[li, ls] = V[lj, pos_in_row]
     return V
+
+
+def operator_v_pairs(H_col: np.ndarray, seed: int) -> np.ndarray:
+    """A symmetric operator V on H's pattern whose entry for the orbital pair {i, j} does not
+    depend on the pattern: U(-1, 1) from a SplitMix64 hash of (seed, min(i, j), max(i, j)).  Used
+    where the pattern changes between uses (displacement steps) and V must stay the same."""
+    N, W = H_col.shape
+    rows = np.repeat(np.arange(N, dtype=np.uint64), W).reshape(N, W)
+    cols = np.where(H_col >= 0, H_col, 0).astype(np.uint64)
+    a = np.minimum(rows, cols)
+    b = np.maximum(rows, cols)
+    with np.errstate(over="ignore"):
+        z = (np.uint64(seed) * np.uint64(0x9E3779B97F4A7C15) + a * np.uint64(1 << 32) + b)
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    u = (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)  # [0, 1)
+    return np.where(H_col >= 0, 2.0 * u - 1.0, 0.0)
 
 
 def _bulk_find(H_col, rows, targets):

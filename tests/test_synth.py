@@ -73,3 +73,32 @@ def test_clustered_geometry_small():
     m = make_model(spec)
     assert m["N"] == 6000
     assert m["pos"].min() >= 0.0 and m["pos"].max() < m["L"]
+
+
+def test_operator_v_pairs_is_symmetric_and_pattern_independent():
+    from synth import make_model, operator_v_pairs, displace_sites, rebuild_hamiltonian
+    m = make_model("small256")
+    V = operator_v_pairs(m["H_col"], 51)
+    N, W = m["H_col"].shape
+    val = {}
+    for i in range(N):
+        for t in range(W):
+            j = int(m["H_col"][i, t])
+            if j >= 0:
+                val[(i, j)] = V[i, t]
+                assert -1.0 <= V[i, t] < 1.0
+            else:
+                assert V[i, t] == 0.0
+    for (i, j), v in val.items():
+        assert val[(j, i)] == v
+    rng = np.random.default_rng(52)
+    m2 = rebuild_hamiltonian(m, displace_sites(m["pos"], m["L"], 0.3, rng))
+    V2 = operator_v_pairs(m2["H_col"], 51)
+    same = 0
+    for i in range(N):
+        for t in range(m2["H_col"].shape[1]):
+            j = int(m2["H_col"][i, t])
+            if (i, j) in val:
+                assert V2[i, t] == val[(i, j)]
+                same += 1
+    assert same > 0
