@@ -52,7 +52,9 @@ def square_kernel_name(precision, stats):
     if precision.startswith("bf16"):
         planes = {"bf16": 1, "bf16x3": 2, "bf16x6": 3}[precision]
         v = stats.get("planes_db", 0)
-        return "k_symm_mm_planes3p" if v == 2 else f"k_symm_mm_planes<{planes}, {v}>"
+        if v == 2:
+            return "k_symm_mm_planes3p"
+        return f"k_symm_mm_planes<{planes}, {2 if v == 3 else v}>"
     t = "double" if precision == "fp64" else "float"
     if stats.get("n_stage3", 0) == stats["n_sub"]:
         return f"k_symm_mm<{t}, 0, 64, 3>"
@@ -352,7 +354,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from-pmc", default=None,
                     help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "db", "sb", "pipe"])
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "db", "sb", "pipe", "sbr"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)

@@ -208,7 +208,8 @@ typedef struct {
                               * 2 = 64-edge, 4 = 64-edge with three LDS stages;               *
                               * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
                               * buffered LDS, 2 = single-buffered, 3 = pipelined (three       *
-                              * planes; others as 2).  FP64 / FP32 treat 3 as 0.              */
+                              * planes; others as 2), 4 = single-buffered, register-staged.   *
+                              * FP64 / FP32 treat 3 as 0.                                     */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
 } gb_sp2_opts;
 
@@ -231,7 +232,7 @@ typedef struct {
   int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */
   int32_t n_refine_done;     /* McWeeny steps applied                                        */
   int32_t planes_db;         /* split-bf16 loops: kernel variant (0 single-, 1 double-buffered, *
-                              * 2 pipelined)                                                  */
+                              * 2 pipelined, 3 register-staged)                               */
   int32_t n_stage3;          /* subgraphs squared with the three-stage 64-edge kernel         */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */

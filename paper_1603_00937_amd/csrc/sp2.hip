@@ -22,6 +22,7 @@ namespace gbi {
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
@@ -397,9 +398,11 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
 
 // DB = 1: the LDS holds two chunks (96 KB with three planes, one workgroup per CU) and the
 // next chunk's loads run under the current chunk's products; DB = 0: one chunk (two
-// workgroups per CU), loaded and then consumed.
+// workgroups per CU), loaded and then consumed; DB = 2: one chunk, staged through registers
+// (ordinary 16-byte global loads of the next chunk issued before the current chunk's products,
+// written to LDS after them) instead of the global-to-LDS path.
 template <int NP, int DB>
-__global__ __launch_bounds__(kT, DB ? 1 : 2) void k_symm_mm_planes(const __bf16* __restrict__ Xp,
+__global__ __launch_bounds__(kT, DB == 1 ? 1 : 2) void k_symm_mm_planes(const __bf16* __restrict__ Xp,
                                                           int64_t pstride, float* __restrict__ S,
                                                           __bf16* __restrict__ Sp,
                                                           const int4* __restrict__ tiles,
@@ -412,14 +415,15 @@ __global__ __launch_bounds__(kT, DB ? 1 : 2) void k_symm_mm_planes(const __bf16*
   constexpr int OPB = kBT * 64;
   // [plane][operand][rows of 64 B; piece c of row r at slot c ^ ((r >> 2) & 3), so sixteen
   // lanes reading one piece of sixteen consecutive rows cover all sixteen 16-byte bank groups]
-  __shared__ __align__(1024) unsigned char lds[DB + 1][NP][2][OPB];
+  __shared__ __align__(1024) unsigned char lds[DB == 1 ? 2 : 1][NP][2][OPB];
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;
   const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
   const int64_t off = offs[s];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  // global -> LDS (global_load_lds_dwordx4, two 1-KB wave windows per plane and operand)
+  // global -> LDS (global_load_lds_dwordx4, two 1-KB wave windows per plane and operand; the
+  // register-staged variant writes the same 16 bytes per lane to the same place)
   const __bf16* asrc[2];
   const __bf16* bsrc[2];
 #pragma unroll
@@ -452,16 +456,47 @@ __global__ __launch_bounds__(kT, DB ? 1 : 2) void k_symm_mm_planes(const __bf16*
       load_lds16(asrc[j] + p * pstride + (k0), &lds[b][p][0][(wave * 2 + j) * 1024]);         \
       load_lds16(bsrc[j] + p * pstride + (k0), &lds[b][p][1][(wave * 2 + j) * 1024]);         \
     }
-  if (DB) {
+  // register staging (DB = 2): the first planes of the next chunk are loaded before the
+  // current chunk's products (their registers live across them); the last plane is loaded
+  // after them, which keeps the kernel inside 256 registers
+  constexpr int NPRE = NP > 1 ? NP - 1 : 1;
+  u4v stg[NP][2][2];  // [plane][operand][j]
+#define GB_STAGE(k0, p0, p1)                                                                  \
+  _Pragma("unroll") for (int p = (p0); p < (p1); ++p)                                         \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
+      stg[p][0][j] = *reinterpret_cast<const u4v*>(asrc[j] + p * pstride + (k0));            \
+      stg[p][1][j] = *reinterpret_cast<const u4v*>(bsrc[j] + p * pstride + (k0));            \
+    }
+  if (DB == 1) {
     GB_ISSUE(0, 0)
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
   }
+  if (DB == 2) {
+    GB_STAGE(0, 0, NP)
+  }
   for (int kc = 0; kc < nk; ++kc) {
-    const int buf = DB ? (kc & 1) : 0;
-    if (DB) {
+    const int buf = DB == 1 ? (kc & 1) : 0;
+    if (DB == 1) {
       if (kc + 1 < nk) {
         GB_ISSUE(buf ^ 1, (kc + 1) * KC)
+      }
+    } else if (DB == 2) {
+      if (kc > 0 && NPRE < NP) {
+        GB_STAGE(kc * KC, NPRE, NP)
+      }
+      __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int o = 0; o < 2; ++o)
+            *reinterpret_cast<u4v*>(&lds[0][p][o][(wave * 2 + j) * 1024 + lane * 16]) =
+                stg[p][o][j];
+      __syncthreads();
+      if (kc + 1 < nk) {
+        GB_STAGE((kc + 1) * KC, 0, NPRE)
       }
     } else {
       __syncthreads();  // the previous chunk's reads are done
@@ -522,11 +557,12 @@ __global__ __launch_bounds__(kT, DB ? 1 : 2) void k_symm_mm_planes(const __bf16*
       }
     }
     }  // active
-    if (DB) {
+    if (DB == 1) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();  // chunk kc + 1 has landed and every wave is done with chunk kc
     }
   }
+#undef GB_STAGE
 #undef GB_ISSUE
 #undef GB_FRAG
   if (!active) return;
@@ -1209,7 +1245,10 @@ void launch_planes_np(const __bf16* Xp, const float* X, float* S, __bf16* Sp, in
   if (NP == 3 && db == 2)
     hipLaunchKernelGGL(k_symm_mm_planes3p, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
                        offs, stopped, X, lin, lin_flag);
-  else if (db)
+  else if (db == 3)
+    hipLaunchKernelGGL((k_symm_mm_planes<NP, 2>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
+                       tiles, offs, stopped, X, lin, lin_flag);
+  else if (db == 1)
     hipLaunchKernelGGL((k_symm_mm_planes<NP, 1>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
                        tiles, offs, stopped, X, lin, lin_flag);
   else
@@ -1351,7 +1390,8 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
 }
 
 // Split-bf16 kernel variant: 1 double-buffered LDS (one workgroup per CU), 0 single-buffered
-// (two per CU), 2 pipelined three-plane kernel (two per CU).  Policy 1 / 2 / 3 force 1 / 0 / 2;
+// (two per CU), 2 pipelined three-plane kernel (two per CU), 3 single-buffered with register
+// staging (two per CU).  Policy 1 / 2 / 3 / 4 force 1 / 0 / 2 / 3;
 // policy 0 times one batched launch with each (one warm-up, one timed) the first time a plane
 // count is seen and keeps the fastest for the life of the process.
 int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, const float* X,
@@ -1360,6 +1400,7 @@ int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, c
   if (policy == 1) return 1;
   if (policy == 2) return 0;
   if (policy == 3) return planes == 3 ? 2 : 0;
+  if (policy == 4) return 3;
   const std::pair<int, int> key{20 + planes, 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1370,7 +1411,7 @@ int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, c
   const int nl = (int)pl.launch.size();
   float best = INFINITY;
   int choice = 1;
-  for (int db : {2, 1, 0}) {
+  for (int db : {3, 2, 1, 0}) {
     if (db == 2 && planes != 3) continue;
     launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
     GB_HIP(hipEventRecord(tm.a, s));

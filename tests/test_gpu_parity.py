@@ -187,11 +187,11 @@ def test_launch_modes_agree(gb, model_cache, precision):
 
 @pytest.mark.parametrize("name,core", [("small256", 16), ("n1024", 16)])
 def test_split_bf16_kernel_variants_agree(gb, model_cache, name, core):
-    """The three split-bf16 kernels (single-buffered, double-buffered, pipelined) accumulate
+    """The split-bf16 kernels (single- and double-buffered, pipelined, register-staged) accumulate
     the same products in the same order: bit-identical results, in every launch mode."""
     m = model_cache(name)
     outs = {}
-    for pol in ("sb", "db", "pipe"):
+    for pol in ("sb", "db", "pipe", "sbr"):
         for mode in ("batched", "graph"):
             D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
                                           core_size=core, precision="bf16x6", tile_policy=pol,
@@ -200,6 +200,7 @@ def test_split_bf16_kernel_variants_agree(gb, model_cache, name, core):
                                  st["planes_db"])
     ref = outs[("sb", "batched")]
     assert ref[3] == 0 and outs[("db", "batched")][3] == 1 and outs[("pipe", "batched")][3] == 2
+    assert outs[("sbr", "batched")][3] == 3
     for key, o in outs.items():
         assert o[2] == ref[2], key
         assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), key
