@@ -57,9 +57,11 @@ def square_kernel_name(precision, stats):
         return f"k_symm_mm_planes<{planes}, {2 if v == 3 else v}>"
     t = "double" if precision == "fp64" else "float"
     if stats.get("n_stage3", 0) == stats["n_sub"]:
-        return f"k_symm_mm<{t}, 0, 64, 3>"
+        return f"k_symm_mm<{t}, 0, 64, 3, 0>"
+    if stats.get("n_regstage", 0) == stats["n_sub"]:
+        return f"k_symm_mm<{t}, 0, 64, 2, 1>"
     edge = 64 if stats["n_tile64"] == stats["n_sub"] else 128
-    return f"k_symm_mm<{t}, 0, {edge}, 2>"
+    return f"k_symm_mm<{t}, 0, {edge}, 2, 0>"
 
 
 def _largest_grid_counter(db, prefix, counter):
@@ -354,7 +356,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from-pmc", default=None,
                     help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "db", "sb", "pipe", "sbr"])
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r", "db", "sb", "pipe", "sbr"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)

@@ -205,7 +205,8 @@ typedef struct {
                               *    and replayed (no host round trip per step; no tape)        */
   int32_t tile_policy;       /* FP64 / FP32 squares: kernel variant autotuned per 256-wide    *
                               * size bucket (0, timed once per process), 1 = 128-edge tiles,  *
-                              * 2 = 64-edge, 4 = 64-edge with three LDS stages;               *
+                              * 2 = 64-edge, 4 = 64-edge with three LDS stages, 5 = 64-edge   *
+                              * with register-staged loads;                                   *
                               * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
                               * buffered LDS, 2 = single-buffered, 3 = pipelined (three       *
                               * planes; others as 2), 4 = single-buffered, register-staged.   *
@@ -234,6 +235,7 @@ typedef struct {
   int32_t planes_db;         /* split-bf16 loops: kernel variant (0 single-, 1 double-buffered, *
                               * 2 pipelined, 3 register-staged)                               */
   int32_t n_stage3;          /* subgraphs squared with the three-stage 64-edge kernel         */
+  int32_t n_regstage;        /* subgraphs squared with the register-staged 64-edge kernel     */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
   struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */

@@ -46,6 +46,7 @@ class GbSp2Stats(ctypes.Structure):
                 ("ms_square_lo", ctypes.c_float), ("n_square_lo", ctypes.c_int32),
                 ("n_tile64", ctypes.c_int32), ("n_refine_done", ctypes.c_int32),
                 ("planes_db", ctypes.c_int32), ("n_stage3", ctypes.c_int32),
+                ("n_regstage", ctypes.c_int32),
                 ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double),
                 ("tape", ctypes.c_void_p)]
 

@@ -212,6 +212,7 @@ def _stats_dict(st: L.GbSp2Stats) -> dict:
                 "square", "square_lo")},
         "n_square": st.n_square, "n_square_lo": st.n_square_lo, "n_tile64": st.n_tile64,
         "n_refine_done": st.n_refine_done, "planes_db": st.planes_db, "n_stage3": st.n_stage3,
+        "n_regstage": st.n_regstage,
         "square_flops": st.square_flops,
         "square_flops_exec": st.square_flops_exec,
     }
@@ -285,7 +286,7 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     # split-bf16 variants: "db" double-buffered, "sb" single-buffered, "pipe" pipelined three
     # planes, "sbr" single-buffered with register staging
     o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "db": 1, "sb": 2,
-                     "pipe": 3, "64s3": 4, "sbr": 4}.get(tile_policy, tile_policy)
+                     "pipe": 3, "64s3": 4, "sbr": 4, "64r": 5}.get(tile_policy, tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     st = L.GbSp2Stats()
     _check(_lib().gb_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),
@@ -348,8 +349,8 @@ def foe_density(H_col, H_val, n_occ, threshold, beta, order, mu=None, partition=
     o.core_size = int(core_size)
     if emin is not None and emax is not None:
         o.emin, o.emax = float(emin), float(emax)
-    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4}.get(tile_policy,
-                                                                                   tile_policy)
+    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5}.get(
+        tile_policy, tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     st = L.GbFoeStats()
     _check(_lib().gb_foe_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),

@@ -471,7 +471,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
       fail(GB_EUNSUPPORTED, "keep_tape needs precision GB_FP64");
     if (o.tape_stride < 0) fail(GB_EINVAL, "tape_stride must be >= 0");
     if (o.launch_mode < 0 || o.launch_mode > 2) fail(GB_EINVAL, "unknown launch_mode %d", o.launch_mode);
-    if (o.tile_policy < 0 || o.tile_policy > 4) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
+    if (o.tile_policy < 0 || o.tile_policy > 5) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
     if (o.keep_tape && o.launch_mode == 2)
       fail(GB_EUNSUPPORTED, "keep_tape needs launch_mode 0 or 1");
@@ -598,7 +598,7 @@ gb_status gb_foe_density(const gb_ell* H, int32_t n_occ, double threshold, const
     if (std::isnan(o.mu) && (n_occ < 0 || n_occ > H->n))
       fail(GB_EINVAL, "n_occ = %d outside [0, %d]", n_occ, H->n);
     if (std::isinf(o.mu)) fail(GB_EINVAL, "mu must be finite (or NaN to solve for it)");
-    if (o.tile_policy < 0 || o.tile_policy > 4 || o.tile_policy == 3)
+    if (o.tile_policy < 0 || o.tile_policy > 5 || o.tile_policy == 3)
       fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
     const int core_size = o.core_size > 0 ? o.core_size : 32;

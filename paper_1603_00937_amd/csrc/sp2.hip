@@ -144,7 +144,10 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
 // else X^2.  X is symmetric, so the mirrored entry takes the same value.
 // STAGES = 2: the next chunk loads while the current one is consumed; STAGES = 3: the two next
 // chunks are in flight (one more LDS buffer), for latency the second buffer cannot hide.
-template <typename T, int MODE, int BT = 128, int STAGES = 2>
+// LOADER = 0: chunks go from global memory straight into LDS; LOADER = 1 (two stages): the
+// chunk after next is loaded into registers under the current products and written to LDS
+// once they are done.
+template <typename T, int MODE, int BT = 128, int STAGES = 2, int LOADER = 0>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, const T* __restrict__ B,
                                                    const T* __restrict__ E, T* __restrict__ out,
                                                    T alpha, T beta, const int4* __restrict__ tiles,
@@ -223,18 +226,38 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
     if constexpr (2 * NLD == 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); \
     else asm volatile("s_waitcnt vmcnt(8)" ::: "memory");          \
   } while (0)
-  GB_ISSUE(0, 0)
-  if (STAGES == 3 && nk > 1) {
-    GB_ISSUE(1, KC)
-    GB_WAIT_ALL_BUT_NEWEST();
+  static_assert(LOADER == 0 || STAGES == 2, "register staging uses two LDS buffers");
+  u4v stg[2][NLD];  // LOADER = 1: [operand][j], the 16 bytes this lane moves
+#define GB_STAGE(k0)                                                                        \
+  _Pragma("unroll") for (int j = 0; j < NLD; ++j) {                                         \
+    stg[0][j] = *reinterpret_cast<const u4v*>(asrc[j] + (k0));                             \
+    stg[1][j] = *reinterpret_cast<const u4v*>(bsrc[j] + (k0));                             \
+  }
+#define GB_PUT(buf)                                                                         \
+  _Pragma("unroll") for (int j = 0; j < NLD; ++j) {                                         \
+    *reinterpret_cast<u4v*>(&lds[buf][0][(wave * NLD + j) * 1024 + lane * 16]) = stg[0][j]; \
+    *reinterpret_cast<u4v*>(&lds[buf][1][(wave * NLD + j) * 1024 + lane * 16]) = stg[1][j]; \
+  }
+  if (LOADER == 1) {
+    GB_STAGE(0)
+    GB_PUT(0)
+    if (nk > 1) {
+      GB_STAGE(KC)
+    }
   } else {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    GB_ISSUE(0, 0)
+    if (STAGES == 3 && nk > 1) {
+      GB_ISSUE(1, KC)
+      GB_WAIT_ALL_BUT_NEWEST();
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
   }
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc % STAGES;
     const int ahead = kc + STAGES - 1;  // the chunk issued in this iteration
-    if (ahead < nk) {
+    if (LOADER == 0 && ahead < nk) {
       GB_ISSUE(ahead % STAGES, ahead * KC)
     }
     if (active) {
@@ -257,11 +280,24 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
             for (int n = 0; n < MB; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
       }
     }
-    // chunk kc + 1 must have landed; with three stages chunk kc + 2 may stay in flight
-    if (STAGES == 3 && kc + 2 < nk) GB_WAIT_ALL_BUT_NEWEST();
-    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (LOADER == 1) {
+      // chunk kc + 1 (in registers) into the other buffer, then the chunk after it
+      if (kc + 1 < nk) {
+        GB_PUT(buf ^ 1)
+      }
+      if (kc + 2 < nk) {
+        GB_STAGE((kc + 2) * KC)
+      }
+    } else if (STAGES == 3 && kc + 2 < nk) {
+      // chunk kc + 1 must have landed; with three stages chunk kc + 2 may stay in flight
+      GB_WAIT_ALL_BUT_NEWEST();
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
     __syncthreads();
   }
+#undef GB_PUT
+#undef GB_STAGE
 #undef GB_WAIT_ALL_BUT_NEWEST
 #undef GB_ISSUE
 
@@ -1066,14 +1102,20 @@ int grid_for(int64_t n, int t, int cap = 1 << 20) {
 // Square tiles are listed 128-edge tiles first, then 64-edge tiles; within each group the
 // largest blocks come first (most k work per tile).
 // Kernel variants of the batched products, one code per subgraph: 128 (128-edge tiles, two LDS
-// stages), 64 (64-edge, two stages), 63 (64-edge, three stages).
-constexpr int kVariants[3] = {128, 64, 63};
+// stages), 64 (64-edge, two stages), 63 (64-edge, three stages), 62 (64-edge, two stages,
+// register-staged loads).
+constexpr int kNVar = 4;
+constexpr int kVariants[kNVar] = {128, 64, 63, 62};
 inline int variant_edge(int code) { return code == 128 ? 128 : 64; }
+inline int variant_index(int code) {
+  for (int v = 0; v < kNVar; ++v)
+    if (kVariants[v] == code) return v;
+  return -1;
+}
 
-// tiles per variant group (launch order: 128, 64, 63)
+// tiles per variant group (launch order as kVariants)
 struct Groups {
-  int n[3] = {0, 0, 0};
-  int total() const { return n[0] + n[1] + n[2]; }
+  int n[kNVar] = {0, 0, 0, 0};
 };
 
 struct Plan {
@@ -1140,8 +1182,8 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
   }
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return pl.npad[a] > pl.npad[b]; });
-  size_t r_first[4] = {0, 0, 0, 0};
-  for (int v = 0; v < 3; ++v) {
+  size_t r_first[kNVar + 1] = {};
+  for (int v = 0; v < kNVar; ++v) {
     const int code = kVariants[v], edge = variant_edge(code);
     const int t0 = (int)pl.tiles.size();
     r_first[v] = pl.ranges.size();
@@ -1159,10 +1201,10 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
     }
     pl.tg.n[v] = (int)pl.tiles.size() - t0;
   }
-  r_first[3] = pl.ranges.size();
+  r_first[kNVar] = pl.ranges.size();
   // launch list of the batched squaring: each group in XCD order (or as listed)
   if (xcd) {
-    for (int v = 0; v < 3; ++v) {
+    for (int v = 0; v < kNVar; ++v) {
       const size_t before = pl.launch.size();
       xcd_order(pl.launch, pl.tiles, pl.ranges, r_first[v], r_first[v + 1]);
       pl.lg.n[v] = (int)(pl.launch.size() - before);
@@ -1218,6 +1260,10 @@ void launch_symm(const T* A, const T* B, const T* E, T* out, T alpha, T beta, co
   if (g.n[2] > 0)
     hipLaunchKernelGGL((k_symm_mm<T, MODE, 64, 3>), dim3(g.n[2]), dim3(kT), 0, s, A, B, E, out,
                        alpha, beta, t, offs, stopped, lin, lin_flag, dacc, cn);
+  t += g.n[2];
+  if (g.n[3] > 0)
+    hipLaunchKernelGGL((k_symm_mm<T, MODE, 64, 2, 1>), dim3(g.n[3]), dim3(kT), 0, s, A, B, E,
+                       out, alpha, beta, t, offs, stopped, lin, lin_flag, dacc, cn);
   GB_LAUNCH_CHECK();
 }
 
@@ -1233,7 +1279,7 @@ void launch_square(const T* X, T* S, const int4* tiles, const Groups& g, const i
 // a single group (the idempotency check's 128-edge tiles, one subgraph's range)
 inline Groups one_group(int code, int count) {
   Groups g;
-  g.n[code == 128 ? 0 : (code == 64 ? 1 : 2)] = count;
+  g.n[variant_index(code)] = count;
   return g;
 }
 
@@ -1376,15 +1422,18 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   std::vector<int> bt(pl.n_sub, kBT);
   if (policy == 2) bt.assign(pl.n_sub, 64);
   else if (policy == 4) bt.assign(pl.n_sub, 63);
+  else if (policy == 5) bt.assign(pl.n_sub, 62);
   else if (policy == 0 || policy == 3) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd);
   if (policy == 1) return;
   pl = make_plan(P, &bt, xcd);
   tiles = upload_tiles(pl, s);
   st.n_tile64 = 0;
   st.n_stage3 = 0;
+  st.n_regstage = 0;
   for (int e : bt) {
     st.n_tile64 += e != 128;
     st.n_stage3 += e == 63;
+    st.n_regstage += e == 62;
   }
   st.square_flops_exec = pl.flops_exec;
 }

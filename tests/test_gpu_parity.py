@@ -224,13 +224,15 @@ def test_tile_edges_agree(gb, model_cache, precision, refine):
     depends on the tile edge, so that path agrees only to rounding.)"""
     m = model_cache("small256")
     outs = []
-    for pol in ("128", "64", "auto", "64s3"):
+    for pol in ("128", "64", "auto", "64s3", "64r"):
         D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
                                       core_size=16, precision=precision, tile_policy=pol,
                                       refine=refine)
         outs.append((D_val.cpu().numpy(), st["branch"], st["n_tile64"], st["n_refine_done"]))
         if pol == "64s3":
             assert st["n_stage3"] == st["n_sub"]
+        if pol == "64r":
+            assert st["n_regstage"] == st["n_sub"]
     assert outs[0][2] == 0 and outs[1][2] > 0
     for q, o in enumerate(outs[1:]):
         diff = np.abs(o[0] - outs[0][0]).max()
