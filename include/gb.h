@@ -297,6 +297,8 @@ typedef struct {
   double emin, emax;         /* spectral bounds; both 0 = Gershgorin                           */
   int32_t tile_policy;       /* as in gb_sp2_opts (FP64 tile edge)                             */
   int32_t tile_order;        /* as in gb_sp2_opts                                              */
+  double* traces;            /* (host) NULL, or order + 1 doubles receiving the summed core    *
+                              * traces t_n (reuse them with gb_foe_solve_mu for other n_occ)  */
 } gb_foe_opts;
 
 typedef struct {

@@ -58,7 +58,8 @@ class GbFoeOpts(ctypes.Structure):
                 ("order", ctypes.c_int32), ("n_nodes", ctypes.c_int32),
                 ("partition", ctypes.c_void_p), ("core_size", ctypes.c_int32),
                 ("emin", ctypes.c_double), ("emax", ctypes.c_double),
-                ("tile_policy", ctypes.c_int32), ("tile_order", ctypes.c_int32)]
+                ("tile_policy", ctypes.c_int32), ("tile_order", ctypes.c_int32),
+                ("traces", ctypes.c_void_p)]
 
 
 class GbFoeStats(ctypes.Structure):

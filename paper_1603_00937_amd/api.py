@@ -352,10 +352,13 @@ def foe_density(H_col, H_val, n_occ, threshold, beta, order, mu=None, partition=
     o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5}.get(
         tile_policy, tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
+    tr = (ctypes.c_double * (int(order) + 1))()
+    o.traces = ctypes.cast(tr, ctypes.c_void_p)
     st = L.GbFoeStats()
     _check(_lib().gb_foe_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),
                                  ctypes.byref(De), ctypes.byref(st), _stream()))
     out = {f: getattr(st, f) for f, _ in L.GbFoeStats._fields_}
+    out["traces"] = list(tr)
     return D_col, D_val, out
 
 

@@ -2216,6 +2216,7 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   for (int n = 0; n <= M; ++n) tr += c[n] * traces[n];
   st.trace = tr;
   st.coef_tail = std::fabs(c[M]) + std::fabs(c[M - 1]);
+  if (o.traces) std::memcpy(o.traces, traces.data(), (M + 1) * sizeof(double));
 
   GB_HIP(hipEventRecord(t_stage.a, s));
   hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, Dacc, offs.get(),

@@ -129,3 +129,23 @@ def test_n18000_sampled_subgraphs(gb, model_cache):
           f"({st['product_flops'] / ms / 1e9:.1f} TF algorithmic) total {st['ms_total']:.0f} ms")
     assert err <= 1e-10
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,core,beta,order", [("small256", 16, 5.0, 300),
+                                                  ("n1024", 512, 5.0, 300)])
+def test_high_order_solved_mu(gb, model_cache, name, core, beta, order):
+    """The benchmark's order and temperature: the recorded traces, the solved mu and D."""
+    from oracle.foe import foe_partitioned
+    m = model_cache(name)
+    cols, info = foe_partitioned(m["H_col"], m["H_val"], 1e-5, core, beta, order,
+                                 n_occ=m["n_occ"])
+    D_col, D_val, st = gb.foe_density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      beta, order, core_size=core)
+    tr_err = float(np.abs(np.array(st["traces"]) - info["traces"]).max())
+    err = _compare(D_col, D_val, cols, m["N"])
+    print(f"{name} M={order}: mu={st['mu']!r} oracle={info['mu']!r} traces {tr_err:.2e} "
+          f"err={err:.3e} trace={st['trace']!r}")
+    assert tr_err < 1e-8
+    assert abs(st["mu"] - info["mu"]) < 1e-9
+    assert abs(st["trace"] - m["n_occ"]) < 1e-7
+    assert err <= 1e-9
