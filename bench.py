@@ -54,6 +54,8 @@ def square_kernel_name(precision, stats):
         v = stats.get("planes_db", 0)
         if v == 2:
             return "k_symm_mm_planes3p"
+        if v == 5:
+            return f"k_symm_mm_split<{planes}>"
         return f"k_symm_mm_planes<{planes}, {2 if v == 3 else v}>"
     t = "double" if precision == "fp64" else "float"
     if stats.get("n_stage3", 0) == stats["n_sub"]:
@@ -356,7 +358,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from-pmc", default=None,
                     help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r", "db", "sb", "pipe", "sbr"])
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r", "db", "sb", "pipe", "sbr",
+                             "split"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
     ap.add_argument("--n-fp64-first", type=int, default=0)

@@ -209,8 +209,9 @@ typedef struct {
                               * with register-staged loads;                                   *
                               * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
                               * buffered LDS, 2 = single-buffered, 3 = pipelined (three       *
-                              * planes; others as 2), 4 = single-buffered, register-staged.   *
-                              * FP64 / FP32 treat 3 as 0.                                     */
+                              * planes; others as 2), 4 = single-buffered, register-staged,   *
+                              * 5 = split into planes in registers from the FP32 iterate (no  *
+                              * stored planes).  FP64 / FP32 treat 3 as 0.                    */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
 } gb_sp2_opts;
 
@@ -233,7 +234,7 @@ typedef struct {
   int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */
   int32_t n_refine_done;     /* McWeeny steps applied                                        */
   int32_t planes_db;         /* split-bf16 loops: kernel variant (0 single-, 1 double-buffered, *
-                              * 2 pipelined, 3 register-staged)                               */
+                              * 2 pipelined, 3 register-staged, 5 split in registers)          */
   int32_t n_stage3;          /* subgraphs squared with the three-stage 64-edge kernel         */
   int32_t n_regstage;        /* subgraphs squared with the register-staged 64-edge kernel     */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */

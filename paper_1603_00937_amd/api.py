@@ -284,9 +284,10 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     o.launch_mode = {"batched": 0, "per_subgraph": 1, "graph": 2}.get(launch_mode, launch_mode)
     # "db" / "sb": the split-bf16 kernel variant (double- / single-buffered LDS)
     # split-bf16 variants: "db" double-buffered, "sb" single-buffered, "pipe" pipelined three
-    # planes, "sbr" single-buffered with register staging
+    # planes, "sbr" single-buffered with register staging, "split" planes formed in registers
     o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "db": 1, "sb": 2,
-                     "pipe": 3, "64s3": 4, "sbr": 4, "64r": 5}.get(tile_policy, tile_policy)
+                     "pipe": 3, "64s3": 4, "sbr": 4, "64r": 5, "split": 5}.get(tile_policy,
+                                                                           tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     st = L.GbSp2Stats()
     _check(_lib().gb_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),

@@ -379,7 +379,7 @@ __device__ __forceinline__ void split_planes(float x, __bf16* out) {
 // contiguous run of the transposed row: the mirrored copy (and the x read by the 2x - v branch,
 // X being symmetric) moves as one 16-byte FP32 access and one 8-byte access per plane.  Rows
 // come in groups of four and npad is a multiple of 64, so a group is entirely inside or outside.
-template <int NP>
+template <int NP, bool WRITE_PLANES = true>
 __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4v (&small)[4][4],
                                                 float* __restrict__ S, __bf16* __restrict__ Sp,
                                                 const float* __restrict__ X, int64_t pstride,
@@ -406,27 +406,33 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
         for (int r = 0; r < 4; ++r) v[r] = 2.0f * xt[r] - v[r];
       }
       __bf16 pl[NP][4];
+      if (WRITE_PLANES) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        __bf16 t[NP];
-        split_planes<NP>(v[r], t);
+        for (int r = 0; r < 4; ++r) {
+          __bf16 t[NP];
+          split_planes<NP>(v[r], t);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) pl[p][r] = t[p];
+          for (int p = 0; p < NP; ++p) pl[p][r] = t[p];
+        }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t q1 = (int64_t)(grow0 + r) * np + gcol;
         o[q1] = v[r];
+        if (WRITE_PLANES) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p][r];
+          for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p][r];
+        }
       }
       if (mirror) {
         *reinterpret_cast<f4v*>(o + qt) = f4v{v[0], v[1], v[2], v[3]};
+        if (WRITE_PLANES) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          uint2 u;
-          __builtin_memcpy(&u, pl[p], 8);
-          *reinterpret_cast<uint2*>(Sp + p * pstride + off + qt) = u;
+          for (int p = 0; p < NP; ++p) {
+            uint2 u;
+            __builtin_memcpy(&u, pl[p], 8);
+            *reinterpret_cast<uint2*>(Sp + p * pstride + off + qt) = u;
+          }
         }
       }
     }
@@ -729,6 +735,146 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_planes3p(const __bf16* __rest
   if (!active) return;
   planes_epilogue<3>(big, small, S, Sp, X, pstride, off, np, bi, bj, wr, wc, lane,
                      lin_flag ? *lin_flag == 1 : lin != 0);
+}
+
+// Split in registers: the FP32 iterate itself is read (4 bytes per element instead of 2 NP
+// for stored planes) and each lane splits the 16 bytes it loads into the NP bf16 planes while
+// staging them into the same swizzled LDS layout; the epilogue then writes only the FP32
+// result.  Same products in the same order as the kernels above, so the same results.  The
+// next chunk is loaded into registers under the current chunk's products.
+template <int NP>
+__global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict__ X,
+                                                        float* __restrict__ S,
+                                                        const int4* __restrict__ tiles,
+                                                        const int64_t* __restrict__ offs,
+                                                        const int32_t* __restrict__ stopped,
+                                                        int lin,
+                                                        const int32_t* __restrict__ lin_flag) {
+  if (stopped && *stopped) return;
+  constexpr int KC = 32;
+  constexpr int OPB = kBT * 64;
+  __shared__ __align__(1024) unsigned char lds[NP][2][OPB];
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;
+  const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
+  const int64_t off = offs[s];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  // staging: thread t moves FP32 piece c8 = t % 8 (k = 4 c8 .. 4 c8 + 3) of rows
+  // t / 8 + 32 q (q = 0..3) of each operand; eight threads cover one row's 128 bytes
+  const int c8 = tid & 7, r0 = tid >> 3;
+  const float* asrc[4];
+  const float* bsrc[4];
+  int ldo[4];  // byte offset of the 8-byte run in a plane's operand array
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + 32 * q;
+    const int ar = bi * kBT + r, br = bj * kBT + r;
+    asrc[q] = X + off + (int64_t)(ar < np ? ar : 0) * np + 4 * c8;
+    bsrc[q] = X + off + (int64_t)(br < np ? br : 0) * np + 4 * c8;
+    ldo[q] = r * 64 + (((c8 >> 1) ^ ((r >> 2) & 3)) << 4) + (c8 & 1) * 8;
+  }
+  f4v big[4][4], small[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      big[m][n] = f4v{0, 0, 0, 0};
+      small[m][n] = f4v{0, 0, 0, 0};
+    }
+  const int g = lane >> 4, r16 = lane & 15;
+  const int nk = np / KC;
+  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
+  const bool active = in_range && !(bi == bj && wr > wc);
+  const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
+  const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
+  f4v stg[2][4];  // [operand][q]
+#define GB_STAGE(k0)                                                                          \
+  _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
+    stg[0][q] = *reinterpret_cast<const f4v*>(asrc[q] + (k0));                                \
+    stg[1][q] = *reinterpret_cast<const f4v*>(bsrc[q] + (k0));                                \
+  }
+#define GB_FRAG(dst, plane, opnd, base, m) \
+  __builtin_memcpy(&(dst), &lds[plane][opnd][(base) + (m) * 16 * 64 + pc], 16)
+  GB_STAGE(0)
+  for (int kc = 0; kc < nk; ++kc) {
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        __bf16 pl[NP][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          __bf16 t[NP];
+          split_planes<NP>(stg[o][q][e], t);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) pl[p][e] = t[p];
+        }
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          uint2 u;
+          __builtin_memcpy(&u, pl[p], 8);
+          *reinterpret_cast<uint2*>(&lds[p][o][ldo[q]]) = u;
+        }
+      }
+    __syncthreads();
+    if (kc + 1 < nk) {
+      GB_STAGE((kc + 1) * KC)
+    }
+    if (active) {
+      bf8v A0[4], B0[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        GB_FRAG(A0[m], 0, 0, pa0, m);
+        GB_FRAG(B0[m], 0, 1, pb0, m);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) big[m][n] = mma_bf16(A0[m], B0[n], big[m][n]);
+      if (NP >= 2) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          bf8v BL;
+          GB_FRAG(BL, NP - 1, 1, pb0, m);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) small[r][m] = mma_bf16(A0[r], BL, small[r][m]);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          bf8v AL;
+          GB_FRAG(AL, NP - 1, 0, pa0, m);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(AL, B0[n], small[m][n]);
+        }
+      }
+      if (NP >= 3) {
+        bf8v BM[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) GB_FRAG(BM[m], 1, 1, pb0, m);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(A0[m], BM[n], small[m][n]);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          bf8v AM;
+          GB_FRAG(AM, 1, 0, pa0, m);
+#pragma unroll
+          for (int n = 0; n < 4; ++n) {
+            small[m][n] = mma_bf16(AM, B0[n], small[m][n]);
+            small[m][n] = mma_bf16(AM, BM[n], small[m][n]);
+          }
+        }
+      }
+    }
+  }
+#undef GB_FRAG
+#undef GB_STAGE
+  if (!active) return;
+  planes_epilogue<NP, false>(big, small, S, nullptr, X, 0, off, np, bi, bj, wr, wc, lane,
+                             lin_flag ? *lin_flag == 1 : lin != 0);
 }
 
 // planes of an FP32 batch buffer (after the gather)
@@ -1294,6 +1440,9 @@ void launch_planes_np(const __bf16* Xp, const float* X, float* S, __bf16* Sp, in
   else if (db == 3)
     hipLaunchKernelGGL((k_symm_mm_planes<NP, 2>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
                        tiles, offs, stopped, X, lin, lin_flag);
+  else if (db == 5)
+    hipLaunchKernelGGL(k_symm_mm_split<NP>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
+                       stopped, lin, lin_flag);
   else if (db == 1)
     hipLaunchKernelGGL((k_symm_mm_planes<NP, 1>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
                        tiles, offs, stopped, X, lin, lin_flag);
@@ -1440,27 +1589,33 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
 
 // Split-bf16 kernel variant: 1 double-buffered LDS (one workgroup per CU), 0 single-buffered
 // (two per CU), 2 pipelined three-plane kernel (two per CU), 3 single-buffered with register
-// staging (two per CU).  Policy 1 / 2 / 3 / 4 force 1 / 0 / 2 / 3;
+// staging (two per CU), 5 split in registers from the FP32 iterate (no stored planes).
+// Policy 1 / 2 / 3 / 4 / 5 force 1 / 0 / 2 / 3 / 5;
 // policy 0 times one batched launch with each (one warm-up, one timed) the first time a plane
 // count is seen and keeps the fastest for the life of the process.
-int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, const float* X,
-                          float* S, __bf16* Sp, const int64_t* offs, hipStream_t s, int planes,
-                          int policy) {
+// The variant a policy forces, or the one the tuner already chose for this plane count (-1:
+// not tuned yet).
+int known_planes_variant(int planes, int policy) {
   if (policy == 1) return 1;
   if (policy == 2) return 0;
   if (policy == 3) return planes == 3 ? 2 : 0;
   if (policy == 4) return 3;
-  const std::pair<int, int> key{20 + planes, 0};
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(key);
-    if (it != g_tune.end()) return it->second;
-  }
+  if (policy == 5) return 5;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({20 + planes, 0});
+  return it != g_tune.end() ? it->second : -1;
+}
+
+int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, const float* X,
+                          float* S, __bf16* Sp, const int64_t* offs, hipStream_t s, int planes,
+                          int policy) {
+  const int known = known_planes_variant(planes, policy);
+  if (known >= 0) return known;
   Timer tm;
   const int nl = (int)pl.launch.size();
   float best = INFINITY;
-  int choice = 1;
-  for (int db : {3, 2, 1, 0}) {
+  int choice = 0;
+  for (int db : {5, 3, 2, 1, 0}) {
     if (db == 2 && planes != 3) continue;
     launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
     GB_HIP(hipEventRecord(tm.a, s));
@@ -1474,7 +1629,7 @@ int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, c
     }
   }
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[key] = choice;
+  g_tune[{20 + planes, 0}] = choice;
   return choice;
 }
 
@@ -1749,14 +1904,22 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     }
     if (!done) {
       if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
-      // split-bf16: planes of X and of X^2 (NP bf16 arrays of the batch size each)
-      __bf16* xp = planes > 0 ? ws->get<__bf16>(5, (size_t)planes * pl.total, s) : nullptr;
-      __bf16* sp = planes > 0 ? ws->get<__bf16>(6, (size_t)planes * pl.total, s) : nullptr;
+      // split-bf16: the stored planes of X and S (NP bf16 arrays of the batch size each) are
+      // needed only by the variants that read planes (and by the first tuning)
+      __bf16* xp = nullptr;
+      __bf16* sp = nullptr;
       if (planes > 0) {
-        make_planes(xf, xp, pl.total, s, planes);
-        pl.planes_db = choose_planes_variant(pl, tiles.get(), xp, xf, sf, sp, offs.get(), s,
-                                             planes, o.tile_policy);
+        const int known = known_planes_variant(planes, o.tile_policy);
+        if (known != 5) {
+          xp = ws->get<__bf16>(5, (size_t)planes * pl.total, s);
+          sp = ws->get<__bf16>(6, (size_t)planes * pl.total, s);
+          make_planes(xf, xp, pl.total, s, planes);
+        }
+        pl.planes_db = known >= 0 ? known
+                                  : choose_planes_variant(pl, tiles.get(), xp, xf, sf, sp,
+                                                          offs.get(), s, planes, o.tile_policy);
         st.planes_db = pl.planes_db;
+        if (pl.planes_db != 5 && !xp) fail(GB_EHIP, "plane buffers missing");
       }
       // The low-precision loop runs until its own rounding floor (the stagnation stop) unless
       // the traces already agree to 1e-7 per 1024 orbitals, so that one FP64 McWeeny step

@@ -191,7 +191,7 @@ def test_split_bf16_kernel_variants_agree(gb, model_cache, name, core):
     the same products in the same order: bit-identical results, in every launch mode."""
     m = model_cache(name)
     outs = {}
-    for pol in ("sb", "db", "pipe", "sbr"):
+    for pol in ("sb", "db", "pipe", "sbr", "split"):
         for mode in ("batched", "graph"):
             D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
                                           core_size=core, precision="bf16x6", tile_policy=pol,
@@ -200,7 +200,7 @@ def test_split_bf16_kernel_variants_agree(gb, model_cache, name, core):
                                  st["planes_db"])
     ref = outs[("sb", "batched")]
     assert ref[3] == 0 and outs[("db", "batched")][3] == 1 and outs[("pipe", "batched")][3] == 2
-    assert outs[("sbr", "batched")][3] == 3
+    assert outs[("sbr", "batched")][3] == 3 and outs[("split", "batched")][3] == 5
     for key, o in outs.items():
         assert o[2] == ref[2], key
         assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), key
