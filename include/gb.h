@@ -280,7 +280,8 @@ void gb_tape_destroy(gb_tape_t* tape);
  * the terms built by the recurrence of Eq. 5 and evaluated per subgraph as in Eq. 6):
  *   D = [exp(beta (H - mu)) + 1]^-1 ~ sum_{n=0..order} c_n T_n(Ht),
  *   Ht = (2H - (e_max + e_min) I)/(e_max - e_min),  T_0 = I, T_1 = Ht,
- *   T_{n+1} = 2 Ht T_n - T_{n-1}  (one batched FP64 product per term over every subgraph),
+ *   T_{n+1} = 2 Ht T_n - T_{n-1}, formed as Ht T_n + (Ht T_n)^T - T_{n-1} (one batched FP64
+ *   general product per term over every subgraph, then an explicit symmetrisation),
  * c_n by K-node Chebyshev-Gauss quadrature (gb_chebyshev_fermi).  Graph and partition as for
  * gb_density (X2 graph at `threshold` + block cores of core_size unless a partition is given).
  * With mu = NaN the chemical potential is chosen so that the summed core traces
@@ -296,7 +297,8 @@ typedef struct {
   const gb_partition_t* partition; /* NULL: build X2(threshold) + BLOCK(core_size) inside      */
   int32_t core_size;         /* used when partition == NULL; default 32                       */
   double emin, emax;         /* spectral bounds; both 0 = Gershgorin                           */
-  int32_t tile_policy;       /* as in gb_sp2_opts (FP64 tile edge)                             */
+  int32_t tile_policy;       /* accepted for symmetry with gb_sp2_opts; the general product    *
+                              * always uses 128-edge tiles                                     */
   int32_t tile_order;        /* as in gb_sp2_opts                                              */
   double* traces;            /* (host) NULL, or order + 1 doubles receiving the summed core    *
                               * traces t_n (reuse them with gb_foe_solve_mu for other n_occ)  */
@@ -311,7 +313,7 @@ typedef struct {
   float ms_bounds, ms_graph, ms_part, ms_gather, ms_terms, ms_scatter, ms_total;
   float ms_product;          /* summed device time of the product launches                    */
   int32_t n_product;         /* number of product launches                                     */
-  double product_flops;      /* algorithmic flops of one product launch: sum_s 2 n_s^3        */
+  double product_flops;      /* flops of one product launch: sum_s 2 n_s^3                    */
 } gb_foe_stats;
 
 gb_status gb_foe_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_foe_opts* opts,

@@ -1275,6 +1275,7 @@ struct Plan {
   std::vector<int4> launch;      // the same tiles as launched in one batch, each variant group
   Groups lg;                     //   in XCD order
   std::vector<int4> tiles_full;  // every (bi, bj) with edge 128 (general products)
+  std::vector<int4> full_launch; // the same in XCD order (the launch list of general products)
   std::vector<int4> ranges;      // per subgraph: first tile, tile count, variant code, s
   std::vector<int4> idem;        // 128-edge upper tiles covering the core rows (final check)
   int planes_db = 1;             // split-bf16 kernel variant
@@ -1359,16 +1360,22 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
     pl.launch = pl.tiles;
     pl.lg = pl.tg;
   }
+  std::vector<int4> full_ranges;
   for (int s : order) {
     const int np = pl.npad[s];
     const int nb = (np + kBT - 1) / kBT;
     const int k = P.h_core_ptr[s + 1] - P.h_core_ptr[s];
+    const int first = (int)pl.tiles_full.size();
     for (int bi = 0; bi < nb; ++bi)
       for (int bj = 0; bj < nb; ++bj) {
         pl.tiles_full.push_back(make_int4(s, bi, bj, np));
         if (bj >= bi && bi * kBT < k) pl.idem.push_back(make_int4(s, bi, bj, np));
       }
+    full_ranges.push_back(make_int4(first, (int)pl.tiles_full.size() - first, 128, s));
   }
+  // the general-product tiles in XCD order (queues padded with empty entries) or as listed
+  if (xcd) xcd_order(pl.full_launch, pl.tiles_full, full_ranges, 0, full_ranges.size());
+  else pl.full_launch = pl.tiles_full;
   return pl;
 }
 
@@ -1965,9 +1972,9 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       t->tiles = DBuf<int4>(pl.launch.size(), nullptr);
       GB_HIP(hipMemcpyAsync(t->tiles.get(), pl.launch.data(), pl.launch.size() * sizeof(int4),
                             hipMemcpyHostToDevice, s));
-      t->tiles_full = DBuf<int4>(pl.tiles_full.size(), nullptr);
-      GB_HIP(hipMemcpyAsync(t->tiles_full.get(), pl.tiles_full.data(),
-                            pl.tiles_full.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+      t->tiles_full = DBuf<int4>(pl.full_launch.size(), nullptr);
+      GB_HIP(hipMemcpyAsync(t->tiles_full.get(), pl.full_launch.data(),
+                            pl.full_launch.size() * sizeof(int4), hipMemcpyHostToDevice, s));
       dup_i32(t->core_ptr, P.core_ptr, P.n_sub + 1);
       dup_i32(t->sub_ptr, P.sub_ptr, P.n_sub + 1);
       dup_i32(t->sub_idx, P.sub_idx, P.total);
@@ -2108,7 +2115,7 @@ void density_vjp(TapeData& t, const gb_ell& G_D, const gb_ell& H, double* G_H, h
   for (int q = 1; q < c; ++q) seg.emplace_back(pl.total, s);
   const int max_nt = pl.max_npad / 32;
   const dim3 cgrid(max_nt * max_nt, pl.n_sub);
-  const int ntf = (int)pl.tiles_full.size();
+  const int ntf = (int)pl.full_launch.size();
   for (int m = (K - 1) / c; m >= 0 && K > 0; --m) {
     const int start = m * c, end = std::min(start + c, K);
     std::vector<double*> xs;
@@ -2204,15 +2211,48 @@ __global__ __launch_bounds__(kT) void k_trace_total(const double* __restrict__ p
   if (threadIdx.x == 0) *out = t1;
 }
 
-// T_next = 2 A T_cur - T_prev on every upper tile (A and T_cur commute, so the product is
-// symmetric), and with dacc: dacc += cn T_next
+// Tn = P + P^T - Tp on 32 x 32 tile pairs (P^T through LDS), and with dacc: dacc += cn Tn
+__global__ __launch_bounds__(256) void k_cheb_combine(const double* __restrict__ P,
+                                                      const double* __restrict__ Tp,
+                                                      double* __restrict__ Tn,
+                                                      double* __restrict__ dacc, double cn,
+                                                      const int64_t* __restrict__ offs,
+                                                      const int32_t* __restrict__ npad,
+                                                      int max_nt) {
+  __shared__ double t[32][33];
+  const int s = blockIdx.y;
+  const int np = npad[s], nt = np / 32;
+  const int bx = blockIdx.x % max_nt, by = blockIdx.x / max_nt;
+  if (bx >= nt || by >= nt) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t off = offs[s];
+  const double* p = P + off;
+  for (int r = ty; r < 32; r += 8) t[r][tx] = p[(int64_t)(bx * 32 + r) * np + by * 32 + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t q = off + (int64_t)(by * 32 + r) * np + bx * 32 + tx;
+    const double v = (P[q] + t[tx][r]) - Tp[q];
+    Tn[q] = v;
+    if (dacc) dacc[q] += cn * v;
+  }
+}
+
+// One Chebyshev term, T_next = Ht T_cur + (Ht T_cur)^T - T_prev (= 2 Ht T_cur - T_prev, since
+// T_cur is a polynomial in Ht), with dacc += cn T_next.  The product is formed on every tile
+// and symmetrised explicitly: taking one triangle of Ht T_cur and mirroring it would turn the
+// rounding part of the commutator [Ht, T_cur] into a symmetric error that the recurrence
+// amplifies (the traces run away after about 200 terms).
 void launch_cheb(const double* A, const double* Tc, const double* Tp, double* Tn, double* dacc,
-                 double cn, const Plan& pl, const int4* tiles, const int64_t* offs, hipStream_t s) {
-  if (dacc)
-    launch_symm<double, 4>(A, Tc, Tp, Tn, 2.0, -1.0, tiles, pl.lg, offs, s, nullptr, 0, nullptr,
-                           dacc, cn);
-  else
-    launch_symm<double, 1>(A, Tc, Tp, Tn, 2.0, -1.0, tiles, pl.lg, offs, s);
+                 double cn, double* P, const Plan& pl, const int4* tiles_full,
+                 const int64_t* offs, const int32_t* npad, hipStream_t s) {
+  const int ntf = (int)pl.full_launch.size();
+  hipLaunchKernelGGL((k_symm_mm<double, 3>), dim3(ntf), dim3(kT), 0, s, A, Tc, Tc, P, 1.0, 0.0,
+                     tiles_full, offs, nullptr, 0, nullptr, (double*)nullptr, 0.0);
+  GB_LAUNCH_CHECK();
+  const int max_nt = pl.max_npad / 32;
+  hipLaunchKernelGGL(k_cheb_combine, dim3(max_nt * max_nt, pl.n_sub), dim3(256), 0, s, P, Tp, Tn,
+                     dacc, cn, offs, npad, max_nt);
+  GB_LAUNCH_CHECK();
 }
 
 int quad_nodes(int order, int n_nodes) { return n_nodes > 0 ? n_nodes : std::max(4 * (order + 1), 1024); }
@@ -2301,6 +2341,7 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   double* const B1 = ws->get<double>(2, pl.total, s);
   double* const B2 = ws->get<double>(3, pl.total, s);
   double* const Dacc = ws->get<double>(4, pl.total, s);
+  double* const Pm = ws->get<double>(5, pl.total, s);  // the full product Ht T_n
   hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, ht.get(), H.width,
                      P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
                      A);
@@ -2308,9 +2349,9 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   GB_HIP(hipEventRecord(t_stage.b, s));
   GB_HIP(hipStreamSynchronize(s));
   st.ms_gather = elapsed(t_stage.a, t_stage.b);
-  gb_sp2_stats tune_st{};
-  choose_tiles<double>(P, pl, A, B2, tiles, offs.get(), s, o.tile_policy, 0, tune_st,
-                       xcd);
+  DBuf<int4> tiles_full(pl.full_launch.size(), s);
+  GB_HIP(hipMemcpyAsync(tiles_full.get(), pl.full_launch.data(),
+                        pl.full_launch.size() * sizeof(int4), hipMemcpyHostToDevice, s));
 
   double t0 = 0;  // t_0 = sum of the core sizes
   for (int q = 0; q < P.n_sub; ++q) t0 += P.h_core_ptr[q + 1] - P.h_core_ptr[q];
@@ -2345,8 +2386,8 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
     for (int n = 1; n < M; ++n) {
       marks.emplace_back();
       GB_HIP(hipEventRecord(marks.back().a, s));
-      launch_cheb(A, tc, tp, tn, c ? Dacc : nullptr, c ? c[n + 1] : 0.0, pl,
-                  tiles.get(), offs.get(), s);
+      launch_cheb(A, tc, tp, tn, c ? Dacc : nullptr, c ? c[n + 1] : 0.0, Pm, pl,
+                  tiles_full.get(), offs.get(), npad.get(), s);
       GB_HIP(hipEventRecord(marks.back().b, s));
       record_trace(tn, n + 1);
       double* r = tp;
