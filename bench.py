@@ -199,6 +199,7 @@ def md_run(args):
     D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], core_size=cfg["core"])
     steps = []
     pos = m["pos"]
+    prev_branch = st["branch"]
     for t in range(args.md_steps):
         pos = displace_sites(pos, m["L"], 0.02, rng)
         m = rebuild_hamiltonian(m, pos)
@@ -207,8 +208,19 @@ def md_run(args):
         t0 = time.perf_counter()
         g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
         p = gb.partition(g, cfg["core"])
+        # pre-determined sequence (MD section): replay the previous step's branches; fall back
+        # to the trace-driven rule if the replay ends short of the stop test
+        replayed = args.md_sequence == "replay" and prev_branch is not None
         D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
-                                      core_size=cfg["core"], keep_tape=True)
+                                      core_size=cfg["core"], keep_tape=True,
+                                      branch_in=prev_branch if replayed else None)
+        fallback = False
+        if replayed and not st["converged"]:
+            st.pop("tape")
+            D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
+                                          core_size=cfg["core"], keep_tape=True)
+            fallback = True
+        prev_branch = st["branch"]
         # dL/dD for L = Tr[D V] on D's pattern (V on H's pattern), then the adjoint
         tape = st.pop("tape")
         # V on this step's pattern (the ELL width of H changes as sites move; a pair keeps its
@@ -230,7 +242,8 @@ def md_run(args):
         dt = time.perf_counter() - t0
         sizes = np.diff(p.arrays()[1].cpu().numpy())
         steps.append({"step": t + 1, "ms": dt * 1e3, "iters": st["iters"],
-                      "converged": st["converged"], "graph_nnz": g.nnz,
+                      "converged": st["converged"], "replayed": replayed,
+                      "fallback": fallback, "graph_nnz": g.nnz,
                       "sub_min": int(sizes.min()), "sub_mean": float(sizes.mean()),
                       "sub_max": int(sizes.max()), "trace_DV": L,
                       "grad_norm": float(G_H.norm())})
@@ -366,6 +379,8 @@ def main():
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--rocpd-counters", default=None,
                     help="summarise the counters of a rocprofv3 --pmc database")
+    ap.add_argument("--md-sequence", default="trace", choices=["trace", "replay"],
+                    help="MD: choose each branch from the traces, or replay the previous step's")
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run the adaptive-graph displacement loop instead of the benchmark")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
