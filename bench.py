@@ -199,7 +199,7 @@ def md_run(args):
     D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], core_size=cfg["core"])
     steps = []
     pos = m["pos"]
-    prev_branch = st["branch"]
+    prev_branch = st["branch"] + [0, 1]
     for t in range(args.md_steps):
         pos = displace_sites(pos, m["L"], 0.02, rng)
         m = rebuild_hamiltonian(m, pos)
@@ -208,8 +208,9 @@ def md_run(args):
         t0 = time.perf_counter()
         g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
         p = gb.partition(g, cfg["core"])
-        # pre-determined sequence (MD section): replay the previous step's branches; fall back
-        # to the trace-driven rule if the replay ends short of the stop test
+        # pre-determined sequence (MD section): replay the previous step's branches plus one
+        # X^2 / 2X - X^2 pair as a margin; fall back to the trace-driven rule if the replay ends
+        # short of the stop test
         replayed = args.md_sequence == "replay" and prev_branch is not None
         D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
                                       core_size=cfg["core"], keep_tape=True,
@@ -220,7 +221,8 @@ def md_run(args):
             D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
                                           core_size=cfg["core"], keep_tape=True)
             fallback = True
-        prev_branch = st["branch"]
+        prev_branch = (st["branch"][:st["iters"]] if not replayed or fallback
+                       else prev_branch[:-2]) + [0, 1]
         # dL/dD for L = Tr[D V] on D's pattern (V on H's pattern), then the adjoint
         tape = st.pop("tape")
         # V on this step's pattern (the ELL width of H changes as sites move; a pair keeps its

@@ -39,7 +39,8 @@ def test_three_md_steps_match_oracle():
 
 def test_md_with_the_previous_sequence_replayed():
     """The MD section's pre-determined sequence: each step replays the branch sequence the
-    previous step chose (no trace exchange during the expansion).  The replay converges, matches
+    previous step chose, with one X^2 / 2X - X^2 pair appended as a margin (no trace exchange
+    during the expansion; the pair leaves a converged X unchanged).  The replay converges, matches
     the oracle's replay of the same sequence, and agrees with the trace-driven D of the same
     step to the accuracy of the stop rule."""
     import torch
@@ -52,7 +53,7 @@ def test_md_with_the_previous_sequence_replayed():
     rng = np.random.default_rng(52)
     tau, tau_d, core = 1e-5, 1e-4, 16
     D_col, D_val, st = gb.density(dev(m["H_col"]), dev(m["H_val"]), m["n_occ"], tau, core_size=core)
-    seq = st["branch"]
+    seq = st["branch"] + [0, 1]
     oc, ov = D_col.cpu().numpy(), D_val.cpu().numpy()
     pos = m["pos"]
     for step in range(3):
@@ -72,4 +73,4 @@ def test_md_with_the_previous_sequence_replayed():
         _, tv, tst = gb.density(dev(m["H_col"]), dev(m["H_val"]), m["n_occ"], tau, partition=p)
         assert np.abs(D_val.cpu().numpy() - tv.cpu().numpy()).max() <= 1e-7
         oc, ov = D_col.cpu().numpy(), D_val.cpu().numpy()
-        seq = st["branch"]
+        seq = tst["branch"] + [0, 1]
