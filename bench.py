@@ -68,7 +68,7 @@ def square_kernel_name(precision, stats):
 
 def _largest_grid_counter(db, prefix, counter):
     """(kernel, average value) of ``counter`` over the largest-grid dispatches of the kernels
-    whose short name starts with ``prefix`` (None: a device copy)."""
+    whose short name starts with one of ``prefix`` (None: a device copy)."""
     import sqlite3
     c = sqlite3.connect(db)
     rows = c.execute("select kernel_name, grid_size, counter_name, value from counters_collection"
@@ -82,7 +82,7 @@ def _largest_grid_counter(db, prefix, counter):
         if prefix is None:
             if "copy" not in short.lower():
                 continue
-        elif not short.startswith(prefix):
+        elif not short.startswith(tuple(prefix)):
             continue
         per.setdefault((grid, short), []).append(float(val))
     key = max(per)
@@ -108,8 +108,8 @@ def traffic_from_pmc(pmc_dir, workload="n18000"):
         w = os.path.join(pmc_dir, run + "_write", "run_results.db")
         if not (os.path.exists(f) and os.path.exists(w)):
             continue
-        prefix = "k_symm_mm_planes" if run.startswith("bf16") else (
-            "k_symm_mm<double, 0," if run.startswith("fp64") else "k_symm_mm<float, 0,")
+        prefix = ("k_symm_mm_split", "k_symm_mm_planes") if run.startswith("bf16") else (
+            ("k_symm_mm<double, 0,",) if run.startswith("fp64") else ("k_symm_mm<float, 0,",))
         kf, fv = _largest_grid_counter(f, prefix, "FETCH_SIZE")
         kw, wv = _largest_grid_counter(w, prefix, "WRITE_SIZE")
         assert kf == kw, (kf, kw)
