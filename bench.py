@@ -297,7 +297,7 @@ def foe_run(args):
                    "n_sub": st["n_sub"], "max_sub": st["max_sub"]},
         "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["fp64"],
                      "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["fp64"] if ach else None,
-                     "traffic": None, "kernel": "k_symm_mm MODE 4 (2 Ht T_n - T_{n-1}, D += c T)",
+                     "traffic": None, "kernel": "k_symm_mm MODE 3 (Ht T_n) + k_cheb_combine",
                      "flops_per_launch_alg": st["product_flops"],
                      "avg_launch_ms": avg * 1e3 if avg else None},
         "result": {"mu": st["mu"], "trace": st["trace"], "coef_tail": st["coef_tail"]},
@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true",
                     help="skip the FP64 GPU measurement reported beside a mixed-precision run")
-    ap.add_argument("--cpu-sample", type=int, default=12)
+    ap.add_argument("--cpu-sample", type=int, default=96)
     args = ap.parse_args()
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
