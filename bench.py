@@ -208,20 +208,32 @@ def md_run(args):
         t0 = time.perf_counter()
         g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
         p = gb.partition(g, cfg["core"])
-        # pre-determined sequence (MD section): replay the previous step's branches plus one
-        # X^2 / 2X - X^2 pair as a margin; fall back to the trace-driven rule if the replay ends
-        # short of the stop test
-        replayed = args.md_sequence == "replay" and prev_branch is not None
+        # pre-determined sequence (MD section), no trace rule during the expansion: "replay"
+        # repeats the previous step's branches plus one X^2 / 2X - X^2 pair as a margin; "gap"
+        # builds the sequence from the HOMO/LUMO bracket estimated from the previous step's
+        # traces (bounds narrowed by 5 % of their width).  Either falls back to the trace-driven
+        # rule if the replay ends short of the stop test.
+        seq = None
+        if args.md_sequence == "replay":
+            seq = prev_branch
+        elif args.md_sequence == "gap":
+            try:
+                est = gb.sp2_estimate_gap(**gb.gap_inputs(st, m["n_occ"]))
+                hb, lb = est["homo_bound"], est["lumo_bound"]
+                lo, hi = gb.spectral_bounds(Hc, Hv)
+                seq = gb.sp2_sequence(lo, hi, hb + 0.05 * (lb - hb), lb - 0.05 * (lb - hb))
+            except gb.GbError:
+                seq = None
+        replayed = seq is not None
         D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
-                                      core_size=cfg["core"], keep_tape=True,
-                                      branch_in=prev_branch if replayed else None)
+                                      core_size=cfg["core"], keep_tape=True, branch_in=seq)
         fallback = False
         if replayed and not st["converged"]:
             st.pop("tape")
             D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p,
                                           core_size=cfg["core"], keep_tape=True)
             fallback = True
-        prev_branch = (st["branch"][:st["iters"]] if not replayed or fallback
+        prev_branch = (st["branch"][:st["iters"]] if args.md_sequence != "replay" or fallback
                        else prev_branch[:-2]) + [0, 1]
         # dL/dD for L = Tr[D V] on D's pattern (V on H's pattern), then the adjoint
         tape = st.pop("tape")
@@ -245,7 +257,8 @@ def md_run(args):
         sizes = np.diff(p.arrays()[1].cpu().numpy())
         steps.append({"step": t + 1, "ms": dt * 1e3, "iters": st["iters"],
                       "converged": st["converged"], "replayed": replayed,
-                      "fallback": fallback, "graph_nnz": g.nnz,
+                      "fallback": fallback, "seq_len": len(seq) if replayed else None,
+                      "graph_nnz": g.nnz,
                       "sub_min": int(sizes.min()), "sub_mean": float(sizes.mean()),
                       "sub_max": int(sizes.max()), "trace_DV": L,
                       "grad_norm": float(G_H.norm())})
@@ -381,8 +394,9 @@ def main():
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--rocpd-counters", default=None,
                     help="summarise the counters of a rocprofv3 --pmc database")
-    ap.add_argument("--md-sequence", default="trace", choices=["trace", "replay"],
-                    help="MD: choose each branch from the traces, or replay the previous step's")
+    ap.add_argument("--md-sequence", default="trace", choices=["trace", "replay", "gap"],
+                    help="MD: choose each branch from the traces, replay the previous step's "
+                         "sequence, or build it from the gap estimated from its traces")
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run the adaptive-graph displacement loop instead of the benchmark")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))

@@ -343,6 +343,35 @@ gb_status gb_foe_solve_mu(const double* traces, int32_t order, double emin, doub
 gb_status gb_sp2_sequence(double emin, double emax, double e_homo, double e_lumo, double delta,
                           int32_t max_len, uint8_t* out, int32_t* len);
 
+/* Host: HOMO/LUMO estimates from the core traces of an SP2 expansion (MD section: the next
+ * step's sequence comes from the gap estimated during the previous step, after Rubensson and
+ * Niklasson's interior-eigenvalue estimates).  Uses only the traces the trace rule computes:
+ * t1[i] = Tr X_i and t2[i] = Tr X_i^2 for i = 0 .. n_branch (gb_sp2_stats.t1 / t2 with
+ * n_branch = iters), branch[i] the update after iterate i.  With A = t1 - t2, B = t1 - n_occ,
+ * L = (A + B)/2 and U = (A - B)/2 are, to fourth order, the sums over the unoccupied
+ * eigenvalues of g(x) = x - x^2/2 (right after a step 2X - X^2) and over the occupied ones of
+ * g(1 - x) (right after a step X^2).  From the latest such iterate whose sum exceeds `floor`:
+ * the bound g^-1(L + U^2/2) is at least the LUMO image, so lumo_bound <= e_lumo (and likewise
+ * homo_bound >= e_homo); from the latest pair of such iterates with a squaring of that side
+ * between them, the ratio of their sums solved for one level by bisection gives lumo_ratio
+ * >= e_lumo and homo_ratio <= e_homo.  Images are mapped back to X0 through the inverse branch
+ * maps, which shrinks their relative error at every square root.  The bracket holds to fourth
+ * order in the distances and to the rounding of the traces; a sequence from the bounds
+ * (gb_sp2_sequence) is long enough for the spectrum the traces came from.
+ * floor <= 0 takes max(100 (|t1 - n_occ| + |t1 - t2|) at the last iterate, 1e-12 n_occ).
+ * GB_EINVAL for NULL pointers, n_branch < 1, emax <= emin, a branch other than 0/1, or when a
+ * side has no usable iterate above the floor (an expansion that did not converge). */
+typedef struct {
+  double homo_bound, lumo_bound;   /* homo_bound >= e_homo, lumo_bound <= e_lumo              */
+  double homo_ratio, lumo_ratio;   /* homo_ratio <= e_homo, lumo_ratio >= e_lumo              */
+  double floor;                    /* the noise floor used                                     */
+  int32_t homo_iter[3], lumo_iter[3];  /* iterates used: bound, ratio pair (i, j)            */
+} gb_gap_estimate;
+
+gb_status gb_sp2_estimate_gap(const double* t1, const double* t2, const uint8_t* branch,
+                              int32_t n_branch, double n_occ, double emin, double emax,
+                              double floor, gb_gap_estimate* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,13 @@ class GbFoeStats(ctypes.Structure):
                 ("n_product", ctypes.c_int32), ("product_flops", ctypes.c_double)]
 
 
+class GbGapEstimate(ctypes.Structure):
+    _fields_ = [("homo_bound", ctypes.c_double), ("lumo_bound", ctypes.c_double),
+                ("homo_ratio", ctypes.c_double), ("lumo_ratio", ctypes.c_double),
+                ("floor", ctypes.c_double), ("homo_iter", ctypes.c_int32 * 3),
+                ("lumo_iter", ctypes.c_int32 * 3)]
+
+
 # gb_alloc_fn / gb_free_fn
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
@@ -113,6 +120,10 @@ SIGNATURES = {
     "gb_sp2_sequence": (ctypes.c_int32, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                          _P(ctypes.c_uint8), _P(ctypes.c_int32)]),
+    "gb_sp2_estimate_gap": (ctypes.c_int32, [_P(ctypes.c_double), _P(ctypes.c_double),
+                                             _P(ctypes.c_uint8), ctypes.c_int32, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                             _P(GbGapEstimate)]),
     "gb_foe_solve_mu": (ctypes.c_int32, [_P(ctypes.c_double), ctypes.c_int32, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int32, _P(ctypes.c_double)]),

@@ -315,6 +315,32 @@ def sp2_sequence(emin, emax, e_homo, e_lumo, delta=1e-12, max_len=127):
     return [int(out[i]) for i in range(n.value)]
 
 
+def sp2_estimate_gap(t1, t2, branch, n_occ, emin, emax, floor=0.0):
+    """Host: HOMO/LUMO bracket from an SP2 expansion's core traces (t1, t2: one more entry than
+    branch).  From a density() stats dict: ``sp2_estimate_gap(**gap_inputs(st, n_occ))``.  Returns a
+    dict: homo_bound >= e_homo, lumo_bound <= e_lumo, homo_ratio <= e_homo, lumo_ratio >= e_lumo,
+    floor, homo_iter, lumo_iter."""
+    nb = len(branch)
+    if len(t1) < nb + 1 or len(t2) < nb + 1:
+        raise ValueError("t1 and t2 need len(branch) + 1 entries")
+    a1 = (ctypes.c_double * (nb + 1))(*[float(x) for x in t1[:nb + 1]])
+    a2 = (ctypes.c_double * (nb + 1))(*[float(x) for x in t2[:nb + 1]])
+    b = (ctypes.c_uint8 * max(nb, 1))(*[int(x) for x in branch])
+    r = L.GbGapEstimate()
+    _check(_lib().gb_sp2_estimate_gap(a1, a2, b, nb, float(n_occ), float(emin), float(emax),
+                                      float(floor), ctypes.byref(r)))
+    return {"homo_bound": r.homo_bound, "lumo_bound": r.lumo_bound,
+            "homo_ratio": r.homo_ratio, "lumo_ratio": r.lumo_ratio, "floor": r.floor,
+            "homo_iter": tuple(r.homo_iter), "lumo_iter": tuple(r.lumo_iter)}
+
+
+def gap_inputs(st, n_occ):
+    """The arguments of sp2_estimate_gap from a density() stats dict."""
+    k = st["iters"]
+    return {"t1": st["t1"][:k + 1], "t2": st["t2"][:k + 1], "branch": st["branch"][:k],
+            "n_occ": n_occ, "emin": st["emin"], "emax": st["emax"]}
+
+
 def foe_solve_mu(traces, emin, emax, beta, n_occ, n_nodes=0):
     """Host: mu with sum_n c_n(mu) traces[n] = n_occ."""
     t = (ctypes.c_double * len(traces))(*[float(x) for x in traces])

@@ -568,6 +568,120 @@ gb_status gb_sp2_sequence(double emin, double emax, double e_homo, double e_lumo
   });
 }
 
+namespace {
+
+// Distance of an eigenvalue image from its target (side 0: the unoccupied side, distance from 0;
+// side 1: the occupied side, distance from 1) taken through branches b[0..n).  Branch `side`
+// squares the distance; the other takes d to 2d - d^2.
+double gap_forward(double d, const uint8_t* b, int n, int side) {
+  for (int k = 0; k < n; ++k) d = (int)b[k] == side ? d * d : 2.0 * d - d * d;
+  return d;
+}
+
+// The inverse: a distance at step k mapped back through b[k-1], ..., b[0] to step 0.
+double gap_back(double d, const uint8_t* b, int k, int side) {
+  for (int q = k - 1; q >= 0; --q)
+    d = (int)b[q] == side ? std::sqrt(d) : d / (1.0 + std::sqrt(1.0 - d));
+  return d;
+}
+
+double gap_g(double x) { return x - 0.5 * x * x; }
+
+// x in (0, 1) with g(F(x)) = rho g(x), F the branch maps b[0..n) (bisection to the last
+// representable midpoint; g(F(x))/g(x) rises through (0, 1) on an initial interval of x and
+// stays >= 1 beyond it).
+double gap_solve_ratio(double rho, const uint8_t* b, int n, int side) {
+  double lo = 0.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (gap_g(gap_forward(mid, b, n, side)) - rho * gap_g(mid) < 0.0) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+gb_status gb_sp2_estimate_gap(const double* t1, const double* t2, const uint8_t* branch,
+                              int32_t n_branch, double n_occ, double emin, double emax,
+                              double floor, gb_gap_estimate* out) {
+  return guarded([&] {
+    if (!t1 || !t2 || !branch || !out) fail(GB_EINVAL, "t1 / t2 / branch / out is NULL");
+    if (n_branch < 1) fail(GB_EINVAL, "n_branch = %d must be >= 1", n_branch);
+    if (!(emax > emin)) fail(GB_EINVAL, "need emax > emin");
+    for (int i = 0; i < n_branch; ++i)
+      if (branch[i] > 1) fail(GB_EINVAL, "branch[%d] = %d is not 0 or 1", i, (int)branch[i]);
+    const int nb = n_branch;
+    if (!(floor > 0.0))
+      floor = std::max(100.0 * (std::fabs(t1[nb] - n_occ) + std::fabs(t1[nb] - t2[nb])),
+                       1e-12 * n_occ);
+    // per-iterate sums of the distances: side 0 (unoccupied) L = (A + B)/2, side 1 (occupied)
+    // U = (A - B)/2, A = t1 - t2, B = t1 - n_occ
+    std::vector<double> S[2];
+    for (int i = 0; i <= nb; ++i) {
+      const double A = t1[i] - t2[i], B = t1[i] - n_occ;
+      S[0].push_back(0.5 * (A + B));
+      S[1].push_back(0.5 * (A - B));
+    }
+    const double w = emax - emin;
+    gb_gap_estimate r;
+    std::memset(&r, 0, sizeof(r));
+    r.floor = floor;
+    for (int side = 0; side < 2; ++side) {
+      const std::vector<double>& own = S[side];
+      const std::vector<double>& oth = S[1 - side];
+      // clean iterates of this side: right after a branch that does not square it
+      std::vector<int> clean;
+      for (int i = 1; i <= nb; ++i)
+        if ((int)branch[i - 1] != side) clean.push_back(i);
+      int ib = -1;
+      for (int i : clean) {
+        const double val = own[i] + 0.5 * oth[i] * oth[i];
+        if (own[i] > floor && val < 0.5) ib = i;
+      }
+      if (ib < 0)
+        fail(GB_EINVAL, "no clean iterate of the %s side above the noise floor %g",
+             side ? "occupied" : "unoccupied", floor);
+      const double val = own[ib] + 0.5 * oth[ib] * oth[ib];
+      const double d_bound = gap_back(2.0 * val / (1.0 + std::sqrt(1.0 - 2.0 * val)), branch, ib,
+                                      side);
+      int pi = -1, pj = -1;
+      for (size_t a = 0; a < clean.size(); ++a) {
+        const int i = clean[a];
+        for (size_t c = a + 1; c < clean.size(); ++c) {
+          const int j = clean[c];
+          bool squares = false;
+          for (int q = i; q < j; ++q) squares |= (int)branch[q] == side;
+          if (!squares) continue;
+          if (own[j] > floor && own[i] > own[j]) {
+            pi = i;
+            pj = j;
+          }
+          break;
+        }
+      }
+      if (pi < 0)
+        fail(GB_EINVAL, "no pair of clean iterates of the %s side above the noise floor %g",
+             side ? "occupied" : "unoccupied", floor);
+      const double d_ratio =
+          gap_back(gap_solve_ratio(own[pj] / own[pi], branch + pi, pj - pi, side), branch, pi, side);
+      int32_t* it = side ? r.homo_iter : r.lumo_iter;
+      it[0] = ib;
+      it[1] = pi;
+      it[2] = pj;
+      if (side == 0) {
+        r.lumo_bound = emax - d_bound * w;
+        r.lumo_ratio = emax - d_ratio * w;
+      } else {
+        r.homo_bound = emax - (1.0 - d_bound) * w;
+        r.homo_ratio = emax - (1.0 - d_ratio) * w;
+      }
+    }
+    *out = r;
+  });
+}
+
 gb_status gb_foe_solve_mu(const double* traces, int32_t order, double emin, double emax,
                           double beta, double n_occ, int32_t n_nodes, double* mu) {
   return guarded([&] {

@@ -136,7 +136,8 @@ def test_struct_layout_matches_header(tmp_path):
     if shutil.which("gcc") is None:
         pytest.skip("no host C compiler")
     fields = {"gb_sp2_opts": L.GbSp2Opts, "gb_sp2_stats": L.GbSp2Stats, "gb_ell": L.GbEll,
-              "gb_foe_opts": L.GbFoeOpts, "gb_foe_stats": L.GbFoeStats}
+              "gb_foe_opts": L.GbFoeOpts, "gb_foe_stats": L.GbFoeStats,
+              "gb_gap_estimate": L.GbGapEstimate}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
     for cname, py in fields.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
@@ -210,3 +211,68 @@ def test_sp2_sequence_matches_oracle(lib):
         gb.sp2_sequence(0.0, 1.0, 0.6, 0.4)
     with pytest.raises(gb.GbError):
         gb.sp2_sequence(-8.6, 8.7, -1.2, 0.48, max_len=3)
+
+
+def _dense_expansion(name):
+    from synth import make_model
+    from oracle.bounds import ell_to_dense, gershgorin
+    from oracle.sp2 import sp2_partitioned
+    m = make_model(name)
+    H = ell_to_dense(m["H_col"], m["H_val"])
+    lo, hi = gershgorin(m["H_col"], m["H_val"])
+    X0 = (hi * np.eye(len(H)) - H) / (hi - lo)
+    _, info = sp2_partitioned([X0], [len(H)], m["n_occ"], 1e-10 * len(H) / 1024)
+    return info["traces"], info["branch"], m["n_occ"], lo, hi
+
+
+def _diag_expansion(levels, n_occ):
+    from oracle.sp2 import sp2_partitioned
+    h = np.array(list(levels) + [-2.0, 2.0])
+    _, info = sp2_partitioned([np.diag((2.0 - h) / 4.0)], [len(h)], n_occ + 1, 1e-14)
+    return info["traces"], info["branch"], n_occ + 1, -2.0, 2.0
+
+
+def test_sp2_estimate_gap_matches_oracle(lib):
+    """Host entry point against the oracle's estimator on the same traces."""
+    from oracle.sequence import estimate_gap
+    import paper_1603_00937_amd as gb
+    cases = [_dense_expansion("tiny48"), _dense_expansion("small256"),
+             _diag_expansion([-0.7, 0.4], 1), _diag_expansion([-0.05] * 4 + [0.3], 4)]
+    for tr, br, n, lo, hi in cases:
+        for floor in (0.0, 1e-3):
+            args = ([t[0] for t in tr], [t[1] for t in tr], br, n, lo, hi, floor)
+            try:
+                ref = estimate_gap(tr, br, n, lo, hi, floor=floor or None)
+            except ValueError:
+                with pytest.raises(gb.GbError):     # both sides find no usable iterate
+                    gb.sp2_estimate_gap(*args)
+                continue
+            got = gb.sp2_estimate_gap(*args)
+            for k in ("homo_bound", "lumo_bound", "homo_ratio", "lumo_ratio", "floor"):
+                assert abs(got[k] - ref[k]) <= 1e-12 * (hi - lo), k
+            assert got["homo_iter"] == ref["homo_iterates"]
+            assert got["lumo_iter"] == ref["lumo_iterates"]
+
+
+def test_sp2_estimate_gap_rejects_bad_arguments(lib):
+    import paper_1603_00937_amd as gb
+    from paper_1603_00937_amd._lib import GbGapEstimate, GB_EINVAL
+    tr, br, n, lo, hi = _diag_expansion([-0.7, 0.4], 1)
+    t1 = [t[0] for t in tr]
+    t2 = [t[1] for t in tr]
+    with pytest.raises(gb.GbError):          # floor above every sum
+        gb.sp2_estimate_gap(t1, t2, br, n, lo, hi, 1.0)
+    with pytest.raises(gb.GbError):          # no usable iterate after one step
+        gb.sp2_estimate_gap(t1[:2], t2[:2], br[:1], n, lo, hi)
+    with pytest.raises(gb.GbError):
+        gb.sp2_estimate_gap(t1, t2, br, n, hi, lo)
+    with pytest.raises(gb.GbError):
+        gb.sp2_estimate_gap(t1, t2, [2] + list(br[1:]), n, lo, hi)
+    with pytest.raises(ValueError):
+        gb.sp2_estimate_gap(t1[:3], t2[:3], br, n, lo, hi)
+    a = (ctypes.c_double * 4)()
+    b = (ctypes.c_uint8 * 3)()
+    r = GbGapEstimate()
+    assert lib.gb_sp2_estimate_gap(None, a, b, 3, 1.0, 0.0, 1.0, 0.0, ctypes.byref(r)) == GB_EINVAL
+    assert lib.gb_sp2_estimate_gap(a, a, b, 0, 1.0, 0.0, 1.0, 0.0, ctypes.byref(r)) == GB_EINVAL
+    assert lib.gb_sp2_estimate_gap(a, a, b, 3, 1.0, 0.0, 1.0, 0.0, None) == GB_EINVAL
