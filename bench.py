@@ -389,7 +389,7 @@ def main():
     ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r", "db", "sb", "pipe", "sbr",
                              "split"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
-    ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2"])
+    ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2", "mcweeny_blocks"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--rocpd-counters", default=None,

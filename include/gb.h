@@ -183,10 +183,14 @@ typedef struct {
   int32_t precision;         /* gb_precision; default GB_FP64                                */
   int32_t n_refine;          /* low precision: at most this many FP64 refinement steps       *
                               * (0 = 8 McWeeny steps / 16 SP2 steps)                          */
-  int32_t refine_kind;       /* low precision: 0 = McWeeny X <- 3X^2 - 2X^3 until the FP64    *
-                              * stop test holds; 1 = FP64 SP2 steps until it holds, the first *
-                              * by the trace rule, then alternating X^2 / 2X - X^2 (replayed  *
-                              * from branch_in when that extends past the low-precision loop) */
+  int32_t refine_kind;       /* low precision: 0 = McWeeny X <- 3X^2 - 2X^3 on the core rows  *
+                              * that D keeps (one or two steps, p or p(p), by products of the *
+                              * k core rows with X; 2 n^2 k flops each), accepted if the FP64 *
+                              * stop test holds on them, else as 2;                           *
+                              * 1 = FP64 SP2 steps until it holds, the first by the trace     *
+                              * rule, then alternating X^2 / 2X - X^2 (replayed from          *
+                              * branch_in when that extends past the low-precision loop);     *
+                              * 2 = McWeeny steps on whole blocks until the stop test holds   */
   int32_t n_fp64_first;      /* low precision: run the first SP2 steps in FP64 (default 0)   */
   int32_t max_iter;          /* default 100 when 0                                           */
   double idem_tol;           /* stop when |Tr X - Tr X^2| <= idem_tol; 0 = 1e-10 * n / 1024   */

@@ -266,7 +266,7 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     o = L.GbSp2Opts()
     o.precision = L.PRECISIONS[precision]
     o.n_refine = int(n_refine)
-    o.refine_kind = {"mcweeny": 0, "sp2": 1}[refine]
+    o.refine_kind = {"mcweeny": 0, "sp2": 1, "mcweeny_blocks": 2}[refine]
     o.n_fp64_first = int(n_fp64_first)
     o.max_iter = int(max_iter)
     o.idem_tol = float(idem_tol)

@@ -459,7 +459,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (o.precision < GB_FP64 || o.precision > GB_BF16X6_REFINE)
       fail(GB_EINVAL, "unknown precision %d", o.precision);
     if (o.max_iter < 0 || o.n_refine < 0) fail(GB_EINVAL, "max_iter / n_refine must be >= 0");
-    if (o.refine_kind < 0 || o.refine_kind > 1) fail(GB_EINVAL, "unknown refine_kind %d", o.refine_kind);
+    if (o.refine_kind < 0 || o.refine_kind > 2) fail(GB_EINVAL, "unknown refine_kind %d", o.refine_kind);
     if (!(o.idem_tol >= 0.0)) fail(GB_EINVAL, "idem_tol must be >= 0");
     if (o.branch_in && (o.n_branch_in < 0 || o.n_branch_in > 128))
       fail(GB_EINVAL, "n_branch_in = %d outside [0, 128]", o.n_branch_in);

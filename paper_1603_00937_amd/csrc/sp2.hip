@@ -1100,6 +1100,82 @@ __global__ __launch_bounds__(kT) void k_idem(const T* __restrict__ X, const T* _
   if (threadIdx.x == 0) out[s] = red[0];
 }
 
+// ---- core rows of a polynomial in X (FP64 refinement on the rows D keeps) -----------------
+// A "row slab" holds k_s rows of width np_s per subgraph at soffs[s] (row stride np_s), the
+// same layout as the first k_s rows of a block, so the trace, check and scatter kernels read a
+// slab as they read a block.  Since X is symmetric, the core rows of q(X) are the transposed
+// core columns, and V q(X) for a slab V needs only products V X.
+
+// W = V X: one thread per column c of W, 256 columns per workgroup, V staged in LDS in chunks of
+// 64 columns; X is read once, coalesced along its rows.
+template <int KMAX>
+__global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
+                                                 const int64_t* __restrict__ offs,
+                                                 const int32_t* __restrict__ npad,
+                                                 const double* __restrict__ V,
+                                                 double* __restrict__ W,
+                                                 const int64_t* __restrict__ soffs,
+                                                 const int32_t* __restrict__ core_ptr) {
+  __shared__ double vt[KMAX][64];
+  const int s = blockIdx.y;
+  const int np = npad[s];
+  const int c0 = blockIdx.x * 256;
+  if (c0 >= np) return;  // the whole workgroup leaves together
+  const int k = core_ptr[s + 1] - core_ptr[s];
+  const int c = c0 + threadIdx.x;
+  const bool live = c < np;
+  const double* xs = X + offs[s];
+  const double* vs = V + soffs[s];
+  double acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+  for (int a0 = 0; a0 < np; a0 += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < KMAX * 64; e += 256) {
+      const int j = e >> 6, a = e & 63;
+      vt[j][a] = j < k ? vs[(int64_t)j * np + a0 + a] : 0.0;
+    }
+    __syncthreads();
+    if (live) {
+      const double* xr = xs + (int64_t)a0 * np + c;
+#pragma unroll 4
+      for (int a = 0; a < 64; ++a) {
+        const double x = xr[(int64_t)a * np];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) acc[j] = fma(vt[j][a], x, acc[j]);
+      }
+    }
+  }
+  if (live) {
+    double* ws = W + soffs[s];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) ws[(int64_t)j * np + c] = acc[j];
+  }
+}
+
+// W = the first k_s rows of X (= E X for the core unit rows E)
+__global__ __launch_bounds__(256) void k_rows_copy(const double* __restrict__ X,
+                                                   const int64_t* __restrict__ offs,
+                                                   const int32_t* __restrict__ npad,
+                                                   double* __restrict__ W,
+                                                   const int64_t* __restrict__ soffs,
+                                                   const int32_t* __restrict__ core_ptr) {
+  const int s = blockIdx.y;
+  const int np = npad[s], k = core_ptr[s + 1] - core_ptr[s];
+  const int64_t n = (int64_t)k * np;
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
+    W[soffs[s] + p] = X[offs[s] + p];
+}
+
+// out = a x + b y over a whole slab (flat)
+__global__ void k_lin2(double* __restrict__ out, double a, const double* __restrict__ x, double b,
+                       const double* __restrict__ y, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+    out[p] = a * x[p] + b * y[p];
+}
+
 __global__ void k_max(const double* __restrict__ in, int n, double* __restrict__ out) {
   __shared__ double red[kT];
   double m = 0.0;
@@ -1840,6 +1916,72 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
 }  // namespace
 
 // Full gb_density pipeline on an already built partition.
+// ---- FP64 McWeeny refinement on the core rows --------------------------------------------
+// D keeps only the core columns of each block, i.e. (X symmetric) its core rows E q(X) for the
+// core unit rows E.  For p(x) = 3x^2 - 2x^3: E p(X) = 3 E X^2 - 2 E X^3, V p(X) = 3 V X^2 -
+// 2 V X^3 for any slab V, and p(p(X)) = 3 p(X)^2 - 2 p(X)^3, so one or two McWeeny steps on the
+// core rows take 2 or 8 slab products V X (2 n^2 k flops each instead of 2 n^3 for a block
+// square), evaluated nested so every intermediate stays a polynomial bounded on [0, 1].
+struct CoreRows {
+  int kmax = 0;
+  int colblocks = 0;
+  int64_t total = 0;  // doubles per slab
+  DBuf<int64_t> soffs;
+};
+
+bool core_rows_plan(const Part& P, const Plan& pl, CoreRows& cr, hipStream_t s) {
+  int kmax = 0;
+  for (int q = 0; q < pl.n_sub; ++q) {
+    kmax = std::max(kmax, P.h_core_ptr[q + 1] - P.h_core_ptr[q]);
+    if (pl.npad[q] % 64) return false;
+  }
+  if (kmax > 32) return false;
+  std::vector<int64_t> so(pl.n_sub);
+  int64_t t = 0;
+  for (int q = 0; q < pl.n_sub; ++q) {
+    so[q] = t;
+    t += (int64_t)(P.h_core_ptr[q + 1] - P.h_core_ptr[q]) * pl.npad[q];
+  }
+  cr.kmax = kmax <= 16 ? 16 : 32;
+  cr.colblocks = (pl.max_npad + 255) / 256;
+  cr.total = std::max<int64_t>(t, 1);
+  cr.soffs = DBuf<int64_t>(pl.n_sub, s);
+  GB_HIP(hipMemcpyAsync(cr.soffs.get(), so.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
+  GB_HIP(hipStreamSynchronize(s));
+  return true;
+}
+
+struct RowsCtx {
+  const CoreRows& cr;
+  const Plan& pl;
+  const Part& P;
+  const int64_t* offs;
+  const int32_t* npad;
+  hipStream_t s;
+  void mm(const double* X, const double* V, double* W) const {
+    const dim3 grid(cr.colblocks, pl.n_sub);
+    if (cr.kmax == 16)
+      hipLaunchKernelGGL(k_rows_mm<16>, grid, dim3(256), 0, s, X, offs, npad, V, W, cr.soffs.get(),
+                         P.core_ptr.get());
+    else
+      hipLaunchKernelGGL(k_rows_mm<32>, grid, dim3(256), 0, s, X, offs, npad, V, W, cr.soffs.get(),
+                         P.core_ptr.get());
+    GB_LAUNCH_CHECK();
+  }
+  void lin2(double* out, double a, const double* x, double b, const double* y) const {
+    hipLaunchKernelGGL(k_lin2, dim3(grid_for(cr.total, 256, 65536)), dim3(256), 0, s, out, a, x, b,
+                       y, cr.total);
+    GB_LAUNCH_CHECK();
+  }
+  // out = V p(X) (out may be V); t0, t1 scratch slabs
+  void apply_p(const double* X, const double* V, double* out, double* t0, double* t1) const {
+    mm(X, V, t0);
+    mm(X, t0, t1);
+    mm(X, t1, t0);
+    lin2(out, 3.0, t1, -2.0, t0);
+  }
+};
+
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
              double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s,
              TapeData** tape_out) {
@@ -1993,21 +2135,24 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   // (with split-bf16 squares tile_policy picks that kernel's variant; the FP64 refinement tunes
   // its own tile edge)
   else if (low && planes > 0) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, 0, 0, st, xcd);
+  CoreRows cr;
+  const double* rows_final = nullptr;  // core-row refinement: the core rows of D and of D^2
+  const double* rows_check = nullptr;
   GB_HIP(hipEventRecord(t_stage.a, s));
   if (low && done) {
     // converged during the FP64 steps: nothing to refine
-  } else if (low && o.refine_kind == 0) {
-    // FP64 refinement by McWeeny purification X <- 3X^2 - 2X^3 = 3S - 2 S X (S = X^2; S and X
-    // commute, so S X is computed on upper tiles and mirrored).  It drives every eigenvalue to
+  } else if (low && (o.refine_kind == 0 || o.refine_kind == 2)) {
+    // FP64 refinement by McWeeny purification X <- 3X^2 - 2X^3.  It drives every eigenvalue to
     // 0 or 1 without acting on the trace, so the occupation the low-precision loop reached is
-    // kept.  Steps repeat until the FP64 stop test holds (at most n_refine, default 8); the
-    // test takes the traces from X itself, so no square is spent on it.
-    DBuf<double> part(2 * (size_t)pl.n_sub, s);
-    double* td = ws->get<double>(2, pl.total, s);
-    const int max_steps = n_refine > 0 ? n_refine : 8;
+    // kept.  The stop test takes the traces from X itself, so no square is spent on it.
     const int at = std::min(it_end, 127);
-    StepRec r;
-    for (int step = 0;; ++step) {
+    // Core rows (refine_kind 0): one or two steps (the count from e <- 12 e^2 per step, a bound
+    // on how the summed distances of the eigenvalues from 0 and 1 contract) evaluated on the
+    // core rows only, then the stop test on them; if it fails, whole-block steps from the same X.
+    bool refined = false;
+    if (o.refine_kind == 0 && core_rows_plan(P, pl, cr, s)) {
+      DBuf<double> part(2 * (size_t)pl.n_sub, s);
+      StepRec r;
       hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, offs.get(),
                          npad.get(), P.core_ptr.get(), part.get(), nullptr);
       hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, (double)n_occ,
@@ -2015,16 +2160,86 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       GB_LAUNCH_CHECK();
       GB_HIP(hipMemcpyAsync(&r, recs.get(), sizeof(r), hipMemcpyDeviceToHost, s));
       GB_HIP(hipStreamSynchronize(s));
-      if (r.e <= tol || step == max_steps) break;
-      launch_square<double>(xd, sd, tiles.get(), pl.lg, offs.get(), s);
-      launch_symm<double, 1>(sd, xd, sd, td, -2.0, 3.0, tiles.get(), pl.lg, offs.get(), s);
-      std::swap(xd, td);
-      ++st.n_refine_done;
+      if (r.e <= tol) {
+        refined = true;  // nothing to refine; the whole-block check below
+      } else {
+        const int m = (12.0 * r.e * r.e <= tol || n_refine == 1) ? 1 : 2;
+        double* sl = ws->get<double>(7, 5 * (size_t)cr.total, s);
+        double *y = sl, *s1 = sl + cr.total, *s2 = sl + 2 * cr.total, *t0 = sl + 3 * cr.total,
+               *t1 = sl + 4 * cr.total;
+        const RowsCtx rc{cr, pl, P, offs.get(), npad.get(), s};
+        // E p(X) = 3 E X^2 - 2 E X^3 (E X: the first k rows of X)
+        hipLaunchKernelGGL(k_rows_copy, dim3(cr.colblocks * 4, pl.n_sub), dim3(256), 0, s, xd,
+                           offs.get(), npad.get(), t0, cr.soffs.get(), P.core_ptr.get());
+        GB_LAUNCH_CHECK();
+        rc.mm(xd, t0, t1);
+        rc.mm(xd, t1, t0);
+        rc.lin2(y, 3.0, t1, -2.0, t0);
+        if (m == 2) {  // E p(p(X)) = 3 E p(X)^2 - 2 E p(X)^3
+          rc.apply_p(xd, y, s1, t0, t1);
+          rc.apply_p(xd, s1, s2, t0, t1);
+          rc.lin2(y, 3.0, s1, -2.0, s2);
+        }
+        hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, y,
+                           cr.soffs.get(), npad.get(), P.core_ptr.get(), part.get(), nullptr);
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub,
+                           (double)n_occ, tol, 2, 0, recs.get());
+        GB_LAUNCH_CHECK();
+        StepRec r2;
+        GB_HIP(hipMemcpyAsync(&r2, recs.get(), sizeof(r2), hipMemcpyDeviceToHost, s));
+        GB_HIP(hipStreamSynchronize(s));
+        if (r2.e <= tol) {
+          // the check's square: Z = Y P(X) (P = p or p o p), the core rows of D^2
+          rc.apply_p(xd, y, s1, t0, t1);
+          if (m == 2) {
+            rc.apply_p(xd, s1, s2, t0, t1);
+            rc.mm(xd, s2, t0);
+            rc.mm(xd, t0, t1);
+            rc.mm(xd, t1, t0);
+            rc.lin2(s1, 3.0, s2, -6.0, t1);  // 3 A2 - 2 (3 A2 X^2 - 2 A2 X^3)
+            rc.lin2(s1, 1.0, s1, 4.0, t0);
+          }
+          rows_final = y;
+          rows_check = s1;
+          st.n_refine_done = m;
+          r = r2;
+          refined = true;
+        }
+      }
+      if (refined) {
+        st.idem = r.e;
+        st.t1[at] = r.t1;
+        st.t2[at] = r.t2;
+        stop_kind = 1;
+      }
     }
-    st.idem = r.e;
-    st.t1[at] = r.t1;
-    st.t2[at] = r.t2;
-    stop_kind = r.e <= tol ? 1 : 2;
+    if (!refined) {
+      // Whole blocks: X^2 = S, then 3S - 2 S X (S and X commute, so S X is computed on upper
+      // tiles and mirrored); steps repeat until the FP64 stop test holds (at most n_refine,
+      // default 8).
+      DBuf<double> part(2 * (size_t)pl.n_sub, s);
+      double* td = ws->get<double>(2, pl.total, s);
+      const int max_steps = n_refine > 0 ? n_refine : 8;
+      StepRec r;
+      for (int step = 0;; ++step) {
+        hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, offs.get(),
+                           npad.get(), P.core_ptr.get(), part.get(), nullptr);
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub,
+                           (double)n_occ, tol, 2, 0, recs.get());
+        GB_LAUNCH_CHECK();
+        GB_HIP(hipMemcpyAsync(&r, recs.get(), sizeof(r), hipMemcpyDeviceToHost, s));
+        GB_HIP(hipStreamSynchronize(s));
+        if (r.e <= tol || step == max_steps) break;
+        launch_square<double>(xd, sd, tiles.get(), pl.lg, offs.get(), s);
+        launch_symm<double, 1>(sd, xd, sd, td, -2.0, 3.0, tiles.get(), pl.lg, offs.get(), s);
+        std::swap(xd, td);
+        ++st.n_refine_done;
+      }
+      st.idem = r.e;
+      st.t1[at] = r.t1;
+      st.t2[at] = r.t2;
+      stop_kind = r.e <= tol ? 1 : 2;
+    }
   } else if (low) {
     // FP64 refinement: SP2 steps with FP64 traces from where the FP32 loop stopped
     const uint8_t* bin = nullptr;
@@ -2061,20 +2276,27 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
 
   // final idempotency check on the core rows: X^2 restricted to the tiles that hold them (all
   // upper tiles in tile rows below the core size), then max |X^2 - X| over the core rows
-  DBuf<int4> idem_tiles(std::max<size_t>(pl.idem.size(), 1), s);
-  GB_HIP(hipMemcpyAsync(idem_tiles.get(), pl.idem.data(), pl.idem.size() * sizeof(int4),
-                        hipMemcpyHostToDevice, s));
-  launch_square<double>(xd, sd, idem_tiles.get(), one_group(128, (int)pl.idem.size()), offs.get(),
-                        s);
+  // (after the core-row refinement the core rows of X and X^2 are already there)
+  const double* xfin = rows_final ? rows_final : xd;
+  const int64_t* foffs = rows_final ? cr.soffs.get() : offs.get();
+  if (!rows_final) {
+    DBuf<int4> idem_tiles(std::max<size_t>(pl.idem.size(), 1), s);
+    GB_HIP(hipMemcpyAsync(idem_tiles.get(), pl.idem.data(), pl.idem.size() * sizeof(int4),
+                          hipMemcpyHostToDevice, s));
+    launch_square<double>(xd, sd, idem_tiles.get(), one_group(128, (int)pl.idem.size()),
+                          offs.get(), s);
+    GB_HIP(hipStreamSynchronize(s));  // idem_tiles is freed at the end of this scope
+  }
+  const double* sfin = rows_final ? rows_check : sd;
   DBuf<double> per(pl.n_sub, s), mx(1, s);
-  hipLaunchKernelGGL(k_idem<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, sd, offs.get(), npad.get(),
-                     P.core_ptr.get(), P.sub_ptr.get(), per.get());
+  hipLaunchKernelGGL(k_idem<double>, dim3(pl.n_sub), dim3(kT), 0, s, xfin, sfin, foffs,
+                     npad.get(), P.core_ptr.get(), P.sub_ptr.get(), per.get());
   GB_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_max, dim3(1), dim3(kT), 0, s, per.get(), pl.n_sub, mx.get());
   GB_LAUNCH_CHECK();
   // scatter
   GB_HIP(hipEventRecord(t_stage.a, s));
-  hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, xd, offs.get(), npad.get(),
+  hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, xfin, foffs, npad.get(),
                      P.sub_ptr.get(), P.sub_idx.get(), P.sub_pos.get(), P.col_sub.get(),
                      P.col_loc.get(), D.width, D.col, D.val);
   GB_LAUNCH_CHECK();

@@ -74,7 +74,8 @@ def test_fp32_small_matches_oracle_pattern(gb, model_cache):
     assert np.abs(D_val.cpu().numpy() - ov).max() <= 1e-6
 
 
-@pytest.mark.parametrize("refine,first", [("mcweeny", 0), ("sp2", 0), ("mcweeny", 3)])
+@pytest.mark.parametrize("refine,first", [("mcweeny", 0), ("sp2", 0), ("mcweeny", 3),
+                                          ("mcweeny_blocks", 0)])
 def test_refinement_variants(gb, model_cache, ref1024, refine, first):
     m = model_cache("n1024")
     D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
@@ -86,3 +87,31 @@ def test_refinement_variants(gb, model_cache, ref1024, refine, first):
     assert st["converged"]
     assert st["idem_max"] < 1e-8
     assert err <= 2e-6
+
+
+@pytest.mark.parametrize("precision,core", [("fp32", 16), ("bf16x6", 16), ("bf16x6", 32),
+                                            ("fp32", 40)])
+def test_core_row_refinement_matches_whole_blocks(gb, model_cache, precision, core):
+    """McWeeny on the core rows (products of the k core rows with X) against McWeeny on whole
+    blocks from the same low-precision X: same pattern, values and check to rounding.  Cores
+    of 40 exceed the core-row path's 32 rows and take whole blocks both times."""
+    m = model_cache("n1024")
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+    out = {}
+    for refine in ("mcweeny", "mcweeny_blocks"):
+        D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], 1e-5, core_size=core,
+                                      precision=precision, refine=refine)
+        out[refine] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st)
+    (rc, rv, rs), (bc, bv, bs) = out["mcweeny"], out["mcweeny_blocks"]
+    diff = float(np.abs(rv - bv).max())
+    print(f"{precision} core={core}: rows {rs['n_refine_done']} steps idem_max "
+          f"{rs['idem_max']:.2e} {rs['ms']['refine']:.2f} ms; blocks {bs['n_refine_done']} steps "
+          f"idem_max {bs['idem_max']:.2e} {bs['ms']['refine']:.2f} ms; max diff {diff:.2e}")
+    assert rs["converged"] and bs["converged"]
+    assert rs["iters"] == bs["iters"] and rs["branch"] == bs["branch"]
+    assert np.array_equal(rc, bc)
+    # the core-row path picks its step count in advance, so it may take one step more
+    assert rs["n_refine_done"] >= bs["n_refine_done"]
+    assert diff <= (1e-11 if rs["n_refine_done"] == bs["n_refine_done"] else 1e-8)
+    assert abs(rs["idem_max"] - bs["idem_max"]) <= 1e-10
+    assert abs(rs["trace"] - bs["trace"]) <= 1e-9
