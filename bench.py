@@ -121,9 +121,18 @@ def traffic_from_pmc(pmc_dir, workload="n18000"):
     print(json.dumps(recs, indent=1))
 
 
-def run_step(gb, Hc, Hv, n_occ, tau, core, D, args):
+def run_step(gb, Hc, Hv, n_occ, tau, core, D, args, times=None):
+    import torch
+    t0 = time.perf_counter()
     g = gb.build_graph(Hc, Hv, tau)
-    p = gb.partition(g, core)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p = gb.partition(g, core, method=args.partition)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if times is not None:
+        times["graph"] += (t1 - t0) * 1e3
+        times["part"] += (t2 - t1) * 1e3
     return gb.density(Hc, Hv, n_occ, tau, partition=p, core_size=core, precision=args.precision,
                       D=D, launch_mode=args.launch_mode, tile_policy=args.tile_policy,
                       tile_order=args.tile_order, refine=args.refine,
@@ -391,6 +400,9 @@ def main():
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2", "mcweeny_blocks"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
+    ap.add_argument("--partition", default="block", choices=["block", "multilevel"],
+                    help="cores: blocks of the (spatially sorted) vertex order, or multilevel "
+                         "communities of at most the core size")
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--rocpd-counters", default=None,
                     help="summarise the counters of a rocprofv3 --pmc database")
@@ -441,7 +453,8 @@ def main():
     cfg = WORKLOADS[args.workload]
     model = make_model(args.workload)
     N = model["N"]
-    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_fp64_partitioned.json")
+    tag = "partitioned" if args.partition == "block" else args.partition
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.workload}_fp64_{tag}.json")
     golden = json.load(open(gpath)) if os.path.exists(gpath) else None
     if golden and golden["H_sha256"] != ell_sha256(model["H_col"], model["H_val"]):
         golden = None
@@ -449,7 +462,7 @@ def main():
     Hc = torch.from_numpy(model["H_col"]).to(dev)
     Hv = torch.from_numpy(model["H_val"]).to(dev)
     g = gb.build_graph(Hc, Hv, cfg["tau"])
-    p = gb.partition(g, cfg["core"])
+    p = gb.partition(g, cfg["core"], method=args.partition)
     D = (torch.empty((N, p.max_sub), dtype=torch.int32, device=dev),
          torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
     del g, p
@@ -475,13 +488,17 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
     low = precision != "fp64"
     key = "square_lo" if low else "square"
     sq_ms, sq_n, stats = 0.0, 0, None
+    host_ms = {"graph": 0.0, "part": 0.0}
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, a)
+        _, _, stats = run_step(gb, Hc, Hv, n_occ, cfg["tau"], cfg["core"], D, a, host_ms)
         sq_ms += stats["ms"][key]
         sq_n += stats["n_" + key]
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
+    # graph and partition are separate calls before gb_density: their wall time per step
+    stats["ms"]["graph"] = host_ms["graph"] / args.steps
+    stats["ms"]["part"] = host_ms["part"] / args.steps
     flops_alg = stats["square_flops"]
     flops_exec = stats["square_flops_exec"] * PLANE_PRODUCTS.get(precision, 1)
     # the dominant kernel is the squaring launch of the loop's precision (the low-precision
@@ -498,7 +515,10 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
         "dtype": {"fp64": "f64", "fp32": "f32+f64"}.get(precision, "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: seeded 3D tight-binding model, N={N} orbitals, "
-                               f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}",
+                               f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}"
+                               + ("" if args.partition == "block" else
+                                  f" (at most; {args.partition} communities)"),
+                   "partition": args.partition,
                    "precision": precision, "launch_mode": args.launch_mode,
                    "tile_policy": args.tile_policy, "tile_order": args.tile_order,
                    "refine": args.refine, "n_fp64_first": args.n_fp64_first,

@@ -139,9 +139,13 @@ void gb_graph_destroy(gb_graph_t* g);
 /* Core selection (obs. vi-vii: a core may be any set of vertices, a "community"). */
 typedef enum {
   GB_PART_BLOCK = 0, /* cores = consecutive runs of core_size vertices in vertex order      */
-  GB_PART_BFS = 1    /* the same runs cut from a Cuthill-McKee order of the graph: start at  *
+  GB_PART_BFS = 1,   /* the same runs cut from a Cuthill-McKee order of the graph: start at  *
                       * the unvisited vertex of smallest (degree, index), append unvisited   *
                       * neighbours by (degree, index); each core's vertices then ascending   */
+  GB_PART_MULTILEVEL = 2 /* communities of at most core_size vertices from a multilevel     *
+                      * partitioner (the paper takes its communities from one) aimed at the  *
+                      * cost sum_s (|core| + |halo|)^3 and independent of vertex order; see  *
+                      * gb_partition_host.  Runs on the host (the graph is copied back).     */
 } gb_part_method;
 
 typedef struct gb_partition_s gb_partition_t;
@@ -153,6 +157,23 @@ typedef struct gb_partition_s gb_partition_t;
  */
 gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, void* stream,
                        gb_partition_t** out);
+/*
+ * Host: the cores GB_PART_MULTILEVEL chooses for a host CSR graph (row_ptr [n+1], col [nnz],
+ * symmetric; self loops ignored).  Heavy-edge matching coarsens the graph (pairs up to
+ * core_size/4 vertices, a fixed pseudo-random visiting order: vertices sorted by SplitMix64 of
+ * (level << 32 | v)) until no pair can be matched; parts of at most core_size vertices are
+ * grown on the coarsest graph (seeds in breadth-first order, each part taking the unassigned
+ * neighbour most strongly tied to it); at every level back, boundary vertices move to the
+ * neighbouring part that cuts most edge weight and has room; on the input graph vertices move
+ * when that lowers sum_s (|core| + |halo|)^3 exactly.  All choices have fixed tie-breaks, so
+ * the cores are a function of the graph.  Outputs (host, caller-owned): *n_cores; core_ptr
+ * [n_cores + 1] (room for n + 1); core_vtx [n] (each core ascending, cores in ascending order
+ * of their smallest vertex); *cost = sum_s (|core| + |halo|)^3 (any of cost may be NULL).
+ * GB_EINVAL for NULL arrays, n < 1 or core_size < 1.
+ */
+gb_status gb_partition_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                            int32_t core_size, int32_t* n_cores, int32_t* core_ptr,
+                            int32_t* core_vtx, int64_t* cost);
 /* n_sub subgraphs, the largest has max_sub vertices, total = sum of sizes (host outputs). */
 gb_status gb_partition_info(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
                             int64_t* total);

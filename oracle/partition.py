@@ -13,7 +13,8 @@ Layout (bit-exact on the GPU):
 
 Partitions: BLOCK = contiguous runs of ``core_size`` vertices in vertex order (the
 generator emits spatially sorted vertices, so blocks are compact communities);
-BFS = the same blocks cut from a deterministic breadth-first (Cuthill-McKee) order.
+BFS = the same blocks cut from a deterministic breadth-first (Cuthill-McKee) order;
+MULTILEVEL = communities of at most ``core_size`` vertices (oracle/multilevel.py).
 """
 import numpy as np
 
@@ -76,6 +77,12 @@ def partition(row_ptr, col, core_size: int, method: str = "block"):
     """(core_ptr, core_vertices, sub_ptr, sub_idx).  core_vertices lists each core's
     vertices in the same order as the first entries of its subgraph."""
     N = len(row_ptr) - 1
+    if method == "multilevel":
+        from oracle.multilevel import partition_multilevel
+        ptr, cv, _ = partition_multilevel(row_ptr, col, core_size)
+        cores = [cv[ptr[c]:ptr[c + 1]] for c in range(len(ptr) - 1)]
+        sub_ptr, sub_idx = halo_subgraphs(row_ptr, col, cores)
+        return ptr, cv, sub_ptr, sub_idx
     order = None if method == "block" else bfs_order(row_ptr, col)
     ptr, cores = core_lists(N, core_size, order)
     sub_ptr, sub_idx = halo_subgraphs(row_ptr, col, cores)

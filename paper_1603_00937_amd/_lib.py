@@ -9,7 +9,7 @@ GB_OK, GB_EINVAL, GB_ENOMEM, GB_EHIP, GB_ESHAPE, GB_EUNSUPPORTED = 0, -1, -2, -3
 STATUS_NAMES = {0: "GB_OK", -1: "GB_EINVAL", -2: "GB_ENOMEM", -3: "GB_EHIP", -4: "GB_ESHAPE",
                 -5: "GB_EUNSUPPORTED"}
 GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2, "dprev_symbolic": 3}
-PART_METHODS = {"block": 0, "bfs": 1}
+PART_METHODS = {"block": 0, "bfs": 1, "multilevel": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4}
 
 
@@ -100,6 +100,10 @@ SIGNATURES = {
                                        _P(_vp)]),
     "gb_graph_destroy": (None, [_vp]),
     "gb_partition": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _P(_vp)]),
+    "gb_partition_host": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                           ctypes.c_int32, _P(ctypes.c_int32),
+                                           _P(ctypes.c_int32), _P(ctypes.c_int32),
+                                           _P(ctypes.c_int64)]),
     "gb_partition_info": (ctypes.c_int32, [_vp, _P(ctypes.c_int32), _P(ctypes.c_int32),
                                            _P(ctypes.c_int64)]),
     "gb_partition_copy": (ctypes.c_int32, [_vp, _vp, _vp, _vp, _vp]),

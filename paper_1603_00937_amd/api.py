@@ -198,6 +198,24 @@ def partition(graph: Graph, core_size: int, method="block") -> Partition:
     return Partition(out)
 
 
+def partition_host(row_ptr, col, core_size):
+    """Host: the multilevel cores of a host CSR graph (numpy int32 arrays).  Returns
+    (core_ptr, core_vtx, cost) as numpy arrays and the summed (|core| + |halo|)^3."""
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    n = len(rp) - 1
+    cp = np.zeros(n + 1, dtype=np.int32)
+    cv = np.zeros(max(n, 1), dtype=np.int32)
+    nc = ctypes.c_int32()
+    cost = ctypes.c_int64()
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    _check(_lib().gb_partition_host(n, rp.ctypes.data_as(i32), cl.ctypes.data_as(i32),
+                                    int(core_size), ctypes.byref(nc), cp.ctypes.data_as(i32),
+                                    cv.ctypes.data_as(i32), ctypes.byref(cost)))
+    return cp[:nc.value + 1].copy(), cv[:n].copy(), int(cost.value)
+
+
 def _stats_dict(st: L.GbSp2Stats) -> dict:
     k = st.iters
     nt = min(k + 1, 128)

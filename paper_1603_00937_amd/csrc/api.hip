@@ -385,12 +385,15 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
     *out = nullptr;
     if (!g) fail(GB_EINVAL, "graph is NULL");
     if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
-    if (method != GB_PART_BLOCK && method != GB_PART_BFS)
+    if (method != GB_PART_BLOCK && method != GB_PART_BFS && method != GB_PART_MULTILEVEL)
       fail(GB_EINVAL, "unknown partition method %d", method);
     hipStream_t s = as_stream(stream);
     auto* p = new gb_partition_s();
     try {
-      partition_block(g->csr, core_size, p->part, s, method);
+      if (method == GB_PART_MULTILEVEL)
+        partition_multilevel_dev(g->csr, core_size, p->part, s, nullptr);
+      else
+        partition_block(g->csr, core_size, p->part, s, method);
       GB_HIP(hipStreamSynchronize(s));
       detach(p->part);
     } catch (...) {
@@ -398,6 +401,30 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
       throw;
     }
     *out = p;
+  });
+}
+
+gb_status gb_partition_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                            int32_t core_size, int32_t* n_cores, int32_t* core_ptr,
+                            int32_t* core_vtx, int64_t* cost) {
+  return guarded([&] {
+    if (!row_ptr || !col || !n_cores || !core_ptr || !core_vtx)
+      fail(GB_EINVAL, "row_ptr / col / n_cores / core_ptr / core_vtx is NULL");
+    if (n < 1) fail(GB_EINVAL, "n = %d must be >= 1", n);
+    if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
+    if (row_ptr[0] != 0) fail(GB_EINVAL, "row_ptr[0] must be 0");
+    for (int v = 0; v < n; ++v) {
+      if (row_ptr[v + 1] < row_ptr[v]) fail(GB_EINVAL, "row_ptr decreases at %d", v);
+      for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+        if (col[e] < 0 || col[e] >= n) fail(GB_EINVAL, "col[%d] = %d out of range", e, col[e]);
+    }
+    std::vector<int32_t> cp, cv;
+    MlStats st;
+    partition_multilevel(n, row_ptr, col, core_size, cp, cv, &st);
+    *n_cores = (int32_t)cp.size() - 1;
+    std::memcpy(core_ptr, cp.data(), cp.size() * 4);
+    std::memcpy(core_vtx, cv.data(), cv.size() * 4);
+    if (cost) *cost = st.cost;
   });
 }
 

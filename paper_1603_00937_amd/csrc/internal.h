@@ -134,6 +134,22 @@ struct Part {
   std::vector<int32_t> h_core_ptr, h_sub_ptr;  // host copies (sizes for planning)
 };
 void partition_block(const Csr& g, int32_t core_size, Part& out, hipStream_t s, int method);
+void finish_partition(const Csr& g, Part& P, hipStream_t s);
+void partition_from_cores(const Csr& g, const std::vector<int32_t>& core_ptr,
+                          const std::vector<int32_t>& core_vtx, Part& P, hipStream_t s);
+struct MlStats {
+  int levels = 0, coarsest = 0;
+  int64_t cost = 0;  // sum over subgraphs of (|core| + |halo|)^3
+  double ms_weights = 0, ms_coarsen = 0, ms_grow = 0, ms_cut = 0, ms_cost = 0;
+};
+// Multilevel cores of at most `cap` vertices (host; mlpart.hip); core_vtx ascending per core.
+// ew (optional): per CSR entry, the number of common closed neighbours of its two ends
+// (computed here when NULL).
+void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
+                          std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
+                          MlStats* stats, const int32_t* ew = nullptr);
+void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
+                              MlStats* stats);
 void detach(Csr& c);
 void detach(Part& p);
 

@@ -229,6 +229,37 @@ __global__ void k_sort_cores(const int32_t* __restrict__ order, const int32_t* _
   }
 }
 
+// Common closed neighbours of the ends of every edge: w[e] = |row u ∩ row col[e]| for the rows
+// of a CSR graph that holds its self loops (so each row is the closed neighbourhood).  One
+// workgroup per vertex u: row u as a bitmap in LDS, then one wave per neighbour v counting the
+// entries of row v found in it.
+__global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  int32_t* __restrict__ w) {
+  extern __shared__ uint32_t bits[];
+  const int u = blockIdx.x;
+  const int nw = (n + 31) >> 5;
+  for (int i = threadIdx.x; i < nw; i += kT) bits[i] = 0u;
+  __syncthreads();
+  const int b = rp[u], e_end = rp[u + 1];
+  for (int e = b + threadIdx.x; e < e_end; e += kT) {
+    const int x = col[e];
+    atomicOr(&bits[x >> 5], 1u << (x & 31));
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int e = b + wave; e < e_end; e += kT / 64) {
+    const int v = col[e];
+    int c = 0;
+    for (int f = rp[v] + lane; f < rp[v + 1]; f += 64) {
+      const int x = col[f];
+      c += (bits[x >> 5] >> (x & 31)) & 1u;
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
+    if (lane == 0) w[e] = c;
+  }
+}
+
 }  // namespace
 
 void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s, int method) {
@@ -264,7 +295,56 @@ void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s, in
     hipLaunchKernelGGL(k_iota, dim3((n + kT - 1) / kT), dim3(kT), 0, s, P.core_vtx.get(), n);
     GB_LAUNCH_CHECK();
   }
+  finish_partition(g, P, s);
+}
 
+void partition_from_cores(const Csr& g, const std::vector<int32_t>& core_ptr,
+                          const std::vector<int32_t>& core_vtx, Part& P, hipStream_t s) {
+  const int n = g.n;
+  if ((int64_t)core_vtx.size() != n || core_ptr.empty() || core_ptr.back() != n)
+    fail(GB_ESHAPE, "core lists do not cover the %d vertices", n);
+  P.n = n;
+  P.n_sub = (int)core_ptr.size() - 1;
+  P.h_core_ptr = core_ptr;
+  P.core_ptr = DBuf<int32_t>(P.n_sub + 1, s);
+  GB_HIP(hipMemcpyAsync(P.core_ptr.get(), core_ptr.data(), core_ptr.size() * 4,
+                        hipMemcpyHostToDevice, s));
+  P.core_vtx = DBuf<int32_t>(n, s);
+  GB_HIP(hipMemcpyAsync(P.core_vtx.get(), core_vtx.data(), (size_t)n * 4, hipMemcpyHostToDevice,
+                        s));
+  finish_partition(g, P, s);
+}
+
+void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
+                              MlStats* stats) {
+  const int n = g.n;
+  std::vector<int32_t> rp(n + 1), col(g.nnz), w(g.nnz), cp, cv;
+  // edge weights on the device (the graphs built here hold every self loop), the rest on the
+  // host
+  const size_t lds = (size_t)((n + 31) >> 5) * 4;
+  if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "multilevel: n = %d too large for one LDS bitmap", n);
+  DBuf<int32_t> dw(std::max<int64_t>(g.nnz, 1), s);
+  hipLaunchKernelGGL(k_common_nb, dim3(n), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
+                     dw.get());
+  GB_LAUNCH_CHECK();
+  GB_HIP(hipMemcpyAsync(rp.data(), g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(col.data(), g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(w.data(), dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  for (int v = 0; v < n; ++v) {
+    bool self = false;
+    for (int e = rp[v]; e < rp[v + 1]; ++e) self |= col[e] == v;
+    if (!self) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", v);
+  }
+  partition_multilevel(n, rp.data(), col.data(), core_size, cp, cv, stats, w.data());
+  partition_from_cores(g, cp, cv, P, s);
+}
+
+// halos, subgraph lists and index maps for the cores in P.core_ptr / P.core_vtx (each core's
+// vertices ascending)
+void finish_partition(const Csr& g, Part& P, hipStream_t s) {
+  const int n = g.n;
+  const int n_sub = P.n_sub;
   const int nw = (n + 31) >> 5;
   const size_t lds = (size_t)nw * 8 + kT * 4 + 64;
   if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "partition: n = %d too large for one LDS bitmap", n);

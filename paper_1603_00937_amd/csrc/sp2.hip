@@ -1047,6 +1047,35 @@ __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64
   for (int64_t p = i; p < n; p += stride) out[p] = (TO)in[p];
 }
 
+// FP64 copy of an FP32 iterate made exactly symmetric: out = (X + X^T)/2 per block.  The
+// split-bf16 square computes both triangles of its diagonal tiles, pairing the planes of an
+// entry and of its transpose differently, so the FP32 iterate is symmetric only to rounding;
+// the FP64 refinement relies on symmetry.  One workgroup per 64x64 tile, the tile and its
+// transpose partner through LDS.
+__global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X,
+                                                     double* __restrict__ out,
+                                                     const int64_t* __restrict__ offs,
+                                                     const int32_t* __restrict__ npad) {
+  __shared__ float ta[64][65], tb[64][65];
+  const int s = blockIdx.y;
+  const int np = npad[s], nt = np / 64;
+  const int t = blockIdx.x;
+  if (t >= nt * nt) return;  // the whole workgroup leaves together
+  const int bi = t / nt, bj = t % nt;
+  const float* xs = X + offs[s];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    ta[r][c] = xs[(int64_t)(bi * 64 + r) * np + bj * 64 + c];
+    tb[r][c] = xs[(int64_t)(bj * 64 + r) * np + bi * 64 + c];
+  }
+  __syncthreads();
+  double* os = out + offs[s];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    os[(int64_t)(bi * 64 + r) * np + bj * 64 + c] = 0.5 * ((double)ta[r][c] + (double)tb[c][r]);
+  }
+}
+
 // ---- scatter: column i of D = column (= row, X symmetric) j of its subgraph block -------
 template <typename T>
 __global__ __launch_bounds__(kT) void k_scatter(const T* __restrict__ X, const int64_t* __restrict__ offs,
@@ -2082,9 +2111,11 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
         it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
                                  o.branch_in, o.n_branch_in, true, it_end, st, recs, s, &stop_kind,
                                  nullptr, planes, o.launch_mode == 1, &xp, &sp);
-      // the final low-precision square was only the stop test: continue from X in FP64
-      hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT),
-                         0, s, xf, xd, pl.total);
+      // the final low-precision square was only the stop test: continue from X in FP64, made
+      // exactly symmetric (every block is padded to a multiple of 64)
+      const int max_nt = pl.max_npad / 64;
+      hipLaunchKernelGGL(k_sym_convert, dim3(max_nt * max_nt, pl.n_sub), dim3(256), 0, s, xf, xd,
+                         offs.get(), npad.get());
       GB_LAUNCH_CHECK();
     }
     GB_HIP(hipEventRecord(t_stage.b, s));
@@ -2146,9 +2177,10 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     // 0 or 1 without acting on the trace, so the occupation the low-precision loop reached is
     // kept.  The stop test takes the traces from X itself, so no square is spent on it.
     const int at = std::min(it_end, 127);
-    // Core rows (refine_kind 0): one or two steps (the count from e <- 12 e^2 per step, a bound
-    // on how the summed distances of the eigenvalues from 0 and 1 contract) evaluated on the
-    // core rows only, then the stop test on them; if it fails, whole-block steps from the same X.
+    // Core rows (refine_kind 0): two steps, or one when e <- 12 e^2 (how the summed distances of
+    // the eigenvalues from 0 and 1 contract per step, for one block) lands far below the
+    // tolerance, evaluated on the core rows only, then the stop test on them; if it fails,
+    // whole-block steps from the same X.
     bool refined = false;
     if (o.refine_kind == 0 && core_rows_plan(P, pl, cr, s)) {
       DBuf<double> part(2 * (size_t)pl.n_sub, s);
@@ -2163,7 +2195,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       if (r.e <= tol) {
         refined = true;  // nothing to refine; the whole-block check below
       } else {
-        const int m = (12.0 * r.e * r.e <= tol || n_refine == 1) ? 1 : 2;
+        const int m = (12.0 * r.e * r.e <= 1e-3 * tol || n_refine == 1) ? 1 : 2;
         double* sl = ws->get<double>(7, 5 * (size_t)cr.total, s);
         double *y = sl, *s1 = sl + cr.total, *s2 = sl + 2 * cr.total, *t0 = sl + 3 * cr.total,
                *t1 = sl + 4 * cr.total;

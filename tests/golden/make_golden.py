@@ -1,6 +1,8 @@
 """Writes the stored expected values under tests/golden/ (calls only synth and oracle).
 
-Usage: python tests/golden/make_golden.py [hashes] [n1024] [n18000]
+Usage: python tests/golden/make_golden.py [hashes] [n1024] [n18000] [n100000] [n1024_ml]
+                                          [n18000_ml]
+(the _ml variants use the multilevel cores instead of blocks of the vertex order)
 Every value written here comes from the CPU oracle in oracle/ run on the seeded
 inputs from synth/; nothing comes from the GPU library.
 """
@@ -26,18 +28,20 @@ def write_hashes():
     json.dump(out, open(os.path.join(HERE, "model_hashes.json"), "w"), indent=1)
 
 
-def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory=False):
+def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory=False,
+                      method="block"):
     m = make_model(name)
     t = time.time()
     D_col, D_val, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], tau, core_size,
-                                             low_memory=low_memory)
+                                             method=method, low_memory=low_memory)
     N = m["N"]
     rng = np.random.default_rng(seed)
     rows = rng.integers(0, N, n_samples)
     nnz_row = (D_col >= 0).sum(1)
     slots = (rng.random(n_samples) * nnz_row[rows]).astype(np.int64)
     rec = {
-        "model": name, "tau": tau, "core_size": core_size, "N": N, "n_occ": m["n_occ"],
+        "model": name, "tau": tau, "core_size": core_size, "partition": method, "N": N,
+        "n_occ": m["n_occ"],
         "H_sha256": ell_sha256(m["H_col"], m["H_val"]),
         "emin": info["emin"].hex(), "emax": info["emax"].hex(),
         "graph_sha256": ell_sha256(info["row_ptr"], info["col"]),
@@ -55,7 +59,8 @@ def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory
         "samples": [[int(r), int(s), float(D_val[r, s]).hex()] for r, s in zip(rows, slots)],
         "oracle_seconds": time.time() - t,
     }
-    json.dump(rec, open(os.path.join(HERE, f"{name}_fp64_partitioned.json"), "w"))
+    tag = "partitioned" if method == "block" else method
+    json.dump(rec, open(os.path.join(HERE, f"{name}_fp64_{tag}.json"), "w"))
     return rec
 
 
@@ -69,3 +74,7 @@ if __name__ == "__main__":
         write_partitioned("n18000", 1e-5, 32)
     if "n100000" in what:
         write_partitioned("n100000", 1e-5, 32, low_memory=True)
+    if "n1024_ml" in what:
+        write_partitioned("n1024", 1e-5, 16, method="multilevel")
+    if "n18000_ml" in what:
+        write_partitioned("n18000", 1e-5, 32, method="multilevel", low_memory=True)

@@ -11,8 +11,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _golden(name):
-    path = os.path.join(GOLDEN, f"{name}_fp64_partitioned.json")
+def _golden(name, method="block"):
+    tag = "partitioned" if method == "block" else method
+    path = os.path.join(GOLDEN, f"{name}_fp64_{tag}.json")
     if not os.path.exists(path):
         pytest.skip(f"no stored oracle run for {name}")
     return json.load(open(path))
@@ -26,10 +27,10 @@ def gb():
     return gb
 
 
-def _run(gb, name, precision, launch_mode="batched", **kw):
+def _run(gb, name, precision, launch_mode="batched", method="block", **kw):
     import torch
     from synth import make_model, ell_sha256
-    ref = _golden(name)
+    ref = _golden(name, method)
     m = make_model(name)
     assert ell_sha256(m["H_col"], m["H_val"]) == ref["H_sha256"], "inputs differ from the oracle's"
     Hc = torch.from_numpy(m["H_col"]).cuda()
@@ -39,7 +40,7 @@ def _run(gb, name, precision, launch_mode="batched", **kw):
     g = gb.build_graph(Hc, Hv, ref["tau"])
     rp, cl = [t.cpu().numpy() for t in g.arrays()]
     assert ell_sha256(rp, cl) == ref["graph_sha256"]
-    p = gb.partition(g, ref["core_size"])
+    p = gb.partition(g, ref["core_size"], method=method)
     cp, sp, si = [t.cpu().numpy() for t in p.arrays()]
     assert ell_sha256(cp, sp, si) == ref["partition_sha256"]
     D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], ref["tau"], partition=p,
@@ -77,6 +78,21 @@ def test_n18000_fp32(gb, first):
     ref, st, err = _run(gb, "n18000", "fp32", n_fp64_first=first)
     assert st["converged"]
     assert err <= (1e-6 if first else 1.5e-6)
+
+
+def test_n18000_multilevel_fp64(gb):
+    """Multilevel communities (cores of at most 32): partition index for index, branches and D
+    against the oracle's run on the same communities."""
+    ref, st, err = _run(gb, "n18000", "fp64", method="multilevel")
+    assert "".join(map(str, st["branch"])) == ref["branch"]
+    assert st["iters"] == ref["iters"] and st["converged"]
+    assert err <= 1e-9
+
+
+def test_n18000_multilevel_bf16x6(gb):
+    ref, st, err = _run(gb, "n18000", "bf16x6", method="multilevel")
+    assert st["converged"]
+    assert err <= 1e-6
 
 
 def test_n100000_fp64(gb):

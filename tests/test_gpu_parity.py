@@ -286,3 +286,32 @@ def test_tile_edges_mcweeny_agree_to_rounding(gb, model_cache):
                                       core_size=16, precision="fp32", tile_policy=pol)
         vals.append(D_val.cpu().numpy())
     assert np.abs(vals[0] - vals[1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("name,tau,core", [("small256", 1e-5, 16), ("n1024", 1e-5, 16),
+                                           ("tiny48", 1e-2, 5)])
+def test_multilevel_partition_bit_exact(gb, model_cache, name, tau, core):
+    from oracle.graph import graph_x2
+    from oracle.partition import partition
+    m = model_cache(name)
+    g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), tau)
+    p = gb.partition(g, core, method="multilevel")
+    cp, sp, si = _host(*p.arrays())
+    ocp, ocv, osp, osi = partition(*graph_x2(m["H_col"], m["H_val"], tau), core, "multilevel")
+    assert np.array_equal(cp, ocp) and np.array_equal(sp, osp) and np.array_equal(si, osi)
+
+
+def test_density_n1024_multilevel_golden(gb, model_cache):
+    """FP64 D on multilevel communities against the oracle's stored run on the same cores."""
+    from synth import ell_sha256
+    ref = json.load(open(os.path.join(GOLDEN, "n1024_fp64_multilevel.json")))
+    m = model_cache("n1024")
+    g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), ref["tau"])
+    p = gb.partition(g, ref["core_size"], method="multilevel")
+    assert ell_sha256(*_host(*p.arrays())) == ref["partition_sha256"]
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], ref["tau"],
+                                  partition=p)
+    dc, dv = _host(D_col, D_val)
+    assert "".join(map(str, st["branch"])) == ref["branch"]
+    assert ell_sha256(dc) == ref["D_col_sha256"]
+    assert max(abs(dv[r, s] - float.fromhex(v)) for r, s, v in ref["samples"]) <= FP64_TOL

@@ -1,0 +1,133 @@
+"""Pins for the multilevel community oracle (cores of at most cap vertices aimed at the summed
+cubed subgraph sizes), and the host entry point of the library against it index for index.
+CPU only."""
+import numpy as np
+import pytest
+
+from synth import make_model
+from oracle.graph import graph_x2
+from oracle.partition import halo_subgraphs, partition
+from oracle.multilevel import partition_multilevel, splitmix64
+
+
+def _csr(rows):
+    rp = np.zeros(len(rows) + 1, dtype=np.int32)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    col = np.concatenate([np.sort(np.asarray(r, dtype=np.int32)) for r in rows])
+    return rp, col
+
+
+def _cost(rp, col, cp, cv):
+    cores = [cv[cp[i]:cp[i + 1]] for i in range(len(cp) - 1)]
+    sp, _ = halo_subgraphs(rp, col, cores)
+    return int((np.diff(sp).astype(np.int64) ** 3).sum())
+
+
+def _check_valid(n, cp, cv, cap):
+    assert cp[0] == 0 and cp[-1] == n
+    sizes = np.diff(cp)
+    assert sizes.min() >= 1 and sizes.max() <= cap
+    assert np.array_equal(np.sort(cv), np.arange(n))
+    for i in range(len(cp) - 1):
+        c = cv[cp[i]:cp[i + 1]]
+        assert np.all(np.diff(c) > 0)
+    firsts = [cv[cp[i]] for i in range(len(cp) - 1)]
+    assert firsts == sorted(firsts)
+
+
+def test_splitmix64_reference_values():
+    # the published generator seeded with 0 yields these first outputs (state += golden gamma)
+    g = 0x9E3779B97F4A7C15
+    outs = [splitmix64((k * g) & ((1 << 64) - 1)) for k in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def _cliques(n_cliques, size, perm=None):
+    n = n_cliques * size
+    lab = np.arange(n) if perm is None else perm
+    rows = [[] for _ in range(n)]
+    for c in range(n_cliques):
+        members = [int(lab[c * size + i]) for i in range(size)]
+        for a in members:
+            rows[a] = members
+    return rows
+
+
+@pytest.mark.parametrize("relabel", [False, True])
+def test_disjoint_cliques_are_found(relabel):
+    perm = np.random.default_rng(3).permutation(40) if relabel else None
+    rp, col = _csr(_cliques(5, 8, perm))
+    cp, cv, cost = partition_multilevel(rp, col, 8)
+    _check_valid(40, cp, cv, 8)
+    got = sorted(tuple(cv[cp[i]:cp[i + 1]]) for i in range(len(cp) - 1))
+    lab = np.arange(40) if perm is None else perm
+    want = sorted(tuple(sorted(int(lab[c * 8 + i]) for i in range(8))) for c in range(5))
+    assert got == want
+    assert cost == 5 * 8 ** 3      # no halos
+
+
+def test_path_is_cut_into_runs():
+    n = 30
+    rows = [[j for j in (i - 1, i, i + 1) if 0 <= j < n] for i in range(n)]
+    rp, col = _csr(rows)
+    cp, cv, cost = partition_multilevel(rp, col, 6)
+    _check_valid(n, cp, cv, 6)
+    for i in range(len(cp) - 1):
+        c = cv[cp[i]:cp[i + 1]]
+        assert c[-1] - c[0] == len(c) - 1      # consecutive vertices
+    assert cost == _cost(rp, col, cp, cv)
+
+
+@pytest.mark.parametrize("name,cap", [("tiny48", 5), ("small256", 16), ("small256", 7)])
+def test_valid_cores_and_reported_cost(name, cap):
+    m = make_model(name)
+    rp, col = graph_x2(m["H_col"], m["H_val"], 1e-5)
+    cp, cv, cost = partition_multilevel(rp, col, cap)
+    _check_valid(len(rp) - 1, cp, cv, cap)
+    assert cost == _cost(rp, col, cp, cv)
+
+
+def test_cheaper_than_blocks_and_independent_of_numbering():
+    """On the N = 1024 model the communities cost less than blocks of the (already spatially
+    sorted) vertex order, and a random relabelling of the graph costs about the same, where
+    blocks of the relabelled order lose all locality."""
+    m = make_model("n1024")
+    rp, col = graph_x2(m["H_col"], m["H_val"], 1e-5)
+    n = len(rp) - 1
+    _, _, sp, _ = partition(rp, col, 16)
+    block_cost = int((np.diff(sp).astype(np.int64) ** 3).sum())
+    _, _, cost = partition_multilevel(rp, col, 16)
+    assert cost < block_cost
+    perm = np.random.default_rng(5).permutation(n)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    rows = [inv[col[rp[perm[i]]:rp[perm[i] + 1]]] for i in range(n)]
+    rp2, col2 = _csr(rows)
+    _, _, cost2 = partition_multilevel(rp2, col2, 16)
+    _, _, sp2, _ = partition(rp2, col2, 16)
+    shuffled_block = int((np.diff(sp2).astype(np.int64) ** 3).sum())
+    assert abs(cost2 - cost) < 0.1 * cost
+    assert cost2 < shuffled_block
+
+
+@pytest.mark.parametrize("name,cap", [("tiny48", 5), ("tiny48", 16), ("small256", 16),
+                                      ("small256", 7), ("n1024", 32)])
+def test_library_host_entry_point_matches_oracle(name, cap):
+    import paper_1603_00937_amd as gb
+    m = make_model(name)
+    rp, col = graph_x2(m["H_col"], m["H_val"], 1e-5)
+    ocp, ocv, ocost = partition_multilevel(rp, col, cap)
+    ccp, ccv, ccost = gb.partition_host(rp, col, cap)
+    assert np.array_equal(ocp, ccp) and np.array_equal(ocv, ccv)
+    assert ocost == ccost
+
+
+def test_library_host_entry_point_rejects_bad_arguments():
+    import paper_1603_00937_amd as gb
+    rp, col = _csr(_cliques(2, 4))
+    with pytest.raises(gb.GbError):
+        gb.partition_host(rp, col, 0)
+    bad = col.copy()
+    bad[3] = 99
+    with pytest.raises(gb.GbError):
+        gb.partition_host(rp, bad, 4)
