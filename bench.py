@@ -205,7 +205,8 @@ def md_run(args):
     dev = torch.device("cuda:0")
     up = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
     Hc, Hv = up(m["H_col"]), up(m["H_val"])
-    D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], core_size=cfg["core"])
+    p = gb.partition(gb.build_graph(Hc, Hv, cfg["tau"]), cfg["core"], method=args.partition)
+    D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], cfg["tau"], partition=p)
     steps = []
     pos = m["pos"]
     prev_branch = st["branch"] + [0, 1]
@@ -216,7 +217,14 @@ def md_run(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
-        p = gb.partition(g, cfg["core"])
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        # multilevel communities are carried over from the previous step and improved in place
+        # (on-the-fly update); blocks are recut from the vertex order
+        p = (gb.partition_update(g, p, cfg["core"]) if args.partition == "multilevel"
+             else gb.partition(g, cfg["core"]))
+        torch.cuda.synchronize()
+        part_ms = (time.perf_counter() - tp) * 1e3
         # pre-determined sequence (MD section), no trace rule during the expansion: "replay"
         # repeats the previous step's branches plus one X^2 / 2X - X^2 pair as a margin; "gap"
         # builds the sequence from the HOMO/LUMO bracket estimated from the previous step's
@@ -264,7 +272,9 @@ def md_run(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         sizes = np.diff(p.arrays()[1].cpu().numpy())
-        steps.append({"step": t + 1, "ms": dt * 1e3, "iters": st["iters"],
+        steps.append({"step": t + 1, "ms": dt * 1e3, "part_ms": part_ms,
+                      "sum_n3": float((sizes.astype(np.float64) ** 3).sum()),
+                      "iters": st["iters"],
                       "converged": st["converged"], "replayed": replayed,
                       "fallback": fallback, "seq_len": len(seq) if replayed else None,
                       "graph_nnz": g.nnz,

@@ -174,6 +174,24 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
 gb_status gb_partition_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
                             int32_t core_size, int32_t* n_cores, int32_t* core_ptr,
                             int32_t* core_vtx, int64_t* cost);
+/*
+ * On-the-fly update (MD): the cores of `prev` (a partition of a graph on the same vertices,
+ * e.g. the previous step's) carried to graph g and improved by the exact-cost passes of
+ * GB_PART_MULTILEVEL only (vertices in ascending order move to one of their three most tied
+ * neighbouring cores with room when that lowers sum_s (|core| + |halo|)^3; up to four passes),
+ * so the cost on g never exceeds that of the carried cores.  Cores of at most core_size
+ * vertices receive moves; a carried core may exceed it.  Then the subgraphs as in
+ * gb_partition.  GB_ESHAPE if prev covers a different vertex count.
+ */
+gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, int32_t core_size,
+                              void* stream, gb_partition_t** out);
+/* Host form of gb_partition_update on a host CSR graph: prev_core_ptr [prev_n_cores + 1] and
+ * prev_core_vtx [n] (every vertex exactly once); outputs as gb_partition_host. */
+gb_status gb_partition_update_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                   int32_t core_size, int32_t prev_n_cores,
+                                   const int32_t* prev_core_ptr, const int32_t* prev_core_vtx,
+                                   int32_t* n_cores, int32_t* core_ptr, int32_t* core_vtx,
+                                   int64_t* cost);
 /* n_sub subgraphs, the largest has max_sub vertices, total = sum of sizes (host outputs). */
 gb_status gb_partition_info(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
                             int64_t* total);

@@ -289,3 +289,26 @@ def partition_multilevel(row_ptr, col, cap: int):
     core_ptr[1:] = np.cumsum([len(c) for c in cores])
     core_vtx = np.concatenate([np.array(c, dtype=np.int32) for c in cores])
     return core_ptr, core_vtx, int(cost)
+
+
+def partition_update(row_ptr, col, cap: int, prev_core_ptr, prev_core_vtx):
+    """The previous cores carried to a new graph on the same vertices and improved by step 5
+    alone (on-the-fly update between MD steps): (core_ptr, core_vertices, cost)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    n = len(row_ptr) - 1
+    adj0, ew0 = common_neighbour_weights(row_ptr, col)
+    n_parts = len(prev_core_ptr) - 1
+    part = [-1] * n
+    for p in range(n_parts):
+        for i in range(prev_core_ptr[p], prev_core_ptr[p + 1]):
+            part[int(prev_core_vtx[i])] = p
+    cost = refine_cost(adj0, ew0, part, n_parts, cap)
+    members = {}
+    for v in range(n):
+        members.setdefault(part[v], []).append(v)
+    cores = sorted(members.values(), key=lambda c: c[0])
+    core_ptr = np.zeros(len(cores) + 1, dtype=np.int32)
+    core_ptr[1:] = np.cumsum([len(c) for c in cores])
+    core_vtx = np.concatenate([np.array(c, dtype=np.int32) for c in cores])
+    return core_ptr, core_vtx, int(cost)

@@ -198,6 +198,36 @@ def partition(graph: Graph, core_size: int, method="block") -> Partition:
     return Partition(out)
 
 
+def partition_update(graph: Graph, prev: Partition, core_size: int) -> Partition:
+    """The cores of ``prev`` carried to ``graph`` (same vertices) and improved by the exact-cost
+    passes of the multilevel partitioner (on-the-fly update between MD steps)."""
+    out = ctypes.c_void_p()
+    _check(_lib().gb_partition_update(graph.handle, prev.handle, int(core_size), _stream(),
+                                      ctypes.byref(out)))
+    return Partition(out)
+
+
+def partition_update_host(row_ptr, col, core_size, prev_core_ptr, prev_core_vtx):
+    """Host form of partition_update on numpy CSR and core arrays."""
+    import numpy as np
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    pp = np.ascontiguousarray(prev_core_ptr, dtype=np.int32)
+    pv = np.ascontiguousarray(prev_core_vtx, dtype=np.int32)
+    n = len(rp) - 1
+    cp = np.zeros(n + 1, dtype=np.int32)
+    cv = np.zeros(max(n, 1), dtype=np.int32)
+    nc = ctypes.c_int32()
+    cost = ctypes.c_int64()
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    _check(_lib().gb_partition_update_host(n, rp.ctypes.data_as(i32), cl.ctypes.data_as(i32),
+                                           int(core_size), len(pp) - 1, pp.ctypes.data_as(i32),
+                                           pv.ctypes.data_as(i32), ctypes.byref(nc),
+                                           cp.ctypes.data_as(i32), cv.ctypes.data_as(i32),
+                                           ctypes.byref(cost)))
+    return cp[:nc.value + 1].copy(), cv[:n].copy(), int(cost.value)
+
+
 def partition_host(row_ptr, col, core_size):
     """Host: the multilevel cores of a host CSR graph (numpy int32 arrays).  Returns
     (core_ptr, core_vtx, cost) as numpy arrays and the summed (|core| + |halo|)^3."""

@@ -404,23 +404,89 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
   });
 }
 
+namespace {
+
+void check_host_csr(int32_t n, const int32_t* row_ptr, const int32_t* col) {
+  if (n < 1) fail(GB_EINVAL, "n = %d must be >= 1", n);
+  if (row_ptr[0] != 0) fail(GB_EINVAL, "row_ptr[0] must be 0");
+  for (int v = 0; v < n; ++v) {
+    if (row_ptr[v + 1] < row_ptr[v]) fail(GB_EINVAL, "row_ptr decreases at %d", v);
+    for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+      if (col[e] < 0 || col[e] >= n) fail(GB_EINVAL, "col[%d] = %d out of range", e, col[e]);
+  }
+}
+
+void check_cover(int32_t n, int32_t n_cores, const int32_t* ptr, const int32_t* vtx) {
+  if (n_cores < 1) fail(GB_EINVAL, "prev_n_cores = %d must be >= 1", n_cores);
+  if (ptr[0] != 0 || ptr[n_cores] != n) fail(GB_EINVAL, "prev_core_ptr must run from 0 to n");
+  std::vector<char> seen(n, 0);
+  for (int c = 0; c < n_cores; ++c) {
+    if (ptr[c + 1] <= ptr[c]) fail(GB_EINVAL, "previous core %d is empty or ptr decreases", c);
+    for (int i = ptr[c]; i < ptr[c + 1]; ++i) {
+      const int v = vtx[i];
+      if (v < 0 || v >= n || seen[v]) fail(GB_EINVAL, "prev_core_vtx[%d] = %d repeats or is out of range", i, v);
+      seen[v] = 1;
+    }
+  }
+}
+
+}  // namespace
+
 gb_status gb_partition_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
                             int32_t core_size, int32_t* n_cores, int32_t* core_ptr,
                             int32_t* core_vtx, int64_t* cost) {
   return guarded([&] {
     if (!row_ptr || !col || !n_cores || !core_ptr || !core_vtx)
       fail(GB_EINVAL, "row_ptr / col / n_cores / core_ptr / core_vtx is NULL");
-    if (n < 1) fail(GB_EINVAL, "n = %d must be >= 1", n);
     if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
-    if (row_ptr[0] != 0) fail(GB_EINVAL, "row_ptr[0] must be 0");
-    for (int v = 0; v < n; ++v) {
-      if (row_ptr[v + 1] < row_ptr[v]) fail(GB_EINVAL, "row_ptr decreases at %d", v);
-      for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
-        if (col[e] < 0 || col[e] >= n) fail(GB_EINVAL, "col[%d] = %d out of range", e, col[e]);
-    }
+    check_host_csr(n, row_ptr, col);
     std::vector<int32_t> cp, cv;
     MlStats st;
     partition_multilevel(n, row_ptr, col, core_size, cp, cv, &st);
+    *n_cores = (int32_t)cp.size() - 1;
+    std::memcpy(core_ptr, cp.data(), cp.size() * 4);
+    std::memcpy(core_vtx, cv.data(), cv.size() * 4);
+    if (cost) *cost = st.cost;
+  });
+}
+
+gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, int32_t core_size,
+                              void* stream, gb_partition_t** out) {
+  return guarded([&] {
+    if (!out) fail(GB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g || !prev) fail(GB_EINVAL, "graph / prev is NULL");
+    if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
+    hipStream_t s = as_stream(stream);
+    auto* p = new gb_partition_s();
+    try {
+      partition_multilevel_dev(g->csr, core_size, p->part, s, nullptr, &prev->part);
+      GB_HIP(hipStreamSynchronize(s));
+      detach(p->part);
+    } catch (...) {
+      delete p;
+      throw;
+    }
+    *out = p;
+  });
+}
+
+gb_status gb_partition_update_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
+                                   int32_t core_size, int32_t prev_n_cores,
+                                   const int32_t* prev_core_ptr, const int32_t* prev_core_vtx,
+                                   int32_t* n_cores, int32_t* core_ptr, int32_t* core_vtx,
+                                   int64_t* cost) {
+  return guarded([&] {
+    if (!row_ptr || !col || !prev_core_ptr || !prev_core_vtx || !n_cores || !core_ptr ||
+        !core_vtx)
+      fail(GB_EINVAL, "an array argument is NULL");
+    if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
+    check_host_csr(n, row_ptr, col);
+    check_cover(n, prev_n_cores, prev_core_ptr, prev_core_vtx);
+    std::vector<int32_t> pp(prev_core_ptr, prev_core_ptr + prev_n_cores + 1),
+        pv(prev_core_vtx, prev_core_vtx + n), cp, cv;
+    MlStats st;
+    partition_update(n, row_ptr, col, core_size, pp, pv, cp, cv, &st);
     *n_cores = (int32_t)cp.size() - 1;
     std::memcpy(core_ptr, cp.data(), cp.size() * 4);
     std::memcpy(core_vtx, cv.data(), cv.size() * 4);

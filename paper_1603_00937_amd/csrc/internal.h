@@ -148,8 +148,14 @@ struct MlStats {
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
                           MlStats* stats, const int32_t* ew = nullptr);
+// The previous cores carried to a new graph on the same vertices: the exact-cost passes of
+// the multilevel partitioner started from them (on-the-fly update between MD steps).
+void partition_update(int n, const int32_t* row_ptr, const int32_t* col, int cap,
+                      const std::vector<int32_t>& prev_ptr, const std::vector<int32_t>& prev_vtx,
+                      std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
+                      MlStats* stats, const int32_t* ew = nullptr);
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
-                              MlStats* stats);
+                              MlStats* stats, const Part* prev = nullptr);
 void detach(Csr& c);
 void detach(Part& p);
 

@@ -338,20 +338,15 @@ int64_t refine_cost(const Level& g, std::vector<int32_t>& part, int np, int cap,
 
 }  // namespace
 
-void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
-                          std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                          MlStats* stats, const int32_t* ew) {
-  using clk = std::chrono::steady_clock;
-  auto ms_since = [](clk::time_point t) {
-    return std::chrono::duration<double, std::milli>(clk::now() - t).count();
-  };
-  auto t0 = clk::now();
-  double ms_weights = 0, ms_coarsen = 0, ms_grow = 0, ms_cut = 0, ms_cost = 0;
-  std::vector<Level> lv(1);  // lv grows below: levels are addressed by index, not reference
-  {
-  Level& g0 = lv[0];
+namespace {
+
+// Level 0: the input graph without self loops, weights = common closed neighbours (given, or
+// counted here), unit vertex weights.
+void input_level(int n, const int32_t* row_ptr, const int32_t* col, const int32_t* ew, Level& g0) {
   g0.n = n;
   g0.rp.assign(n + 1, 0);
+  g0.adj.clear();
+  g0.ew.clear();
   for (int v = 0; v < n; ++v) {
     for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
       if (col[e] != v) {
@@ -360,11 +355,13 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
       }
     g0.rp[v + 1] = (int32_t)g0.adj.size();
   }
+  g0.vw.assign(n, 1);
+  if (ew) return;
   // edge weight = number of common neighbours (each vertex counted as its own neighbour): the
   // pair's joint halo is smallest for the neighbour sharing most of its neighbourhood
-  if (!ew) g0.ew.assign(g0.adj.size(), 0);
-  std::vector<int32_t> mark(ew ? 0 : n, -1);
-  for (int u = 0; u < (ew ? 0 : n); ++u) {
+  g0.ew.assign(g0.adj.size(), 0);
+  std::vector<int32_t> mark(n, -1);
+  for (int u = 0; u < n; ++u) {
     mark[u] = u;
     for (int e = g0.rp[u]; e < g0.rp[u + 1]; ++e) mark[g0.adj[e]] = u;
     for (int e = g0.rp[u]; e < g0.rp[u + 1]; ++e) {
@@ -374,38 +371,11 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
       g0.ew[e] = c;
     }
   }
-  g0.vw.assign(n, 1);
-  }
-  ms_weights = ms_since(t0);
-  t0 = clk::now();
-  const int ccap = std::max(1, cap / 4);
-  for (int level = 0;; ++level) {
-    Level c;
-    if (!coarsen(lv.back(), ccap, level, c)) break;
-    lv.push_back(std::move(c));
-  }
-  ms_coarsen = ms_since(t0);
-  t0 = clk::now();
-  std::vector<int32_t> part = grow_parts(lv.back(), cap);
-  ms_grow = ms_since(t0);
-  t0 = clk::now();
-  int np = 0;
-  for (int p : part) np = std::max(np, p + 1);
-  for (int l = (int)lv.size() - 1; l >= 0; --l) {
-    if (l < (int)lv.size() - 1) {
-      std::vector<int32_t> fine(lv[l].n);
-      for (int v = 0; v < lv[l].n; ++v) fine[v] = part[lv[l].cmap[v]];
-      part.swap(fine);
-    }
-    std::vector<int32_t> pw(np, 0);
-    for (int v = 0; v < lv[l].n; ++v) pw[part[v]] += lv[l].vw[v];
-    refine_cut(lv[l], part, pw, cap, 4);
-  }
-  ms_cut = ms_since(t0);
-  t0 = clk::now();
-  const int64_t cost = refine_cost(lv[0], part, np, cap, 4);
-  ms_cost = ms_since(t0);
-  // parts in ascending order of their smallest vertex, vertices ascending; empty parts dropped
+}
+
+// Non-empty parts in ascending order of their smallest vertex, vertices ascending.
+void emit_cores(int n, const std::vector<int32_t>& part, int np, std::vector<int32_t>& core_ptr,
+                std::vector<int32_t>& core_vtx) {
   std::vector<int32_t> first(np, INT_MAX), rank(np, -1), size(np, 0);
   for (int v = 0; v < n; ++v) {
     first[part[v]] = std::min(first[part[v]], v);
@@ -423,6 +393,51 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
   core_vtx.assign(n, 0);
   std::vector<int32_t> fill(core_ptr.begin(), core_ptr.end() - 1);
   for (int v = 0; v < n; ++v) core_vtx[fill[rank[part[v]]]++] = v;
+}
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t).count();
+}
+
+}  // namespace
+
+void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
+                          std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
+                          MlStats* stats, const int32_t* ew) {
+  auto t0 = clk::now();
+  std::vector<Level> lv(1);  // lv grows below: levels are addressed by index, not reference
+  input_level(n, row_ptr, col, ew, lv[0]);
+  const double ms_weights = ms_since(t0);
+  t0 = clk::now();
+  const int ccap = std::max(1, cap / 4);
+  for (int level = 0;; ++level) {
+    Level c;
+    if (!coarsen(lv.back(), ccap, level, c)) break;
+    lv.push_back(std::move(c));
+  }
+  const double ms_coarsen = ms_since(t0);
+  t0 = clk::now();
+  std::vector<int32_t> part = grow_parts(lv.back(), cap);
+  const double ms_grow = ms_since(t0);
+  t0 = clk::now();
+  int np = 0;
+  for (int p : part) np = std::max(np, p + 1);
+  for (int l = (int)lv.size() - 1; l >= 0; --l) {
+    if (l < (int)lv.size() - 1) {
+      std::vector<int32_t> fine(lv[l].n);
+      for (int v = 0; v < lv[l].n; ++v) fine[v] = part[lv[l].cmap[v]];
+      part.swap(fine);
+    }
+    std::vector<int32_t> pw(np, 0);
+    for (int v = 0; v < lv[l].n; ++v) pw[part[v]] += lv[l].vw[v];
+    refine_cut(lv[l], part, pw, cap, 4);
+  }
+  const double ms_cut = ms_since(t0);
+  t0 = clk::now();
+  const int64_t cost = refine_cost(lv[0], part, np, cap, 4);
+  const double ms_cost = ms_since(t0);
+  emit_cores(n, part, np, core_ptr, core_vtx);
   if (stats) {
     stats->levels = (int)lv.size();
     stats->coarsest = lv.back().n;
@@ -432,6 +447,30 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
     stats->ms_grow = ms_grow;
     stats->ms_cut = ms_cut;
     stats->ms_cost = ms_cost;
+  }
+}
+
+void partition_update(int n, const int32_t* row_ptr, const int32_t* col, int cap,
+                      const std::vector<int32_t>& prev_ptr, const std::vector<int32_t>& prev_vtx,
+                      std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
+                      MlStats* stats, const int32_t* ew) {
+  auto t0 = clk::now();
+  Level g0;
+  input_level(n, row_ptr, col, ew, g0);
+  const double ms_weights = ms_since(t0);
+  t0 = clk::now();
+  const int np = (int)prev_ptr.size() - 1;
+  std::vector<int32_t> part(n, -1);
+  for (int p = 0; p < np; ++p)
+    for (int i = prev_ptr[p]; i < prev_ptr[p + 1]; ++i) part[prev_vtx[i]] = p;
+  const int64_t cost = refine_cost(g0, part, np, cap, 4);
+  emit_cores(n, part, np, core_ptr, core_vtx);
+  if (stats) {
+    stats->levels = 1;
+    stats->coarsest = n;
+    stats->cost = cost;
+    stats->ms_weights = ms_weights;
+    stats->ms_cost = ms_since(t0);
   }
 }
 

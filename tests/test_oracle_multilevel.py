@@ -131,3 +131,47 @@ def test_library_host_entry_point_rejects_bad_arguments():
     bad[3] = 99
     with pytest.raises(gb.GbError):
         gb.partition_host(rp, bad, 4)
+
+
+def _displaced(name, steps=1, seed=52):
+    from synth import displace_sites, rebuild_hamiltonian
+    m = make_model(name)
+    rng = np.random.default_rng(seed)
+    pos = m["pos"]
+    for _ in range(steps):
+        pos = displace_sites(pos, m["L"], 0.02, rng)
+        m = rebuild_hamiltonian(m, pos)
+    return m
+
+
+@pytest.mark.parametrize("start", ["multilevel", "block"])
+def test_update_never_raises_the_cost(start):
+    """Cores carried to the graph of a displaced system and improved by the exact-cost passes:
+    valid, no costlier than the carried cores, and the library's host entry point gives the
+    same cores."""
+    import paper_1603_00937_amd as gb
+    from oracle.multilevel import partition_update
+    m0 = make_model("small256")
+    rp0, col0 = graph_x2(m0["H_col"], m0["H_val"], 1e-5)
+    if start == "multilevel":
+        pcp, pcv, _ = partition_multilevel(rp0, col0, 16)
+    else:
+        pcp, pcv, _, _ = partition(rp0, col0, 16)
+    m1 = _displaced("small256", 3)
+    rp1, col1 = graph_x2(m1["H_col"], m1["H_val"], 1e-5)
+    carried = _cost(rp1, col1, pcp, pcv)
+    cp, cv, cost = partition_update(rp1, col1, 16, pcp, pcv)
+    _check_valid(len(rp1) - 1, cp, cv, 16)
+    assert cost == _cost(rp1, col1, cp, cv)
+    assert cost <= carried
+    ccp, ccv, ccost = gb.partition_update_host(rp1, col1, 16, pcp, pcv)
+    assert np.array_equal(cp, ccp) and np.array_equal(cv, ccv) and cost == ccost
+
+
+def test_update_rejects_a_bad_cover():
+    import paper_1603_00937_amd as gb
+    rp, col = _csr(_cliques(2, 4))
+    with pytest.raises(gb.GbError):
+        gb.partition_update_host(rp, col, 4, np.array([0, 4, 8]), np.array([0, 1, 2, 3, 4, 5, 6, 6]))
+    with pytest.raises(gb.GbError):
+        gb.partition_update_host(rp, col, 4, np.array([0, 4, 7]), np.arange(8))
