@@ -401,7 +401,7 @@ gb_status gb_sp2_sequence(double emin, double emax, double e_homo, double e_lumo
  * maps, which shrinks their relative error at every square root.  The bracket holds to fourth
  * order in the distances and to the rounding of the traces; a sequence from the bounds
  * (gb_sp2_sequence) is long enough for the spectrum the traces came from.
- * floor <= 0 takes max(100 (|t1 - n_occ| + |t1 - t2|) at the last iterate, 1e-12 n_occ).
+ * floor <= 0 takes max(10 (|t1 - n_occ| + |t1 - t2|) at the last iterate, 1e-12 n_occ).
  * GB_EINVAL for NULL pointers, n_branch < 1, emax <= emin, a branch other than 0/1, or when a
  * side has no usable iterate above the floor (an expansion that did not converge). */
 typedef struct {

@@ -16,3 +16,9 @@ def density_exact(H: np.ndarray, n_occ: int):
     D = Vo @ Vo.T
     gap = float(w[n_occ] - w[n_occ - 1]) if 0 < n_occ < H.shape[0] else np.inf
     return D, w, gap
+
+
+def frontier_levels(H: np.ndarray, n_occ: int):
+    """(e_homo, e_lumo): the n_occ-th and (n_occ+1)-th eigenvalues of a dense symmetric H."""
+    w = np.linalg.eigvalsh(H)
+    return float(w[n_occ - 1]), float(w[n_occ])

@@ -32,7 +32,7 @@ The two bracket the LUMO image; the U side brackets the HOMO the same way.  The 
 maps (a squaring: d -> sqrt(d); the other branch: d -> d / (1 + sqrt(1 - d)) on the distance d)
 take them back to step 0; every square root halves the relative error, so the latest clean
 iterates whose sums are above a noise floor give the tightest bracket.  The default floor is
-100 times the last iterate's |t1 - n_occ| + |t1 - t2| (the rounding and truncation level of
+10 times the last iterate's |t1 - n_occ| + |t1 - t2| (the rounding and truncation level of
 partitioned traces), and at least 1e-12 n_occ.  A sequence built from the bound is long enough
 for the expansion the traces came from.
 
@@ -117,7 +117,7 @@ def _solve_ratio(rho, seg, side, n_bisect=200):
 
 def default_floor(traces, n_occ):
     t1, t2 = traces[-1]
-    return max(100.0 * (abs(t1 - n_occ) + abs(t1 - t2)), 1e-12 * n_occ)
+    return max(10.0 * (abs(t1 - n_occ) + abs(t1 - t2)), 1e-12 * n_occ)
 
 
 def estimate_gap(traces, branches, n_occ, emin, emax, floor=None):

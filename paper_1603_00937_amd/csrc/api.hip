@@ -707,7 +707,7 @@ gb_status gb_sp2_estimate_gap(const double* t1, const double* t2, const uint8_t*
       if (branch[i] > 1) fail(GB_EINVAL, "branch[%d] = %d is not 0 or 1", i, (int)branch[i]);
     const int nb = n_branch;
     if (!(floor > 0.0))
-      floor = std::max(100.0 * (std::fabs(t1[nb] - n_occ) + std::fabs(t1[nb] - t2[nb])),
+      floor = std::max(10.0 * (std::fabs(t1[nb] - n_occ) + std::fabs(t1[nb] - t2[nb])),
                        1e-12 * n_occ);
     // per-iterate sums of the distances: side 0 (unoccupied) L = (A + B)/2, side 1 (occupied)
     // U = (A - B)/2, A = t1 - t2, B = t1 - n_occ

@@ -1135,8 +1135,12 @@ __global__ __launch_bounds__(kT) void k_idem(const T* __restrict__ X, const T* _
 // slab as they read a block.  Since X is symmetric, the core rows of q(X) are the transposed
 // core columns, and V q(X) for a slab V needs only products V X.
 
-// W = V X: one thread per column c of W, 256 columns per workgroup, V staged in LDS in chunks of
-// 64 columns; X is read once, coalesced along its rows.
+// W = V X on the FP64 matrix cores: a wave computes all KMAX rows of 64 columns of W
+// (KMAX/16 x 4 tiles of 16 x 16, v_mfma_f64_16x16x4).  Per step of 4 rows of X, lane l
+// supplies A = V[16m + l%16][a + l/16] and B = X[a + l/16][c + 16n + l%16] (16 consecutive
+// columns per lane group, so every row segment is one 128-byte read); X is read once, V (a few
+// hundred KB per block) from cache.  Rows of V beyond k_s read as zero.  Output register r of
+// lane l holds row 4r + l/16 of its tile.
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
                                                  const int64_t* __restrict__ offs,
@@ -1145,42 +1149,49 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
                                                  double* __restrict__ W,
                                                  const int64_t* __restrict__ soffs,
                                                  const int32_t* __restrict__ core_ptr) {
-  __shared__ double vt[KMAX][64];
+  using M = Mfma<double>;
+  constexpr int MT = KMAX / 16, NT = 4;
   const int s = blockIdx.y;
   const int np = npad[s];
-  const int c0 = blockIdx.x * 256;
-  if (c0 >= np) return;  // the whole workgroup leaves together
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cw = blockIdx.x * 256 + wave * 64;
+  if (cw >= np) return;  // np is a multiple of 64: a wave is wholly inside or outside
   const int k = core_ptr[s + 1] - core_ptr[s];
-  const int c = c0 + threadIdx.x;
-  const bool live = c < np;
-  const double* xs = X + offs[s];
-  const double* vs = V + soffs[s];
-  double acc[KMAX];
+  const int i16 = lane & 15, kq = lane >> 4;
+  const double* xs = X + offs[s] + (int64_t)kq * np + cw + i16;
+  const double* vs = V + soffs[s] + kq;
+  M::acc_t acc[MT][NT];
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-  for (int a0 = 0; a0 < np; a0 += 64) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < KMAX * 64; e += 256) {
-      const int j = e >> 6, a = e & 63;
-      vt[j][a] = j < k ? vs[(int64_t)j * np + a0 + a] : 0.0;
-    }
-    __syncthreads();
-    if (live) {
-      const double* xr = xs + (int64_t)a0 * np + c;
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NT; ++n) acc[m][n] = M::acc_t{0, 0, 0, 0};
+  bool rows_in[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) rows_in[m] = m * 16 + i16 < k;
 #pragma unroll 4
-      for (int a = 0; a < 64; ++a) {
-        const double x = xr[(int64_t)a * np];
+  for (int a = 0; a < np; a += 4) {
+    double fa[MT], fb[NT];
 #pragma unroll
-        for (int j = 0; j < KMAX; ++j) acc[j] = fma(vt[j][a], x, acc[j]);
+    for (int m = 0; m < MT; ++m)
+      fa[m] = rows_in[m] ? vs[(int64_t)(m * 16 + i16) * np + a] : 0.0;
+#pragma unroll
+    for (int n = 0; n < NT; ++n) fb[n] = xs[(int64_t)a * np + n * 16];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[m][n] = M::mma(fa[m], fb[n], acc[m][n]);
+  }
+  double* ws = W + soffs[s] + cw + i16;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = m * 16 + M::row(lane, r);
+      if (j < k) {
+#pragma unroll
+        for (int n = 0; n < NT; ++n) ws[(int64_t)j * np + n * 16] = acc[m][n][r];
       }
     }
-  }
-  if (live) {
-    double* ws = W + soffs[s];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) ws[(int64_t)j * np + c] = acc[j];
-  }
 }
 
 // W = the first k_s rows of X (= E X for the core unit rows E)

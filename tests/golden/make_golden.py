@@ -1,7 +1,7 @@
 """Writes the stored expected values under tests/golden/ (calls only synth and oracle).
 
 Usage: python tests/golden/make_golden.py [hashes] [n1024] [n18000] [n100000] [n1024_ml]
-                                          [n18000_ml]
+                                          [n18000_ml] [n18000_levels]
 (the _ml variants use the multilevel cores instead of blocks of the vertex order)
 Every value written here comes from the CPU oracle in oracle/ run on the seeded
 inputs from synth/; nothing comes from the GPU library.
@@ -18,6 +18,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from synth import make_model, ell_sha256  # noqa: E402
 from oracle.sp2 import density_partitioned  # noqa: E402
+from oracle.exact import frontier_levels  # noqa: E402
+from oracle.bounds import ell_to_dense  # noqa: E402
 
 
 def write_hashes():
@@ -64,6 +66,16 @@ def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory
     return rec
 
 
+def write_levels(name):
+    """HOMO and LUMO of the model by dense diagonalisation."""
+    m = make_model(name)
+    t = time.time()
+    eh, el = frontier_levels(ell_to_dense(m["H_col"], m["H_val"]), m["n_occ"])
+    rec = {"model": name, "H_sha256": ell_sha256(m["H_col"], m["H_val"]), "n_occ": m["n_occ"],
+           "e_homo": eh.hex(), "e_lumo": el.hex(), "oracle_seconds": time.time() - t}
+    json.dump(rec, open(os.path.join(HERE, f"{name}_levels.json"), "w"), indent=1)
+
+
 if __name__ == "__main__":
     what = sys.argv[1:] or ["hashes", "n1024"]
     if "hashes" in what:
@@ -76,5 +88,7 @@ if __name__ == "__main__":
         write_partitioned("n100000", 1e-5, 32, low_memory=True)
     if "n1024_ml" in what:
         write_partitioned("n1024", 1e-5, 16, method="multilevel")
+    if "n18000_levels" in what:
+        write_levels("n18000")
     if "n18000_ml" in what:
         write_partitioned("n18000", 1e-5, 32, method="multilevel", low_memory=True)

@@ -147,3 +147,23 @@ def test_n100000_sampled_graph_partition_and_properties(gb):
         sub = np.sort(si[sp[c]:sp[c + 1]])
         for v in range(cp[c], cp[c + 1]):
             assert np.array_equal(dc[v, :len(sub)], sub)
+
+
+def test_n18000_gap_bracket_from_gpu_traces(gb):
+    """The HOMO/LUMO bracket from the GPU expansion's traces holds the dense diagonalisation's
+    levels (stored) and equals the oracle estimator's on the same traces."""
+    from oracle.sequence import estimate_gap
+    ref, st, err = _run(gb, "n18000", "fp64")
+    lv = json.load(open(os.path.join(GOLDEN, "n18000_levels.json")))
+    inp = gb.gap_inputs(st, ref["n_occ"])
+    est = gb.sp2_estimate_gap(**inp)
+    o = estimate_gap(list(zip(inp["t1"], inp["t2"])), inp["branch"], ref["n_occ"], inp["emin"],
+                     inp["emax"])
+    W = inp["emax"] - inp["emin"]
+    for k in ("homo_bound", "lumo_bound", "homo_ratio", "lumo_ratio"):
+        assert abs(est[k] - o[k]) <= 1e-12 * W
+    eh, el = float.fromhex(lv["e_homo"]), float.fromhex(lv["e_lumo"])
+    print(f"n18000: homo {eh:.5f} in [{est['homo_ratio']:.5f}, {est['homo_bound']:.5f}], "
+          f"lumo {el:.5f} in [{est['lumo_bound']:.5f}, {est['lumo_ratio']:.5f}]")
+    assert est["homo_ratio"] <= eh <= est["homo_bound"]
+    assert est["lumo_bound"] <= el <= est["lumo_ratio"]

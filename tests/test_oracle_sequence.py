@@ -164,3 +164,24 @@ def test_estimate_needs_usable_iterates():
     # a floor above every sum
     with pytest.raises(ValueError):
         estimate_gap(info["traces"], info["branch"], 2, -2.0, 2.0, floor=1.0)
+
+
+def test_n18000_traces_bracket_the_levels():
+    """The full-size system: the oracle's recorded traces (stored run) bracket the HOMO and LUMO
+    of its dense diagonalisation (stored), within 3 % of the spectral range."""
+    import json
+    import os
+    gdir = os.path.join(os.path.dirname(__file__), "golden")
+    ref = json.load(open(os.path.join(gdir, "n18000_fp64_partitioned.json")))
+    lv = json.load(open(os.path.join(gdir, "n18000_levels.json")))
+    assert ref["H_sha256"] == lv["H_sha256"]
+    tr = [(float.fromhex(a), float.fromhex(b)) for a, b in ref["traces"]]
+    br = [int(c) for c in ref["branch"]]
+    lo, hi = float.fromhex(ref["emin"]), float.fromhex(ref["emax"])
+    e = estimate_gap(tr, br, ref["n_occ"], lo, hi)
+    eh, el = float.fromhex(lv["e_homo"]), float.fromhex(lv["e_lumo"])
+    W = hi - lo
+    assert e["homo_ratio"] <= eh <= e["homo_bound"]
+    assert e["lumo_bound"] <= el <= e["lumo_ratio"]
+    assert e["homo_bound"] - e["homo_ratio"] < 0.04 * W
+    assert e["lumo_ratio"] - e["lumo_bound"] < 0.04 * W
