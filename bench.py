@@ -238,7 +238,9 @@ def md_run(args):
                 est = gb.sp2_estimate_gap(**gb.gap_inputs(st, m["n_occ"]))
                 hb, lb = est["homo_bound"], est["lumo_bound"]
                 lo, hi = gb.spectral_bounds(Hc, Hv)
-                seq = gb.sp2_sequence(lo, hi, hb + 0.05 * (lb - hb), lb - 0.05 * (lb - hb))
+                # both frontier images within 1 % of the stop tolerance of 0 or 1
+                delta = 1e-12 * m["N"] / 1024.0
+                seq = gb.sp2_sequence(lo, hi, hb + 0.05 * (lb - hb), lb - 0.05 * (lb - hb), delta)
             except gb.GbError:
                 seq = None
         replayed = seq is not None

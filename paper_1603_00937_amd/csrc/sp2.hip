@@ -1165,21 +1165,35 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = M::acc_t{0, 0, 0, 0};
+  // rows beyond k read row k - 1 (in bounds) and are zeroed by a select, so the loop has no
+  // branches and its loads can be issued U steps ahead of their products
   bool rows_in[MT];
+  int64_t roff[MT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) rows_in[m] = m * 16 + i16 < k;
-#pragma unroll 4
-  for (int a = 0; a < np; a += 4) {
-    double fa[MT], fb[NT];
+  for (int m = 0; m < MT; ++m) {
+    rows_in[m] = m * 16 + i16 < k;
+    roff[m] = (int64_t)min(m * 16 + i16, k - 1) * np;
+  }
+  constexpr int U = 8;  // np is a multiple of 64 = 4 U rows
+  for (int a0 = 0; a0 < np; a0 += 4 * U) {
+    double fa[U][MT], fb[U][NT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
-      fa[m] = rows_in[m] ? vs[(int64_t)(m * 16 + i16) * np + a] : 0.0;
+    for (int u = 0; u < U; ++u) {
+      const int a = a0 + 4 * u;
 #pragma unroll
-    for (int n = 0; n < NT; ++n) fb[n] = xs[(int64_t)a * np + n * 16];
+      for (int m = 0; m < MT; ++m) {
+        const double va = vs[roff[m] + a];
+        fa[u][m] = rows_in[m] ? va : 0.0;
+      }
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+      for (int n = 0; n < NT; ++n) fb[u][n] = xs[(int64_t)a * np + n * 16];
+    }
 #pragma unroll
-      for (int n = 0; n < NT; ++n) acc[m][n] = M::mma(fa[m], fb[n], acc[m][n]);
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = M::mma(fa[u][m], fb[u][n], acc[m][n]);
   }
   double* ws = W + soffs[s] + cw + i16;
 #pragma unroll
