@@ -219,9 +219,9 @@ def md_run(args):
         g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        # multilevel communities are carried over from the previous step and improved in place
+        # multilevel communities are carried over from the previous step with new halos
         # (on-the-fly update); blocks are recut from the vertex order
-        p = (gb.partition_update(g, p, cfg["core"]) if args.partition == "multilevel"
+        p = (gb.partition_update(g, p) if args.partition == "multilevel"
              else gb.partition(g, cfg["core"]))
         torch.cuda.synchronize()
         part_ms = (time.perf_counter() - tp) * 1e3

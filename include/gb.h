@@ -159,14 +159,14 @@ gb_status gb_partition(const gb_graph_t* g, int32_t core_size, int32_t method, v
                        gb_partition_t** out);
 /*
  * Host: the cores GB_PART_MULTILEVEL chooses for a host CSR graph (row_ptr [n+1], col [nnz],
- * symmetric; self loops ignored).  Heavy-edge matching coarsens the graph (pairs up to
- * core_size/4 vertices, a fixed pseudo-random visiting order: vertices sorted by SplitMix64 of
+ * symmetric; self loops ignored).  Edges are weighted by the number of common closed
+ * neighbours of their ends; heavy-edge matching coarsens the graph (pairs up to core_size/4
+ * vertices, a fixed pseudo-random visiting order: vertices sorted by SplitMix64 of
  * (level << 32 | v)) until no pair can be matched; parts of at most core_size vertices are
  * grown on the coarsest graph (seeds in breadth-first order, each part taking the unassigned
- * neighbour most strongly tied to it); at every level back, boundary vertices move to the
- * neighbouring part that cuts most edge weight and has room; on the input graph vertices move
- * when that lowers sum_s (|core| + |halo|)^3 exactly.  All choices have fixed tie-breaks, so
- * the cores are a function of the graph.  Outputs (host, caller-owned): *n_cores; core_ptr
+ * neighbour most strongly tied to it) and projected back to the input graph.  All choices
+ * have fixed tie-breaks, so the cores are a function of the graph.  Outputs (host,
+ * caller-owned): *n_cores; core_ptr
  * [n_cores + 1] (room for n + 1); core_vtx [n] (each core ascending, cores in ascending order
  * of their smallest vertex); *cost = sum_s (|core| + |halo|)^3 (any of cost may be NULL).
  * GB_EINVAL for NULL arrays, n < 1 or core_size < 1.
@@ -176,22 +176,19 @@ gb_status gb_partition_host(int32_t n, const int32_t* row_ptr, const int32_t* co
                             int32_t* core_vtx, int64_t* cost);
 /*
  * On-the-fly update (MD): the cores of `prev` (a partition of a graph on the same vertices,
- * e.g. the previous step's) carried to graph g and improved by the exact-cost passes of
- * GB_PART_MULTILEVEL only (vertices in ascending order move to one of their three most tied
- * neighbouring cores with room when that lowers sum_s (|core| + |halo|)^3; up to four passes),
- * so the cost on g never exceeds that of the carried cores.  Cores of at most core_size
- * vertices receive moves; a carried core may exceed it.  Then the subgraphs as in
- * gb_partition.  GB_ESHAPE if prev covers a different vertex count.
+ * e.g. the previous step's) carried to graph g, renumbered as gb_partition_host emits cores,
+ * and their subgraphs on g as in gb_partition.  No edge weights or coarsening are computed, so
+ * the cost is that of building the halos.  GB_ESHAPE if prev covers a different vertex count.
  */
-gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, int32_t core_size,
-                              void* stream, gb_partition_t** out);
+gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, void* stream,
+                              gb_partition_t** out);
 /* Host form of gb_partition_update on a host CSR graph: prev_core_ptr [prev_n_cores + 1] and
- * prev_core_vtx [n] (every vertex exactly once); outputs as gb_partition_host. */
+ * prev_core_vtx [n] (every vertex exactly once); outputs as gb_partition_host (the cost on the
+ * new graph). */
 gb_status gb_partition_update_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
-                                   int32_t core_size, int32_t prev_n_cores,
-                                   const int32_t* prev_core_ptr, const int32_t* prev_core_vtx,
-                                   int32_t* n_cores, int32_t* core_ptr, int32_t* core_vtx,
-                                   int64_t* cost);
+                                   int32_t prev_n_cores, const int32_t* prev_core_ptr,
+                                   const int32_t* prev_core_vtx, int32_t* n_cores,
+                                   int32_t* core_ptr, int32_t* core_vtx, int64_t* cost);
 /* n_sub subgraphs, the largest has max_sub vertices, total = sum of sizes (host outputs). */
 gb_status gb_partition_info(const gb_partition_t* p, int32_t* n_sub, int32_t* max_sub,
                             int64_t* total);

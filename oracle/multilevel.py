@@ -16,20 +16,18 @@ implements, step by step, so that the library's cores can be checked index for i
    smallest vertex, neighbours ascending); a part repeatedly takes the unassigned vertex
    maximising (summed edge weight to the part, -vertex weight, -index) that keeps it within
    cap.
-4. From the coarsest level down to the input graph (the partition projected at each step),
-   up to 4 passes: each vertex in ascending order moves to the neighbouring part with the
-   largest positive gain in edge weight to it (ties: smaller part index) if that part has room.
-5. On the input graph, up to 4 passes: each vertex in ascending order considers its three most
-   tied neighbouring parts with room (by summed edge weight to them, ties by smaller index) and
-   moves to the first of them that lowers sum (k_p + h_p)^3 most (strictly), k_p the core size
-   and h_p the number of vertices outside p adjacent to p.
-6. Non-empty parts in ascending order of their smallest vertex, vertices ascending.
+4. The parts are projected back to the input graph; non-empty parts in ascending order of
+   their smallest vertex, vertices ascending.
+The cost returned is sum (k_p + h_p)^3, k_p the core size and h_p the number of vertices
+outside p adjacent to p.  The on-the-fly update carries given cores to a new graph on the same
+vertices (renumbered as in step 4) and returns their cost there.
 
 Pins (tests): every vertex in exactly one core of at most cap vertices; the reported cost
 equals sum (|core| + |halo|)^3 recomputed from the halos; hand-checkable graphs (disjoint
 cliques of cap vertices are found exactly, a path is cut into consecutive runs); the cores do
-not depend on the vertex numbering of a clique graph; a random relabelling of a spatial model
-gives cores of about the same cost.
+not depend on the vertex numbering of a clique graph; a spatial model gets cheaper cores than
+blocks of its sorted vertex order, and a random relabelling of it gets cores of about the same
+cost.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -167,88 +165,27 @@ def grow_parts(adj, ew, vw, cap):
     return part
 
 
-def refine_cut(adj, ew, vw, part, pw, cap, passes=4):
-    for _ in range(passes):
-        moved = 0
-        for v in range(len(adj)):
-            a = part[v]
-            conn = {}
-            for u, w in zip(adj[v], ew[v]):
-                conn[part[u]] = conn.get(part[u], 0) + w
-            own = conn.get(a, 0)
-            best, key = -1, None
-            for b, cb in conn.items():
-                if b == a or pw[b] + vw[v] > cap:
-                    continue
-                gain = cb - own
-                if gain > 0 and (key is None or (gain, -b) > key):
-                    best, key = b, (gain, -b)
-            if best >= 0:
-                part[v] = best
-                pw[a] -= vw[v]
-                pw[best] += vw[v]
-                moved += 1
-        if not moved:
-            break
-
-
-def refine_cost(adj, ew, part, n_parts, cap, passes=4):
-    """Moves lowering sum (k_p + h_p)^3; returns the final cost."""
-    n = len(adj)
-    cnt = [dict() for _ in range(n)]   # cnt[u][p]: neighbours of u in part p
-    for u in range(n):
-        for x in adj[u]:
-            cnt[u][part[x]] = cnt[u].get(part[x], 0) + 1
+def subgraph_cost(adj, part, n_parts):
+    """sum over parts of (k_p + h_p)^3."""
     k = [0] * n_parts
-    h = [0] * n_parts
+    halo = [set() for _ in range(n_parts)]
+    for u in range(len(adj)):
+        k[part[u]] += 1
+        for x in adj[u]:
+            if part[x] != part[u]:
+                halo[part[x]].add(u)
+    return sum((k[p] + len(halo[p])) ** 3 for p in range(n_parts))
+
+
+def _emit(part, n):
+    members = {}
     for v in range(n):
-        k[part[v]] += 1
-    for u in range(n):
-        for p, c in cnt[u].items():
-            if c > 0 and p != part[u]:
-                h[p] += 1
-    cost = sum((k[p] + h[p]) ** 3 for p in range(n_parts))
-    for _ in range(passes):
-        moved = 0
-        for v in range(n):
-            a = part[v]
-            dha = 1 if cnt[v].get(a, 0) > 0 else 0
-            for u in adj[v]:
-                if part[u] != a and cnt[u].get(a, 0) == 1:
-                    dha -= 1
-            conn = {}
-            for u, w in zip(adj[v], ew[v]):
-                if part[u] != a:
-                    conn[part[u]] = conn.get(part[u], 0) + w
-            cands = sorted((b for b in conn if k[b] + 1 <= cap), key=lambda b: (-conn[b], b))[:3]
-            before_a = (k[a] + h[a]) ** 3
-            after_a = (k[a] - 1 + h[a] + dha) ** 3
-            best, best_d, best_dhb = -1, 0, 0
-            for b in cands:
-                dhb = -1 if cnt[v].get(b, 0) > 0 else 0
-                for u in adj[v]:
-                    if part[u] != b and cnt[u].get(b, 0) == 0:
-                        dhb += 1
-                d = after_a - before_a + (k[b] + 1 + h[b] + dhb) ** 3 - (k[b] + h[b]) ** 3
-                if d < best_d:
-                    best, best_d, best_dhb = b, d, dhb
-            if best < 0:
-                continue
-            for u in adj[v]:
-                cnt[u][a] -= 1
-                if cnt[u][a] == 0:
-                    del cnt[u][a]
-                cnt[u][best] = cnt[u].get(best, 0) + 1
-            h[a] += dha
-            h[best] += best_dhb
-            k[a] -= 1
-            k[best] += 1
-            part[v] = best
-            cost += best_d
-            moved += 1
-        if not moved:
-            break
-    return cost
+        members.setdefault(part[v], []).append(v)
+    cores = sorted(members.values(), key=lambda c: c[0])
+    core_ptr = np.zeros(len(cores) + 1, dtype=np.int32)
+    core_ptr[1:] = np.cumsum([len(c) for c in cores])
+    core_vtx = np.concatenate([np.array(c, dtype=np.int32) for c in cores])
+    return core_ptr, core_vtx
 
 
 def partition_multilevel(row_ptr, col, cap: int):
@@ -272,43 +209,25 @@ def partition_multilevel(row_ptr, col, cap: int):
         level += 1
     part = grow_parts(*levels[-1], cap)
     n_parts = max(part) + 1
-    for l in range(len(levels) - 1, -1, -1):
-        if l < len(levels) - 1:
-            part = [part[cmaps[l][v]] for v in range(len(levels[l][0]))]
-        adj, ew, vw = levels[l]
-        pw = [0] * n_parts
-        for v in range(len(adj)):
-            pw[part[v]] += vw[v]
-        refine_cut(adj, ew, vw, part, pw, cap)
-    cost = refine_cost(adj0, ew0, part, n_parts, cap)
-    members = {}
-    for v in range(n):
-        members.setdefault(part[v], []).append(v)
-    cores = sorted(members.values(), key=lambda c: c[0])
-    core_ptr = np.zeros(len(cores) + 1, dtype=np.int32)
-    core_ptr[1:] = np.cumsum([len(c) for c in cores])
-    core_vtx = np.concatenate([np.array(c, dtype=np.int32) for c in cores])
+    for l in range(len(levels) - 2, -1, -1):
+        part = [part[cmaps[l][v]] for v in range(len(levels[l][0]))]
+    cost = subgraph_cost(adj0, part, n_parts)
+    core_ptr, core_vtx = _emit(part, n)
     return core_ptr, core_vtx, int(cost)
 
 
-def partition_update(row_ptr, col, cap: int, prev_core_ptr, prev_core_vtx):
-    """The previous cores carried to a new graph on the same vertices and improved by step 5
-    alone (on-the-fly update between MD steps): (core_ptr, core_vertices, cost)."""
+def partition_update(row_ptr, col, prev_core_ptr, prev_core_vtx):
+    """Given cores carried to a new graph on the same vertices (on-the-fly update between MD
+    steps): (core_ptr, core_vertices, cost on the new graph)."""
     row_ptr = np.asarray(row_ptr, dtype=np.int64)
     col = np.asarray(col, dtype=np.int64)
     n = len(row_ptr) - 1
-    adj0, ew0 = common_neighbour_weights(row_ptr, col)
+    adj = [[int(v) for v in col[row_ptr[u]:row_ptr[u + 1]] if v != u] for u in range(n)]
     n_parts = len(prev_core_ptr) - 1
     part = [-1] * n
     for p in range(n_parts):
         for i in range(prev_core_ptr[p], prev_core_ptr[p + 1]):
             part[int(prev_core_vtx[i])] = p
-    cost = refine_cost(adj0, ew0, part, n_parts, cap)
-    members = {}
-    for v in range(n):
-        members.setdefault(part[v], []).append(v)
-    cores = sorted(members.values(), key=lambda c: c[0])
-    core_ptr = np.zeros(len(cores) + 1, dtype=np.int32)
-    core_ptr[1:] = np.cumsum([len(c) for c in cores])
-    core_vtx = np.concatenate([np.array(c, dtype=np.int32) for c in cores])
+    cost = subgraph_cost(adj, part, n_parts)
+    core_ptr, core_vtx = _emit(part, n)
     return core_ptr, core_vtx, int(cost)

@@ -104,9 +104,9 @@ SIGNATURES = {
                                            ctypes.c_int32, _P(ctypes.c_int32),
                                            _P(ctypes.c_int32), _P(ctypes.c_int32),
                                            _P(ctypes.c_int64)]),
-    "gb_partition_update": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _vp, _P(_vp)]),
+    "gb_partition_update": (ctypes.c_int32, [_vp, _vp, _vp, _P(_vp)]),
     "gb_partition_update_host": (ctypes.c_int32, [ctypes.c_int32, _P(ctypes.c_int32),
-                                                  _P(ctypes.c_int32), ctypes.c_int32,
+                                                  _P(ctypes.c_int32),
                                                   ctypes.c_int32, _P(ctypes.c_int32),
                                                   _P(ctypes.c_int32), _P(ctypes.c_int32),
                                                   _P(ctypes.c_int32), _P(ctypes.c_int32),

@@ -198,16 +198,15 @@ def partition(graph: Graph, core_size: int, method="block") -> Partition:
     return Partition(out)
 
 
-def partition_update(graph: Graph, prev: Partition, core_size: int) -> Partition:
-    """The cores of ``prev`` carried to ``graph`` (same vertices) and improved by the exact-cost
-    passes of the multilevel partitioner (on-the-fly update between MD steps)."""
+def partition_update(graph: Graph, prev: Partition) -> Partition:
+    """The cores of ``prev`` carried to ``graph`` (same vertices) with their new halos
+    (on-the-fly update between MD steps)."""
     out = ctypes.c_void_p()
-    _check(_lib().gb_partition_update(graph.handle, prev.handle, int(core_size), _stream(),
-                                      ctypes.byref(out)))
+    _check(_lib().gb_partition_update(graph.handle, prev.handle, _stream(), ctypes.byref(out)))
     return Partition(out)
 
 
-def partition_update_host(row_ptr, col, core_size, prev_core_ptr, prev_core_vtx):
+def partition_update_host(row_ptr, col, prev_core_ptr, prev_core_vtx):
     """Host form of partition_update on numpy CSR and core arrays."""
     import numpy as np
     rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
@@ -221,7 +220,7 @@ def partition_update_host(row_ptr, col, core_size, prev_core_ptr, prev_core_vtx)
     cost = ctypes.c_int64()
     i32 = ctypes.POINTER(ctypes.c_int32)
     _check(_lib().gb_partition_update_host(n, rp.ctypes.data_as(i32), cl.ctypes.data_as(i32),
-                                           int(core_size), len(pp) - 1, pp.ctypes.data_as(i32),
+                                           len(pp) - 1, pp.ctypes.data_as(i32),
                                            pv.ctypes.data_as(i32), ctypes.byref(nc),
                                            cp.ctypes.data_as(i32), cv.ctypes.data_as(i32),
                                            ctypes.byref(cost)))

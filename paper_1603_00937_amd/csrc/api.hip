@@ -450,17 +450,16 @@ gb_status gb_partition_host(int32_t n, const int32_t* row_ptr, const int32_t* co
   });
 }
 
-gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, int32_t core_size,
-                              void* stream, gb_partition_t** out) {
+gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, void* stream,
+                              gb_partition_t** out) {
   return guarded([&] {
     if (!out) fail(GB_EINVAL, "out is NULL");
     *out = nullptr;
     if (!g || !prev) fail(GB_EINVAL, "graph / prev is NULL");
-    if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
     hipStream_t s = as_stream(stream);
     auto* p = new gb_partition_s();
     try {
-      partition_multilevel_dev(g->csr, core_size, p->part, s, nullptr, &prev->part);
+      partition_multilevel_dev(g->csr, 0, p->part, s, nullptr, &prev->part);
       GB_HIP(hipStreamSynchronize(s));
       detach(p->part);
     } catch (...) {
@@ -472,21 +471,19 @@ gb_status gb_partition_update(const gb_graph_t* g, const gb_partition_t* prev, i
 }
 
 gb_status gb_partition_update_host(int32_t n, const int32_t* row_ptr, const int32_t* col,
-                                   int32_t core_size, int32_t prev_n_cores,
-                                   const int32_t* prev_core_ptr, const int32_t* prev_core_vtx,
-                                   int32_t* n_cores, int32_t* core_ptr, int32_t* core_vtx,
-                                   int64_t* cost) {
+                                   int32_t prev_n_cores, const int32_t* prev_core_ptr,
+                                   const int32_t* prev_core_vtx, int32_t* n_cores,
+                                   int32_t* core_ptr, int32_t* core_vtx, int64_t* cost) {
   return guarded([&] {
     if (!row_ptr || !col || !prev_core_ptr || !prev_core_vtx || !n_cores || !core_ptr ||
         !core_vtx)
       fail(GB_EINVAL, "an array argument is NULL");
-    if (core_size < 1) fail(GB_EINVAL, "core_size = %d must be >= 1", core_size);
     check_host_csr(n, row_ptr, col);
     check_cover(n, prev_n_cores, prev_core_ptr, prev_core_vtx);
     std::vector<int32_t> pp(prev_core_ptr, prev_core_ptr + prev_n_cores + 1),
         pv(prev_core_vtx, prev_core_vtx + n), cp, cv;
     MlStats st;
-    partition_update(n, row_ptr, col, core_size, pp, pv, cp, cv, &st);
+    partition_update(n, row_ptr, col, pp, pv, cp, cv, &st);
     *n_cores = (int32_t)cp.size() - 1;
     std::memcpy(core_ptr, cp.data(), cp.size() * 4);
     std::memcpy(core_vtx, cv.data(), cv.size() * 4);

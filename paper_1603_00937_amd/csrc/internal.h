@@ -140,7 +140,7 @@ void partition_from_cores(const Csr& g, const std::vector<int32_t>& core_ptr,
 struct MlStats {
   int levels = 0, coarsest = 0;
   int64_t cost = 0;  // sum over subgraphs of (|core| + |halo|)^3
-  double ms_weights = 0, ms_coarsen = 0, ms_grow = 0, ms_cut = 0, ms_cost = 0;
+  double ms_weights = 0, ms_coarsen = 0, ms_grow = 0, ms_cost = 0;
 };
 // Multilevel cores of at most `cap` vertices (host; mlpart.hip); core_vtx ascending per core.
 // ew (optional): per CSR entry, the number of common closed neighbours of its two ends
@@ -148,12 +148,12 @@ struct MlStats {
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
                           MlStats* stats, const int32_t* ew = nullptr);
-// The previous cores carried to a new graph on the same vertices: the exact-cost passes of
-// the multilevel partitioner started from them (on-the-fly update between MD steps).
-void partition_update(int n, const int32_t* row_ptr, const int32_t* col, int cap,
+// The previous cores carried to a new graph on the same vertices (on-the-fly update between MD
+// steps): the cores renumbered as the partitioner emits them, and their cost on the new graph.
+void partition_update(int n, const int32_t* row_ptr, const int32_t* col,
                       const std::vector<int32_t>& prev_ptr, const std::vector<int32_t>& prev_vtx,
                       std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                      MlStats* stats, const int32_t* ew = nullptr);
+                      MlStats* stats);
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
                               MlStats* stats, const Part* prev = nullptr);
 void detach(Csr& c);

@@ -4,17 +4,18 @@
 // products of every subgraph; the paper's cost discussion after Eq. 6), and the paper takes its
 // communities from a multilevel graph partitioner.  This one is written for that objective with
 // a hard cap on the core size (the batched kernels are sized for it):
-//   1. coarsening by heavy-edge matching, pairs limited to a quarter of the cap, until no pair
-//      can be matched: each level halves the graph while keeping strongly tied vertices
-//      together;
-//   2. on the coarsest graph, parts grown one at a time by always adding the unassigned
+//   1. edge weights = common closed neighbours of the two ends, so that strongly tied vertices
+//      are the ones whose joint halo is smallest;
+//   2. coarsening by heavy-edge matching, pairs limited to a quarter of the cap, until no pair
+//      can be matched;
+//   3. on the coarsest graph, parts grown one at a time by always adding the unassigned
 //      neighbour most strongly tied to the part while it fits under the cap, seeds taken in
 //      breadth-first order so that parts follow one another through the graph;
-//   3. on the way back to the input graph, at every level, greedy passes moving boundary
-//      vertices to the neighbouring part they are most tied to when that cuts edge weight and
-//      the part has room;
-//   4. on the input graph, passes moving vertices to one of their three most tied neighbouring
-//      parts when that lowers sum (|core| + |halo|)^3 exactly (halo sizes kept incrementally).
+//   4. the parts projected back to the input graph.
+// Greedy single-vertex refinement passes were tried on the input graph (edge-cut gain, and the
+// exact change of sum (|core| + |halo|)^3): with every part at the cap no vertex has room to
+// move, the cost passes moved nothing and the edge-cut passes raised the cost slightly, so they
+// are not part of the pipeline.
 // Everything is integer and every choice has a fixed tie-break, so the result is a function of
 // the graph alone.  The visiting order of the matching is a fixed pseudo-random permutation
 // (vertices sorted by SplitMix64 of (level << 32 | v)).
@@ -187,153 +188,25 @@ std::vector<int32_t> grow_parts(const Level& g, int cap) {
   return part;
 }
 
-// Greedy passes on g: each vertex (ascending) moves to the neighbouring part with the largest
-// positive gain in internal edge weight (ties: smaller part index) if that part has room.
-void refine_cut(const Level& g, std::vector<int32_t>& part, std::vector<int32_t>& pw, int cap,
-                int passes) {
-  const int np = (int)pw.size();
-  std::vector<int32_t> conn(np, 0), touched;
-  for (int pass = 0; pass < passes; ++pass) {
-    int moved = 0;
-    for (int v = 0; v < g.n; ++v) {
-      const int a = part[v];
-      touched.clear();
-      for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) {
-        const int b = part[g.adj[e]];
-        if (conn[b] == 0) touched.push_back(b);
-        conn[b] += g.ew[e];
-      }
-      const int own = conn[a];
-      int best = -1, bg = 0;
-      for (int b : touched) {
-        if (b == a || pw[b] + g.vw[v] > cap) continue;
-        const int gain = conn[b] - own;
-        if (gain > bg || (gain == bg && gain > 0 && b < best)) {
-          best = b;
-          bg = gain;
-        }
-      }
-      for (int b : touched) conn[b] = 0;
-      if (best >= 0) {
-        part[v] = best;
-        pw[a] -= g.vw[v];
-        pw[best] += g.vw[v];
-        ++moved;
-      }
-    }
-    if (!moved) break;
-  }
-}
-
 int64_t cube(int64_t x) { return x * x * x; }
 
-// Per-vertex counts of neighbours in each part: a sorted (part, count) list per vertex.
-struct PartCounts {
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> c;
-  int get(int u, int p) const {
-    const auto& l = c[u];
-    auto it = std::lower_bound(l.begin(), l.end(), std::make_pair(p, INT_MIN));
-    return (it != l.end() && it->first == p) ? it->second : 0;
-  }
-  void add(int u, int p, int d) {
-    auto& l = c[u];
-    auto it = std::lower_bound(l.begin(), l.end(), std::make_pair(p, INT_MIN));
-    if (it != l.end() && it->first == p) {
-      it->second += d;
-      if (it->second == 0) l.erase(it);
-    } else {
-      l.insert(it, {p, d});
-    }
-  }
-};
-
-// Passes on the input graph lowering sum_p (k_p + h_p)^3 exactly: each vertex (ascending)
-// tries its three most tied neighbouring parts (ties: smaller index) with room, and moves to
-// the one with the largest decrease.
-int64_t refine_cost(const Level& g, std::vector<int32_t>& part, int np, int cap, int passes) {
-  const int n = g.n;
-  PartCounts pc;
-  pc.c.resize(n);
+// sum over parts of (|core| + |halo|)^3 on g (halo: vertices outside the part adjacent to it)
+int64_t subgraph_cost(const Level& g, const std::vector<int32_t>& part, int np) {
   std::vector<int64_t> k(np, 0), h(np, 0);
-  for (int v = 0; v < n; ++v) ++k[part[v]];
-  for (int u = 0; u < n; ++u) {
-    for (int e = g.rp[u]; e < g.rp[u + 1]; ++e) pc.add(u, part[g.adj[e]], 1);
-    for (const auto& pr : pc.c[u])
-      if (pr.first != part[u]) ++h[pr.first];
-  }
-  int64_t cost = 0;
-  for (int p = 0; p < np; ++p) cost += cube(k[p] + h[p]);
-  std::vector<int32_t> conn(np, 0), touched;
-  for (int pass = 0; pass < passes; ++pass) {
-    int moved = 0;
-    for (int v = 0; v < n; ++v) {
-      const int a = part[v];
-      // change of h_a if v leaves a: neighbours outside a whose only tie to a is v leave the
-      // halo; v joins it if it keeps a neighbour in a
-      int64_t dha = pc.get(v, a) > 0 ? 1 : 0;
-      for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) {
-        const int u = g.adj[e];
-        if (part[u] != a && pc.get(u, a) == 1) --dha;
+  std::vector<int32_t> stamp(np, -1);
+  for (int u = 0; u < g.n; ++u) {
+    ++k[part[u]];
+    for (int e = g.rp[u]; e < g.rp[u + 1]; ++e) {
+      const int p = part[g.adj[e]];
+      if (p != part[u] && stamp[p] != u) {
+        stamp[p] = u;
+        ++h[p];
       }
-      touched.clear();
-      for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) {
-        const int b = part[g.adj[e]];
-        if (b == a) continue;
-        if (conn[b] == 0) touched.push_back(b);
-        conn[b] += g.ew[e];
-      }
-      // the three most tied candidate parts with room
-      int cand[3] = {-1, -1, -1};
-      for (int b : touched) {
-        if (k[b] + 1 > cap) continue;
-        for (int q = 0; q < 3; ++q) {
-          const int c = cand[q];
-          if (c < 0 || conn[b] > conn[c] || (conn[b] == conn[c] && b < c)) {
-            for (int r = 2; r > q; --r) cand[r] = cand[r - 1];
-            cand[q] = b;
-            break;
-          }
-        }
-      }
-      for (int b : touched) conn[b] = 0;
-      const int64_t before_a = cube(k[a] + h[a]);
-      const int64_t after_a = cube(k[a] - 1 + h[a] + dha);
-      int best = -1;
-      int64_t best_d = 0, best_dhb = 0;
-      for (int q = 0; q < 3; ++q) {
-        const int b = cand[q];
-        if (b < 0) break;
-        // change of h_b if v joins b: v leaves the halo of b; neighbours outside b with no tie
-        // to b yet join it
-        int64_t dhb = pc.get(v, b) > 0 ? -1 : 0;
-        for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) {
-          const int u = g.adj[e];
-          if (part[u] != b && pc.get(u, b) == 0) ++dhb;
-        }
-        const int64_t d = after_a - before_a + cube(k[b] + 1 + h[b] + dhb) - cube(k[b] + h[b]);
-        if (d < best_d) {
-          best_d = d;
-          best = b;
-          best_dhb = dhb;
-        }
-      }
-      if (best < 0) continue;
-      for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) {
-        const int u = g.adj[e];
-        pc.add(u, a, -1);
-        pc.add(u, best, 1);
-      }
-      h[a] += dha;
-      h[best] += best_dhb;
-      --k[a];
-      ++k[best];
-      part[v] = best;
-      cost += best_d;
-      ++moved;
     }
-    if (!moved) break;
   }
-  return cost;
+  int64_t c = 0;
+  for (int p = 0; p < np; ++p) c += cube(k[p] + h[p]);
+  return c;
 }
 
 }  // namespace
@@ -341,8 +214,9 @@ int64_t refine_cost(const Level& g, std::vector<int32_t>& part, int np, int cap,
 namespace {
 
 // Level 0: the input graph without self loops, weights = common closed neighbours (given, or
-// counted here), unit vertex weights.
-void input_level(int n, const int32_t* row_ptr, const int32_t* col, const int32_t* ew, Level& g0) {
+// counted here unless want_weights is false), unit vertex weights.
+void input_level(int n, const int32_t* row_ptr, const int32_t* col, const int32_t* ew, Level& g0,
+                 bool want_weights = true) {
   g0.n = n;
   g0.rp.assign(n + 1, 0);
   g0.adj.clear();
@@ -356,7 +230,7 @@ void input_level(int n, const int32_t* row_ptr, const int32_t* col, const int32_
     g0.rp[v + 1] = (int32_t)g0.adj.size();
   }
   g0.vw.assign(n, 1);
-  if (ew) return;
+  if (ew || !want_weights) return;
   // edge weight = number of common neighbours (each vertex counted as its own neighbour): the
   // pair's joint halo is smallest for the neighbour sharing most of its neighbourhood
   g0.ew.assign(g0.adj.size(), 0);
@@ -423,19 +297,12 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
   t0 = clk::now();
   int np = 0;
   for (int p : part) np = std::max(np, p + 1);
-  for (int l = (int)lv.size() - 1; l >= 0; --l) {
-    if (l < (int)lv.size() - 1) {
-      std::vector<int32_t> fine(lv[l].n);
-      for (int v = 0; v < lv[l].n; ++v) fine[v] = part[lv[l].cmap[v]];
-      part.swap(fine);
-    }
-    std::vector<int32_t> pw(np, 0);
-    for (int v = 0; v < lv[l].n; ++v) pw[part[v]] += lv[l].vw[v];
-    refine_cut(lv[l], part, pw, cap, 4);
+  for (int l = (int)lv.size() - 2; l >= 0; --l) {
+    std::vector<int32_t> fine(lv[l].n);
+    for (int v = 0; v < lv[l].n; ++v) fine[v] = part[lv[l].cmap[v]];
+    part.swap(fine);
   }
-  const double ms_cut = ms_since(t0);
-  t0 = clk::now();
-  const int64_t cost = refine_cost(lv[0], part, np, cap, 4);
+  const int64_t cost = subgraph_cost(lv[0], part, np);
   const double ms_cost = ms_since(t0);
   emit_cores(n, part, np, core_ptr, core_vtx);
   if (stats) {
@@ -445,31 +312,27 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
     stats->ms_weights = ms_weights;
     stats->ms_coarsen = ms_coarsen;
     stats->ms_grow = ms_grow;
-    stats->ms_cut = ms_cut;
     stats->ms_cost = ms_cost;
   }
 }
 
-void partition_update(int n, const int32_t* row_ptr, const int32_t* col, int cap,
+void partition_update(int n, const int32_t* row_ptr, const int32_t* col,
                       const std::vector<int32_t>& prev_ptr, const std::vector<int32_t>& prev_vtx,
                       std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                      MlStats* stats, const int32_t* ew) {
+                      MlStats* stats) {
   auto t0 = clk::now();
   Level g0;
-  input_level(n, row_ptr, col, ew, g0);
-  const double ms_weights = ms_since(t0);
-  t0 = clk::now();
+  input_level(n, row_ptr, col, nullptr, g0, false);
   const int np = (int)prev_ptr.size() - 1;
   std::vector<int32_t> part(n, -1);
   for (int p = 0; p < np; ++p)
     for (int i = prev_ptr[p]; i < prev_ptr[p + 1]; ++i) part[prev_vtx[i]] = p;
-  const int64_t cost = refine_cost(g0, part, np, cap, 4);
+  const int64_t cost = subgraph_cost(g0, part, np);
   emit_cores(n, part, np, core_ptr, core_vtx);
   if (stats) {
     stats->levels = 1;
     stats->coarsest = n;
     stats->cost = cost;
-    stats->ms_weights = ms_weights;
     stats->ms_cost = ms_since(t0);
   }
 }

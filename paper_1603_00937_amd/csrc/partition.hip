@@ -318,9 +318,23 @@ void partition_from_cores(const Csr& g, const std::vector<int32_t>& core_ptr,
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
                               MlStats* stats, const Part* prev) {
   const int n = g.n;
-  std::vector<int32_t> rp(n + 1), col(g.nnz), w(g.nnz), cp, cv;
+  std::vector<int32_t> rp(n + 1), col(g.nnz), cp, cv;
+  if (prev) {
+    // on-the-fly update: the previous cores carried to this graph (no weights needed)
+    if (prev->n != n) fail(GB_ESHAPE, "previous partition has %d vertices, graph %d", prev->n, n);
+    std::vector<int32_t> pv(n);
+    GB_HIP(hipMemcpyAsync(rp.data(), g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(col.data(), g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(pv.data(), prev->core_vtx.get(), (size_t)n * 4, hipMemcpyDeviceToHost,
+                          s));
+    GB_HIP(hipStreamSynchronize(s));
+    partition_update(n, rp.data(), col.data(), prev->h_core_ptr, pv, cp, cv, stats);
+    partition_from_cores(g, cp, cv, P, s);
+    return;
+  }
   // edge weights on the device (the graphs built here hold every self loop), the rest on the
   // host
+  std::vector<int32_t> w(g.nnz);
   const size_t lds = (size_t)((n + 31) >> 5) * 4;
   if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "multilevel: n = %d too large for one LDS bitmap", n);
   DBuf<int32_t> dw(std::max<int64_t>(g.nnz, 1), s);
@@ -336,17 +350,7 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
     for (int e = rp[v]; e < rp[v + 1]; ++e) self |= col[e] == v;
     if (!self) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", v);
   }
-  if (prev) {
-    if (prev->n != n) fail(GB_ESHAPE, "previous partition has %d vertices, graph %d", prev->n, n);
-    std::vector<int32_t> pv(n);
-    GB_HIP(hipMemcpyAsync(pv.data(), prev->core_vtx.get(), (size_t)n * 4, hipMemcpyDeviceToHost,
-                          s));
-    GB_HIP(hipStreamSynchronize(s));
-    partition_update(n, rp.data(), col.data(), core_size, prev->h_core_ptr, pv, cp, cv, stats,
-                     w.data());
-  } else {
-    partition_multilevel(n, rp.data(), col.data(), core_size, cp, cv, stats, w.data());
-  }
+  partition_multilevel(n, rp.data(), col.data(), core_size, cp, cv, stats, w.data());
   partition_from_cores(g, cp, cv, P, s);
 }
 

@@ -319,7 +319,7 @@ def test_density_n1024_multilevel_golden(gb, model_cache):
 
 def test_partition_update_bit_exact(gb, model_cache):
     """On-the-fly update: the previous step's multilevel cores carried to the displaced
-    system's graph and improved, against the oracle, index for index."""
+    system's graph, with their halos there, against the oracle, index for index."""
     from synth import displace_sites, rebuild_hamiltonian
     from oracle.graph import graph_x2
     from oracle.multilevel import partition_multilevel, partition_update
@@ -331,9 +331,9 @@ def test_partition_update_bit_exact(gb, model_cache):
     rng = np.random.default_rng(52)
     m1 = rebuild_hamiltonian(m0, displace_sites(m0["pos"], m0["L"], 0.02, rng))
     g1 = gb.build_graph(_dev(m1["H_col"]), _dev(m1["H_val"]), 1e-5)
-    p1 = gb.partition_update(g1, p0, 16)
+    p1 = gb.partition_update(g1, p0)
     cp, sp, si = _host(*p1.arrays())
     rp1, col1 = graph_x2(m1["H_col"], m1["H_val"], 1e-5)
-    ocp, ocv, _ = partition_update(rp1, col1, 16, ocp0, ocv0)
+    ocp, ocv, _ = partition_update(rp1, col1, ocp0, ocv0)
     osp, osi = halo_subgraphs(rp1, col1, [ocv[ocp[i]:ocp[i + 1]] for i in range(len(ocp) - 1)])
     assert np.array_equal(cp, ocp) and np.array_equal(sp, osp) and np.array_equal(si, osi)
