@@ -219,10 +219,12 @@ def md_run(args):
         g = gb.build_graph(Hc, Hv, cfg["tau"], mode="dprev", aux=(D_col, D_val), tau_aux=1e-4)
         torch.cuda.synchronize()
         tp = time.perf_counter()
-        # multilevel communities are carried over from the previous step with new halos
-        # (on-the-fly update); blocks are recut from the vertex order
-        p = (gb.partition_update(g, p) if args.partition == "multilevel"
-             else gb.partition(g, cfg["core"]))
+        # cores from the new graph each step, or (--md-carry-cores) the previous step's multilevel
+        # communities carried over with their halos on the new graph (on-the-fly update)
+        if args.partition == "multilevel" and args.md_carry_cores:
+            p = gb.partition_update(g, p)
+        else:
+            p = gb.partition(g, cfg["core"], method=args.partition)
         torch.cuda.synchronize()
         part_ms = (time.perf_counter() - tp) * 1e3
         # pre-determined sequence (MD section), no trace rule during the expansion: "replay"
@@ -421,6 +423,8 @@ def main():
     ap.add_argument("--md-sequence", default="trace", choices=["trace", "replay", "gap"],
                     help="MD: choose each branch from the traces, replay the previous step's "
                          "sequence, or build it from the gap estimated from its traces")
+    ap.add_argument("--md-carry-cores", action="store_true",
+                    help="MD with multilevel communities: carry the previous step's cores")
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run the adaptive-graph displacement loop instead of the benchmark")
     ap.add_argument("--workload", default="n18000", choices=list(WORKLOADS))
