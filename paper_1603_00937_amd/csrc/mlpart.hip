@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <thread>
 #include <cstdint>
 #include <vector>
 
@@ -37,6 +38,23 @@ uint64_t splitmix64(uint64_t x) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
+}
+
+// host threads for the independent parts (at most 16)
+int worker_count() {
+  const unsigned h = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, h));
+}
+
+template <typename F>
+void run_workers(int nt, F&& f) {
+  if (nt <= 1) {
+    f(0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back(f, t);
+  for (auto& x : th) x.join();
 }
 
 struct Level {
@@ -91,35 +109,52 @@ bool coarsen(Level& f, int cap, int level, Level& c) {
     }
   c.n = nc;
   c.vw.assign(nc, 0);
-  for (int v = 0; v < n; ++v) c.vw[f.cmap[v]] += f.vw[v];
-  // coarse adjacency: summed edge weights, neighbours ascending, no self loops
-  c.rp.assign(nc + 1, 0);
-  c.adj.clear();
-  c.ew.clear();
-  std::vector<int32_t> acc(nc, 0), touched;
-  int cv = 0;
+  std::vector<int32_t> lead(nc, -1);  // the lower member of each pair
   for (int v = 0; v < n; ++v) {
-    if (f.cmap[v] != cv) continue;  // the lower member of each pair opens its coarse vertex
-    const int members[2] = {v, match[v]};
-    const int nm = match[v] == v ? 1 : 2;
-    touched.clear();
-    for (int q = 0; q < nm; ++q) {
-      const int x = members[q];
-      for (int e = f.rp[x]; e < f.rp[x + 1]; ++e) {
-        const int cu = f.cmap[f.adj[e]];
-        if (cu == cv) continue;
-        if (acc[cu] == 0) touched.push_back(cu);
-        acc[cu] += f.ew[e];
+    c.vw[f.cmap[v]] += f.vw[v];
+    if (lead[f.cmap[v]] < 0) lead[f.cmap[v]] = v;
+  }
+  // coarse adjacency: summed edge weights, neighbours ascending, no self loops.  Coarse
+  // vertices are independent, so contiguous ranges of them are built on separate threads and
+  // concatenated in order (the result does not depend on the thread count).
+  const int nt = nc >= 1024 ? worker_count() : 1;
+  std::vector<std::vector<int32_t>> adj_t(nt), ew_t(nt);
+  std::vector<int32_t> deg(nc, 0);
+  auto build = [&](int t) {
+    const int c0 = (int)((int64_t)nc * t / nt), c1 = (int)((int64_t)nc * (t + 1) / nt);
+    std::vector<int32_t> acc(nc, 0), touched;
+    for (int cv = c0; cv < c1; ++cv) {
+      const int v = lead[cv];
+      const int members[2] = {v, match[v]};
+      const int nm = match[v] == v ? 1 : 2;
+      touched.clear();
+      for (int q = 0; q < nm; ++q) {
+        const int x = members[q];
+        for (int e = f.rp[x]; e < f.rp[x + 1]; ++e) {
+          const int cu = f.cmap[f.adj[e]];
+          if (cu == cv) continue;
+          if (acc[cu] == 0) touched.push_back(cu);
+          acc[cu] += f.ew[e];
+        }
       }
+      std::sort(touched.begin(), touched.end());
+      for (int cu : touched) {
+        adj_t[t].push_back(cu);
+        ew_t[t].push_back(acc[cu]);
+        acc[cu] = 0;
+      }
+      deg[cv] = (int32_t)touched.size();
     }
-    std::sort(touched.begin(), touched.end());
-    for (int cu : touched) {
-      c.adj.push_back(cu);
-      c.ew.push_back(acc[cu]);
-      acc[cu] = 0;
-    }
-    c.rp[cv + 1] = (int32_t)c.adj.size();
-    ++cv;
+  };
+  run_workers(nt, build);
+  c.rp.assign(nc + 1, 0);
+  for (int cv = 0; cv < nc; ++cv) c.rp[cv + 1] = c.rp[cv] + deg[cv];
+  c.adj.resize(c.rp[nc]);
+  c.ew.resize(c.rp[nc]);
+  for (int t = 0; t < nt; ++t) {
+    const int c0 = (int)((int64_t)nc * t / nt);
+    std::copy(adj_t[t].begin(), adj_t[t].end(), c.adj.begin() + c.rp[c0]);
+    std::copy(ew_t[t].begin(), ew_t[t].end(), c.ew.begin() + c.rp[c0]);
   }
   return true;
 }

@@ -111,8 +111,9 @@ def test_cheaper_than_blocks_and_independent_of_numbering():
 
 
 @pytest.mark.parametrize("name,cap", [("tiny48", 5), ("tiny48", 16), ("small256", 16),
-                                      ("small256", 7), ("n1024", 32)])
+                                      ("small256", 7), ("n1024", 32), ("n4096", 32)])
 def test_library_host_entry_point_matches_oracle(name, cap):
+    """n4096 is large enough for the library to build its coarse graphs on several threads."""
     import paper_1603_00937_amd as gb
     m = make_model(name)
     rp, col = graph_x2(m["H_col"], m["H_val"], 1e-5)
