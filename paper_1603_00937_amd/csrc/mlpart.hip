@@ -57,10 +57,16 @@ void run_workers(int nt, F&& f) {
   for (auto& x : th) x.join();
 }
 
+// A graph level: CSR with edge and vertex weights.  The input level reads the caller's CSR in
+// place (its self loops are skipped where they matter); coarse levels own their arrays.
 struct Level {
   int n = 0;
-  std::vector<int32_t> rp, adj, ew, vw;  // CSR without self loops, edge and vertex weights
-  std::vector<int32_t> cmap;             // vertex -> vertex of the next coarser level
+  const int32_t* rp = nullptr;
+  const int32_t* adj = nullptr;
+  const int32_t* ew = nullptr;
+  std::vector<int32_t> rp_v, adj_v, ew_v;  // storage of a coarse level (or of host weights)
+  std::vector<int32_t> vw;                 // vertex weights
+  std::vector<int32_t> cmap;               // vertex -> vertex of the next coarser level
 };
 
 std::vector<int32_t> visit_order(int n, int level) {
@@ -82,7 +88,7 @@ bool coarsen(Level& f, int cap, int level, Level& c) {
     int best = -1, bw = -1, bvw = INT_MAX;
     for (int e = f.rp[v]; e < f.rp[v + 1]; ++e) {
       const int u = f.adj[e];
-      if (match[u] >= 0 || f.vw[u] + f.vw[v] > cap) continue;
+      if (u == v || match[u] >= 0 || f.vw[u] + f.vw[v] > cap) continue;
       const int w = f.ew[e];
       if (w > bw || (w == bw && (f.vw[u] < bvw || (f.vw[u] == bvw && u < best)))) {
         best = u;
@@ -147,15 +153,18 @@ bool coarsen(Level& f, int cap, int level, Level& c) {
     }
   };
   run_workers(nt, build);
-  c.rp.assign(nc + 1, 0);
-  for (int cv = 0; cv < nc; ++cv) c.rp[cv + 1] = c.rp[cv] + deg[cv];
-  c.adj.resize(c.rp[nc]);
-  c.ew.resize(c.rp[nc]);
+  c.rp_v.assign(nc + 1, 0);
+  for (int cv = 0; cv < nc; ++cv) c.rp_v[cv + 1] = c.rp_v[cv] + deg[cv];
+  c.adj_v.resize(c.rp_v[nc]);
+  c.ew_v.resize(c.rp_v[nc]);
   for (int t = 0; t < nt; ++t) {
     const int c0 = (int)((int64_t)nc * t / nt);
-    std::copy(adj_t[t].begin(), adj_t[t].end(), c.adj.begin() + c.rp[c0]);
-    std::copy(ew_t[t].begin(), ew_t[t].end(), c.ew.begin() + c.rp[c0]);
+    std::copy(adj_t[t].begin(), adj_t[t].end(), c.adj_v.begin() + c.rp_v[c0]);
+    std::copy(ew_t[t].begin(), ew_t[t].end(), c.ew_v.begin() + c.rp_v[c0]);
   }
+  c.rp = c.rp_v.data();
+  c.adj = c.adj_v.data();
+  c.ew = c.ew_v.data();
   return true;
 }
 
@@ -227,20 +236,32 @@ int64_t cube(int64_t x) { return x * x * x; }
 
 // sum over parts of (|core| + |halo|)^3 on g (halo: vertices outside the part adjacent to it)
 int64_t subgraph_cost(const Level& g, const std::vector<int32_t>& part, int np) {
-  std::vector<int64_t> k(np, 0), h(np, 0);
-  std::vector<int32_t> stamp(np, -1);
-  for (int u = 0; u < g.n; ++u) {
-    ++k[part[u]];
-    for (int e = g.rp[u]; e < g.rp[u + 1]; ++e) {
-      const int p = part[g.adj[e]];
-      if (p != part[u] && stamp[p] != u) {
-        stamp[p] = u;
-        ++h[p];
+  const int nt = g.n >= 1024 ? worker_count() : 1;
+  std::vector<std::vector<int64_t>> kt(nt, std::vector<int64_t>(np, 0)),
+      ht(nt, std::vector<int64_t>(np, 0));
+  run_workers(nt, [&](int t) {
+    const int u0 = (int)((int64_t)g.n * t / nt), u1 = (int)((int64_t)g.n * (t + 1) / nt);
+    std::vector<int32_t> stamp(np, -1);
+    for (int u = u0; u < u1; ++u) {
+      ++kt[t][part[u]];
+      for (int e = g.rp[u]; e < g.rp[u + 1]; ++e) {
+        const int p = part[g.adj[e]];
+        if (p != part[u] && stamp[p] != u) {
+          stamp[p] = u;
+          ++ht[t][p];
+        }
       }
     }
-  }
+  });
   int64_t c = 0;
-  for (int p = 0; p < np; ++p) c += cube(k[p] + h[p]);
+  for (int p = 0; p < np; ++p) {
+    int64_t k = 0, h = 0;
+    for (int t = 0; t < nt; ++t) {
+      k += kt[t][p];
+      h += ht[t][p];
+    }
+    c += cube(k + h);
+  }
   return c;
 }
 
@@ -248,38 +269,37 @@ int64_t subgraph_cost(const Level& g, const std::vector<int32_t>& part, int np) 
 
 namespace {
 
-// Level 0: the input graph without self loops, weights = common closed neighbours (given, or
-// counted here unless want_weights is false), unit vertex weights.
+// Level 0: the input graph in place (self loops skipped where they matter), weights = common
+// closed neighbours (given per CSR entry, or counted here unless want_weights is false), unit
+// vertex weights.
 void input_level(int n, const int32_t* row_ptr, const int32_t* col, const int32_t* ew, Level& g0,
                  bool want_weights = true) {
   g0.n = n;
-  g0.rp.assign(n + 1, 0);
-  g0.adj.clear();
-  g0.ew.clear();
-  for (int v = 0; v < n; ++v) {
-    for (int e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
-      if (col[e] != v) {
-        g0.adj.push_back(col[e]);
-        if (ew) g0.ew.push_back(ew[e]);
-      }
-    g0.rp[v + 1] = (int32_t)g0.adj.size();
-  }
+  g0.rp = row_ptr;
+  g0.adj = col;
   g0.vw.assign(n, 1);
+  g0.ew = ew;
   if (ew || !want_weights) return;
-  // edge weight = number of common neighbours (each vertex counted as its own neighbour): the
-  // pair's joint halo is smallest for the neighbour sharing most of its neighbourhood
-  g0.ew.assign(g0.adj.size(), 0);
-  std::vector<int32_t> mark(n, -1);
-  for (int u = 0; u < n; ++u) {
-    mark[u] = u;
-    for (int e = g0.rp[u]; e < g0.rp[u + 1]; ++e) mark[g0.adj[e]] = u;
-    for (int e = g0.rp[u]; e < g0.rp[u + 1]; ++e) {
-      const int v = g0.adj[e];
-      int c = mark[v] == u ? 1 : 0;  // v itself (it is a neighbour of u)
-      for (int f = g0.rp[v]; f < g0.rp[v + 1]; ++f) c += mark[g0.adj[f]] == u;
-      g0.ew[e] = c;
+  // the number of common closed neighbours: the pair's joint halo is smallest for the
+  // neighbour sharing most of its neighbourhood
+  g0.ew_v.assign(row_ptr[n], 0);
+  const int nt = n >= 1024 ? worker_count() : 1;
+  run_workers(nt, [&](int t) {
+    const int u0 = (int)((int64_t)n * t / nt), u1 = (int)((int64_t)n * (t + 1) / nt);
+    std::vector<int32_t> mark(n, -1);
+    for (int u = u0; u < u1; ++u) {
+      mark[u] = u;
+      for (int e = row_ptr[u]; e < row_ptr[u + 1]; ++e) mark[col[e]] = u;
+      for (int e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+        const int v = col[e];
+        if (v == u) continue;
+        int c = 1;  // v itself (it is a neighbour of u)
+        for (int f = row_ptr[v]; f < row_ptr[v + 1]; ++f) c += col[f] != v && mark[col[f]] == u;
+        g0.ew_v[e] = c;
+      }
     }
-  }
+  });
+  g0.ew = g0.ew_v.data();
 }
 
 // Non-empty parts in ascending order of their smallest vertex, vertices ascending.

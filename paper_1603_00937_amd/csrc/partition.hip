@@ -345,11 +345,9 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
   GB_HIP(hipMemcpyAsync(col.data(), g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(w.data(), dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipStreamSynchronize(s));
-  for (int v = 0; v < n; ++v) {
-    bool self = false;
-    for (int e = rp[v]; e < rp[v + 1]; ++e) self |= col[e] == v;
-    if (!self) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", v);
-  }
+  for (int v = 0; v < n; ++v)  // rows are sorted ascending
+    if (!std::binary_search(col.begin() + rp[v], col.begin() + rp[v + 1], v))
+      fail(GB_EINVAL, "multilevel: vertex %d has no self loop", v);
   partition_multilevel(n, rp.data(), col.data(), core_size, cp, cv, stats, w.data());
   partition_from_cores(g, cp, cv, P, s);
 }
