@@ -33,15 +33,17 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, partition):
     """HBM bytes per launch of the squaring kernel from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None when no record
-    exists for this workload and kernel or the kernel source changed since it was taken."""
+    exists for this workload, partition and kernel or the kernel source changed since it was
+    taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     for rec in json.load(open(path)):
         if (rec["workload"] == workload and rec["kernel"] == kernel
+                and rec.get("partition") == partition
                 and rec["sp2_source_sha256"] == kernel_source_hash()):
             return rec["bytes_per_launch"]
     return None
@@ -114,7 +116,9 @@ def traffic_from_pmc(pmc_dir, workload="n18000"):
         kw, wv = _largest_grid_counter(w, prefix, "WRITE_SIZE")
         assert kf == kw, (kf, kw)
         fb, wb = fv * 1024.0 * sf, wv * 1024.0 * sw
-        recs.append({"workload": workload, "kernel": kf, "run": run,
+        # run names: <precision>_<partition> (the counter passes' directories)
+        part = "multilevel" if "_multilevel" in run else "block"
+        recs.append({"workload": workload, "kernel": kf, "run": run, "partition": part,
                      "sp2_source_sha256": kernel_source_hash(), "fetch_bytes": fb,
                      "write_bytes": wb, "bytes_per_launch": fb + wb,
                      "copy_scale_fetch": sf, "copy_scale_write": sw})
@@ -374,7 +378,16 @@ def cpu_baseline(model, workload, golden, n_sub_sample):
     Hc, Hv = model["H_col"], model["H_val"]
     N = model["N"]
     core = cfg["core"]
-    n_cores = (N + core - 1) // core
+    if golden and "core_ptr" in golden:
+        # the oracle's own communities, stored with its run
+        cptr = np.asarray(golden["core_ptr"])
+        cvtx = np.asarray(golden["core_vtx"], dtype=np.int32)
+        kind = golden.get("partition", "stored") + " cores"
+    else:
+        cptr = np.minimum(np.arange(0, N + core, core), N)
+        cvtx = np.arange(N, dtype=np.int32)
+        kind = "block cores"
+    n_cores = len(cptr) - 1
     rng = np.random.default_rng(0)
     picks = np.sort(rng.choice(n_cores, size=n_sub_sample, replace=False))
     branch = [int(c) for c in golden["branch"]] if golden else None
@@ -383,7 +396,7 @@ def cpu_baseline(model, workload, golden, n_sub_sample):
     x0 = x0_values(Hc, Hv, emin, emax)
     blocks, kc = [], []
     for c in picks:
-        verts = np.arange(c * core, min((c + 1) * core, N))
+        verts = cvtx[cptr[c]:cptr[c + 1]]
         rows = graph_x2(Hc, Hv, cfg["tau"], emin, emax, rows=verts)
         halo = np.setdiff1d(np.unique(np.concatenate(rows)), verts)
         sub = np.concatenate([verts, halo]).astype(np.int32)
@@ -394,7 +407,7 @@ def cpu_baseline(model, workload, golden, n_sub_sample):
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     return {"value": float(sum(kc) / dt), "unit": "orbitals/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{n_sub_sample} of {n_cores} subgraphs of {workload} (graph rows, halo, "
+            "sample": f"{n_sub_sample} of {n_cores} subgraphs of {workload}, {kind} (graph rows, halo, "
                       f"gather, {len(branch) if branch else 'all'} SP2 steps), {dt:.1f} s"}
 
 
@@ -414,9 +427,9 @@ def main():
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2", "mcweeny_blocks"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
-    ap.add_argument("--partition", default="block", choices=["block", "multilevel"],
-                    help="cores: blocks of the (spatially sorted) vertex order, or multilevel "
-                         "communities of at most the core size")
+    ap.add_argument("--partition", default="multilevel", choices=["block", "multilevel"],
+                    help="cores: multilevel communities of at most the core size (default), or "
+                         "blocks of the (spatially sorted) vertex order")
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--rocpd-counters", default=None,
                     help="summarise the counters of a rocprofv3 --pmc database")
@@ -543,7 +556,8 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
                    "refine_steps": stats["n_refine_done"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak if achieved else None,
-                     "traffic": measured_traffic(args.workload, square_kernel_name(precision, stats)),
+                     "traffic": measured_traffic(args.workload, square_kernel_name(precision, stats),
+                                                 args.partition),
                      "kernel": square_kernel_name(precision, stats),
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
                      "exec_tflops": flops_exec / avg_launch_s / 1e12 if avg_launch_s else None,

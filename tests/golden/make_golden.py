@@ -61,6 +61,10 @@ def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory
         "samples": [[int(r), int(s), float(D_val[r, s]).hex()] for r, s in zip(rows, slots)],
         "oracle_seconds": time.time() - t,
     }
+    if method != "block":
+        # the communities themselves (the CPU baseline samples them)
+        rec["core_ptr"] = [int(x) for x in info["core_ptr"]]
+        rec["core_vtx"] = [int(x) for x in info["core_vertices"]]
     tag = "partitioned" if method == "block" else method
     json.dump(rec, open(os.path.join(HERE, f"{name}_fp64_{tag}.json"), "w"))
     return rec
