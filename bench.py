@@ -23,8 +23,12 @@ METRIC = "orbitals/s of D at ≤1e-6 err vs FP64 oracle; mixed vs FP64 GPU; X² 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "bf16x6": 2500.0}
 # bf16 plane products per algorithmic multiply-add
 PLANE_PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6}
-WORKLOADS = {"n18000": dict(tau=1e-5, core=32), "n1024": dict(tau=1e-5, core=16),
-             "n100000": dict(tau=1e-5, core=32)}
+# default cores per workload: the faster of the two partitions as measured on one MI355X
+# (multilevel communities pay for their host partitioner at N = 18000, not at N = 1024, where it
+# takes a third of the step, nor at N = 100000, where it takes 0.3 s)
+WORKLOADS = {"n18000": dict(tau=1e-5, core=32, partition="multilevel"),
+             "n1024": dict(tau=1e-5, core=16, partition="block"),
+             "n100000": dict(tau=1e-5, core=32, partition="block")}
 
 
 def kernel_source_hash() -> str:
@@ -427,9 +431,9 @@ def main():
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2", "mcweeny_blocks"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
-    ap.add_argument("--partition", default="multilevel", choices=["block", "multilevel"],
-                    help="cores: multilevel communities of at most the core size (default), or "
-                         "blocks of the (spatially sorted) vertex order")
+    ap.add_argument("--partition", default=None, choices=["block", "multilevel"],
+                    help="cores: multilevel communities of at most the core size, or blocks of "
+                         "the (spatially sorted) vertex order (default: per workload)")
     ap.add_argument("--rocpd-summary", default=None, help="summarise a rocprofv3 database")
     ap.add_argument("--rocpd-counters", default=None,
                     help="summarise the counters of a rocprofv3 --pmc database")
@@ -451,6 +455,8 @@ def main():
                     help="skip the FP64 GPU measurement reported beside a mixed-precision run")
     ap.add_argument("--cpu-sample", type=int, default=96)
     args = ap.parse_args()
+    if args.partition is None:
+        args.partition = WORKLOADS[args.workload]["partition"]
     if args.rocpd_summary:
         rocpd_summary(args.rocpd_summary)
         return

@@ -1,7 +1,7 @@
 """Writes the stored expected values under tests/golden/ (calls only synth and oracle).
 
 Usage: python tests/golden/make_golden.py [hashes] [n1024] [n18000] [n100000] [n1024_ml]
-                                          [n18000_ml] [n18000_levels]
+                                          [n18000_ml] [n100000_ml] [n18000_levels]
 (the _ml variants use the multilevel cores instead of blocks of the vertex order)
 Every value written here comes from the CPU oracle in oracle/ run on the seeded
 inputs from synth/; nothing comes from the GPU library.
@@ -94,5 +94,7 @@ if __name__ == "__main__":
         write_partitioned("n1024", 1e-5, 16, method="multilevel")
     if "n18000_levels" in what:
         write_levels("n18000")
+    if "n100000_ml" in what:
+        write_partitioned("n100000", 1e-5, 32, method="multilevel", low_memory=True)
     if "n18000_ml" in what:
         write_partitioned("n18000", 1e-5, 32, method="multilevel", low_memory=True)
