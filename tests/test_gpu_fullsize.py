@@ -167,3 +167,18 @@ def test_n18000_gap_bracket_from_gpu_traces(gb):
           f"lumo {el:.5f} in [{est['lumo_bound']:.5f}, {est['lumo_ratio']:.5f}]")
     assert est["homo_ratio"] <= eh <= est["homo_bound"]
     assert est["lumo_bound"] <= el <= est["lumo_ratio"]
+
+
+def test_n100000_multilevel_fp64(gb):
+    """The heterogeneous system on multilevel communities: partition index for index, branches
+    and D against the oracle's run on the same communities."""
+    ref, st, err = _run(gb, "n100000", "fp64", method="multilevel")
+    assert "".join(map(str, st["branch"])) == ref["branch"]
+    assert st["iters"] == ref["iters"] and st["converged"]
+    assert err <= 1e-9
+
+
+def test_n100000_multilevel_bf16x6(gb):
+    ref, st, err = _run(gb, "n100000", "bf16x6", method="multilevel")
+    assert st["converged"]
+    assert err <= 1e-6
