@@ -42,7 +42,9 @@ typedef int32_t gb_status;
 
 /* The dense batch buffers of gb_density / gb_foe_density are cached between calls (per device
  * and per concurrent call, grown when a call needs more), so a loop of calls does not
- * reallocate them.  gb_trim frees the cached buffers of every call that has returned. */
+ * reallocate them; so are the host buffers of the multilevel partitioner (its coarse graphs
+ * and the pinned copy of the graph it reads).  gb_trim frees the cached buffers of every call
+ * that has returned. */
 gb_status gb_trim(void);
 
 /* Library version string (static storage). */

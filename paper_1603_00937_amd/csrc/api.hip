@@ -250,7 +250,10 @@ const char* gb_version(void) { return "libgb 0.1.0 (gfx950)"; }
 const char* gb_last_error(void) { return g_err; }
 
 gb_status gb_trim(void) {
-  return guarded([&] { ws_trim(); });
+  return guarded([&] {
+    ws_trim();
+    ml_trim();
+  });
 }
 
 gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx) {

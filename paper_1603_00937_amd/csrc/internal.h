@@ -142,12 +142,28 @@ struct MlStats {
   int64_t cost = 0;  // sum over subgraphs of (|core| + |halo|)^3
   double ms_weights = 0, ms_coarsen = 0, ms_grow = 0, ms_cost = 0;
 };
+// Host buffers of the multilevel partitioner, kept between calls (mlpart.hip): on graphs of
+// millions of edges, touching fresh pages (a fault per 4 KiB) costs as much as the coarsening
+// itself, so a call leases a set whose vectors keep their capacity, plus pinned staging for
+// the device graph.  gb_trim releases the idle sets.
+struct MlScratch;
+struct MlLease {
+  MlScratch* p;
+  MlLease();
+  ~MlLease();
+  MlLease(const MlLease&) = delete;
+  MlLease& operator=(const MlLease&) = delete;
+};
+void ml_trim();
+// pinned host arrays of the lease for a graph of n vertices and nnz entries (grown on demand):
+// row pointers, columns, edge weights
+void ml_stage(MlScratch& sc, int n, int64_t nnz, int32_t** rp, int32_t** col, int32_t** w);
 // Multilevel cores of at most `cap` vertices (host; mlpart.hip); core_vtx ascending per core.
 // ew (optional): per CSR entry, the number of common closed neighbours of its two ends
-// (computed here when NULL).
+// (computed here when NULL).  sc: the caller's lease (one is taken here when NULL).
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                          MlStats* stats, const int32_t* ew = nullptr);
+                          MlStats* stats, const int32_t* ew = nullptr, MlScratch* sc = nullptr);
 // The previous cores carried to a new graph on the same vertices (on-the-fly update between MD
 // steps): the cores renumbered as the partitioner emits them, and their cost on the new graph.
 void partition_update(int n, const int32_t* row_ptr, const int32_t* col,

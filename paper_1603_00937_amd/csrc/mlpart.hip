@@ -25,6 +25,8 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <cstdint>
 #include <vector>
@@ -69,31 +71,106 @@ struct Level {
   std::vector<int32_t> cmap;               // vertex -> vertex of the next coarser level
 };
 
-std::vector<int32_t> visit_order(int n, int level) {
-  std::vector<std::pair<uint64_t, int32_t>> k(n);
+}  // namespace
+
+struct MlScratch {
+  std::vector<Level> lv;  // lv[0]: the input level; coarse levels after it
+  std::vector<std::pair<uint64_t, int32_t>> keys;
+  std::vector<int32_t> order, top, match, lead, deg;
+  std::vector<std::vector<int32_t>> adj_t, ew_t, acc;
+  int32_t *h_rp = nullptr, *h_col = nullptr, *h_w = nullptr;  // pinned staging
+  size_t cap_rp = 0, cap_col = 0, cap_w = 0;
+};
+
+namespace {
+
+std::mutex g_ml_mu;
+std::vector<MlScratch*> g_ml_free;  // idle sets (never destroyed at exit: no HIP calls then)
+
+void pinned_reserve(int32_t*& p, size_t& cap, size_t count) {
+  if (count <= cap) return;
+  if (p) GB_HIP(hipHostFree(p));
+  p = nullptr;
+  const size_t want = count + count / 8;  // headroom for graphs that grow a little
+  GB_HIP(hipHostMalloc((void**)&p, want * sizeof(int32_t), hipHostMallocDefault));
+  cap = want;
+}
+
+void visit_order(int n, int level, MlScratch& sc) {
+  auto& k = sc.keys;
+  k.resize(n);
   for (int v = 0; v < n; ++v) k[v] = {splitmix64(((uint64_t)level << 32) | (uint32_t)v), v};
   std::sort(k.begin(), k.end());
-  std::vector<int32_t> o(n);
-  for (int i = 0; i < n; ++i) o[i] = k[i].second;
-  return o;
+  sc.order.resize(n);
+  for (int i = 0; i < n; ++i) sc.order[i] = k[i].second;
+}
+
+// The kTop heaviest candidates of every vertex by (edge weight, -vertex weight, -index),
+// heaviest first (-1 pads short lists), found on host threads.  The matching below walks a
+// vertex's list and takes the first candidate that is still unmatched and fits: that is the
+// maximum over all its neighbours unless every listed candidate is taken, in which case it
+// scans the whole row as before.
+constexpr int kTop = 8;
+bool heavier(const Level& f, int e, int u, int e2, int u2) {
+  if (f.ew[e] != f.ew[e2]) return f.ew[e] > f.ew[e2];
+  if (f.vw[u] != f.vw[u2]) return f.vw[u] < f.vw[u2];
+  return u < u2;
+}
+void top_candidates(const Level& f, std::vector<int32_t>& top) {
+  const int n = f.n;
+  top.assign((size_t)n * kTop, -1);
+  const int nt = f.rp[n] >= (1 << 16) ? worker_count() : 1;
+  run_workers(nt, [&](int t) {
+    const int v0 = (int)((int64_t)n * t / nt), v1 = (int)((int64_t)n * (t + 1) / nt);
+    int te[kTop];
+    for (int v = v0; v < v1; ++v) {
+      int m = 0;
+      for (int e = f.rp[v]; e < f.rp[v + 1]; ++e) {
+        const int u = f.adj[e];
+        if (u == v) continue;
+        if (m == kTop && !heavier(f, e, u, te[m - 1], f.adj[te[m - 1]])) continue;
+        int i = m < kTop ? m++ : kTop - 1;
+        for (; i > 0 && heavier(f, e, u, te[i - 1], f.adj[te[i - 1]]); --i) te[i] = te[i - 1];
+        te[i] = e;
+      }
+      for (int i = 0; i < m; ++i) top[(size_t)v * kTop + i] = f.adj[te[i]];
+    }
+  });
 }
 
 // Heavy-edge matching of f (pairs of weight <= cap); returns false if no pair was matched.
-bool coarsen(Level& f, int cap, int level, Level& c) {
+bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc) {
   const int n = f.n;
-  std::vector<int32_t> match(n, -1);
+  std::vector<int32_t>& match = sc.match;
+  match.assign(n, -1);
+  std::vector<int32_t>& top = sc.top;
+  top_candidates(f, top);
+  visit_order(n, level, sc);
   bool any = false;
-  for (int v : visit_order(n, level)) {
+  for (int v : sc.order) {
     if (match[v] >= 0) continue;
-    int best = -1, bw = -1, bvw = INT_MAX;
-    for (int e = f.rp[v]; e < f.rp[v + 1]; ++e) {
-      const int u = f.adj[e];
-      if (u == v || match[u] >= 0 || f.vw[u] + f.vw[v] > cap) continue;
-      const int w = f.ew[e];
-      if (w > bw || (w == bw && (f.vw[u] < bvw || (f.vw[u] == bvw && u < best)))) {
+    int best = -1;
+    bool listed_all = true;  // the list holds every neighbour, so no scan is needed
+    for (int i = 0; i < kTop; ++i) {
+      const int u = top[(size_t)v * kTop + i];
+      if (u < 0) break;
+      if (i == kTop - 1) listed_all = false;
+      if (match[u] < 0 && f.vw[u] + f.vw[v] <= cap) {
         best = u;
-        bw = w;
-        bvw = f.vw[u];
+        break;
+      }
+    }
+    if (best < 0 && !listed_all) {
+      int bw = -1, bvw = INT_MAX;
+      for (int e = f.rp[v]; e < f.rp[v + 1]; ++e) {
+        const int u = f.adj[e];
+        if (u == v || match[u] >= 0 || f.vw[u] + f.vw[v] > cap) continue;
+        const int w = f.ew[e];
+        if (w > bw || (w == bw && (f.vw[u] < bvw || (f.vw[u] == bvw && u < best)))) {
+          best = u;
+          bw = w;
+          bvw = f.vw[u];
+        }
       }
     }
     if (best >= 0) {
@@ -115,20 +192,34 @@ bool coarsen(Level& f, int cap, int level, Level& c) {
     }
   c.n = nc;
   c.vw.assign(nc, 0);
-  std::vector<int32_t> lead(nc, -1);  // the lower member of each pair
+  std::vector<int32_t>& lead = sc.lead;  // the lower member of each pair
+  lead.assign(nc, -1);
   for (int v = 0; v < n; ++v) {
     c.vw[f.cmap[v]] += f.vw[v];
     if (lead[f.cmap[v]] < 0) lead[f.cmap[v]] = v;
   }
-  // coarse adjacency: summed edge weights, neighbours ascending, no self loops.  Coarse
-  // vertices are independent, so contiguous ranges of them are built on separate threads and
-  // concatenated in order (the result does not depend on the thread count).
+  // coarse adjacency: summed edge weights, no self loops, neighbours in the order first met
+  // (the matching breaks every tie by index, so only the breadth-first order on the coarsest
+  // level needs them ascending; sort_rows does that there).  Coarse vertices are independent,
+  // so contiguous ranges of them are built on separate threads and concatenated in order (the
+  // result does not depend on the thread count).
   const int nt = nc >= 1024 ? worker_count() : 1;
-  std::vector<std::vector<int32_t>> adj_t(nt), ew_t(nt);
-  std::vector<int32_t> deg(nc, 0);
+  if ((int)sc.adj_t.size() < nt) {
+    sc.adj_t.resize(nt);
+    sc.ew_t.resize(nt);
+    sc.acc.resize(nt);
+  }
+  auto& adj_t = sc.adj_t;
+  auto& ew_t = sc.ew_t;
+  std::vector<int32_t>& deg = sc.deg;
+  deg.assign(nc, 0);
   auto build = [&](int t) {
     const int c0 = (int)((int64_t)nc * t / nt), c1 = (int)((int64_t)nc * (t + 1) / nt);
-    std::vector<int32_t> acc(nc, 0), touched;
+    std::vector<int32_t>& acc = sc.acc[t];
+    acc.assign(nc, 0);
+    std::vector<int32_t> touched;
+    adj_t[t].clear();
+    ew_t[t].clear();
     for (int cv = c0; cv < c1; ++cv) {
       const int v = lead[cv];
       const int members[2] = {v, match[v]};
@@ -143,7 +234,6 @@ bool coarsen(Level& f, int cap, int level, Level& c) {
           acc[cu] += f.ew[e];
         }
       }
-      std::sort(touched.begin(), touched.end());
       for (int cu : touched) {
         adj_t[t].push_back(cu);
         ew_t[t].push_back(acc[cu]);
@@ -166,6 +256,24 @@ bool coarsen(Level& f, int cap, int level, Level& c) {
   c.adj = c.adj_v.data();
   c.ew = c.ew_v.data();
   return true;
+}
+
+// Neighbours of a coarse level in ascending order, with their edge weights.
+void sort_rows(Level& g) {
+  const int nt = g.rp[g.n] >= (1 << 16) ? worker_count() : 1;
+  run_workers(nt, [&](int t) {
+    const int v0 = (int)((int64_t)g.n * t / nt), v1 = (int)((int64_t)g.n * (t + 1) / nt);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int v = v0; v < v1; ++v) {
+      row.clear();
+      for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) row.emplace_back(g.adj_v[e], g.ew_v[e]);
+      std::sort(row.begin(), row.end());
+      for (int e = g.rp[v], i = 0; e < g.rp[v + 1]; ++e, ++i) {
+        g.adj_v[e] = row[i].first;
+        g.ew_v[e] = row[i].second;
+      }
+    }
+  });
 }
 
 // Breadth-first order of a graph: components in ascending order of their smallest vertex,
@@ -331,38 +439,80 @@ double ms_since(clk::time_point t) {
 
 }  // namespace
 
+MlLease::MlLease() {
+  std::lock_guard<std::mutex> lk(g_ml_mu);
+  if (g_ml_free.empty()) {
+    p = new MlScratch;
+  } else {
+    p = g_ml_free.back();
+    g_ml_free.pop_back();
+  }
+}
+
+MlLease::~MlLease() {
+  std::lock_guard<std::mutex> lk(g_ml_mu);
+  g_ml_free.push_back(p);
+}
+
+void ml_trim() {
+  std::lock_guard<std::mutex> lk(g_ml_mu);
+  for (MlScratch* sc : g_ml_free) {
+    for (int32_t* q : {sc->h_rp, sc->h_col, sc->h_w})
+      if (q) GB_HIP(hipHostFree(q));
+    delete sc;
+  }
+  g_ml_free.clear();
+}
+
+void ml_stage(MlScratch& sc, int n, int64_t nnz, int32_t** rp, int32_t** col, int32_t** w) {
+  pinned_reserve(sc.h_rp, sc.cap_rp, (size_t)n + 1);
+  pinned_reserve(sc.h_col, sc.cap_col, (size_t)std::max<int64_t>(nnz, 1));
+  if (w) pinned_reserve(sc.h_w, sc.cap_w, (size_t)std::max<int64_t>(nnz, 1));
+  *rp = sc.h_rp;
+  *col = sc.h_col;
+  if (w) *w = sc.h_w;
+}
+
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                          MlStats* stats, const int32_t* ew) {
+                          MlStats* stats, const int32_t* ew, MlScratch* scr) {
+  std::unique_ptr<MlLease> own;
+  if (!scr) {
+    own.reset(new MlLease);
+    scr = own->p;
+  }
+  MlScratch& sc = *scr;
   auto t0 = clk::now();
-  std::vector<Level> lv(1);  // lv grows below: levels are addressed by index, not reference
-  input_level(n, row_ptr, col, ew, lv[0]);
+  if (sc.lv.empty()) sc.lv.resize(1);  // levels are addressed by index: lv may grow below
+  input_level(n, row_ptr, col, ew, sc.lv[0]);
   const double ms_weights = ms_since(t0);
   t0 = clk::now();
   const int ccap = std::max(1, cap / 4);
+  int nl = 1;
   for (int level = 0;; ++level) {
-    Level c;
-    if (!coarsen(lv.back(), ccap, level, c)) break;
-    lv.push_back(std::move(c));
+    if ((int)sc.lv.size() == nl) sc.lv.emplace_back();
+    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc)) break;
+    ++nl;
   }
+  if (nl > 1) sort_rows(sc.lv[nl - 1]);  // the input level keeps the caller's row order
   const double ms_coarsen = ms_since(t0);
   t0 = clk::now();
-  std::vector<int32_t> part = grow_parts(lv.back(), cap);
+  std::vector<int32_t> part = grow_parts(sc.lv[nl - 1], cap);
   const double ms_grow = ms_since(t0);
   t0 = clk::now();
   int np = 0;
   for (int p : part) np = std::max(np, p + 1);
-  for (int l = (int)lv.size() - 2; l >= 0; --l) {
-    std::vector<int32_t> fine(lv[l].n);
-    for (int v = 0; v < lv[l].n; ++v) fine[v] = part[lv[l].cmap[v]];
+  for (int l = nl - 2; l >= 0; --l) {
+    std::vector<int32_t> fine(sc.lv[l].n);
+    for (int v = 0; v < sc.lv[l].n; ++v) fine[v] = part[sc.lv[l].cmap[v]];
     part.swap(fine);
   }
-  const int64_t cost = subgraph_cost(lv[0], part, np);
+  const int64_t cost = subgraph_cost(sc.lv[0], part, np);
   const double ms_cost = ms_since(t0);
   emit_cores(n, part, np, core_ptr, core_vtx);
   if (stats) {
-    stats->levels = (int)lv.size();
-    stats->coarsest = lv.back().n;
+    stats->levels = nl;
+    stats->coarsest = sc.lv[nl - 1].n;
     stats->cost = cost;
     stats->ms_weights = ms_weights;
     stats->ms_coarsen = ms_coarsen;

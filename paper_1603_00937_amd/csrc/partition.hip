@@ -318,37 +318,40 @@ void partition_from_cores(const Csr& g, const std::vector<int32_t>& core_ptr,
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
                               MlStats* stats, const Part* prev) {
   const int n = g.n;
-  std::vector<int32_t> rp(n + 1), col(g.nnz), cp, cv;
+  std::vector<int32_t> cp, cv;
+  MlLease lease;  // pinned staging and coarse levels kept from earlier calls
+  int32_t *rp, *col, *w;
   if (prev) {
     // on-the-fly update: the previous cores carried to this graph (no weights needed)
     if (prev->n != n) fail(GB_ESHAPE, "previous partition has %d vertices, graph %d", prev->n, n);
+    ml_stage(*lease.p, n, g.nnz, &rp, &col, nullptr);
     std::vector<int32_t> pv(n);
-    GB_HIP(hipMemcpyAsync(rp.data(), g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
-    GB_HIP(hipMemcpyAsync(col.data(), g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(rp, g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(col, g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
     GB_HIP(hipMemcpyAsync(pv.data(), prev->core_vtx.get(), (size_t)n * 4, hipMemcpyDeviceToHost,
                           s));
     GB_HIP(hipStreamSynchronize(s));
-    partition_update(n, rp.data(), col.data(), prev->h_core_ptr, pv, cp, cv, stats);
+    partition_update(n, rp, col, prev->h_core_ptr, pv, cp, cv, stats);
     partition_from_cores(g, cp, cv, P, s);
     return;
   }
   // edge weights on the device (the graphs built here hold every self loop), the rest on the
   // host
-  std::vector<int32_t> w(g.nnz);
+  ml_stage(*lease.p, n, g.nnz, &rp, &col, &w);
   const size_t lds = (size_t)((n + 31) >> 5) * 4;
   if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "multilevel: n = %d too large for one LDS bitmap", n);
   DBuf<int32_t> dw(std::max<int64_t>(g.nnz, 1), s);
   hipLaunchKernelGGL(k_common_nb, dim3(n), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
                      dw.get());
   GB_LAUNCH_CHECK();
-  GB_HIP(hipMemcpyAsync(rp.data(), g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
-  GB_HIP(hipMemcpyAsync(col.data(), g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
-  GB_HIP(hipMemcpyAsync(w.data(), dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(rp, g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(col, g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(w, dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipStreamSynchronize(s));
   for (int v = 0; v < n; ++v)  // rows are sorted ascending
-    if (!std::binary_search(col.begin() + rp[v], col.begin() + rp[v + 1], v))
+    if (!std::binary_search(col + rp[v], col + rp[v + 1], v))
       fail(GB_EINVAL, "multilevel: vertex %d has no self loop", v);
-  partition_multilevel(n, rp.data(), col.data(), core_size, cp, cv, stats, w.data());
+  partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p);
   partition_from_cores(g, cp, cv, P, s);
 }
 
