@@ -1136,11 +1136,16 @@ __global__ __launch_bounds__(kT) void k_idem(const T* __restrict__ X, const T* _
 // core columns, and V q(X) for a slab V needs only products V X.
 
 // W = V X on the FP64 matrix cores: a wave computes all KMAX rows of 64 columns of W
-// (KMAX/16 x 4 tiles of 16 x 16, v_mfma_f64_16x16x4).  Per step of 4 rows of X, lane l
-// supplies A = V[16m + l%16][a + l/16] and B = X[a + l/16][c + 16n + l%16] (16 consecutive
-// columns per lane group, so every row segment is one 128-byte read); X is read once, V (a few
-// hundred KB per block) from cache.  Rows of V beyond k_s read as zero.  Output register r of
-// lane l holds row 4r + l/16 of its tile.
+// (KMAX/16 x 4 tiles of 16 x 16, v_mfma_f64_16x16x4) and walks the reduction in chunks of 16
+// rows of X.  Within a chunk, lane l (i = l%16, q = l/16) takes the four consecutive rows
+// a + 4q + u, u = the MFMA index: its A operands of a row tile are one 32-byte run of V
+// (V[16m + i][a + 4q .. a + 4q + 3]), and its B operands are 16-byte pairs of columns
+// (X[a + 4q + u][c + 32g + 2i, +1]; tile 2g + h holds the columns of parity h of group g), so a
+// chunk costs a wave 4 + 8 wide loads for 32 MFMAs.  X is read once; V (a few hundred KB per
+// block) comes from L2: the workgroups are numbered so that all column blocks of a subgraph run
+// on one XCD (workgroup i goes to XCD i mod 8), which fetches V into its L2 once.  Rows of V
+// beyond k_s are read in bounds (row k_s - 1) and zeroed by a select, keeping the loop free of
+// branches.  Output register r of lane l holds row 4r + q of its tile.
 template <int KMAX>
 __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
                                                  const int64_t* __restrict__ offs,
@@ -1148,25 +1153,24 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
                                                  const double* __restrict__ V,
                                                  double* __restrict__ W,
                                                  const int64_t* __restrict__ soffs,
-                                                 const int32_t* __restrict__ core_ptr) {
+                                                 const int32_t* __restrict__ core_ptr,
+                                                 int n_sub, int colblocks) {
   using M = Mfma<double>;
-  constexpr int MT = KMAX / 16, NT = 4;
-  const int s = blockIdx.y;
+  constexpr int MT = KMAX / 16, NT = 4, U = 4;
+  const int id = blockIdx.x, q8 = id >> 3;
+  const int s = (id & 7) + 8 * (q8 / colblocks), cb = q8 % colblocks;
+  if (s >= n_sub) return;  // the grid covers n_sub rounded up to 8
   const int np = npad[s];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int cw = blockIdx.x * 256 + wave * 64;
+  const int cw = cb * 256 + wave * 64;
   if (cw >= np) return;  // np is a multiple of 64: a wave is wholly inside or outside
   const int k = core_ptr[s + 1] - core_ptr[s];
   const int i16 = lane & 15, kq = lane >> 4;
-  const double* xs = X + offs[s] + (int64_t)kq * np + cw + i16;
-  const double* vs = V + soffs[s] + kq;
   M::acc_t acc[MT][NT];
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
     for (int n = 0; n < NT; ++n) acc[m][n] = M::acc_t{0, 0, 0, 0};
-  // rows beyond k read row k - 1 (in bounds) and are zeroed by a select, so the loop has no
-  // branches and its loads can be issued U steps ahead of their products
   bool rows_in[MT];
   int64_t roff[MT];
 #pragma unroll
@@ -1174,20 +1178,27 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
     rows_in[m] = m * 16 + i16 < k;
     roff[m] = (int64_t)min(m * 16 + i16, k - 1) * np;
   }
-  constexpr int U = 8;  // np is a multiple of 64 = 4 U rows
-  for (int a0 = 0; a0 < np; a0 += 4 * U) {
+  const double* vb = V + soffs[s] + 4 * kq;
+  const double* xb = X + offs[s] + (int64_t)(4 * kq) * np + cw + 2 * i16;
+  for (int a0 = 0; a0 < np; a0 += 16) {  // np is a multiple of 64
     double fa[U][MT], fb[U][NT];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int a = a0 + 4 * u;
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const double va = vs[roff[m] + a];
-        fa[u][m] = rows_in[m] ? va : 0.0;
-      }
-#pragma unroll
-      for (int n = 0; n < NT; ++n) fb[u][n] = xs[(int64_t)a * np + n * 16];
+    for (int m = 0; m < MT; ++m) {
+      const double2* pv = reinterpret_cast<const double2*>(vb + roff[m] + a0);
+      const double2 v0 = pv[0], v1 = pv[1];
+      fa[0][m] = rows_in[m] ? v0.x : 0.0;
+      fa[1][m] = rows_in[m] ? v0.y : 0.0;
+      fa[2][m] = rows_in[m] ? v1.x : 0.0;
+      fa[3][m] = rows_in[m] ? v1.y : 0.0;
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const double2 xv = *reinterpret_cast<const double2*>(xb + (int64_t)(a0 + u) * np + 32 * g);
+        fb[u][2 * g] = xv.x;
+        fb[u][2 * g + 1] = xv.y;
+      }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
@@ -1195,7 +1206,7 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = M::mma(fa[u][m], fb[u][n], acc[m][n]);
   }
-  double* ws = W + soffs[s] + cw + i16;
+  double* wb = W + soffs[s] + cw + 2 * i16;
 #pragma unroll
   for (int m = 0; m < MT; ++m)
 #pragma unroll
@@ -1203,7 +1214,9 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
       const int j = m * 16 + M::row(lane, r);
       if (j < k) {
 #pragma unroll
-        for (int n = 0; n < NT; ++n) ws[(int64_t)j * np + n * 16] = acc[m][n][r];
+        for (int g = 0; g < 2; ++g)
+          *reinterpret_cast<double2*>(wb + (int64_t)j * np + 32 * g) =
+              double2{acc[m][2 * g][r], acc[m][2 * g + 1][r]};
       }
     }
 }
@@ -2013,13 +2026,13 @@ struct RowsCtx {
   const int32_t* npad;
   hipStream_t s;
   void mm(const double* X, const double* V, double* W) const {
-    const dim3 grid(cr.colblocks, pl.n_sub);
+    const dim3 grid(cr.colblocks * ((pl.n_sub + 7) / 8 * 8));
     if (cr.kmax == 16)
       hipLaunchKernelGGL(k_rows_mm<16>, grid, dim3(256), 0, s, X, offs, npad, V, W, cr.soffs.get(),
-                         P.core_ptr.get());
+                         P.core_ptr.get(), pl.n_sub, cr.colblocks);
     else
       hipLaunchKernelGGL(k_rows_mm<32>, grid, dim3(256), 0, s, X, offs, npad, V, W, cr.soffs.get(),
-                         P.core_ptr.get());
+                         P.core_ptr.get(), pl.n_sub, cr.colblocks);
     GB_LAUNCH_CHECK();
   }
   void lin2(double* out, double a, const double* x, double b, const double* y) const {
