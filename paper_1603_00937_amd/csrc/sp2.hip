@@ -373,6 +373,27 @@ __device__ __forceinline__ void split_planes(float x, __bf16* out) {
   }
 }
 
+// The same split for two values at once, each plane's pair packed in one 32-bit word (x0 in the
+// low half): one packed conversion per plane, the plane values recovered by a shift and a mask
+// of that word, so the planes are bit-identical to split_planes.
+template <int NP>
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
+  float r0 = x0, r1 = x1;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+    const bf2v h = __builtin_convertvector(f2v{r0, r1}, bf2v);
+    uint32_t u;
+    __builtin_memcpy(&u, &h, 4);
+    w[p] = u;
+    if (p + 1 < NP) {
+      r0 -= __uint_as_float(u << 16);
+      r1 -= __uint_as_float(u & 0xffff0000u);
+    }
+  }
+}
+
 // Epilogue shared by the split-bf16 kernels: the new iterate v = big + small (or 2x - v), its
 // planes, each written at (row, col) and, off the diagonal blocks, at (col, row).  Lane l holds
 // rows 4(l/16) .. 4(l/16) + 3 of column l%16 of each 16 x 16 block, so its four values are one
@@ -803,20 +824,12 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
     for (int o = 0; o < 2; ++o)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        __bf16 pl[NP][4];
+        uint32_t lo[NP], hi[NP];
+        split_pair<NP>(stg[o][q][0], stg[o][q][1], lo);
+        split_pair<NP>(stg[o][q][2], stg[o][q][3], hi);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          __bf16 t[NP];
-          split_planes<NP>(stg[o][q][e], t);
-#pragma unroll
-          for (int p = 0; p < NP; ++p) pl[p][e] = t[p];
-        }
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          uint2 u;
-          __builtin_memcpy(&u, pl[p], 8);
-          *reinterpret_cast<uint2*>(&lds[p][o][ldo[q]]) = u;
-        }
+        for (int p = 0; p < NP; ++p)
+          *reinterpret_cast<uint2*>(&lds[p][o][ldo[q]]) = uint2{lo[p], hi[p]};
       }
     __syncthreads();
     if (kc + 1 < nk) {
