@@ -79,7 +79,9 @@ __global__ void k_x0(const int32_t* __restrict__ col, const double* __restrict__
 //   3. for k in row i, ascending: acc[rank(j)] += x0_ik * x0_kj for j in row k -- each j
 //      appears once per k, and a barrier separates the k steps, so every accumulator takes
 //      its terms in ascending k;
-//   4. keep j if |acc| >= tau or j == i; PASS 0 counts, PASS 1 writes the sorted columns.
+//   4. keep j if |acc| >= tau or j == i: the count, and the sorted columns into the row's slot
+//      of a staging array (cap entries per row; k_x2_compact then packs them into the CSR), so
+//      the product is computed once.
 struct X2Lds {
   uint32_t* bits;
   int32_t* pre;
@@ -125,12 +127,10 @@ __device__ int32_t lds_exclusive_scan(int32_t* v, int m, int32_t* red) {
   return carry;
 }
 
-template <int PASS>
 __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol,
                                                 const double* __restrict__ x0, int n, int w,
                                                 double tau, int cap, int32_t* __restrict__ cnt,
-                                                const int32_t* __restrict__ row_ptr,
-                                                int32_t* __restrict__ out_col,
+                                                int32_t* __restrict__ rows,
                                                 int32_t* __restrict__ overflow) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int i = blockIdx.x;
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
   if (ncand > cap) {
     if (threadIdx.x == 0) {
       atomicMax(overflow, ncand);
-      if (PASS == 0) cnt[i] = 0;
+      cnt[i] = 0;
     }
     return;
   }
@@ -204,23 +204,31 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
   }
   __syncthreads();
   const int32_t kept = lds_exclusive_scan(L.wcnt, nw, red);
-  if (PASS == 0) {
-    if (threadIdx.x == 0) cnt[i] = kept;
-    return;
-  }
-  const int32_t base = row_ptr[i];
+  if (threadIdx.x == 0) cnt[i] = kept;
+  int32_t* dst = rows + (int64_t)i * cap;  // kept <= ncand <= cap
   for (int q = threadIdx.x; q < nw; q += kT) {
     uint32_t word = L.bits[q];
     int r = L.pre[q];
-    int32_t pos = base + L.wcnt[q];
+    int32_t pos = L.wcnt[q];
     while (word) {
       const int b = __ffs(word) - 1;
       const int j = (q << 5) + b;
-      if (fabs(L.acc[r]) >= tau || j == i) out_col[pos++] = j;
+      if (fabs(L.acc[r]) >= tau || j == i) dst[pos++] = j;
       ++r;
       word &= word - 1u;
     }
   }
+}
+
+// row i of the staging array (cnt[i] columns at i * cap) -> the CSR at row_ptr[i]
+__global__ __launch_bounds__(kT) void k_x2_compact(const int32_t* __restrict__ rows, int cap,
+                                                   const int32_t* __restrict__ cnt,
+                                                   const int32_t* __restrict__ row_ptr,
+                                                   int32_t* __restrict__ out_col) {
+  const int i = blockIdx.x;
+  const int32_t* src = rows + (int64_t)i * cap;
+  int32_t* dst = out_col + row_ptr[i];
+  for (int t = threadIdx.x; t < cnt[i]; t += kT) dst[t] = src[t];
 }
 
 size_t x2_lds_bytes(int n, int w, int cap) {
@@ -516,16 +524,17 @@ void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream
   const int64_t cap_lds = (int64_t)((160 * 1024 - fixed) / 8);
   int64_t cap = std::min<int64_t>(std::min<int64_t>((int64_t)w * w, n), 4096);
   cap = std::min(cap, cap_lds);
-  DBuf<int32_t> cnt(n, s), ovf(1, s);
+  DBuf<int32_t> cnt(n, s), ovf(1, s), rows;
   out.n = n;
   out.row_ptr = DBuf<int32_t>(n + 1, s);
   int32_t h[2];
   for (int attempt = 0; attempt < 2; ++attempt) {
     const size_t lds = x2_lds_bytes(n, w, (int)cap);
     check_lds(lds, "X2 graph");
+    rows = DBuf<int32_t>((size_t)n * cap, s);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
-    hipLaunchKernelGGL(k_x2_rows<0>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
-                       cnt.get(), nullptr, nullptr, ovf.get());
+    hipLaunchKernelGGL(k_x2_rows, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
+                       cnt.get(), rows.get(), ovf.get());
     GB_LAUNCH_CHECK();
     exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
     GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
@@ -540,9 +549,8 @@ void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream
   }
   out.nnz = h[0];
   out.col = DBuf<int32_t>(h[0] > 0 ? h[0] : 1, s);
-  const size_t lds = x2_lds_bytes(n, w, (int)cap);
-  hipLaunchKernelGGL(k_x2_rows<1>, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
-                     nullptr, out.row_ptr.get(), out.col.get(), ovf.get());
+  hipLaunchKernelGGL(k_x2_compact, dim3(n), dim3(kT), 0, s, rows.get(), (int)cap, cnt.get(),
+                     out.row_ptr.get(), out.col.get());
   GB_LAUNCH_CHECK();
 }
 
