@@ -123,6 +123,26 @@ def test_library_host_entry_point_matches_oracle(name, cap):
     assert ocost == ccost
 
 
+def test_library_host_buffers_reused_across_graphs():
+    """The library keeps its coarse graphs and candidate lists between calls: calls on graphs
+    of different sizes, in an order that shrinks and regrows them, each give the oracle's
+    cores."""
+    import paper_1603_00937_amd as gb
+    graphs = {}
+    for name in ("small256", "tiny48", "n1024", "small256"):
+        if name not in graphs:
+            m = make_model(name)
+            rp, col = graph_x2(m["H_col"], m["H_val"], 1e-5)
+            graphs[name] = (rp, col, partition_multilevel(rp, col, 16))
+        rp, col, (ocp, ocv, ocost) = graphs[name]
+        ccp, ccv, ccost = gb.partition_host(rp, col, 16)
+        assert np.array_equal(ocp, ccp) and np.array_equal(ocv, ccv) and ocost == ccost, name
+    gb.trim()  # releases the idle buffer sets; the next call allocates afresh
+    rp, col, (ocp, ocv, ocost) = graphs["tiny48"]
+    ccp, ccv, ccost = gb.partition_host(rp, col, 16)
+    assert np.array_equal(ocp, ccp) and np.array_equal(ocv, ccv) and ocost == ccost
+
+
 def test_library_host_entry_point_rejects_bad_arguments():
     import paper_1603_00937_amd as gb
     rp, col = _csr(_cliques(2, 4))
