@@ -224,22 +224,37 @@ bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc) {
       const int v = lead[cv];
       const int members[2] = {v, match[v]};
       const int nm = match[v] == v ? 1 : 2;
-      touched.clear();
+      // every entry is written to the list and kept only if it is the first of its coarse
+      // neighbour (weights are positive, so acc == 0 means not yet met): no data-dependent
+      // branch in the loop over the edges; the coarse vertex itself starts marked, so self
+      // loops never enter the list
+      size_t span = 0;
+      for (int q = 0; q < nm; ++q) span += f.rp[members[q] + 1] - f.rp[members[q]];
+      if (touched.size() < span) touched.resize(span);
+      int32_t* tp = touched.data();
+      int m = 0;
+      acc[cv] = 1;
       for (int q = 0; q < nm; ++q) {
         const int x = members[q];
         for (int e = f.rp[x]; e < f.rp[x + 1]; ++e) {
           const int cu = f.cmap[f.adj[e]];
-          if (cu == cv) continue;
-          if (acc[cu] == 0) touched.push_back(cu);
-          acc[cu] += f.ew[e];
+          const int32_t a = acc[cu];
+          tp[m] = cu;
+          m += a == 0;
+          acc[cu] = a + f.ew[e];
         }
       }
-      for (int cu : touched) {
-        adj_t[t].push_back(cu);
-        ew_t[t].push_back(acc[cu]);
+      acc[cv] = 0;
+      const size_t o = adj_t[t].size();
+      adj_t[t].resize(o + m);
+      ew_t[t].resize(o + m);
+      for (int i = 0; i < m; ++i) {
+        const int cu = tp[i];
+        adj_t[t][o + i] = cu;
+        ew_t[t][o + i] = acc[cu];
         acc[cu] = 0;
       }
-      deg[cv] = (int32_t)touched.size();
+      deg[cv] = m;
     }
   };
   run_workers(nt, build);
@@ -247,11 +262,11 @@ bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc) {
   for (int cv = 0; cv < nc; ++cv) c.rp_v[cv + 1] = c.rp_v[cv] + deg[cv];
   c.adj_v.resize(c.rp_v[nc]);
   c.ew_v.resize(c.rp_v[nc]);
-  for (int t = 0; t < nt; ++t) {
+  run_workers(nt, [&](int t) {
     const int c0 = (int)((int64_t)nc * t / nt);
     std::copy(adj_t[t].begin(), adj_t[t].end(), c.adj_v.begin() + c.rp_v[c0]);
     std::copy(ew_t[t].begin(), ew_t[t].end(), c.ew_v.begin() + c.rp_v[c0]);
-  }
+  });
   c.rp = c.rp_v.data();
   c.adj = c.adj_v.data();
   c.ew = c.ew_v.data();
