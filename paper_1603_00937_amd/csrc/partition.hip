@@ -10,25 +10,34 @@ namespace {
 constexpr int kT = 256;
 
 __device__ int32_t lds_exclusive_scan(int32_t* v, int m, int32_t* red) {
-  int32_t carry = 0;
-  for (int base = 0; base < m; base += kT) {
-    const int k = base + threadIdx.x;
-    const int32_t x = k < m ? v[k] : 0;
+  // thread t owns the contiguous segment [t s, t s + s) of v, s = ceil(m / kT): segment sums,
+  // one scan of the kT sums, then each segment rewritten from its offset (one scan however
+  // long v is)
+  const int seg = (m + kT - 1) / kT;
+  const int b = min((int)threadIdx.x * seg, m), e = min(b + seg, m);
+  int32_t sum = 0;
+  for (int k = b; k < e; ++k) sum += v[k];
+  __syncthreads();
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over kT values
+  for (int d = 1; d < kT; d <<= 1) {
+    const int32_t y = threadIdx.x >= d ? red[threadIdx.x - d] : 0;
     __syncthreads();
-    red[threadIdx.x] = x;
-    __syncthreads();
-    for (int d = 1; d < kT; d <<= 1) {
-      const int32_t y = threadIdx.x >= d ? red[threadIdx.x - d] : 0;
-      __syncthreads();
-      red[threadIdx.x] += y;
-      __syncthreads();
-    }
-    if (k < m) v[k] = carry + red[threadIdx.x] - x;
-    carry += red[kT - 1];
+    red[threadIdx.x] += y;
     __syncthreads();
   }
-  return carry;
+  int32_t run = red[threadIdx.x] - sum;
+  for (int k = b; k < e; ++k) {
+    const int32_t x = v[k];
+    v[k] = run;
+    run += x;
+  }
+  const int32_t total = red[kT - 1];
+  __syncthreads();
+  return total;
 }
+
 
 template <int PASS>
 __global__ __launch_bounds__(kT) void k_halo(int n, const int32_t* __restrict__ rp,
