@@ -89,8 +89,10 @@ std::vector<MlScratch*> g_ml_free;  // idle sets (never destroyed at exit: no HI
 
 void pinned_reserve(int32_t*& p, size_t& cap, size_t count) {
   if (count <= cap) return;
-  if (p) GB_HIP(hipHostFree(p));
-  p = nullptr;
+  int32_t* old = p;
+  p = nullptr;  // consistent (empty) if a call below fails
+  cap = 0;
+  if (old) GB_HIP(hipHostFree(old));
   const size_t want = count + count / 8;  // headroom for graphs that grow a little
   GB_HIP(hipHostMalloc((void**)&p, want * sizeof(int32_t), hipHostMallocDefault));
   cap = want;
