@@ -135,6 +135,8 @@ __device__ int32_t lds_exclusive_scan(int32_t* v, int m, int32_t* red) {
 }
 
 
+constexpr int kX2Q = 4;  // ELL row entries per thread in the X2 accumulation (width <= 1024)
+
 __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol,
                                                 const double* __restrict__ x0, int n, int w,
                                                 double tau, int cap, int32_t* __restrict__ cnt,
@@ -179,21 +181,57 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
     }
     return;
   }
+  // the rows k taken are those before the first padding entry of row i
+  if (threadIdx.x == 0) red[0] = w;
   for (int r = threadIdx.x; r < ncand; r += kT) L.acc[r] = 0.0;
   __syncthreads();
-  // 3. canonical accumulation, k ascending
-  for (int t = 0; t < w; ++t) {
-    const int32_t k = L.ci[t];
-    if ((unsigned)k >= (unsigned)n) break;
+  for (int t = threadIdx.x; t < w; t += kT)
+    if ((unsigned)L.ci[t] >= (unsigned)n) atomicMin(&red[0], t);
+  __syncthreads();
+  const int kw = red[0];
+  // 3. canonical accumulation, k ascending: one barrier per row k.  Each thread holds the
+  //    entries of the next two rows in registers (w <= kX2Q kT, checked on the host), so their
+  //    global reads overlap the LDS updates of the current row.
+  int32_t ja[kX2Q], jb[kX2Q], jc[kX2Q];
+  double xa[kX2Q], xb[kX2Q], xc[kX2Q];
+  auto fetch = [&](int t, int32_t (&jj)[kX2Q], double (&xx)[kX2Q]) {
+    const bool on = t < kw;
+    const int32_t k = on ? L.ci[t] : 0;
+#pragma unroll
+    for (int q = 0; q < kX2Q; ++q) {
+      const int u = threadIdx.x + q * kT;
+      jj[q] = -1;
+      xx[q] = 0.0;
+      if (on && u < w) {
+        jj[q] = hcol[(int64_t)k * w + u];
+        xx[q] = x0[(int64_t)k * w + u];
+      }
+    }
+  };
+  auto apply = [&](int t, const int32_t (&jj)[kX2Q], const double (&xx)[kX2Q]) {
+    if (t >= kw) return;
     const double xik = L.xi[t];
-    for (int u = threadIdx.x; u < w; u += kT) {
-      const int32_t j = hcol[(int64_t)k * w + u];
+#pragma unroll
+    for (int q = 0; q < kX2Q; ++q) {
+      const int32_t j = jj[q];
       if ((unsigned)j >= (unsigned)n) continue;
       const uint32_t word = L.bits[j >> 5];
       const int r = L.pre[j >> 5] + __popc(word & ((1u << (j & 31)) - 1u));
-      const double prod = xik * x0[(int64_t)k * w + u];
+      const double prod = xik * xx[q];
       L.acc[r] = L.acc[r] + prod;
     }
+  };
+  fetch(0, ja, xa);
+  fetch(1, jb, xb);
+  for (int t = 0; t < kw; t += 3) {
+    fetch(t + 2, jc, xc);
+    apply(t, ja, xa);
+    __syncthreads();
+    fetch(t + 3, ja, xa);
+    apply(t + 1, jb, xb);
+    __syncthreads();
+    fetch(t + 4, jb, xb);
+    apply(t + 2, jc, xc);
     __syncthreads();
   }
   // 4. keep decision and ordered compaction
@@ -527,6 +565,7 @@ void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream
   const int n = H.n, w = H.width;
   // candidate capacity: small enough for several workgroups per CU; a row with more two-hop
   // candidates makes the counting pass report its count, and both passes rerun with it
+  if (w > kX2Q * kT) fail(GB_EUNSUPPORTED, "X2 graph: ELL width %d above %d", w, kX2Q * kT);
   const size_t fixed = x2_lds_bytes(n, w, 0);
   if (fixed > 150 * 1024) fail(GB_EUNSUPPORTED, "X2 graph: n = %d too large for one LDS bitmap", n);
   const int64_t cap_lds = (int64_t)((160 * 1024 - fixed) / 8);
