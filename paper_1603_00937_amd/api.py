@@ -17,6 +17,17 @@ def _lib():
     return L.load()
 
 
+def _release(obj, fn):
+    """Destroy obj's library handle once.  At interpreter exit the module's globals may already
+    be gone (objects alive then are collected after them); the process is ending and its device
+    memory with it, so there is nothing to release."""
+    h = getattr(obj, "_h", None)
+    if not h or _lib is None or L is None:
+        return
+    getattr(_lib(), fn)(h)
+    obj._h = None
+
+
 def _check(status):
     if status != L.GB_OK:
         raise GbError(status, _lib().gb_last_error().decode(errors="replace"))
@@ -130,9 +141,7 @@ class Graph:
         return rp, col[:self.nnz]
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _lib().gb_graph_destroy(self._h)
-            self._h = None
+        _release(self, "gb_graph_destroy")
 
 
 def build_graph(H_col, H_val, tau, mode="x2", aux=None, tau_aux=0.0) -> Graph:
@@ -186,9 +195,7 @@ class Partition:
         return cp, sp, si[:self.total]
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _lib().gb_partition_destroy(self._h)
-            self._h = None
+        _release(self, "gb_partition_destroy")
 
 
 def partition(graph: Graph, core_size: int, method="block") -> Partition:
@@ -287,9 +294,7 @@ class Tape:
         return G_H_val
 
     def __del__(self):
-        if getattr(self, "_h", None):
-            _lib().gb_tape_destroy(self._h)
-            self._h = None
+        _release(self, "gb_tape_destroy")
 
 
 def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precision="fp64",
