@@ -241,10 +241,12 @@ __global__ void k_sort_cores(const int32_t* __restrict__ order, const int32_t* _
 // Common closed neighbours of the ends of every edge: w[e] = |row u ∩ row col[e]| for the rows
 // of a CSR graph that holds its self loops (so each row is the closed neighbourhood).  One
 // workgroup per vertex u: row u as a bitmap in LDS, then one wave per neighbour v counting the
-// entries of row v found in it.
+// entries of row v found in it.  *missing receives the smallest u whose row lacks u (it is
+// left as it was when every row holds its self loop).
 __global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
-                                                  int32_t* __restrict__ w) {
+                                                  int32_t* __restrict__ w,
+                                                  int32_t* __restrict__ missing) {
   extern __shared__ uint32_t bits[];
   const int u = blockIdx.x;
   const int nw = (n + 31) >> 5;
@@ -256,6 +258,7 @@ __global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restri
     atomicOr(&bits[x >> 5], 1u << (x & 31));
   }
   __syncthreads();
+  if (threadIdx.x == 0 && !((bits[u >> 5] >> (u & 31)) & 1u)) atomicMin(missing, u);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int e = b + wave; e < e_end; e += kT / 64) {
     const int v = col[e];
@@ -349,17 +352,18 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
   ml_stage(*lease.p, n, g.nnz, &rp, &col, &w);
   const size_t lds = (size_t)((n + 31) >> 5) * 4;
   if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "multilevel: n = %d too large for one LDS bitmap", n);
-  DBuf<int32_t> dw(std::max<int64_t>(g.nnz, 1), s);
+  DBuf<int32_t> dw(std::max<int64_t>(g.nnz, 1), s), dmiss(1, s);
+  int32_t miss = n;  // no vertex lacks its self loop
+  GB_HIP(hipMemcpyAsync(dmiss.get(), &miss, 4, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_common_nb, dim3(n), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
-                     dw.get());
+                     dw.get(), dmiss.get());
   GB_LAUNCH_CHECK();
   GB_HIP(hipMemcpyAsync(rp, g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(col, g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(w, dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(&miss, dmiss.get(), 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipStreamSynchronize(s));
-  for (int v = 0; v < n; ++v)  // rows are sorted ascending
-    if (!std::binary_search(col + rp[v], col + rp[v + 1], v))
-      fail(GB_EINVAL, "multilevel: vertex %d has no self loop", v);
+  if (miss < n) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", miss);
   partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p);
   partition_from_cores(g, cp, cv, P, s);
 }
