@@ -76,7 +76,10 @@ struct Level {
 struct MlScratch {
   std::vector<Level> lv;  // lv[0]: the input level; coarse levels after it
   std::vector<std::pair<uint64_t, int32_t>> keys;
-  std::vector<int32_t> order, top, match, lead, deg;
+  std::vector<int32_t> top, match, lead, deg;
+  // visiting orders by level (a function of the level and the vertex count only, so they are
+  // kept for the next call on a graph of the same size)
+  std::vector<std::pair<int, std::vector<int32_t>>> orders;
   std::vector<std::vector<int32_t>> adj_t, ew_t, acc;
   int32_t *h_rp = nullptr, *h_col = nullptr, *h_w = nullptr;  // pinned staging
   size_t cap_rp = 0, cap_col = 0, cap_w = 0;
@@ -98,13 +101,18 @@ void pinned_reserve(int32_t*& p, size_t& cap, size_t count) {
   cap = want;
 }
 
-void visit_order(int n, int level, MlScratch& sc) {
+const std::vector<int32_t>& visit_order(int n, int level, MlScratch& sc) {
+  if ((int)sc.orders.size() <= level) sc.orders.resize(level + 1);
+  auto& slot = sc.orders[level];
+  if (slot.first == n && (int)slot.second.size() == n) return slot.second;
   auto& k = sc.keys;
   k.resize(n);
   for (int v = 0; v < n; ++v) k[v] = {splitmix64(((uint64_t)level << 32) | (uint32_t)v), v};
   std::sort(k.begin(), k.end());
-  sc.order.resize(n);
-  for (int i = 0; i < n; ++i) sc.order[i] = k[i].second;
+  slot.first = n;
+  slot.second.resize(n);
+  for (int i = 0; i < n; ++i) slot.second[i] = k[i].second;
+  return slot.second;
 }
 
 // The kTop heaviest candidates of every vertex by (edge weight, -vertex weight, -index),
@@ -147,9 +155,9 @@ bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc) {
   match.assign(n, -1);
   std::vector<int32_t>& top = sc.top;
   top_candidates(f, top);
-  visit_order(n, level, sc);
+  const std::vector<int32_t>& order = visit_order(n, level, sc);
   bool any = false;
-  for (int v : sc.order) {
+  for (int v : order) {
     if (match[v] >= 0) continue;
     int best = -1;
     bool listed_all = true;  // the list holds every neighbour, so no scan is needed
