@@ -160,12 +160,15 @@ void ml_trim();
 void ml_stage(MlScratch& sc, int n, int64_t nnz, int32_t** rp, int32_t** col, int32_t** w);
 // Multilevel cores of at most `cap` vertices (host; mlpart.hip); core_vtx ascending per core.
 // ew (optional): per CSR entry, the number of common closed neighbours of its two ends
-// (computed here when NULL).  sc: the caller's lease (one is taken here when NULL).
+// (computed here when NULL).  sc: the caller's lease (one is taken here when NULL).  stats
+// (optional) receives the level count, timings and the cost sum (|core| + |halo|)^3, which is
+// only computed when stats is given.
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
                           MlStats* stats, const int32_t* ew = nullptr, MlScratch* sc = nullptr);
 // The previous cores carried to a new graph on the same vertices (on-the-fly update between MD
-// steps): the cores renumbered as the partitioner emits them, and their cost on the new graph.
+// steps): the cores renumbered as the partitioner emits them, and (when stats is given) their
+// cost on the new graph.
 void partition_update(int n, const int32_t* row_ptr, const int32_t* col,
                       const std::vector<int32_t>& prev_ptr, const std::vector<int32_t>& prev_vtx,
                       std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,

@@ -532,7 +532,8 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
     for (int v = 0; v < sc.lv[l].n; ++v) fine[v] = part[sc.lv[l].cmap[v]];
     part.swap(fine);
   }
-  const int64_t cost = subgraph_cost(sc.lv[0], part, np);
+  // the cost is a statistic (the device path gets the subgraph sizes from its halos anyway)
+  const int64_t cost = stats ? subgraph_cost(sc.lv[0], part, np) : 0;
   const double ms_cost = ms_since(t0);
   emit_cores(n, part, np, core_ptr, core_vtx);
   if (stats) {
@@ -557,7 +558,7 @@ void partition_update(int n, const int32_t* row_ptr, const int32_t* col,
   std::vector<int32_t> part(n, -1);
   for (int p = 0; p < np; ++p)
     for (int i = prev_ptr[p]; i < prev_ptr[p + 1]; ++i) part[prev_vtx[i]] = p;
-  const int64_t cost = subgraph_cost(g0, part, np);
+  const int64_t cost = stats ? subgraph_cost(g0, part, np) : 0;
   emit_cores(n, part, np, core_ptr, core_vtx);
   if (stats) {
     stats->levels = 1;
