@@ -158,14 +158,19 @@ void ml_trim();
 // pinned host arrays of the lease for a graph of n vertices and nnz entries (grown on demand):
 // row pointers, columns, edge weights
 void ml_stage(MlScratch& sc, int n, int64_t nnz, int32_t** rp, int32_t** col, int32_t** w);
+// host array of the lease for n vertices' candidate lists (n * kMlTop entries)
+int32_t* ml_top_buffer(MlScratch& sc, int n);
 // Multilevel cores of at most `cap` vertices (host; mlpart.hip); core_vtx ascending per core.
 // ew (optional): per CSR entry, the number of common closed neighbours of its two ends
 // (computed here when NULL).  sc: the caller's lease (one is taken here when NULL).  stats
 // (optional) receives the level count, timings and the cost sum (|core| + |halo|)^3, which is
-// only computed when stats is given.
+// only computed when stats is given.  top0 (optional, with ew): per vertex the kMlTop heaviest
+// neighbours by (weight, -index), heaviest first, -1 padded (what the matching would compute).
+constexpr int kMlTop = 8;
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                          MlStats* stats, const int32_t* ew = nullptr, MlScratch* sc = nullptr);
+                          MlStats* stats, const int32_t* ew = nullptr, MlScratch* sc = nullptr,
+                          const int32_t* top0 = nullptr);
 // The previous cores carried to a new graph on the same vertices (on-the-fly update between MD
 // steps): the cores renumbered as the partitioner emits them, and (when stats is given) their
 // cost on the new graph.

@@ -120,7 +120,7 @@ const std::vector<int32_t>& visit_order(int n, int level, MlScratch& sc) {
 // vertex's list and takes the first candidate that is still unmatched and fits: that is the
 // maximum over all its neighbours unless every listed candidate is taken, in which case it
 // scans the whole row as before.
-constexpr int kTop = 8;
+constexpr int kTop = kMlTop;
 bool heavier(const Level& f, int e, int u, int e2, int u2) {
   if (f.ew[e] != f.ew[e2]) return f.ew[e] > f.ew[e2];
   if (f.vw[u] != f.vw[u2]) return f.vw[u] < f.vw[u2];
@@ -149,12 +149,15 @@ void top_candidates(const Level& f, std::vector<int32_t>& top) {
 }
 
 // Heavy-edge matching of f (pairs of weight <= cap); returns false if no pair was matched.
-bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc) {
+// given_top: the candidate lists of f computed elsewhere (the weights kernel does it for the
+// input level), else NULL
+bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
+             const int32_t* given_top = nullptr) {
   const int n = f.n;
   std::vector<int32_t>& match = sc.match;
   match.assign(n, -1);
-  std::vector<int32_t>& top = sc.top;
-  top_candidates(f, top);
+  if (!given_top) top_candidates(f, sc.top);
+  const int32_t* top = given_top ? given_top : sc.top.data();
   const std::vector<int32_t>& order = visit_order(n, level, sc);
   bool any = false;
   for (int v : order) {
@@ -498,9 +501,15 @@ void ml_stage(MlScratch& sc, int n, int64_t nnz, int32_t** rp, int32_t** col, in
   if (w) *w = sc.h_w;
 }
 
+int32_t* ml_top_buffer(MlScratch& sc, int n) {
+  sc.top.resize((size_t)n * kMlTop);
+  return sc.top.data();
+}
+
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
-                          MlStats* stats, const int32_t* ew, MlScratch* scr) {
+                          MlStats* stats, const int32_t* ew, MlScratch* scr,
+                          const int32_t* top0) {
   std::unique_ptr<MlLease> own;
   if (!scr) {
     own.reset(new MlLease);
@@ -516,7 +525,7 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
   int nl = 1;
   for (int level = 0;; ++level) {
     if ((int)sc.lv.size() == nl) sc.lv.emplace_back();
-    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc)) break;
+    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc, level == 0 ? top0 : nullptr)) break;
     ++nl;
   }
   if (nl > 1) sort_rows(sc.lv[nl - 1]);  // the input level keeps the caller's row order

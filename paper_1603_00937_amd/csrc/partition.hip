@@ -272,6 +272,51 @@ __global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restri
   }
 }
 
+// The kMlTop heaviest neighbours of every vertex by (weight, -index), heaviest first, -1
+// padded, the self loop skipped (the candidate lists the matching of the input level walks).
+// One wave per vertex: each lane keeps the best kMlTop of its strided share of the row as
+// 64-bit keys (weight, ~index), then kMlTop rounds of a wave maximum take the winners in order
+// (keys are unique within a row, so one lane wins each round and drops its head).
+__global__ __launch_bounds__(kT) void k_top_nb(int n, const int32_t* __restrict__ rp,
+                                               const int32_t* __restrict__ col,
+                                               const int32_t* __restrict__ w,
+                                               int32_t* __restrict__ top) {
+  const int lane = threadIdx.x & 63;
+  const int v = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (v >= n) return;  // wave-uniform
+  uint64_t best[kMlTop];
+#pragma unroll
+  for (int i = 0; i < kMlTop; ++i) best[i] = 0;
+  for (int e = rp[v] + lane; e < rp[v + 1]; e += 64) {
+    const int u = col[e];
+    if (u == v) continue;
+    uint64_t x = ((uint64_t)(uint32_t)w[e] << 32) | (uint32_t)(~(uint32_t)u);
+    if (x <= best[kMlTop - 1]) continue;
+#pragma unroll
+    for (int i = 0; i < kMlTop; ++i)
+      if (x > best[i]) {
+        const uint64_t t = best[i];
+        best[i] = x;
+        x = t;
+      }
+  }
+  for (int r = 0; r < kMlTop; ++r) {
+    uint64_t m = best[0];
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t lo = __shfl_xor((uint32_t)m, off, 64);
+      const uint32_t hi = __shfl_xor((uint32_t)(m >> 32), off, 64);
+      const uint64_t o = ((uint64_t)hi << 32) | lo;
+      m = o > m ? o : m;
+    }
+    if (m != 0 && best[0] == m) {
+#pragma unroll
+      for (int i = 0; i + 1 < kMlTop; ++i) best[i] = best[i + 1];
+      best[kMlTop - 1] = 0;
+    }
+    if (lane == 0) top[(int64_t)v * kMlTop + r] = m ? (int32_t)~(uint32_t)m : -1;
+  }
+}
+
 }  // namespace
 
 void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s, int method) {
@@ -358,13 +403,19 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
   hipLaunchKernelGGL(k_common_nb, dim3(n), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
                      dw.get(), dmiss.get());
   GB_LAUNCH_CHECK();
+  DBuf<int32_t> dtop((size_t)n * kMlTop, s);
+  hipLaunchKernelGGL(k_top_nb, dim3((n + kT / 64 - 1) / (kT / 64)), dim3(kT), 0, s, n,
+                     g.row_ptr.get(), g.col.get(), dw.get(), dtop.get());
+  GB_LAUNCH_CHECK();
+  int32_t* top = ml_top_buffer(*lease.p, n);  // read by the matching of the input level
   GB_HIP(hipMemcpyAsync(rp, g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(col, g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(w, dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipMemcpyAsync(top, dtop.get(), (size_t)n * kMlTop * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(&miss, dmiss.get(), 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipStreamSynchronize(s));
   if (miss < n) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", miss);
-  partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p);
+  partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p, top);
   partition_from_cores(g, cp, cv, P, s);
 }
 
