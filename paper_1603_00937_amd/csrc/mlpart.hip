@@ -25,6 +25,9 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <condition_variable>
+#include <exception>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -48,12 +51,80 @@ int worker_count() {
   return (int)std::max(1u, std::min(16u, h));
 }
 
+// Worker threads kept for the life of the process (starting and joining 16 threads costs a few
+// hundred microseconds, and a partition runs a dozen parallel passes).  One job at a time: a
+// call that finds the pool busy (another partition on another host thread) starts threads of
+// its own instead.  The pool is never destroyed, so no thread is joined at exit.
+class WorkerPool {
+ public:
+  bool try_run(int nt, const std::function<void(int)>& f) {
+    std::unique_lock<std::mutex> busy(run_mu_, std::try_to_lock);
+    if (!busy.owns_lock()) return false;
+    while ((int)threads_.size() < nt - 1) {
+      const int idx = (int)threads_.size() + 1;
+      threads_.emplace_back([this, idx] { loop(idx); });
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = &f;
+      nt_ = nt;
+      pending_ = nt - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    std::exception_ptr err;
+    try {
+      f(0);
+    } catch (...) {
+      err = std::current_exception();  // the other threads still use the job: wait first
+    }
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      done_.wait(lk, [this] { return pending_ == 0; });
+      job_ = nullptr;
+    }
+    if (err) std::rethrow_exception(err);
+    return true;
+  }
+
+ private:
+  void loop(int idx) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* f;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        if (idx >= nt_) continue;  // not part of this job
+        f = job_;
+      }
+      (*f)(idx);
+      std::lock_guard<std::mutex> lk(mu_);
+      if (--pending_ == 0) done_.notify_one();
+    }
+  }
+  std::mutex run_mu_, mu_;
+  std::condition_variable cv_, done_;
+  std::vector<std::thread> threads_;
+  const std::function<void(int)>* job_ = nullptr;
+  int nt_ = 0, pending_ = 0;
+  uint64_t gen_ = 0;
+};
+
+WorkerPool& worker_pool() {
+  static WorkerPool* pool = new WorkerPool;  // one for the process, never destroyed
+  return *pool;
+}
+
 template <typename F>
 void run_workers(int nt, F&& f) {
   if (nt <= 1) {
     f(0);
     return;
   }
+  const std::function<void(int)> job = [&f](int t) { f(t); };
+  if (worker_pool().try_run(nt, job)) return;
   std::vector<std::thread> th;
   for (int t = 0; t < nt; ++t) th.emplace_back(f, t);
   for (auto& x : th) x.join();

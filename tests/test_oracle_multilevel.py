@@ -143,6 +143,28 @@ def test_library_host_buffers_reused_across_graphs():
     assert np.array_equal(ocp, ccp) and np.array_equal(ocv, ccv) and ocost == ccost
 
 
+def test_library_host_concurrent_calls():
+    """Calls from several host threads at once (one uses the library's worker pool, the others
+    start threads of their own) each give the oracle's cores."""
+    import threading
+    import paper_1603_00937_amd as gb
+    m = make_model("n1024")
+    rp, col = graph_x2(m["H_col"], m["H_val"], 1e-5)
+    ocp, ocv, ocost = partition_multilevel(rp, col, 32)
+    results = [None] * 4
+
+    def run(i):
+        results[i] = gb.partition_host(rp, col, 32)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    for ccp, ccv, ccost in results:
+        assert np.array_equal(ocp, ccp) and np.array_equal(ocv, ccv) and ocost == ccost
+
+
 def test_library_host_entry_point_rejects_bad_arguments():
     import paper_1603_00937_amd as gb
     rp, col = _csr(_cliques(2, 4))
