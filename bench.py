@@ -28,7 +28,7 @@ PLANE_PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6}
 # takes a third of the step, nor at N = 100000, where it takes 0.3 s)
 WORKLOADS = {"n18000": dict(tau=1e-5, core=32, partition="multilevel"),
              "n1024": dict(tau=1e-5, core=16, partition="block"),
-             "n100000": dict(tau=1e-5, core=32, partition="block")}
+             "n100000": dict(tau=1e-5, core=32, partition="multilevel")}
 
 
 def kernel_source_hash() -> str:
