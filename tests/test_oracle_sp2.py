@@ -251,3 +251,36 @@ def test_low_memory_mode_matches(mid):
     b = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], 1e-5, 16, low_memory=True)
     assert a[2]["branch"] == b[2]["branch"]
     assert np.abs(a[1] - b[1]).max() < 1e-13
+
+
+def test_metrics_hand_example():
+    """Fig. 2 measures on a 2 x 2 case worked by hand.  diff = D - D_ref = [[.1, -.2],
+    [-.1, -.1]] (not symmetric, so a transposed H changes the band energy): max-abs 0.2;
+    Frobenius norm sqrt(.01 + .04 + .01 + .01) = sqrt(.07), per site (2 sites) sqrt(.07)/2;
+    Tr[diff H] = sum_ij diff_ij H_ji = .1*1 - .2*3 - .1*2 - .1*4 = -1.1, per site 0.55
+    (without the transpose it would be -1.0); Tr D = 1; D is idempotent."""
+    D = np.array([[1.0, 0.0], [0.0, 0.0]])
+    D_ref = np.array([[0.9, 0.2], [0.1, 0.1]])
+    H = np.array([[1.0, 2.0], [3.0, 4.0]])
+    e = errors(D, D_ref, H, 2)
+    assert abs(e["max_abs"] - 0.2) < 1e-15
+    assert abs(e["frob_per_site"] - np.sqrt(0.07) / 2) < 1e-15
+    assert abs(e["eband_err_per_site"] - 0.55) < 1e-15
+    assert e["trace"] == 1.0 and e["idem"] == 0.0
+
+
+def test_core_columns_equal_whole_system_oracle(mid):
+    """The oracle restricted to chosen cores (their subgraphs only, the whole run's branch
+    sequence replayed) gives the whole-system oracle's D columns bit for bit."""
+    from oracle.subgraphs import core_columns
+    m = mid
+    D_col, D_val, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], 1e-5, 16)
+    cp = info["core_ptr"]
+    picks = [0, 5, len(cp) - 2]
+    cores = [np.arange(cp[c], cp[c + 1]) for c in picks]
+    out = core_columns(m["H_col"], m["H_val"], m["n_occ"], 1e-5, cores, info["branch"])
+    for verts, (rows, vals) in zip(cores, out):
+        for c, v in enumerate(verts):
+            assert np.array_equal(D_col[v, :len(rows)], rows)
+            assert (D_col[v, len(rows):] == -1).all()
+            assert np.array_equal(D_val[v, :len(rows)], vals[c])
