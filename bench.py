@@ -57,12 +57,7 @@ def square_kernel_name(precision, stats):
     """The rocprof name of the loop's squaring kernel for this run."""
     if precision.startswith("bf16"):
         planes = {"bf16": 1, "bf16x3": 2, "bf16x6": 3}[precision]
-        v = stats.get("planes_db", 0)
-        if v == 2:
-            return "k_symm_mm_planes3p"
-        if v == 5:
-            return f"k_symm_mm_split<{planes}>"
-        return f"k_symm_mm_planes<{planes}, {2 if v == 3 else v}>"
+        return f"k_symm_mm_split<{planes}>"
     t = "double" if precision == "fp64" else "float"
     if stats.get("n_stage3", 0) == stats["n_sub"]:
         return f"k_symm_mm<{t}, 0, 64, 3, 0>"
@@ -114,7 +109,7 @@ def traffic_from_pmc(pmc_dir, workload="n18000"):
         w = os.path.join(pmc_dir, run + "_write", "run_results.db")
         if not (os.path.exists(f) and os.path.exists(w)):
             continue
-        prefix = ("k_symm_mm_split", "k_symm_mm_planes") if run.startswith("bf16") else (
+        prefix = ("k_symm_mm_split",) if run.startswith("bf16") else (
             ("k_symm_mm<double, 0,",) if run.startswith("fp64") else ("k_symm_mm<float, 0,",))
         kf, fv = _largest_grid_counter(f, prefix, "FETCH_SIZE")
         kw, wv = _largest_grid_counter(w, prefix, "WRITE_SIZE")
@@ -360,26 +355,27 @@ def copy_calibration(nbytes=4 << 30, reps=5):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}))
 
 
-def sample_error(D_col, D_val, golden):
-    dc = D_col.cpu().numpy()
-    dv = D_val.cpu().numpy()
-    errs = []
-    for r, s, v in golden["samples"]:
-        errs.append(abs(dv[r, s] - float.fromhex(v)))
-    from synth import ell_sha256
-    return float(max(errs)), ell_sha256(dc) == golden["D_col_sha256"]
+def host_cpu():
+    """CPU model and the number of cores this process may use (the oracle's host)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
 
 
 def cpu_baseline(model, workload, golden, n_sub_sample):
     """The CPU oracle on a bounded sample: graph rows of the sampled cores, their halos,
     gather and the full SP2 sequence (the oracle's own branch sequence, replayed, since
-    the branch needs every subgraph's trace) for n_sub_sample subgraphs."""
+    the branch needs every subgraph's trace) for n_sub_sample subgraphs.  Returns the record
+    and the oracle's D columns of the sampled cores (for the element-wise comparison)."""
     from threadpoolctl import threadpool_info
-    from oracle.bounds import gershgorin, x0_values
-    from oracle.graph import graph_x2
-    from oracle.sp2 import gather, sp2_partitioned
+    from oracle.subgraphs import core_columns
     cfg = WORKLOADS[workload]
-    Hc, Hv = model["H_col"], model["H_val"]
     N = model["N"]
     core = cfg["core"]
     if golden and "core_ptr" in golden:
@@ -393,26 +389,68 @@ def cpu_baseline(model, workload, golden, n_sub_sample):
         kind = "block cores"
     n_cores = len(cptr) - 1
     rng = np.random.default_rng(0)
-    picks = np.sort(rng.choice(n_cores, size=n_sub_sample, replace=False))
-    branch = [int(c) for c in golden["branch"]] if golden else None
+    picks = np.sort(rng.choice(n_cores, size=min(n_sub_sample, n_cores), replace=False))
+    branch = [int(c) for c in golden["branch"]]
+    cores = [cvtx[cptr[c]:cptr[c + 1]] for c in picks]
     t0 = time.time()
-    emin, emax = gershgorin(Hc, Hv)
-    x0 = x0_values(Hc, Hv, emin, emax)
-    blocks, kc = [], []
-    for c in picks:
-        verts = cvtx[cptr[c]:cptr[c + 1]]
-        rows = graph_x2(Hc, Hv, cfg["tau"], emin, emax, rows=verts)
-        halo = np.setdiff1d(np.unique(np.concatenate(rows)), verts)
-        sub = np.concatenate([verts, halo]).astype(np.int32)
-        blocks.append(gather(Hc, x0, sub))
-        kc.append(len(verts))
-    sp2_partitioned(blocks, kc, model["n_occ"], 0.0, branch_in=branch)
+    cols = core_columns(model["H_col"], model["H_val"], model["n_occ"], cfg["tau"], cores, branch)
     dt = time.time() - t0
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-    return {"value": float(sum(kc) / dt), "unit": "orbitals/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"{n_sub_sample} of {n_cores} subgraphs of {workload}, {kind} (graph rows, halo, "
-                      f"gather, {len(branch) if branch else 'all'} SP2 steps), {dt:.1f} s"}
+    cpu_model, n_cpu = host_cpu()
+    k = sum(len(c) for c in cores)
+    rec = {"value": float(k / dt), "unit": "orbitals/s", "cores": int(threads),
+           "kind": "oracle", "cpu_model": cpu_model, "host_cpus": n_cpu,
+           "sample": f"{len(picks)} of {n_cores} subgraphs of {workload}, {kind} (graph rows, "
+                     f"halo, gather, the {len(branch)} SP2 steps of the oracle's sequence), "
+                     f"{dt:.1f} s on {threads} BLAS threads"}
+    return rec, list(zip(cores, cols))
+
+
+def d_errors(dc, dv, ref_cols):
+    """Max-abs and Frobenius error of D (column-ELL host arrays) against the oracle on whole
+    sampled subgraphs (every entry of their core columns); the pattern must match."""
+    worst, sq, n_ent, pattern_ok = 0.0, 0.0, 0, True
+    for verts, (rows, vals) in ref_cols:
+        n = len(rows)
+        pattern_ok &= bool(np.array_equal(dc[verts, :n], np.broadcast_to(rows, (len(verts), n))))
+        d = dv[verts, :n] - vals
+        worst = max(worst, float(np.abs(d).max()))
+        sq += float((d * d).sum())
+        n_ent += d.size
+    return {"max_abs": worst, "frobenius": float(np.sqrt(sq)), "entries": n_ent,
+            "subgraphs": len(ref_cols), "pattern_equal": pattern_ok}
+
+
+def idempotency(dc, dv, col_sets):
+    """|D^2 - D| on the given columns of the assembled D (column-ELL host arrays): column j of
+    D^2 is the sum over the rows r of column j of D[r, j] * column r of D.  Returns max-abs and
+    Frobenius norm over those columns."""
+    worst, sq = 0.0, 0.0
+    for cols in col_sets:
+        rows_j = [dc[j][dc[j] >= 0] for j in cols]
+        R = np.unique(np.concatenate(rows_j))                # rows of the chosen columns
+        cr = [dc[r][dc[r] >= 0] for r in R]
+        U = np.unique(np.concatenate(cr + [R]))              # rows of D^2 on those columns
+        M = np.zeros((len(U), len(R)))
+        for a, r in enumerate(R):
+            M[np.searchsorted(U, cr[a]), a] = dv[r][:len(cr[a])]
+        B = np.zeros((len(R), len(cols)))
+        Dj = np.zeros((len(U), len(cols)))
+        for b, (j, rj) in enumerate(zip(cols, rows_j)):
+            B[np.searchsorted(R, rj), b] = dv[j][:len(rj)]
+            Dj[np.searchsorted(U, rj), b] = dv[j][:len(rj)]
+        E = M @ B - Dj
+        worst = max(worst, float(np.abs(E).max()))
+        sq += float((E * E).sum())
+    return {"max_abs": worst, "frobenius": float(np.sqrt(sq)),
+            "columns": int(sum(len(c) for c in col_sets))}
+
+
+def sym_square_flops(sizes, planes):
+    """Algorithmic flops of one symmetric squaring launch: the n(n+1)/2 upper entries of each
+    block's X^2, 2n flops each, times the bf16 plane products of the split method."""
+    n = np.asarray(sizes, dtype=np.float64)
+    return float((n * n * (n + 1.0)).sum()) * planes
 
 
 def main():
@@ -422,12 +460,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x6",
                     choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
-    ap.add_argument("--launch-mode", default="batched", choices=["batched", "per_subgraph", "graph"])
+    ap.add_argument("--launch-mode", default="device",
+                    choices=["device", "per_subgraph", "graph", "host"])
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from-pmc", default=None,
                     help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r", "db", "sb", "pipe", "sbr",
-                             "split"])
+    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2", "mcweeny_blocks"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
@@ -498,21 +536,68 @@ def main():
     Hv = torch.from_numpy(model["H_val"]).to(dev)
     g = gb.build_graph(Hc, Hv, cfg["tau"])
     p = gb.partition(g, cfg["core"], method=args.partition)
+    sizes = np.diff(p.arrays()[1].cpu().numpy())
     D = (torch.empty((N, p.max_sub), dtype=torch.int32, device=dev),
          torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
     del g, p
 
-    out = measure(gb, torch, args, args.precision, model, cfg, Hc, Hv, D, golden)
-    if args.precision != "fp64" and not args.no_fp64_compare:
-        ref = measure(gb, torch, args, "fp64", model, cfg, Hc, Hv, D, golden)
+    out = measure(gb, torch, args, args.precision, model, cfg, Hc, Hv, D, golden, sizes)
+    dcm, dvm = D[0].cpu().numpy(), D[1].cpu().numpy()
+    low = args.precision != "fp64"
+    dcf = dvf = None
+    if low and not args.no_fp64_compare:
+        ref = measure(gb, torch, args, "fp64", model, cfg, Hc, Hv, D, golden, sizes)
+        dcf, dvf = D[0].cpu().numpy(), D[1].cpu().numpy()
         out["fp64_gpu"] = {k: ref[k] for k in ("value", "ms_per_step", "roofline", "accuracy")}
         out["speedup_vs_fp64_gpu"] = out["value"] / ref["value"]
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(model, args.workload, golden, args.cpu_sample)
-    print(json.dumps(out), flush=True)
+    ref_cols = None
+    if golden and not args.no_cpu_baseline:
+        out["cpu_baseline"], ref_cols = cpu_baseline(model, args.workload, golden,
+                                                     args.cpu_sample)
+    # accuracy (outside the timed region): every entry of the sampled subgraphs' core columns
+    # against the oracle; the whole D against the FP64 GPU path of the same run; |D^2 - D| on
+    # the core columns of 16 of the sampled subgraphs
+    acc = out["accuracy"]
+    n_sites = N // 2
+    if golden:
+        acc["D_pattern_bit_exact"] = ell_sha256(dcm) == golden["D_col_sha256"]
+    if ref_cols is not None:
+        e = d_errors(dcm, dvm, ref_cols)
+        acc["vs_oracle_subgraphs"] = e
+        idem_cols = [v for v, _ in ref_cols[:16]]
+        acc["idempotency_D"] = idempotency(dcm, dvm, idem_cols)
+        if dcf is not None:
+            out["fp64_gpu"]["accuracy"]["vs_oracle_subgraphs"] = d_errors(dcf, dvf, ref_cols)
+            out["fp64_gpu"]["accuracy"]["idempotency_D"] = idempotency(dcf, dvf, idem_cols)
+    if dcf is not None:
+        same = bool(np.array_equal(dcm, dcf))
+        d = dvm - dvf
+        acc["vs_fp64_gpu_whole_D"] = {
+            "pattern_equal": same, "max_abs": float(np.abs(d).max()),
+            "frobenius": float(np.linalg.norm(d)),
+            "frobenius_per_site": float(np.linalg.norm(d)) / n_sites,
+            "entries": int((dcm >= 0).sum())}
+    worst = [acc.get("vs_oracle_subgraphs", {}).get("max_abs")]
+    if "vs_fp64_gpu_whole_D" in acc and "fp64_gpu" in out:
+        fe = out["fp64_gpu"]["accuracy"].get("vs_oracle_subgraphs", {}).get("max_abs", 0.0)
+        worst.append(acc["vs_fp64_gpu_whole_D"]["max_abs"] + fe)
+    known = [w for w in worst if w is not None]
+    acc["meets_1e-6"] = bool(known) and max(known) <= 1e-6
+    print(json.dumps(_finite(out)), flush=True)
 
 
-def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
+def _finite(x):
+    """JSON has no NaN / Inf: such values (an unmeasured quantity) become null."""
+    if isinstance(x, dict):
+        return {k: _finite(v) for k, v in x.items()}
+    if isinstance(x, list):
+        return [_finite(v) for v in x]
+    if isinstance(x, float) and not np.isfinite(x):
+        return None
+    return x
+
+
+def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
     """Warm-up, then K timed steps of the whole path in ``precision``; one result record."""
     N, n_occ = model["N"], model["n_occ"]
     a = argparse.Namespace(**vars(args))
@@ -534,15 +619,18 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
     # graph and partition are separate calls before gb_density: their wall time per step
     stats["ms"]["graph"] = host_ms["graph"] / args.steps
     stats["ms"]["part"] = host_ms["part"] / args.steps
-    flops_alg = stats["square_flops"]
-    flops_exec = stats["square_flops_exec"] * PLANE_PRODUCTS.get(precision, 1)
-    # the dominant kernel is the squaring launch of the loop's precision (the low-precision
-    # path also runs a few FP64 refinement squares, reported in stage_ms)
+    planes = PLANE_PRODUCTS.get(precision, 1)
+    # algorithmic work of one squaring launch: the symmetric square (upper triangle) of every
+    # block, times the plane products of the split method; executed: what the matrix cores
+    # run (blocks padded to 64, whole diagonal tiles); dense-equivalent: sum 2 n^3
+    flops_alg = sym_square_flops(sizes, planes)
+    flops_exec = stats["square_flops_exec"] * planes
+    flops_dense = stats["square_flops"]
     peak = PEAK_TFLOPS[precision]
-    # per-launch events exist in the host-driven modes only (the hipGraph loop runs unsplit)
+    # per-launch HIP events around every square (host and device-driven loops; the hipGraph
+    # replay has none)
     avg_launch_s = (sq_ms / sq_n / 1e3) if (sq_n and sq_ms > 0) else None
     achieved = flops_alg / avg_launch_s / 1e12 if avg_launch_s else None
-    err, pattern_ok = (sample_error(D[0], D[1], golden) if golden else (None, None))
     return {
         "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
@@ -566,15 +654,16 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden):
                                                  args.partition),
                      "kernel": square_kernel_name(precision, stats),
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
-                     "exec_tflops": flops_exec / avg_launch_s / 1e12 if avg_launch_s else None,
-                     "avg_launch_ms": avg_launch_s * 1e3 if avg_launch_s else None},
-        "accuracy": {"max_abs_err_vs_oracle_samples": err,
-                     "meets_1e-6": (err is not None and err <= 1e-6),
-                     "D_pattern_bit_exact": pattern_ok,
-                     "converged": stats["converged"], "trace_D": stats["trace"],
-                     "idem_max": stats["idem_max"], "branch": "".join(map(str, stats["branch"])),
+                     "flops_per_launch_dense_2n3": flops_dense,
+                     "exec_frac": (flops_exec / avg_launch_s / 1e12 / peak) if avg_launch_s
+                     else None,
+                     "avg_launch_ms": avg_launch_s * 1e3 if avg_launch_s else None,
+                     "launches": sq_n},
+        "accuracy": {"converged": stats["converged"], "trace_D": stats["trace"],
+                     "branch": "".join(map(str, stats["branch"])),
                      "branch_matches_oracle": (golden is not None and
-                                               "".join(map(str, stats["branch"])) == golden["branch"])},
+                                               "".join(map(str, stats["branch"])) == golden["branch"]),
+                     "n_near_tie": stats["n_near_tie"]},
         "stage_ms": stats["ms"],
     }
 

@@ -235,26 +235,35 @@ typedef struct {
   const gb_partition_t* partition; /* NULL: build X2(threshold) + BLOCK(core_size) inside    */
   int32_t core_size;         /* used when partition == NULL; default 32                      */
   const uint8_t* branch_in;  /* (host) replay this branch sequence instead of choosing it    */
-  int32_t n_branch_in;
+  int32_t n_branch_in;       /* at most 127 (the stats record 128 steps)                     */
   double emin, emax;         /* spectral bounds; both 0 = Gershgorin                          */
   int32_t keep_tape;         /* 1: keep SP2 checkpoints for gb_density_vjp (GB_FP64 only)    */
   int32_t tape_stride;       /* checkpoint every tape_stride-th iterate; 0 = 4               */
-  int32_t launch_mode;       /* 0: one batched squaring launch per step, the host reads the   *
-                              *    stop flag after every step (default);                      *
-                              * 1: one launch per subgraph per step (baseline);               *
-                              * 2: batched launches with the stop flag, counter and branch    *
-                              *    records on the device, two steps captured in a hipGraph    *
-                              *    and replayed (no host round trip per step; no tape)        */
+  int32_t launch_mode;       /* 0 (default): device-driven loop -- one batched squaring     *
+                              *    launch per step over every subgraph; the stop flag, step   *
+                              *    counter, branch and step records stay on the device, every *
+                              *    launch reads the branch there and returns at once after    *
+                              *    the stop, so the host enqueues 32 steps (then 8 at a time) *
+                              *    without waiting for any decision;                          *
+                              * 1: one launch per subgraph per step, decided on the host     *
+                              *    (the baseline);                                            *
+                              * 2: as 0 with two steps captured in a hipGraph and replayed;   *
+                              * 3: batched launches, every decision read back by the host.    *
+                              * keep_tape and refine_kind 1 run their steps as in 3.          */
   int32_t tile_policy;       /* FP64 / FP32 squares: kernel variant autotuned per 256-wide    *
                               * size bucket (0, timed once per process), 1 = 128-edge tiles,  *
                               * 2 = 64-edge, 4 = 64-edge with three LDS stages, 5 = 64-edge   *
                               * with register-staged loads;                                   *
-                              * split-bf16 squares: kernel variant autotuned (0), 1 = double- *
-                              * buffered LDS, 2 = single-buffered, 3 = pipelined (three       *
-                              * planes; others as 2), 4 = single-buffered, register-staged,   *
-                              * 5 = split into planes in registers from the FP32 iterate (no  *
-                              * stored planes).  FP64 / FP32 treat 3 as 0.                    */
+                              * split-bf16 squares ignore it (one kernel).  3 is taken as 0. */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
+  int32_t check_idem;        /* 1: also compute stats.idem_max, max |X^2 - X| over the core   *
+                              *    columns (one more square of the core tiles, or nine slab  *
+                              *    products after the core-row refinement); 0 (default): the  *
+                              *    FP64 trace stop test alone, stats.idem_max = NaN           */
+  void* workspace;           /* caller-owned device memory for the batch buffers and X0     *
+                              * (256-byte aligned, at least gb_density_workspace bytes; needs *
+                              * a partition); NULL: buffers cached by the library (gb_trim)   */
+  size_t workspace_bytes;
 } gb_sp2_opts;
 
 typedef struct {
@@ -282,6 +291,9 @@ typedef struct {
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
   double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
   struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */
+  int32_t n_near_tie;        /* trace-rule decisions whose margin is within the rounding of   *
+                              * the summed traces (64 ulp of |t1| + |t2| + n_occ): another     *
+                              * summation order could have taken the other branch             */
 } gb_sp2_stats;
 
 typedef struct gb_tape_s gb_tape_t;
@@ -293,12 +305,27 @@ typedef struct gb_tape_s gb_tape_t;
  *   Loop: square every subgraph block; t1, t2 = sums of the core diagonals of X and X^2 over
  *   all subgraphs (FP64); stop if |t1 - t2| <= idem_tol (D is the current X); otherwise
  *   X <- X^2 if |t2 - n_occ| < |2 t1 - t2 - n_occ|, else X <- 2X - X^2, for every subgraph.
- * Non-convergence is not an error (stats->converged = 0).  stats may be NULL.  The call
- * synchronises `stream` once per SP2 iteration (to read the stop flag) and at the end.
- * GB_ESHAPE if D->width < max_sub (stats->max_sub then holds the needed width).
+ * Non-convergence is not an error (stats->converged = 0).  stats may be NULL.
+ * Synchronisation (launch modes 0 and 2): `stream` is waited for once to read the spectral
+ * bounds, once when the squaring loop has stopped (once more per 8 steps beyond the first 32),
+ * once after the low-precision refinement check, and at the end; modes 1 and 3 also wait once
+ * per SP2 step.  Without a partition the graph and partition steps add one wait each.
+ * GB_EINVAL if H holds NaN or Inf (checked on the Gershgorin pass, also with given bounds).
+ * GB_ESHAPE if D->width < max_sub (stats->max_sub then holds the needed width), or if the
+ * caller's workspace is smaller than gb_density_workspace returns.
  */
 gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_sp2_opts* opts,
                      gb_ell* D, gb_sp2_stats* stats, void* stream);
+
+/*
+ * Bytes of caller-owned workspace gb_density needs with these options on opts->partition (the
+ * dense batch buffers of the partition's subgraphs, padded to multiples of 64, in the loop's
+ * precision and FP64, the core-row refinement slabs and X0 on H's pattern; statement of the
+ * problem: D from H through the subgraph expansions).  Host only; H's arrays are not read
+ * (only H->n and H->width).  GB_EINVAL without a partition.  Handles, the tape and small
+ * per-call arrays (offsets, tile lists, partial traces) still come from the allocator.
+ */
+gb_status gb_density_workspace(const gb_ell* H, const gb_sp2_opts* opts, size_t* bytes);
 
 /*
  * a14. Adjoint of the expansion recorded by gb_density(keep_tape = 1): given dL/dD on D's

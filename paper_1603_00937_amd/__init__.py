@@ -7,5 +7,5 @@ from .api import (  # noqa: F401
     GbError, Graph, Partition, Tape, DensityFn, spectral_bounds, build_graph, partition, density,
     density_with_grad, version, TorchAllocator, set_allocator, foe_density, chebyshev_fermi,
     foe_solve_mu, sp2_sequence, sp2_estimate_gap, gap_inputs, build_graph_rcut, trim,
-    partition_host, partition_update, partition_update_host,
+    partition_host, partition_update, partition_update_host, density_workspace,
 )

@@ -11,6 +11,8 @@ STATUS_NAMES = {0: "GB_OK", -1: "GB_EINVAL", -2: "GB_ENOMEM", -3: "GB_EHIP", -4:
 GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2, "dprev_symbolic": 3}
 PART_METHODS = {"block": 0, "bfs": 1, "multilevel": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4}
+# launch modes of gb_density ("batched" is the device-driven default)
+LAUNCH_MODES = {"device": 0, "batched": 0, "per_subgraph": 1, "graph": 2, "host": 3}
 
 
 class GbEll(ctypes.Structure):
@@ -27,7 +29,8 @@ class GbSp2Opts(ctypes.Structure):
                 ("emin", ctypes.c_double), ("emax", ctypes.c_double),
                 ("keep_tape", ctypes.c_int32), ("tape_stride", ctypes.c_int32),
                 ("launch_mode", ctypes.c_int32), ("tile_policy", ctypes.c_int32),
-                ("tile_order", ctypes.c_int32)]
+                ("tile_order", ctypes.c_int32), ("check_idem", ctypes.c_int32),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class GbSp2Stats(ctypes.Structure):
@@ -48,7 +51,7 @@ class GbSp2Stats(ctypes.Structure):
                 ("planes_db", ctypes.c_int32), ("n_stage3", ctypes.c_int32),
                 ("n_regstage", ctypes.c_int32),
                 ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double),
-                ("tape", ctypes.c_void_p)]
+                ("tape", ctypes.c_void_p), ("n_near_tie", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -121,6 +124,7 @@ SIGNATURES = {
     "gb_trim": (ctypes.c_int32, []),
     "gb_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double, _P(GbSp2Opts),
                                     _P(GbEll), _P(GbSp2Stats), _vp]),
+    "gb_density_workspace": (ctypes.c_int32, [_P(GbEll), _P(GbSp2Opts), _P(ctypes.c_size_t)]),
     "gb_density_vjp": (ctypes.c_int32, [_vp, _P(GbEll), _P(GbEll), _vp]),
     "gb_tape_destroy": (None, [_vp]),
     "gb_foe_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double,

@@ -269,6 +269,7 @@ def _stats_dict(st: L.GbSp2Stats) -> dict:
         "n_regstage": st.n_regstage,
         "square_flops": st.square_flops,
         "square_flops_exec": st.square_flops_exec,
+        "n_near_tie": st.n_near_tie,
     }
 
 
@@ -297,13 +298,50 @@ class Tape:
         _release(self, "gb_tape_destroy")
 
 
+def _sp2_opts(precision="fp64", n_refine=0, max_iter=0, idem_tol=0.0, part=None, core_size=32,
+              refine="mcweeny", n_fp64_first=0, keep_tape=False, tape_stride=0, launch_mode=0,
+              tile_policy="auto", tile_order="xcd", check_idem=False, emin=None, emax=None):
+    o = L.GbSp2Opts()
+    o.precision = L.PRECISIONS[precision]
+    o.n_refine = int(n_refine)
+    o.refine_kind = {"mcweeny": 0, "sp2": 1, "mcweeny_blocks": 2}[refine]
+    o.n_fp64_first = int(n_fp64_first)
+    o.max_iter = int(max_iter)
+    o.idem_tol = float(idem_tol)
+    o.partition = part.handle if part is not None else None
+    o.core_size = int(core_size)
+    if emin is not None and emax is not None:
+        o.emin, o.emax = float(emin), float(emax)
+    o.keep_tape = 1 if keep_tape else 0
+    o.tape_stride = int(tape_stride)
+    o.launch_mode = L.LAUNCH_MODES.get(launch_mode, launch_mode)
+    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4,
+                     "64r": 5}.get(tile_policy, tile_policy)
+    o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
+    o.check_idem = 1 if check_idem else 0
+    return o
+
+
+def density_workspace(H_col, partition, precision="fp64", **kw) -> int:
+    """Bytes of caller-owned workspace :func:`density` needs on ``partition`` (pass a uint8
+    GPU tensor of at least this size as ``workspace=``)."""
+    _dev(H_col, torch.int32, "H_col")
+    H = L.GbEll(H_col.shape[0], H_col.shape[1], H_col.data_ptr(), None)
+    o = _sp2_opts(precision=precision, part=partition, **kw)
+    nb = ctypes.c_size_t()
+    _check(_lib().gb_density_workspace(ctypes.byref(H), ctypes.byref(o), ctypes.byref(nb)))
+    return nb.value
+
+
 def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precision="fp64",
             n_refine=0, max_iter=0, idem_tol=0.0, branch_in=None, emin=None, emax=None,
             D=None, refine="mcweeny", n_fp64_first=0, keep_tape=False, tape_stride=0, launch_mode=0,
-            tile_policy="auto", tile_order="xcd"):
+            tile_policy="auto", tile_order="xcd", check_idem=False, workspace=None):
     """Partitioned SP2 density matrix.  Returns (D_col, D_val, stats); D is column-ELL
     [n, max_sub] (row i of the arrays = column i of D).  With ``partition`` None the X2 graph
-    at ``threshold`` and a block partition with ``core_size`` are built first."""
+    at ``threshold`` and a block partition with ``core_size`` are built first.  ``workspace``:
+    a uint8 GPU tensor of at least :func:`density_workspace` bytes for the batch buffers
+    (needs ``partition``)."""
     H = _ell(H_col, H_val)
     part = partition
     if part is None:
@@ -315,32 +353,20 @@ def density(H_col, H_val, n_occ, threshold, partition=None, core_size=32, precis
     else:
         D_col, D_val = D
     De = _ell(D_col, D_val)
-    o = L.GbSp2Opts()
-    o.precision = L.PRECISIONS[precision]
-    o.n_refine = int(n_refine)
-    o.refine_kind = {"mcweeny": 0, "sp2": 1, "mcweeny_blocks": 2}[refine]
-    o.n_fp64_first = int(n_fp64_first)
-    o.max_iter = int(max_iter)
-    o.idem_tol = float(idem_tol)
-    o.partition = part.handle
-    o.core_size = int(core_size)
+    o = _sp2_opts(precision, n_refine, max_iter, idem_tol, part, core_size, refine, n_fp64_first,
+                  keep_tape, tape_stride, launch_mode, tile_policy, tile_order, check_idem,
+                  emin, emax)
+    if workspace is not None:
+        if partition is None:
+            raise ValueError("a caller-owned workspace needs a partition")
+        _dev(workspace, torch.uint8, "workspace")
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel()
     keep = None
     if branch_in is not None:
         keep = (ctypes.c_uint8 * max(len(branch_in), 1))(*[int(b) for b in branch_in])
         o.branch_in = ctypes.cast(keep, ctypes.c_void_p)
         o.n_branch_in = len(branch_in)
-    if emin is not None and emax is not None:
-        o.emin, o.emax = float(emin), float(emax)
-    o.keep_tape = 1 if keep_tape else 0
-    o.tape_stride = int(tape_stride)
-    o.launch_mode = {"batched": 0, "per_subgraph": 1, "graph": 2}.get(launch_mode, launch_mode)
-    # "db" / "sb": the split-bf16 kernel variant (double- / single-buffered LDS)
-    # split-bf16 variants: "db" double-buffered, "sb" single-buffered, "pipe" pipelined three
-    # planes, "sbr" single-buffered with register staging, "split" planes formed in registers
-    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "db": 1, "sb": 2,
-                     "pipe": 3, "64s3": 4, "sbr": 4, "64r": 5, "split": 5}.get(tile_policy,
-                                                                           tile_policy)
-    o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     st = L.GbSp2Stats()
     _check(_lib().gb_density(ctypes.byref(H), int(n_occ), float(threshold), ctypes.byref(o),
                              ctypes.byref(De), ctypes.byref(st), _stream()))

@@ -62,7 +62,35 @@ void dfree(void* p, hipStream_t s, const Allocator& a) {
   else (void)hipFreeAsync(p, s);
 }
 
+size_t workspace_total(const size_t slot[Workspace::kSlots]) {
+  size_t t = 0;
+  for (int i = 0; i < Workspace::kSlots; ++i) t += (slot[i] + 255) / 256 * 256;
+  return t;
+}
+
+void workspace_layout(Workspace& w, void* base, size_t bytes, const size_t slot[Workspace::kSlots]) {
+  const size_t need = workspace_total(slot);
+  if (bytes < need)
+    fail(GB_ESHAPE, "workspace of %zu bytes is smaller than the %zu bytes this call needs", bytes,
+         need);
+  if (reinterpret_cast<uintptr_t>(base) % 256)
+    fail(GB_EINVAL, "workspace must be 256-byte aligned");
+  w.ext = static_cast<char*>(base);
+  size_t off = 0;
+  for (int i = 0; i < Workspace::kSlots; ++i) {
+    w.ext_off[i] = off;
+    w.ext_size[i] = slot[i];
+    off += (slot[i] + 255) / 256 * 256;
+  }
+}
+
 void* Workspace::get_bytes(int slot, size_t bytes, hipStream_t s) {
+  if (ext) {
+    if (bytes > ext_size[slot])
+      fail(GB_ESHAPE, "workspace slot %d needs %zu bytes, its layout holds %zu", slot, bytes,
+           ext_size[slot]);
+    return ext + ext_off[slot];
+  }
   Slab& b = slab[slot];
   if (bytes > b.bytes) {
     if (b.p) dfree(b.p, s, b.a);
@@ -125,7 +153,7 @@ void ws_trim() {
 
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
              double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s,
-             TapeData** tape_out);
+             TapeData** tape_out, Workspace* ext);
 
 void detach(Csr& c) {
   c.row_ptr.detach_stream();
@@ -178,6 +206,13 @@ void check_tau(double t, const char* name) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Bounds given by the caller (both 0: Gershgorin): checked before any device work.
+void check_given_bounds(double emin, double emax) {
+  const bool given = !(emin == 0.0 && emax == 0.0);
+  if (given && !(emax > emin && std::isfinite(emin) && std::isfinite(emax)))
+    fail(GB_EINVAL, "need finite emax > emin (given %g, %g)", emin, emax);
+}
+
 struct EvPair {
   hipEvent_t a = nullptr, b = nullptr;
   EvPair() {
@@ -203,6 +238,9 @@ struct EvPair {
 struct Front {
   double emin = 0, emax = 0;
   DBuf<double> x0;
+  double* x0_ext = nullptr;  // X0 in a caller-owned workspace (then x0 stays empty)
+  const double* x0p() const { return x0_ext ? x0_ext : x0.get(); }
+  EvPair ev_bounds;  // around the bounds and X0 (read after the call's final wait)
   gb_partition_s own;
   const Part* P = nullptr;
   float ms_bounds = 0, ms_graph = 0, ms_part = 0;
@@ -211,24 +249,27 @@ struct Front {
 void prepare_front(const gb_ell& H, double threshold, double emin_in, double emax_in,
                    const gb_partition_t* part, int core_size, hipStream_t s, Front& f) {
   const bool given_bounds = !(emin_in == 0.0 && emax_in == 0.0);
-  if (given_bounds && !(emax_in > emin_in)) fail(GB_EINVAL, "need emax > emin");
+  if (given_bounds && !(emax_in > emin_in && std::isfinite(emin_in) && std::isfinite(emax_in)))
+    fail(GB_EINVAL, "need finite emax > emin");
   if (part && part->part.n != H.n)
     fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", part->part.n, H.n);
   EvPair ev;
-  GB_HIP(hipEventRecord(ev.a, s));
-  f.emin = emin_in;
-  f.emax = emax_in;
-  if (!given_bounds) bounds(H, s, &f.emin, &f.emax);
-  f.x0 = DBuf<double>((size_t)H.n * H.width, s);
-  x0_ell(H, f.emin, f.emax, f.x0.get(), s);
-  GB_HIP(hipEventRecord(ev.b, s));
-  GB_HIP(hipStreamSynchronize(s));
-  f.ms_bounds = ev.ms();
+  GB_HIP(hipEventRecord(f.ev_bounds.a, s));
+  // the Gershgorin pass also rejects an H holding NaN or Inf (given bounds included)
+  double lo = 0, hi = 0;
+  bounds(H, s, &lo, &hi);
+  f.emin = given_bounds ? emin_in : lo;
+  f.emax = given_bounds ? emax_in : hi;
+  if (!(f.emax > f.emin))
+    fail(GB_EINVAL, "H has an empty spectral range (e_min = e_max = %g)", f.emin);
+  if (!f.x0_ext) f.x0 = DBuf<double>((size_t)H.n * H.width, s);
+  x0_ell(H, f.emin, f.emax, const_cast<double*>(f.x0p()), s);
+  GB_HIP(hipEventRecord(f.ev_bounds.b, s));
   f.P = part ? &part->part : nullptr;
   if (!f.P) {
     GB_HIP(hipEventRecord(ev.a, s));
     Csr g;
-    graph_x2(H, f.x0.get(), threshold, g, s);
+    graph_x2(H, f.x0p(), threshold, g, s);
     GB_HIP(hipEventRecord(ev.b, s));
     GB_HIP(hipStreamSynchronize(s));
     f.ms_graph = ev.ms();
@@ -554,8 +595,8 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (o.max_iter < 0 || o.n_refine < 0) fail(GB_EINVAL, "max_iter / n_refine must be >= 0");
     if (o.refine_kind < 0 || o.refine_kind > 2) fail(GB_EINVAL, "unknown refine_kind %d", o.refine_kind);
     if (!(o.idem_tol >= 0.0)) fail(GB_EINVAL, "idem_tol must be >= 0");
-    if (o.branch_in && (o.n_branch_in < 0 || o.n_branch_in > 128))
-      fail(GB_EINVAL, "n_branch_in = %d outside [0, 128]", o.n_branch_in);
+    if (o.branch_in && (o.n_branch_in < 0 || o.n_branch_in > 127))
+      fail(GB_EINVAL, "n_branch_in = %d outside [0, 127]", o.n_branch_in);
     if (o.branch_in)
       for (int i = 0; i < o.n_branch_in; ++i)
         if (o.branch_in[i] > 1) fail(GB_EINVAL, "branch_in[%d] = %d is not 0 or 1", i, o.branch_in[i]);
@@ -563,22 +604,31 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (o.keep_tape && o.precision != GB_FP64)
       fail(GB_EUNSUPPORTED, "keep_tape needs precision GB_FP64");
     if (o.tape_stride < 0) fail(GB_EINVAL, "tape_stride must be >= 0");
-    if (o.launch_mode < 0 || o.launch_mode > 2) fail(GB_EINVAL, "unknown launch_mode %d", o.launch_mode);
+    if (o.launch_mode < 0 || o.launch_mode > 3) fail(GB_EINVAL, "unknown launch_mode %d", o.launch_mode);
+    if (o.check_idem < 0 || o.check_idem > 1) fail(GB_EINVAL, "check_idem must be 0 or 1");
+    if (o.workspace && !o.partition)
+      fail(GB_EINVAL, "a caller-owned workspace needs a partition (its size depends on it)");
     if (o.tile_policy < 0 || o.tile_policy > 5) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
-    if (o.keep_tape && o.launch_mode == 2)
-      fail(GB_EUNSUPPORTED, "keep_tape needs launch_mode 0 or 1");
+    check_given_bounds(o.emin, o.emax);
     const int core_size = o.core_size > 0 ? o.core_size : 32;
     hipStream_t s = as_stream(stream);
     Front f;
+    Workspace ext;
+    if (o.workspace) {
+      if (o.partition->part.n != H->n)
+        fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", o.partition->part.n, H->n);
+      size_t slot[Workspace::kSlots];
+      density_slots(o.partition->part, H->n, H->width, o, slot);
+      workspace_layout(ext, o.workspace, o.workspace_bytes, slot);
+      f.x0_ext = static_cast<double*>(ext.get_bytes(8, slot[8], s));
+    }
     prepare_front(*H, threshold, o.emin, o.emax, o.partition, core_size, s, f);
     const double emin = f.emin, emax = f.emax;
     st.emin = emin;
     st.emax = emax;
-    st.ms_bounds = f.ms_bounds;
     st.ms_graph = f.ms_graph;
     st.ms_part = f.ms_part;
-    const float ms_front = f.ms_bounds + f.ms_graph + f.ms_part;
     const Part* P = f.P;
     st.n_sub = P->n_sub;
     st.max_sub = P->max_sub;
@@ -587,7 +637,8 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
            P->max_sub);
     TapeData* tape = nullptr;
     try {
-      density(*H, n_occ, o, *P, emin, emax, f.x0.get(), *D, st, s, o.keep_tape ? &tape : nullptr);
+      density(*H, n_occ, o, *P, emin, emax, f.x0p(), *D, st, s, o.keep_tape ? &tape : nullptr,
+              o.workspace ? &ext : nullptr);
     } catch (...) {
       tape_destroy(tape);
       throw;
@@ -595,7 +646,26 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (tape) {
       st.tape = new gb_tape_s{tape};
     }
-    st.ms_total += ms_front;
+    st.ms_bounds = f.ev_bounds.ms();  // the call has waited for its stream
+    st.ms_total += st.ms_bounds + f.ms_graph + f.ms_part;
+  });
+}
+
+gb_status gb_density_workspace(const gb_ell* H, const gb_sp2_opts* opts, size_t* bytes) {
+  return guarded([&] {
+    if (!bytes) fail(GB_EINVAL, "bytes is NULL");
+    *bytes = 0;
+    if (!H) fail(GB_EINVAL, "H is NULL");
+    if (H->n <= 0 || H->width <= 0) fail(GB_EINVAL, "H->n and H->width must be positive");
+    if (!opts || !opts->partition)
+      fail(GB_EINVAL, "the workspace size depends on the partition: opts->partition is NULL");
+    if (opts->precision < GB_FP64 || opts->precision > GB_BF16X6_REFINE)
+      fail(GB_EINVAL, "unknown precision %d", opts->precision);
+    if (opts->partition->part.n != H->n)
+      fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", opts->partition->part.n, H->n);
+    size_t slot[Workspace::kSlots];
+    density_slots(opts->partition->part, H->n, H->width, *opts, slot);
+    *bytes = workspace_total(slot);
   });
 }
 
@@ -808,13 +878,13 @@ gb_status gb_foe_density(const gb_ell* H, int32_t n_occ, double threshold, const
     if (o.tile_policy < 0 || o.tile_policy > 5 || o.tile_policy == 3)
       fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
+    check_given_bounds(o.emin, o.emax);
     const int core_size = o.core_size > 0 ? o.core_size : 32;
     hipStream_t s = as_stream(stream);
     Front f;
     prepare_front(*H, threshold, o.emin, o.emax, o.partition, core_size, s, f);
     st.emin = f.emin;
     st.emax = f.emax;
-    st.ms_bounds = f.ms_bounds;
     st.ms_graph = f.ms_graph;
     st.ms_part = f.ms_part;
     st.n_sub = f.P->n_sub;
@@ -823,7 +893,8 @@ gb_status gb_foe_density(const gb_ell* H, int32_t n_occ, double threshold, const
       fail(GB_ESHAPE, "D->width = %d is smaller than the largest subgraph (%d)", D->width,
            f.P->max_sub);
     foe(*H, n_occ, o, *f.P, f.emin, f.emax, *D, st, s);
-    st.ms_total += f.ms_bounds + f.ms_graph + f.ms_part;
+    st.ms_bounds = f.ev_bounds.ms();
+    st.ms_total += st.ms_bounds + f.ms_graph + f.ms_part;
   });
 }
 

@@ -37,28 +37,35 @@ __global__ void k_row_discs(const int32_t* __restrict__ col, const double* __res
   hi[i] = d + r;
 }
 
-// min of lo, max of hi over n rows (exact, order-free); one block.
+// min of lo, max of hi over n rows (exact, order-free); one block.  out[2] counts the rows
+// whose ends are not finite (a NaN or Inf anywhere in the row makes them so; fmin / fmax would
+// silently skip a NaN).
 __global__ void k_minmax(const double* __restrict__ lo, const double* __restrict__ hi, int n,
                          double* __restrict__ out) {
-  __shared__ double smin[kT], smax[kT];
-  double a = INFINITY, b = -INFINITY;
+  __shared__ double smin[kT], smax[kT], sbad[kT];
+  double a = INFINITY, b = -INFINITY, bad = 0.0;
   for (int i = threadIdx.x; i < n; i += kT) {
-    a = fmin(a, lo[i]);
-    b = fmax(b, hi[i]);
+    const double l = lo[i], h = hi[i];
+    if (!isfinite(l) || !isfinite(h)) bad += 1.0;
+    a = fmin(a, l);
+    b = fmax(b, h);
   }
   smin[threadIdx.x] = a;
   smax[threadIdx.x] = b;
+  sbad[threadIdx.x] = bad;
   __syncthreads();
   for (int s = kT / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
       smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      sbad[threadIdx.x] += sbad[threadIdx.x + s];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     out[0] = smin[0];
     out[1] = smax[0];
+    out[2] = sbad[0];
   }
 }
 
@@ -540,15 +547,17 @@ void transpose(int n, const int32_t* rp, const int32_t* c, int64_t nnz, DBuf<int
 
 void bounds(const gb_ell& H, hipStream_t s, double* emin, double* emax) {
   const int n = H.n;
-  DBuf<double> lo(n, s), hi(n, s), out(2, s);
+  DBuf<double> lo(n, s), hi(n, s), out(3, s);
   hipLaunchKernelGGL(k_row_discs, dim3(blocks_for(n, kT)), dim3(kT), 0, s, H.col, H.val, n,
                      H.width, lo.get(), hi.get());
   GB_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_minmax, dim3(1), dim3(kT), 0, s, lo.get(), hi.get(), n, out.get());
   GB_LAUNCH_CHECK();
-  double h[2];
+  double h[3];
   GB_HIP(hipMemcpyAsync(h, out.get(), sizeof(h), hipMemcpyDeviceToHost, s));
   GB_HIP(hipStreamSynchronize(s));
+  if (h[2] != 0.0)
+    fail(GB_EINVAL, "H holds NaN or Inf values (%.0f rows): no spectral bounds", h[2]);
   *emin = h[0];
   *emax = h[1];
 }

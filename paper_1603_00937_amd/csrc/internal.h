@@ -81,8 +81,12 @@ struct Workspace {
     size_t bytes = 0;
     Allocator a;
   };
-  static constexpr int kSlots = 8;
+  static constexpr int kSlots = 9;
   Slab slab[kSlots];
+  // caller-owned memory (gb_sp2_opts.workspace): every slot at a fixed offset of one buffer,
+  // sized by density_slots; a request beyond a slot's size is an error, never an allocation
+  char* ext = nullptr;
+  size_t ext_off[kSlots] = {}, ext_size[kSlots] = {};
   void* get_bytes(int slot, size_t bytes, hipStream_t s);
   template <typename T>
   T* get(int slot, size_t count, hipStream_t s) {
@@ -95,8 +99,12 @@ void ws_release(Workspace* w);
 void ws_trim();
 struct WsLease {
   Workspace* w;
-  WsLease() : w(ws_acquire()) {}
-  ~WsLease() { ws_release(w); }
+  bool own;
+  // ext: a caller-owned workspace (not leased, not returned); nullptr leases a cached one
+  explicit WsLease(Workspace* ext = nullptr) : w(ext ? ext : ws_acquire()), own(ext == nullptr) {}
+  ~WsLease() {
+    if (own) ws_release(w);
+  }
   WsLease(const WsLease&) = delete;
   WsLease& operator=(const WsLease&) = delete;
   Workspace* operator->() const { return w; }
@@ -182,6 +190,14 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
                               MlStats* stats, const Part* prev = nullptr);
 void detach(Csr& c);
 void detach(Part& p);
+
+// Bytes of each workspace slot a gb_density call takes on partition P of an n x width H
+// (sp2.hip); their 256-byte aligned sum is the caller-owned workspace size.
+void density_slots(const Part& P, int n, int width, const gb_sp2_opts& o,
+                   size_t bytes[Workspace::kSlots]);
+// Lays the slots out in a caller buffer of `bytes` bytes (GB_ESHAPE if it is too small).
+void workspace_layout(Workspace& w, void* base, size_t bytes, const size_t slot[Workspace::kSlots]);
+size_t workspace_total(const size_t slot[Workspace::kSlots]);
 
 struct TapeData;  // SP2 checkpoints for the adjoint (sp2.hip)
 void tape_destroy(TapeData* t);

@@ -263,6 +263,19 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
     if (active) {
       const unsigned char* la = lds[buf][0];
       const unsigned char* lb = lds[buf][1];
+      // FP32: the chunk's 32 k-terms go to a fresh partial sum that is added to the running
+      // one once per chunk (blocked summation): an output then passes through n/32 + 8
+      // roundings instead of n/4 accumulating MFMAs, which keeps FP32 squares of blocks of
+      // ~2000 rows well inside the 1e-6 accuracy bar after refinement.  FP64 accumulates
+      // directly.
+      constexpr bool kBlocked = std::is_same<T, float>::value;
+      acc_t part[kBlocked ? MB : 1][kBlocked ? MB : 1];
+      if constexpr (kBlocked) {
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+          for (int n = 0; n < MB; ++n) part[m][n] = acc_t{0, 0, 0, 0};
+      }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int pc = h ? pc1 : pc0;
@@ -277,7 +290,16 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 #pragma unroll
           for (int m = 0; m < MB; ++m)
 #pragma unroll
-            for (int n = 0; n < MB; ++n) acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
+            for (int n = 0; n < MB; ++n) {
+              if constexpr (kBlocked) part[m][n] = M::mma(fa[m][e], fb[n][e], part[m][n]);
+              else acc[m][n] = M::mma(fa[m][e], fb[n][e], acc[m][n]);
+            }
+      }
+      if constexpr (kBlocked) {
+#pragma unroll
+        for (int m = 0; m < MB; ++m)
+#pragma unroll
+          for (int n = 0; n < MB; ++n) acc[m][n] += part[m][n];
       }
     }
     if (LOADER == 1) {
@@ -459,305 +481,6 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
     }
 }
 
-// DB = 1: the LDS holds two chunks (96 KB with three planes, one workgroup per CU) and the
-// next chunk's loads run under the current chunk's products; DB = 0: one chunk (two
-// workgroups per CU), loaded and then consumed; DB = 2: one chunk, staged through registers
-// (ordinary 16-byte global loads of the next chunk issued before the current chunk's products,
-// written to LDS after them) instead of the global-to-LDS path.
-template <int NP, int DB>
-__global__ __launch_bounds__(kT, DB == 1 ? 1 : 2) void k_symm_mm_planes(const __bf16* __restrict__ Xp,
-                                                          int64_t pstride, float* __restrict__ S,
-                                                          __bf16* __restrict__ Sp,
-                                                          const int4* __restrict__ tiles,
-                                                          const int64_t* __restrict__ offs,
-                                                          const int32_t* __restrict__ stopped,
-                                                          const float* __restrict__ X, int lin,
-                                                          const int32_t* __restrict__ lin_flag) {
-  if (stopped && *stopped) return;
-  constexpr int KC = 32;   // k per chunk (one bf16 MFMA): 64-byte rows of four 16-byte pieces
-  constexpr int OPB = kBT * 64;
-  // [plane][operand][rows of 64 B; piece c of row r at slot c ^ ((r >> 2) & 3), so sixteen
-  // lanes reading one piece of sixteen consecutive rows cover all sixteen 16-byte bank groups]
-  __shared__ __align__(1024) unsigned char lds[DB == 1 ? 2 : 1][NP][2][OPB];
-  const int4 tl = tiles[blockIdx.x];
-  if (tl.x < 0) return;
-  const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
-  const int64_t off = offs[s];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  // global -> LDS (global_load_lds_dwordx4, two 1-KB wave windows per plane and operand; the
-  // register-staged variant writes the same 16 bytes per lane to the same place)
-  const __bf16* asrc[2];
-  const __bf16* bsrc[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int slot = (wave * 2 + j) * 64 + lane;
-    const int r = slot >> 2, c = (slot & 3) ^ ((r >> 2) & 3);
-    const int ar = bi * kBT + r, br = bj * kBT + r;
-    asrc[j] = Xp + off + (int64_t)(ar < np ? ar : 0) * np + c * 8;
-    bsrc[j] = Xp + off + (int64_t)(br < np ? br : 0) * np + c * 8;
-  }
-  f4v big[4][4], small[4][4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      big[m][n] = f4v{0, 0, 0, 0};
-      small[m][n] = f4v{0, 0, 0, 0};
-    }
-  const int g = lane >> 4, r16 = lane & 15;
-  const int nk = np / KC;
-  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
-  const bool active = in_range && !(bi == bj && wr > wc);
-  const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
-  const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
-#define GB_FRAG(dst, plane, opnd, base, m) \
-  __builtin_memcpy(&(dst), &lds[buf][plane][opnd][(base) + (m) * 16 * 64 + pc], 16)
-#define GB_ISSUE(b, k0)                                                                       \
-  _Pragma("unroll") for (int p = 0; p < NP; ++p)                                              \
-    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
-      load_lds16(asrc[j] + p * pstride + (k0), &lds[b][p][0][(wave * 2 + j) * 1024]);         \
-      load_lds16(bsrc[j] + p * pstride + (k0), &lds[b][p][1][(wave * 2 + j) * 1024]);         \
-    }
-  // register staging (DB = 2): the first planes of the next chunk are loaded before the
-  // current chunk's products (their registers live across them); the last plane is loaded
-  // after them, which keeps the kernel inside 256 registers
-  constexpr int NPRE = NP > 1 ? NP - 1 : 1;
-  u4v stg[NP][2][2];  // [plane][operand][j]
-#define GB_STAGE(k0, p0, p1)                                                                  \
-  _Pragma("unroll") for (int p = (p0); p < (p1); ++p)                                         \
-    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                           \
-      stg[p][0][j] = *reinterpret_cast<const u4v*>(asrc[j] + p * pstride + (k0));            \
-      stg[p][1][j] = *reinterpret_cast<const u4v*>(bsrc[j] + p * pstride + (k0));            \
-    }
-  if (DB == 1) {
-    GB_ISSUE(0, 0)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-  }
-  if (DB == 2) {
-    GB_STAGE(0, 0, NP)
-  }
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = DB == 1 ? (kc & 1) : 0;
-    if (DB == 1) {
-      if (kc + 1 < nk) {
-        GB_ISSUE(buf ^ 1, (kc + 1) * KC)
-      }
-    } else if (DB == 2) {
-      if (kc > 0 && NPRE < NP) {
-        GB_STAGE(kc * KC, NPRE, NP)
-      }
-      __syncthreads();  // the previous chunk's reads are done
-#pragma unroll
-      for (int p = 0; p < NP; ++p)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int o = 0; o < 2; ++o)
-            *reinterpret_cast<u4v*>(&lds[0][p][o][(wave * 2 + j) * 1024 + lane * 16]) =
-                stg[p][o][j];
-      __syncthreads();
-      if (kc + 1 < nk) {
-        GB_STAGE((kc + 1) * KC, 0, NPRE)
-      }
-    } else {
-      __syncthreads();  // the previous chunk's reads are done
-      GB_ISSUE(0, kc * KC)
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-    }
-    if (active) {
-    bf8v A0[4], B0[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      GB_FRAG(A0[m], 0, 0, pa0, m);
-      GB_FRAG(B0[m], 0, 1, pb0, m);
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-#pragma unroll
-      for (int n = 0; n < 4; ++n)
-        big[m][n] = mma_bf16(A0[m], B0[n], big[m][n]);
-    if (NP >= 2) {
-      // (hi, last plane) and (last plane, hi)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bf8v BL;
-        GB_FRAG(BL, NP - 1, 1, pb0, m);
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          small[r][m] = mma_bf16(A0[r], BL, small[r][m]);
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bf8v AL;
-        GB_FRAG(AL, NP - 1, 0, pa0, m);
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          small[m][n] = mma_bf16(AL, B0[n], small[m][n]);
-      }
-    }
-    if (NP >= 3) {
-      // (hi, mid), (mid, hi), (mid, mid)
-      bf8v BM[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) GB_FRAG(BM[m], 1, 1, pb0, m);
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n)
-          small[m][n] = mma_bf16(A0[m], BM[n], small[m][n]);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bf8v AM;
-        GB_FRAG(AM, 1, 0, pa0, m);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          small[m][n] = mma_bf16(AM, B0[n], small[m][n]);
-          small[m][n] = mma_bf16(AM, BM[n], small[m][n]);
-        }
-      }
-    }
-    }  // active
-    if (DB == 1) {
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();  // chunk kc + 1 has landed and every wave is done with chunk kc
-    }
-  }
-#undef GB_STAGE
-#undef GB_ISSUE
-#undef GB_FRAG
-  if (!active) return;
-  planes_epilogue<NP>(big, small, S, Sp, X, pstride, off, np, bi, bj, wr, wc, lane,
-                      lin_flag ? *lin_flag == 1 : lin != 0);
-}
-
-// Three planes, pipelined within 80 KB of LDS (two workgroups per CU): the hi and mid planes
-// of the next chunk load into a second buffer while the current chunk is consumed; the lo
-// plane has one buffer, so each chunk first forms the two lo products, then (after a barrier)
-// starts the next chunk's lo load and forms the hi/mid products under it.
-__global__ __launch_bounds__(kT, 2) void k_symm_mm_planes3p(const __bf16* __restrict__ Xp,
-                                                           int64_t pstride, float* __restrict__ S,
-                                                           __bf16* __restrict__ Sp,
-                                                           const int4* __restrict__ tiles,
-                                                           const int64_t* __restrict__ offs,
-                                                           const int32_t* __restrict__ stopped,
-                                                           const float* __restrict__ X, int lin,
-                                                           const int32_t* __restrict__ lin_flag) {
-  if (stopped && *stopped) return;
-  constexpr int KC = 32;
-  constexpr int OPB = kBT * 64;
-  __shared__ __align__(1024) unsigned char lhi[2][2][OPB];  // [buffer][operand]
-  __shared__ __align__(1024) unsigned char lmid[2][2][OPB];
-  __shared__ __align__(1024) unsigned char llo[2][OPB];     // [operand]
-  const int4 tl = tiles[blockIdx.x];
-  if (tl.x < 0) return;
-  const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
-  const int64_t off = offs[s];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const __bf16* asrc[2];
-  const __bf16* bsrc[2];
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int slot = (wave * 2 + j) * 64 + lane;
-    const int r = slot >> 2, c = (slot & 3) ^ ((r >> 2) & 3);
-    const int ar = bi * kBT + r, br = bj * kBT + r;
-    asrc[j] = Xp + off + (int64_t)(ar < np ? ar : 0) * np + c * 8;
-    bsrc[j] = Xp + off + (int64_t)(br < np ? br : 0) * np + c * 8;
-  }
-  f4v big[4][4], small[4][4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      big[m][n] = f4v{0, 0, 0, 0};
-      small[m][n] = f4v{0, 0, 0, 0};
-    }
-  const int g = lane >> 4, r16 = lane & 15;
-  const int nk = np / KC;
-  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
-  const bool active = in_range && !(bi == bj && wr > wc);
-  const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
-  const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
-#define GB_LOAD(dst, plane, k0)                                                           \
-  _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                         \
-    load_lds16(asrc[j] + (plane) * pstride + (k0), &(dst)[0][(wave * 2 + j) * 1024]);     \
-    load_lds16(bsrc[j] + (plane) * pstride + (k0), &(dst)[1][(wave * 2 + j) * 1024]);     \
-  }
-#define GB_FRAG(dst, arr, opnd, base, m) \
-  __builtin_memcpy(&(dst), &(arr)[opnd][(base) + (m) * 16 * 64 + pc], 16)
-  GB_LOAD(lhi[0], 0, 0)
-  GB_LOAD(lmid[0], 1, 0)
-  GB_LOAD(llo, 2, 0)
-  for (int kc = 0; kc < nk; ++kc) {
-    const int buf = kc & 1;
-    const int k1 = (kc + 1) * KC;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();  // chunk kc is in LDS; every wave is done with chunk kc - 1
-    if (kc + 1 < nk) {
-      GB_LOAD(lhi[buf ^ 1], 0, k1)
-      GB_LOAD(lmid[buf ^ 1], 1, k1)
-    }
-    bf8v A0[4], B0[4];
-    if (active) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        GB_FRAG(A0[m], lhi[buf], 0, pa0, m);
-        GB_FRAG(B0[m], lhi[buf], 1, pb0, m);
-      }
-      // (hi, lo) and (lo, hi)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bf8v BL;
-        GB_FRAG(BL, llo, 1, pb0, m);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) small[r][m] = mma_bf16(A0[r], BL, small[r][m]);
-      }
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bf8v AL;
-        GB_FRAG(AL, llo, 0, pa0, m);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(AL, B0[n], small[m][n]);
-      }
-    }
-    __syncthreads();  // every wave is done with the lo plane of chunk kc
-    if (kc + 1 < nk) {
-      GB_LOAD(llo, 2, k1)
-    }
-    if (active) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) big[m][n] = mma_bf16(A0[m], B0[n], big[m][n]);
-      bf8v BM[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) GB_FRAG(BM[m], lmid[buf], 1, pb0, m);
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(A0[m], BM[n], small[m][n]);
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        bf8v AM;
-        GB_FRAG(AM, lmid[buf], 0, pa0, m);
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-          small[m][n] = mma_bf16(AM, B0[n], small[m][n]);
-          small[m][n] = mma_bf16(AM, BM[n], small[m][n]);
-        }
-      }
-    }
-  }
-#undef GB_FRAG
-#undef GB_LOAD
-  if (!active) return;
-  planes_epilogue<3>(big, small, S, Sp, X, pstride, off, np, bi, bj, wr, wc, lane,
-                     lin_flag ? *lin_flag == 1 : lin != 0);
-}
-
 // Split in registers: the FP32 iterate itself is read (4 bytes per element instead of 2 NP
 // for stored planes) and each lane splits the 16 bytes it loads into the NP bf16 planes while
 // staging them into the same swizzled LDS layout; the epilogue then writes only the FP32
@@ -890,19 +613,6 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
                              lin_flag ? *lin_flag == 1 : lin != 0);
 }
 
-// planes of an FP32 batch buffer (after the gather)
-template <int NP>
-__global__ void k_make_planes(const float* __restrict__ X, __bf16* __restrict__ Xp, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = i; q < n; q += stride) {
-    __bf16 pl[NP];
-    split_planes<NP>(X[q], pl);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) Xp[p * n + q] = pl[p];
-  }
-}
-
 
 // ---- traces and the branch decision --------------------------------------------------------
 // t1 = sum over subgraphs of the core diagonal of X; t2 = the same for X^2, which for the
@@ -1015,6 +725,12 @@ struct LoopState {
   uint8_t forced[128];
   StepRec recs[128];
 };
+// The loop's parameters, passed by value to the kernel that sets up LoopState.
+struct LoopInit {
+  int32_t it0, max_iter, n_forced, stag;
+  double n_occ, tol;
+  uint8_t forced[128];
+};
 
 __global__ __launch_bounds__(kT) void k_decide_dev(const double* __restrict__ part, int n_sub,
                                                    LoopState* __restrict__ st) {
@@ -1034,7 +750,9 @@ __global__ __launch_bounds__(kT) void k_decide_dev(const double* __restrict__ pa
     q.pad0 = q.pad1 = 0;
     q.b = -1;
     q.stop = 0;
-    if (st->n_forced >= 0) {
+    if (it >= 127) {
+      q.stop = st->n_forced >= 0 ? 1 : 2;  // the records hold 128 steps
+    } else if (st->n_forced >= 0) {
       if (it >= st->n_forced) q.stop = 1;
       else q.b = st->forced[it];
     } else if (e <= st->tol) {
@@ -1592,47 +1310,21 @@ inline Groups one_group(int code, int count) {
   return g;
 }
 
-// the same with split-bf16 squares: planes of X -> new iterate (FP32) and its planes
-template <int NP>
-void launch_planes_np(const __bf16* Xp, const float* X, float* S, __bf16* Sp, int64_t total,
-                      const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s, int db,
-                      int lin, const int32_t* stopped, const int32_t* lin_flag) {
-  if (NP == 3 && db == 2)
-    hipLaunchKernelGGL(k_symm_mm_planes3p, dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp, tiles,
-                       offs, stopped, X, lin, lin_flag);
-  else if (db == 3)
-    hipLaunchKernelGGL((k_symm_mm_planes<NP, 2>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
-                       tiles, offs, stopped, X, lin, lin_flag);
-  else if (db == 5)
-    hipLaunchKernelGGL(k_symm_mm_split<NP>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
-                       stopped, lin, lin_flag);
-  else if (db == 1)
-    hipLaunchKernelGGL((k_symm_mm_planes<NP, 1>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
-                       tiles, offs, stopped, X, lin, lin_flag);
-  else
-    hipLaunchKernelGGL((k_symm_mm_planes<NP, 0>), dim3(ntiles), dim3(kT), 0, s, Xp, total, S, Sp,
-                       tiles, offs, stopped, X, lin, lin_flag);
-  GB_LAUNCH_CHECK();
-}
-
-void launch_square_planes(const __bf16* Xp, const float* X, float* S, __bf16* Sp, int64_t total,
-                          const int4* tiles, int ntiles, const int64_t* offs, hipStream_t s,
-                          int planes, int db, int lin, const int32_t* stopped = nullptr,
-                          const int32_t* lin_flag = nullptr) {
+// the same with split-bf16 squares (FP32 iterate X -> new FP32 iterate S, `planes` bf16 planes
+// formed in the kernel)
+void launch_split(const float* X, float* S, const int4* tiles, int ntiles, const int64_t* offs,
+                  hipStream_t s, int planes, int lin, const int32_t* stopped = nullptr,
+                  const int32_t* lin_flag = nullptr) {
   if (ntiles <= 0) return;
   if (planes == 1)
-    launch_planes_np<1>(Xp, X, S, Sp, total, tiles, ntiles, offs, s, db, lin, stopped, lin_flag);
+    hipLaunchKernelGGL(k_symm_mm_split<1>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
+                       stopped, lin, lin_flag);
   else if (planes == 2)
-    launch_planes_np<2>(Xp, X, S, Sp, total, tiles, ntiles, offs, s, db, lin, stopped, lin_flag);
+    hipLaunchKernelGGL(k_symm_mm_split<2>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
+                       stopped, lin, lin_flag);
   else
-    launch_planes_np<3>(Xp, X, S, Sp, total, tiles, ntiles, offs, s, db, lin, stopped, lin_flag);
-}
-
-void make_planes(const float* X, __bf16* Xp, int64_t total, hipStream_t s, int planes) {
-  const int gr = grid_for(total, kT, 65536);
-  if (planes == 1) hipLaunchKernelGGL(k_make_planes<1>, dim3(gr), dim3(kT), 0, s, X, Xp, total);
-  else if (planes == 2) hipLaunchKernelGGL(k_make_planes<2>, dim3(gr), dim3(kT), 0, s, X, Xp, total);
-  else hipLaunchKernelGGL(k_make_planes<3>, dim3(gr), dim3(kT), 0, s, X, Xp, total);
+    hipLaunchKernelGGL(k_symm_mm_split<3>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
+                       stopped, lin, lin_flag);
   GB_LAUNCH_CHECK();
 }
 
@@ -1750,70 +1442,71 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   st.square_flops_exec = pl.flops_exec;
 }
 
-// Split-bf16 kernel variant: 1 double-buffered LDS (one workgroup per CU), 0 single-buffered
-// (two per CU), 2 pipelined three-plane kernel (two per CU), 3 single-buffered with register
-// staging (two per CU), 5 split in registers from the FP32 iterate (no stored planes).
-// Policy 1 / 2 / 3 / 4 / 5 force 1 / 0 / 2 / 3 / 5;
-// policy 0 times one batched launch with each (one warm-up, one timed) the first time a plane
-// count is seen and keeps the fastest for the life of the process.
-// The variant a policy forces, or the one the tuner already chose for this plane count (-1:
-// not tuned yet).
-int known_planes_variant(int planes, int policy) {
-  if (policy == 1) return 1;
-  if (policy == 2) return 0;
-  if (policy == 3) return planes == 3 ? 2 : 0;
-  if (policy == 4) return 3;
-  if (policy == 5) return 5;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find({20 + planes, 0});
-  return it != g_tune.end() ? it->second : -1;
+// Decisions whose margin | |t2 - n| - |2 t1 - t2 - n| | is within the rounding of the summed
+// traces (64 units in the last place of |t1| + |t2| + n_occ) could go the other way under
+// another summation order; they are counted in the stats.
+inline bool near_tie(const StepRec& r, double n_occ) {
+  return r.margin <= 64.0 * 1.1102230246251565e-16 * (fabs(r.t1) + fabs(r.t2) + fabs(n_occ));
 }
 
-int choose_planes_variant(const Plan& pl, const int4* tiles, const __bf16* Xp, const float* X,
-                          float* S, __bf16* Sp, const int64_t* offs, hipStream_t s, int planes,
-                          int policy) {
-  const int known = known_planes_variant(planes, policy);
-  if (known >= 0) return known;
-  Timer tm;
+// Records of one step into the stats (it < 128).
+inline void record_step(gb_sp2_stats& st, int it, const StepRec& r, bool applied, bool by_rule,
+                        double n_occ) {
+  if (it >= 128) return;
+  st.t1[it] = r.t1;
+  st.t2[it] = r.t2;
+  st.idem = r.e;
+  if (!applied) return;
+  st.branch[it] = (uint8_t)r.b;
+  if (by_rule) {
+    st.min_margin = std::min(st.min_margin, r.margin);
+    if (near_tie(r, n_occ)) ++st.n_near_tie;
+  }
+}
+
+// One squaring launch of a step: the new iterate S = X^2 or 2X - X^2 (lin, or *lin_flag on the
+// device-driven loops), batched over every subgraph or (per_subgraph) one launch per subgraph.
+template <typename T>
+void launch_step(const T* X, T* S, const Plan& pl, const int4* tiles, const int64_t* offs,
+                 hipStream_t s, int planes, int lin, bool per_subgraph,
+                 const int32_t* stopped = nullptr, const int32_t* lin_flag = nullptr) {
   const int nl = (int)pl.launch.size();
-  float best = INFINITY;
-  int choice = 0;
-  for (int db : {5, 3, 2, 1, 0}) {
-    if (db == 2 && planes != 3) continue;
-    launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
-    GB_HIP(hipEventRecord(tm.a, s));
-    launch_square_planes(Xp, X, S, Sp, pl.total, tiles, nl, offs, s, planes, db, 0);
-    GB_HIP(hipEventRecord(tm.b, s));
-    GB_HIP(hipStreamSynchronize(s));
-    const float ms = elapsed(tm.a, tm.b);
-    if (ms < best) {
-      best = ms;
-      choice = db;
+  if constexpr (std::is_same<T, float>::value) {
+    if (planes > 0) {
+      if (per_subgraph)
+        for (const int4& rg : pl.ranges)
+          launch_split(X, S, tiles + nl + rg.x, rg.y, offs, s, planes, lin, stopped, lin_flag);
+      else
+        launch_split(X, S, tiles, nl, offs, s, planes, lin, stopped, lin_flag);
+      return;
     }
   }
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[{20 + planes, 0}] = choice;
-  return choice;
+  if (per_subgraph)
+    for (const int4& rg : pl.ranges)
+      launch_square<T>(X, S, tiles + nl + rg.x, one_group(rg.z, rg.y), offs, s, lin, stopped,
+                       lin_flag);
+  else
+    launch_square<T>(X, S, tiles, pl.lg, offs, s, lin, stopped, lin_flag);
 }
 
-// Runs the SP2 loop in precision T on buffers X (current iterate) and S (scratch).  Each step:
-// core traces of X and X^2 (from X), the FP64 decision, then one squaring launch that writes
-// the next iterate.  Returns the step index at which the stop rule fired, the replay ended,
-// max_iter was reached, or (low precision) the idempotency error stagnated; X then holds the
-// result.  Records every step into stats.
+// Host-driven SP2 loop in precision T on buffers X (current iterate) and S (scratch): each step
+// takes the core traces of X and X^2 (from X), the FP64 decision, reads it back (one host round
+// trip per step), then one squaring launch writes the next iterate.  Used for one launch per
+// subgraph, for the tape of the adjoint and for the alternating FP64 refinement.  Returns the
+// step index at which the stop rule fired, the replay ended, max_iter was reached, or (low
+// precision) the idempotency error stagnated; X then holds the result.
 template <typename T>
 int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
              const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
              const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
              gb_sp2_stats& st, DBuf<StepRec>& recs, hipStream_t s, int* stop_kind,
              TapeData* tape = nullptr, int planes = 0, bool per_subgraph = false,
-             __bf16** Xp = nullptr, __bf16** Sp = nullptr, bool alternate = false) {
+             bool alternate = false) {
   Timer tm;
   PinnedRec pin;
   int it = it0;
   int prev_b = -1;
   std::vector<double> es;
-  const int nl = (int)pl.launch.size();
   DBuf<double> part(2 * (size_t)pl.n_sub, s);
   for (;;) {
     hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, s, X, offs.get(), npad.get(),
@@ -1821,58 +1514,31 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
     int forced = -1;
     if (branch_in) forced = it < n_branch_in ? (int)branch_in[it] : 2;
     else if (alternate && prev_b >= 0) forced = 10 + (1 - prev_b);
-    const int at_max = it >= max_iter ? 1 : 0;
+    const int at_max = it >= max_iter || it >= 127 ? 1 : 0;
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, n_occ, tol, forced,
                        at_max, recs.get());
     GB_LAUNCH_CHECK();
     GB_HIP(hipMemcpyAsync(pin.h, recs.get(), sizeof(StepRec), hipMemcpyDeviceToHost, s));
     GB_HIP(hipStreamSynchronize(s));
     const StepRec r = *pin.h;
-    if (it < 128) {
-      st.t1[it] = r.t1;
-      st.t2[it] = r.t2;
-    }
-    st.idem = r.e;
     es.push_back(r.e);
+    const bool stag = !r.stop && stagnation_stop && es.size() >= 10 &&
+                      es.back() > es[es.size() - 3];
+    record_step(st, it, r, !r.stop && !stag, branch_in == nullptr && !alternate, n_occ);
     if (r.stop) {
       *stop_kind = (r.stop == 1 && (branch_in == nullptr || r.e <= tol)) ? 1 : 2;
       if (branch_in && r.stop == 1) *stop_kind = r.e <= tol ? 1 : 3;
       return it;
     }
-    if (stagnation_stop && es.size() >= 10 && es.back() > es[es.size() - 3]) {
+    if (stag) {
       *stop_kind = 4;
       return it;
     }
-    if (it < 128) st.branch[it] = (uint8_t)r.b;
-    if (branch_in == nullptr && !alternate) st.min_margin = std::min(st.min_margin, r.margin);
     prev_b = r.b;
-    const int lin = r.b == 1 ? 1 : 0;
     GB_HIP(hipEventRecord(tm.a, s));
-    bool launched = false;
-    if constexpr (std::is_same<T, float>::value) {
-      if (planes > 0) {
-        if (per_subgraph)
-          for (const int4& rg : pl.ranges)
-            launch_square_planes(*Xp, X, S, *Sp, pl.total, tiles.get() + nl + rg.x, rg.y,
-                                 offs.get(), s, planes, pl.planes_db, lin);
-        else
-          launch_square_planes(*Xp, X, S, *Sp, pl.total, tiles.get(), nl, offs.get(), s, planes,
-                               pl.planes_db, lin);
-        launched = true;
-      }
-    }
-    if (!launched) {
-      if (per_subgraph) {
-        for (const int4& rg : pl.ranges)
-          launch_square<T>(X, S, tiles.get() + nl + rg.x, one_group(rg.z, rg.y), offs.get(), s,
-                           lin);
-      } else {
-        launch_square<T>(X, S, tiles.get(), pl.lg, offs.get(), s, lin);
-      }
-    }
+    launch_step<T>(X, S, pl, tiles.get(), offs.get(), s, planes, r.b == 1 ? 1 : 0, per_subgraph);
     GB_HIP(hipEventRecord(tm.b, s));
     std::swap(X, S);
-    if (planes > 0) std::swap(*Xp, *Sp);
     ++it;
     if (tape) {
       tape->branch.push_back((uint8_t)r.b);
@@ -1893,33 +1559,80 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
   }
 }
 
+// Events of the device-driven loop (one pair per enqueued step), kept per thread and device for
+// the life of the process.
+std::vector<hipEvent_t>& step_events(size_t need) {
+  thread_local std::map<int, std::vector<hipEvent_t>> pool;
+  int dev = 0;
+  GB_HIP(hipGetDevice(&dev));
+  auto& v = pool[dev];
+  while (v.size() < need) {
+    hipEvent_t e;
+    GB_HIP(hipEventCreate(&e));
+    v.push_back(e);
+  }
+  return v;
+}
 
-// Device-driven loop: two iterations (one per buffer parity: traces, decision, squaring
-// launch reading the decision) captured once in a hipGraph and replayed; the host reads the
-// stop flag every kReplays graph launches.
+__global__ void k_loop_init(LoopState* __restrict__ st, LoopInit in) {
+  st->it = in.it0;
+  st->it0 = in.it0;
+  st->stopped = 0;
+  st->max_iter = in.max_iter;
+  st->n_forced = in.n_forced;
+  st->stag = in.stag;
+  st->cur_b = -1;
+  st->n_occ = in.n_occ;
+  st->tol = in.tol;
+  for (int i = 0; i < 128; ++i) st->forced[i] = in.forced[i];
+}
+
+// Device-driven SP2 loop (launch modes 0 and 2): the stop flag, the step counter, the branch
+// and the step records live on the device, each squaring launch reads the branch there, and
+// every kernel of a step returns at once after the stop, so steps are enqueued without waiting
+// for any decision.  The host enqueues the first kFirst steps (or every step the loop can still
+// take, if fewer), then reads the loop state once; only an expansion longer than that costs one
+// more read per kMore further steps.  Mode 0 enqueues the kernels on the stream (a pair of
+// events around every square gives its duration); mode 2 captures two steps, one per buffer
+// parity, in a hipGraph and replays it.
 template <typename T>
-int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
-                   const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
-                   const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
-                   gb_sp2_stats& st, hipStream_t s, int* stop_kind, int planes,
-                   __bf16** Xp = nullptr, __bf16** Sp = nullptr) {
-  constexpr int kReplays = 4;
-  LoopState h;
-  std::memset(&h, 0, sizeof(h));
-  h.it = it0;
-  h.it0 = it0;
-  h.max_iter = max_iter;
-  h.n_forced = branch_in ? n_branch_in : -1;
-  h.stag = stagnation_stop ? 1 : 0;
-  h.n_occ = n_occ;
-  h.tol = tol;
-  if (branch_in) std::memcpy(h.forced, branch_in, std::min(n_branch_in, 128));
+int sp2_loop_dev(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<int64_t>& offs,
+                 const DBuf<int32_t>& npad, const Part& P, double n_occ, double tol, int max_iter,
+                 const uint8_t* branch_in, int n_branch_in, bool stagnation_stop, int it0,
+                 gb_sp2_stats& st, hipStream_t s, int* stop_kind, int planes, bool graph) {
+  constexpr int kFirst = 32, kMore = 8;
+  // index of the last decision the loop can reach: it stops there at the latest
+  const int last = branch_in ? std::min(n_branch_in, 127) : std::min(max_iter, 127);
+  if (last < it0) fail(GB_EINVAL, "no SP2 step left (first step %d, last %d)", it0, last);
+  const int max_dec = last - it0 + 1;
+  LoopInit in{};
+  in.it0 = it0;
+  in.max_iter = max_iter;
+  in.n_forced = branch_in ? std::min(n_branch_in, 127) : -1;
+  in.stag = stagnation_stop ? 1 : 0;
+  in.n_occ = n_occ;
+  in.tol = tol;
+  if (branch_in) std::memcpy(in.forced, branch_in, std::min(n_branch_in, 128));
   DBuf<LoopState> d(1, s);
   DBuf<double> part(2 * (size_t)pl.n_sub, s);
-  GB_HIP(hipMemcpyAsync(d.get(), &h, sizeof(h), hipMemcpyHostToDevice, s));
-  GB_HIP(hipStreamSynchronize(s));
+  hipLaunchKernelGGL(k_loop_init, dim3(1), dim3(1), 0, s, d.get(), in);
+  GB_LAUNCH_CHECK();
+  const int32_t* stopped = &d.get()->stopped;
+  const int32_t* cur_b = &d.get()->cur_b;
+  auto& ev = step_events(2 * (size_t)max_dec);
+  auto enqueue = [&](hipStream_t q, int k, bool timed) {  // step k of the loop (0-based)
+    T* A = (k & 1) ? S : X;
+    T* B = (k & 1) ? X : S;
+    hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, q, A, offs.get(),
+                       npad.get(), P.core_ptr.get(), part.get(), stopped);
+    hipLaunchKernelGGL(k_decide_dev, dim3(1), dim3(kT), 0, q, part.get(), pl.n_sub, d.get());
+    GB_LAUNCH_CHECK();
+    if (timed) GB_HIP(hipEventRecord(ev[2 * k], q));
+    launch_step<T>(A, B, pl, tiles.get(), offs.get(), q, planes, 0, false, stopped, cur_b);
+    if (timed) GB_HIP(hipEventRecord(ev[2 * k + 1], q));
+  };
   hipStream_t cs = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t gr = nullptr;
   hipGraphExec_t exec = nullptr;
   struct Cleanup {
     hipStream_t& cs;
@@ -1930,66 +1643,51 @@ int sp2_loop_graph(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const 
       if (g) (void)hipGraphDestroy(g);
       if (cs) (void)hipStreamDestroy(cs);
     }
-  } cleanup{cs, graph, exec};
-  GB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-  GB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  const int nl = (int)pl.launch.size();
-  const int32_t* stopped = &d.get()->stopped;
-  const int32_t* cur_b = &d.get()->cur_b;
-  for (int par = 0; par < 2; ++par) {
-    T* A = par ? S : X;
-    T* B = par ? X : S;
-    hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, cs, A, offs.get(), npad.get(),
-                       P.core_ptr.get(), part.get(), stopped);
-    hipLaunchKernelGGL(k_decide_dev, dim3(1), dim3(kT), 0, cs, part.get(), pl.n_sub, d.get());
-    bool launched = false;
-    if constexpr (std::is_same<T, float>::value) {
-      if (planes > 0) {
-        __bf16* Ap = par ? *Sp : *Xp;
-        __bf16* Bp = par ? *Xp : *Sp;
-        launch_square_planes(Ap, A, B, Bp, pl.total, tiles.get(), nl, offs.get(), cs, planes,
-                             pl.planes_db, 0, stopped, cur_b);
-        launched = true;
-      }
-    }
-    if (!launched)
-      launch_square<T>(A, B, tiles.get(), pl.lg, offs.get(), cs, 0, stopped, cur_b);
+  } cleanup{cs, gr, exec};
+  if (graph) {
+    GB_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    GB_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    enqueue(cs, 0, false);
+    enqueue(cs, 1, false);
+    GB_HIP(hipStreamEndCapture(cs, &gr));
+    GB_HIP(hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0));
   }
-  GB_HIP(hipStreamEndCapture(cs, &graph));
-  GB_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  int32_t flag[2] = {0, 0};
-  int launched = 0;
+  LoopState h;
+  int queued = 0;
   for (;;) {
-    for (int r = 0; r < kReplays; ++r) GB_HIP(hipGraphLaunch(exec, s));
-    launched += 2 * kReplays;
-    GB_HIP(hipMemcpyAsync(flag, d.get(), sizeof(flag), hipMemcpyDeviceToHost, s));
-    GB_HIP(hipStreamSynchronize(s));
-    if (flag[1]) break;
-    if (launched > max_iter + 2 * kReplays + 2) fail(GB_EHIP, "device-driven SP2 loop did not stop");
-  }
-  GB_HIP(hipMemcpyAsync(&h, d.get(), sizeof(h), hipMemcpyDeviceToHost, s));
-  GB_HIP(hipStreamSynchronize(s));
-  const int it_stop = h.it;
-  for (int it = it0; it <= it_stop && it < 128; ++it) {
-    const StepRec& r = h.recs[it];
-    st.t1[it] = r.t1;
-    st.t2[it] = r.t2;
-    st.idem = r.e;
-    if (it < it_stop) {
-      st.branch[it] = (uint8_t)r.b;
-      if (!branch_in) st.min_margin = std::min(st.min_margin, r.margin);
+    const int batch = std::min(queued == 0 ? kFirst : kMore, max_dec - queued);
+    if (graph) {
+      const int pairs = (batch + 1) / 2;  // the graph holds two steps
+      for (int r = 0; r < pairs; ++r) GB_HIP(hipGraphLaunch(exec, s));
+      queued += 2 * pairs;
+    } else {
+      for (int k = queued; k < queued + batch; ++k) enqueue(s, k, true);
+      queued += batch;
     }
+    GB_HIP(hipMemcpyAsync(&h, d.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+    GB_HIP(hipStreamSynchronize(s));
+    if (h.stopped) break;
+    if (queued >= max_dec) fail(GB_EHIP, "device-driven SP2 loop did not stop");
   }
-  if (std::is_same<T, float>::value) st.n_square_lo += it_stop - it0;
-  else st.n_square += it_stop - it0;
-  const StepRec& last = h.recs[it_stop];
-  if (last.stop == 1) *stop_kind = (branch_in && last.e > tol) ? 3 : 1;
-  else *stop_kind = last.stop == 4 ? 4 : 2;
-  // it_stop - it0 squares were applied, each moving the iterate to the other buffer
-  if ((it_stop - it0) % 2 == 1) {
-    std::swap(X, S);
-    if (planes > 0) std::swap(*Xp, *Sp);
+  const int it_stop = h.it;
+  for (int it = it0; it <= it_stop && it < 128; ++it)
+    record_step(st, it, h.recs[it], it < it_stop, branch_in == nullptr, n_occ);
+  const int n_sq = it_stop - it0;
+  float ms = 0.f;
+  if (!graph)
+    for (int k = 0; k < n_sq; ++k) ms += elapsed(ev[2 * k], ev[2 * k + 1]);
+  if (std::is_same<T, float>::value) {
+    st.n_square_lo += n_sq;
+    st.ms_square_lo += ms;
+  } else {
+    st.n_square += n_sq;
+    st.ms_square += ms;
   }
+  const StepRec& lr = h.recs[it_stop];
+  if (lr.stop == 1) *stop_kind = (branch_in && lr.e > tol) ? 3 : 1;
+  else *stop_kind = lr.stop == 4 ? 4 : 2;
+  // n_sq squares were applied, each moving the iterate to the other buffer
+  if (n_sq % 2 == 1) std::swap(X, S);
   return it_stop;
 }
 
@@ -2006,28 +1704,35 @@ struct CoreRows {
   int kmax = 0;
   int colblocks = 0;
   int64_t total = 0;  // doubles per slab
-  DBuf<int64_t> soffs;
+  std::vector<int64_t> so;  // slab offset of each subgraph (host)
+  DBuf<int64_t> soffs;      // the same on the device
 };
 
-bool core_rows_plan(const Part& P, const Plan& pl, CoreRows& cr, hipStream_t s) {
+// host part: the slab layout (false when a core exceeds 32 rows: whole blocks instead)
+bool core_rows_sizes(const Part& P, const Plan& pl, CoreRows& cr) {
   int kmax = 0;
   for (int q = 0; q < pl.n_sub; ++q) {
     kmax = std::max(kmax, P.h_core_ptr[q + 1] - P.h_core_ptr[q]);
     if (pl.npad[q] % 64) return false;
   }
   if (kmax > 32) return false;
-  std::vector<int64_t> so(pl.n_sub);
+  cr.so.resize(pl.n_sub);
   int64_t t = 0;
   for (int q = 0; q < pl.n_sub; ++q) {
-    so[q] = t;
+    cr.so[q] = t;
     t += (int64_t)(P.h_core_ptr[q + 1] - P.h_core_ptr[q]) * pl.npad[q];
   }
   cr.kmax = kmax <= 16 ? 16 : 32;
   cr.colblocks = (pl.max_npad + 255) / 256;
   cr.total = std::max<int64_t>(t, 1);
+  return true;
+}
+
+bool core_rows_plan(const Part& P, const Plan& pl, CoreRows& cr, hipStream_t s) {
+  if (!core_rows_sizes(P, pl, cr)) return false;
   cr.soffs = DBuf<int64_t>(pl.n_sub, s);
-  GB_HIP(hipMemcpyAsync(cr.soffs.get(), so.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
-  GB_HIP(hipStreamSynchronize(s));
+  // cr.so lives as long as cr, so the copy needs no wait
+  GB_HIP(hipMemcpyAsync(cr.soffs.get(), cr.so.data(), pl.n_sub * 8, hipMemcpyHostToDevice, s));
   return true;
 }
 
@@ -2062,10 +1767,25 @@ struct RowsCtx {
   }
 };
 
+void density_slots(const Part& P, int n, int width, const gb_sp2_opts& o,
+                   size_t bytes[Workspace::kSlots]) {
+  for (int i = 0; i < Workspace::kSlots; ++i) bytes[i] = 0;
+  const Plan pl = make_plan(P, nullptr, o.tile_order == 0);
+  const size_t t = (size_t)pl.total;
+  bytes[0] = bytes[1] = t * 8;  // FP64 X, S
+  if (o.precision != GB_FP64) {
+    bytes[2] = t * 8;             // FP64 McWeeny product (whole-block refinement)
+    bytes[3] = bytes[4] = t * 4;  // FP32 X, S
+    CoreRows cr;
+    if (core_rows_sizes(P, pl, cr)) bytes[7] = 5 * (size_t)cr.total * 8;  // core-row slabs
+  }
+  bytes[8] = (size_t)n * width * 8;  // X0 on H's pattern
+}
+
 void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P, double emin,
              double emax, const double* x0, gb_ell& D, gb_sp2_stats& st, hipStream_t s,
-             TapeData** tape_out) {
-  Timer t_all, t_stage;
+             TapeData** tape_out, Workspace* ext) {
+  Timer t_all;
   GB_HIP(hipEventRecord(t_all.a, s));
   const bool xcd = o.tile_order == 0;
   Plan pl = make_plan(P, nullptr, xcd);
@@ -2085,15 +1805,20 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   const int planes = o.precision == GB_BF16_REFINE ? 1 : o.precision == GB_BF16X3_REFINE ? 2
                    : o.precision == GB_BF16X6_REFINE ? 3 : 0;
   const int n_refine = o.n_refine;
+  // launch modes 0 (default) and 2 run the loop on the device; 1 (one launch per subgraph) and
+  // 3 read every decision back on the host
+  const bool dev_loop = o.launch_mode == 0 || o.launch_mode == 2;
   int stop_kind = 0;
+  // stage timings: events read once the call has finished its work (no wait per stage)
+  Timer t_gather, t_sp2, t_ref, t_scat;
   // the gather is timed with the first buffer allocation included
-  GB_HIP(hipEventRecord(t_stage.a, s));
+  GB_HIP(hipEventRecord(t_gather.a, s));
   const size_t lds_g = (size_t)pl.max_npad * 8 + (size_t)P.max_sub * 4 + 64;
   if (lds_g > 160 * 1024) fail(GB_EUNSUPPORTED, "subgraph of %d vertices too large", P.max_sub);
   const dim3 ggrid(pl.n_sub, (pl.max_npad + kRows - 1) / kRows);
-  // batch buffers from the cached workspace: slots 0-2 FP64 (X, S, McWeeny T), 3-4 FP32,
-  // 5-6 the bf16 planes of X and S
-  WsLease ws;
+  // batch buffers from the cached workspace or the caller's: slots 0-2 FP64 (X, S, McWeeny
+  // T), 3-4 FP32, 7 the core-row slabs
+  WsLease ws(ext);
   double* const X64 = ws->get<double>(0, pl.total, s);
   double* const S64 = ws->get<double>(1, pl.total, s);
   double* xd = X64;
@@ -2114,16 +1839,19 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
                          npad.get(), xf);
     }
     GB_LAUNCH_CHECK();
-    GB_HIP(hipEventRecord(t_stage.b, s));
-    GB_HIP(hipStreamSynchronize(s));
-    st.ms_gather = elapsed(t_stage.a, t_stage.b);
-    GB_HIP(hipEventRecord(t_stage.a, s));
+    GB_HIP(hipEventRecord(t_gather.b, s));
+    GB_HIP(hipEventRecord(t_sp2.a, s));
     if (nhi > 0) {
       // the first steps, where the spectral gap of X is smallest and rounding errors are
       // amplified most, in FP64
-      it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, nhi, o.branch_in,
-                                o.n_branch_in, false, 0, st, recs, s, &stop_kind, nullptr, 0,
-                                o.launch_mode == 1);
+      if (dev_loop)
+        it_end = sp2_loop_dev<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, nhi,
+                                      o.branch_in, o.n_branch_in, false, 0, st, s, &stop_kind, 0,
+                                      o.launch_mode == 2);
+      else
+        it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, nhi, o.branch_in,
+                                  o.n_branch_in, false, 0, st, recs, s, &stop_kind, nullptr, 0,
+                                  o.launch_mode == 1);
       done = stop_kind == 1 || stop_kind == 3;
       if (!done) {
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(pl.total, kT, 65536)),
@@ -2133,35 +1861,19 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     }
     if (!done) {
       if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
-      // split-bf16: the stored planes of X and S (NP bf16 arrays of the batch size each) are
-      // needed only by the variants that read planes (and by the first tuning)
-      __bf16* xp = nullptr;
-      __bf16* sp = nullptr;
-      if (planes > 0) {
-        const int known = known_planes_variant(planes, o.tile_policy);
-        if (known != 5) {
-          xp = ws->get<__bf16>(5, (size_t)planes * pl.total, s);
-          sp = ws->get<__bf16>(6, (size_t)planes * pl.total, s);
-          make_planes(xf, xp, pl.total, s, planes);
-        }
-        pl.planes_db = known >= 0 ? known
-                                  : choose_planes_variant(pl, tiles.get(), xp, xf, sf, sp,
-                                                          offs.get(), s, planes, o.tile_policy);
-        st.planes_db = pl.planes_db;
-        if (pl.planes_db != 5 && !xp) fail(GB_EHIP, "plane buffers missing");
-      }
+      else st.planes_db = 5;
       // The low-precision loop runs until its own rounding floor (the stagnation stop) unless
       // the traces already agree to 1e-7 per 1024 orbitals, so that one FP64 McWeeny step
       // usually finishes the job.
       const double tol_lo = 1e-7 * N / 1024.0;
-      if (o.launch_mode == 2)
-        it_end = sp2_loop_graph<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
-                                       o.branch_in, o.n_branch_in, true, it_end, st, s, &stop_kind,
-                                       planes, &xp, &sp);
+      if (dev_loop)
+        it_end = sp2_loop_dev<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
+                                     o.branch_in, o.n_branch_in, true, it_end, st, s, &stop_kind,
+                                     planes, o.launch_mode == 2);
       else
         it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
                                  o.branch_in, o.n_branch_in, true, it_end, st, recs, s, &stop_kind,
-                                 nullptr, planes, o.launch_mode == 1, &xp, &sp);
+                                 nullptr, planes, o.launch_mode == 1);
       // the final low-precision square was only the stop test: continue from X in FP64, made
       // exactly symmetric (every block is padded to a multiple of 64)
       const int max_nt = pl.max_npad / 64;
@@ -2169,9 +1881,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
                          offs.get(), npad.get());
       GB_LAUNCH_CHECK();
     }
-    GB_HIP(hipEventRecord(t_stage.b, s));
-    GB_HIP(hipStreamSynchronize(s));
-    st.ms_sp2 = elapsed(t_stage.a, t_stage.b);
+    GB_HIP(hipEventRecord(t_sp2.b, s));
   } else {
     hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
                        P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
@@ -2208,9 +1918,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       t->ckpt.push_back(std::move(c));
       GB_HIP(hipStreamSynchronize(s));  // host plan vectors above are copied before return
     }
-    GB_HIP(hipEventRecord(t_stage.b, s));
-    GB_HIP(hipStreamSynchronize(s));
-    st.ms_gather = elapsed(t_stage.a, t_stage.b);
+    GB_HIP(hipEventRecord(t_gather.b, s));
   }
 
   if (!low && !tape_out) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
@@ -2220,7 +1928,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   CoreRows cr;
   const double* rows_final = nullptr;  // core-row refinement: the core rows of D and of D^2
   const double* rows_check = nullptr;
-  GB_HIP(hipEventRecord(t_stage.a, s));
+  Timer& t_loop = low ? t_ref : t_sp2;
+  GB_HIP(hipEventRecord(t_loop.a, s));
   if (low && done) {
     // converged during the FP64 steps: nothing to refine
   } else if (low && (o.refine_kind == 0 || o.refine_kind == 2)) {
@@ -2272,9 +1981,10 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
         GB_HIP(hipMemcpyAsync(&r2, recs.get(), sizeof(r2), hipMemcpyDeviceToHost, s));
         GB_HIP(hipStreamSynchronize(s));
         if (r2.e <= tol) {
-          // the check's square: Z = Y P(X) (P = p or p o p), the core rows of D^2
-          rc.apply_p(xd, y, s1, t0, t1);
-          if (m == 2) {
+          // the check's square: Z = Y P(X) (P = p or p o p), the core rows of D^2 (nine more
+          // slab products; only when the max-norm check is asked for)
+          if (o.check_idem) rc.apply_p(xd, y, s1, t0, t1);
+          if (o.check_idem && m == 2) {
             rc.apply_p(xd, s1, s2, t0, t1);
             rc.mm(xd, s2, t0);
             rc.mm(xd, t0, t1);
@@ -2339,56 +2049,62 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     const int cap = std::min(it_end + (n_refine > 0 ? n_refine : 16), 127);
     it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, cap, bin, nbin, false,
                               it_end, st, recs, s, &stop_kind, nullptr, 0, o.launch_mode == 1,
-                              nullptr, nullptr, bin == nullptr);
+                              bin == nullptr);
   } else {
-    if (o.launch_mode == 2)
-      it_end = sp2_loop_graph<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter,
-                                      o.branch_in, o.n_branch_in, false, 0, st, s, &stop_kind, 0);
+    if (dev_loop && !tape_out)
+      it_end = sp2_loop_dev<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter,
+                                    o.branch_in, o.n_branch_in, false, 0, st, s, &stop_kind, 0,
+                                    o.launch_mode == 2);
     else
       it_end = sp2_loop<double>(xd, sd, pl, tiles, offs, npad, P, n_occ, tol, max_iter,
                                 o.branch_in, o.n_branch_in, false, 0, st, recs, s, &stop_kind,
                                 tape_out ? *tape_out : nullptr, 0, o.launch_mode == 1);
     if (tape_out) (*tape_out)->K = it_end;
   }
-  GB_HIP(hipEventRecord(t_stage.b, s));
-  GB_HIP(hipStreamSynchronize(s));
-  if (low) st.ms_refine = elapsed(t_stage.a, t_stage.b);
-  else st.ms_sp2 = elapsed(t_stage.a, t_stage.b);
+  GB_HIP(hipEventRecord(t_loop.b, s));
   st.iters = it_end;
   st.converged = stop_kind == 1 ? 1 : 0;
 
   // final idempotency check on the core rows: X^2 restricted to the tiles that hold them (all
   // upper tiles in tile rows below the core size), then max |X^2 - X| over the core rows
   // (after the core-row refinement the core rows of X and X^2 are already there)
+  // (only with check_idem: the trace-based FP64 stop test above is the default check)
   const double* xfin = rows_final ? rows_final : xd;
   const int64_t* foffs = rows_final ? cr.soffs.get() : offs.get();
-  if (!rows_final) {
-    DBuf<int4> idem_tiles(std::max<size_t>(pl.idem.size(), 1), s);
-    GB_HIP(hipMemcpyAsync(idem_tiles.get(), pl.idem.data(), pl.idem.size() * sizeof(int4),
-                          hipMemcpyHostToDevice, s));
-    launch_square<double>(xd, sd, idem_tiles.get(), one_group(128, (int)pl.idem.size()),
-                          offs.get(), s);
-    GB_HIP(hipStreamSynchronize(s));  // idem_tiles is freed at the end of this scope
+  DBuf<int4> idem_tiles;
+  DBuf<double> per, mx;
+  if (o.check_idem) {
+    if (!rows_final) {
+      idem_tiles = DBuf<int4>(std::max<size_t>(pl.idem.size(), 1), s);
+      GB_HIP(hipMemcpyAsync(idem_tiles.get(), pl.idem.data(), pl.idem.size() * sizeof(int4),
+                            hipMemcpyHostToDevice, s));
+      launch_square<double>(xd, sd, idem_tiles.get(), one_group(128, (int)pl.idem.size()),
+                            offs.get(), s);
+    }
+    const double* sfin = rows_final ? rows_check : sd;
+    per = DBuf<double>(pl.n_sub, s);
+    mx = DBuf<double>(1, s);
+    hipLaunchKernelGGL(k_idem<double>, dim3(pl.n_sub), dim3(kT), 0, s, xfin, sfin, foffs,
+                       npad.get(), P.core_ptr.get(), P.sub_ptr.get(), per.get());
+    GB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_max, dim3(1), dim3(kT), 0, s, per.get(), pl.n_sub, mx.get());
+    GB_LAUNCH_CHECK();
   }
-  const double* sfin = rows_final ? rows_check : sd;
-  DBuf<double> per(pl.n_sub, s), mx(1, s);
-  hipLaunchKernelGGL(k_idem<double>, dim3(pl.n_sub), dim3(kT), 0, s, xfin, sfin, foffs,
-                     npad.get(), P.core_ptr.get(), P.sub_ptr.get(), per.get());
-  GB_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_max, dim3(1), dim3(kT), 0, s, per.get(), pl.n_sub, mx.get());
-  GB_LAUNCH_CHECK();
   // scatter
-  GB_HIP(hipEventRecord(t_stage.a, s));
+  GB_HIP(hipEventRecord(t_scat.a, s));
   hipLaunchKernelGGL(k_scatter<double>, dim3(N), dim3(kT), 0, s, xfin, foffs, npad.get(),
                      P.sub_ptr.get(), P.sub_idx.get(), P.sub_pos.get(), P.col_sub.get(),
                      P.col_loc.get(), D.width, D.col, D.val);
   GB_LAUNCH_CHECK();
-  GB_HIP(hipEventRecord(t_stage.b, s));
-  double idem_max = 0;
-  GB_HIP(hipMemcpyAsync(&idem_max, mx.get(), 8, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipEventRecord(t_scat.b, s));
+  double idem_max = NAN;
+  if (o.check_idem) GB_HIP(hipMemcpyAsync(&idem_max, mx.get(), 8, hipMemcpyDeviceToHost, s));
   GB_HIP(hipEventRecord(t_all.b, s));
   GB_HIP(hipStreamSynchronize(s));
-  st.ms_scatter = elapsed(t_stage.a, t_stage.b);
+  st.ms_gather = elapsed(t_gather.a, t_gather.b);
+  st.ms_sp2 = elapsed(t_sp2.a, t_sp2.b);
+  if (low) st.ms_refine = elapsed(t_ref.a, t_ref.b);
+  st.ms_scatter = elapsed(t_scat.a, t_scat.b);
   st.idem_max = idem_max;
   const int last = std::min(it_end, 127);
   st.trace = st.t1[last];

@@ -81,6 +81,38 @@ def test_density_rejects_bad_arguments(lib):
     o.emin, o.emax = 2.0, 1.0
     assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
                           None) == GB_EINVAL
+    # the step records hold 128 traces: a replay of 128 updates would overrun them
+    o = GbSp2Opts()
+    seq = (ctypes.c_uint8 * 128)(*([0] * 128))
+    o.branch_in = ctypes.cast(seq, ctypes.c_void_p)
+    o.n_branch_in = 128
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                          None) == GB_EINVAL
+    assert "n_branch_in" in _err(lib)
+    for field, value in (("launch_mode", 4), ("check_idem", 2), ("launch_mode", -1)):
+        o = GbSp2Opts()
+        setattr(o, field, value)
+        assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                              None) == GB_EINVAL, field
+    # a caller-owned workspace is laid out for a partition: none given
+    o = GbSp2Opts()
+    o.workspace = bogus
+    o.workspace_bytes = 1 << 20
+    assert lib.gb_density(ctypes.byref(H), 4, 1e-5, ctypes.byref(o), ctypes.byref(D), None,
+                          None) == GB_EINVAL
+    assert "partition" in _err(lib)
+
+
+def test_workspace_query_rejects_bad_arguments(lib):
+    from paper_1603_00937_amd._lib import GbEll, GbSp2Opts, GB_EINVAL
+    H = GbEll(8, 3, 0x1000, 0x1000)
+    nb = ctypes.c_size_t(123)
+    assert lib.gb_density_workspace(ctypes.byref(H), None, ctypes.byref(nb)) == GB_EINVAL
+    assert nb.value == 0 and "partition" in _err(lib)
+    o = GbSp2Opts()
+    assert lib.gb_density_workspace(ctypes.byref(H), ctypes.byref(o), ctypes.byref(nb)) == GB_EINVAL
+    assert lib.gb_density_workspace(None, ctypes.byref(o), ctypes.byref(nb)) == GB_EINVAL
+    assert lib.gb_density_workspace(ctypes.byref(H), ctypes.byref(o), None) == GB_EINVAL
 
 
 def test_graph_and_partition_reject_bad_arguments(lib):

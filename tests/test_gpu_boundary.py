@@ -1,0 +1,81 @@
+"""The C-ABI boundary on the GPU: non-finite input is rejected, a caller-owned workspace gives
+the same D as the library's cached buffers, and the max-norm idempotency check is optional."""
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gb():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1603_00937_amd as gb
+    return gb
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf")])
+def test_non_finite_h_is_rejected(gb, model_cache, bad):
+    from paper_1603_00937_amd._lib import GB_EINVAL
+    m = model_cache("small256")
+    hv = m["H_val"].copy()
+    # an off-diagonal entry (slot 1 of row 7) and, separately, a diagonal one
+    for r, t in ((7, 1), (11, int(np.nonzero(m["H_col"][11] == 11)[0][0]))):
+        h = hv.copy()
+        h[r, t] = bad
+        Hc, Hv = _dev(m["H_col"]), _dev(h)
+        for call in (lambda: gb.spectral_bounds(Hc, Hv),
+                     lambda: gb.build_graph(Hc, Hv, 1e-5),
+                     lambda: gb.density(Hc, Hv, m["n_occ"], 1e-5, core_size=16),
+                     lambda: gb.density(Hc, Hv, m["n_occ"], 1e-5, core_size=16, emin=-5.0,
+                                        emax=5.0)):
+            with pytest.raises(gb.GbError) as e:
+                call()
+            assert e.value.status == GB_EINVAL and "NaN or Inf" in str(e.value)
+    # the library still works afterwards
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(hv), m["n_occ"], 1e-5, core_size=16)
+    assert st["converged"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6", "fp32"])
+def test_caller_workspace_matches_cached_buffers(gb, model_cache, precision):
+    import torch
+    from paper_1603_00937_amd._lib import GB_ESHAPE
+    m = model_cache("n1024")
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+    p = gb.partition(gb.build_graph(Hc, Hv, 1e-5), 16)
+    nb = gb.density_workspace(Hc, p, precision=precision)
+    total = sum(npad * npad for npad in
+                ((np.diff(p.arrays()[1].cpu().numpy()) + 63) // 64 * 64).tolist())
+    assert nb >= 2 * 8 * total and nb % 256 == 0
+    ref = gb.density(Hc, Hv, m["n_occ"], 1e-5, partition=p, precision=precision)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    for _ in range(2):  # the same workspace twice in a row
+        out = gb.density(Hc, Hv, m["n_occ"], 1e-5, partition=p, precision=precision,
+                         workspace=ws)
+        assert out[2]["branch"] == ref[2]["branch"] and out[2]["iters"] == ref[2]["iters"]
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+    with pytest.raises(gb.GbError) as e:
+        gb.density(Hc, Hv, m["n_occ"], 1e-5, partition=p, precision=precision,
+                   workspace=ws[:nb - 256])
+    assert e.value.status == GB_ESHAPE
+
+
+def test_idempotency_check_is_optional(gb, model_cache):
+    m = model_cache("small256")
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+    for precision in ("fp64", "bf16x6"):
+        a = gb.density(Hc, Hv, m["n_occ"], 1e-5, core_size=16, precision=precision)
+        b = gb.density(Hc, Hv, m["n_occ"], 1e-5, core_size=16, precision=precision,
+                       check_idem=True)
+        assert math.isnan(a[2]["idem_max"]) and b[2]["idem_max"] < 1e-8
+        assert a[2]["branch"] == b[2]["branch"]
+        assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+        assert a[2]["n_near_tie"] == 0

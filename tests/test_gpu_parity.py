@@ -168,52 +168,67 @@ def test_diagonal_hamiltonian(gb):
         assert np.abs(np.delete(dv[i, :len(rows)], i - c0)).max() < 1e-14
 
 
+LAUNCH_MODES = ("device", "per_subgraph", "graph", "host")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6"])
 def test_launch_modes_agree(gb, model_cache, precision):
-    """Batched launch, one launch per subgraph, and the device-driven hipGraph loop run the
-    same kernels on the same data: results agree bit for bit."""
+    """The device-driven loop (default), one launch per subgraph, the hipGraph replay and the
+    host-driven loop run the same kernels on the same data: results agree bit for bit."""
     m = model_cache("small256")
     outs = {}
-    for mode in ("batched", "per_subgraph", "graph"):
+    for mode in LAUNCH_MODES:
         D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
                                       core_size=16, precision=precision, launch_mode=mode)
         outs[mode] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"], st["iters"])
-    ref = outs["batched"]
-    for mode in ("per_subgraph", "graph"):
+    ref = outs["device"]
+    for mode in LAUNCH_MODES[1:]:
         o = outs[mode]
         assert o[2] == ref[2] and o[3] == ref[3], mode
         assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), mode
 
 
-@pytest.mark.parametrize("name,core", [("small256", 16), ("n1024", 16)])
-def test_split_bf16_kernel_variants_agree(gb, model_cache, name, core):
-    """The split-bf16 kernels (single- and double-buffered, pipelined, register-staged) accumulate
-    the same products in the same order: bit-identical results, in every launch mode."""
-    m = model_cache(name)
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
+def test_launch_modes_agree_n1024(gb, model_cache, precision):
+    """The same at N = 1024 (blocks of up to 1024 rows, several tiles per edge and a ragged
+    last tile), where the device-driven loops run past their first batch only if the
+    expansion is long."""
+    m = model_cache("n1024")
     outs = {}
-    for pol in ("sb", "db", "pipe", "sbr", "split"):
-        for mode in ("batched", "graph"):
-            D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
-                                          core_size=core, precision="bf16x6", tile_policy=pol,
-                                          launch_mode=mode)
-            outs[(pol, mode)] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"],
-                                 st["planes_db"])
-    ref = outs[("sb", "batched")]
-    assert ref[3] == 0 and outs[("db", "batched")][3] == 1 and outs[("pipe", "batched")][3] == 2
-    assert outs[("sbr", "batched")][3] == 3 and outs[("split", "batched")][3] == 5
-    for key, o in outs.items():
-        assert o[2] == ref[2], key
-        assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), key
+    for mode in ("device", "graph", "host"):
+        D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      core_size=16, precision=precision, launch_mode=mode)
+        outs[mode] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"], st["n_square"],
+                      st["n_square_lo"])
+        print(mode, st["iters"], st["ms"]["sp2"], st["ms"]["total"])
+    ref = outs["device"]
+    for mode in ("graph", "host"):
+        o = outs[mode]
+        assert o[2] == ref[2] and o[3:] == ref[3:], mode
+        assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), mode
 
 
-def test_graph_mode_replay_and_max_iter(gb, model_cache):
+@pytest.mark.parametrize("mode", ["device", "graph", "host"])
+def test_replay_and_max_iter(gb, model_cache, mode):
     m = model_cache("small256")
     D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
-                                  core_size=16, launch_mode="graph", max_iter=5)
+                                  core_size=16, launch_mode=mode, max_iter=5)
     assert st["iters"] == 5 and not st["converged"]
     D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
-                                  core_size=16, launch_mode="graph", branch_in=[1, 0, 1])
+                                  core_size=16, launch_mode=mode, branch_in=[1, 0, 1])
     assert st["iters"] == 3 and st["branch"] == [1, 0, 1]
+
+
+@pytest.mark.parametrize("mode", ["device", "graph", "host"])
+def test_replay_of_127_steps(gb, model_cache, mode):
+    """The longest replay the records hold (127 updates, 128 trace pairs), past the default
+    max_iter: every step is applied and recorded, in every launch mode."""
+    m = model_cache("small256")
+    seq = [i % 2 for i in range(127)]
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, launch_mode=mode, branch_in=seq)
+    assert st["iters"] == 127 and st["branch"] == seq
+    assert len(st["t1"]) == 128 and np.isfinite(st["t1"]).all()
 
 
 @pytest.mark.parametrize("precision,refine", [("fp64", "sp2"), ("fp32", "sp2")])
