@@ -20,9 +20,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "orbitals/s of D at ≤1e-6 err vs FP64 oracle; mixed vs FP64 GPU; X² MFMA util"
 # dense matrix-core peaks of the precision the dominant squaring kernel runs in (TFLOP/s)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "bf16x6": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "bf16x6": 2500.0,
+               "fp16x3": 2500.0}
 # bf16 plane products per algorithmic multiply-add
-PLANE_PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6}
+PLANE_PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
 # default cores per workload: the faster of the two partitions as measured on one MI355X
 # (multilevel communities pay for their host partitioner at N = 18000, not at N = 1024, where it
 # takes a third of the step, nor at N = 100000, where it takes 0.3 s)
@@ -55,9 +56,9 @@ def measured_traffic(workload, kernel, partition):
 
 def square_kernel_name(precision, stats):
     """The rocprof name of the loop's squaring kernel for this run."""
-    if precision.startswith("bf16"):
-        planes = {"bf16": 1, "bf16x3": 2, "bf16x6": 3}[precision]
-        return f"k_symm_mm_split<{planes}>"
+    if precision.startswith("bf16") or precision == "fp16x3":
+        planes = {"bf16": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 2}[precision]
+        return f"k_symm_mm_split<{planes}, {'true' if precision == 'fp16x3' else 'false'}>"
     t = "double" if precision == "fp64" else "float"
     if stats.get("n_stage3", 0) == stats["n_sub"]:
         return f"k_symm_mm<{t}, 0, 64, 3, 0>"
@@ -459,7 +460,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x6",
-                    choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6"])
+                    choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6", "fp16x3"])
     ap.add_argument("--launch-mode", default="device",
                     choices=["device", "per_subgraph", "graph", "host"])
     ap.add_argument("--copy-calibration", action="store_true")
@@ -550,6 +551,14 @@ def main():
         dcf, dvf = D[0].cpu().numpy(), D[1].cpu().numpy()
         out["fp64_gpu"] = {k: ref[k] for k in ("value", "ms_per_step", "roofline", "accuracy")}
         out["speedup_vs_fp64_gpu"] = out["value"] / ref["value"]
+    # the two-plane fp16 split (three products) beside the headline split-bf16 run
+    ext = None
+    if args.precision == "bf16x6" and not args.no_fp64_compare:
+        ext = measure(gb, torch, args, "fp16x3", model, cfg, Hc, Hv, D, golden, sizes)
+        dce, dve = D[0].cpu().numpy(), D[1].cpu().numpy()
+        out["fp16x3_gpu"] = {k: ext[k] for k in ("value", "ms_per_step", "dtype", "roofline",
+                                                   "accuracy")}
+        out["fp16x3_gpu"]["speedup_vs_fp64_gpu"] = ext["value"] / out["fp64_gpu"]["value"]
     ref_cols = None
     if golden and not args.no_cpu_baseline:
         out["cpu_baseline"], ref_cols = cpu_baseline(model, args.workload, golden,
@@ -569,6 +578,15 @@ def main():
         if dcf is not None:
             out["fp64_gpu"]["accuracy"]["vs_oracle_subgraphs"] = d_errors(dcf, dvf, ref_cols)
             out["fp64_gpu"]["accuracy"]["idempotency_D"] = idempotency(dcf, dvf, idem_cols)
+    if ext is not None:
+        ea = out["fp16x3_gpu"]["accuracy"]
+        if ref_cols is not None:
+            ea["vs_oracle_subgraphs"] = d_errors(dce, dve, ref_cols)
+        d = dve - dvf
+        ea["vs_fp64_gpu_whole_D"] = {"pattern_equal": bool(np.array_equal(dce, dcf)),
+                                     "max_abs": float(np.abs(d).max()),
+                                     "frobenius": float(np.linalg.norm(d))}
+        del dce, dve
     if dcf is not None:
         same = bool(np.array_equal(dcm, dcf))
         d = dvm - dvf
@@ -635,7 +653,8 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
         "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32+f64"}.get(precision, "bf16+f64"),
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "fp16x3": "f16+f64"}.get(precision,
+                                                                               "bf16+f64"),
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: seeded 3D tight-binding model, N={N} orbitals, "
                                f"n_occ={n_occ}, tau={cfg['tau']}, cores of {cfg['core']}"

@@ -214,7 +214,8 @@ typedef enum {
   GB_FP32_REFINE = 1,   /* squares on FP32 MFMA (FP32 accumulate), then FP64 refinement      */
   GB_BF16_REFINE = 2,   /* squares on BF16 MFMA from one bf16 plane (FP32 accumulate)        */
   GB_BF16X3_REFINE = 3, /* two bf16 planes hi + lo, three products (about 16 bits)           */
-  GB_BF16X6_REFINE = 4  /* three bf16 planes, six products (about FP32 precision)            */
+  GB_BF16X6_REFINE = 4, /* three bf16 planes, six products (about FP32 precision)            */
+  GB_FP16X3_REFINE = 5  /* two fp16 planes of 2^14 X (hi, lo), three products (about 22 bits) */
 } gb_precision;
 
 typedef struct {
@@ -254,7 +255,8 @@ typedef struct {
                               * size bucket (0, timed once per process), 1 = 128-edge tiles,  *
                               * 2 = 64-edge, 4 = 64-edge with three LDS stages, 5 = 64-edge   *
                               * with register-staged loads;                                   *
-                              * split-bf16 squares ignore it (one kernel).  3 is taken as 0. */
+                              * split squares (bf16, fp16 planes) have one kernel and ignore *
+                              * it.  3 is taken as 0.                                         */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
   int32_t check_idem;        /* 1: also compute stats.idem_max, max |X^2 - X| over the core   *
                               *    columns (one more square of the core tiles, or nine slab  *
@@ -284,8 +286,7 @@ typedef struct {
   int32_t n_square_lo;
   int32_t n_tile64;          /* subgraphs squared with 64-edge tiles                         */
   int32_t n_refine_done;     /* McWeeny steps applied                                        */
-  int32_t planes_db;         /* split-bf16 loops: kernel variant (0 single-, 1 double-buffered, *
-                              * 2 pipelined, 3 register-staged, 5 split in registers)          */
+  int32_t planes_db;         /* split loops: 1-3 bf16 planes, 4 = two fp16 planes; 0 otherwise */
   int32_t n_stage3;          /* subgraphs squared with the three-stage 64-edge kernel         */
   int32_t n_regstage;        /* subgraphs squared with the register-staged 64-edge kernel     */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */

@@ -10,7 +10,7 @@ STATUS_NAMES = {0: "GB_OK", -1: "GB_EINVAL", -2: "GB_ENOMEM", -3: "GB_EHIP", -4:
                 -5: "GB_EUNSUPPORTED"}
 GRAPH_MODES = {"x2": 0, "pattern": 1, "dprev": 2, "dprev_symbolic": 3}
 PART_METHODS = {"block": 0, "bfs": 1, "multilevel": 2}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "bf16x6": 4, "fp16x3": 5}
 # launch modes of gb_density ("batched" is the device-driven default)
 LAUNCH_MODES = {"device": 0, "batched": 0, "per_subgraph": 1, "graph": 2, "host": 3}
 

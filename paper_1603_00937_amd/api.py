@@ -24,7 +24,10 @@ def _release(obj, fn):
     h = getattr(obj, "_h", None)
     if not h or _lib is None or L is None:
         return
-    getattr(_lib(), fn)(h)
+    try:
+        getattr(_lib(), fn)(h)
+    except (TypeError, AttributeError):  # module state already torn down at exit
+        return
     obj._h = None
 
 

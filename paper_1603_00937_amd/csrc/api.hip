@@ -590,7 +590,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     check_tau(threshold, "threshold");
     gb_sp2_opts o{};
     if (opts) o = *opts;
-    if (o.precision < GB_FP64 || o.precision > GB_BF16X6_REFINE)
+    if (o.precision < GB_FP64 || o.precision > GB_FP16X3_REFINE)
       fail(GB_EINVAL, "unknown precision %d", o.precision);
     if (o.max_iter < 0 || o.n_refine < 0) fail(GB_EINVAL, "max_iter / n_refine must be >= 0");
     if (o.refine_kind < 0 || o.refine_kind > 2) fail(GB_EINVAL, "unknown refine_kind %d", o.refine_kind);
@@ -659,7 +659,7 @@ gb_status gb_density_workspace(const gb_ell* H, const gb_sp2_opts* opts, size_t*
     if (H->n <= 0 || H->width <= 0) fail(GB_EINVAL, "H->n and H->width must be positive");
     if (!opts || !opts->partition)
       fail(GB_EINVAL, "the workspace size depends on the partition: opts->partition is NULL");
-    if (opts->precision < GB_FP64 || opts->precision > GB_BF16X6_REFINE)
+    if (opts->precision < GB_FP64 || opts->precision > GB_FP16X3_REFINE)
       fail(GB_EINVAL, "unknown precision %d", opts->precision);
     if (opts->partition->part.n != H->n)
       fail(GB_ESHAPE, "partition is for n = %d, H has n = %d", opts->partition->part.n, H->n);

@@ -59,6 +59,19 @@ __device__ inline void load_lds16(const void* g, void* lds) {
 __device__ inline f4v mma_bf16(bf8v a, bf8v b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+// fp16 planes travel in the same 16-byte registers as bf16 ones and are reinterpreted here
+__device__ inline f4v mma_f16(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a),
+                                                __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+}
+// plane products of either type
+template <bool F16>
+__device__ __forceinline__ f4v mma_p(bf8v a, bf8v b, f4v c) {
+  if constexpr (F16) return mma_f16(a, b, c);
+  else return mma_bf16(a, b, c);
+}
+
 
 namespace {
 
@@ -398,20 +411,42 @@ __device__ __forceinline__ void split_planes(float x, __bf16* out) {
 // The same split for two values at once, each plane's pair packed in one 32-bit word (x0 in the
 // low half): one packed conversion per plane, the plane values recovered by a shift and a mask
 // of that word, so the planes are bit-identical to split_planes.
-template <int NP>
+// F16: two fp16 planes of 2^14 x instead (hi = fp16(2^14 x), lo = fp16(2^14 x - hi), about 22
+// bits; |x| <= 1 for an iterate with its spectrum in [0, 1], so 2^14 x stays far below the fp16
+// maximum and values down to ~4e-9 stay normal); the products then carry a factor 2^28, which
+// the epilogue removes exactly.
+constexpr float kF16Scale = 16384.0f;            // 2^14
+constexpr float kF16Unscale = 3.7252902984619140625e-09f;  // 2^-28
+template <int NP, bool F16 = false>
 __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
-  float r0 = x0, r1 = x1;
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  if constexpr (F16) {
+    typedef _Float16 h2v __attribute__((ext_vector_type(2)));
+    float r0 = x0 * kF16Scale, r1 = x1 * kF16Scale;
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    typedef float f2v __attribute__((ext_vector_type(2)));
-    typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
-    const bf2v h = __builtin_convertvector(f2v{r0, r1}, bf2v);
-    uint32_t u;
-    __builtin_memcpy(&u, &h, 4);
-    w[p] = u;
-    if (p + 1 < NP) {
-      r0 -= __uint_as_float(u << 16);
-      r1 -= __uint_as_float(u & 0xffff0000u);
+    for (int p = 0; p < NP; ++p) {
+      const h2v h = __builtin_convertvector(f2v{r0, r1}, h2v);
+      uint32_t u;
+      __builtin_memcpy(&u, &h, 4);
+      w[p] = u;
+      if (p + 1 < NP) {
+        r0 -= (float)h[0];
+        r1 -= (float)h[1];
+      }
+    }
+  } else {
+    float r0 = x0, r1 = x1;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+      const bf2v h = __builtin_convertvector(f2v{r0, r1}, bf2v);
+      uint32_t u;
+      __builtin_memcpy(&u, &h, 4);
+      w[p] = u;
+      if (p + 1 < NP) {
+        r0 -= __uint_as_float(u << 16);
+        r1 -= __uint_as_float(u & 0xffff0000u);
+      }
     }
   }
 }
@@ -422,7 +457,7 @@ __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
 // contiguous run of the transposed row: the mirrored copy (and the x read by the 2x - v branch,
 // X being symmetric) moves as one 16-byte FP32 access and one 8-byte access per plane.  Rows
 // come in groups of four and npad is a multiple of 64, so a group is entirely inside or outside.
-template <int NP, bool WRITE_PLANES = true>
+template <int NP, bool WRITE_PLANES = true, bool F16 = false>
 __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4v (&small)[4][4],
                                                 float* __restrict__ S, __bf16* __restrict__ Sp,
                                                 const float* __restrict__ X, int64_t pstride,
@@ -442,7 +477,10 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
       const int64_t qt = (int64_t)gcol * np + grow0;  // (gcol, grow0 .. grow0 + 3)
       float v[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = big[m][n][r] + small[m][n][r];
+      for (int r = 0; r < 4; ++r) {
+        v[r] = big[m][n][r] + small[m][n][r];
+        if (F16) v[r] *= kF16Unscale;
+      }
       if (do_lin) {
         const f4v xt = *reinterpret_cast<const f4v*>(xa + qt);
 #pragma unroll
@@ -486,7 +524,7 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
 // staging them into the same swizzled LDS layout; the epilogue then writes only the FP32
 // result.  Same products in the same order as the kernels above, so the same results.  The
 // next chunk is loaded into registers under the current chunk's products.
-template <int NP>
+template <int NP, bool F16 = false>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict__ X,
                                                         float* __restrict__ S,
                                                         const int4* __restrict__ tiles,
@@ -548,8 +586,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         uint32_t lo[NP], hi[NP];
-        split_pair<NP>(stg[o][q][0], stg[o][q][1], lo);
-        split_pair<NP>(stg[o][q][2], stg[o][q][3], hi);
+        split_pair<NP, F16>(stg[o][q][0], stg[o][q][1], lo);
+        split_pair<NP, F16>(stg[o][q][2], stg[o][q][3], hi);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
           *reinterpret_cast<uint2*>(&lds[p][o][ldo[q]]) = uint2{lo[p], hi[p]};
@@ -568,21 +606,21 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) big[m][n] = mma_bf16(A0[m], B0[n], big[m][n]);
+        for (int n = 0; n < 4; ++n) big[m][n] = mma_p<F16>(A0[m], B0[n], big[m][n]);
       if (NP >= 2) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           bf8v BL;
           GB_FRAG(BL, NP - 1, 1, pb0, m);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) small[r][m] = mma_bf16(A0[r], BL, small[r][m]);
+          for (int r = 0; r < 4; ++r) small[r][m] = mma_p<F16>(A0[r], BL, small[r][m]);
         }
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           bf8v AL;
           GB_FRAG(AL, NP - 1, 0, pa0, m);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(AL, B0[n], small[m][n]);
+          for (int n = 0; n < 4; ++n) small[m][n] = mma_p<F16>(AL, B0[n], small[m][n]);
         }
       }
       if (NP >= 3) {
@@ -592,15 +630,15 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
-          for (int n = 0; n < 4; ++n) small[m][n] = mma_bf16(A0[m], BM[n], small[m][n]);
+          for (int n = 0; n < 4; ++n) small[m][n] = mma_p<F16>(A0[m], BM[n], small[m][n]);
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
           bf8v AM;
           GB_FRAG(AM, 1, 0, pa0, m);
 #pragma unroll
           for (int n = 0; n < 4; ++n) {
-            small[m][n] = mma_bf16(AM, B0[n], small[m][n]);
-            small[m][n] = mma_bf16(AM, BM[n], small[m][n]);
+            small[m][n] = mma_p<F16>(AM, B0[n], small[m][n]);
+            small[m][n] = mma_p<F16>(AM, BM[n], small[m][n]);
           }
         }
       }
@@ -609,7 +647,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #undef GB_FRAG
 #undef GB_STAGE
   if (!active) return;
-  planes_epilogue<NP, false>(big, small, S, nullptr, X, 0, off, np, bi, bj, wr, wc, lane,
+  planes_epilogue<NP, false, F16>(big, small, S, nullptr, X, 0, off, np, bi, bj, wr, wc, lane,
                              lin_flag ? *lin_flag == 1 : lin != 0);
 }
 
@@ -1152,7 +1190,6 @@ struct Plan {
   std::vector<int4> full_launch; // the same in XCD order (the launch list of general products)
   std::vector<int4> ranges;      // per subgraph: first tile, tile count, variant code, s
   std::vector<int4> idem;        // 128-edge upper tiles covering the core rows (final check)
-  int planes_db = 1;             // split-bf16 kernel variant
   double flops_alg = 0, flops_exec = 0;
   int max_npad = 0;
 };
@@ -1316,15 +1353,19 @@ void launch_split(const float* X, float* S, const int4* tiles, int ntiles, const
                   hipStream_t s, int planes, int lin, const int32_t* stopped = nullptr,
                   const int32_t* lin_flag = nullptr) {
   if (ntiles <= 0) return;
-  if (planes == 1)
-    hipLaunchKernelGGL(k_symm_mm_split<1>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
-                       stopped, lin, lin_flag);
-  else if (planes == 2)
-    hipLaunchKernelGGL(k_symm_mm_split<2>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
-                       stopped, lin, lin_flag);
-  else
-    hipLaunchKernelGGL(k_symm_mm_split<3>, dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs,
-                       stopped, lin, lin_flag);
+#define GB_SPLIT(NP, F)                                                                      \
+  hipLaunchKernelGGL((k_symm_mm_split<NP, F>), dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, \
+                     stopped, lin, lin_flag);
+  if (planes == 1) {
+    GB_SPLIT(1, false)
+  } else if (planes == 2) {
+    GB_SPLIT(2, false)
+  } else if (planes == 4) {
+    GB_SPLIT(2, true)
+  } else {
+    GB_SPLIT(3, false)
+  }
+#undef GB_SPLIT
   GB_LAUNCH_CHECK();
 }
 
@@ -1802,8 +1843,11 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   const int max_iter = o.max_iter > 0 ? o.max_iter : 100;
   const bool low = o.precision != GB_FP64;
   // bf16 planes of the low-precision square: 0 = native FP32 MFMA
+  // split planes of the low-precision square: 0 = native FP32 MFMA; 1 / 2 / 3 bf16 planes;
+  // 4 = two fp16 planes
   const int planes = o.precision == GB_BF16_REFINE ? 1 : o.precision == GB_BF16X3_REFINE ? 2
-                   : o.precision == GB_BF16X6_REFINE ? 3 : 0;
+                   : o.precision == GB_BF16X6_REFINE ? 3 : o.precision == GB_FP16X3_REFINE ? 4
+                   : 0;
   const int n_refine = o.n_refine;
   // launch modes 0 (default) and 2 run the loop on the device; 1 (one launch per subgraph) and
   // 3 read every decision back on the host
@@ -1861,7 +1905,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     }
     if (!done) {
       if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
-      else st.planes_db = 5;
+      st.planes_db = planes;
       // The low-precision loop runs until its own rounding floor (the stagnation stop) unless
       // the traces already agree to 1e-7 per 1024 orbitals, so that one FP64 McWeeny step
       // usually finishes the job.

@@ -11,7 +11,8 @@ loop.
   oracle's subgraphs.
 
 Bars: FP64 1e-9 max-abs with the oracle's branch sequence and step count; the mixed-precision
-loops (FP32 or split-bf16 squares with FP64 traces, branches and refinement) 1e-6 max-abs."""
+loops (FP32, split-bf16 or split-fp16 squares with FP64 traces, branches and refinement) 1e-6
+max-abs."""
 import json
 import os
 
@@ -20,7 +21,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-BAR = {"fp64": 1e-9, "fp32": 1e-6, "bf16x6": 1e-6}
+BAR = {"fp64": 1e-9, "fp32": 1e-6, "bf16x6": 1e-6, "fp16x3": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +45,7 @@ def whole1024(model_cache):
     return m, oc, ov, info
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6", "fp16x3"])
 def test_n1024_whole_D(gb, whole1024, precision):
     m, oc, ov, info = whole1024
     D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
@@ -113,19 +114,23 @@ def _oracle_columns(key, picks):
     return cols
 
 
-CASES = [("n18000", "multilevel", "fp64", "batched"),
-         ("n18000", "multilevel", "bf16x6", "batched"),
+CASES = [("n18000", "multilevel", "fp64", "device"),
+         ("n18000", "multilevel", "bf16x6", "device"),
          ("n18000", "multilevel", "bf16x6", "graph"),
-         ("n18000", "multilevel", "fp32", "batched"),
-         ("n18000", "block", "fp64", "batched"),
-         ("n18000", "block", "bf16x6", "batched"),
-         ("n18000", "block", "fp32", "batched"),
-         ("n100000", "multilevel", "fp64", "batched"),
-         ("n100000", "multilevel", "bf16x6", "batched"),
+         ("n18000", "multilevel", "fp32", "device"),
+         ("n18000", "multilevel", "fp16x3", "device"),
+         ("n18000", "block", "fp64", "device"),
+         ("n18000", "block", "bf16x6", "host"),
+         ("n18000", "block", "fp32", "device"),
+         ("n18000", "block", "fp16x3", "device"),
+         ("n100000", "multilevel", "fp64", "device"),
+         ("n100000", "multilevel", "bf16x6", "device"),
          ("n100000", "multilevel", "bf16x6", "graph"),
-         ("n100000", "multilevel", "fp32", "batched"),
-         ("n100000", "block", "bf16x6", "batched"),
-         ("n100000", "block", "fp32", "batched")]
+         ("n100000", "multilevel", "fp32", "device"),
+         ("n100000", "multilevel", "fp16x3", "device"),
+         ("n100000", "block", "bf16x6", "device"),
+         ("n100000", "block", "fp32", "device"),
+         ("n100000", "block", "fp16x3", "device")]
 
 
 @pytest.mark.parametrize("name,method,precision,launch_mode", CASES)
