@@ -92,6 +92,20 @@ typedef struct {
  * Synchronises `stream`.
  */
 gb_status gb_spectral_bounds(const gb_ell* H, void* stream, double* emin, double* emax);
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): gb_spectral_bounds without any allocation.  The
+ * per-workgroup partials and the result live in a fixed device array of the library
+ * (3 x 1024 + 3 doubles, 24 KB, held on every GPU the library runs on until the process ends);
+ * the call makes no hipMalloc, hipFree or other allocating call.  Rows are grid-strided over at
+ * most 1024 workgroups, so any n is accepted and the array never needs more room.  Same
+ * e_min / e_max bit for bit as gb_spectral_bounds (min and max are exact).  Every call on one GPU
+ * shares that GPU's array (each workgroup writes its own partial before the final pass reads
+ * it, so nothing has to start at zero): calls that overlap on one GPU, from several streams or
+ * threads, race and must be serialised by the caller.  Synchronises `stream`.  Errors as
+ * gb_spectral_bounds (GB_EINVAL for NULL arguments or an H holding NaN or Inf).
+ */
+gb_status gb_spectral_bounds_noalloc(const gb_ell* H, void* stream, double* emin, double* emax);
 
 /* Graph rules (Eq. 2, Eq. 8, obs. viii).  Every rule adds all self-loops (T^(0) = I puts
  * vertex i in its own subgraph, Eqs. 5-6) and the result is symmetric. */

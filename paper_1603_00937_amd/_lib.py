@@ -93,6 +93,8 @@ SIGNATURES = {
     "gb_last_error": (ctypes.c_char_p, []),
     "gb_spectral_bounds": (ctypes.c_int32, [_P(GbEll), _vp, _P(ctypes.c_double),
                                             _P(ctypes.c_double)]),
+    "gb_spectral_bounds_noalloc": (ctypes.c_int32, [_P(GbEll), _vp, _P(ctypes.c_double),
+                                                    _P(ctypes.c_double)]),
     "gb_build_graph": (ctypes.c_int32, [_P(GbEll), _P(GbEll), ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int32, _vp, _P(_vp)]),
     "gb_build_graph_rcut": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,

@@ -118,6 +118,16 @@ def spectral_bounds(H_col, H_val):
     return lo.value, hi.value
 
 
+def spectral_bounds_noalloc(H_col, H_val):
+    """Gershgorin (e_min, e_max) of H without any device allocation (the library's fixed
+    scratch array holds the partials; calls overlapping on one GPU race)."""
+    H = _ell(H_col, H_val)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(_lib().gb_spectral_bounds_noalloc(ctypes.byref(H), _stream(), ctypes.byref(lo),
+                                             ctypes.byref(hi)))
+    return lo.value, hi.value
+
+
 class Graph:
     """Device CSR graph owned by the library."""
 

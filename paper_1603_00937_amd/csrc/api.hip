@@ -315,6 +315,14 @@ gb_status gb_spectral_bounds(const gb_ell* H, void* stream, double* emin, double
   });
 }
 
+gb_status gb_spectral_bounds_noalloc(const gb_ell* H, void* stream, double* emin, double* emax) {
+  return guarded([&] {
+    check_ell(H, "H");
+    if (!emin || !emax) fail(GB_EINVAL, "emin / emax output pointer is NULL");
+    bounds_noalloc(*H, as_stream(stream), emin, emax);
+  });
+}
+
 gb_status gb_build_graph(const gb_ell* H, const gb_ell* aux, double tau, double tau_aux,
                          int32_t mode, void* stream, gb_graph_t** out) {
   return guarded([&] {

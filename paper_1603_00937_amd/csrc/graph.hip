@@ -6,6 +6,9 @@
 // ascending order.  The library is compiled with floating-point contraction disabled.
 #include "internal.h"
 
+#include <map>
+#include <mutex>
+
 #pragma clang fp contract(off)
 
 namespace gbi {
@@ -66,6 +69,79 @@ __global__ void k_minmax(const double* __restrict__ lo, const double* __restrict
     out[0] = smin[0];
     out[1] = smax[0];
     out[2] = sbad[0];
+  }
+}
+
+// ---- spectral bounds without allocated memory ----------------------------------------------
+// The same row ends as k_row_discs, reduced per workgroup (rows grid-strided over at most
+// kNoallocBlocks workgroups) into (min lo, max hi, non-finite rows) partials, then by one
+// workgroup into the final triple; min and max are exact, so the bounds equal k_minmax's bit for
+// bit.  Partials and result live in `scratch`, a fixed device array: each workgroup writes its
+// own three entries before the final pass reads them, so nothing has to start at zero.
+constexpr int kNoallocBlocks = 1024;
+static __device__ __align__(256) double scratch[3 * kNoallocBlocks + 3];
+
+__device__ __forceinline__ void reduce3(double& a, double& b, double& c, double* sa, double* sb,
+                                        double* sc) {
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = kT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      sa[threadIdx.x] = fmin(sa[threadIdx.x], sa[threadIdx.x + h]);
+      sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + h]);
+      sc[threadIdx.x] += sc[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  a = sa[0];
+  b = sb[0];
+  c = sc[0];
+}
+
+__global__ __launch_bounds__(kT) void k_disc_partials(const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val, int n, int w,
+                                                      double* __restrict__ part) {
+  __shared__ double sa[kT], sb[kT], sc[kT];
+  double a = INFINITY, b = -INFINITY, bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const int32_t* c = col + i * w;
+    const double* v = val + i * w;
+    double r = 0.0, d = 0.0;
+    for (int t = 0; t < w; ++t) {
+      const int32_t j = c[t];
+      if (j < 0) break;
+      if (j == i) d = v[t];
+      else r = r + fabs(v[t]);
+    }
+    const double lo = d - r, hi = d + r;
+    if (!isfinite(lo) || !isfinite(hi)) bad += 1.0;
+    a = fmin(a, lo);
+    b = fmax(b, hi);
+  }
+  reduce3(a, b, bad, sa, sb, sc);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = a;
+    part[3 * blockIdx.x + 1] = b;
+    part[3 * blockIdx.x + 2] = bad;
+  }
+}
+
+__global__ __launch_bounds__(kT) void k_disc_final(const double* __restrict__ part, int nb,
+                                                   double* __restrict__ out) {
+  __shared__ double sa[kT], sb[kT], sc[kT];
+  double a = INFINITY, b = -INFINITY, bad = 0.0;
+  for (int q = threadIdx.x; q < nb; q += kT) {
+    a = fmin(a, part[3 * q]);
+    b = fmax(b, part[3 * q + 1]);
+    bad += part[3 * q + 2];
+  }
+  reduce3(a, b, bad, sa, sb, sc);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+    out[2] = bad;
   }
 }
 
@@ -555,6 +631,39 @@ void bounds(const gb_ell& H, hipStream_t s, double* emin, double* emax) {
   GB_LAUNCH_CHECK();
   double h[3];
   GB_HIP(hipMemcpyAsync(h, out.get(), sizeof(h), hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(s));
+  if (h[2] != 0.0)
+    fail(GB_EINVAL, "H holds NaN or Inf values (%.0f rows): no spectral bounds", h[2]);
+  *emin = h[0];
+  *emax = h[1];
+}
+
+// Device address of `scratch` on the current device, looked up once per device (each GPU holds
+// its own copy of the array).  Host code uses only this address, never the array's name.
+double* scratch_ptr() {
+  static std::mutex mu;
+  static std::map<int, double*> ptrs;
+  int dev = 0;
+  GB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it != ptrs.end()) return it->second;
+  void* p = nullptr;
+  GB_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) fail(GB_EHIP, "no device address for the bounds scratch array");
+  ptrs[dev] = static_cast<double*>(p);
+  return static_cast<double*>(p);
+}
+
+void bounds_noalloc(const gb_ell& H, hipStream_t s, double* emin, double* emax) {
+  double* sc = scratch_ptr();
+  const int nb = std::min(blocks_for(H.n, kT), kNoallocBlocks);
+  hipLaunchKernelGGL(k_disc_partials, dim3(nb), dim3(kT), 0, s, H.col, H.val, H.n, H.width, sc);
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_disc_final, dim3(1), dim3(kT), 0, s, sc, nb, sc + 3 * kNoallocBlocks);
+  GB_LAUNCH_CHECK();
+  double h[3];
+  GB_HIP(hipMemcpyAsync(h, sc + 3 * kNoallocBlocks, sizeof(h), hipMemcpyDeviceToHost, s));
   GB_HIP(hipStreamSynchronize(s));
   if (h[2] != 0.0)
     fail(GB_EINVAL, "H holds NaN or Inf values (%.0f rows): no spectral bounds", h[2]);

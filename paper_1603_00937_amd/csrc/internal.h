@@ -122,6 +122,8 @@ struct Csr {
   DBuf<int32_t> row_ptr, col;
 };
 void bounds(const gb_ell& H, hipStream_t s, double* emin, double* emax);  // synchronises
+// the same without allocated device memory (a fixed device array holds the partials)
+void bounds_noalloc(const gb_ell& H, hipStream_t s, double* emin, double* emax);
 void x0_ell(const gb_ell& H, double emin, double emax, double* x0, hipStream_t s);
 void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s);
 void graph_pattern(const gb_ell& A, double tau, Csr& out, hipStream_t s);
