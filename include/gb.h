@@ -47,6 +47,18 @@ typedef int32_t gb_status;
  * that has returned. */
 gb_status gb_trim(void);
 
+/* Kernel-variant table of the autotuner (the tile edge, and for FP64 / FP32 the LDS staging,
+ * chosen per 256-wide size bucket of padded subgraph sizes by timing each variant once; see
+ * gb_sp2_opts.tile_policy).  gb_tune_save writes the table of this process as JSON to `path`
+ * (tagged with the library's source hash and the device: "libgb-tune-1" format); gb_tune_load
+ * merges such a file into it, so a later process skips the timing runs.  A file written by
+ * another build of the library or on another device, or malformed, is GB_EINVAL and leaves the
+ * table unchanged.  With the environment variable GB_TUNE_FILE set, the library reads that
+ * file at its first tuning (ignoring it if unusable) and rewrites it after every new entry.
+ * n_entries (may be NULL) receives the number of entries written / read.  Host only. */
+gb_status gb_tune_save(const char* path, int32_t* n_entries);
+gb_status gb_tune_load(const char* path, int32_t* n_entries);
+
 /* Library version string (static storage). */
 const char* gb_version(void);
 /* Message for the last failing call on this thread ("" if none). */

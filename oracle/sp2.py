@@ -174,13 +174,17 @@ def density_partitioned(H_col, H_val, n_occ, tau, core_size, method="block", ide
     return D_col, D_val, info
 
 
-def sp2_dense(X0: np.ndarray, n_occ, idem_tol, max_iter=100, tau=0.0):
+def sp2_dense(X0: np.ndarray, n_occ, idem_tol, max_iter=100, tau=0.0, stall_stop=False):
     """Whole-matrix SP2 on a dense X0; with tau > 0 every entry of magnitude below tau
-    is zeroed after each update (the thresholded sparse-algebra expansion)."""
+    is zeroed after each update (the thresholded sparse-algebra expansion).  With
+    ``stall_stop`` the expansion also ends once e_n = |t1 - t2| stops decreasing (after at least
+    ten steps, e_n > e_{n-2}): thresholding perturbs every step, so e_n settles at a floor
+    above a tight idem_tol, as rounding does for a low-precision expansion."""
     N = X0.shape[0]
     x = np.array(X0, dtype=np.float64, copy=True)
     branches, traces = [], []
     converged = False
+    stalled = False
     for it in range(max_iter + 1):
         s = x @ x
         t1 = 0.0
@@ -192,6 +196,9 @@ def sp2_dense(X0: np.ndarray, n_occ, idem_tol, max_iter=100, tau=0.0):
         if abs(t1 - t2) <= idem_tol:
             converged = True
             break
+        if stall_stop and it >= 9 and abs(t1 - t2) > abs(traces[-3][0] - traces[-3][1]):
+            stalled = True
+            break
         if it == max_iter:
             break
         b = 0 if abs(t2 - n_occ) < abs(2.0 * t1 - t2 - n_occ) else 1
@@ -199,8 +206,8 @@ def sp2_dense(X0: np.ndarray, n_occ, idem_tol, max_iter=100, tau=0.0):
         x = s if b == 0 else 2.0 * x - s
         if tau > 0.0:
             x[np.abs(x) < tau] = 0.0
-    return x, {"iters": len(branches), "converged": converged, "branch": branches,
-               "traces": traces}
+    return x, {"iters": len(branches), "converged": converged, "stalled": stalled,
+               "branch": branches, "traces": traces}
 
 
 def x0_dense(H_col, H_val, emin=None, emax=None):

@@ -104,6 +104,20 @@ def set_allocator(allocator):
     _check(_lib().gb_set_allocator(allocator._alloc_fn, allocator._free_fn, None))
 
 
+def tune_save(path) -> int:
+    """Write the autotuner's table (JSON, tagged with the library build and device)."""
+    n = ctypes.c_int32()
+    _check(_lib().gb_tune_save(str(path).encode(), ctypes.byref(n)))
+    return n.value
+
+
+def tune_load(path) -> int:
+    """Merge a table written by tune_save on this device and library build."""
+    n = ctypes.c_int32()
+    _check(_lib().gb_tune_load(str(path).encode(), ctypes.byref(n)))
+    return n.value
+
+
 def trim():
     """Free the batch buffers the library caches between calls."""
     _check(_lib().gb_trim())

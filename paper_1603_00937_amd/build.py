@@ -17,10 +17,22 @@ def hipcc_flags():
     ]
 
 
+def source_hash() -> str:
+    """SHA-256 of the library sources (the tag of its autotuning tables)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(HERE, "csrc"))):
+        h.update(name.encode())
+        h.update(open(os.path.join(HERE, "csrc", name), "rb").read())
+    h.update(open(os.path.join(HERE, "..", "include", "gb.h"), "rb").read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(HERE, "csrc", s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = ["/opt/rocm/bin/hipcc", *hipcc_flags(), *srcs, "-o", tmp]
+    cmd = ["/opt/rocm/bin/hipcc", *hipcc_flags(), f'-DGB_SOURCE_SHA="{source_hash()}"', *srcs,
+           "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -307,6 +307,25 @@ gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx) {
   });
 }
 
+gb_status gb_tune_save(const char* path, int32_t* n_entries) {
+  return guarded([&] {
+    if (!path || !*path) fail(GB_EINVAL, "path is NULL or empty");
+    const int n = tune_save(path);
+    if (n < 0) fail(GB_EINVAL, "cannot write the tuning table to %s", path);
+    if (n_entries) *n_entries = n;
+  });
+}
+
+gb_status gb_tune_load(const char* path, int32_t* n_entries) {
+  return guarded([&] {
+    if (!path || !*path) fail(GB_EINVAL, "path is NULL or empty");
+    std::string why;
+    const int n = tune_load(path, &why);
+    if (n < 0) fail(GB_EINVAL, "tuning table %s not used: %s", path, why.c_str());
+    if (n_entries) *n_entries = n;
+  });
+}
+
 gb_status gb_spectral_bounds(const gb_ell* H, void* stream, double* emin, double* emax) {
   return guarded([&] {
     check_ell(H, "H");

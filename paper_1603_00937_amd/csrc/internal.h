@@ -201,6 +201,10 @@ void density_slots(const Part& P, int n, int width, const gb_sp2_opts& o,
 void workspace_layout(Workspace& w, void* base, size_t bytes, const size_t slot[Workspace::kSlots]);
 size_t workspace_total(const size_t slot[Workspace::kSlots]);
 
+// autotuning table (sp2.hip): write / read a JSON file; read returns the entry count or -1
+int tune_save(const char* path);
+int tune_load(const char* path, std::string* why);
+
 struct TapeData;  // SP2 checkpoints for the adjoint (sp2.hip)
 void tape_destroy(TapeData* t);
 void tape_dims(const TapeData* t, int* n, int* max_sub);

@@ -9,7 +9,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <deque>
+#include <string>
 #include <map>
 #include <mutex>
 #include <numeric>
@@ -386,31 +388,17 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 }
 
 
-// ---- split-BF16 squaring ------------------------------------------------------------------
-// An FP32 iterate x is kept alongside its bf16 planes: hi = bf16(x), mid = bf16(x - hi),
+// ---- split squaring ---------------------------------------------------------------------
+// An FP32 iterate x is split into planes: bf16 ones hi = bf16(x), mid = bf16(x - hi),
 // lo = bf16(x - hi - mid) (each remainder is exact in FP32, and hi + mid + lo = x whenever x
-// is an FP32 number).  X*X is summed over the plane products that keep about NP*8 bits
-// (NP = 1: hi*hi; NP = 2 (hi, lo = bf16(x - hi)): + hi*lo, lo*hi; NP = 3: + hi*mid, mid*hi,
-// hi*lo, lo*hi, mid*mid) on v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the leading
-// product and the corrections accumulate separately and are added once at the end.  The
-// epilogue applies the SP2 update (X^2 or 2X - X^2, from the FP32 iterate) and writes the new
-// iterate in FP32 and its planes, so the next step reads ready planes.  Tiling, symmetry and XCD order as in k_symm_mm; a lane
-// group owns 8 consecutive k of each 32-k chunk.
+// is an FP32 number), or two fp16 planes of 2^14 x.  X*X is summed over the plane products
+// that keep about NP*8 bits (NP = 1: hi*hi; NP = 2 (hi, lo = bf16(x - hi)): + hi*lo, lo*hi;
+// NP = 3: + hi*mid, mid*hi, hi*lo, lo*hi, mid*mid) or, for the fp16 planes, hi*hi + hi*lo +
+// lo*hi (about 22 bits), on the 16 x 16 x 32 matrix cores with FP32 accumulation.
 
-template <int NP>
-__device__ __forceinline__ void split_planes(float x, __bf16* out) {
-  float rem = x;
-#pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const __bf16 h = (__bf16)rem;
-    out[p] = h;
-    rem = rem - (float)h;
-  }
-}
-
-// The same split for two values at once, each plane's pair packed in one 32-bit word (x0 in the
-// low half): one packed conversion per plane, the plane values recovered by a shift and a mask
-// of that word, so the planes are bit-identical to split_planes.
+// The split of two values at once, each plane's pair packed in one 32-bit word (x0 in the low
+// half): one packed conversion per plane, the plane values recovered from that word (a shift or
+// a mask for bf16, a conversion for fp16) for the next remainder.
 // F16: two fp16 planes of 2^14 x instead (hi = fp16(2^14 x), lo = fp16(2^14 x - hi), about 22
 // bits; |x| <= 1 for an iterate with its spectrum in [0, 1], so 2^14 x stays far below the fp16
 // maximum and values down to ~4e-9 stay normal); the products then carry a factor 2^28, which
@@ -451,28 +439,29 @@ __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
   }
 }
 
-// Epilogue shared by the split-bf16 kernels: the new iterate v = big + small (or 2x - v), its
-// planes, each written at (row, col) and, off the diagonal blocks, at (col, row).  Lane l holds
+// Epilogue of the split kernels: the new iterate v = big + small (times 2^-28 for fp16 planes),
+// or 2x - v, written at (row, col) and, off the diagonal blocks, at (col, row).  Lane l holds
 // rows 4(l/16) .. 4(l/16) + 3 of column l%16 of each 16 x 16 block, so its four values are one
 // contiguous run of the transposed row: the mirrored copy (and the x read by the 2x - v branch,
-// X being symmetric) moves as one 16-byte FP32 access and one 8-byte access per plane.  Rows
-// come in groups of four and npad is a multiple of 64, so a group is entirely inside or outside.
-template <int NP, bool WRITE_PLANES = true, bool F16 = false>
-__device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4v (&small)[4][4],
-                                                float* __restrict__ S, __bf16* __restrict__ Sp,
-                                                const float* __restrict__ X, int64_t pstride,
-                                                int64_t off, int np, int bi, int bj, int wr,
-                                                int wc, int lane, bool do_lin) {
+// X being symmetric) moves as one 16-byte access.  Rows come in groups of four and npad is a
+// multiple of 64, so a group is entirely inside or outside.
+template <int BT, bool F16>
+__device__ __forceinline__ void split_epilogue(const f4v (&big)[BT / 32][BT / 32],
+                                               const f4v (&small)[BT / 32][BT / 32],
+                                               float* __restrict__ S, const float* __restrict__ X,
+                                               int64_t off, int np, int bi, int bj, int wr, int wc,
+                                               int lane, bool do_lin) {
+  constexpr int MB = BT / 32, WT = BT / 2;
   float* o = S + off;
   const float* xa = X + off;
   const int r16 = lane & 15;
   const bool mirror = bi != bj || wr < wc;
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const int grow0 = bi * kBT + wr * 64 + m * 16 + 4 * (lane >> 4);
-      const int gcol = bj * kBT + wc * 64 + n * 16 + r16;
+    for (int n = 0; n < MB; ++n) {
+      const int grow0 = bi * BT + wr * WT + m * 16 + 4 * (lane >> 4);
+      const int gcol = bj * BT + wc * WT + n * 16 + r16;
       if (grow0 >= np || gcol >= np) continue;
       const int64_t qt = (int64_t)gcol * np + grow0;  // (gcol, grow0 .. grow0 + 3)
       float v[4];
@@ -486,45 +475,23 @@ __device__ __forceinline__ void planes_epilogue(const f4v (&big)[4][4], const f4
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = 2.0f * xt[r] - v[r];
       }
-      __bf16 pl[NP][4];
-      if (WRITE_PLANES) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          __bf16 t[NP];
-          split_planes<NP>(v[r], t);
-#pragma unroll
-          for (int p = 0; p < NP; ++p) pl[p][r] = t[p];
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t q1 = (int64_t)(grow0 + r) * np + gcol;
-        o[q1] = v[r];
-        if (WRITE_PLANES) {
-#pragma unroll
-          for (int p = 0; p < NP; ++p) Sp[p * pstride + off + q1] = pl[p][r];
-        }
-      }
-      if (mirror) {
-        *reinterpret_cast<f4v*>(o + qt) = f4v{v[0], v[1], v[2], v[3]};
-        if (WRITE_PLANES) {
-#pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            uint2 u;
-            __builtin_memcpy(&u, pl[p], 8);
-            *reinterpret_cast<uint2*>(Sp + p * pstride + off + qt) = u;
-          }
-        }
-      }
+      for (int r = 0; r < 4; ++r) o[(int64_t)(grow0 + r) * np + gcol] = v[r];
+      if (mirror) *reinterpret_cast<f4v*>(o + qt) = f4v{v[0], v[1], v[2], v[3]};
     }
 }
 
-// Split in registers: the FP32 iterate itself is read (4 bytes per element instead of 2 NP
-// for stored planes) and each lane splits the 16 bytes it loads into the NP bf16 planes while
-// staging them into the same swizzled LDS layout; the epilogue then writes only the FP32
-// result.  Same products in the same order as the kernels above, so the same results.  The
-// next chunk is loaded into registers under the current chunk's products.
-template <int NP, bool F16 = false>
+// Split squaring: the FP32 iterate itself is read and each lane splits the 16 bytes it loads
+// into the NP planes (bf16, or fp16 of 2^14 x) while staging them into the swizzled LDS layout
+// (eight 16-byte pieces per 64-byte plane row, piece index XORed with bits of the row so that
+// sixteen lanes reading one piece of sixteen rows hit different banks).  X^2 is the sum of the
+// plane products that keep about 8 NP bits (bf16) or 22 bits (two fp16 planes) on the 16 x 16 x
+// 32 matrix cores, the leading product and the corrections in separate FP32 accumulators, added
+// once at the end; the epilogue applies the SP2 update and writes only the FP32 result.  The
+// next chunk is loaded into registers under the current chunk's products.  A workgroup of four
+// waves (2 x 2) computes a BT x BT tile (bi <= bj) of the symmetric product, BT = 128 or 64;
+// tiles and XCD order as in k_symm_mm.
+template <int NP, bool F16, int BT>
 __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict__ X,
                                                         float* __restrict__ S,
                                                         const int4* __restrict__ tiles,
@@ -533,8 +500,11 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
                                                         int lin,
                                                         const int32_t* __restrict__ lin_flag) {
   if (stopped && *stopped) return;
-  constexpr int KC = 32;
-  constexpr int OPB = kBT * 64;
+  constexpr int KC = 32;           // k per chunk (64 bytes per plane row)
+  constexpr int OPB = BT * 64;     // bytes per plane and operand
+  constexpr int MB = BT / 32;      // 16 x 16 blocks per wave-tile edge
+  constexpr int WT = BT / 2;       // wave-tile edge
+  constexpr int NQ = BT / 32;      // rows per staging thread and operand
   __shared__ __align__(1024) unsigned char lds[NP][2][OPB];
   const int4 tl = tiles[blockIdx.x];
   if (tl.x < 0) return;
@@ -543,36 +513,39 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   // staging: thread t moves FP32 piece c8 = t % 8 (k = 4 c8 .. 4 c8 + 3) of rows
-  // t / 8 + 32 q (q = 0..3) of each operand; eight threads cover one row's 128 bytes
+  // t / 8 + 32 q (q < NQ) of each operand; eight threads cover one row's 128 bytes.  Rows beyond
+  // np read row 0 (they only feed outputs that are never stored).
   const int c8 = tid & 7, r0 = tid >> 3;
-  const float* asrc[4];
-  const float* bsrc[4];
-  int ldo[4];  // byte offset of the 8-byte run in a plane's operand array
+  const float* asrc[NQ];
+  const float* bsrc[NQ];
+  int ldo[NQ];  // byte offset of the 8-byte run in a plane's operand array
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int r = r0 + 32 * q;
-    const int ar = bi * kBT + r, br = bj * kBT + r;
+    const int ar = bi * BT + r, br = bj * BT + r;
     asrc[q] = X + off + (int64_t)(ar < np ? ar : 0) * np + 4 * c8;
     bsrc[q] = X + off + (int64_t)(br < np ? br : 0) * np + 4 * c8;
     ldo[q] = r * 64 + (((c8 >> 1) ^ ((r >> 2) & 3)) << 4) + (c8 & 1) * 8;
   }
-  f4v big[4][4], small[4][4];
+  f4v big[MB][MB], small[MB][MB];
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < MB; ++m)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
+    for (int n = 0; n < MB; ++n) {
       big[m][n] = f4v{0, 0, 0, 0};
       small[m][n] = f4v{0, 0, 0, 0};
     }
   const int g = lane >> 4, r16 = lane & 15;
   const int nk = np / KC;
-  const bool in_range = bi * kBT + wr * 64 < np && bj * kBT + wc * 64 < np;
+  // a wave whose block lies in the padding beyond np has nothing to compute; on a diagonal tile
+  // the lower-left block is the transpose of the upper-right one, which that wave writes twice
+  const bool in_range = bi * BT + wr * WT < np && bj * BT + wc * WT < np;
   const bool active = in_range && !(bi == bj && wr > wc);
-  const int pa0 = (wr * 64 + r16) * 64, pb0 = (wc * 64 + r16) * 64;
+  const int pa0 = (wr * WT + r16) * 64, pb0 = (wc * WT + r16) * 64;
   const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
-  f4v stg[2][4];  // [operand][q]
+  f4v stg[2][NQ];  // [operand][q]
 #define GB_STAGE(k0)                                                                          \
-  _Pragma("unroll") for (int q = 0; q < 4; ++q) {                                             \
+  _Pragma("unroll") for (int q = 0; q < NQ; ++q) {                                            \
     stg[0][q] = *reinterpret_cast<const f4v*>(asrc[q] + (k0));                                \
     stg[1][q] = *reinterpret_cast<const f4v*>(bsrc[q] + (k0));                                \
   }
@@ -584,7 +557,7 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #pragma unroll
     for (int o = 0; o < 2; ++o)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         uint32_t lo[NP], hi[NP];
         split_pair<NP, F16>(stg[o][q][0], stg[o][q][1], lo);
         split_pair<NP, F16>(stg[o][q][2], stg[o][q][3], hi);
@@ -597,46 +570,48 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
       GB_STAGE((kc + 1) * KC)
     }
     if (active) {
-      bf8v A0[4], B0[4];
+      bf8v A0[MB], B0[MB];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
+      for (int m = 0; m < MB; ++m) {
         GB_FRAG(A0[m], 0, 0, pa0, m);
         GB_FRAG(B0[m], 0, 1, pb0, m);
       }
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < MB; ++m)
 #pragma unroll
-        for (int n = 0; n < 4; ++n) big[m][n] = mma_p<F16>(A0[m], B0[n], big[m][n]);
+        for (int n = 0; n < MB; ++n) big[m][n] = mma_p<F16>(A0[m], B0[n], big[m][n]);
       if (NP >= 2) {
+        // hi x last plane, last plane x hi (lo for NP = 2, lo for NP = 3)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < MB; ++m) {
           bf8v BL;
           GB_FRAG(BL, NP - 1, 1, pb0, m);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) small[r][m] = mma_p<F16>(A0[r], BL, small[r][m]);
+          for (int r = 0; r < MB; ++r) small[r][m] = mma_p<F16>(A0[r], BL, small[r][m]);
         }
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < MB; ++m) {
           bf8v AL;
           GB_FRAG(AL, NP - 1, 0, pa0, m);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) small[m][n] = mma_p<F16>(AL, B0[n], small[m][n]);
+          for (int n = 0; n < MB; ++n) small[m][n] = mma_p<F16>(AL, B0[n], small[m][n]);
         }
       }
       if (NP >= 3) {
-        bf8v BM[4];
+        // hi x mid, mid x hi, mid x mid
+        bf8v BM[MB];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) GB_FRAG(BM[m], 1, 1, pb0, m);
+        for (int m = 0; m < MB; ++m) GB_FRAG(BM[m], 1, 1, pb0, m);
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < MB; ++m)
 #pragma unroll
-          for (int n = 0; n < 4; ++n) small[m][n] = mma_p<F16>(A0[m], BM[n], small[m][n]);
+          for (int n = 0; n < MB; ++n) small[m][n] = mma_p<F16>(A0[m], BM[n], small[m][n]);
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < MB; ++m) {
           bf8v AM;
           GB_FRAG(AM, 1, 0, pa0, m);
 #pragma unroll
-          for (int n = 0; n < 4; ++n) {
+          for (int n = 0; n < MB; ++n) {
             small[m][n] = mma_p<F16>(AM, B0[n], small[m][n]);
             small[m][n] = mma_p<F16>(AM, BM[n], small[m][n]);
           }
@@ -647,10 +622,9 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #undef GB_FRAG
 #undef GB_STAGE
   if (!active) return;
-  planes_epilogue<NP, false, F16>(big, small, S, nullptr, X, 0, off, np, bi, bj, wr, wc, lane,
-                             lin_flag ? *lin_flag == 1 : lin != 0);
+  split_epilogue<BT, F16>(big, small, S, X, off, np, bi, bj, wr, wc, lane,
+                          lin_flag ? *lin_flag == 1 : lin != 0);
 }
-
 
 // ---- traces and the branch decision --------------------------------------------------------
 // t1 = sum over subgraphs of the core diagonal of X; t2 = the same for X^2, which for the
@@ -1347,26 +1321,29 @@ inline Groups one_group(int code, int count) {
   return g;
 }
 
-// the same with split-bf16 squares (FP32 iterate X -> new FP32 iterate S, `planes` bf16 planes
-// formed in the kernel)
-void launch_split(const float* X, float* S, const int4* tiles, int ntiles, const int64_t* offs,
-                  hipStream_t s, int planes, int lin, const int32_t* stopped = nullptr,
-                  const int32_t* lin_flag = nullptr) {
-  if (ntiles <= 0) return;
-#define GB_SPLIT(NP, F)                                                                      \
-  hipLaunchKernelGGL((k_symm_mm_split<NP, F>), dim3(ntiles), dim3(kT), 0, s, X, S, tiles, offs, \
-                     stopped, lin, lin_flag);
-  if (planes == 1) {
-    GB_SPLIT(1, false)
-  } else if (planes == 2) {
-    GB_SPLIT(2, false)
-  } else if (planes == 4) {
-    GB_SPLIT(2, true)
-  } else {
-    GB_SPLIT(3, false)
-  }
-#undef GB_SPLIT
+// the same with split squares (FP32 iterate X -> new FP32 iterate S; `planes` 1-3 bf16 planes
+// or 4 = two fp16 planes), 128-edge tiles first, then 64-edge tiles
+template <int NP, bool F16>
+void launch_split_np(const float* X, float* S, const int4* tiles, const Groups& g,
+                     const int64_t* offs, hipStream_t s, int lin, const int32_t* stopped,
+                     const int32_t* lin_flag) {
+  if (g.n[0] > 0)
+    hipLaunchKernelGGL((k_symm_mm_split<NP, F16, 128>), dim3(g.n[0]), dim3(kT), 0, s, X, S,
+                       tiles, offs, stopped, lin, lin_flag);
+  if (g.n[1] > 0)
+    hipLaunchKernelGGL((k_symm_mm_split<NP, F16, 64>), dim3(g.n[1]), dim3(kT), 0, s, X, S,
+                       tiles + g.n[0], offs, stopped, lin, lin_flag);
+  if (g.n[2] > 0 || g.n[3] > 0) fail(GB_EHIP, "split squares take 128- or 64-edge tiles only");
   GB_LAUNCH_CHECK();
+}
+
+void launch_split(const float* X, float* S, const int4* tiles, const Groups& g,
+                  const int64_t* offs, hipStream_t s, int planes, int lin,
+                  const int32_t* stopped = nullptr, const int32_t* lin_flag = nullptr) {
+  if (planes == 1) launch_split_np<1, false>(X, S, tiles, g, offs, s, lin, stopped, lin_flag);
+  else if (planes == 2) launch_split_np<2, false>(X, S, tiles, g, offs, s, lin, stopped, lin_flag);
+  else if (planes == 4) launch_split_np<2, true>(X, S, tiles, g, offs, s, lin, stopped, lin_flag);
+  else launch_split_np<3, false>(X, S, tiles, g, offs, s, lin, stopped, lin_flag);
 }
 
 // device tile table: the launch list, then the subgraph-major list
@@ -1414,19 +1391,133 @@ struct PinnedRec {
 
 // ---- autotuner: tile edge per size bucket ----------------------------------------------------
 // Subgraphs are bucketed by padded size (256-wide buckets).  The first time a bucket is seen
-// for a precision, one squaring launch of that bucket's blocks is timed with 128- and 64-edge
-// tiles (one warm-up, two timed launches each) and the faster edge is kept for the life of
-// the process.
+// for a kind of square (0 FP64, 1 FP32, 10 + planes for the split squares), one squaring
+// launch of that bucket's blocks is timed with each kernel variant (one warm-up, two timed
+// launches each) and the fastest is kept.  The table lives for the process and can be kept in
+// a JSON file (gb_tune_save / gb_tune_load, or the GB_TUNE_FILE environment variable: read at
+// the first tuning, rewritten after every new entry), tagged with the library's source hash and
+// the device; a file with another tag is not used.
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, int> g_tune;  // (precision kind, bucket) -> tile edge
+std::map<std::pair<int, int>, int> g_tune;  // (square kind, bucket) -> variant code
+bool g_tune_env_read = false;
 
+#ifndef GB_SOURCE_SHA
+#define GB_SOURCE_SHA "unknown"
+#endif
+
+std::string tune_identity() {
+  int dev = 0;
+  GB_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t pr;
+  GB_HIP(hipGetDeviceProperties(&pr, dev));
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s cu=%d %s", pr.gcnArchName, pr.multiProcessorCount, pr.name);
+  for (char* c = buf; *c; ++c)
+    if (*c == '"' || *c == '\\') *c = ' ';
+  return buf;
+}
+
+// writes the table (caller holds g_tune_mu); false if the file cannot be written
+bool tune_write(const char* path) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  fprintf(f, "{\"format\": \"libgb-tune-1\", \"library\": \"%s\", \"device\": \"%s\",\n \"entries\": [",
+          GB_SOURCE_SHA, tune_identity().c_str());
+  bool first = true;
+  for (const auto& kv : g_tune) {
+    fprintf(f, "%s\n  {\"kind\": %d, \"bucket\": %d, \"variant\": %d}", first ? "" : ",",
+            kv.first.first, kv.first.second, kv.second);
+    first = false;
+  }
+  fprintf(f, "]}\n");
+  const bool ok = fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+// reads a table written by tune_write into g_tune (caller holds g_tune_mu); returns the number
+// of entries, or -1 (message in *why) if the file is missing, malformed or for another library
+// or device
+int tune_read(const char* path, std::string* why) {
+  FILE* f = fopen(path, "r");
+  if (!f) {
+    *why = "cannot open the file";
+    return -1;
+  }
+  std::string txt;
+  char chunk[4096];
+  size_t got;
+  while ((got = fread(chunk, 1, sizeof(chunk), f)) > 0) txt.append(chunk, got);
+  fclose(f);
+  auto field = [&](const char* key) -> std::string {
+    const std::string k = std::string("\"") + key + "\": \"";
+    const size_t a = txt.find(k);
+    if (a == std::string::npos) return std::string("\x01");
+    const size_t b = txt.find('"', a + k.size());
+    return b == std::string::npos ? std::string("\x01") : txt.substr(a + k.size(), b - a - k.size());
+  };
+  if (field("format") != "libgb-tune-1") {
+    *why = "not a libgb tuning table";
+    return -1;
+  }
+  if (field("library") != GB_SOURCE_SHA) {
+    *why = "written by another build of the library";
+    return -1;
+  }
+  if (field("device") != tune_identity()) {
+    *why = "written on another device";
+    return -1;
+  }
+  std::map<std::pair<int, int>, int> t;
+  size_t pos = 0;
+  while ((pos = txt.find("{\"kind\":", pos)) != std::string::npos) {
+    int kind, bucket, variant;
+    if (sscanf(txt.c_str() + pos, "{\"kind\": %d, \"bucket\": %d, \"variant\": %d}", &kind,
+               &bucket, &variant) != 3) {
+      *why = "malformed entry";
+      return -1;
+    }
+    const bool known = variant == 128 || variant == 64 || variant == 63 || variant == 62;
+    const bool split = kind >= 11 && kind <= 14;
+    if (!known || bucket < 1 || !(kind == 0 || kind == 1 || split) ||
+        (split && variant != 128 && variant != 64)) {
+      *why = "entry with an unknown kind, bucket or variant";
+      return -1;
+    }
+    t[{kind, bucket}] = variant;
+    pos += 8;
+  }
+  for (const auto& kv : t) g_tune[kv.first] = kv.second;
+  return (int)t.size();
+}
+
+// the GB_TUNE_FILE table, read once (caller holds g_tune_mu; an unusable file is ignored)
+void tune_env_read() {
+  if (g_tune_env_read) return;
+  g_tune_env_read = true;
+  const char* path = std::getenv("GB_TUNE_FILE");
+  std::string why;
+  if (path && *path) (void)tune_read(path, &why);
+}
+
+void tune_env_write() {
+  const char* path = std::getenv("GB_TUNE_FILE");
+  if (path && *path) (void)tune_write(path);
+}
+
+// planes = 0: launch_square<T>; planes > 0 (T = float): the split squares, 128- or 64-edge tiles
 template <typename T>
 std::vector<int> tune_tiles(const Part& P, const Plan& pl, T* X, T* S, const int64_t* offs,
-                            hipStream_t s, int kind, bool xcd) {
+                            hipStream_t s, int kind, bool xcd, int planes = 0) {
   std::vector<int> bt(pl.n_sub, kBT);
   std::map<int, std::vector<int>> buckets;
   for (int i = 0; i < pl.n_sub; ++i) buckets[(pl.npad[i] + 255) / 256].push_back(i);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_read();
+  }
   Timer tm;
+  bool added = false;
   for (auto& kv : buckets) {
     int choice = 0;
     {
@@ -1437,14 +1528,24 @@ std::vector<int> tune_tiles(const Part& P, const Plan& pl, T* X, T* S, const int
     if (!choice) {
       float best = INFINITY;
       for (int code : kVariants) {
+        if (planes > 0 && code != 128 && code != 64) continue;
         std::vector<int> e(pl.n_sub, 0);
         for (int i : kv.second) e[i] = code;
         const Plan sub = make_plan(P, &e, xcd);
         DBuf<int4> tl = upload_tiles(sub, s);
-        launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
+        auto run = [&] {
+          if constexpr (std::is_same<T, float>::value) {
+            if (planes > 0) {
+              launch_split(X, S, tl.get(), sub.lg, offs, s, planes, 0);
+              return;
+            }
+          }
+          launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
+        };
+        run();
         GB_HIP(hipEventRecord(tm.a, s));
-        launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
-        launch_square<T>(X, S, tl.get(), sub.lg, offs, s);
+        run();
+        run();
         GB_HIP(hipEventRecord(tm.b, s));
         GB_HIP(hipStreamSynchronize(s));
         const float ms = elapsed(tm.a, tm.b);
@@ -1455,23 +1556,30 @@ std::vector<int> tune_tiles(const Part& P, const Plan& pl, T* X, T* S, const int
       }
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune[{kind, kv.first}] = choice;
+      added = true;
     }
     for (int i : kv.second) bt[i] = choice;
+  }
+  if (added) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_write();
   }
   return bt;
 }
 
 template <typename T>
 void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const int64_t* offs,
-                  hipStream_t s, int policy, int kind, gb_sp2_stats& st, bool xcd) {
+                  hipStream_t s, int policy, int kind, gb_sp2_stats& st, bool xcd,
+                  int planes = 0, bool record = true) {
   std::vector<int> bt(pl.n_sub, kBT);
   if (policy == 2) bt.assign(pl.n_sub, 64);
-  else if (policy == 4) bt.assign(pl.n_sub, 63);
-  else if (policy == 5) bt.assign(pl.n_sub, 62);
-  else if (policy == 0 || policy == 3) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd);
+  else if (policy == 4 && planes == 0) bt.assign(pl.n_sub, 63);
+  else if (policy == 5 && planes == 0) bt.assign(pl.n_sub, 62);
+  else if (policy != 1) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd, planes);
   if (policy == 1) return;
   pl = make_plan(P, &bt, xcd);
   tiles = upload_tiles(pl, s);
+  if (!record) return;  // the refinement's squares: the stats describe the loop's
   st.n_tile64 = 0;
   st.n_stage3 = 0;
   st.n_regstage = 0;
@@ -1516,9 +1624,10 @@ void launch_step(const T* X, T* S, const Plan& pl, const int4* tiles, const int6
     if (planes > 0) {
       if (per_subgraph)
         for (const int4& rg : pl.ranges)
-          launch_split(X, S, tiles + nl + rg.x, rg.y, offs, s, planes, lin, stopped, lin_flag);
+          launch_split(X, S, tiles + nl + rg.x, one_group(rg.z, rg.y), offs, s, planes, lin,
+                       stopped, lin_flag);
       else
-        launch_split(X, S, tiles, nl, offs, s, planes, lin, stopped, lin_flag);
+        launch_split(X, S, tiles, pl.lg, offs, s, planes, lin, stopped, lin_flag);
       return;
     }
   }
@@ -1808,6 +1917,19 @@ struct RowsCtx {
   }
 };
 
+int tune_save(const char* path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_env_read();
+  if (!tune_write(path)) return -1;
+  return (int)g_tune.size();
+}
+
+int tune_load(const char* path, std::string* why) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_env_read = true;  // an explicit table replaces the environment's
+  return tune_read(path, why);
+}
+
 void density_slots(const Part& P, int n, int width, const gb_sp2_opts& o,
                    size_t bytes[Workspace::kSlots]) {
   for (int i = 0; i < Workspace::kSlots; ++i) bytes[i] = 0;
@@ -1904,7 +2026,9 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       }
     }
     if (!done) {
-      if (planes == 0) choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy, 1, st, xcd);
+      // FP32 squares: kind 1; split squares: kind 10 + planes (128- or 64-edge tiles)
+      choose_tiles<float>(P, pl, xf, sf, tiles, offs.get(), s, o.tile_policy,
+                          planes ? 10 + planes : 1, st, xcd, planes);
       st.planes_db = planes;
       // The low-precision loop runs until its own rounding floor (the stagnation stop) unless
       // the traces already agree to 1e-7 per 1024 orbitals, so that one FP64 McWeeny step
@@ -1968,7 +2092,12 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   if (!low && !tape_out) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, o.tile_policy, 0, st, xcd);
   // (with split-bf16 squares tile_policy picks that kernel's variant; the FP64 refinement tunes
   // its own tile edge)
-  else if (low && planes > 0) choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, 0, 0, st, xcd);
+  // (after split squares the plan holds the split's tile edges; FP64 squares on whole blocks --
+  // the refinement's fallback, refine_kind 1 and 2 -- tune their own variant when they run)
+  auto fp64_tiles_for_blocks = [&] {
+    if (low && planes > 0)
+      choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, 0, 0, st, xcd, 0, false);
+  };
   CoreRows cr;
   const double* rows_final = nullptr;  // core-row refinement: the core rows of D and of D^2
   const double* rows_check = nullptr;
@@ -2054,6 +2183,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       // Whole blocks: X^2 = S, then 3S - 2 S X (S and X commute, so S X is computed on upper
       // tiles and mirrored); steps repeat until the FP64 stop test holds (at most n_refine,
       // default 8).
+      fp64_tiles_for_blocks();
       DBuf<double> part(2 * (size_t)pl.n_sub, s);
       double* td = ws->get<double>(2, pl.total, s);
       const int max_steps = n_refine > 0 ? n_refine : 8;
@@ -2079,6 +2209,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     }
   } else if (low) {
     // FP64 refinement: SP2 steps with FP64 traces from where the FP32 loop stopped
+    fp64_tiles_for_blocks();
     const uint8_t* bin = nullptr;
     int nbin = 0;
     if (o.branch_in && o.n_branch_in > it_end) {

@@ -308,3 +308,18 @@ def test_sp2_estimate_gap_rejects_bad_arguments(lib):
     assert lib.gb_sp2_estimate_gap(None, a, b, 3, 1.0, 0.0, 1.0, 0.0, ctypes.byref(r)) == GB_EINVAL
     assert lib.gb_sp2_estimate_gap(a, a, b, 0, 1.0, 0.0, 1.0, 0.0, ctypes.byref(r)) == GB_EINVAL
     assert lib.gb_sp2_estimate_gap(a, a, b, 3, 1.0, 0.0, 1.0, 0.0, None) == GB_EINVAL
+
+
+def test_tune_table_rejects_foreign_files(lib, tmp_path):
+    from paper_1603_00937_amd._lib import GB_EINVAL
+    n = ctypes.c_int32(-7)
+    assert lib.gb_tune_load(str(tmp_path / "missing.json").encode(), ctypes.byref(n)) == GB_EINVAL
+    assert lib.gb_tune_load(None, ctypes.byref(n)) == GB_EINVAL
+    bad = tmp_path / "other.json"
+    bad.write_text('{"format": "libgb-tune-1", "library": "another-build", "device": "x",\n'
+                   ' "entries": [\n  {"kind": 0, "bucket": 4, "variant": 62}]}\n')
+    assert lib.gb_tune_load(str(bad).encode(), ctypes.byref(n)) == GB_EINVAL
+    assert "another build" in _err(lib) and n.value == -7
+    bad.write_text('{"format": "something-else"}')
+    assert lib.gb_tune_load(str(bad).encode(), ctypes.byref(n)) == GB_EINVAL
+    assert "not a libgb tuning table" in _err(lib)

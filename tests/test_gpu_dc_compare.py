@@ -92,3 +92,34 @@ def test_error_against_cost(gb, model_cache):
         assert len(errs) == 3
         assert errs[0] > errs[1] > errs[2] and costs[0] < costs[1] < costs[2]
     assert min(r[2] for r in rows) < 2e-3
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6", "fp16x3", "fp32"])
+def test_n1024_error_against_exact(gb, model_cache, precision):
+    """The GPU D at N = 1024 (blocks of 16, tau = 1e-5) against the dense diagonalisation (run
+    here on the CPU): the truncation error of the method, which the stored comparison of the
+    CPU references measured for the partitioned oracle (tests/golden/method_comparison.json);
+    the GPU result reproduces it to 1e-9 (FP64) or 1e-6 (mixed precision), measure by measure."""
+    import json
+    import os
+    from oracle.bounds import ell_to_dense
+    from oracle.exact import density_exact
+    from oracle.metrics import column_ell_to_dense, errors
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "method_comparison.json")))["n1024"]
+    m = model_cache("n1024")
+    D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                  core_size=16, precision=precision)
+    H = ell_to_dense(m["H_col"], m["H_val"])
+    De, w, gap = density_exact(H, m["n_occ"])
+    e = errors(column_ell_to_dense(D_col.cpu().numpy(), D_val.cpu().numpy()), De, H,
+               m["N"] // 2)
+    o = ref["O3"]["vs_O1"]
+    print(f"{precision}: vs exact max-abs {e['max_abs']:.3e} (oracle {o['max_abs']:.3e}), "
+          f"Frobenius/site {e['frob_per_site']:.3e} ({o['frob_per_site']:.3e}), E_band/site "
+          f"{e['eband_err_per_site']:.3e} ({o['eband_err_per_site']:.3e}); whole-matrix "
+          f"thresholded SP2: {ref['O2']['vs_O1']['max_abs']:.3e}")
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    assert abs(e["max_abs"] - o["max_abs"]) <= tol
+    assert abs(e["frob_per_site"] - o["frob_per_site"]) <= tol
+    assert abs(e["eband_err_per_site"] - o["eband_err_per_site"]) <= tol

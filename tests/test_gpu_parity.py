@@ -208,6 +208,44 @@ def test_launch_modes_agree_n1024(gb, model_cache, precision):
         assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), mode
 
 
+@pytest.mark.parametrize("name,core", [("small256", 16), ("n1024", 16)])
+@pytest.mark.parametrize("precision", ["bf16x6", "fp16x3"])
+def test_split_tile_edges_agree(gb, model_cache, name, core, precision):
+    """Split squares on 128- and 64-edge tiles (and the tuner's per-bucket choice) accumulate
+    every entry over k in the same order, but which of the mirrored pair (r, c) / (c, r) a tile
+    computes depends on the tile edge, and the plane products pair the two differently: the
+    results agree to the rounding of the low-precision loop (about 1e-8 here, far inside the
+    1e-6 bar each of them meets against the oracle)."""
+    m = model_cache(name)
+    outs = {}
+    for pol in ("128", "64", "auto"):
+        D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
+                                      core_size=core, precision=precision, tile_policy=pol)
+        outs[pol] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"], st["n_tile64"])
+    assert outs["128"][3] == 0 and outs["64"][3] > 0
+    for pol in ("64", "auto"):
+        assert outs[pol][2] == outs["128"][2]
+        assert np.array_equal(outs[pol][0], outs["128"][0])
+        assert np.abs(outs[pol][1] - outs["128"][1]).max() < 2e-7, pol
+
+
+def test_tune_table_round_trip(gb, model_cache, tmp_path):
+    import json
+    m = model_cache("n1024")
+    gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5, core_size=16,
+               precision="bf16x6")
+    path = tmp_path / "tune.json"
+    n = gb.tune_save(path)
+    t = json.loads(path.read_text())
+    assert n >= 1 and len(t["entries"]) == n and t["format"] == "libgb-tune-1"
+    assert any(e["kind"] == 13 for e in t["entries"])  # the split-bf16 squares
+    assert gb.tune_load(path) == n
+    t["device"] = "another device"
+    path.write_text(json.dumps(t))
+    with pytest.raises(gb.GbError):
+        gb.tune_load(path)
+
+
 @pytest.mark.parametrize("mode", ["device", "graph", "host"])
 def test_replay_and_max_iter(gb, model_cache, mode):
     m = model_cache("small256")

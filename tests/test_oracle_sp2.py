@@ -284,3 +284,19 @@ def test_core_columns_equal_whole_system_oracle(mid):
             assert np.array_equal(D_col[v, :len(rows)], rows)
             assert (D_col[v, len(rows):] == -1).all()
             assert np.array_equal(D_val[v, :len(rows)], vals[c])
+
+
+def test_thresholded_sp2_stall_stop(mid):
+    """With thresholding the idempotency measure stalls above a tight tolerance; the stall stop
+    ends the expansion there, after at least ten steps, at an error against the eigensolver of
+    the order of the threshold, while tau = 1e-12 still converges without it."""
+    m = mid
+    X0 = x0_dense(m["H_col"], m["H_val"])
+    De, w, gap = density_exact(ell_to_dense(m["H_col"], m["H_val"]), m["n_occ"])
+    x, info = sp2_dense(X0, m["n_occ"], 1e-12, tau=1e-5, stall_stop=True)
+    e = [abs(a - b) for a, b in info["traces"]]
+    assert info["stalled"] and not info["converged"] and info["iters"] >= 10
+    assert e[-1] > e[-3]
+    assert np.abs(x - De).max() < 1e-3
+    x2, info2 = sp2_dense(X0, m["n_occ"], 1e-10, tau=1e-12, stall_stop=True)
+    assert info2["converged"] and not info2["stalled"]
