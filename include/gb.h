@@ -316,7 +316,9 @@ typedef struct {
   int32_t n_stage3;          /* subgraphs squared with the three-stage 64-edge kernel         */
   int32_t n_regstage;        /* subgraphs squared with the register-staged 64-edge kernel     */
   double square_flops;       /* algorithmic flops of one square launch: sum_s 2 n_s^3        */
-  double square_flops_exec;  /* matrix-core flops one launch executes (padding, symmetry)    */
+  double square_flops_exec;  /* matrix-core flops one launch executes: every active wave's    *
+                              * block over the padded size (upper tiles, padding; times the   *
+                              * plane products for split squares, applied by the caller)      */
   struct gb_tape_s* tape;    /* with keep_tape: the recorded expansion (free: gb_tape_destroy) */
   int32_t n_near_tie;        /* trace-rule decisions whose margin is within the rounding of   *
                               * the summed traces (64 ulp of |t1| + |t2| + n_occ): another     *

@@ -5,6 +5,7 @@
 // order, x0 = (e_max*delta_ij - h_ij)/(e_max - e_min), and (X0^2)_ij accumulated over k in
 // ascending order.  The library is compiled with floating-point contraction disabled.
 #include "internal.h"
+#include "lds_scan.h"
 
 #include <map>
 #include <mutex>
@@ -187,36 +188,6 @@ __device__ __forceinline__ int32_t block_sum_i32(int32_t v, int32_t* red) {
   return r;
 }
 
-// exclusive scan of v[0..m) in place (LDS), returns total; all threads call
-__device__ int32_t lds_exclusive_scan(int32_t* v, int m, int32_t* red) {
-  // thread t owns the contiguous segment [t s, t s + s) of v, s = ceil(m / kT): segment sums,
-  // one scan of the kT sums, then each segment rewritten from its offset (one scan however
-  // long v is)
-  const int seg = (m + kT - 1) / kT;
-  const int b = min((int)threadIdx.x * seg, m), e = min(b + seg, m);
-  int32_t sum = 0;
-  for (int k = b; k < e; ++k) sum += v[k];
-  __syncthreads();
-  red[threadIdx.x] = sum;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over kT values
-  for (int d = 1; d < kT; d <<= 1) {
-    const int32_t y = threadIdx.x >= d ? red[threadIdx.x - d] : 0;
-    __syncthreads();
-    red[threadIdx.x] += y;
-    __syncthreads();
-  }
-  int32_t run = red[threadIdx.x] - sum;
-  for (int k = b; k < e; ++k) {
-    const int32_t x = v[k];
-    v[k] = run;
-    run += x;
-  }
-  const int32_t total = red[kT - 1];
-  __syncthreads();
-  return total;
-}
-
 
 constexpr int kX2Q = 4;  // ELL row entries per thread in the X2 accumulation (width <= 1024)
 
@@ -256,7 +227,7 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
   // 2. ranks
   for (int q = threadIdx.x; q < nw; q += kT) L.pre[q] = __popc(L.bits[q]);
   __syncthreads();
-  const int32_t ncand = lds_exclusive_scan(L.pre, nw, red);
+  const int32_t ncand = lds_exclusive_scan<kT>(L.pre, nw, red);
   if (ncand > cap) {
     if (threadIdx.x == 0) {
       atomicMax(overflow, ncand);
@@ -332,7 +303,7 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
     L.wcnt[q] = c;
   }
   __syncthreads();
-  const int32_t kept = lds_exclusive_scan(L.wcnt, nw, red);
+  const int32_t kept = lds_exclusive_scan<kT>(L.wcnt, nw, red);
   if (threadIdx.x == 0) cnt[i] = kept;
   int32_t* dst = rows + (int64_t)i * cap;  // kept <= ncand <= cap
   for (int q = threadIdx.x; q < nw; q += kT) {
@@ -397,7 +368,7 @@ __global__ __launch_bounds__(kT) void k_union_rows(int n, const int32_t* __restr
   __syncthreads();
   for (int q = threadIdx.x; q < nw; q += kT) wc[q] = __popc(bits[q]);
   __syncthreads();
-  const int32_t tot = lds_exclusive_scan(wc, nw, red);
+  const int32_t tot = lds_exclusive_scan<kT>(wc, nw, red);
   if (PASS == 0) {
     if (threadIdx.x == 0) cnt[i] = tot;
     return;
@@ -442,7 +413,7 @@ __global__ __launch_bounds__(kT) void k_twohop_rows(int n, const int32_t* __rest
   __syncthreads();
   for (int q = threadIdx.x; q < nw; q += kT) wc[q] = __popc(bits[q]);
   __syncthreads();
-  const int32_t tot = lds_exclusive_scan(wc, nw, red);
+  const int32_t tot = lds_exclusive_scan<kT>(wc, nw, red);
   if (PASS == 0) {
     if (threadIdx.x == 0) cnt[i] = tot;
     return;

@@ -3,40 +3,12 @@
 // core adjacent to a core vertex -- ascending.  One workgroup per core builds the halo in an
 // LDS bitmap over all vertices, so the lists come out sorted and duplicate-free.
 #include "internal.h"
+#include "lds_scan.h"
 
 namespace gbi {
 namespace {
 
 constexpr int kT = 256;
-
-__device__ int32_t lds_exclusive_scan(int32_t* v, int m, int32_t* red) {
-  // thread t owns the contiguous segment [t s, t s + s) of v, s = ceil(m / kT): segment sums,
-  // one scan of the kT sums, then each segment rewritten from its offset (one scan however
-  // long v is)
-  const int seg = (m + kT - 1) / kT;
-  const int b = min((int)threadIdx.x * seg, m), e = min(b + seg, m);
-  int32_t sum = 0;
-  for (int k = b; k < e; ++k) sum += v[k];
-  __syncthreads();
-  red[threadIdx.x] = sum;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over kT values
-  for (int d = 1; d < kT; d <<= 1) {
-    const int32_t y = threadIdx.x >= d ? red[threadIdx.x - d] : 0;
-    __syncthreads();
-    red[threadIdx.x] += y;
-    __syncthreads();
-  }
-  int32_t run = red[threadIdx.x] - sum;
-  for (int k = b; k < e; ++k) {
-    const int32_t x = v[k];
-    v[k] = run;
-    run += x;
-  }
-  const int32_t total = red[kT - 1];
-  __syncthreads();
-  return total;
-}
 
 
 template <int PASS>
@@ -71,7 +43,7 @@ __global__ __launch_bounds__(kT) void k_halo(int n, const int32_t* __restrict__ 
   __syncthreads();
   for (int q = threadIdx.x; q < nw; q += kT) wc[q] = __popc(bits[q]);
   __syncthreads();
-  const int32_t halo = lds_exclusive_scan(wc, nw, red);
+  const int32_t halo = lds_exclusive_scan<kT>(wc, nw, red);
   if (PASS == 0) {
     if (threadIdx.x == 0) cnt[c] = (c1 - c0) + halo;
     return;

@@ -1224,10 +1224,16 @@ Plan make_plan(const Part& P, const std::vector<int>* bt = nullptr, bool xcd = t
       const int np = pl.npad[s];
       const int nb = (np + edge - 1) / edge;
       const int first = (int)pl.tiles.size();
+      const int wt = edge / 2;  // wave tile edge (2 x 2 waves per tile)
       for (int bi = 0; bi < nb; ++bi)
         for (int bj = bi; bj < nb; ++bj) {
           pl.tiles.push_back(make_int4(s, bi, bj, np));
-          pl.flops_exec += 2.0 * edge * edge * (double)np;
+          // matrix-core work the tile executes: every wave whose block lies inside npad, except
+          // the lower-left one of a diagonal tile
+          for (int wr = 0; wr < 2; ++wr)
+            for (int wc = 0; wc < 2; ++wc)
+              if (bi * edge + wr * wt < np && bj * edge + wc * wt < np && !(bi == bj && wr > wc))
+                pl.flops_exec += 2.0 * wt * wt * (double)np;
         }
       pl.ranges.push_back(make_int4(first, (int)pl.tiles.size() - first, code, s));
     }
