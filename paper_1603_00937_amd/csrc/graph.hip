@@ -5,9 +5,12 @@
 // order, x0 = (e_max*delta_ij - h_ij)/(e_max - e_min), and (X0^2)_ij accumulated over k in
 // ascending order.  The library is compiled with floating-point contraction disabled.
 #include "internal.h"
+#include "lds_hash.h"
 #include "lds_scan.h"
 
+#include <cstdlib>
 #include <map>
+#include <string>
 #include <mutex>
 
 #pragma clang fp contract(off)
@@ -320,6 +323,136 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
   }
 }
 
+// The same rows for any n: the two-hop candidates of row i go into an LDS hash set instead of
+// an n-bit bitmap and are sorted to fix their ranks; the accumulation (ascending k, one barrier
+// per row k) and the keep rule are those of k_x2_rows, so the graph is the same bit for bit.
+// LDS: acc [cap], x0 of row i [w], keys and their ranks [2^log2h each], the sorted candidates
+// [2^log2u >= cap], columns of row i [w], scratch [kT].  Inserts stop once more than cap
+// candidates were counted (at most kT more land, and 2^log2h >= cap + kT + 1 keeps the set from
+// filling); such a row reports its count through `overflow`.
+__global__ __launch_bounds__(kT) void k_x2_rows_hash(const int32_t* __restrict__ hcol,
+                                                     const double* __restrict__ x0, int n, int w,
+                                                     double tau, int cap, int log2h, int log2u,
+                                                     int32_t* __restrict__ cnt,
+                                                     int32_t* __restrict__ rows,
+                                                     int32_t* __restrict__ overflow) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t count, gathered;
+  const int i = blockIdx.x;
+  const int H = 1 << log2h, P = 1 << log2u;
+  double* acc = reinterpret_cast<double*>(smem);
+  double* xi = acc + cap;
+  int32_t* keys = reinterpret_cast<int32_t*>(xi + w);
+  int32_t* rk = keys + H;
+  int32_t* U = rk + H;
+  int32_t* ci = U + P;
+  int32_t* red = ci + w;
+  for (int t = threadIdx.x; t < w; t += kT) {
+    ci[t] = hcol[(int64_t)i * w + t];
+    xi[t] = x0[(int64_t)i * w + t];
+  }
+  for (int q = threadIdx.x; q < H; q += kT) keys[q] = kHashEmpty;
+  if (threadIdx.x == 0) {
+    count = 0;
+    gathered = 0;
+  }
+  __syncthreads();
+  // 1. two-hop candidates (and i itself)
+  if (threadIdx.x == 0 && hset_insert(keys, log2h, i)) atomicAdd(&count, 1);
+  for (int p = threadIdx.x; p < w * w; p += kT) {
+    const int t = p / w, u = p - t * w;
+    const int32_t k = ci[t];
+    if ((unsigned)k >= (unsigned)n) continue;
+    const int32_t j = hcol[(int64_t)k * w + u];
+    if ((unsigned)j >= (unsigned)n) continue;
+    if (*(volatile int32_t*)&count > cap) break;
+    if (hset_insert(keys, log2h, j)) atomicAdd(&count, 1);
+  }
+  __syncthreads();
+  const int ncand = count;
+  if (ncand > cap) {
+    if (threadIdx.x == 0) {
+      atomicMax(overflow, ncand);
+      cnt[i] = 0;
+    }
+    return;
+  }
+  // 2. ranks: the candidates sorted ascending
+  for (int q = threadIdx.x; q < H; q += kT) {
+    const int32_t k = keys[q];
+    if (k != kHashEmpty) U[atomicAdd(&gathered, 1)] = k;
+  }
+  __syncthreads();
+  for (int r = ncand + threadIdx.x; r < P; r += kT) U[r] = INT32_MAX;
+  bitonic_sort<kT>(U, P);
+  for (int r = threadIdx.x; r < ncand; r += kT) {
+    rk[hset_find(keys, log2h, U[r])] = r;
+    acc[r] = 0.0;
+  }
+  if (threadIdx.x == 0) red[0] = w;
+  __syncthreads();
+  for (int t = threadIdx.x; t < w; t += kT)
+    if ((unsigned)ci[t] >= (unsigned)n) atomicMin(&red[0], t);
+  __syncthreads();
+  const int kw = red[0];
+  __syncthreads();
+  // 3. canonical accumulation, k ascending, one barrier per row k (as k_x2_rows)
+  int32_t ja[kX2Q], jb[kX2Q], jc[kX2Q];
+  double xa[kX2Q], xb[kX2Q], xc[kX2Q];
+  auto fetch = [&](int t, int32_t (&jj)[kX2Q], double (&xx)[kX2Q]) {
+    const bool on = t < kw;
+    const int32_t k = on ? ci[t] : 0;
+#pragma unroll
+    for (int q = 0; q < kX2Q; ++q) {
+      const int u = threadIdx.x + q * kT;
+      jj[q] = -1;
+      xx[q] = 0.0;
+      if (on && u < w) {
+        jj[q] = hcol[(int64_t)k * w + u];
+        xx[q] = x0[(int64_t)k * w + u];
+      }
+    }
+  };
+  auto apply = [&](int t, const int32_t (&jj)[kX2Q], const double (&xx)[kX2Q]) {
+    if (t >= kw) return;
+    const double xik = xi[t];
+#pragma unroll
+    for (int q = 0; q < kX2Q; ++q) {
+      const int32_t j = jj[q];
+      if ((unsigned)j >= (unsigned)n) continue;
+      const int r = rk[hset_find(keys, log2h, j)];
+      const double prod = xik * xx[q];
+      acc[r] = acc[r] + prod;
+    }
+  };
+  fetch(0, ja, xa);
+  fetch(1, jb, xb);
+  for (int t = 0; t < kw; t += 3) {
+    fetch(t + 2, jc, xc);
+    apply(t, ja, xa);
+    __syncthreads();
+    fetch(t + 3, ja, xa);
+    apply(t + 1, jb, xb);
+    __syncthreads();
+    fetch(t + 4, jb, xb);
+    apply(t + 2, jc, xc);
+    __syncthreads();
+  }
+  // 4. keep decision and ordered compaction (rk reused for the kept flags and their offsets)
+  for (int r = threadIdx.x; r < ncand; r += kT) rk[r] = (fabs(acc[r]) >= tau || U[r] == i) ? 1 : 0;
+  __syncthreads();
+  const int32_t kept = lds_exclusive_scan<kT>(rk, ncand, red);
+  if (threadIdx.x == 0) cnt[i] = kept;
+  int32_t* dst = rows + (int64_t)i * cap;
+  for (int r = threadIdx.x; r < ncand; r += kT)
+    if (fabs(acc[r]) >= tau || U[r] == i) dst[rk[r]] = U[r];
+}
+
+size_t x2_hash_lds_bytes(int w, int cap, int log2h, int log2u) {
+  return (size_t)cap * 8 + (size_t)w * 8 + ((size_t)2 << log2h) * 4 + ((size_t)1 << log2u) * 4 +
+         (size_t)w * 4 + (size_t)kT * 4 + 64;
+}
+
 // row i of the staging array (cnt[i] columns at i * cap) -> the CSR at row_ptr[i]
 __global__ __launch_bounds__(kT) void k_x2_compact(const int32_t* __restrict__ rows, int cap,
                                                    const int32_t* __restrict__ cnt,
@@ -592,6 +725,13 @@ void transpose(int n, const int32_t* rp, const int32_t* c, int64_t nnz, DBuf<int
 
 }  // namespace
 
+bool use_hash_sets(int n) {
+  const char* e = std::getenv("GB_VERTEX_SETS");
+  if (e && std::string(e) == "hash") return true;
+  if (e && std::string(e) == "bitmap") return false;
+  return n > (1 << 17);
+}
+
 void bounds(const gb_ell& H, hipStream_t s, double* emin, double* emax) {
   const int n = H.n;
   DBuf<double> lo(n, s), hi(n, s), out(3, s);
@@ -650,8 +790,49 @@ void x0_ell(const gb_ell& H, double emin, double emax, double* x0, hipStream_t s
   GB_LAUNCH_CHECK();
 }
 
+// X2 graph through the hash-set kernel: candidate capacity 2048 to start with (two workgroups
+// per CU), raised to the largest count a row reports and run again (at most twice).
+void graph_x2_hash(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s) {
+  const int n = H.n, w = H.width;
+  if (w > kX2Q * kT) fail(GB_EUNSUPPORTED, "X2 graph: ELL width %d above %d", w, kX2Q * kT);
+  int cap = (int)std::min<int64_t>(std::min<int64_t>((int64_t)w * w, n) + 1, 2048);
+  cap = std::max(cap, kT);
+  DBuf<int32_t> cnt(n, s), ovf(1, s), rows;
+  out.n = n;
+  out.row_ptr = DBuf<int32_t>(n + 1, s);
+  int32_t h[2] = {0, 0};
+  for (int attempt = 0;; ++attempt) {
+    const int log2h = ceil_log2((int64_t)cap + kT + 1), log2u = ceil_log2(cap);
+    const size_t lds = x2_hash_lds_bytes(w, cap, log2h, log2u);
+    if (lds > 160 * 1024)
+      fail(GB_EUNSUPPORTED, "X2 graph: a row has %d two-hop candidates, more than LDS holds", cap);
+    rows = DBuf<int32_t>((size_t)n * cap, s);
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
+    hipLaunchKernelGGL(k_x2_rows_hash, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, cap,
+                       log2h, log2u, cnt.get(), rows.get(), ovf.get());
+    GB_LAUNCH_CHECK();
+    exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
+    GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipMemcpyAsync(&h[1], ovf.get(), 4, hipMemcpyDeviceToHost, s));
+    GB_HIP(hipStreamSynchronize(s));
+    if (h[1] == 0) break;
+    if (attempt == 2) fail(GB_EUNSUPPORTED, "X2 graph: candidate count did not settle");
+    // a stopped row counted at least cap + 1 candidates; grow past what was reported
+    cap = std::max(((h[1] + 255) / 256) * 256, 2 * cap);
+  }
+  out.nnz = h[0];
+  out.col = DBuf<int32_t>(h[0] > 0 ? h[0] : 1, s);
+  hipLaunchKernelGGL(k_x2_compact, dim3(n), dim3(kT), 0, s, rows.get(), cap, cnt.get(),
+                     out.row_ptr.get(), out.col.get());
+  GB_LAUNCH_CHECK();
+}
+
 void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s) {
   const int n = H.n, w = H.width;
+  if (use_hash_sets(n)) {
+    graph_x2_hash(H, x0, tau, out, s);
+    return;
+  }
   // candidate capacity: small enough for several workgroups per CU; a row with more two-hop
   // candidates makes the counting pass report its count, and both passes rerun with it
   if (w > kX2Q * kT) fail(GB_EUNSUPPORTED, "X2 graph: ELL width %d above %d", w, kX2Q * kT);

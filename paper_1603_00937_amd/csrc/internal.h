@@ -115,6 +115,13 @@ struct WsLease {
 void exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t s);
 void exclusive_scan_i64(const int32_t* in, int64_t* out, int n, hipStream_t s);
 
+// ---- vertex sets in LDS (graph.hip) ----
+// The graph and halo kernels keep vertex sets either as n-bit LDS bitmaps (fast while n is
+// small; LDS grows with n) or as LDS hash sets sorted afterwards (work and LDS independent of
+// n).  Hash sets are used above 2^17 vertices; the environment variable GB_VERTEX_SETS=bitmap
+// or =hash forces one kind (both give the same sets, in the same order).
+bool use_hash_sets(int n);
+
 // ---- graph (graph.hip) ----
 struct Csr {
   int32_t n = 0;

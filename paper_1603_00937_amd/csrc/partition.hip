@@ -3,6 +3,7 @@
 // core adjacent to a core vertex -- ascending.  One workgroup per core builds the halo in an
 // LDS bitmap over all vertices, so the lists come out sorted and duplicate-free.
 #include "internal.h"
+#include "lds_hash.h"
 #include "lds_scan.h"
 
 namespace gbi {
@@ -62,6 +63,74 @@ __global__ __launch_bounds__(kT) void k_halo(int n, const int32_t* __restrict__ 
   }
 }
 
+// The same subgraph lists for any n: the neighbours of the core vertices go into an LDS hash set
+// (2^log2h slots, empty kHashEmpty), the core vertices are dropped while the set is gathered
+// (binary search in the ascending core), and the halo is sorted.  Inserts stop past cap
+// entries (the set keeps room for kT more); such a core reports its count through `overflow`.
+template <int PASS>
+__global__ __launch_bounds__(kT) void k_halo_hash(int n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ col,
+                                                  const int32_t* __restrict__ core_ptr,
+                                                  const int32_t* __restrict__ core_vtx,
+                                                  int cap, int log2h, int log2u,
+                                                  int32_t* __restrict__ cnt,
+                                                  const int32_t* __restrict__ sub_ptr,
+                                                  int32_t* __restrict__ sub_idx,
+                                                  int32_t* __restrict__ overflow) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t count, gathered;
+  const int c = blockIdx.x;
+  const int H = 1 << log2h, P = 1 << log2u;
+  int32_t* keys = reinterpret_cast<int32_t*>(smem);
+  int32_t* U = keys + H;
+  const int c0 = core_ptr[c], c1 = core_ptr[c + 1];
+  for (int q = threadIdx.x; q < H; q += kT) keys[q] = kHashEmpty;
+  if (threadIdx.x == 0) {
+    count = 0;
+    gathered = 0;
+  }
+  __syncthreads();
+  for (int v = c0; v < c1 && *(volatile int32_t*)&count <= cap; ++v) {
+    const int u = core_vtx[v];
+    for (int p = rp[u] + threadIdx.x; p < rp[u + 1]; p += kT) {
+      if (*(volatile int32_t*)&count > cap) break;
+      if (hset_insert(keys, log2h, col[p])) atomicAdd(&count, 1);
+    }
+  }
+  __syncthreads();
+  if (count > cap) {
+    if (threadIdx.x == 0) {
+      atomicMax(overflow, count);
+      if (PASS == 0) cnt[c] = 0;
+    }
+    return;
+  }
+  // gather the set minus the core (ascending: binary search)
+  for (int q = threadIdx.x; q < H; q += kT) {
+    const int32_t k = keys[q];
+    if (k == kHashEmpty) continue;
+    int lo = c0, hi = c1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (core_vtx[mid] < k) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo < c1 && core_vtx[lo] == k) continue;
+    U[atomicAdd(&gathered, 1)] = k;
+  }
+  __syncthreads();
+  const int halo = gathered;
+  if (PASS == 0) {
+    if (threadIdx.x == 0) cnt[c] = (c1 - c0) + halo;
+    return;
+  }
+  for (int r = halo + threadIdx.x; r < P; r += kT) U[r] = INT32_MAX;
+  bitonic_sort<kT>(U, P);
+  const int32_t base = sub_ptr[c];
+  for (int v = c0 + threadIdx.x; v < c1; v += kT) sub_idx[base + (v - c0)] = core_vtx[v];
+  for (int r = threadIdx.x; r < halo; r += kT) sub_idx[base + (c1 - c0) + r] = U[r];
+}
+
 // rank of every subgraph entry in ascending global order: the two sorted runs (core, halo)
 // are merged by binary search of each entry in the other run.
 __global__ void k_sub_pos(int n_sub, const int32_t* __restrict__ core_ptr,
@@ -97,6 +166,8 @@ __global__ void k_col_map(int n_sub, const int32_t* __restrict__ core_ptr,
     col_loc[u] = v - core_ptr[s];
   }
 }
+
+__global__ void k_zero1(int32_t* p) { *p = 0; }
 
 __global__ void k_iota(int32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -397,11 +468,42 @@ void finish_partition(const Csr& g, Part& P, hipStream_t s) {
   const int n = g.n;
   const int n_sub = P.n_sub;
   const int nw = (n + 31) >> 5;
+  const bool hash = use_hash_sets(n);
   const size_t lds = (size_t)nw * 8 + kT * 4 + 64;
-  if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "partition: n = %d too large for one LDS bitmap", n);
+  if (!hash && lds > 160 * 1024)
+    fail(GB_EUNSUPPORTED, "partition: n = %d too large for one LDS bitmap", n);
+  // hash sets: the union of the core's rows, capacity raised to what a core reports (cap + kT
+  // + 1 slots keep inserts that pass cap from filling the set)
+  int cap = 4096, log2h = 0, log2u = 0;
+  size_t lds_h = 0;
+  DBuf<int32_t> ovf(1, s);
+  auto sizes = [&] {
+    log2h = ceil_log2((int64_t)cap + kT + 1);
+    log2u = ceil_log2(cap);
+    lds_h = (((size_t)1 << log2h) + ((size_t)1 << log2u)) * 4 + 64;
+    if (lds_h > 160 * 1024)
+      fail(GB_EUNSUPPORTED, "partition: a core has about %d neighbours, more than LDS holds", cap);
+  };
   DBuf<int32_t> cnt(n_sub, s);
-  hipLaunchKernelGGL(k_halo<0>, dim3(n_sub), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
-                     P.core_ptr.get(), P.core_vtx.get(), cnt.get(), nullptr, nullptr);
+  if (hash) {
+    for (int attempt = 0;; ++attempt) {
+      sizes();
+      int32_t h = 0;
+      hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, s, ovf.get());
+      hipLaunchKernelGGL(k_halo_hash<0>, dim3(n_sub), dim3(kT), lds_h, s, n, g.row_ptr.get(),
+                         g.col.get(), P.core_ptr.get(), P.core_vtx.get(), cap, log2h, log2u,
+                         cnt.get(), nullptr, nullptr, ovf.get());
+      GB_LAUNCH_CHECK();
+      GB_HIP(hipMemcpyAsync(&h, ovf.get(), 4, hipMemcpyDeviceToHost, s));
+      GB_HIP(hipStreamSynchronize(s));
+      if (h == 0) break;
+      if (attempt == 2) fail(GB_EUNSUPPORTED, "partition: neighbour count did not settle");
+      cap = std::max(((h + 255) / 256) * 256, 2 * cap);
+    }
+  } else {
+    hipLaunchKernelGGL(k_halo<0>, dim3(n_sub), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
+                       P.core_ptr.get(), P.core_vtx.get(), cnt.get(), nullptr, nullptr);
+  }
   GB_LAUNCH_CHECK();
   P.sub_ptr = DBuf<int32_t>(n_sub + 1, s);
   exclusive_scan_i32(cnt.get(), P.sub_ptr.get(), n_sub, s);
@@ -414,9 +516,14 @@ void finish_partition(const Csr& g, Part& P, hipStream_t s) {
   for (int c = 0; c < n_sub; ++c)
     P.max_sub = std::max(P.max_sub, P.h_sub_ptr[c + 1] - P.h_sub_ptr[c]);
   P.sub_idx = DBuf<int32_t>(P.total, s);
-  hipLaunchKernelGGL(k_halo<1>, dim3(n_sub), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
-                     P.core_ptr.get(), P.core_vtx.get(), nullptr, P.sub_ptr.get(),
-                     P.sub_idx.get());
+  if (hash)
+    hipLaunchKernelGGL(k_halo_hash<1>, dim3(n_sub), dim3(kT), lds_h, s, n, g.row_ptr.get(),
+                       g.col.get(), P.core_ptr.get(), P.core_vtx.get(), cap, log2h, log2u,
+                       nullptr, P.sub_ptr.get(), P.sub_idx.get(), ovf.get());
+  else
+    hipLaunchKernelGGL(k_halo<1>, dim3(n_sub), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
+                       P.core_ptr.get(), P.core_vtx.get(), nullptr, P.sub_ptr.get(),
+                       P.sub_idx.get());
   GB_LAUNCH_CHECK();
   P.sub_pos = DBuf<int32_t>(P.total, s);
   hipLaunchKernelGGL(k_sub_pos, dim3(n_sub), dim3(kT), 0, s, n_sub, P.core_ptr.get(),

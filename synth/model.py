@@ -61,6 +61,8 @@ CONFIGS = {
     "tiny48": ModelSpec(n_sites=24, density=0.01, seed=7, cutoff=6.0, name="tiny48"),
     "small256": ModelSpec(n_sites=128, density=0.05, seed=3, name="small256"),
     "n4096": ModelSpec(n_sites=2048, seed=5, name="n4096"),
+    # beyond the n-bit LDS bitmaps of the graph and halo kernels (their hash-set paths)
+    "n500000": ModelSpec(n_sites=250000, seed=6, name="n500000"),
 }
 
 _LN2_HI = 6.93147180369123816490e-01   # ln 2 high part, low bits zero

@@ -183,3 +183,61 @@ def test_n100000_multilevel_bf16x6(gb):
     ref, st, err = _run(gb, "n100000", "bf16x6", method="multilevel")
     assert st["converged"]
     assert err <= 1e-6
+
+
+@pytest.mark.parametrize("name,method", [("n18000", "block"), ("n100000", "multilevel")])
+def test_hash_vertex_sets_give_the_same_graph_and_partition(gb, name, method, monkeypatch):
+    """The graph and halo kernels on LDS hash sets (forced here; the default above 2^17
+    vertices) against the oracle's stored graph and partition: bit for bit."""
+    import torch
+    from synth import make_model, ell_sha256
+    ref = _golden(name, method)
+    m = make_model(name)
+    Hc = torch.from_numpy(m["H_col"]).cuda()
+    Hv = torch.from_numpy(m["H_val"]).cuda()
+    monkeypatch.setenv("GB_VERTEX_SETS", "hash")
+    g = gb.build_graph(Hc, Hv, ref["tau"])
+    rp, cl = [t.cpu().numpy() for t in g.arrays()]
+    assert ell_sha256(rp, cl) == ref["graph_sha256"]
+    p = gb.partition(g, ref["core_size"], method=method)
+    cp, sp, si = [t.cpu().numpy() for t in p.arrays()]
+    assert ell_sha256(cp, sp, si) == ref["partition_sha256"]
+
+
+def test_n500000_graph_and_halos_beyond_the_bitmaps(gb):
+    """N = 500000 (250000 sites), past the n-bit LDS bitmaps: the graph rows and subgraphs of
+    sampled cores against the oracle computed row by row, and the graph's symmetry."""
+    import time
+    import torch
+    from synth import make_model
+    from oracle.bounds import gershgorin
+    from oracle.graph import graph_x2
+    m = make_model("n500000")
+    Hc = torch.from_numpy(m["H_col"]).cuda()
+    Hv = torch.from_numpy(m["H_val"]).cuda()
+    emin, emax = gershgorin(m["H_col"], m["H_val"])
+    assert gb.spectral_bounds(Hc, Hv) == (emin, emax)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    g = gb.build_graph(Hc, Hv, 1e-5)
+    p = gb.partition(g, 32)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    rp, cl = [t.cpu().numpy() for t in g.arrays()]
+    cp, sp, si = [t.cpu().numpy() for t in p.arrays()]
+    sizes = np.diff(sp)
+    print(f"n500000: graph nnz {g.nnz}, {len(sizes)} subgraphs of {sizes.min()}..{sizes.max()} "
+          f"vertices, graph + partition {dt * 1e3:.0f} ms")
+    rng = np.random.default_rng(11)
+    for c in rng.choice(len(cp) - 1, size=6, replace=False):
+        verts = np.arange(cp[c], cp[c + 1])
+        rows = graph_x2(m["H_col"], m["H_val"], 1e-5, emin, emax, rows=verts)
+        for v, r in zip(verts, rows):
+            assert np.array_equal(cl[rp[v]:rp[v + 1]], r), v
+        halo = np.setdiff1d(np.unique(np.concatenate(rows)), verts)
+        assert np.array_equal(si[sp[c]:sp[c + 1]], np.concatenate([verts, halo]))
+    # symmetric: the transposed pattern equals the pattern
+    r = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    a = np.sort(r.astype(np.int64) * (len(rp) - 1) + cl)
+    b = np.sort(cl.astype(np.int64) * (len(rp) - 1) + r)
+    assert np.array_equal(a, b)

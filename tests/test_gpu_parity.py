@@ -390,3 +390,21 @@ def test_partition_update_bit_exact(gb, model_cache):
     ocp, ocv, _ = partition_update(rp1, col1, ocp0, ocv0)
     osp, osi = halo_subgraphs(rp1, col1, [ocv[ocp[i]:ocp[i + 1]] for i in range(len(ocp) - 1)])
     assert np.array_equal(cp, ocp) and np.array_equal(sp, osp) and np.array_equal(si, osi)
+
+
+@pytest.mark.parametrize("name,tau,core", [("small256", 1e-5, 16), ("n1024", 1e-5, 16),
+                                           ("tiny48", 1e-2, 5)])
+def test_hash_vertex_sets_bit_exact(gb, model_cache, name, tau, core, monkeypatch):
+    """Graph and halos on LDS hash sets (the kernels past 2^17 vertices) against the oracle."""
+    from oracle.graph import graph_x2
+    from oracle.partition import partition
+    m = model_cache(name)
+    monkeypatch.setenv("GB_VERTEX_SETS", "hash")
+    g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), tau)
+    rp, cl = _host(*g.arrays())
+    orp, ocl = graph_x2(m["H_col"], m["H_val"], tau)
+    assert np.array_equal(rp, orp) and np.array_equal(cl, ocl)
+    p = gb.partition(g, core)
+    cp, sp, si = _host(*p.arrays())
+    ocp, ocv, osp, osi = partition(orp, ocl, core, "block")
+    assert np.array_equal(cp, ocp) and np.array_equal(sp, osp) and np.array_equal(si, osi)
