@@ -659,6 +659,11 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
     # replay has none)
     avg_launch_s = (sq_ms / sq_n / 1e3) if (sq_n and sq_ms > 0) else None
     achieved = flops_alg / avg_launch_s / 1e12 if avg_launch_s else None
+    # the matrix-core rate this device sustains on register operands in the kernel's input
+    # type (the library's own MFMA chains): what the executed rate is read against
+    mfma_kind = {"fp64": "fp64", "fp32": "fp32", "fp16x3": "fp16"}.get(precision, "bf16")
+    sustained = gb.peak_rate(mfma_kind)
+    exec_rate = flops_exec / avg_launch_s / 1e12 if avg_launch_s else None
     return {
         "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
@@ -684,8 +689,9 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
                      "kernel": square_kernel_name(precision, stats),
                      "flops_per_launch_alg": flops_alg, "flops_per_launch_exec": flops_exec,
                      "flops_per_launch_dense_2n3": flops_dense,
-                     "exec_frac": (flops_exec / avg_launch_s / 1e12 / peak) if avg_launch_s
-                     else None,
+                     "exec_frac": exec_rate / peak if exec_rate else None,
+                     "sustained_mfma_peak": sustained, "sustained_mfma_kind": mfma_kind,
+                     "exec_frac_of_sustained": exec_rate / sustained if exec_rate else None,
                      "avg_launch_ms": avg_launch_s * 1e3 if avg_launch_s else None,
                      "launches": sq_n},
         "accuracy": {"converged": stats["converged"], "trace_D": stats["trace"],

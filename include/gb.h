@@ -59,6 +59,14 @@ gb_status gb_trim(void);
 gb_status gb_tune_save(const char* path, int32_t* n_entries);
 gb_status gb_tune_load(const char* path, int32_t* n_entries);
 
+/* Rate this device sustains, measured by the library's own kernels (the measured denominators
+ * of the squaring kernels' rooflines, beside the datasheet figures): kind 0 / 1 / 2 / 3 = dense
+ * matrix-core TFLOP/s in FP64 (16x16x4), FP32 (16x16x4), bf16 (16x16x32) or fp16 (16x16x32)
+ * from eight independent accumulation chains per wave on register operands over 8 workgroups
+ * per CU (no memory traffic); kind 4 = HBM GB/s (bytes read + written) of a 2 GiB streaming
+ * copy.  One warm-up launch, then five timed.  Synchronises `stream`. */
+gb_status gb_peak_rate(int32_t kind, void* stream, double* rate);
+
 /* Library version string (static storage). */
 const char* gb_version(void);
 /* Message for the last failing call on this thread ("" if none). */
@@ -277,12 +285,12 @@ typedef struct {
                               * 2: as 0 with two steps captured in a hipGraph and replayed;   *
                               * 3: batched launches, every decision read back by the host.    *
                               * keep_tape and refine_kind 1 run their steps as in 3.          */
-  int32_t tile_policy;       /* FP64 / FP32 squares: kernel variant autotuned per 256-wide    *
-                              * size bucket (0, timed once per process), 1 = 128-edge tiles,  *
-                              * 2 = 64-edge, 4 = 64-edge with three LDS stages, 5 = 64-edge   *
-                              * with register-staged loads;                                   *
-                              * split squares (bf16, fp16 planes) have one kernel and ignore *
-                              * it.  3 is taken as 0.                                         */
+  int32_t tile_policy;       /* kernel variant of the squares: autotuned per 256-wide size   *
+                              * bucket (0, timed once per process or read from the tuning    *
+                              * table), 1 = 128-edge tiles, 2 = 64-edge; FP64 / FP32 squares *
+                              * also 4 = 64-edge with three LDS stages, 5 = 64-edge with      *
+                              * register-staged loads.  Values a precision has no kernel for  *
+                              * (4 and 5 for split squares) are taken as 0, as 3 is by all.   */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
   int32_t check_idem;        /* 1: also compute stats.idem_max, max |X^2 - X| over the core   *
                               *    columns (one more square of the core tiles, or nine slab  *

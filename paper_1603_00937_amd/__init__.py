@@ -8,5 +8,5 @@ from .api import (  # noqa: F401
     density_with_grad, version, TorchAllocator, set_allocator, foe_density, chebyshev_fermi,
     foe_solve_mu, sp2_sequence, sp2_estimate_gap, gap_inputs, build_graph_rcut, trim,
     partition_host, partition_update, partition_update_host, density_workspace,
-    spectral_bounds_noalloc, tune_save, tune_load,
+    spectral_bounds_noalloc, tune_save, tune_load, peak_rate,
 )

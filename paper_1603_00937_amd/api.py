@@ -104,6 +104,20 @@ def set_allocator(allocator):
     _check(_lib().gb_set_allocator(allocator._alloc_fn, allocator._free_fn, None))
 
 
+# kernel variant names of gb_sp2_opts.tile_policy
+TILE_POLICIES = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5}
+
+PEAK_KINDS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "hbm": 4}
+
+
+def peak_rate(kind) -> float:
+    """Rate this device sustains by the library's own kernels: matrix-core TFLOP/s for "fp64",
+    "fp32", "bf16", "fp16"; HBM GB/s (read + written) for "hbm"."""
+    r = ctypes.c_double()
+    _check(_lib().gb_peak_rate(PEAK_KINDS.get(kind, -1), _stream(), ctypes.byref(r)))
+    return r.value
+
+
 def tune_save(path) -> int:
     """Write the autotuner's table (JSON, tagged with the library build and device)."""
     n = ctypes.c_int32()
@@ -342,8 +356,7 @@ def _sp2_opts(precision="fp64", n_refine=0, max_iter=0, idem_tol=0.0, part=None,
     o.keep_tape = 1 if keep_tape else 0
     o.tape_stride = int(tape_stride)
     o.launch_mode = L.LAUNCH_MODES.get(launch_mode, launch_mode)
-    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4,
-                     "64r": 5}.get(tile_policy, tile_policy)
+    o.tile_policy = TILE_POLICIES.get(tile_policy, tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     o.check_idem = 1 if check_idem else 0
     return o
@@ -481,8 +494,7 @@ def foe_density(H_col, H_val, n_occ, threshold, beta, order, mu=None, partition=
     o.core_size = int(core_size)
     if emin is not None and emax is not None:
         o.emin, o.emax = float(emin), float(emax)
-    o.tile_policy = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5}.get(
-        tile_policy, tile_policy)
+    o.tile_policy = TILE_POLICIES.get(tile_policy, tile_policy)
     o.tile_order = {"xcd": 0, "plain": 1}[tile_order]
     tr = (ctypes.c_double * (int(order) + 1))()
     o.traces = ctypes.cast(tr, ctypes.c_void_p)

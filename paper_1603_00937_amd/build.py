@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["api.hip", "scan.hip", "graph.hip", "partition.hip", "mlpart.hip", "sp2.hip"]
+SOURCES = ["api.hip", "scan.hip", "graph.hip", "partition.hip", "mlpart.hip", "sp2.hip", "peak.hip"]
 LIB = os.path.join(HERE, "libgb.so")
 
 

@@ -307,6 +307,14 @@ gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx) {
   });
 }
 
+gb_status gb_peak_rate(int32_t kind, void* stream, double* rate) {
+  return guarded([&] {
+    if (!rate) fail(GB_EINVAL, "rate is NULL");
+    if (kind < 0 || kind > 4) fail(GB_EINVAL, "unknown kind %d", kind);
+    *rate = peak_rate(kind, as_stream(stream));
+  });
+}
+
 gb_status gb_tune_save(const char* path, int32_t* n_entries) {
   return guarded([&] {
     if (!path || !*path) fail(GB_EINVAL, "path is NULL or empty");

@@ -79,3 +79,16 @@ def test_idempotency_check_is_optional(gb, model_cache):
         assert a[2]["branch"] == b[2]["branch"]
         assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
         assert a[2]["n_near_tie"] == 0
+
+
+def test_sustained_rates_are_plausible(gb):
+    """The library's own matrix-core and HBM rates: within the datasheet figures, and ordered
+    as the units are (bf16/fp16 > FP32 > FP64)."""
+    r = {k: gb.peak_rate(k) for k in ("fp64", "fp32", "bf16", "fp16", "hbm")}
+    print("sustained:", {k: round(v, 1) for k, v in r.items()})
+    assert 10 < r["fp64"] <= 78.6 * 1.1 and 20 < r["fp32"] <= 157.3 * 1.1
+    assert 200 < r["bf16"] <= 2500 * 1.1 and 200 < r["fp16"] <= 2500 * 1.1
+    assert r["bf16"] > r["fp32"] > r["fp64"]
+    assert 1000 < r["hbm"] <= 8000 * 1.1
+    with pytest.raises(gb.GbError):
+        gb.peak_rate("int8")
