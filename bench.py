@@ -1,11 +1,13 @@
 """Throughput of the graph-partitioned SP2 density matrix on one MI355X.
 
-One step = the whole hot path on one synthetic system already resident in HBM: X2 graph,
-block partition with halos, gather, batched SP2 squarings with the FP64 trace/branch
-decision, refinement (mixed precision), scatter into column-ELL D.  Prints one JSON line.
+One step = the whole hot path on one synthetic system already resident in HBM: spectral
+bounds, X2 graph, cores with halos, gather, batched SP2 squarings with the FP64 trace/branch
+decision, FP64 refinement (mixed precision), scatter into column-ELL D.  Prints one JSON line:
+the headline precision (default: two fp16 planes, three products), the other split method and
+the FP64 path beside it, the roofline of the squaring kernel and the CPU oracle on a sample.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|fp32]
-                  [--workload n18000|n1024] [--no-cpu-baseline]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp16x3|bf16x6|fp32|fp64]
+                  [--workload n18000|n100000|n1024] [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -22,11 +24,11 @@ METRIC = "orbitals/s of D at ≤1e-6 err vs FP64 oracle; mixed vs FP64 GPU; X² 
 # dense matrix-core peaks of the precision the dominant squaring kernel runs in (TFLOP/s)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "bf16x6": 2500.0,
                "fp16x3": 2500.0}
-# bf16 plane products per algorithmic multiply-add
+# plane products per algorithmic multiply-add of the split squares
 PLANE_PRODUCTS = {"bf16": 1, "bf16x3": 3, "bf16x6": 6, "fp16x3": 3}
 # default cores per workload: the faster of the two partitions as measured on one MI355X
-# (multilevel communities pay for their host partitioner at N = 18000, not at N = 1024, where it
-# takes a third of the step, nor at N = 100000, where it takes 0.3 s)
+# (multilevel communities pay for their partitioner at N = 18000 and N = 100000, not at
+# N = 1024, where it would take a large share of a 10 ms step)
 WORKLOADS = {"n18000": dict(tau=1e-5, core=32, partition="multilevel"),
              "n1024": dict(tau=1e-5, core=16, partition="block"),
              "n100000": dict(tau=1e-5, core=32, partition="multilevel")}
@@ -469,7 +471,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16x6",
+    ap.add_argument("--precision", default="fp16x3",
                     choices=["fp64", "fp32", "bf16", "bf16x3", "bf16x6", "fp16x3"])
     ap.add_argument("--launch-mode", default="device",
                     choices=["device", "per_subgraph", "graph", "host"])
@@ -561,14 +563,16 @@ def main():
         dcf, dvf = D[0].cpu().numpy(), D[1].cpu().numpy()
         out["fp64_gpu"] = {k: ref[k] for k in ("value", "ms_per_step", "roofline", "accuracy")}
         out["speedup_vs_fp64_gpu"] = out["value"] / ref["value"]
-    # the two-plane fp16 split (three products) beside the headline split-bf16 run
+    # the other split method beside the headline run: three bf16 planes (six products) beside
+    # two fp16 planes (three products), and the reverse
     ext = None
-    if args.precision == "bf16x6" and not args.no_fp64_compare:
-        ext = measure(gb, torch, args, "fp16x3", model, cfg, Hc, Hv, D, golden, sizes)
+    alt = {"fp16x3": "bf16x6", "bf16x6": "fp16x3"}.get(args.precision)
+    if alt and not args.no_fp64_compare:
+        ext = measure(gb, torch, args, alt, model, cfg, Hc, Hv, D, golden, sizes)
         dce, dve = D[0].cpu().numpy(), D[1].cpu().numpy()
-        out["fp16x3_gpu"] = {k: ext[k] for k in ("value", "ms_per_step", "dtype", "roofline",
-                                                   "accuracy")}
-        out["fp16x3_gpu"]["speedup_vs_fp64_gpu"] = ext["value"] / out["fp64_gpu"]["value"]
+        out[alt + "_gpu"] = {k: ext[k] for k in ("value", "ms_per_step", "dtype", "roofline",
+                                                  "accuracy")}
+        out[alt + "_gpu"]["speedup_vs_fp64_gpu"] = ext["value"] / out["fp64_gpu"]["value"]
     ref_cols = None
     if golden and not args.no_cpu_baseline:
         out["cpu_baseline"], ref_cols = cpu_baseline(model, args.workload, golden,
@@ -589,7 +593,7 @@ def main():
             out["fp64_gpu"]["accuracy"]["vs_oracle_subgraphs"] = d_errors(dcf, dvf, ref_cols)
             out["fp64_gpu"]["accuracy"]["idempotency_D"] = idempotency(dcf, dvf, idem_cols)
     if ext is not None:
-        ea = out["fp16x3_gpu"]["accuracy"]
+        ea = out[alt + "_gpu"]["accuracy"]
         if ref_cols is not None:
             ea["vs_oracle_subgraphs"] = d_errors(dce, dve, ref_cols)
         d = dve - dvf
@@ -662,7 +666,7 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
     # the matrix-core rate this device sustains on register operands in the kernel's input
     # type (the library's own MFMA chains): what the executed rate is read against
     mfma_kind = {"fp64": "fp64", "fp32": "fp32", "fp16x3": "fp16"}.get(precision, "bf16")
-    sustained = gb.peak_rate(mfma_kind)
+    sustained, clock_mhz = gb.peak_rate(mfma_kind, with_clock=True)
     exec_rate = flops_exec / avg_launch_s / 1e12 if avg_launch_s else None
     return {
         "metric": METRIC, "value": N / dt, "unit": "orbitals/s", "n_gpus": 1,
@@ -691,6 +695,7 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
                      "flops_per_launch_dense_2n3": flops_dense,
                      "exec_frac": exec_rate / peak if exec_rate else None,
                      "sustained_mfma_peak": sustained, "sustained_mfma_kind": mfma_kind,
+                     "sustained_mfma_clock_mhz": clock_mhz,
                      "exec_frac_of_sustained": exec_rate / sustained if exec_rate else None,
                      "avg_launch_ms": avg_launch_s * 1e3 if avg_launch_s else None,
                      "launches": sq_n},

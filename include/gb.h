@@ -63,9 +63,12 @@ gb_status gb_tune_load(const char* path, int32_t* n_entries);
  * of the squaring kernels' rooflines, beside the datasheet figures): kind 0 / 1 / 2 / 3 = dense
  * matrix-core TFLOP/s in FP64 (16x16x4), FP32 (16x16x4), bf16 (16x16x32) or fp16 (16x16x32)
  * from eight independent accumulation chains per wave on register operands over 8 workgroups
- * per CU (no memory traffic); kind 4 = HBM GB/s (bytes read + written) of a 2 GiB streaming
- * copy.  One warm-up launch, then five timed.  Synchronises `stream`. */
-gb_status gb_peak_rate(int32_t kind, void* stream, double* rate);
+ * per CU (no memory traffic); kind 5 / 6 = bf16 / fp16 on the 32x32x16 instruction; kind 4 =
+ * HBM GB/s (bytes read + written) of a 2 GiB streaming copy.  One warm-up launch, then five timed.  clock_mhz (host, may be NULL) receives the mean
+ * core clock of the last MFMA launch's workgroups (core cycles over constant-rate wall-clock
+ * ticks; 0 for kind 4): the clock the matrix cores ran at under that load.  GB_EINVAL for an
+ * unknown kind or a NULL rate.  Synchronises `stream`. */
+gb_status gb_peak_rate(int32_t kind, void* stream, double* rate, double* clock_mhz);
 
 /* Library version string (static storage). */
 const char* gb_version(void);

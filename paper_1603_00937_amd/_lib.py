@@ -124,7 +124,8 @@ SIGNATURES = {
     "gb_partition_destroy": (None, [_vp]),
     "gb_set_allocator": (ctypes.c_int32, [ALLOC_FN, FREE_FN, _vp]),
     "gb_trim": (ctypes.c_int32, []),
-    "gb_peak_rate": (ctypes.c_int32, [ctypes.c_int32, _vp, _P(ctypes.c_double)]),
+    "gb_peak_rate": (ctypes.c_int32, [ctypes.c_int32, _vp, _P(ctypes.c_double),
+                                      _P(ctypes.c_double)]),
     "gb_tune_save": (ctypes.c_int32, [ctypes.c_char_p, _P(ctypes.c_int32)]),
     "gb_tune_load": (ctypes.c_int32, [ctypes.c_char_p, _P(ctypes.c_int32)]),
     "gb_density": (ctypes.c_int32, [_P(GbEll), ctypes.c_int32, ctypes.c_double, _P(GbSp2Opts),

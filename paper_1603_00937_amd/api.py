@@ -107,15 +107,19 @@ def set_allocator(allocator):
 # kernel variant names of gb_sp2_opts.tile_policy
 TILE_POLICIES = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5}
 
-PEAK_KINDS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "hbm": 4}
+PEAK_KINDS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "hbm": 4, "bf16_32x32": 5,
+              "fp16_32x32": 6}
 
 
-def peak_rate(kind) -> float:
+def peak_rate(kind, with_clock=False):
     """Rate this device sustains by the library's own kernels: matrix-core TFLOP/s for "fp64",
-    "fp32", "bf16", "fp16"; HBM GB/s (read + written) for "hbm"."""
-    r = ctypes.c_double()
-    _check(_lib().gb_peak_rate(PEAK_KINDS.get(kind, -1), _stream(), ctypes.byref(r)))
-    return r.value
+    "fp32", "bf16", "fp16" (16 x 16 instructions), "bf16_32x32", "fp16_32x32"; HBM GB/s (read +
+    written) for "hbm".  with_clock: also the mean
+    core clock (MHz) during the matrix-core loop, as (rate, clock)."""
+    r, c = ctypes.c_double(), ctypes.c_double()
+    _check(_lib().gb_peak_rate(PEAK_KINDS.get(kind, -1), _stream(), ctypes.byref(r),
+                               ctypes.byref(c)))
+    return (r.value, c.value) if with_clock else r.value
 
 
 def tune_save(path) -> int:

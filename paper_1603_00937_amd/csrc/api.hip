@@ -307,11 +307,11 @@ gb_status gb_set_allocator(gb_alloc_fn alloc, gb_free_fn free_fn, void* ctx) {
   });
 }
 
-gb_status gb_peak_rate(int32_t kind, void* stream, double* rate) {
+gb_status gb_peak_rate(int32_t kind, void* stream, double* rate, double* clock_mhz) {
   return guarded([&] {
     if (!rate) fail(GB_EINVAL, "rate is NULL");
-    if (kind < 0 || kind > 4) fail(GB_EINVAL, "unknown kind %d", kind);
-    *rate = peak_rate(kind, as_stream(stream));
+    if (kind < 0 || kind > 6) fail(GB_EINVAL, "unknown kind %d", kind);
+    *rate = peak_rate(kind, as_stream(stream), clock_mhz);
   });
 }
 

@@ -116,8 +116,9 @@ void exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t s);
 void exclusive_scan_i64(const int32_t* in, int64_t* out, int n, hipStream_t s);
 
 // ---- sustained rates (peak.hip): TFLOP/s of MFMA kind 0 FP64, 1 FP32, 2 bf16, 3 fp16; GB/s of
-// an HBM copy for kind 4 (read + written bytes) ----
-double peak_rate(int kind, hipStream_t s);
+// an HBM copy for kind 4 (read + written bytes); clock_mhz (may be NULL): the core clock during
+// the MFMA loop (0 for kind 4) ----
+double peak_rate(int kind, hipStream_t s, double* clock_mhz);
 
 // ---- vertex sets in LDS (graph.hip) ----
 // The graph and halo kernels keep vertex sets either as n-bit LDS bitmaps (fast while n is

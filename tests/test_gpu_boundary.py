@@ -90,5 +90,9 @@ def test_sustained_rates_are_plausible(gb):
     assert 200 < r["bf16"] <= 2500 * 1.1 and 200 < r["fp16"] <= 2500 * 1.1
     assert r["bf16"] > r["fp32"] > r["fp64"]
     assert 1000 < r["hbm"] <= 8000 * 1.1
+    rate, mhz = gb.peak_rate("bf16", with_clock=True)
+    print(f"bf16 loop: {rate:.0f} TFLOP/s at {mhz:.0f} MHz")
+    # the datasheet peak is quoted at 2400 MHz: the rate per MHz bounds it
+    assert 300 < mhz <= 2600 and rate / mhz <= 2500 / 2400 * 1.1
     with pytest.raises(gb.GbError):
         gb.peak_rate("int8")

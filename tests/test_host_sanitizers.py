@@ -17,8 +17,9 @@ pytestmark = pytest.mark.slow
 def _build_and_run(tmp_path, sanitizers):
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
-    from paper_1603_00937_amd.build import SOURCES, hipcc_flags
-    srcs = [os.path.join(ROOT, "paper_1603_00937_amd", "csrc", s) for s in SOURCES]
+    from paper_1603_00937_amd.build import SOURCES, PROBE_SOURCES, hipcc_flags
+    srcs = [os.path.join(ROOT, "paper_1603_00937_amd", "csrc", s)
+            for s in SOURCES + PROBE_SOURCES]
     flags = [f for f in hipcc_flags() if f not in ("-shared", "-fPIC", "-O3")] + ["-O1", "-g"]
     san = []
     for s in sanitizers:
