@@ -790,13 +790,15 @@ __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64
   for (int64_t p = i; p < n; p += stride) out[p] = (TO)in[p];
 }
 
-// FP64 copy of an FP32 iterate made exactly symmetric: out = (X + X^T)/2 per block.  The
-// split-bf16 square computes both triangles of its diagonal tiles, pairing the planes of an
-// entry and of its transpose differently, so the FP32 iterate is symmetric only to rounding;
-// the FP64 refinement relies on symmetry.  One workgroup per 64x64 tile, the tile and its
-// transpose partner through LDS.
+// An FP32 iterate made exactly symmetric: out = (X + X^T)/2 per block, formed in FP64 and
+// stored as TO (FP32: rounded once; the workgroups of a tile and of its transpose round the
+// same sum, so out stays exactly symmetric).  The split squares compute both triangles of
+// their diagonal tiles, pairing the planes of an entry and of its transpose differently, so
+// the FP32 iterate is symmetric only to rounding; the FP64 refinement relies on symmetry.  One
+// workgroup per 64x64 tile, the tile and its transpose partner through LDS.
+template <typename TO>
 __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X,
-                                                     double* __restrict__ out,
+                                                     TO* __restrict__ out,
                                                      const int64_t* __restrict__ offs,
                                                      const int32_t* __restrict__ npad) {
   __shared__ float ta[64][65], tb[64][65];
@@ -812,10 +814,11 @@ __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X
     tb[r][c] = xs[(int64_t)(bj * 64 + r) * np + bi * 64 + c];
   }
   __syncthreads();
-  double* os = out + offs[s];
+  TO* os = out + offs[s];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
-    os[(int64_t)(bi * 64 + r) * np + bj * 64 + c] = 0.5 * ((double)ta[r][c] + (double)tb[c][r]);
+    os[(int64_t)(bi * 64 + r) * np + bj * 64 + c] =
+        (TO)(0.5 * ((double)ta[r][c] + (double)tb[c][r]));
   }
 }
 
@@ -889,8 +892,8 @@ __global__ __launch_bounds__(kT) void k_idem(const T* __restrict__ X, const T* _
 // on one XCD (workgroup i goes to XCD i mod 8), which fetches V into its L2 once.  Rows of V
 // beyond k_s are read in bounds (row k_s - 1) and zeroed by a select, keeping the loop free of
 // branches.  Output register r of lane l holds row 4r + q of its tile.
-template <int KMAX>
-__global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
+template <int KMAX, typename TX>
+__global__ __launch_bounds__(256) void k_rows_mm(const TX* __restrict__ X,
                                                  const int64_t* __restrict__ offs,
                                                  const int32_t* __restrict__ npad,
                                                  const double* __restrict__ V,
@@ -922,7 +925,7 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
     roff[m] = (int64_t)min(m * 16 + i16, k - 1) * np;
   }
   const double* vb = V + soffs[s] + 4 * kq;
-  const double* xb = X + offs[s] + (int64_t)(4 * kq) * np + cw + 2 * i16;
+  const TX* xb = X + offs[s] + (int64_t)(4 * kq) * np + cw + 2 * i16;
   for (int a0 = 0; a0 < np; a0 += 16) {  // np is a multiple of 64
     double fa[U][MT], fb[U][NT];
 #pragma unroll
@@ -938,9 +941,15 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
     for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int g = 0; g < 2; ++g) {
-        const double2 xv = *reinterpret_cast<const double2*>(xb + (int64_t)(a0 + u) * np + 32 * g);
-        fb[u][2 * g] = xv.x;
-        fb[u][2 * g + 1] = xv.y;
+        if constexpr (std::is_same<TX, double>::value) {
+          const double2 xv = *reinterpret_cast<const double2*>(xb + (int64_t)(a0 + u) * np + 32 * g);
+          fb[u][2 * g] = xv.x;
+          fb[u][2 * g + 1] = xv.y;
+        } else {  // an FP32 X (exact in FP64): half the bytes per product
+          const float2 xv = *reinterpret_cast<const float2*>(xb + (int64_t)(a0 + u) * np + 32 * g);
+          fb[u][2 * g] = (double)xv.x;
+          fb[u][2 * g + 1] = (double)xv.y;
+        }
       }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -965,7 +974,8 @@ __global__ __launch_bounds__(256) void k_rows_mm(const double* __restrict__ X,
 }
 
 // W = the first k_s rows of X (= E X for the core unit rows E)
-__global__ __launch_bounds__(256) void k_rows_copy(const double* __restrict__ X,
+template <typename TX>
+__global__ __launch_bounds__(256) void k_rows_copy(const TX* __restrict__ X,
                                                    const int64_t* __restrict__ offs,
                                                    const int32_t* __restrict__ npad,
                                                    double* __restrict__ W,
@@ -975,7 +985,7 @@ __global__ __launch_bounds__(256) void k_rows_copy(const double* __restrict__ X,
   const int np = npad[s], k = core_ptr[s + 1] - core_ptr[s];
   const int64_t n = (int64_t)k * np;
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
-    W[soffs[s] + p] = X[offs[s] + p];
+    W[soffs[s] + p] = (double)X[offs[s] + p];
 }
 
 // out = a x + b y over a whole slab (flat)
@@ -1899,14 +1909,15 @@ struct RowsCtx {
   const int64_t* offs;
   const int32_t* npad;
   hipStream_t s;
-  void mm(const double* X, const double* V, double* W) const {
+  template <typename TX>
+  void mm(const TX* X, const double* V, double* W) const {
     const dim3 grid(cr.colblocks * ((pl.n_sub + 7) / 8 * 8));
     if (cr.kmax == 16)
-      hipLaunchKernelGGL(k_rows_mm<16>, grid, dim3(256), 0, s, X, offs, npad, V, W, cr.soffs.get(),
-                         P.core_ptr.get(), pl.n_sub, cr.colblocks);
+      hipLaunchKernelGGL((k_rows_mm<16, TX>), grid, dim3(256), 0, s, X, offs, npad, V, W,
+                         cr.soffs.get(), P.core_ptr.get(), pl.n_sub, cr.colblocks);
     else
-      hipLaunchKernelGGL(k_rows_mm<32>, grid, dim3(256), 0, s, X, offs, npad, V, W, cr.soffs.get(),
-                         P.core_ptr.get(), pl.n_sub, cr.colblocks);
+      hipLaunchKernelGGL((k_rows_mm<32, TX>), grid, dim3(256), 0, s, X, offs, npad, V, W,
+                         cr.soffs.get(), P.core_ptr.get(), pl.n_sub, cr.colblocks);
     GB_LAUNCH_CHECK();
   }
   void lin2(double* out, double a, const double* x, double b, const double* y) const {
@@ -1915,7 +1926,8 @@ struct RowsCtx {
     GB_LAUNCH_CHECK();
   }
   // out = V p(X) (out may be V); t0, t1 scratch slabs
-  void apply_p(const double* X, const double* V, double* out, double* t0, double* t1) const {
+  template <typename TX>
+  void apply_p(const TX* X, const double* V, double* out, double* t0, double* t1) const {
     mm(X, V, t0);
     mm(X, t0, t1);
     mm(X, t1, t0);
@@ -1997,6 +2009,11 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   double* sd = S64;
   int it_end = 0;
   bool done = false;  // the FP64 steps before a low-precision loop already converged
+  // After a low-precision loop: its iterate made exactly symmetric in FP32 (what the core-row
+  // refinement reads), and an FP64 copy of it in xd only where whole blocks are refined,
+  // checked or scattered (ensure_xd).
+  const float* xs = nullptr;
+  bool xd_ready = true;
   if (low) {
     float* xf = ws->get<float>(3, pl.total, s);
     float* sf = ws->get<float>(4, pl.total, s);
@@ -2048,12 +2065,14 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
         it_end = sp2_loop<float>(xf, sf, pl, tiles, offs, npad, P, n_occ, tol_lo, max_iter,
                                  o.branch_in, o.n_branch_in, true, it_end, st, recs, s, &stop_kind,
                                  nullptr, planes, o.launch_mode == 1);
-      // the final low-precision square was only the stop test: continue from X in FP64, made
-      // exactly symmetric (every block is padded to a multiple of 64)
+      // the final low-precision square was only the stop test: continue from X made exactly
+      // symmetric, in FP32 (every block is padded to a multiple of 64)
       const int max_nt = pl.max_npad / 64;
-      hipLaunchKernelGGL(k_sym_convert, dim3(max_nt * max_nt, pl.n_sub), dim3(256), 0, s, xf, xd,
-                         offs.get(), npad.get());
+      hipLaunchKernelGGL(k_sym_convert<float>, dim3(max_nt * max_nt, pl.n_sub), dim3(256), 0, s,
+                         xf, sf, offs.get(), npad.get());
       GB_LAUNCH_CHECK();
+      xs = sf;
+      xd_ready = false;
     }
     GB_HIP(hipEventRecord(t_sp2.b, s));
   } else {
@@ -2100,6 +2119,13 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   // its own tile edge)
   // (after split squares the plan holds the split's tile edges; FP64 squares on whole blocks --
   // the refinement's fallback, refine_kind 1 and 2 -- tune their own variant when they run)
+  auto ensure_xd = [&] {
+    if (xd_ready) return;
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT),
+                       0, s, xs, xd, pl.total);
+    GB_LAUNCH_CHECK();
+    xd_ready = true;
+  };
   auto fp64_tiles_for_blocks = [&] {
     if (low && planes > 0)
       choose_tiles<double>(P, pl, xd, sd, tiles, offs.get(), s, 0, 0, st, xcd, 0, false);
@@ -2121,10 +2147,10 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     // tolerance, evaluated on the core rows only, then the stop test on them; if it fails,
     // whole-block steps from the same X.
     bool refined = false;
-    if (o.refine_kind == 0 && core_rows_plan(P, pl, cr, s)) {
+    if (o.refine_kind == 0 && xs && core_rows_plan(P, pl, cr, s)) {
       DBuf<double> part(2 * (size_t)pl.n_sub, s);
       StepRec r;
-      hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, offs.get(),
+      hipLaunchKernelGGL(k_trace_rows<float>, dim3(pl.n_sub), dim3(kT), 0, s, xs, offs.get(),
                          npad.get(), P.core_ptr.get(), part.get(), nullptr);
       hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, (double)n_occ,
                          tol, 2, 0, recs.get());
@@ -2140,15 +2166,15 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
                *t1 = sl + 4 * cr.total;
         const RowsCtx rc{cr, pl, P, offs.get(), npad.get(), s};
         // E p(X) = 3 E X^2 - 2 E X^3 (E X: the first k rows of X)
-        hipLaunchKernelGGL(k_rows_copy, dim3(cr.colblocks * 4, pl.n_sub), dim3(256), 0, s, xd,
-                           offs.get(), npad.get(), t0, cr.soffs.get(), P.core_ptr.get());
+        hipLaunchKernelGGL(k_rows_copy<float>, dim3(cr.colblocks * 4, pl.n_sub), dim3(256), 0, s,
+                           xs, offs.get(), npad.get(), t0, cr.soffs.get(), P.core_ptr.get());
         GB_LAUNCH_CHECK();
-        rc.mm(xd, t0, t1);
-        rc.mm(xd, t1, t0);
+        rc.mm(xs, t0, t1);
+        rc.mm(xs, t1, t0);
         rc.lin2(y, 3.0, t1, -2.0, t0);
         if (m == 2) {  // E p(p(X)) = 3 E p(X)^2 - 2 E p(X)^3
-          rc.apply_p(xd, y, s1, t0, t1);
-          rc.apply_p(xd, s1, s2, t0, t1);
+          rc.apply_p(xs, y, s1, t0, t1);
+          rc.apply_p(xs, s1, s2, t0, t1);
           rc.lin2(y, 3.0, s1, -2.0, s2);
         }
         hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, y,
@@ -2162,12 +2188,12 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
         if (r2.e <= tol) {
           // the check's square: Z = Y P(X) (P = p or p o p), the core rows of D^2 (nine more
           // slab products; only when the max-norm check is asked for)
-          if (o.check_idem) rc.apply_p(xd, y, s1, t0, t1);
+          if (o.check_idem) rc.apply_p(xs, y, s1, t0, t1);
           if (o.check_idem && m == 2) {
-            rc.apply_p(xd, s1, s2, t0, t1);
-            rc.mm(xd, s2, t0);
-            rc.mm(xd, t0, t1);
-            rc.mm(xd, t1, t0);
+            rc.apply_p(xs, s1, s2, t0, t1);
+            rc.mm(xs, s2, t0);
+            rc.mm(xs, t0, t1);
+            rc.mm(xs, t1, t0);
             rc.lin2(s1, 3.0, s2, -6.0, t1);  // 3 A2 - 2 (3 A2 X^2 - 2 A2 X^3)
             rc.lin2(s1, 1.0, s1, 4.0, t0);
           }
@@ -2189,6 +2215,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       // Whole blocks: X^2 = S, then 3S - 2 S X (S and X commute, so S X is computed on upper
       // tiles and mirrored); steps repeat until the FP64 stop test holds (at most n_refine,
       // default 8).
+      ensure_xd();
       fp64_tiles_for_blocks();
       DBuf<double> part(2 * (size_t)pl.n_sub, s);
       double* td = ws->get<double>(2, pl.total, s);
@@ -2215,6 +2242,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     }
   } else if (low) {
     // FP64 refinement: SP2 steps with FP64 traces from where the FP32 loop stopped
+    ensure_xd();
     fp64_tiles_for_blocks();
     const uint8_t* bin = nullptr;
     int nbin = 0;
@@ -2250,6 +2278,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   // upper tiles in tile rows below the core size), then max |X^2 - X| over the core rows
   // (after the core-row refinement the core rows of X and X^2 are already there)
   // (only with check_idem: the trace-based FP64 stop test above is the default check)
+  if (!rows_final) ensure_xd();
   const double* xfin = rows_final ? rows_final : xd;
   const int64_t* foffs = rows_final ? cr.soffs.get() : offs.get();
   DBuf<int4> idem_tiles;
