@@ -61,6 +61,8 @@ def square_kernel_name(precision, stats):
     if precision.startswith("bf16") or precision == "fp16x3":
         planes = {"bf16": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 2}[precision]
         edge = 64 if stats["n_tile64"] == stats["n_sub"] else 128
+        if precision == "fp16x3" and 2 * stats.get("n_split_il", 0) > stats["n_sub"]:
+            return f"k_symm_mm_split_il<{edge}>"
         return f"k_symm_mm_split<{planes}, {'true' if precision == 'fp16x3' else 'false'}, {edge}>"
     t = "double" if precision == "fp64" else "float"
     if stats.get("n_stage3", 0) == stats["n_sub"]:
@@ -478,7 +480,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--traffic-from-pmc", default=None,
                     help="per-launch HBM bytes from a directory of rocprofv3 --pmc runs")
-    ap.add_argument("--tile-policy", default="auto", choices=["auto", "128", "64", "64s3", "64r"])
+    ap.add_argument("--tile-policy", default="auto",
+                    choices=["auto", "128", "64", "64s3", "64r", "128i", "64i"])
     ap.add_argument("--tile-order", default="xcd", choices=["xcd", "plain"])
     ap.add_argument("--refine", default="mcweeny", choices=["mcweeny", "sp2", "mcweeny_blocks"])
     ap.add_argument("--n-fp64-first", type=int, default=0)
@@ -683,7 +686,8 @@ def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):
                    "precision": precision, "launch_mode": args.launch_mode,
                    "tile_policy": args.tile_policy, "tile_order": args.tile_order,
                    "refine": args.refine, "n_fp64_first": args.n_fp64_first,
-                   "n_tile64": stats["n_tile64"], "n_sub": stats["n_sub"],
+                   "n_tile64": stats["n_tile64"], "n_split_il": stats["n_split_il"],
+                   "n_sub": stats["n_sub"],
                    "max_sub": stats["max_sub"], "sp2_iters": stats["iters"],
                    "refine_steps": stats["n_refine_done"]},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",

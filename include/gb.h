@@ -292,8 +292,10 @@ typedef struct {
                               * bucket (0, timed once per process or read from the tuning    *
                               * table), 1 = 128-edge tiles, 2 = 64-edge; FP64 / FP32 squares *
                               * also 4 = 64-edge with three LDS stages, 5 = 64-edge with      *
-                              * register-staged loads.  Values a precision has no kernel for  *
-                              * (4 and 5 for split squares) are taken as 0, as 3 is by all.   */
+                              * register-staged loads; GB_FP16X3_REFINE also 6 / 7 = 128- /   *
+                              * 64-edge tiles with the split under the products (two LDS      *
+                              * buffers; bit-identical to 1 / 2).  Values a precision has no   *
+                              * kernel for are taken as 0, as 3 is by all.                    */
   int32_t tile_order;        /* 0: each subgraph's tiles on one XCD (L2 reuse); 1: as listed */
   int32_t check_idem;        /* 1: also compute stats.idem_max, max |X^2 - X| over the core   *
                               *    columns (one more square of the core tiles, or nine slab  *
@@ -334,6 +336,8 @@ typedef struct {
   int32_t n_near_tie;        /* trace-rule decisions whose margin is within the rounding of   *
                               * the summed traces (64 ulp of |t1| + |t2| + n_occ): another     *
                               * summation order could have taken the other branch             */
+  int32_t n_split_il;        /* fp16 split loops: subgraphs squared with the split under the  *
+                              * products (tile policies 6 / 7, or the tuner's choice)          */
 } gb_sp2_stats;
 
 typedef struct gb_tape_s gb_tape_t;

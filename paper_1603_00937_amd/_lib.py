@@ -51,7 +51,8 @@ class GbSp2Stats(ctypes.Structure):
                 ("planes_db", ctypes.c_int32), ("n_stage3", ctypes.c_int32),
                 ("n_regstage", ctypes.c_int32),
                 ("square_flops", ctypes.c_double), ("square_flops_exec", ctypes.c_double),
-                ("tape", ctypes.c_void_p), ("n_near_tie", ctypes.c_int32)]
+                ("tape", ctypes.c_void_p), ("n_near_tie", ctypes.c_int32),
+                ("n_split_il", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER

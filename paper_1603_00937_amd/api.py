@@ -105,7 +105,8 @@ def set_allocator(allocator):
 
 
 # kernel variant names of gb_sp2_opts.tile_policy
-TILE_POLICIES = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5}
+TILE_POLICIES = {"auto": 0, "128": 1, "64": 2, 128: 1, 64: 2, "64s3": 4, "64r": 5, "128i": 6,
+                 "64i": 7}
 
 PEAK_KINDS = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3, "hbm": 4, "bf16_32x32": 5,
               "fp16_32x32": 6}
@@ -315,6 +316,7 @@ def _stats_dict(st: L.GbSp2Stats) -> dict:
         "square_flops": st.square_flops,
         "square_flops_exec": st.square_flops_exec,
         "n_near_tie": st.n_near_tie,
+        "n_split_il": st.n_split_il,
     }
 
 

@@ -643,7 +643,7 @@ gb_status gb_density(const gb_ell* H, int32_t n_occ, double threshold, const gb_
     if (o.check_idem < 0 || o.check_idem > 1) fail(GB_EINVAL, "check_idem must be 0 or 1");
     if (o.workspace && !o.partition)
       fail(GB_EINVAL, "a caller-owned workspace needs a partition (its size depends on it)");
-    if (o.tile_policy < 0 || o.tile_policy > 5) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
+    if (o.tile_policy < 0 || o.tile_policy > 7) fail(GB_EINVAL, "unknown tile_policy %d", o.tile_policy);
     if (o.tile_order < 0 || o.tile_order > 1) fail(GB_EINVAL, "unknown tile_order %d", o.tile_order);
     check_given_bounds(o.emin, o.emax);
     const int core_size = o.core_size > 0 ? o.core_size : 32;

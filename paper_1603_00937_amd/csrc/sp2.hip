@@ -626,6 +626,186 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
                           lin_flag ? *lin_flag == 1 : lin != 0);
 }
 
+// ---- split squaring with the split under the products -------------------------------------
+// Scheduling hints (the compiler places the named instruction classes in the given order
+// within a block of straight-line code): one matrix-core instruction, n vector-ALU ones, one
+// LDS read or write.
+__device__ inline void sched_mfma1() { __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); }
+__device__ inline void sched_valu2() { __builtin_amdgcn_sched_group_barrier(0x002, 2, 0); }
+__device__ inline void sched_valu4() { __builtin_amdgcn_sched_group_barrier(0x002, 4, 0); }
+__device__ inline void sched_dsr1() { __builtin_amdgcn_sched_group_barrier(0x100, 1, 0); }
+__device__ inline void sched_dsr8() { __builtin_amdgcn_sched_group_barrier(0x100, 8, 0); }
+__device__ inline void sched_dsw1() { __builtin_amdgcn_sched_group_barrier(0x200, 1, 0); }
+__device__ inline void sched_vmr4() { __builtin_amdgcn_sched_group_barrier(0x020, 4, 0); }
+
+// fp16 x 2 planes (three products), as k_symm_mm_split<2, true, BT>, with two LDS buffers: the
+// planes of chunk kc + 1 are split from registers and written to one buffer while the products
+// of chunk kc read the other, the split's vector instructions and LDS writes interleaved with
+// the matrix-core instructions (the first operand's split under the leading products, the
+// second's under the correction products), one barrier per chunk.  Each operand's next chunk
+// is loaded into registers once its split has consumed them.  The two buffers are separate
+// arrays and the loop is unrolled by two, so reads of one and writes of the other are known
+// not to alias.  Products, their order and the accumulators are those of k_symm_mm_split, so
+// both give the same bits.
+template <int BT>
+__global__ __launch_bounds__(kT, 2) void k_symm_mm_split_il(const float* __restrict__ X,
+                                                           float* __restrict__ S,
+                                                           const int4* __restrict__ tiles,
+                                                           const int64_t* __restrict__ offs,
+                                                           const int32_t* __restrict__ stopped,
+                                                           int lin,
+                                                           const int32_t* __restrict__ lin_flag) {
+  if (stopped && *stopped) return;
+  constexpr int NP = 2;
+  constexpr int KC = 32;           // k per chunk (64 bytes per plane row)
+  constexpr int OPB = BT * 64;     // bytes per plane and operand
+  constexpr int MB = BT / 32;      // 16 x 16 blocks per wave-tile edge
+  constexpr int WT = BT / 2;       // wave-tile edge
+  constexpr int NQ = BT / 32;      // rows per staging thread and operand
+  __shared__ __align__(1024) unsigned char lds0[NP][2][OPB];
+  __shared__ __align__(1024) unsigned char lds1[NP][2][OPB];
+  const int4 tl = tiles[blockIdx.x];
+  if (tl.x < 0) return;
+  const int s = tl.x, bi = tl.y, bj = tl.z, np = tl.w;
+  const int64_t off = offs[s];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int c8 = tid & 7, r0 = tid >> 3;
+  // 32-bit element offsets into the block (np^2 < 2^31) from one workgroup-uniform base
+  const float* xblk = X + off;
+  int asrc[NQ], bsrc[NQ], ldo[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int r = r0 + 32 * q;
+    const int ar = bi * BT + r, br = bj * BT + r;
+    asrc[q] = (ar < np ? ar : 0) * np + 4 * c8;
+    bsrc[q] = (br < np ? br : 0) * np + 4 * c8;
+    ldo[q] = r * 64 + (((c8 >> 1) ^ ((r >> 2) & 3)) << 4) + (c8 & 1) * 8;
+  }
+  f4v big[MB][MB], small[MB][MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int n = 0; n < MB; ++n) {
+      big[m][n] = f4v{0, 0, 0, 0};
+      small[m][n] = f4v{0, 0, 0, 0};
+    }
+  const int g = lane >> 4, r16 = lane & 15;
+  const int nk = np / KC;
+  const bool in_range = bi * BT + wr * WT < np && bj * BT + wc * WT < np;
+  const bool active = in_range && !(bi == bj && wr > wc);
+  const int pa0 = (wr * WT + r16) * 64, pb0 = (wc * WT + r16) * 64;
+  const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
+  f4v stg[2][NQ];  // [operand][q]
+  auto load_op = [&](int o, int k0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      stg[o][q] = *reinterpret_cast<const f4v*>(xblk + (o ? bsrc[q] : asrc[q]) + k0);
+  };
+  // the split of operand o, row groups q0 .. q0 + nq - 1, into dst
+  auto split_op = [&](int o, unsigned char (&dst)[NP][2][OPB], int q0, int nq) {
+#pragma unroll
+    for (int q = q0; q < q0 + nq; ++q) {
+      // an empty statement the value passes through, so that the split stays where it is
+      // written (the same code on both sides of the `active` branch would otherwise be hoisted
+      // above it, waiting for every load at the top of the chunk)
+      asm volatile("" : "+v"(stg[o][q]));
+      uint32_t lo[NP], hi[NP];
+      split_pair<NP, true>(stg[o][q][0], stg[o][q][1], lo);
+      split_pair<NP, true>(stg[o][q][2], stg[o][q][3], hi);
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        *reinterpret_cast<uint2*>(&dst[p][o][ldo[q]]) = uint2{lo[p], hi[p]};
+    }
+  };
+  // one chunk: products from `cur`, the next chunk's planes into `nxt`, then the chunk after
+  // that (k element k2) into registers; past the end k2 repeats the last chunk, just read by
+  // the same lanes (a cache hit), whose planes are never written (no branch inside the
+  // interleaved code)
+  auto step = [&](unsigned char (&cur)[NP][2][OPB], unsigned char (&nxt)[NP][2][OPB], int k2) {
+    if (active) {
+      bf8v A0[MB], B0[MB];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        __builtin_memcpy(&A0[m], &cur[0][0][pa0 + m * 16 * 64 + pc], 16);
+        __builtin_memcpy(&B0[m], &cur[0][1][pb0 + m * 16 * 64 + pc], 16);
+      }
+#pragma unroll
+      for (int m = 0; m < MB; ++m)
+#pragma unroll
+        for (int n = 0; n < MB; ++n) big[m][n] = mma_f16(A0[m], B0[n], big[m][n]);
+      split_op(0, nxt, 0, NQ);
+      // 2 MB fragment reads, then MB^2 products each with four split instructions, and one
+      // plane write (both planes of a row group) per MB^2 / NQ products
+      sched_dsr8();
+#pragma unroll
+      for (int i = 0; i < MB * MB; ++i) {
+        sched_mfma1();
+        sched_valu4();
+        if (i % (MB * MB / NQ) == MB * MB / NQ - 1) sched_dsw1();
+      }
+      load_op(0, k2);
+      sched_vmr4();  // the next loads after the split that frees their registers
+      // the second operand's split in two halves, under the hi x lo and the lo x hi products
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        bf8v BL;
+        __builtin_memcpy(&BL, &cur[1][1][pb0 + m * 16 * 64 + pc], 16);
+#pragma unroll
+        for (int r = 0; r < MB; ++r) small[r][m] = mma_f16(A0[r], BL, small[r][m]);
+      }
+      split_op(1, nxt, 0, NQ / 2);
+#pragma unroll
+      for (int i = 0; i < MB * MB; ++i) {
+        if (i % MB == 0) sched_dsr1();
+        sched_mfma1();
+        sched_valu2();
+        if (i % (2 * MB * MB / NQ) == 2 * MB * MB / NQ - 1) sched_dsw1();
+      }
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        bf8v AL;
+        __builtin_memcpy(&AL, &cur[1][0][pa0 + m * 16 * 64 + pc], 16);
+#pragma unroll
+        for (int n = 0; n < MB; ++n) small[m][n] = mma_f16(AL, B0[n], small[m][n]);
+      }
+      split_op(1, nxt, NQ / 2, NQ / 2);
+#pragma unroll
+      for (int i = 0; i < MB * MB; ++i) {
+        if (i % MB == 0) sched_dsr1();
+        sched_mfma1();
+        sched_valu2();
+        if (i % (2 * MB * MB / NQ) == 2 * MB * MB / NQ - 1) sched_dsw1();
+      }
+      load_op(1, k2);
+      sched_vmr4();
+    } else {
+      split_op(0, nxt, 0, NQ);
+      split_op(1, nxt, 0, NQ);
+      load_op(0, k2);
+      load_op(1, k2);
+    }
+    __syncthreads();
+  };
+  load_op(0, 0);
+  load_op(1, 0);
+  split_op(0, lds0, 0, NQ);
+  split_op(1, lds0, 0, NQ);
+  if (nk > 1) {
+    load_op(0, KC);
+    load_op(1, KC);
+  }
+  __syncthreads();
+  // the planes written past the last chunk are never read
+  for (int kc = 0; kc < nk; kc += 2) {
+    step(lds0, lds1, min(kc + 2, nk - 1) * KC);
+    if (kc + 1 < nk) step(lds1, lds0, min(kc + 3, nk - 1) * KC);
+  }
+  if (!active) return;
+  split_epilogue<BT, true>(big, small, S, X, off, np, bi, bj, wr, wc, lane,
+                           lin_flag ? *lin_flag == 1 : lin != 0);
+}
+
 // ---- traces and the branch decision --------------------------------------------------------
 // t1 = sum over subgraphs of the core diagonal of X; t2 = the same for X^2, which for the
 // symmetric X is the sum of the squared entries of the core rows.  Taking t2 from X lets the
@@ -1145,10 +1325,12 @@ int grid_for(int64_t n, int t, int cap = 1 << 20) {
 // largest blocks come first (most k work per tile).
 // Kernel variants of the batched products, one code per subgraph: 128 (128-edge tiles, two LDS
 // stages), 64 (64-edge, two stages), 63 (64-edge, three stages), 62 (64-edge, two stages,
-// register-staged loads).
-constexpr int kNVar = 4;
-constexpr int kVariants[kNVar] = {128, 64, 63, 62};
-inline int variant_edge(int code) { return code == 128 ? 128 : 64; }
+// register-staged loads); split squares: 128 and 64, and for fp16 planes 129 and 65 (128- and
+// 64-edge tiles with the split under the products, k_symm_mm_split_il).
+constexpr int kNVar = 6;
+constexpr int kVariants[kNVar] = {128, 64, 63, 62, 129, 65};
+inline int variant_edge(int code) { return code >= 128 ? 128 : 64; }
+inline bool split_il_code(int code) { return code == 129 || code == 65; }
 inline int variant_index(int code) {
   for (int v = 0; v < kNVar; ++v)
     if (kVariants[v] == code) return v;
@@ -1157,7 +1339,7 @@ inline int variant_index(int code) {
 
 // tiles per variant group (launch order as kVariants)
 struct Groups {
-  int n[kNVar] = {0, 0, 0, 0};
+  int n[kNVar] = {};
 };
 
 struct Plan {
@@ -1302,6 +1484,7 @@ void launch_symm(const T* A, const T* B, const T* E, T* out, T alpha, T beta, co
                  const Groups& g, const int64_t* offs, hipStream_t s,
                  const int32_t* stopped = nullptr, int lin = 0,
                  const int32_t* lin_flag = nullptr, T* dacc = nullptr, T cn = (T)0) {
+  if (g.n[4] > 0 || g.n[5] > 0) fail(GB_EHIP, "split-square tiles given to an FP64/FP32 product");
   const int4* t = tiles;
   if (g.n[0] > 0)
     hipLaunchKernelGGL((k_symm_mm<T, MODE, 128, 2>), dim3(g.n[0]), dim3(kT), 0, s, A, B, E, out,
@@ -1343,13 +1526,29 @@ template <int NP, bool F16>
 void launch_split_np(const float* X, float* S, const int4* tiles, const Groups& g,
                      const int64_t* offs, hipStream_t s, int lin, const int32_t* stopped,
                      const int32_t* lin_flag) {
-  if (g.n[0] > 0)
-    hipLaunchKernelGGL((k_symm_mm_split<NP, F16, 128>), dim3(g.n[0]), dim3(kT), 0, s, X, S,
-                       tiles, offs, stopped, lin, lin_flag);
-  if (g.n[1] > 0)
-    hipLaunchKernelGGL((k_symm_mm_split<NP, F16, 64>), dim3(g.n[1]), dim3(kT), 0, s, X, S,
-                       tiles + g.n[0], offs, stopped, lin, lin_flag);
   if (g.n[2] > 0 || g.n[3] > 0) fail(GB_EHIP, "split squares take 128- or 64-edge tiles only");
+  const int4* t = tiles;
+  if (g.n[0] > 0)
+    hipLaunchKernelGGL((k_symm_mm_split<NP, F16, 128>), dim3(g.n[0]), dim3(kT), 0, s, X, S, t,
+                       offs, stopped, lin, lin_flag);
+  t += g.n[0];
+  if (g.n[1] > 0)
+    hipLaunchKernelGGL((k_symm_mm_split<NP, F16, 64>), dim3(g.n[1]), dim3(kT), 0, s, X, S, t,
+                       offs, stopped, lin, lin_flag);
+  t += g.n[1];
+  if (g.n[4] > 0 || g.n[5] > 0) {
+    if constexpr (NP == 2 && F16) {
+      if (g.n[4] > 0)
+        hipLaunchKernelGGL(k_symm_mm_split_il<128>, dim3(g.n[4]), dim3(kT), 0, s, X, S, t, offs,
+                           stopped, lin, lin_flag);
+      t += g.n[4];
+      if (g.n[5] > 0)
+        hipLaunchKernelGGL(k_symm_mm_split_il<64>, dim3(g.n[5]), dim3(kT), 0, s, X, S, t, offs,
+                           stopped, lin, lin_flag);
+    } else {
+      fail(GB_EHIP, "the interleaved split squares take fp16 planes only");
+    }
+  }
   GB_LAUNCH_CHECK();
 }
 
@@ -1493,10 +1692,13 @@ int tune_read(const char* path, std::string* why) {
       *why = "malformed entry";
       return -1;
     }
-    const bool known = variant == 128 || variant == 64 || variant == 63 || variant == 62;
+    // kinds: 0 FP64, 1 FP32, 10 + planes split squares; the interleaved split (129, 65)
+    // exists for the fp16 planes (kind 14) only
+    const bool known = variant_index(variant) >= 0;
     const bool split = kind >= 11 && kind <= 14;
-    if (!known || bucket < 1 || !(kind == 0 || kind == 1 || split) ||
-        (split && variant != 128 && variant != 64)) {
+    const bool split_ok = variant == 128 || variant == 64 || (kind == 14 && split_il_code(variant));
+    if (!known || bucket < 1 || !(kind == 0 || kind == 1 || split) || (split && !split_ok) ||
+        (!split && split_il_code(variant))) {
       *why = "entry with an unknown kind, bucket or variant";
       return -1;
     }
@@ -1544,7 +1746,9 @@ std::vector<int> tune_tiles(const Part& P, const Plan& pl, T* X, T* S, const int
     if (!choice) {
       float best = INFINITY;
       for (int code : kVariants) {
-        if (planes > 0 && code != 128 && code != 64) continue;
+        if (planes > 0 && code != 128 && code != 64 && !(planes == 4 && split_il_code(code)))
+          continue;
+        if (planes == 0 && split_il_code(code)) continue;
         std::vector<int> e(pl.n_sub, 0);
         for (int i : kv.second) e[i] = code;
         const Plan sub = make_plan(P, &e, xcd);
@@ -1591,6 +1795,8 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   if (policy == 2) bt.assign(pl.n_sub, 64);
   else if (policy == 4 && planes == 0) bt.assign(pl.n_sub, 63);
   else if (policy == 5 && planes == 0) bt.assign(pl.n_sub, 62);
+  else if (policy == 6 && planes == 4) bt.assign(pl.n_sub, 129);
+  else if (policy == 7 && planes == 4) bt.assign(pl.n_sub, 65);
   else if (policy != 1) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd, planes);
   if (policy == 1) return;
   pl = make_plan(P, &bt, xcd);
@@ -1599,8 +1805,10 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   st.n_tile64 = 0;
   st.n_stage3 = 0;
   st.n_regstage = 0;
+  st.n_split_il = 0;
   for (int e : bt) {
-    st.n_tile64 += e != 128;
+    st.n_split_il += split_il_code(e);
+    st.n_tile64 += variant_edge(e) == 64;
     st.n_stage3 += e == 63;
     st.n_regstage += e == 62;
   }

@@ -171,7 +171,7 @@ def test_diagonal_hamiltonian(gb):
 LAUNCH_MODES = ("device", "per_subgraph", "graph", "host")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6", "fp16x3"])
 def test_launch_modes_agree(gb, model_cache, precision):
     """The device-driven loop (default), one launch per subgraph, the hipGraph replay and the
     host-driven loop run the same kernels on the same data: results agree bit for bit."""
@@ -188,21 +188,21 @@ def test_launch_modes_agree(gb, model_cache, precision):
         assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), mode
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6", "fp16x3"])
 def test_launch_modes_agree_n1024(gb, model_cache, precision):
     """The same at N = 1024 (blocks of up to 1024 rows, several tiles per edge and a ragged
     last tile), where the device-driven loops run past their first batch only if the
     expansion is long."""
     m = model_cache("n1024")
     outs = {}
-    for mode in ("device", "graph", "host"):
+    for mode in LAUNCH_MODES:
         D_col, D_val, st = gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5,
                                       core_size=16, precision=precision, launch_mode=mode)
         outs[mode] = (D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"], st["n_square"],
                       st["n_square_lo"])
         print(mode, st["iters"], st["ms"]["sp2"], st["ms"]["total"])
     ref = outs["device"]
-    for mode in ("graph", "host"):
+    for mode in LAUNCH_MODES[1:]:
         o = outs[mode]
         assert o[2] == ref[2] and o[3:] == ref[3:], mode
         assert np.array_equal(o[0], ref[0]) and np.array_equal(o[1], ref[1]), mode
@@ -229,16 +229,38 @@ def test_split_tile_edges_agree(gb, model_cache, name, core, precision):
         assert np.abs(outs[pol][1] - outs["128"][1]).max() < 2e-7, pol
 
 
+@pytest.mark.parametrize("name,core", [("small256", 16), ("n1024", 16), ("n18000", 32)])
+def test_fp16_interleaved_split_is_bit_identical(gb, model_cache, name, core):
+    """The fp16 split square with the split under the products (two LDS buffers, tile policies
+    "128i" / "64i") runs the same products in the same order as the one that splits between
+    barriers: bit-identical D, branches and step counts, for either tile edge."""
+    m = model_cache(name)
+    Hc, Hv = _dev(m["H_col"]), _dev(m["H_val"])
+    p = gb.partition(gb.build_graph(Hc, Hv, 1e-5), core,
+                     method="multilevel" if name == "n18000" else "block")
+    for a, b in (("128", "128i"), ("64", "64i")):
+        outs = []
+        for pol in (a, b):
+            D_col, D_val, st = gb.density(Hc, Hv, m["n_occ"], 1e-5, partition=p,
+                                          precision="fp16x3", tile_policy=pol)
+            outs.append((D_col.cpu().numpy(), D_val.cpu().numpy(), st["branch"], st["iters"],
+                         st["n_refine_done"]))
+        assert outs[0][2:] == outs[1][2:], (a, b)
+        assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_tune_table_round_trip(gb, model_cache, tmp_path):
     import json
     m = model_cache("n1024")
-    gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5, core_size=16,
-               precision="bf16x6")
+    for precision in ("bf16x6", "fp16x3"):
+        gb.density(_dev(m["H_col"]), _dev(m["H_val"]), m["n_occ"], 1e-5, core_size=16,
+                   precision=precision)
     path = tmp_path / "tune.json"
     n = gb.tune_save(path)
     t = json.loads(path.read_text())
     assert n >= 1 and len(t["entries"]) == n and t["format"] == "libgb-tune-1"
     assert any(e["kind"] == 13 for e in t["entries"])  # the split-bf16 squares
+    assert any(e["kind"] == 14 for e in t["entries"])  # the fp16 squares (either split kernel)
     assert gb.tune_load(path) == n
     t["device"] = "another device"
     path.write_text(json.dumps(t))
