@@ -405,8 +405,12 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 // the epilogue removes exactly.
 constexpr float kF16Scale = 16384.0f;            // 2^14
 constexpr float kF16Unscale = 3.7252902984619140625e-09f;  // 2^-28
+// neg1 is -1: passed as a value the compiler cannot see (a register), the remainder
+// r - fp16(r) = fma(-1, fp16(r), r) (exact product, one rounding, as the subtraction) becomes one
+// mixed-precision FMA that reads the fp16 half directly, instead of a conversion and a
+// subtraction.
 template <int NP, bool F16 = false>
-__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w, float neg1 = -1.0f) {
   typedef float f2v __attribute__((ext_vector_type(2)));
   if constexpr (F16) {
     typedef _Float16 h2v __attribute__((ext_vector_type(2)));
@@ -418,8 +422,8 @@ __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w) {
       __builtin_memcpy(&u, &h, 4);
       w[p] = u;
       if (p + 1 < NP) {
-        r0 -= (float)h[0];
-        r1 -= (float)h[1];
+        r0 = __builtin_fmaf(neg1, (float)h[0], r0);
+        r1 = __builtin_fmaf(neg1, (float)h[1], r1);
       }
     }
   } else {
@@ -544,6 +548,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
   const int pa0 = (wr * WT + r16) * 64, pb0 = (wc * WT + r16) * 64;
   const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
   f4v stg[2][NQ];  // [operand][q]
+  float neg1 = -1.0f;  // see split_pair
+  asm volatile("" : "+v"(neg1));
 #define GB_STAGE(k0)                                                                          \
   _Pragma("unroll") for (int q = 0; q < NQ; ++q) {                                            \
     stg[0][q] = *reinterpret_cast<const f4v*>(asrc[q] + (k0));                                \
@@ -559,8 +565,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split(const float* __restrict
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         uint32_t lo[NP], hi[NP];
-        split_pair<NP, F16>(stg[o][q][0], stg[o][q][1], lo);
-        split_pair<NP, F16>(stg[o][q][2], stg[o][q][3], hi);
+        split_pair<NP, F16>(stg[o][q][0], stg[o][q][1], lo, neg1);
+        split_pair<NP, F16>(stg[o][q][2], stg[o][q][3], hi, neg1);
 #pragma unroll
         for (int p = 0; p < NP; ++p)
           *reinterpret_cast<uint2*>(&lds[p][o][ldo[q]]) = uint2{lo[p], hi[p]};
@@ -697,6 +703,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split_il(const float* __restr
   const int pa0 = (wr * WT + r16) * 64, pb0 = (wc * WT + r16) * 64;
   const int pc = (g ^ ((r16 >> 2) & 3)) << 4;
   f4v stg[2][NQ];  // [operand][q]
+  float neg1 = -1.0f;  // see split_pair
+  asm volatile("" : "+v"(neg1));
   auto load_op = [&](int o, int k0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
@@ -711,8 +719,8 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm_split_il(const float* __restr
       // above it, waiting for every load at the top of the chunk)
       asm volatile("" : "+v"(stg[o][q]));
       uint32_t lo[NP], hi[NP];
-      split_pair<NP, true>(stg[o][q][0], stg[o][q][1], lo);
-      split_pair<NP, true>(stg[o][q][2], stg[o][q][3], hi);
+      split_pair<NP, true>(stg[o][q][0], stg[o][q][1], lo, neg1);
+      split_pair<NP, true>(stg[o][q][2], stg[o][q][3], hi, neg1);
 #pragma unroll
       for (int p = 0; p < NP; ++p)
         *reinterpret_cast<uint2*>(&dst[p][o][ldo[q]]) = uint2{lo[p], hi[p]};
