@@ -93,7 +93,8 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
                                                const int32_t* __restrict__ sub_ptr,
                                                const int32_t* __restrict__ sub_idx,
                                                const int64_t* __restrict__ offs,
-                                               const int32_t* __restrict__ npad, T* __restrict__ X) {
+                                               const int32_t* __restrict__ npad, T* __restrict__ X,
+                                               T scale) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int s = blockIdx.x;
   const int np = npad[s];
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(kT) void k_gather(const int32_t* __restrict__ hcol,
     }
     __syncthreads();
     T* dst = base + (int64_t)a * np;
-    for (int c = threadIdx.x; c < np; c += kT) dst[c] = (T)row[c];
+    for (int c = threadIdx.x; c < np; c += kT) dst[c] = (T)row[c] * scale;
     __syncthreads();
   }
 }
@@ -401,10 +402,15 @@ __global__ __launch_bounds__(kT, 2) void k_symm_mm(const T* __restrict__ A, cons
 // a mask for bf16, a conversion for fp16) for the next remainder.
 // F16: two fp16 planes of 2^14 x instead (hi = fp16(2^14 x), lo = fp16(2^14 x - hi), about 22
 // bits; |x| <= 1 for an iterate with its spectrum in [0, 1], so 2^14 x stays far below the fp16
-// maximum and values down to ~4e-9 stay normal); the products then carry a factor 2^28, which
-// the epilogue removes exactly.
-constexpr float kF16Scale = 16384.0f;            // 2^14
-constexpr float kF16Unscale = 3.7252902984619140625e-09f;  // 2^-28
+// maximum and values down to ~4e-9 stay normal).  The fp16 loop keeps its FP32 iterate stored
+// as x' = 2^14 x (the gather and the conversion into the loop scale it, the traces and the
+// conversion out of the loop scale back, all exact powers of two), so the split needs no
+// multiply: hi = fp16(x'), lo = fp16(x' - hi).  The products then carry 2^28 = 2^14 * 2^14;
+// the epilogue multiplies by 2^-14 to store the next iterate, again as 2^14 times its value.
+constexpr float kF16Scale = 16384.0f;                    // 2^14
+constexpr float kF16Down = 6.103515625e-05f;             // 2^-14
+constexpr double kF16TraceDown1 = 6.103515625e-05;       // 2^-14 (diagonal sums)
+constexpr double kF16TraceDown2 = 3.7252902984619140625e-09;  // 2^-28 (sums of squares)
 // neg1 is -1: passed as a value the compiler cannot see (a register), the remainder
 // r - fp16(r) = fma(-1, fp16(r), r) (exact product, one rounding, as the subtraction) becomes one
 // mixed-precision FMA that reads the fp16 half directly, instead of a conversion and a
@@ -414,7 +420,7 @@ __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t* w, floa
   typedef float f2v __attribute__((ext_vector_type(2)));
   if constexpr (F16) {
     typedef _Float16 h2v __attribute__((ext_vector_type(2)));
-    float r0 = x0 * kF16Scale, r1 = x1 * kF16Scale;
+    float r0 = x0, r1 = x1;  // the stored iterate is already 2^14 x
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       const h2v h = __builtin_convertvector(f2v{r0, r1}, h2v);
@@ -472,7 +478,7 @@ __device__ __forceinline__ void split_epilogue(const f4v (&big)[BT / 32][BT / 32
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         v[r] = big[m][n][r] + small[m][n][r];
-        if (F16) v[r] *= kF16Unscale;
+        if (F16) v[r] *= kF16Down;
       }
       if (do_lin) {
         const f4v xt = *reinterpret_cast<const f4v*>(xa + qt);
@@ -832,7 +838,8 @@ __global__ __launch_bounds__(kT) void k_trace_rows(const T* __restrict__ X,
                                                    const int32_t* __restrict__ npad,
                                                    const int32_t* __restrict__ core_ptr,
                                                    double* __restrict__ part,
-                                                   const int32_t* __restrict__ stopped) {
+                                                   const int32_t* __restrict__ stopped,
+                                                   double s1, double s2) {
   if (stopped && *stopped) return;
   __shared__ double r1[kT], r2[kT];
   const int s = blockIdx.x;
@@ -858,8 +865,8 @@ __global__ __launch_bounds__(kT) void k_trace_rows(const T* __restrict__ X,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * s] = r1[0];
-    part[2 * s + 1] = r2[0];
+    part[2 * s] = r1[0] * s1;
+    part[2 * s + 1] = r2[0] * s2;
   }
 }
 
@@ -972,10 +979,10 @@ __global__ __launch_bounds__(kT) void k_decide_dev(const double* __restrict__ pa
 }
 
 template <typename TI, typename TO>
-__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t n) {
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64_t n, TO scale) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = i; p < n; p += stride) out[p] = (TO)in[p];
+  for (int64_t p = i; p < n; p += stride) out[p] = (TO)in[p] * scale;
 }
 
 // An FP32 iterate made exactly symmetric: out = (X + X^T)/2 per block, formed in FP64 and
@@ -988,7 +995,8 @@ template <typename TO>
 __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X,
                                                      TO* __restrict__ out,
                                                      const int64_t* __restrict__ offs,
-                                                     const int32_t* __restrict__ npad) {
+                                                     const int32_t* __restrict__ npad,
+                                                     double scale) {
   __shared__ float ta[64][65], tb[64][65];
   const int s = blockIdx.y;
   const int np = npad[s], nt = np / 64;
@@ -1006,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
     os[(int64_t)(bi * 64 + r) * np + bj * 64 + c] =
-        (TO)(0.5 * ((double)ta[r][c] + (double)tb[c][r]));
+        (TO)(0.5 * ((double)ta[r][c] + (double)tb[c][r]) * scale);
   }
 }
 
@@ -1887,12 +1895,15 @@ int sp2_loop(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DBuf<i
   Timer tm;
   PinnedRec pin;
   int it = it0;
+  // the fp16 loop's iterate is stored as 2^14 X: its traces are scaled back
+  const bool scaled = std::is_same<T, float>::value && planes == 4;
+  const double ts1 = scaled ? kF16TraceDown1 : 1.0, ts2 = scaled ? kF16TraceDown2 : 1.0;
   int prev_b = -1;
   std::vector<double> es;
   DBuf<double> part(2 * (size_t)pl.n_sub, s);
   for (;;) {
     hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, s, X, offs.get(), npad.get(),
-                       P.core_ptr.get(), part.get(), nullptr);
+                       P.core_ptr.get(), part.get(), nullptr, ts1, ts2);
     int forced = -1;
     if (branch_in) forced = it < n_branch_in ? (int)branch_in[it] : 2;
     else if (alternate && prev_b >= 0) forced = 10 + (1 - prev_b);
@@ -1997,6 +2008,9 @@ int sp2_loop_dev(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DB
   if (branch_in) std::memcpy(in.forced, branch_in, std::min(n_branch_in, 128));
   DBuf<LoopState> d(1, s);
   DBuf<double> part(2 * (size_t)pl.n_sub, s);
+  // the fp16 loop's iterate is stored as 2^14 X: its traces are scaled back
+  const bool scaled = std::is_same<T, float>::value && planes == 4;
+  const double ts1 = scaled ? kF16TraceDown1 : 1.0, ts2 = scaled ? kF16TraceDown2 : 1.0;
   hipLaunchKernelGGL(k_loop_init, dim3(1), dim3(1), 0, s, d.get(), in);
   GB_LAUNCH_CHECK();
   const int32_t* stopped = &d.get()->stopped;
@@ -2006,7 +2020,7 @@ int sp2_loop_dev(T*& X, T*& S, const Plan& pl, const DBuf<int4>& tiles, const DB
     T* A = (k & 1) ? S : X;
     T* B = (k & 1) ? X : S;
     hipLaunchKernelGGL(k_trace_rows<T>, dim3(pl.n_sub), dim3(kT), 0, q, A, offs.get(),
-                       npad.get(), P.core_ptr.get(), part.get(), stopped);
+                       npad.get(), P.core_ptr.get(), part.get(), stopped, ts1, ts2);
     hipLaunchKernelGGL(k_decide_dev, dim3(1), dim3(kT), 0, q, part.get(), pl.n_sub, d.get());
     GB_LAUNCH_CHECK();
     if (timed) GB_HIP(hipEventRecord(ev[2 * k], q));
@@ -2237,11 +2251,11 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
     if (nhi > 0) {
       hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
                          P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(),
-                         npad.get(), xd);
+                         npad.get(), xd, 1.0);
     } else {
       hipLaunchKernelGGL(k_gather<float>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
                          P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(),
-                         npad.get(), xf);
+                         npad.get(), xf, planes == 4 ? kF16Scale : 1.0f);
     }
     GB_LAUNCH_CHECK();
     GB_HIP(hipEventRecord(t_gather.b, s));
@@ -2260,7 +2274,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       done = stop_kind == 1 || stop_kind == 3;
       if (!done) {
         hipLaunchKernelGGL((k_convert<double, float>), dim3(grid_for(pl.total, kT, 65536)),
-                           dim3(kT), 0, s, xd, xf, pl.total);
+                           dim3(kT), 0, s, xd, xf, pl.total, planes == 4 ? kF16Scale : 1.0f);
         GB_LAUNCH_CHECK();
       }
     }
@@ -2285,7 +2299,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       // symmetric, in FP32 (every block is padded to a multiple of 64)
       const int max_nt = pl.max_npad / 64;
       hipLaunchKernelGGL(k_sym_convert<float>, dim3(max_nt * max_nt, pl.n_sub), dim3(256), 0, s,
-                         xf, sf, offs.get(), npad.get());
+                         xf, sf, offs.get(), npad.get(),
+                         planes == 4 ? (double)kF16Down : 1.0);
       GB_LAUNCH_CHECK();
       xs = sf;
       xd_ready = false;
@@ -2294,7 +2309,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   } else {
     hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, x0, H.width,
                        P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
-                       X64);
+                       X64, 1.0);
     GB_LAUNCH_CHECK();
     if (tape_out) {
       TapeData* t = new TapeData();
@@ -2338,7 +2353,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   auto ensure_xd = [&] {
     if (xd_ready) return;
     hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT),
-                       0, s, xs, xd, pl.total);
+                       0, s, xs, xd, pl.total, 1.0);
     GB_LAUNCH_CHECK();
     xd_ready = true;
   };
@@ -2367,7 +2382,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       DBuf<double> part(2 * (size_t)pl.n_sub, s);
       StepRec r;
       hipLaunchKernelGGL(k_trace_rows<float>, dim3(pl.n_sub), dim3(kT), 0, s, xs, offs.get(),
-                         npad.get(), P.core_ptr.get(), part.get(), nullptr);
+                         npad.get(), P.core_ptr.get(), part.get(), nullptr, 1.0, 1.0);
       hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, (double)n_occ,
                          tol, 2, 0, recs.get());
       GB_LAUNCH_CHECK();
@@ -2394,7 +2409,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
           rc.lin2(y, 3.0, s1, -2.0, s2);
         }
         hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, y,
-                           cr.soffs.get(), npad.get(), P.core_ptr.get(), part.get(), nullptr);
+                           cr.soffs.get(), npad.get(), P.core_ptr.get(), part.get(), nullptr, 1.0,
+                           1.0);
         hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub,
                            (double)n_occ, tol, 2, 0, recs.get());
         GB_LAUNCH_CHECK();
@@ -2439,7 +2455,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       StepRec r;
       for (int step = 0;; ++step) {
         hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, xd, offs.get(),
-                           npad.get(), P.core_ptr.get(), part.get(), nullptr);
+                           npad.get(), P.core_ptr.get(), part.get(), nullptr, 1.0, 1.0);
         hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub,
                            (double)n_occ, tol, 2, 0, recs.get());
         GB_LAUNCH_CHECK();
@@ -2791,7 +2807,7 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   double* const Pm = ws->get<double>(5, pl.total, s);  // the full product Ht T_n
   hipLaunchKernelGGL(k_gather<double>, ggrid, dim3(kT), lds_g, s, H.col, ht.get(), H.width,
                      P.core_ptr.get(), P.sub_ptr.get(), P.sub_idx.get(), offs.get(), npad.get(),
-                     A);
+                     A, 1.0);
   GB_LAUNCH_CHECK();
   GB_HIP(hipEventRecord(t_stage.b, s));
   GB_HIP(hipStreamSynchronize(s));
@@ -2808,7 +2824,7 @@ void foe(const gb_ell& H, int32_t n_occ, const gb_foe_opts& o, const Part& P, do
   std::deque<Timer> marks;
   auto record_trace = [&](const double* X, int n) {
     hipLaunchKernelGGL(k_trace_rows<double>, dim3(pl.n_sub), dim3(kT), 0, s, X, offs.get(),
-                       npad.get(), P.core_ptr.get(), part.get(), nullptr);
+                       npad.get(), P.core_ptr.get(), part.get(), nullptr, 1.0, 1.0);
     hipLaunchKernelGGL(k_trace_total, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub,
                        tdev.get() + n);
     GB_LAUNCH_CHECK();
