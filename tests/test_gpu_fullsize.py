@@ -71,6 +71,14 @@ def test_n18000_bf16x6(gb):
     assert err <= 1e-6
 
 
+def test_n18000_fp16x3(gb):
+    """Split-fp16 squares (two planes of the pre-scaled iterate, three products) plus FP64
+    McWeeny refinement meet the 1e-6 bar."""
+    ref, st, err = _run(gb, "n18000", "fp16x3")
+    assert st["converged"]
+    assert err <= 1e-6
+
+
 @pytest.mark.parametrize("first", [0, 3])
 def test_n18000_fp32(gb, first):
     """FP32 MFMA squares (blocked summation per 32-k chunk) plus FP64 McWeeny refinement, with

@@ -35,7 +35,7 @@ def _sample_err(D_val, ref):
     return max(abs(dv[r, s] - float.fromhex(v)) for r, s, v in ref["samples"])
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x6", "fp16x3"])
 def test_mixed_precision_within_1e6(gb, model_cache, ref1024, precision):
     from synth import ell_sha256
     m = model_cache("n1024")
@@ -90,7 +90,7 @@ def test_refinement_variants(gb, model_cache, ref1024, refine, first):
 
 
 @pytest.mark.parametrize("precision,core", [("fp32", 16), ("bf16x6", 16), ("bf16x6", 32),
-                                            ("fp32", 40)])
+                                            ("fp16x3", 16), ("fp16x3", 32), ("fp32", 40)])
 def test_core_row_refinement_matches_whole_blocks(gb, model_cache, precision, core):
     """McWeeny on the core rows (products of the k core rows with X) against McWeeny on whole
     blocks from the same low-precision X: same pattern, values and check to rounding.  Cores
