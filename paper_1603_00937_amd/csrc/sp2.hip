@@ -841,18 +841,38 @@ __global__ __launch_bounds__(kT) void k_trace_rows(const T* __restrict__ X,
                                                    const int32_t* __restrict__ stopped,
                                                    double s1, double s2) {
   if (stopped && *stopped) return;
+  constexpr int V = 16 / sizeof(T);  // values per 16-byte load
+  typedef T vec __attribute__((ext_vector_type(V)));
   __shared__ double r1[kT], r2[kT];
   const int s = blockIdx.x;
   const int np = npad[s], k = core_ptr[s + 1] - core_ptr[s];
+  const int nv = np / V;  // np is a multiple of 64
   const T* xs = X + offs[s];
   double p1 = 0.0, p2 = 0.0;
-  for (int j = 0; j < k; ++j) {
-    const T* row = xs + (int64_t)j * np;
-    for (int a = threadIdx.x; a < np; a += kT) {
-      const double v = (double)row[a];
-      p2 += v * v;
+  // 16-byte loads, four rows at a time, so that each thread has several loads in flight; the
+  // thread whose load holds element (j, j) adds it to the diagonal sum
+  auto row_sums = [&](int j, const vec& v, int a) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) p2 += (double)v[e] * (double)v[e];
+    if (a == j / V) p1 += (double)v[j % V];
+  };
+  int j = 0;
+  for (; j + 4 <= k; j += 4) {
+    const vec* r0 = reinterpret_cast<const vec*>(xs + (int64_t)j * np);
+    const vec* r1p = reinterpret_cast<const vec*>(xs + (int64_t)(j + 1) * np);
+    const vec* r2p = reinterpret_cast<const vec*>(xs + (int64_t)(j + 2) * np);
+    const vec* r3p = reinterpret_cast<const vec*>(xs + (int64_t)(j + 3) * np);
+    for (int a = threadIdx.x; a < nv; a += kT) {
+      const vec v0 = r0[a], v1 = r1p[a], v2 = r2p[a], v3 = r3p[a];
+      row_sums(j, v0, a);
+      row_sums(j + 1, v1, a);
+      row_sums(j + 2, v2, a);
+      row_sums(j + 3, v3, a);
     }
-    if (threadIdx.x == 0) p1 += (double)row[j];
+  }
+  for (; j < k; ++j) {
+    const vec* r0 = reinterpret_cast<const vec*>(xs + (int64_t)j * np);
+    for (int a = threadIdx.x; a < nv; a += kT) row_sums(j, r0[a], a);
   }
   r1[threadIdx.x] = p1;
   r2[threadIdx.x] = p2;
@@ -986,11 +1006,12 @@ __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64
 }
 
 // An FP32 iterate made exactly symmetric: out = (X + X^T)/2 per block, formed in FP64 and
-// stored as TO (FP32: rounded once; the workgroups of a tile and of its transpose round the
-// same sum, so out stays exactly symmetric).  The split squares compute both triangles of
-// their diagonal tiles, pairing the planes of an entry and of its transpose differently, so
-// the FP32 iterate is symmetric only to rounding; the FP64 refinement relies on symmetry.  One
-// workgroup per 64x64 tile, the tile and its transpose partner through LDS.
+// stored as TO (FP32: rounded once; an entry and its transpose round the same sum, so out
+// stays exactly symmetric).  The split squares compute both triangles of their diagonal tiles,
+// pairing the planes of an entry and of its transpose differently, so the FP32 iterate is
+// symmetric only to rounding; the FP64 refinement relies on symmetry.  One workgroup per pair
+// of 64x64 tiles (a tile and its transpose partner), both read once through LDS and both
+// written.
 template <typename TO>
 __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X,
                                                      TO* __restrict__ out,
@@ -1000,9 +1021,16 @@ __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X
   __shared__ float ta[64][65], tb[64][65];
   const int s = blockIdx.y;
   const int np = npad[s], nt = np / 64;
-  const int t = blockIdx.x;
-  if (t >= nt * nt) return;  // the whole workgroup leaves together
-  const int bi = t / nt, bj = t % nt;
+  // workgroup t takes the t-th tile pair (bi, bj), bi <= bj, of the upper triangle in row
+  // order: both tiles are read once and both are written
+  int t = blockIdx.x;
+  if (t >= nt * (nt + 1) / 2) return;  // the whole workgroup leaves together
+  int bi = 0;
+  while (t >= nt - bi) {
+    t -= nt - bi;
+    ++bi;
+  }
+  const int bj = bi + t;
   const float* xs = X + offs[s];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
@@ -1015,6 +1043,12 @@ __global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X
     const int r = e >> 6, c = e & 63;
     os[(int64_t)(bi * 64 + r) * np + bj * 64 + c] =
         (TO)(0.5 * ((double)ta[r][c] + (double)tb[c][r]) * scale);
+  }
+  if (bi == bj) return;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {  // (bj, bi): the same sums, transposed
+    const int r = e >> 6, c = e & 63;
+    os[(int64_t)(bj * 64 + r) * np + bi * 64 + c] =
+        (TO)(0.5 * ((double)tb[r][c] + (double)ta[c][r]) * scale);
   }
 }
 
@@ -2298,7 +2332,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       // the final low-precision square was only the stop test: continue from X made exactly
       // symmetric, in FP32 (every block is padded to a multiple of 64)
       const int max_nt = pl.max_npad / 64;
-      hipLaunchKernelGGL(k_sym_convert<float>, dim3(max_nt * max_nt, pl.n_sub), dim3(256), 0, s,
+      hipLaunchKernelGGL(k_sym_convert<float>, dim3(max_nt * (max_nt + 1) / 2, pl.n_sub),
+                         dim3(256), 0, s,
                          xf, sf, offs.get(), npad.get(),
                          planes == 4 ? (double)kF16Down : 1.0);
       GB_LAUNCH_CHECK();
