@@ -282,10 +282,12 @@ __global__ void k_sort_cores(const int32_t* __restrict__ order, const int32_t* _
 }
 
 // Common closed neighbours of the ends of every edge: w[e] = |row u ∩ row col[e]| for the rows
-// of a CSR graph that holds its self loops (so each row is the closed neighbourhood).  One
-// workgroup per vertex u: row u as a bitmap in LDS, then one wave per neighbour v counting the
-// entries of row v found in it.  *missing receives the smallest u whose row lacks u (it is
-// left as it was when every row holds its self loop).
+// of a symmetric CSR graph that holds its self loops (so each row is the closed neighbourhood).
+// One workgroup per vertex u: row u as a bitmap in LDS, then one wave per neighbour v >= u
+// counting the entries of row v found in it; the count is symmetric, so the wave also writes
+// it at the entry of u in row v, which it meets while scanning row v (each entry has one
+// writer).  *missing receives the smallest u whose row lacks u (it is left as it was when
+// every row holds its self loop).
 __global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restrict__ rp,
                                                   const int32_t* __restrict__ col,
                                                   int32_t* __restrict__ w,
@@ -305,13 +307,21 @@ __global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restri
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int e = b + wave; e < e_end; e += kT / 64) {
     const int v = col[e];
-    int c = 0;
+    if (v < u) continue;  // wave-uniform: workgroup v writes this entry
+    int c = 0, pos = -1;
     for (int f = rp[v] + lane; f < rp[v + 1]; f += 64) {
       const int x = col[f];
       c += (bits[x >> 5] >> (x & 31)) & 1u;
+      if (x == u) pos = f;
     }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off, 64);
-    if (lane == 0) w[e] = c;
+    for (int off = 32; off > 0; off >>= 1) {
+      c += __shfl_down(c, off, 64);
+      pos = max(pos, __shfl_down(pos, off, 64));
+    }
+    if (lane == 0) {
+      w[e] = c;
+      if (v != u && pos >= 0) w[pos] = c;  // pos >= 0 in a symmetric graph
+    }
   }
 }
 
