@@ -288,9 +288,11 @@ typedef struct {
                               * 2: as 0 with two steps captured in a hipGraph and replayed;   *
                               * 3: batched launches, every decision read back by the host.    *
                               * keep_tape and refine_kind 1 run their steps as in 3.          */
-  int32_t tile_policy;       /* kernel variant of the squares: autotuned per 256-wide size   *
-                              * bucket (0, timed once per process or read from the tuning    *
-                              * table), 1 = 128-edge tiles, 2 = 64-edge; FP64 / FP32 squares *
+  int32_t tile_policy;       /* kernel variant of the squares: 0 = split squares autotuned   *
+                              * per 256-wide size bucket (timed once per process or read from *
+                              * the tuning table), FP64 / FP32 squares on policy 5 (the       *
+                              * fastest measured in every bucket); 1 = 128-edge tiles, 2 =    *
+                              * 64-edge; FP64 / FP32 squares                                   *
                               * also 4 = 64-edge with three LDS stages, 5 = 64-edge with      *
                               * register-staged loads; GB_FP16X3_REFINE also 6 / 7 = 128- /   *
                               * 64-edge tiles with the split under the products (two LDS      *

@@ -1847,6 +1847,10 @@ void choose_tiles(const Part& P, Plan& pl, T* X, T* S, DBuf<int4>& tiles, const 
   else if (policy == 5 && planes == 0) bt.assign(pl.n_sub, 62);
   else if (policy == 6 && planes == 4) bt.assign(pl.n_sub, 129);
   else if (policy == 7 && planes == 4) bt.assign(pl.n_sub, 65);
+  // FP64 / FP32 squares: the register-staged 64-edge variant, the fastest measured in every
+  // size bucket of the N = 1024, 18000 and 100000 systems (the others stay selectable); split
+  // squares: timed per bucket
+  else if (policy != 1 && planes == 0) bt.assign(pl.n_sub, 62);
   else if (policy != 1) bt = tune_tiles<T>(P, pl, X, S, offs, s, kind, xcd, planes);
   if (policy == 1) return;
   pl = make_plan(P, &bt, xcd);
