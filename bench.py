@@ -553,11 +553,14 @@ def main():
     g = gb.build_graph(Hc, Hv, cfg["tau"])
     p = gb.partition(g, cfg["core"], method=args.partition)
     sizes = np.diff(p.arrays()[1].cpu().numpy())
+    core_sizes = np.diff(p.arrays()[0].cpu().numpy())
     D = (torch.empty((N, p.max_sub), dtype=torch.int32, device=dev),
          torch.empty((N, p.max_sub), dtype=torch.float64, device=dev))
     del g, p
 
     out = measure(gb, torch, args, args.precision, model, cfg, Hc, Hv, D, golden, sizes)
+    out["stage_hbm_gbps"] = stage_hbm(out["stage_ms"], sizes, core_sizes, model,
+                                      args.precision)
     dcm, dvm = D[0].cpu().numpy(), D[1].cpu().numpy()
     low = args.precision != "fp64"
     dcf = dvf = None
@@ -630,6 +633,24 @@ def _finite(x):
     if isinstance(x, float) and not np.isfinite(x):
         return None
     return x
+
+
+def stage_hbm(ms, sizes, core_sizes, model, precision):
+    """Algorithmic HBM rates of the gather and the scatter (GB/s, from the stage times): the
+    gather reads H's ELL (4 + 8 bytes per slot) and writes every padded block (4 bytes per
+    element for the low-precision loops, 8 for FP64); the scatter reads the core columns (8
+    bytes per entry) and writes D's column-ELL (4 + 8 bytes per entry)."""
+    npad = (np.asarray(sizes, dtype=np.int64) + 63) // 64 * 64
+    elem = 8 if precision == "fp64" else 4
+    h_bytes = model["H_col"].size * 12
+    gather = float((npad * npad).sum() * elem + h_bytes)
+    scatter = float((np.asarray(core_sizes, dtype=np.int64) * sizes).sum() * (8 + 12))
+    out = {"gather_bytes": gather, "scatter_bytes": scatter}
+    if ms.get("gather", 0) > 0:
+        out["gather"] = gather / (ms["gather"] * 1e-3) / 1e9
+    if ms.get("scatter", 0) > 0:
+        out["scatter"] = scatter / (ms["scatter"] * 1e-3) / 1e9
+    return out
 
 
 def measure(gb, torch, args, precision, model, cfg, Hc, Hv, D, golden, sizes):

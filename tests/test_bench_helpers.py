@@ -55,3 +55,18 @@ def test_symmetric_square_flops():
     # n = 2: upper entries (0,0), (0,1), (1,1), 2n = 4 flops each = 12 = n^2 (n + 1)
     assert bench.sym_square_flops([2], 1) == 12.0
     assert bench.sym_square_flops([2, 3], 6) == 6 * (12.0 + 36.0)
+
+
+def test_stage_hbm_bytes():
+    """Gather: padded blocks (64-multiples) times the element size plus H's ELL; scatter: 20
+    bytes per D entry (core columns times subgraph rows)."""
+    import numpy as np
+    import bench
+    model = {"H_col": np.zeros((10, 3), np.int32)}
+    out = bench.stage_hbm({"gather": 1.0, "scatter": 2.0}, np.array([65, 64]),
+                          np.array([2, 3]), model, "fp16x3")
+    assert out["gather_bytes"] == (128 * 128 + 64 * 64) * 4 + 30 * 12
+    assert out["scatter_bytes"] == (2 * 65 + 3 * 64) * 20
+    assert abs(out["gather"] - out["gather_bytes"] / 1e-3 / 1e9) < 1e-9
+    fp64 = bench.stage_hbm({}, np.array([65]), np.array([2]), model, "fp64")
+    assert fp64["gather_bytes"] == 128 * 128 * 8 + 30 * 12 and "gather" not in fp64
