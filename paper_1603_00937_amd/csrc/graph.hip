@@ -159,47 +159,136 @@ __global__ void k_x0(const int32_t* __restrict__ col, const double* __restrict__
 }
 
 // ---- X2 graph, one workgroup per row i --------------------------------------------------
-// LDS: candidate bitmap over all n vertices, per-word rank base, accumulators of the
-// candidates (indexed by rank), and row i's columns / x0 values.
+// The edge (i, j) is decided by |(X0^2)_ij| >= tau, the entry summed over k in row i in
+// ascending order (row i's slots in order), every product and sum rounded separately.  The
+// kernels accumulate the entries with LDS atomic adds instead, in whatever order the adds
+// land, with no barrier between the rows k, and keep that order's result only where it cannot
+// change the decision: two summation orders of the same m rounded products p_k differ by at
+// most 2 gamma_{m-1} sum |p_k| (gamma_m = m u / (1 - m u), u = 2^-53; the standard bound on
+// recursive summation), and sum_k |x0_ik x0_kj| <= b_i = sum_k |x0_ik| max_l |x0_kl|.  A
+// candidate with | |acc| - tau | within twice that of tau (at most a few per graph, usually
+// none) is summed again in ascending order by one wave, so the graph is the one of the
+// ascending sums bit for bit.
 //   1. mark every j in row k for every k in row i (two-hop candidates) and i itself;
 //   2. rank = number of candidates below j (per-word popcount prefix);
-//   3. for k in row i, ascending: acc[rank(j)] += x0_ik * x0_kj for j in row k -- each j
-//      appears once per k, and a barrier separates the k steps, so every accumulator takes
-//      its terms in ascending k;
-//   4. keep j if |acc| >= tau or j == i: the count, and the sorted columns into the row's slot
-//      of a staging array (cap entries per row; k_x2_compact then packs them into the CSR), so
-//      the product is computed once.
+//   3. acc[rank(j)] += x0_ik * x0_kj over every (k, j), LDS atomic adds;
+//   4. keep j if j == i or |acc| >= tau (re-summed in ascending order near tau): the count,
+//      and the sorted columns into the row's slot of a staging array (cap entries per row;
+//      k_x2_compact then packs them into the CSR), so the product is computed once.
+// LDS: candidate bitmap over all n vertices, per-word rank base, accumulators of the
+// candidates (indexed by rank), and row i's columns / x0 values.
 struct X2Lds {
   uint32_t* bits;
   int32_t* pre;
   double* acc;
   int32_t* ci;
   double* xi;
-  int32_t* wcnt;
 };
 
-__device__ __forceinline__ int32_t block_sum_i32(int32_t v, int32_t* red) {
-  __syncthreads();
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int s = kT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
+constexpr int kX2Q = 4;  // ELL width limit: kX2Q * kT (the float index split below needs < 2048)
+constexpr int kX2B = 8;  // (k, j) pairs whose loads a thread has in flight at once
+
+// the (slot t of row i, slot u of row k) pair number p = t w + u, split without an integer
+// division: (p + 0.5) / w is at least 0.5 / w away from an integer and p < w^2 < 2^22, so the
+// float quotient truncates to t (the correction below is a guard)
+__device__ __forceinline__ void x2_pair(int p, int w, float inv_w, int& t, int& u) {
+  t = (int)(((float)p + 0.5f) * inv_w);
+  u = p - t * w;
+  if (u < 0) {
+    --t;
+    u += w;
+  } else if (u >= w) {
+    ++t;
+    u -= w;
   }
-  const int32_t r = red[0];
-  __syncthreads();
-  return r;
 }
 
+// the rows k of row i are its slots before the first padding entry
+__device__ __forceinline__ int x2_row_width(const int32_t* ci, int w, int n, int32_t* red) {
+  if (threadIdx.x == 0) red[0] = w;
+  __syncthreads();
+  for (int t = threadIdx.x; t < w; t += kT)
+    if ((unsigned)ci[t] >= (unsigned)n) atomicMin(&red[0], t);
+  __syncthreads();
+  const int kw = red[0];
+  __syncthreads();  // red is reused
+  return kw;
+}
 
-constexpr int kX2Q = 4;  // ELL row entries per thread in the X2 accumulation (width <= 1024)
+// step 1 and step 3 over the kw * w pairs: mark(j), or add(j, x0_ik * x0_kj)
+template <bool ADD, class F>
+__device__ __forceinline__ void x2_pairs(const int32_t* __restrict__ hcol,
+                                         const double* __restrict__ x0, const int32_t* ci,
+                                         const double* xi, int kw, int w, float inv_w, int n,
+                                         F&& f) {
+  const int npair = kw * w;
+  for (int p0 = threadIdx.x; p0 < npair; p0 += kX2B * kT) {
+    int32_t jj[kX2B];
+    double pr[kX2B];
+#pragma unroll
+    for (int q = 0; q < kX2B; ++q) {
+      const int p = p0 + q * kT;
+      jj[q] = -1;
+      pr[q] = 0.0;
+      if (p < npair) {
+        int t, u;
+        x2_pair(p, w, inv_w, t, u);
+        const int64_t e = (int64_t)ci[t] * w + u;
+        jj[q] = hcol[e];
+        if (ADD) pr[q] = x0[e];
+        if (ADD) pr[q] = xi[t] * pr[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kX2B; ++q)
+      if ((unsigned)jj[q] < (unsigned)n) f(jj[q], pr[q]);
+  }
+}
+
+// the half-width of the band around tau in which the order of the sum may decide (see above):
+// twice the bound, b_i rounded, a term for underflow
+__device__ __forceinline__ double x2_margin(int kw, double b, double tau) {
+  return (4.0 * kw + 8.0) * 0x1p-53 * b + 4.0 * 0x1p-53 * tau + 1e-300;
+}
+
+// (X0^2)_ij summed in ascending order of row i's slots, every product and sum rounded
+// separately, by a whole wave: lane l looks j up in the rows k of slots l, l + 64, ... (a scan
+// of the row, which assumes nothing of its order) and the products are added one slot after
+// the other.
+__device__ double x2_sum_ascending(const int32_t* __restrict__ hcol,
+                                   const double* __restrict__ x0, const int32_t* ci,
+                                   const double* xi, int kw, int w, int32_t j) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  for (int t0 = 0; t0 < kw; t0 += 64) {
+    const int t = t0 + lane;
+    double prod = 0.0;
+    int found = 0;
+    if (t < kw) {
+      const int64_t base = (int64_t)ci[t] * w;
+      for (int u = 0; u < w; ++u)
+        if (hcol[base + u] == j) {
+          found = 1;
+          prod = xi[t] * x0[base + u];
+          break;
+        }
+    }
+    const int m = min(64, kw - t0);
+    for (int l = 0; l < m; ++l)
+      if (__shfl(found, l)) acc = acc + __shfl(prod, l);
+  }
+  return acc;
+}
 
 __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol,
-                                                const double* __restrict__ x0, int n, int w,
-                                                double tau, int cap, int32_t* __restrict__ cnt,
+                                                const double* __restrict__ x0,
+                                                const double* __restrict__ rbound, int n, int w,
+                                                float inv_w, double tau, int all_ascending,
+                                                int cap, int32_t* __restrict__ cnt,
                                                 int32_t* __restrict__ rows,
                                                 int32_t* __restrict__ overflow) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t nband;
   const int i = blockIdx.x;
   const int nw = (n + 31) >> 5;
   X2Lds L;
@@ -208,23 +297,19 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
   L.bits = reinterpret_cast<uint32_t*>(L.xi + w);
   L.pre = reinterpret_cast<int32_t*>(L.bits + nw);
   L.ci = L.pre + nw + 1;
-  L.wcnt = L.ci + w;
-  int32_t* red = L.wcnt + nw;  // kT ints
+  int32_t* red = L.ci + w;  // kT ints
 
   for (int t = threadIdx.x; t < w; t += kT) {
     L.ci[t] = hcol[(int64_t)i * w + t];
     L.xi[t] = x0[(int64_t)i * w + t];
   }
   for (int q = threadIdx.x; q < nw; q += kT) L.bits[q] = 0u;
-  __syncthreads();
+  if (threadIdx.x == 0) nband = 0;
+  const int kw = x2_row_width(L.ci, w, n, red);
   // 1. two-hop candidates
-  for (int p = threadIdx.x; p < w * w; p += kT) {  // entries outside [0, n) are padding
-    const int t = p / w, u = p - t * w;
-    const int32_t k = L.ci[t];
-    if ((unsigned)k >= (unsigned)n) continue;
-    const int32_t j = hcol[(int64_t)k * w + u];
-    if ((unsigned)j < (unsigned)n) atomicOr(&L.bits[j >> 5], 1u << (j & 31));
-  }
+  x2_pairs<false>(hcol, x0, L.ci, L.xi, kw, w, inv_w, n, [&](int32_t j, double) {
+    atomicOr(&L.bits[j >> 5], 1u << (j & 31));
+  });
   if (threadIdx.x == 0) atomicOr(&L.bits[i >> 5], 1u << (i & 31));
   __syncthreads();
   // 2. ranks
@@ -238,106 +323,111 @@ __global__ __launch_bounds__(kT) void k_x2_rows(const int32_t* __restrict__ hcol
     }
     return;
   }
-  // the rows k taken are those before the first padding entry of row i
-  if (threadIdx.x == 0) red[0] = w;
   for (int r = threadIdx.x; r < ncand; r += kT) L.acc[r] = 0.0;
   __syncthreads();
-  for (int t = threadIdx.x; t < w; t += kT)
-    if ((unsigned)L.ci[t] >= (unsigned)n) atomicMin(&red[0], t);
+  // 3. accumulation, adds in any order
+  x2_pairs<true>(hcol, x0, L.ci, L.xi, kw, w, inv_w, n, [&](int32_t j, double prod) {
+    const uint32_t word = L.bits[j >> 5];
+    const int r = L.pre[j >> 5] + __popc(word & ((1u << (j & 31)) - 1u));
+    atomicAdd(&L.acc[r], prod);
+  });
   __syncthreads();
-  const int kw = red[0];
-  // 3. canonical accumulation, k ascending: one barrier per row k.  Each thread holds the
-  //    entries of the next two rows in registers (w <= kX2Q kT, checked on the host), so their
-  //    global reads overlap the LDS updates of the current row.
-  int32_t ja[kX2Q], jb[kX2Q], jc[kX2Q];
-  double xa[kX2Q], xb[kX2Q], xc[kX2Q];
-  auto fetch = [&](int t, int32_t (&jj)[kX2Q], double (&xx)[kX2Q]) {
-    const bool on = t < kw;
-    const int32_t k = on ? L.ci[t] : 0;
-#pragma unroll
-    for (int q = 0; q < kX2Q; ++q) {
-      const int u = threadIdx.x + q * kT;
-      jj[q] = -1;
-      xx[q] = 0.0;
-      if (on && u < w) {
-        jj[q] = hcol[(int64_t)k * w + u];
-        xx[q] = x0[(int64_t)k * w + u];
-      }
-    }
-  };
-  auto apply = [&](int t, const int32_t (&jj)[kX2Q], const double (&xx)[kX2Q]) {
-    if (t >= kw) return;
-    const double xik = L.xi[t];
-#pragma unroll
-    for (int q = 0; q < kX2Q; ++q) {
-      const int32_t j = jj[q];
-      if ((unsigned)j >= (unsigned)n) continue;
-      const uint32_t word = L.bits[j >> 5];
-      const int r = L.pre[j >> 5] + __popc(word & ((1u << (j & 31)) - 1u));
-      const double prod = xik * xx[q];
-      L.acc[r] = L.acc[r] + prod;
-    }
-  };
-  fetch(0, ja, xa);
-  fetch(1, jb, xb);
-  for (int t = 0; t < kw; t += 3) {
-    fetch(t + 2, jc, xc);
-    apply(t, ja, xa);
-    __syncthreads();
-    fetch(t + 3, ja, xa);
-    apply(t + 1, jb, xb);
-    __syncthreads();
-    fetch(t + 4, jb, xb);
-    apply(t + 2, jc, xc);
-    __syncthreads();
-  }
-  // 4. keep decision and ordered compaction
+  // 4. decisions: bits[q] becomes the word's kept set, pre[q] (no longer needed for ranks)
+  //    its candidates near tau, then its kept count
+  const double margin = x2_margin(kw, rbound[i], tau);
   for (int q = threadIdx.x; q < nw; q += kT) {
-    uint32_t word = L.bits[q];
+    uint32_t word = L.bits[q], keep = 0u, band = 0u;
     int r = L.pre[q];
-    int32_t c = 0;
     while (word) {
       const int b = __ffs(word) - 1;
       const int j = (q << 5) + b;
-      if (fabs(L.acc[r]) >= tau || j == i) ++c;
+      const double a = fabs(L.acc[r]);
+      if (j == i) keep |= 1u << b;
+      else if (all_ascending || fabs(a - tau) <= margin) band |= 1u << b;
+      else if (a >= tau) keep |= 1u << b;
       ++r;
       word &= word - 1u;
     }
-    L.wcnt[q] = c;
+    L.bits[q] = keep;
+    L.pre[q] = (int32_t)band;
+    if (band) atomicAdd(&nband, __popc(band));
   }
   __syncthreads();
-  const int32_t kept = lds_exclusive_scan<kT>(L.wcnt, nw, red);
+  if (nband > 0) {
+    // ascending sums of the candidates near tau, one wave per word
+    for (int q = threadIdx.x >> 6; q < nw; q += kT / 64) {
+      uint32_t band = (uint32_t)L.pre[q];
+      while (band) {
+        const int b = __ffs(band) - 1;
+        const double a = fabs(x2_sum_ascending(hcol, x0, L.ci, L.xi, kw, w, (q << 5) + b));
+        if ((threadIdx.x & 63) == 0 && a >= tau) atomicOr(&L.bits[q], 1u << b);
+        band &= band - 1u;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < nw; q += kT) L.pre[q] = __popc(L.bits[q]);
+  __syncthreads();
+  const int32_t kept = lds_exclusive_scan<kT>(L.pre, nw, red);
   if (threadIdx.x == 0) cnt[i] = kept;
   int32_t* dst = rows + (int64_t)i * cap;  // kept <= ncand <= cap
   for (int q = threadIdx.x; q < nw; q += kT) {
     uint32_t word = L.bits[q];
-    int r = L.pre[q];
-    int32_t pos = L.wcnt[q];
+    int32_t pos = L.pre[q];
     while (word) {
       const int b = __ffs(word) - 1;
-      const int j = (q << 5) + b;
-      if (fabs(L.acc[r]) >= tau || j == i) dst[pos++] = j;
-      ++r;
+      dst[pos++] = (q << 5) + b;
       word &= word - 1u;
     }
   }
 }
 
+// max_l |x0_kl| of every row k (one wave per row)
+__global__ __launch_bounds__(kT) void k_row_absmax(const double* __restrict__ x0, int n, int w,
+                                                   double* __restrict__ out) {
+  const int row = blockIdx.x * (kT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double m = 0.0;
+  for (int u = lane; u < w; u += 64) m = fmax(m, fabs(x0[(int64_t)row * w + u]));
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if (lane == 0) out[row] = m;
+}
+
+// b_i = sum over the slots of row i of |x0_ik| max_l |x0_kl|, which bounds sum_k |x0_ik x0_kj|
+// for every j (one wave per row)
+__global__ __launch_bounds__(kT) void k_x2_bound(const int32_t* __restrict__ col,
+                                                 const double* __restrict__ x0,
+                                                 const double* __restrict__ amax, int n, int w,
+                                                 double* __restrict__ out) {
+  const int row = blockIdx.x * (kT / 64) + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double b = 0.0;
+  for (int u = lane; u < w; u += 64) {
+    const int64_t e = (int64_t)row * w + u;
+    const int32_t k = col[e];
+    if ((unsigned)k < (unsigned)n) b += fabs(x0[e]) * amax[k];
+  }
+  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o);
+  if (lane == 0) out[row] = b;
+}
+
 // The same rows for any n: the two-hop candidates of row i go into an LDS hash set instead of
-// an n-bit bitmap and are sorted to fix their ranks; the accumulation (ascending k, one barrier
-// per row k) and the keep rule are those of k_x2_rows, so the graph is the same bit for bit.
-// LDS: acc [cap], x0 of row i [w], keys and their ranks [2^log2h each], the sorted candidates
-// [2^log2u >= cap], columns of row i [w], scratch [kT].  Inserts stop once more than cap
-// candidates were counted (at most kT more land, and 2^log2h >= cap + kT + 1 keeps the set from
-// filling); such a row reports its count through `overflow`.
+// an n-bit bitmap and are sorted to fix their ranks; accumulation and decisions are those of
+// k_x2_rows, so the graph is the same bit for bit.  LDS: acc [cap], x0 of row i [w], keys and
+// their ranks [2^log2h each], the sorted candidates [2^log2u >= cap], columns of row i [w],
+// scratch [kT].  Inserts stop once more than cap candidates were counted (at most kT more
+// land, and 2^log2h >= cap + kT + 1 keeps the set from filling); such a row reports its count
+// through `overflow`.
 __global__ __launch_bounds__(kT) void k_x2_rows_hash(const int32_t* __restrict__ hcol,
-                                                     const double* __restrict__ x0, int n, int w,
-                                                     double tau, int cap, int log2h, int log2u,
-                                                     int32_t* __restrict__ cnt,
+                                                     const double* __restrict__ x0,
+                                                     const double* __restrict__ rbound, int n,
+                                                     int w, float inv_w, double tau,
+                                                     int all_ascending, int cap, int log2h,
+                                                     int log2u, int32_t* __restrict__ cnt,
                                                      int32_t* __restrict__ rows,
                                                      int32_t* __restrict__ overflow) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int32_t count, gathered;
+  __shared__ int32_t count, gathered, nband;
   const int i = blockIdx.x;
   const int H = 1 << log2h, P = 1 << log2u;
   double* acc = reinterpret_cast<double*>(smem);
@@ -355,19 +445,14 @@ __global__ __launch_bounds__(kT) void k_x2_rows_hash(const int32_t* __restrict__
   if (threadIdx.x == 0) {
     count = 0;
     gathered = 0;
+    nband = 0;
   }
-  __syncthreads();
+  const int kw = x2_row_width(ci, w, n, red);
   // 1. two-hop candidates (and i itself)
   if (threadIdx.x == 0 && hset_insert(keys, log2h, i)) atomicAdd(&count, 1);
-  for (int p = threadIdx.x; p < w * w; p += kT) {
-    const int t = p / w, u = p - t * w;
-    const int32_t k = ci[t];
-    if ((unsigned)k >= (unsigned)n) continue;
-    const int32_t j = hcol[(int64_t)k * w + u];
-    if ((unsigned)j >= (unsigned)n) continue;
-    if (*(volatile int32_t*)&count > cap) break;
-    if (hset_insert(keys, log2h, j)) atomicAdd(&count, 1);
-  }
+  x2_pairs<false>(hcol, x0, ci, xi, kw, w, inv_w, n, [&](int32_t j, double) {
+    if (*(volatile int32_t*)&count <= cap && hset_insert(keys, log2h, j)) atomicAdd(&count, 1);
+  });
   __syncthreads();
   const int ncand = count;
   if (ncand > cap) {
@@ -389,63 +474,40 @@ __global__ __launch_bounds__(kT) void k_x2_rows_hash(const int32_t* __restrict__
     rk[hset_find(keys, log2h, U[r])] = r;
     acc[r] = 0.0;
   }
-  if (threadIdx.x == 0) red[0] = w;
   __syncthreads();
-  for (int t = threadIdx.x; t < w; t += kT)
-    if ((unsigned)ci[t] >= (unsigned)n) atomicMin(&red[0], t);
+  // 3. accumulation, adds in any order
+  x2_pairs<true>(hcol, x0, ci, xi, kw, w, inv_w, n, [&](int32_t j, double prod) {
+    atomicAdd(&acc[rk[hset_find(keys, log2h, j)]], prod);
+  });
   __syncthreads();
-  const int kw = red[0];
+  // 4. decisions (rk reused: 1 kept, 0 dropped, 2 near tau), ascending sums near tau, ordered
+  //    compaction
+  const double margin = x2_margin(kw, rbound[i], tau);
+  for (int r = threadIdx.x; r < ncand; r += kT) {
+    const double a = fabs(acc[r]);
+    int f;
+    if (U[r] == i) f = 1;
+    else if (all_ascending || fabs(a - tau) <= margin) f = 2;
+    else f = a >= tau ? 1 : 0;
+    rk[r] = f;
+    if (f == 2) atomicAdd(&nband, 1);
+  }
   __syncthreads();
-  // 3. canonical accumulation, k ascending, one barrier per row k (as k_x2_rows)
-  int32_t ja[kX2Q], jb[kX2Q], jc[kX2Q];
-  double xa[kX2Q], xb[kX2Q], xc[kX2Q];
-  auto fetch = [&](int t, int32_t (&jj)[kX2Q], double (&xx)[kX2Q]) {
-    const bool on = t < kw;
-    const int32_t k = on ? ci[t] : 0;
-#pragma unroll
-    for (int q = 0; q < kX2Q; ++q) {
-      const int u = threadIdx.x + q * kT;
-      jj[q] = -1;
-      xx[q] = 0.0;
-      if (on && u < w) {
-        jj[q] = hcol[(int64_t)k * w + u];
-        xx[q] = x0[(int64_t)k * w + u];
-      }
+  if (nband > 0) {
+    for (int r = threadIdx.x >> 6; r < ncand; r += kT / 64) {
+      if (rk[r] != 2) continue;  // uniform over the wave
+      const double a = fabs(x2_sum_ascending(hcol, x0, ci, xi, kw, w, U[r]));
+      if ((threadIdx.x & 63) == 0) rk[r] = a >= tau ? 1 : 0;
     }
-  };
-  auto apply = [&](int t, const int32_t (&jj)[kX2Q], const double (&xx)[kX2Q]) {
-    if (t >= kw) return;
-    const double xik = xi[t];
-#pragma unroll
-    for (int q = 0; q < kX2Q; ++q) {
-      const int32_t j = jj[q];
-      if ((unsigned)j >= (unsigned)n) continue;
-      const int r = rk[hset_find(keys, log2h, j)];
-      const double prod = xik * xx[q];
-      acc[r] = acc[r] + prod;
-    }
-  };
-  fetch(0, ja, xa);
-  fetch(1, jb, xb);
-  for (int t = 0; t < kw; t += 3) {
-    fetch(t + 2, jc, xc);
-    apply(t, ja, xa);
-    __syncthreads();
-    fetch(t + 3, ja, xa);
-    apply(t + 1, jb, xb);
-    __syncthreads();
-    fetch(t + 4, jb, xb);
-    apply(t + 2, jc, xc);
     __syncthreads();
   }
-  // 4. keep decision and ordered compaction (rk reused for the kept flags and their offsets)
-  for (int r = threadIdx.x; r < ncand; r += kT) rk[r] = (fabs(acc[r]) >= tau || U[r] == i) ? 1 : 0;
+  for (int r = threadIdx.x; r < ncand; r += kT) acc[r] = rk[r];  // the flags, for the writes
   __syncthreads();
   const int32_t kept = lds_exclusive_scan<kT>(rk, ncand, red);
   if (threadIdx.x == 0) cnt[i] = kept;
   int32_t* dst = rows + (int64_t)i * cap;
   for (int r = threadIdx.x; r < ncand; r += kT)
-    if (fabs(acc[r]) >= tau || U[r] == i) dst[rk[r]] = U[r];
+    if (acc[r] != 0.0) dst[rk[r]] = U[r];
 }
 
 size_t x2_hash_lds_bytes(int w, int cap, int log2h, int log2u) {
@@ -467,7 +529,7 @@ __global__ __launch_bounds__(kT) void k_x2_compact(const int32_t* __restrict__ r
 size_t x2_lds_bytes(int n, int w, int cap) {
   const int nw = (n + 31) >> 5;
   return (size_t)cap * 8 + (size_t)w * 8 + (size_t)nw * 4 + (size_t)(nw + 1) * 4 + (size_t)w * 4 +
-         (size_t)nw * 4 + (size_t)kT * 4 + 64;
+         (size_t)kT * 4 + 64;
 }
 
 // ---- row unions through an LDS bitmap (pattern graphs, symmetrisation) --------------------
@@ -792,12 +854,35 @@ void x0_ell(const gb_ell& H, double emin, double emax, double* x0, hipStream_t s
 
 // X2 graph through the hash-set kernel: candidate capacity 2048 to start with (two workgroups
 // per CU), raised to the largest count a row reports and run again (at most twice).
+// the bounds b_i of the X2 kernels' order-free sums (see k_x2_rows)
+void x2_row_bounds(const gb_ell& H, const double* x0, DBuf<double>& rb, hipStream_t s) {
+  const int n = H.n, w = H.width;
+  DBuf<double> amax(n, s);
+  rb = DBuf<double>(n, s);
+  const int nb = blocks_for(n, kT / 64);
+  hipLaunchKernelGGL(k_row_absmax, dim3(nb), dim3(kT), 0, s, x0, n, w, amax.get());
+  GB_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_x2_bound, dim3(nb), dim3(kT), 0, s, H.col, x0, amax.get(), n, w,
+                     rb.get());
+  GB_LAUNCH_CHECK();
+}
+
+// GB_X2_SUMS=ascending: every candidate is summed again in ascending order (a check of the
+// path that the candidates near tau take)
+int x2_all_ascending() {
+  const char* e = std::getenv("GB_X2_SUMS");
+  return e && std::string(e) == "ascending" ? 1 : 0;
+}
+
 void graph_x2_hash(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream_t s) {
   const int n = H.n, w = H.width;
   if (w > kX2Q * kT) fail(GB_EUNSUPPORTED, "X2 graph: ELL width %d above %d", w, kX2Q * kT);
   int cap = (int)std::min<int64_t>(std::min<int64_t>((int64_t)w * w, n) + 1, 2048);
   cap = std::max(cap, kT);
   DBuf<int32_t> cnt(n, s), ovf(1, s), rows;
+  DBuf<double> rb;
+  x2_row_bounds(H, x0, rb, s);
+  const int all_asc = x2_all_ascending();
   out.n = n;
   out.row_ptr = DBuf<int32_t>(n + 1, s);
   int32_t h[2] = {0, 0};
@@ -808,8 +893,9 @@ void graph_x2_hash(const gb_ell& H, const double* x0, double tau, Csr& out, hipS
       fail(GB_EUNSUPPORTED, "X2 graph: a row has %d two-hop candidates, more than LDS holds", cap);
     rows = DBuf<int32_t>((size_t)n * cap, s);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
-    hipLaunchKernelGGL(k_x2_rows_hash, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, cap,
-                       log2h, log2u, cnt.get(), rows.get(), ovf.get());
+    hipLaunchKernelGGL(k_x2_rows_hash, dim3(n), dim3(kT), lds, s, H.col, x0, rb.get(), n, w,
+                       1.0f / (float)w, tau, all_asc, cap, log2h, log2u, cnt.get(), rows.get(),
+                       ovf.get());
     GB_LAUNCH_CHECK();
     exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
     GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));
@@ -833,15 +919,19 @@ void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream
     graph_x2_hash(H, x0, tau, out, s);
     return;
   }
-  // candidate capacity: small enough for several workgroups per CU; a row with more two-hop
-  // candidates makes the counting pass report its count, and both passes rerun with it
+  // candidate capacity: small enough for six or more workgroups per CU at n up to ~2e4 (the
+  // accumulators are most of the LDS); a row with more two-hop candidates makes the launch
+  // report its count, and the launch reruns with it
   if (w > kX2Q * kT) fail(GB_EUNSUPPORTED, "X2 graph: ELL width %d above %d", w, kX2Q * kT);
   const size_t fixed = x2_lds_bytes(n, w, 0);
   if (fixed > 150 * 1024) fail(GB_EUNSUPPORTED, "X2 graph: n = %d too large for one LDS bitmap", n);
   const int64_t cap_lds = (int64_t)((160 * 1024 - fixed) / 8);
-  int64_t cap = std::min<int64_t>(std::min<int64_t>((int64_t)w * w, n), 4096);
+  int64_t cap = std::min<int64_t>(std::min<int64_t>((int64_t)w * w, n), 2048);
   cap = std::min(cap, cap_lds);
   DBuf<int32_t> cnt(n, s), ovf(1, s), rows;
+  DBuf<double> rb;
+  x2_row_bounds(H, x0, rb, s);
+  const int all_asc = x2_all_ascending();
   out.n = n;
   out.row_ptr = DBuf<int32_t>(n + 1, s);
   int32_t h[2];
@@ -850,8 +940,8 @@ void graph_x2(const gb_ell& H, const double* x0, double tau, Csr& out, hipStream
     check_lds(lds, "X2 graph");
     rows = DBuf<int32_t>((size_t)n * cap, s);
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ovf.get(), (int64_t)1);
-    hipLaunchKernelGGL(k_x2_rows, dim3(n), dim3(kT), lds, s, H.col, x0, n, w, tau, (int)cap,
-                       cnt.get(), rows.get(), ovf.get());
+    hipLaunchKernelGGL(k_x2_rows, dim3(n), dim3(kT), lds, s, H.col, x0, rb.get(), n, w,
+                       1.0f / (float)w, tau, all_asc, (int)cap, cnt.get(), rows.get(), ovf.get());
     GB_LAUNCH_CHECK();
     exclusive_scan_i32(cnt.get(), out.row_ptr.get(), n, s);
     GB_HIP(hipMemcpyAsync(&h[0], out.row_ptr.get() + n, 4, hipMemcpyDeviceToHost, s));

@@ -51,6 +51,50 @@ def test_x2_graph_bit_exact(gb, model_cache, name, tau):
     assert np.array_equal(rp, orp) and np.array_equal(cl, ocl)
 
 
+@pytest.mark.parametrize("sets", ["bitmap", "hash"])
+@pytest.mark.parametrize("name,tau", [("tiny48", 1e-2), ("tiny48", 0.0), ("small256", 1e-5),
+                                      ("n1024", 1e-5)])
+def test_x2_graph_every_candidate_resummed(gb, model_cache, name, tau, sets, monkeypatch):
+    """The X2 kernels sum the entries in any order and re-sum in ascending k the candidates
+    whose decision that order could change; GB_X2_SUMS=ascending sends every candidate through
+    that re-summation: the graph is still the oracle's bit for bit."""
+    from oracle.graph import graph_x2
+    m = model_cache(name)
+    monkeypatch.setenv("GB_X2_SUMS", "ascending")
+    monkeypatch.setenv("GB_VERTEX_SETS", sets)
+    g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), tau)
+    rp, cl = _host(*g.arrays())
+    orp, ocl = graph_x2(m["H_col"], m["H_val"], tau)
+    assert np.array_equal(rp, orp) and np.array_equal(cl, ocl)
+
+
+@pytest.mark.parametrize("sets", ["bitmap", "hash"])
+def test_x2_graph_threshold_on_an_entry(gb, model_cache, sets, monkeypatch):
+    """tau set to the ascending-order value |(X0^2)_ij| of candidates (so the GPU's own sum,
+    taken in another order, may land on either side of it), and to the next double above:
+    the edge is kept at tau and dropped just above, as the oracle decides."""
+    from oracle.bounds import gershgorin, x0_values
+    from oracle.graph import graph_x2, x2_rows
+    m = model_cache("small256")
+    monkeypatch.setenv("GB_VERTEX_SETS", sets)
+    emin, emax = gershgorin(m["H_col"], m["H_val"])
+    x0 = x0_values(m["H_col"], m["H_val"], emin, emax)
+    rows = np.array([3, 77, 200])
+    (_, acc, touched), = list(x2_rows(m["H_col"], x0, rows, chunk=len(rows)))
+    vals = []
+    for r, i in enumerate(rows):
+        cand = np.flatnonzero(touched[r])
+        cand = cand[cand != i]
+        a = np.abs(acc[r, cand])
+        vals.append(float(np.sort(a)[len(a) // 2]))  # a mid-sized entry of the row
+    for v in vals:
+        for tau in (v, float(np.nextafter(v, np.inf))):
+            g = gb.build_graph(_dev(m["H_col"]), _dev(m["H_val"]), tau)
+            rp, cl = _host(*g.arrays())
+            orp, ocl = graph_x2(m["H_col"], m["H_val"], tau)
+            assert np.array_equal(rp, orp) and np.array_equal(cl, ocl)
+
+
 def test_pattern_graph_bit_exact(gb, model_cache):
     from oracle.graph import graph_pattern
     m = model_cache("small256")
