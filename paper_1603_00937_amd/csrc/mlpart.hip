@@ -197,7 +197,9 @@ bool heavier(const Level& f, int e, int u, int e2, int u2) {
   if (f.vw[u] != f.vw[u2]) return f.vw[u] < f.vw[u2];
   return u < u2;
 }
-void top_candidates(const Level& f, std::vector<int32_t>& top) {
+// Only vertices that can pair with some vertex (vw[v] + min vw <= cap) get a list: the matching
+// never reads the others'.
+void top_candidates(const Level& f, int cap, int min_vw, std::vector<int32_t>& top) {
   const int n = f.n;
   top.assign((size_t)n * kTop, -1);
   const int nt = f.rp[n] >= (1 << 16) ? worker_count() : 1;
@@ -205,6 +207,7 @@ void top_candidates(const Level& f, std::vector<int32_t>& top) {
     const int v0 = (int)((int64_t)n * t / nt), v1 = (int)((int64_t)n * (t + 1) / nt);
     int te[kTop];
     for (int v = v0; v < v1; ++v) {
+      if (f.vw[v] + min_vw > cap) continue;
       int m = 0;
       for (int e = f.rp[v]; e < f.rp[v + 1]; ++e) {
         const int u = f.adj[e];
@@ -225,14 +228,24 @@ void top_candidates(const Level& f, std::vector<int32_t>& top) {
 bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
              const int32_t* given_top = nullptr) {
   const int n = f.n;
+  // a vertex whose weight plus the smallest weight exceeds cap has no partner (the search below
+  // would find none): it stays single without a look at its row, and when no two vertices fit
+  // together no pair can form at all
+  int min_vw = INT_MAX;
+  for (int v = 0; v < n; ++v) min_vw = std::min(min_vw, f.vw[v]);
+  if (n < 2 || 2 * (int64_t)min_vw > cap) return false;
   std::vector<int32_t>& match = sc.match;
   match.assign(n, -1);
-  if (!given_top) top_candidates(f, sc.top);
+  if (!given_top) top_candidates(f, cap, min_vw, sc.top);
   const int32_t* top = given_top ? given_top : sc.top.data();
   const std::vector<int32_t>& order = visit_order(n, level, sc);
   bool any = false;
   for (int v : order) {
     if (match[v] >= 0) continue;
+    if (f.vw[v] + min_vw > cap) {
+      match[v] = v;
+      continue;
+    }
     int best = -1;
     bool listed_all = true;  // the list holds every neighbour, so no scan is needed
     for (int i = 0; i < kTop; ++i) {

@@ -6,6 +6,9 @@
 #include "lds_hash.h"
 #include "lds_scan.h"
 
+#include <map>
+#include <mutex>
+
 namespace gbi {
 namespace {
 
@@ -425,6 +428,36 @@ void partition_from_cores(const Csr& g, const std::vector<int32_t>& core_ptr,
   finish_partition(g, P, s);
 }
 
+// A second stream per device for the copies that overlap the weights kernel (created on first
+// use with the default priority and kept for the life of the process).
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  GB_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  GB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  streams[dev] = st;
+  return st;
+}
+
+struct SideCopy {  // an event that orders the side stream after the caller's stream
+  hipEvent_t ev = nullptr;
+  hipStream_t cs = nullptr;
+  SideCopy(hipStream_t s) : cs(side_stream()) {
+    GB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    GB_HIP(hipEventRecord(ev, s));
+    GB_HIP(hipStreamWaitEvent(cs, ev, 0));
+  }
+  ~SideCopy() {
+    (void)hipStreamSynchronize(cs);  // nothing of the copies outlives the call
+    (void)hipEventDestroy(ev);
+  }
+};
+
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
                               MlStats* stats, const Part* prev) {
   const int n = g.n;
@@ -451,6 +484,10 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
   const size_t lds = (size_t)((n + 31) >> 5) * 4;
   if (lds > 160 * 1024) fail(GB_EUNSUPPORTED, "multilevel: n = %d too large for one LDS bitmap", n);
   DBuf<int32_t> dw(std::max<int64_t>(g.nnz, 1), s), dmiss(1, s);
+  // the graph itself goes to the host on the side stream while the weights are computed
+  SideCopy side(s);
+  GB_HIP(hipMemcpyAsync(rp, g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, side.cs));
+  GB_HIP(hipMemcpyAsync(col, g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, side.cs));
   int32_t miss = n;  // no vertex lacks its self loop
   GB_HIP(hipMemcpyAsync(dmiss.get(), &miss, 4, hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_common_nb, dim3(n), dim3(kT), lds, s, n, g.row_ptr.get(), g.col.get(),
@@ -461,11 +498,10 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
                      g.row_ptr.get(), g.col.get(), dw.get(), dtop.get());
   GB_LAUNCH_CHECK();
   int32_t* top = ml_top_buffer(*lease.p, n);  // read by the matching of the input level
-  GB_HIP(hipMemcpyAsync(rp, g.row_ptr.get(), (n + 1) * 4, hipMemcpyDeviceToHost, s));
-  GB_HIP(hipMemcpyAsync(col, g.col.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(w, dw.get(), g.nnz * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(top, dtop.get(), (size_t)n * kMlTop * 4, hipMemcpyDeviceToHost, s));
   GB_HIP(hipMemcpyAsync(&miss, dmiss.get(), 4, hipMemcpyDeviceToHost, s));
+  GB_HIP(hipStreamSynchronize(side.cs));
   GB_HIP(hipStreamSynchronize(s));
   if (miss < n) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", miss);
   partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p, top);
