@@ -416,8 +416,12 @@ std::vector<int32_t> bfs_order(const Level& g) {
 // Parts grown on g (weights <= cap): seeds in breadth-first order; a part repeatedly takes the
 // unassigned neighbour with the largest summed edge weight to it (ties: smaller weight, then
 // smaller index) that still fits.
+// A part that no vertex fits into any more (its weight plus the smallest weight above cap) is
+// closed at once: the search would find nothing.
 std::vector<int32_t> grow_parts(const Level& g, int cap) {
   std::vector<int32_t> part(g.n, -1), conn(g.n, 0), touched;
+  int min_vw = INT_MAX;
+  for (int v = 0; v < g.n; ++v) min_vw = std::min(min_vw, g.vw[v]);
   int np = 0;
   for (int seed : bfs_order(g)) {
     if (part[seed] >= 0) continue;
@@ -428,6 +432,7 @@ std::vector<int32_t> grow_parts(const Level& g, int cap) {
     for (;;) {
       part[v] = p;
       w += g.vw[v];
+      if ((int64_t)w + min_vw > cap) break;
       for (int e = g.rp[v]; e < g.rp[v + 1]; ++e) {
         const int u = g.adj[e];
         if (part[u] >= 0) continue;
