@@ -312,10 +312,17 @@ __global__ __launch_bounds__(kT) void k_common_nb(int n, const int32_t* __restri
     const int v = col[e];
     if (v < u) continue;  // wave-uniform: workgroup v writes this entry
     int c = 0, pos = -1;
-    for (int f = rp[v] + lane; f < rp[v + 1]; f += 64) {
-      const int x = col[f];
-      c += (bits[x >> 5] >> (x & 31)) & 1u;
-      if (x == u) pos = f;
+    const int f1 = rp[v + 1];
+    for (int f = rp[v] + lane; f < f1; f += 4 * 64) {  // four loads in flight per lane
+      int x[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = f + 64 * i < f1 ? col[f + 64 * i] : -1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (x[i] >= 0) {
+          c += (bits[x[i] >> 5] >> (x[i] & 31)) & 1u;
+          if (x[i] == u) pos = f + 64 * i;
+        }
     }
     for (int off = 32; off > 0; off >>= 1) {
       c += __shfl_down(c, off, 64);
