@@ -1005,50 +1005,26 @@ __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, int64
   for (int64_t p = i; p < n; p += stride) out[p] = (TO)in[p] * scale;
 }
 
-// An FP32 iterate made exactly symmetric: out = (X + X^T)/2 per block, formed in FP64 and
-// stored as TO (FP32: rounded once; an entry and its transpose round the same sum, so out
-// stays exactly symmetric).  The split squares compute both triangles of their diagonal tiles,
-// pairing the planes of an entry and of its transpose differently, so the FP32 iterate is
-// symmetric only to rounding; the FP64 refinement relies on symmetry.  One workgroup per pair
-// of 64x64 tiles (a tile and its transpose partner), both read once through LDS and both
-// written.
-template <typename TO>
-__global__ __launch_bounds__(256) void k_sym_convert(const float* __restrict__ X,
-                                                     TO* __restrict__ out,
-                                                     const int64_t* __restrict__ offs,
-                                                     const int32_t* __restrict__ npad,
-                                                     double scale) {
-  __shared__ float ta[64][65], tb[64][65];
-  const int s = blockIdx.y;
-  const int np = npad[s], nt = np / 64;
-  // workgroup t takes the t-th tile pair (bi, bj), bi <= bj, of the upper triangle in row
-  // order: both tiles are read once and both are written
-  int t = blockIdx.x;
-  if (t >= nt * (nt + 1) / 2) return;  // the whole workgroup leaves together
-  int bi = 0;
-  while (t >= nt - bi) {
-    t -= nt - bi;
-    ++bi;
-  }
-  const int bj = bi + t;
-  const float* xs = X + offs[s];
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    ta[r][c] = xs[(int64_t)(bi * 64 + r) * np + bj * 64 + c];
-    tb[r][c] = xs[(int64_t)(bj * 64 + r) * np + bi * 64 + c];
-  }
+// The FP32 iterate made exactly symmetric in place: the split and FP32 squares compute both
+// triangles only inside the 64 x 64 tiles on the diagonal of a block (everything else is
+// computed once and mirrored), pairing the planes of an entry and of its transpose
+// differently there, so X is symmetric only to rounding inside those tiles; the FP64
+// refinement relies on symmetry.  Each such tile becomes (T + T^T)/2, formed in FP64 and
+// rounded once (an entry and its transpose round the same sum).  One workgroup per diagonal
+// tile, read once through LDS.
+__global__ __launch_bounds__(256) void k_sym_diag(float* __restrict__ X,
+                                                  const int64_t* __restrict__ offs,
+                                                  const int32_t* __restrict__ npad) {
+  __shared__ float t[64][65];
+  const int s = blockIdx.y, b = blockIdx.x;
+  const int np = npad[s];
+  if (b * 64 >= np) return;  // the whole workgroup leaves together
+  float* x = X + offs[s] + (int64_t)(b * 64) * np + b * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) t[e >> 6][e & 63] = x[(int64_t)(e >> 6) * np + (e & 63)];
   __syncthreads();
-  TO* os = out + offs[s];
   for (int e = threadIdx.x; e < 64 * 64; e += 256) {
     const int r = e >> 6, c = e & 63;
-    os[(int64_t)(bi * 64 + r) * np + bj * 64 + c] =
-        (TO)(0.5 * ((double)ta[r][c] + (double)tb[c][r]) * scale);
-  }
-  if (bi == bj) return;
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {  // (bj, bi): the same sums, transposed
-    const int r = e >> 6, c = e & 63;
-    os[(int64_t)(bj * 64 + r) * np + bi * 64 + c] =
-        (TO)(0.5 * ((double)tb[r][c] + (double)ta[c][r]) * scale);
+    x[(int64_t)r * np + c] = (float)(0.5 * ((double)t[r][c] + (double)t[c][r]));
   }
 }
 
@@ -1111,7 +1087,9 @@ __global__ __launch_bounds__(kT) void k_idem(const T* __restrict__ X, const T* _
 // slab as they read a block.  Since X is symmetric, the core rows of q(X) are the transposed
 // core columns, and V q(X) for a slab V needs only products V X.
 
-// W = V X on the FP64 matrix cores: a wave computes all KMAX rows of 64 columns of W
+// W = (scale V) X on the FP64 matrix cores (scale a power of two, applied exactly to V's entries
+// as they are loaded: the stored iterate may be X / scale): a wave computes all KMAX rows of 64
+// columns of W
 // (KMAX/16 x 4 tiles of 16 x 16, v_mfma_f64_16x16x4) and walks the reduction in chunks of 16
 // rows of X.  Within a chunk, lane l (i = l%16, q = l/16) takes the four consecutive rows
 // a + 4q + u, u = the MFMA index: its A operands of a row tile are one 32-byte run of V
@@ -1130,7 +1108,7 @@ __global__ __launch_bounds__(256) void k_rows_mm(const TX* __restrict__ X,
                                                  double* __restrict__ W,
                                                  const int64_t* __restrict__ soffs,
                                                  const int32_t* __restrict__ core_ptr,
-                                                 int n_sub, int colblocks) {
+                                                 int n_sub, int colblocks, double scale) {
   using M = Mfma<double>;
   constexpr int MT = KMAX / 16, NT = 4, U = 4;
   const int id = blockIdx.x, q8 = id >> 3;
@@ -1162,10 +1140,10 @@ __global__ __launch_bounds__(256) void k_rows_mm(const TX* __restrict__ X,
     for (int m = 0; m < MT; ++m) {
       const double2* pv = reinterpret_cast<const double2*>(vb + roff[m] + a0);
       const double2 v0 = pv[0], v1 = pv[1];
-      fa[0][m] = rows_in[m] ? v0.x : 0.0;
-      fa[1][m] = rows_in[m] ? v0.y : 0.0;
-      fa[2][m] = rows_in[m] ? v1.x : 0.0;
-      fa[3][m] = rows_in[m] ? v1.y : 0.0;
+      fa[0][m] = rows_in[m] ? v0.x * scale : 0.0;
+      fa[1][m] = rows_in[m] ? v0.y * scale : 0.0;
+      fa[2][m] = rows_in[m] ? v1.x * scale : 0.0;
+      fa[3][m] = rows_in[m] ? v1.y * scale : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -1203,19 +1181,20 @@ __global__ __launch_bounds__(256) void k_rows_mm(const TX* __restrict__ X,
     }
 }
 
-// W = the first k_s rows of X (= E X for the core unit rows E)
+// W = the first k_s rows of X (= E X for the core unit rows E), times scale (a power of two)
 template <typename TX>
 __global__ __launch_bounds__(256) void k_rows_copy(const TX* __restrict__ X,
                                                    const int64_t* __restrict__ offs,
                                                    const int32_t* __restrict__ npad,
                                                    double* __restrict__ W,
                                                    const int64_t* __restrict__ soffs,
-                                                   const int32_t* __restrict__ core_ptr) {
+                                                   const int32_t* __restrict__ core_ptr,
+                                                   double scale) {
   const int s = blockIdx.y;
   const int np = npad[s], k = core_ptr[s + 1] - core_ptr[s];
   const int64_t n = (int64_t)k * np;
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
-    W[soffs[s] + p] = (double)X[offs[s] + p];
+    W[soffs[s] + p] = (double)X[offs[s] + p] * scale;
 }
 
 // out = a x + b y over a whole slab (flat)
@@ -2177,15 +2156,16 @@ struct RowsCtx {
   const int64_t* offs;
   const int32_t* npad;
   hipStream_t s;
+  double xscale;  // the stored iterate is X / xscale
   template <typename TX>
   void mm(const TX* X, const double* V, double* W) const {
     const dim3 grid(cr.colblocks * ((pl.n_sub + 7) / 8 * 8));
     if (cr.kmax == 16)
       hipLaunchKernelGGL((k_rows_mm<16, TX>), grid, dim3(256), 0, s, X, offs, npad, V, W,
-                         cr.soffs.get(), P.core_ptr.get(), pl.n_sub, cr.colblocks);
+                         cr.soffs.get(), P.core_ptr.get(), pl.n_sub, cr.colblocks, xscale);
     else
       hipLaunchKernelGGL((k_rows_mm<32, TX>), grid, dim3(256), 0, s, X, offs, npad, V, W,
-                         cr.soffs.get(), P.core_ptr.get(), pl.n_sub, cr.colblocks);
+                         cr.soffs.get(), P.core_ptr.get(), pl.n_sub, cr.colblocks, xscale);
     GB_LAUNCH_CHECK();
   }
   void lin2(double* out, double a, const double* x, double b, const double* y) const {
@@ -2278,9 +2258,10 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   int it_end = 0;
   bool done = false;  // the FP64 steps before a low-precision loop already converged
   // After a low-precision loop: its iterate made exactly symmetric in FP32 (what the core-row
-  // refinement reads), and an FP64 copy of it in xd only where whole blocks are refined,
-  // checked or scattered (ensure_xd).
+  // refinement reads; stored as X / xs_scale, the fp16 loop's 2^14 X), and an FP64 copy of X
+  // in xd only where whole blocks are refined, checked or scattered (ensure_xd).
   const float* xs = nullptr;
+  double xs_scale = 1.0;
   bool xd_ready = true;
   if (low) {
     float* xf = ws->get<float>(3, pl.total, s);
@@ -2334,14 +2315,12 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
                                  o.branch_in, o.n_branch_in, true, it_end, st, recs, s, &stop_kind,
                                  nullptr, planes, o.launch_mode == 1);
       // the final low-precision square was only the stop test: continue from X made exactly
-      // symmetric, in FP32 (every block is padded to a multiple of 64)
-      const int max_nt = pl.max_npad / 64;
-      hipLaunchKernelGGL(k_sym_convert<float>, dim3(max_nt * (max_nt + 1) / 2, pl.n_sub),
-                         dim3(256), 0, s,
-                         xf, sf, offs.get(), npad.get(),
-                         planes == 4 ? (double)kF16Down : 1.0);
+      // symmetric, in FP32, in place (every block is padded to a multiple of 64)
+      hipLaunchKernelGGL(k_sym_diag, dim3(pl.max_npad / 64, pl.n_sub), dim3(256), 0, s, xf,
+                         offs.get(), npad.get());
       GB_LAUNCH_CHECK();
-      xs = sf;
+      xs = xf;
+      xs_scale = planes == 4 ? (double)kF16Down : 1.0;
       xd_ready = false;
     }
     GB_HIP(hipEventRecord(t_sp2.b, s));
@@ -2392,7 +2371,7 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
   auto ensure_xd = [&] {
     if (xd_ready) return;
     hipLaunchKernelGGL((k_convert<float, double>), dim3(grid_for(pl.total, kT, 65536)), dim3(kT),
-                       0, s, xs, xd, pl.total, 1.0);
+                       0, s, xs, xd, pl.total, xs_scale);
     GB_LAUNCH_CHECK();
     xd_ready = true;
   };
@@ -2421,7 +2400,8 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
       DBuf<double> part(2 * (size_t)pl.n_sub, s);
       StepRec r;
       hipLaunchKernelGGL(k_trace_rows<float>, dim3(pl.n_sub), dim3(kT), 0, s, xs, offs.get(),
-                         npad.get(), P.core_ptr.get(), part.get(), nullptr, 1.0, 1.0);
+                         npad.get(), P.core_ptr.get(), part.get(), nullptr, xs_scale,
+                         xs_scale * xs_scale);
       hipLaunchKernelGGL(k_decide, dim3(1), dim3(kT), 0, s, part.get(), pl.n_sub, (double)n_occ,
                          tol, 2, 0, recs.get());
       GB_LAUNCH_CHECK();
@@ -2434,10 +2414,11 @@ void density(const gb_ell& H, int32_t n_occ, const gb_sp2_opts& o, const Part& P
         double* sl = ws->get<double>(7, 5 * (size_t)cr.total, s);
         double *y = sl, *s1 = sl + cr.total, *s2 = sl + 2 * cr.total, *t0 = sl + 3 * cr.total,
                *t1 = sl + 4 * cr.total;
-        const RowsCtx rc{cr, pl, P, offs.get(), npad.get(), s};
+        const RowsCtx rc{cr, pl, P, offs.get(), npad.get(), s, xs_scale};
         // E p(X) = 3 E X^2 - 2 E X^3 (E X: the first k rows of X)
         hipLaunchKernelGGL(k_rows_copy<float>, dim3(cr.colblocks * 4, pl.n_sub), dim3(256), 0, s,
-                           xs, offs.get(), npad.get(), t0, cr.soffs.get(), P.core_ptr.get());
+                           xs, offs.get(), npad.get(), t0, cr.soffs.get(), P.core_ptr.get(),
+                           xs_scale);
         GB_LAUNCH_CHECK();
         rc.mm(xs, t0, t1);
         rc.mm(xs, t1, t0);
