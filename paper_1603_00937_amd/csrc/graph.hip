@@ -224,24 +224,26 @@ __device__ __forceinline__ void x2_pairs(const int32_t* __restrict__ hcol,
   const int npair = kw * w;
   for (int p0 = threadIdx.x; p0 < npair; p0 += kX2B * kT) {
     int32_t jj[kX2B];
-    double pr[kX2B];
+    double xk[kX2B], xx[kX2B];  // x0_ik, x0_kj
 #pragma unroll
-    for (int q = 0; q < kX2B; ++q) {
+    for (int q = 0; q < kX2B; ++q) {  // every load of the batch first
       const int p = p0 + q * kT;
       jj[q] = -1;
-      pr[q] = 0.0;
+      xk[q] = xx[q] = 0.0;
       if (p < npair) {
         int t, u;
         x2_pair(p, w, inv_w, t, u);
         const int64_t e = (int64_t)ci[t] * w + u;
         jj[q] = hcol[e];
-        if (ADD) pr[q] = x0[e];
-        if (ADD) pr[q] = xi[t] * pr[q];
+        if (ADD) {
+          xx[q] = x0[e];
+          xk[q] = xi[t];
+        }
       }
     }
 #pragma unroll
     for (int q = 0; q < kX2B; ++q)
-      if ((unsigned)jj[q] < (unsigned)n) f(jj[q], pr[q]);
+      if ((unsigned)jj[q] < (unsigned)n) f(jj[q], ADD ? xk[q] * xx[q] : 0.0);
   }
 }
 
