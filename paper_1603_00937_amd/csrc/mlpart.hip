@@ -138,6 +138,7 @@ struct Level {
   const int32_t* adj = nullptr;
   const int32_t* ew = nullptr;
   std::vector<int32_t> rp_v, adj_v, ew_v;  // storage of a coarse level (or of host weights)
+  bool sorted = false;                     // rows ascending (a level built on the device)
   std::vector<int32_t> vw;                 // vertex weights
   std::vector<int32_t> cmap;               // vertex -> vertex of the next coarser level
 };
@@ -148,12 +149,16 @@ struct MlScratch {
   std::vector<Level> lv;  // lv[0]: the input level; coarse levels after it
   std::vector<std::pair<uint64_t, int32_t>> keys;
   std::vector<int32_t> top, match, lead, deg;
+  const int32_t* top1 = nullptr;  // the first coarse level's lists when the device built it
   // visiting orders by level (a function of the level and the vertex count only, so they are
   // kept for the next call on a graph of the same size)
   std::vector<std::pair<int, std::vector<int32_t>>> orders;
   std::vector<std::vector<int32_t>> adj_t, ew_t, acc;
   int32_t *h_rp = nullptr, *h_col = nullptr, *h_w = nullptr;  // pinned staging
   size_t cap_rp = 0, cap_col = 0, cap_w = 0;
+  // pinned arrays of a first coarse level built on the device
+  int32_t *h_rp1 = nullptr, *h_adj1 = nullptr, *h_ew1 = nullptr, *h_top1 = nullptr;
+  size_t cap_rp1 = 0, cap_adj1 = 0, cap_ew1 = 0, cap_top1 = 0;
 };
 
 namespace {
@@ -225,8 +230,11 @@ void top_candidates(const Level& f, int cap, int min_vw, std::vector<int32_t>& t
 // Heavy-edge matching of f (pairs of weight <= cap); returns false if no pair was matched.
 // given_top: the candidate lists of f computed elsewhere (the weights kernel does it for the
 // input level), else NULL
+// dev1: builds the coarse level (and its candidate lists, into sc.top1, for pair cap next_cap)
+// from the input level's device graph instead of the host
 bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
-             const int32_t* given_top = nullptr) {
+             const int32_t* given_top = nullptr, MlCoarseDevice* dev1 = nullptr,
+             int next_cap = 0) {
   const int n = f.n;
   // a vertex whose weight plus the smallest weight exceeds cap has no partner (the search below
   // would find none): it stays single without a look at its row, and when no two vertices fit
@@ -295,6 +303,13 @@ bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
     c.vw[f.cmap[v]] += f.vw[v];
     if (lead[f.cmap[v]] < 0) lead[f.cmap[v]] = v;
   }
+  if (dev1 && dev1->build(n, nc, match, f.cmap, lead, c.vw, next_cap, &c.rp, &c.adj, &c.ew,
+                          &sc.top1)) {
+    c.sorted = true;
+    return true;
+  }
+  sc.top1 = nullptr;
+  c.sorted = false;
   // coarse adjacency: summed edge weights, no self loops, neighbours in the order first met
   // (the matching breaks every tie by index, so only the breadth-first order on the coarsest
   // level needs them ascending; sort_rows does that there).  Coarse vertices are independent,
@@ -574,7 +589,8 @@ MlLease::~MlLease() {
 void ml_trim() {
   std::lock_guard<std::mutex> lk(g_ml_mu);
   for (MlScratch* sc : g_ml_free) {
-    for (int32_t* q : {sc->h_rp, sc->h_col, sc->h_w})
+    for (int32_t* q : {sc->h_rp, sc->h_col, sc->h_w, sc->h_rp1, sc->h_adj1, sc->h_ew1,
+                       sc->h_top1})
       if (q) GB_HIP(hipHostFree(q));
     delete sc;
   }
@@ -590,6 +606,18 @@ void ml_stage(MlScratch& sc, int n, int64_t nnz, int32_t** rp, int32_t** col, in
   if (w) *w = sc.h_w;
 }
 
+void ml_stage1(MlScratch& sc, int nc, int64_t nnz, int32_t** rp, int32_t** adj, int32_t** ew,
+               int32_t** top) {
+  pinned_reserve(sc.h_rp1, sc.cap_rp1, (size_t)nc + 1);
+  pinned_reserve(sc.h_adj1, sc.cap_adj1, (size_t)std::max<int64_t>(nnz, 1));
+  pinned_reserve(sc.h_ew1, sc.cap_ew1, (size_t)std::max<int64_t>(nnz, 1));
+  pinned_reserve(sc.h_top1, sc.cap_top1, (size_t)nc * kMlTop);
+  *rp = sc.h_rp1;
+  *adj = sc.h_adj1;
+  *ew = sc.h_ew1;
+  *top = sc.h_top1;
+}
+
 int32_t* ml_top_buffer(MlScratch& sc, int n) {
   sc.top.resize((size_t)n * kMlTop);
   return sc.top.data();
@@ -598,7 +626,7 @@ int32_t* ml_top_buffer(MlScratch& sc, int n) {
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,
                           std::vector<int32_t>& core_ptr, std::vector<int32_t>& core_vtx,
                           MlStats* stats, const int32_t* ew, MlScratch* scr,
-                          const int32_t* top0) {
+                          const int32_t* top0, MlCoarseDevice* dev1) {
   std::unique_ptr<MlLease> own;
   if (!scr) {
     own.reset(new MlLease);
@@ -606,6 +634,7 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
   }
   MlScratch& sc = *scr;
   auto t0 = clk::now();
+  sc.top1 = nullptr;  // set by this call's dev1 only
   if (sc.lv.empty()) sc.lv.resize(1);  // levels are addressed by index: lv may grow below
   input_level(n, row_ptr, col, ew, sc.lv[0]);
   const double ms_weights = ms_since(t0);
@@ -614,10 +643,17 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
   int nl = 1;
   for (int level = 0;; ++level) {
     if ((int)sc.lv.size() == nl) sc.lv.emplace_back();
-    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc, level == 0 ? top0 : nullptr)) break;
+    // the input level's lists come from top0; the first coarse level's from dev1 when it built
+    // that level
+    const int32_t* given = level == 0 ? top0
+                           : (level == 1 ? sc.top1 : nullptr);
+    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc, given, level == 0 ? dev1 : nullptr,
+                 ccap))
+      break;
     ++nl;
   }
-  if (nl > 1) sort_rows(sc.lv[nl - 1]);  // the input level keeps the caller's row order
+  // the input level keeps the caller's row order
+  if (nl > 1 && !sc.lv[nl - 1].sorted) sort_rows(sc.lv[nl - 1]);
   const double ms_coarsen = ms_since(t0);
   t0 = clk::now();
   std::vector<int32_t> part = grow_parts(sc.lv[nl - 1], cap);

@@ -380,6 +380,122 @@ __global__ __launch_bounds__(kT) void k_top_nb(int n, const int32_t* __restrict_
   }
 }
 
+// The first coarse level of the multilevel partitioner on the device.  Coarse vertex c is the
+// pair {lead[c], match[lead[c]]} (one vertex when it is its own match); its row is the set of
+// coarse vertices cmap[u] of its members' neighbours u other than c itself, ascending, each
+// with the summed weights of the edges that lead to it (integer sums: any order gives the
+// same).  One workgroup per coarse vertex, the set as an LDS bitmap over the nc coarse
+// vertices; PASS 0 counts the row, PASS 1 writes it (accumulators indexed by rank, at most
+// acap = the members' summed degrees).
+template <int PASS>
+__global__ __launch_bounds__(kT) void k_coarse_rows(int nc, const int32_t* __restrict__ rp,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ w,
+                                                    const int32_t* __restrict__ lead,
+                                                    const int32_t* __restrict__ match,
+                                                    const int32_t* __restrict__ cmap,
+                                                    int32_t* __restrict__ cnt,
+                                                    const int32_t* __restrict__ crp,
+                                                    int32_t* __restrict__ cadj,
+                                                    int32_t* __restrict__ cew) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int c = blockIdx.x;
+  const int nw = (nc + 31) >> 5;
+  uint32_t* bits = reinterpret_cast<uint32_t*>(smem);
+  int32_t* pre = reinterpret_cast<int32_t*>(bits + nw);
+  int32_t* red = pre + nw + 1;
+  int32_t* acc = red + kT;
+  const int a = lead[c], b = match[a];
+  const int nm = b == a ? 1 : 2;
+  for (int q = threadIdx.x; q < nw; q += kT) bits[q] = 0u;
+  __syncthreads();
+  for (int i = 0; i < nm; ++i) {
+    const int m = i ? b : a;
+    for (int e = rp[m] + threadIdx.x; e < rp[m + 1]; e += kT) {
+      const int cu = cmap[col[e]];
+      if (cu != c) atomicOr(&bits[cu >> 5], 1u << (cu & 31));
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < nw; q += kT) pre[q] = __popc(bits[q]);
+  __syncthreads();
+  const int32_t total = lds_exclusive_scan<kT>(pre, nw, red);
+  if (PASS == 0) {
+    if (threadIdx.x == 0) cnt[c] = total;
+    return;
+  }
+  for (int r = threadIdx.x; r < total; r += kT) acc[r] = 0;
+  __syncthreads();
+  for (int i = 0; i < nm; ++i) {
+    const int m = i ? b : a;
+    for (int e = rp[m] + threadIdx.x; e < rp[m + 1]; e += kT) {
+      const int cu = cmap[col[e]];
+      if (cu == c) continue;
+      const int r = pre[cu >> 5] + __popc(bits[cu >> 5] & ((1u << (cu & 31)) - 1u));
+      atomicAdd(&acc[r], w[e]);
+    }
+  }
+  __syncthreads();
+  const int32_t base = crp[c];
+  for (int q = threadIdx.x; q < nw; q += kT) {
+    uint32_t word = bits[q];
+    int r = pre[q];
+    while (word) {
+      const int bt = __ffs(word) - 1;
+      cadj[base + r] = (q << 5) + bt;
+      cew[base + r] = acc[r];
+      ++r;
+      word &= word - 1u;
+    }
+  }
+}
+
+// The candidate lists of the first coarse level: as k_top_nb, ordered by (weight, -vertex
+// weight, -index) -- key (weight << 32) | ~(vw << 24 | u), vw < 256 and u < 2^24 checked on the
+// host -- and only for vertices that can pair (vw + min vw <= cap; the others keep -1).
+__global__ __launch_bounds__(kT) void k_top_coarse(int nc, const int32_t* __restrict__ crp,
+                                                   const int32_t* __restrict__ cadj,
+                                                   const int32_t* __restrict__ cew,
+                                                   const int32_t* __restrict__ cvw, int cap,
+                                                   int min_vw, int32_t* __restrict__ top) {
+  const int lane = threadIdx.x & 63;
+  const int v = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (v >= nc) return;  // wave-uniform
+  uint64_t best[kMlTop];
+#pragma unroll
+  for (int i = 0; i < kMlTop; ++i) best[i] = 0;
+  if (cvw[v] + min_vw <= cap)
+    for (int e = crp[v] + lane; e < crp[v + 1]; e += 64) {
+      const int u = cadj[e];
+      uint64_t x = ((uint64_t)(uint32_t)cew[e] << 32) |
+                   (uint32_t)(~(((uint32_t)cvw[u] << 24) | (uint32_t)u));
+      if (x <= best[kMlTop - 1]) continue;
+#pragma unroll
+      for (int i = 0; i < kMlTop; ++i)
+        if (x > best[i]) {
+          const uint64_t t = best[i];
+          best[i] = x;
+          x = t;
+        }
+    }
+  for (int r = 0; r < kMlTop; ++r) {
+    uint64_t m = best[0];
+    for (int off = 32; off > 0; off >>= 1) {
+      const uint32_t lo = __shfl_xor((uint32_t)m, off, 64);
+      const uint32_t hi = __shfl_xor((uint32_t)(m >> 32), off, 64);
+      const uint64_t o = ((uint64_t)hi << 32) | lo;
+      m = o > m ? o : m;
+    }
+    if (m != 0 && best[0] == m) {
+#pragma unroll
+      for (int i = 0; i + 1 < kMlTop; ++i) best[i] = best[i + 1];
+      best[kMlTop - 1] = 0;
+    }
+    if (lane == 0)
+      top[(int64_t)v * kMlTop + r] = m ? (int32_t)(~(uint32_t)m & 0xFFFFFFu) : -1;
+  }
+}
+
 }  // namespace
 
 void partition_block(const Csr& g, int32_t core_size, Part& P, hipStream_t s, int method) {
@@ -465,6 +581,71 @@ struct SideCopy {  // an event that orders the side stream after the caller's st
   }
 };
 
+// The first coarse level from the input graph on the device (k_coarse_rows, k_top_coarse), its
+// rows and lists copied into the lease's pinned arrays.
+class DevCoarse : public MlCoarseDevice {
+ public:
+  DevCoarse(const Csr& g, const int32_t* dw, int max_deg, MlScratch& sc, hipStream_t s)
+      : g_(g), dw_(dw), max_deg_(max_deg), sc_(sc), s_(s) {}
+  bool build(int n, int nc, const std::vector<int32_t>& match, const std::vector<int32_t>& cmap,
+             const std::vector<int32_t>& lead, const std::vector<int32_t>& cvw, int cap,
+             const int32_t** rp, const int32_t** adj, const int32_t** ew,
+             const int32_t** top) override {
+    if (n != g_.n || nc < 1 || nc >= (1 << 24)) return false;
+    int min_vw = INT_MAX, max_vw = 0;
+    for (int x : cvw) {
+      min_vw = std::min(min_vw, x);
+      max_vw = std::max(max_vw, x);
+    }
+    if (max_vw > 255) return false;  // the candidate keys hold 8 bits of vertex weight
+    const int nw = (nc + 31) >> 5;
+    const size_t lds0 = ((size_t)2 * nw + 1 + kT) * 4 + 64;
+    const size_t lds1 = lds0 + (size_t)2 * max_deg_ * 4;  // a row: at most both members' degrees
+    if (lds1 > 160 * 1024) return false;
+    DBuf<int32_t> dm(n, s_), dc(n, s_), dl(nc, s_), dv(nc, s_), cnt(nc, s_), crp(nc + 1, s_);
+    GB_HIP(hipMemcpyAsync(dm.get(), match.data(), (size_t)n * 4, hipMemcpyHostToDevice, s_));
+    GB_HIP(hipMemcpyAsync(dc.get(), cmap.data(), (size_t)n * 4, hipMemcpyHostToDevice, s_));
+    GB_HIP(hipMemcpyAsync(dl.get(), lead.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s_));
+    GB_HIP(hipMemcpyAsync(dv.get(), cvw.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s_));
+    hipLaunchKernelGGL(k_coarse_rows<0>, dim3(nc), dim3(kT), lds0, s_, nc, g_.row_ptr.get(),
+                       g_.col.get(), dw_, dl.get(), dm.get(), dc.get(), cnt.get(), nullptr,
+                       nullptr, nullptr);
+    GB_LAUNCH_CHECK();
+    exclusive_scan_i32(cnt.get(), crp.get(), nc, s_);
+    int32_t nnz = 0;
+    GB_HIP(hipMemcpyAsync(&nnz, crp.get() + nc, 4, hipMemcpyDeviceToHost, s_));
+    GB_HIP(hipStreamSynchronize(s_));
+    DBuf<int32_t> cadj(std::max(nnz, 1), s_), cew(std::max(nnz, 1), s_),
+        dtop((size_t)nc * kMlTop, s_);
+    hipLaunchKernelGGL(k_coarse_rows<1>, dim3(nc), dim3(kT), lds1, s_, nc, g_.row_ptr.get(),
+                       g_.col.get(), dw_, dl.get(), dm.get(), dc.get(), nullptr, crp.get(),
+                       cadj.get(), cew.get());
+    GB_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_top_coarse, dim3((nc + kT / 64 - 1) / (kT / 64)), dim3(kT), 0, s_, nc,
+                       crp.get(), cadj.get(), cew.get(), dv.get(), cap, min_vw, dtop.get());
+    GB_LAUNCH_CHECK();
+    int32_t *hrp, *hadj, *hew, *htop;
+    ml_stage1(sc_, nc, nnz, &hrp, &hadj, &hew, &htop);
+    GB_HIP(hipMemcpyAsync(hrp, crp.get(), (size_t)(nc + 1) * 4, hipMemcpyDeviceToHost, s_));
+    GB_HIP(hipMemcpyAsync(hadj, cadj.get(), (size_t)nnz * 4, hipMemcpyDeviceToHost, s_));
+    GB_HIP(hipMemcpyAsync(hew, cew.get(), (size_t)nnz * 4, hipMemcpyDeviceToHost, s_));
+    GB_HIP(hipMemcpyAsync(htop, dtop.get(), (size_t)nc * kMlTop * 4, hipMemcpyDeviceToHost, s_));
+    GB_HIP(hipStreamSynchronize(s_));
+    *rp = hrp;
+    *adj = hadj;
+    *ew = hew;
+    *top = htop;
+    return true;
+  }
+
+ private:
+  const Csr& g_;
+  const int32_t* dw_;
+  int max_deg_;
+  MlScratch& sc_;
+  hipStream_t s_;
+};
+
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
                               MlStats* stats, const Part* prev) {
   const int n = g.n;
@@ -511,7 +692,10 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
   GB_HIP(hipStreamSynchronize(side.cs));
   GB_HIP(hipStreamSynchronize(s));
   if (miss < n) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", miss);
-  partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p, top);
+  int max_deg = 0;
+  for (int v = 0; v < n; ++v) max_deg = std::max(max_deg, rp[v + 1] - rp[v]);
+  DevCoarse dev1(g, dw.get(), max_deg, *lease.p, s);
+  partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p, top, &dev1);
   partition_from_cores(g, cp, cv, P, s);
 }
 
