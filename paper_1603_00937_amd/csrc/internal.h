@@ -189,24 +189,26 @@ int32_t* ml_top_buffer(MlScratch& sc, int n);
 // only computed when stats is given.  top0 (optional, with ew): per vertex the kMlTop heaviest
 // neighbours by (weight, -index), heaviest first, -1 padded (what the matching would compute).
 constexpr int kMlTop = 8;
-// The first coarse level built where the input graph lives (the device path, partition.hip):
-// given the input level's matching -- coarse vertex c is {lead[c], match[lead[c]]}, cmap the
-// fine -> coarse map, cvw the coarse weights -- it fills the coarse rows (neighbours ascending,
-// the summed weights of the edges between the two vertex sets, no self loops) and the coarse
-// level's candidate lists for pair cap `cap` (those the host would compute: the kMlTop heaviest
-// by (weight, -vertex weight, -index) of every vertex with cvw + min cvw <= cap, else -1).
-// Returns false when it cannot (then the host builds the level).
-// On success *rp, *adj, *ew (CSR of the nc coarse vertices) and *top (nc * kMlTop) point at
-// host arrays that stay valid until the partition call returns.
+// Coarse levels built where the graph lives (the device path, partition.hip): given the
+// matching of level `level` (n vertices, host row pointers frp) -- coarse vertex c is
+// {lead[c], match[lead[c]]}, cmap the fine -> coarse map, cvw the coarse weights -- it builds
+// the coarse rows (neighbours ascending, the summed weights of the edges between the two vertex
+// sets, no self loops) from its own copy of the fine level (the input graph for level 0, else
+// the level it built last) and the coarse level's candidate lists for pair cap `cap` (those
+// the host would compute: the kMlTop heaviest by (weight, -vertex weight, -index) of every
+// vertex with cvw + min cvw <= cap, else -1).  On success *rp, *adj, *ew (CSR of the nc coarse
+// vertices) and *top (nc * kMlTop) point at host arrays valid until the next build or the end
+// of the partition call; on false the host builds the level (and every later one).
 struct MlCoarseDevice {
   virtual ~MlCoarseDevice() = default;
-  virtual bool build(int n, int nc, const std::vector<int32_t>& match,
-                     const std::vector<int32_t>& cmap, const std::vector<int32_t>& lead,
-                     const std::vector<int32_t>& cvw, int cap, const int32_t** rp,
-                     const int32_t** adj, const int32_t** ew, const int32_t** top) = 0;
+  virtual bool build(int level, int n, const int32_t* frp, int nc,
+                     const std::vector<int32_t>& match, const std::vector<int32_t>& cmap,
+                     const std::vector<int32_t>& lead, const std::vector<int32_t>& cvw, int cap,
+                     const int32_t** rp, const int32_t** adj, const int32_t** ew,
+                     const int32_t** top) = 0;
 };
-// pinned host arrays of the lease for the first coarse level (nc vertices, nnz entries, the
-// candidate lists), grown on demand
+// pinned host arrays of the lease for a coarse level built on the device (nc vertices, nnz
+// entries, the candidate lists), grown on demand
 void ml_stage1(MlScratch& sc, int nc, int64_t nnz, int32_t** rp, int32_t** adj, int32_t** ew,
                int32_t** top);
 void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int cap,

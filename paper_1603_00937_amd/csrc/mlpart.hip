@@ -149,14 +149,14 @@ struct MlScratch {
   std::vector<Level> lv;  // lv[0]: the input level; coarse levels after it
   std::vector<std::pair<uint64_t, int32_t>> keys;
   std::vector<int32_t> top, match, lead, deg;
-  const int32_t* top1 = nullptr;  // the first coarse level's lists when the device built it
+  const int32_t* top1 = nullptr;  // the lists of the level the device built last
   // visiting orders by level (a function of the level and the vertex count only, so they are
   // kept for the next call on a graph of the same size)
   std::vector<std::pair<int, std::vector<int32_t>>> orders;
   std::vector<std::vector<int32_t>> adj_t, ew_t, acc;
   int32_t *h_rp = nullptr, *h_col = nullptr, *h_w = nullptr;  // pinned staging
   size_t cap_rp = 0, cap_col = 0, cap_w = 0;
-  // pinned arrays of a first coarse level built on the device
+  // pinned arrays of the coarse level built on the device last
   int32_t *h_rp1 = nullptr, *h_adj1 = nullptr, *h_ew1 = nullptr, *h_top1 = nullptr;
   size_t cap_rp1 = 0, cap_adj1 = 0, cap_ew1 = 0, cap_top1 = 0;
 };
@@ -231,7 +231,7 @@ void top_candidates(const Level& f, int cap, int min_vw, std::vector<int32_t>& t
 // given_top: the candidate lists of f computed elsewhere (the weights kernel does it for the
 // input level), else NULL
 // dev1: builds the coarse level (and its candidate lists, into sc.top1, for pair cap next_cap)
-// from the input level's device graph instead of the host
+// on the device instead of the host
 bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
              const int32_t* given_top = nullptr, MlCoarseDevice* dev1 = nullptr,
              int next_cap = 0) {
@@ -303,8 +303,8 @@ bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
     c.vw[f.cmap[v]] += f.vw[v];
     if (lead[f.cmap[v]] < 0) lead[f.cmap[v]] = v;
   }
-  if (dev1 && dev1->build(n, nc, match, f.cmap, lead, c.vw, next_cap, &c.rp, &c.adj, &c.ew,
-                          &sc.top1)) {
+  if (dev1 && dev1->build(level, n, f.rp, nc, match, f.cmap, lead, c.vw, next_cap, &c.rp,
+                          &c.adj, &c.ew, &sc.top1)) {
     c.sorted = true;
     return true;
   }
@@ -643,13 +643,10 @@ void partition_multilevel(int n, const int32_t* row_ptr, const int32_t* col, int
   int nl = 1;
   for (int level = 0;; ++level) {
     if ((int)sc.lv.size() == nl) sc.lv.emplace_back();
-    // the input level's lists come from top0; the first coarse level's from dev1 when it built
-    // that level
-    const int32_t* given = level == 0 ? top0
-                           : (level == 1 ? sc.top1 : nullptr);
-    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc, given, level == 0 ? dev1 : nullptr,
-                 ccap))
-      break;
+    // the input level's lists come from top0; a coarse level's from dev1 when it built that
+    // level (sc.top1 is reset whenever the host builds one)
+    const int32_t* given = level == 0 ? top0 : sc.top1;
+    if (!coarsen(sc.lv[nl - 1], ccap, level, sc.lv[nl], sc, given, dev1, ccap)) break;
     ++nl;
   }
   // the input level keeps the caller's row order

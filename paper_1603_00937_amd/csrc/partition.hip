@@ -581,35 +581,43 @@ struct SideCopy {  // an event that orders the side stream after the caller's st
   }
 };
 
-// The first coarse level from the input graph on the device (k_coarse_rows, k_top_coarse), its
-// rows and lists copied into the lease's pinned arrays.
+// Coarse levels on the device (k_coarse_rows, k_top_coarse): the first from the input graph and
+// its weights, each later one from the level built before it (kept on the device); rows and
+// lists are copied into the lease's pinned arrays.
 class DevCoarse : public MlCoarseDevice {
  public:
-  DevCoarse(const Csr& g, const int32_t* dw, int max_deg, MlScratch& sc, hipStream_t s)
-      : g_(g), dw_(dw), max_deg_(max_deg), sc_(sc), s_(s) {}
-  bool build(int n, int nc, const std::vector<int32_t>& match, const std::vector<int32_t>& cmap,
-             const std::vector<int32_t>& lead, const std::vector<int32_t>& cvw, int cap,
-             const int32_t** rp, const int32_t** adj, const int32_t** ew,
-             const int32_t** top) override {
-    if (n != g_.n || nc < 1 || nc >= (1 << 24)) return false;
+  DevCoarse(const Csr& g, const int32_t* dw, MlScratch& sc, hipStream_t s)
+      : g_(g), dw_(dw), sc_(sc), s_(s) {}
+  bool build(int level, int n, const int32_t* frp, int nc, const std::vector<int32_t>& match,
+             const std::vector<int32_t>& cmap, const std::vector<int32_t>& lead,
+             const std::vector<int32_t>& cvw, int cap, const int32_t** rp, const int32_t** adj,
+             const int32_t** ew, const int32_t** top) override {
+    // the fine level: the input graph, or the level built last (its rows still on the device)
+    const bool input = level == 0;
+    if (input ? n != g_.n : (level != built_ || n != n_built_)) return false;
+    if (nc < 1 || nc >= (1 << 24)) return false;
     int min_vw = INT_MAX, max_vw = 0;
     for (int x : cvw) {
       min_vw = std::min(min_vw, x);
       max_vw = std::max(max_vw, x);
     }
     if (max_vw > 255) return false;  // the candidate keys hold 8 bits of vertex weight
+    int max_deg = 0;
+    for (int v = 0; v < n; ++v) max_deg = std::max(max_deg, frp[v + 1] - frp[v]);
     const int nw = (nc + 31) >> 5;
     const size_t lds0 = ((size_t)2 * nw + 1 + kT) * 4 + 64;
-    const size_t lds1 = lds0 + (size_t)2 * max_deg_ * 4;  // a row: at most both members' degrees
+    const size_t lds1 = lds0 + (size_t)2 * max_deg * 4;  // a row: at most both members' degrees
     if (lds1 > 160 * 1024) return false;
+    const int32_t* frp_d = input ? g_.row_ptr.get() : rp_.get();
+    const int32_t* fadj_d = input ? g_.col.get() : adj_.get();
+    const int32_t* few_d = input ? dw_ : ew_.get();
     DBuf<int32_t> dm(n, s_), dc(n, s_), dl(nc, s_), dv(nc, s_), cnt(nc, s_), crp(nc + 1, s_);
     GB_HIP(hipMemcpyAsync(dm.get(), match.data(), (size_t)n * 4, hipMemcpyHostToDevice, s_));
     GB_HIP(hipMemcpyAsync(dc.get(), cmap.data(), (size_t)n * 4, hipMemcpyHostToDevice, s_));
     GB_HIP(hipMemcpyAsync(dl.get(), lead.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s_));
     GB_HIP(hipMemcpyAsync(dv.get(), cvw.data(), (size_t)nc * 4, hipMemcpyHostToDevice, s_));
-    hipLaunchKernelGGL(k_coarse_rows<0>, dim3(nc), dim3(kT), lds0, s_, nc, g_.row_ptr.get(),
-                       g_.col.get(), dw_, dl.get(), dm.get(), dc.get(), cnt.get(), nullptr,
-                       nullptr, nullptr);
+    hipLaunchKernelGGL(k_coarse_rows<0>, dim3(nc), dim3(kT), lds0, s_, nc, frp_d, fadj_d, few_d,
+                       dl.get(), dm.get(), dc.get(), cnt.get(), nullptr, nullptr, nullptr);
     GB_LAUNCH_CHECK();
     exclusive_scan_i32(cnt.get(), crp.get(), nc, s_);
     int32_t nnz = 0;
@@ -617,9 +625,8 @@ class DevCoarse : public MlCoarseDevice {
     GB_HIP(hipStreamSynchronize(s_));
     DBuf<int32_t> cadj(std::max(nnz, 1), s_), cew(std::max(nnz, 1), s_),
         dtop((size_t)nc * kMlTop, s_);
-    hipLaunchKernelGGL(k_coarse_rows<1>, dim3(nc), dim3(kT), lds1, s_, nc, g_.row_ptr.get(),
-                       g_.col.get(), dw_, dl.get(), dm.get(), dc.get(), nullptr, crp.get(),
-                       cadj.get(), cew.get());
+    hipLaunchKernelGGL(k_coarse_rows<1>, dim3(nc), dim3(kT), lds1, s_, nc, frp_d, fadj_d, few_d,
+                       dl.get(), dm.get(), dc.get(), nullptr, crp.get(), cadj.get(), cew.get());
     GB_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_top_coarse, dim3((nc + kT / 64 - 1) / (kT / 64)), dim3(kT), 0, s_, nc,
                        crp.get(), cadj.get(), cew.get(), dv.get(), cap, min_vw, dtop.get());
@@ -631,6 +638,12 @@ class DevCoarse : public MlCoarseDevice {
     GB_HIP(hipMemcpyAsync(hew, cew.get(), (size_t)nnz * 4, hipMemcpyDeviceToHost, s_));
     GB_HIP(hipMemcpyAsync(htop, dtop.get(), (size_t)nc * kMlTop * 4, hipMemcpyDeviceToHost, s_));
     GB_HIP(hipStreamSynchronize(s_));
+    // the new level becomes the fine level of the next build
+    rp_ = std::move(crp);
+    adj_ = std::move(cadj);
+    ew_ = std::move(cew);
+    built_ = level + 1;
+    n_built_ = nc;
     *rp = hrp;
     *adj = hadj;
     *ew = hew;
@@ -641,9 +654,10 @@ class DevCoarse : public MlCoarseDevice {
  private:
   const Csr& g_;
   const int32_t* dw_;
-  int max_deg_;
   MlScratch& sc_;
   hipStream_t s_;
+  DBuf<int32_t> rp_, adj_, ew_;  // the level built last
+  int built_ = -1, n_built_ = 0;
 };
 
 void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStream_t s,
@@ -692,9 +706,7 @@ void partition_multilevel_dev(const Csr& g, int32_t core_size, Part& P, hipStrea
   GB_HIP(hipStreamSynchronize(side.cs));
   GB_HIP(hipStreamSynchronize(s));
   if (miss < n) fail(GB_EINVAL, "multilevel: vertex %d has no self loop", miss);
-  int max_deg = 0;
-  for (int v = 0; v < n; ++v) max_deg = std::max(max_deg, rp[v + 1] - rp[v]);
-  DevCoarse dev1(g, dw.get(), max_deg, *lease.p, s);
+  DevCoarse dev1(g, dw.get(), *lease.p, s);
   partition_multilevel(n, rp, col, core_size, cp, cv, stats, w, lease.p, top, &dev1);
   partition_from_cores(g, cp, cv, P, s);
 }
