@@ -228,8 +228,8 @@ void top_candidates(const Level& f, int cap, int min_vw, std::vector<int32_t>& t
 }
 
 // Heavy-edge matching of f (pairs of weight <= cap); returns false if no pair was matched.
-// given_top: the candidate lists of f computed elsewhere (the weights kernel does it for the
-// input level), else NULL
+// given_top: the candidate lists of f computed elsewhere (by the weights kernel for the input
+// level, by dev1 for a coarse level it built), else NULL
 // dev1: builds the coarse level (and its candidate lists, into sc.top1, for pair cap next_cap)
 // on the device instead of the host
 bool coarsen(Level& f, int cap, int level, Level& c, MlScratch& sc,
