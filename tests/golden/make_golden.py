@@ -32,6 +32,16 @@ def write_hashes():
 
 def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory=False,
                       method="block"):
+    rec = partitioned_record(name, tau, core_size, n_samples, seed, low_memory, method)
+    tag = "partitioned" if method == "block" else method
+    json.dump(rec, open(os.path.join(HERE, f"{name}_fp64_{tag}.json"), "w"))
+    return rec
+
+
+def partitioned_record(name, tau, core_size, n_samples=4096, seed=123, low_memory=False,
+                       method="block"):
+    """The stored record of one partitioned FP64 oracle run (graph, partition, SP2 sequence,
+    traces, D hashes and sampled entries)."""
     m = make_model(name)
     t = time.time()
     D_col, D_val, info = density_partitioned(m["H_col"], m["H_val"], m["n_occ"], tau, core_size,
@@ -65,8 +75,6 @@ def write_partitioned(name, tau, core_size, n_samples=4096, seed=123, low_memory
         # the communities themselves (the CPU baseline samples them)
         rec["core_ptr"] = [int(x) for x in info["core_ptr"]]
         rec["core_vtx"] = [int(x) for x in info["core_vertices"]]
-    tag = "partitioned" if method == "block" else method
-    json.dump(rec, open(os.path.join(HERE, f"{name}_fp64_{tag}.json"), "w"))
     return rec
 
 
