@@ -6,6 +6,7 @@
 #include "lds_hash.h"
 #include "lds_scan.h"
 
+#include <climits>
 #include <map>
 #include <mutex>
 
