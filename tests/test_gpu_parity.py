@@ -420,6 +420,23 @@ def test_multilevel_partition_bit_exact(gb, model_cache, name, tau, core):
     assert np.array_equal(cp, ocp) and np.array_equal(sp, osp) and np.array_equal(si, osi)
 
 
+def test_multilevel_device_levels_match_host_levels(gb):
+    """The device path builds every coarse level on the GPU (rows ascending, candidate lists
+    from k_top_coarse); the host entry point builds them on host threads (rows in first-met
+    order): at N = 18000 (four levels) the cores agree index for index."""
+    import torch
+    from synth import make_model
+    m = make_model("n18000")
+    g = gb.build_graph(torch.from_numpy(m["H_col"]).cuda(), torch.from_numpy(m["H_val"]).cuda(),
+                       1e-5)
+    p = gb.partition(g, 32, method="multilevel")
+    cp, sp, si = _host(*p.arrays())
+    rp, cl = _host(*g.arrays())
+    hcp, hcv, _ = gb.partition_host(rp, cl, 32)
+    dev_vtx = np.concatenate([si[sp[c]:sp[c] + (cp[c + 1] - cp[c])] for c in range(len(cp) - 1)])
+    assert np.array_equal(cp, hcp) and np.array_equal(dev_vtx, hcv)
+
+
 def test_density_n1024_multilevel_golden(gb, model_cache):
     """FP64 D on multilevel communities against the oracle's stored run on the same cores."""
     from synth import ell_sha256
